@@ -1,0 +1,454 @@
+"""Pins of the FP64 oracle against what the mathematics fixes.
+
+The paper prints no numerical value for the chi0 path, so every pin here is
+a closed form, an identity, an invariant or a brute-force evaluation written
+independently of the oracle's FFT-based code (explicit Python loops over the
+grid, plane waves whose matrix elements are Kronecker deltas, ...).
+"""
+import cmath
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+L = 10.0
+VOL = L ** 3
+
+
+def _bands(rng, nb, n, ortho=True):
+    return gen.orthonormal_bands(rng, nb, n, VOL, ortho)
+
+
+def _all_g(n):
+    """Every Miller triple with g_i in [-N_i/2, N_i/2): one per grid point."""
+    axes = [range(-(k // 2), k - k // 2) for k in n]
+    return np.array(list(itertools.product(*axes)), dtype=np.int32)
+
+
+def _plane_waves(ks, n):
+    """psi_k(r) = exp(i k.r)/sqrt(Omega) for integer k (grid wave vectors)."""
+    n1, n2, n3 = n
+    j1, j2, j3 = np.meshgrid(np.arange(n1), np.arange(n2), np.arange(n3), indexing="ij")
+    out = []
+    for k in ks:
+        arg = 2 * np.pi * (k[0] * j1 / n1 + k[1] * j2 / n2 + k[2] * j3 / n3)
+        out.append(np.exp(1j * arg).reshape(-1) / math.sqrt(VOL))
+    return np.array(out)
+
+
+def _brute_m(psi_v_row, psi_c_row, g, n):
+    """Direct triple loop over the grid with cmath (no numpy transforms)."""
+    n1, n2, n3 = n
+    dv = VOL / (n1 * n2 * n3)
+    acc = 0j
+    for j1 in range(n1):
+        for j2 in range(n2):
+            for j3 in range(n3):
+                r = (j1 * n2 + j2) * n3 + j3
+                ph = cmath.exp(2j * math.pi * (g[0] * j1 / n1 + g[1] * j2 / n2 + g[2] * j3 / n3))
+                acc += psi_v_row[r].conjugate() * psi_c_row[r] * ph
+    return dv * acc
+
+
+# ---------------------------------------------------------------- inputs
+
+def test_gsphere_counts_and_order():
+    # complete shells |g|^2 <= R^2 of the workloads (~150, ~2000, ~6000, ~1200)
+    for r2, count in ((10, 147), (61, 2007), (126, 6031), (42, 1189)):
+        g = gen.gsphere(r2)
+        assert g.shape == (count, 3)
+        n2 = (g.astype(np.int64) ** 2).sum(1)
+        assert np.all(np.diff(n2) >= 0)
+        assert len({tuple(x) for x in g}) == count
+        assert tuple(g[0]) == (0, 0, 0)
+
+
+def test_gsphere_shifted_sizes():
+    qs, ng, nc = gen.batched_shapes()
+    assert qs.shape == (64, 3)
+    assert ng.min() == 400 and ng.max() == 4000 and len(set(ng.tolist())) == 64
+    assert nc.min() == 300 and nc.max() == 900
+    g = gen.gsphere_shifted(qs[5], int(ng[5]))
+    assert g.shape == (ng[5], 3) and len({tuple(x) for x in g}) == ng[5]
+    k2 = ((g + qs[5]) ** 2).sum(1)
+    assert np.all(np.diff(k2) >= -1e-12)
+
+
+def test_generated_bands_orthonormal():
+    rng = np.random.default_rng(0)
+    n = (6, 5, 4)
+    psi = _bands(rng, 20, n)
+    dv = VOL / np.prod(n)
+    gram = dv * psi.conj() @ psi.T
+    assert np.abs(gram - np.eye(20)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- MTXEL
+
+def test_plane_wave_mtxel_is_kronecker_delta():
+    """psi_n = exp(i k_n.r)/sqrt(Omega) gives M_vc(G) = 1 iff G = k_v - k_c mod N."""
+    n = (8, 6, 10)
+    kv = [(0, 0, 0), (3, -2, 4), (-4, 2, -5)]
+    kc = [(1, 0, 0), (3, -2, 3), (-3, 2, 4), (0, 1, -1), (4, 3, 0)]   # includes wraps
+    pv, pc = _plane_waves(kv, n), _plane_waves(kc, n)
+    gl = _all_g(n)
+    m = oracle.mtxel(pv, pc, gl, n, VOL)
+    nn = np.array(n)
+    for v, c in itertools.product(range(len(kv)), range(len(kc))):
+        target = (np.array(kv[v]) - np.array(kc[c])) % nn
+        want = np.all((gl % nn) == target, axis=1).astype(float)
+        assert want.sum() == 1
+        assert np.abs(m[v * len(kc) + c] - want).max() < 1e-12
+
+
+def test_plane_wave_mtxel_sign_discriminates():
+    """The opposite exponent sign would put the 1 at k_c - k_v instead."""
+    n = (8, 8, 8)
+    pv, pc = _plane_waves([(1, 2, 3)], n), _plane_waves([(0, 0, 0)], n)
+    m = oracle.mtxel(pv, pc, np.array([[1, 2, 3], [-1, -2, -3]], np.int32), n, VOL)
+    assert abs(m[0, 0] - 1) < 1e-12 and abs(m[0, 1]) < 1e-12
+
+
+@pytest.mark.parametrize("n", [(4, 4, 4), (6, 6, 6), (8, 8, 8), (10, 10, 10), (12, 12, 12), (4, 6, 5)])
+def test_mtxel_brute_force_dft(n):
+    rng = np.random.default_rng(sum(n))
+    psi = _bands(rng, 5, n, ortho=False)
+    pv, pc = psi[:2], psi[2:]
+    gl = _all_g(n)
+    sel = rng.choice(len(gl), size=min(6, len(gl)), replace=False)
+    g = gl[sel]
+    m = oracle.mtxel(pv, pc, g, n, VOL)
+    for p in range(6):
+        v, c = divmod(p, 3)
+        for i in range(len(g)):
+            ref = _brute_m(pv[v], pc[c], g[i], n)
+            assert abs(m[p, i] - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_mtxel_direct_matches_brute_force():
+    n = (4, 6, 5)
+    rng = np.random.default_rng(7)
+    psi = _bands(rng, 4, n, ortho=False)
+    g = (1, -3, 2)
+    d = oracle.mtxel_direct(psi[:2], psi[2:], g, n, VOL)
+    for v, c in itertools.product(range(2), range(2)):
+        assert abs(d[v, c] - _brute_m(psi[v], psi[2 + c], g, n)) < 1e-12
+
+
+def test_mtxel_parseval_full_grid():
+    n = (6, 8, 5)
+    rng = np.random.default_rng(3)
+    psi = _bands(rng, 4, n)
+    gl = _all_g(n)
+    m = oracle.mtxel(psi[:2], psi[2:], gl, n, VOL)
+    dv = VOL / np.prod(n)
+    for p in range(4):
+        v, c = divmod(p, 2)
+        rhs = VOL * dv * np.sum(np.abs(psi[v]) ** 2 * np.abs(psi[2 + c]) ** 2)
+        assert abs(np.sum(np.abs(m[p]) ** 2) - rhs) < 1e-12 * rhs
+
+
+def test_mtxel_completeness_sum_rule():
+    """With N_b = N_r orthonormal states, sum_n |M_vn(G)|^2 = <v|v> = 1."""
+    n = (4, 4, 3)
+    nr = int(np.prod(n))
+    rng = np.random.default_rng(5)
+    psi = _bands(rng, nr, n)
+    gl = _all_g(n)[::5]
+    m = oracle.mtxel(psi[:3], psi, gl, n, VOL).reshape(3, nr, -1)
+    s = np.sum(np.abs(m) ** 2, axis=1)
+    assert np.abs(s - 1.0).max() < 1e-12
+
+
+def test_mtxel_orthogonality_at_g0():
+    n = (8, 8, 8)
+    rng = np.random.default_rng(9)
+    psi = _bands(rng, 12, n)
+    m = oracle.mtxel(psi[:4], psi[4:], np.zeros((1, 3), np.int32), n, VOL)
+    assert np.abs(m).max() < 1e-12
+
+
+def test_mtxel_translation_phase():
+    n = (6, 8, 10)
+    rng = np.random.default_rng(11)
+    psi = _bands(rng, 4, n, ortho=False)
+    a = (2, -3, 4)
+    shifted = np.roll(psi.reshape(4, *n), shift=a, axis=(1, 2, 3)).reshape(4, -1)
+    gl = _all_g(n)[::7]
+    m0 = oracle.mtxel(psi[:2], psi[2:], gl, n, VOL)
+    m1 = oracle.mtxel(shifted[:2], shifted[2:], gl, n, VOL)
+    ph = np.exp(2j * np.pi * (gl[:, 0] * a[0] / n[0] + gl[:, 1] * a[1] / n[1] + gl[:, 2] * a[2] / n[2]))
+    assert np.abs(m1 - m0 * ph[None, :]).max() < 1e-12
+
+
+def test_mtxel_aliasing_mod_n():
+    n = (6, 6, 6)
+    rng = np.random.default_rng(13)
+    psi = _bands(rng, 3, n, ortho=False)
+    g = np.array([[1, -2, 3], [1 + 6, -2 - 6, 3 + 12]], np.int32)
+    m = oracle.mtxel(psi[:1], psi[1:], g, n, VOL)
+    assert np.abs(m[:, 0] - m[:, 1]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- energy factor
+
+def test_energy_factor_closed_forms():
+    e_v = np.array([-0.3, -0.1])
+    e_c = np.array([0.2, 0.7, 1.0])
+    de = (e_v[:, None] - e_c[None, :]).reshape(-1)
+    d0 = oracle.energy_factor(e_v, e_c, [0.0])[0]
+    assert np.allclose(d0, 2.0 / de, rtol=1e-15, atol=0)
+    w = 0.37
+    di = oracle.energy_factor(e_v, e_c, [1j * w])[0]
+    assert np.abs(di.imag).max() < 1e-15
+    assert np.allclose(di.real, 2 * de / (de ** 2 + w ** 2), rtol=1e-14, atol=0)
+    # real axis with broadening: resonant + anti-resonant, retarded
+    z = 0.5 + 0.01j
+    dr = oracle.energy_factor(e_v, e_c, [z])[0]
+    ecv = -de
+    assert np.allclose(dr, 1 / (z - ecv) - 1 / (z + ecv), rtol=1e-14, atol=0)
+
+
+def test_energy_factor_derivative():
+    e_v = np.array([-0.3, -0.05])
+    e_c = np.array([0.2, 0.9])
+    z = np.array([0.0, 0.4j, 0.3 + 0.02j])
+    d = oracle.energy_factor_dE(e_v, e_c, z)
+    h = 1e-6
+    fd = (oracle.energy_factor(e_v + h, e_c, z) - oracle.energy_factor(e_v - h, e_c, z)) / (2 * h)
+    # each E_v shift moves both pairs of that v, so compare per pair
+    assert np.allclose(d, fd, rtol=1e-7, atol=1e-7)
+    fdc = (oracle.energy_factor(e_v, e_c + h, z) - oracle.energy_factor(e_v, e_c - h, z)) / (2 * h)
+    assert np.allclose(-d, fdc, rtol=1e-7, atol=1e-7)
+
+
+# ---------------------------------------------------------------- chi0
+
+def test_plane_wave_chi_closed_form():
+    """chi_GG'(z) = s delta_GG' sum over pairs with k_v - k_c = G of Delta_vc(z)."""
+    n = (8, 8, 8)
+    kv = [(0, 0, 0), (1, 0, 0)]
+    kc = [(1, 0, 0), (2, 0, 0), (0, 1, 0), (0, 0, 3), (-1, 0, 0)]
+    pv, pc = _plane_waves(kv, n), _plane_waves(kc, n)
+    e_v = np.array([-0.2, -0.35])
+    e_c = np.array([0.1, 0.3, 0.45, 0.8, 1.05])
+    z = np.array([0.0, 0.6j, 0.25 + 0.005j])
+    gl = gen.gsphere(10)
+    chi = oracle.chi0(pv, pc, e_v, e_c, gl, z, n, VOL, spin=2.0, pair_chunk=3)
+    want = np.zeros_like(chi)
+    for w, zz in enumerate(z):
+        for v, c in itertools.product(range(2), range(5)):
+            gdiff = np.array(kv[v]) - np.array(kc[c])
+            hit = np.where(np.all(gl == gdiff, axis=1))[0]
+            de = e_v[v] - e_c[c]
+            if hit.size:
+                want[w, hit[0], hit[0]] += 2.0 * (1 / (de + zz) + 1 / (de - zz))
+    assert np.abs(chi - want).max() < 1e-12 * np.abs(want).max()
+
+
+def test_chi0_brute_force_quadruple_loop():
+    n = (4, 4, 6)
+    rng = np.random.default_rng(17)
+    psi = _bands(rng, 5, n)
+    pv, pc = psi[:2], psi[2:]
+    e_v, e_c = np.array([-0.3, -0.05]), np.array([0.1, 0.6, 0.9])
+    g = np.array([[0, 0, 0], [1, 0, -1], [0, -2, 2], [-1, 1, 1]], np.int32)
+    z = np.array([0.3j, 0.4 + 0.01j])
+    chi = oracle.chi0(pv, pc, e_v, e_c, g, z, n, VOL, spin=2.0, pair_chunk=4)
+    for w, zz in enumerate(z):
+        for i, j in itertools.product(range(4), range(4)):
+            acc = 0j
+            for v, c in itertools.product(range(2), range(3)):
+                de = e_v[v] - e_c[c]
+                delta = 1 / (de + zz) + 1 / (de - zz)
+                acc += _brute_m(pv[v], pc[c], g[i], n).conjugate() * delta * _brute_m(pv[v], pc[c], g[j], n)
+            assert abs(chi[w, i, j] - 2 * acc) < 1e-12 * max(1e-3, abs(acc))
+
+
+def _small_problem(seed=21, n=(6, 6, 6), nv=3, nc=7, r2=3, z=(0.0, 0.5j, 0.3 + 0.005j)):
+    return gen.make_problem(n, nv, nc, r2=r2, z=z, seed=seed, pair_chunk=5)
+
+
+def _chi(p, **kw):
+    args = dict(spin=p.spin, pair_chunk=p.pair_chunk)
+    args.update(kw)
+    return oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, **args)
+
+
+def test_chi0_trace_identity_full_grid():
+    n = (4, 6, 4)
+    p = gen.make_problem(n, 2, 5, gvec=_all_g(n), z=(0.0, 0.7j), seed=2)
+    chi = _chi(p)
+    dv = p.volume / np.prod(n)
+    delta = oracle.energy_factor(p.e_v, p.e_c, p.z)
+    for w in range(2):
+        rhs = 0j
+        for v, c in itertools.product(range(2), range(5)):
+            rho2 = np.sum(np.abs(p.psi_v[v]) ** 2 * np.abs(p.psi_c[c]) ** 2)
+            rhs += 2.0 * delta[w, v * 5 + c] * p.volume * dv * rho2
+        assert abs(np.trace(chi[w]) - rhs) < 1e-12 * abs(rhs)
+
+
+def test_chi0_hermiticity_and_conjugate_frequency():
+    p = _small_problem(z=(0.0, 0.8j, 0.4 + 0.01j, 0.4 - 0.01j))
+    chi = _chi(p)
+    for w in (0, 1):
+        assert np.abs(chi[w] - chi[w].conj().T).max() < 1e-13 * np.abs(chi[w]).max()
+    # chi(z)^H = chi(conj z)
+    assert np.abs(chi[2].conj().T - chi[3]).max() < 1e-13 * np.abs(chi[2]).max()
+    # a complex frequency is not Hermitian (catches a dropped conj/transposition)
+    assert np.abs(chi[2] - chi[2].conj().T).max() > 1e-6 * np.abs(chi[2]).max()
+
+
+def test_chi0_negative_semidefinite_and_rank():
+    p = _small_problem(nv=2, nc=3, r2=6, z=(0.0, 1.3j))
+    chi = _chi(p)
+    assert chi.shape[1] > p.npairs          # more G than pairs -> rank deficient
+    for w in range(2):
+        ev = np.linalg.eigvalsh(chi[w])
+        assert ev.max() <= 1e-13 * np.abs(ev).max()
+        assert np.sum(np.abs(ev) > 1e-10 * np.abs(ev).max()) <= p.npairs
+
+
+def test_chi0_head_and_wings_vanish_at_q0():
+    p = _small_problem()
+    chi = _chi(p)
+    assert tuple(p.gvec[0]) == (0, 0, 0)
+    scale = np.abs(chi).max()
+    assert np.abs(chi[:, 0, :]).max() < 1e-13 * scale
+    assert np.abs(chi[:, :, 0]).max() < 1e-13 * scale
+
+
+def test_chi0_invariances():
+    p = _small_problem()
+    ref = _chi(p)
+    scale = np.abs(ref).max()
+    rng = np.random.default_rng(1)
+    # band phases
+    q = gen.Problem(**{**p.__dict__})
+    q.psi_v = p.psi_v * np.exp(1j * rng.uniform(0, 2 * np.pi, p.nv))[:, None]
+    q.psi_c = p.psi_c * np.exp(1j * rng.uniform(0, 2 * np.pi, p.nc))[:, None]
+    assert np.abs(_chi(q) - ref).max() < 1e-13 * scale
+    # common energy shift
+    q = gen.Problem(**{**p.__dict__})
+    q.e_v, q.e_c = p.e_v + 0.123, p.e_c + 0.123
+    assert np.abs(_chi(q) - ref).max() < 1e-12 * scale
+    # pair order: permute conduction bands together with their energies
+    perm = rng.permutation(p.nc)
+    q = gen.Problem(**{**p.__dict__})
+    q.psi_c, q.e_c = p.psi_c[perm], p.e_c[perm]
+    assert np.abs(_chi(q) - ref).max() < 1e-13 * scale
+    # chunk size
+    for chunk in (1, 4, 1000):
+        assert np.abs(_chi(p, pair_chunk=chunk) - ref).max() < 1e-13 * scale
+
+
+def test_chi0_single_pair_rank_one():
+    p = _small_problem(nv=1, nc=1)
+    chi = _chi(p)
+    m = oracle.mtxel(p.psi_v, p.psi_c, p.gvec, p.n, p.volume)[0]
+    delta = oracle.energy_factor(p.e_v, p.e_c, p.z)[:, 0]
+    for w in range(len(p.z)):
+        want = 2.0 * delta[w] * np.outer(m.conj(), m)
+        assert np.abs(chi[w] - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_chi0_entries_match_full():
+    p = _small_problem(n=(8, 6, 10), r2=5)
+    chi = _chi(p)
+    rows, cols = [0, 3, 7], [1, 2, 8, 11]
+    e = oracle.chi0_entries(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec[rows], p.gvec[cols], p.z,
+                            p.n, p.volume, p.spin)
+    assert np.abs(e - chi[:, rows][:, :, cols]).max() < 1e-13 * np.abs(chi).max()
+
+
+# ---------------------------------------------------------------- adjoint
+
+def _loss(p, a):
+    chi = _chi(p)
+    return float(np.real(np.sum(a * chi, axis=(1, 2)).sum()))
+
+
+def _rand_herm(rng, nz, ng):
+    x = rng.standard_normal((nz, ng, ng)) + 1j * rng.standard_normal((nz, ng, ng))
+    return 0.5 * (x + np.conj(np.transpose(x, (0, 2, 1))))
+
+
+def test_adjoint_matches_central_differences():
+    """L = Re sum_w tr(A_w chi_w) with A Hermitian: dL/dchi = A^T = conj(A), i.e.
+    W = conj(A) in the torch convention (dL = Re sum conj(W) dchi)."""
+    rng = np.random.default_rng(3)
+    p = _small_problem(nv=2, nc=3, r2=3, z=(0.0, 0.7j, 0.2 + 0.01j))
+    a = _rand_herm(rng, len(p.z), p.ng)
+    # tr(A chi) = sum_ij A_ji chi_ij -> dL/dchi_ij (torch) = conj(A_ji)... = conj(A^T)_ij
+    w = np.conj(np.transpose(a, (0, 2, 1)))
+    gv, gc, gev, gec = oracle.chi0_backward(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n,
+                                            p.volume, w, spin=p.spin, pair_chunk=p.pair_chunk)
+    tr = lambda q: float(np.real(sum(np.trace(a[k] @ _chi(q)[k]) for k in range(len(p.z)))))
+    h = 1e-6
+    for trial in range(3):
+        for which in ("psi_v", "psi_c", "e"):
+            q_plus = gen.Problem(**{**p.__dict__})
+            q_minus = gen.Problem(**{**p.__dict__})
+            if which == "e":
+                dv_, dc_ = rng.standard_normal(p.nv), rng.standard_normal(p.nc)
+                q_plus.e_v, q_plus.e_c = p.e_v + h * dv_, p.e_c + h * dc_
+                q_minus.e_v, q_minus.e_c = p.e_v - h * dv_, p.e_c - h * dc_
+                pred = gev @ dv_ + gec @ dc_
+            else:
+                x = getattr(p, which)
+                d = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
+                setattr(q_plus, which, x + h * d)
+                setattr(q_minus, which, x - h * d)
+                g = gv if which == "psi_v" else gc
+                pred = float(np.real(np.sum(np.conj(g) * d)))
+            fd = (tr(q_plus) - tr(q_minus)) / (2 * h)
+            assert abs(fd - pred) < 1e-6 * max(1.0, abs(fd)), (which, fd, pred)
+
+
+def test_adjoint_invariances():
+    rng = np.random.default_rng(4)
+    p = _small_problem(nv=2, nc=4, r2=3, z=(0.0, 0.9j))
+    a = _rand_herm(rng, len(p.z), p.ng)
+    w = np.conj(np.transpose(a, (0, 2, 1)))
+    gv, gc, gev, gec = oracle.chi0_backward(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n,
+                                            p.volume, w, spin=p.spin, pair_chunk=3)
+    scale = np.abs(gev).max() + np.abs(gec).max()
+    assert abs(gev.sum() + gec.sum()) < 1e-12 * scale                 # energy shift
+    for x, g in ((p.psi_v, gv), (p.psi_c, gc)):                        # band phases
+        im = np.imag(np.sum(np.conj(g) * x, axis=1))
+        assert np.abs(im).max() < 1e-11 * np.abs(g).max() * np.abs(x).max() * x.shape[1]
+
+
+def test_adjoint_plane_wave_energy_gradient():
+    """For plane waves, L = Re sum_w tr(A chi_w) = s sum_pairs Re[A_GG Delta(z)] for
+    the G hit by each pair, so dL/dE_v = s sum Re[A_GG dDelta/dE_v]."""
+    n = (6, 6, 6)
+    kv = [(0, 0, 0), (1, 1, 0)]
+    kc = [(1, 0, 0), (0, 0, 1), (2, 1, 0)]
+    pv, pc = _plane_waves(kv, n), _plane_waves(kc, n)
+    e_v, e_c = np.array([-0.2, -0.1]), np.array([0.3, 0.5, 0.8])
+    gl = gen.gsphere(3)
+    z = np.array([0.0, 0.5j])
+    rng = np.random.default_rng(8)
+    a = _rand_herm(rng, 2, len(gl))
+    w = np.conj(np.transpose(a, (0, 2, 1)))
+    _, _, gev, gec = oracle.chi0_backward(pv, pc, e_v, e_c, gl, z, n, VOL, w, spin=2.0)
+    want_v, want_c = np.zeros(2), np.zeros(3)
+    for wi, zz in enumerate(z):
+        for v, c in itertools.product(range(2), range(3)):
+            gdiff = np.array(kv[v]) - np.array(kc[c])
+            hit = np.where(np.all(gl == gdiff, axis=1))[0]
+            if not hit.size:
+                continue
+            de = e_v[v] - e_c[c]
+            dd = -1 / (de + zz) ** 2 - 1 / (de - zz) ** 2
+            val = 2.0 * np.real(a[wi, hit[0], hit[0]] * dd)
+            want_v[v] += val
+            want_c[c] -= val
+    assert np.abs(gev - want_v).max() < 1e-12 * np.abs(want_v).max()
+    assert np.abs(gec - want_c).max() < 1e-12 * np.abs(want_v).max()

@@ -1,0 +1,195 @@
+"""Seeded input recipes for the chi0 build (input preparation only).
+
+Conventions (the paper's statement of the problem, Overview section and
+Eq. (4); the concrete sizes are the five workloads of the benchmark):
+
+* cubic cell of edge ``L = 10`` bohr, volume ``Omega = L**3``;
+* FFT grid ``N1 x N2 x N3``; a real-space array is stored row-major with the
+  third index fastest, ``r = (j1*N2 + j2)*N3 + j3``;
+* wavefunctions are complex128 ``[N_b][N1*N2*N3]``, valence rows first, with
+  iid N(0,1) real and imaginary parts, made orthonormal on the grid in band
+  order (Gram-Schmidt), i.e. ``dV * sum_r conj(psi_m) psi_n = delta_mn`` with
+  ``dV = Omega / (N1*N2*N3)``;
+* valence energies uniform in [-0.4, 0] Ha, conduction energies uniform in
+  [0.05, 1.1] Ha;
+* the G-sphere is the complete set of integer Miller triples with
+  ``|g|^2 <= R^2``, ordered by (|g|^2, lexicographic g);
+* frequencies are complex numbers ``z``: ``omega + i*eta`` on the real axis,
+  ``i*omega`` on the imaginary axis, ``0`` for the static case.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+
+CELL_L = 10.0          # bohr
+SPIN = 2.0             # spin factor of Eq. (4)
+
+# (grid, N_v, N_c, R^2 of the G-sphere, frequency recipe, pair chunk)
+CONFIG_SHAPES = {
+    0: dict(n=(16, 16, 16), nv=4, nc=28, r2=10, freq=("static", 1), pair_chunk=4096),
+    1: dict(n=(48, 48, 48), nv=64, nc=960, r2=61, freq=("real", 4), pair_chunk=4096),
+    2: dict(n=(72, 72, 72), nv=256, nc=3840, r2=126, freq=("imag", 8), pair_chunk=4096),
+    3: dict(n=(32, 32, 32), nv=32, nc=480, r2=42, freq=("static", 1), pair_chunk=4096),
+}
+
+
+@dataclass
+class Problem:
+    """One chi0 problem (one q-point): inputs only."""
+    n: tuple
+    volume: float
+    psi_v: np.ndarray          # complex128 [nv, N_r]
+    psi_c: np.ndarray          # complex128 [nc, N_r]
+    e_v: np.ndarray            # float64 [nv]
+    e_c: np.ndarray            # float64 [nc]
+    gvec: np.ndarray           # int32 [ng, 3]
+    z: np.ndarray              # complex128 [nz]
+    spin: float = SPIN
+    pair_chunk: int = 4096
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nv(self):
+        return self.psi_v.shape[0]
+
+    @property
+    def nc(self):
+        return self.psi_c.shape[0]
+
+    @property
+    def ng(self):
+        return self.gvec.shape[0]
+
+    @property
+    def npairs(self):
+        return self.nv * self.nc
+
+    @property
+    def nr(self):
+        return int(np.prod(self.n))
+
+
+def gsphere(r2: int) -> np.ndarray:
+    """All integer g with |g|^2 <= r2, ordered by (|g|^2, g lexicographic)."""
+    r = int(np.floor(np.sqrt(r2)))
+    ax = np.arange(-r, r + 1)
+    g = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    n2 = (g * g).sum(1)
+    g, n2 = g[n2 <= r2], n2[n2 <= r2]
+    order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], n2))
+    return np.ascontiguousarray(g[order], dtype=np.int32)
+
+
+def gsphere_shifted(q, count: int) -> np.ndarray:
+    """The ``count`` integer g with the smallest |q+g|^2 (q in reciprocal-lattice
+    units of the cubic cell), ties broken lexicographically in g."""
+    q = np.asarray(q, dtype=np.float64)
+    r = int(np.ceil((3.0 * count / (4.0 * np.pi)) ** (1.0 / 3.0))) + 3
+    ax = np.arange(-r, r + 1)
+    g = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    k2 = ((g + q[None, :]) ** 2).sum(1)
+    order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], k2))[:count]
+    return np.ascontiguousarray(g[order], dtype=np.int32)
+
+
+def orthonormal_bands(rng: np.random.Generator, nb: int, n, volume: float,
+                      orthonormalize: bool = True) -> np.ndarray:
+    """Draw ``nb`` complex Gaussian bands on the grid and orthonormalise them
+    in band order (two passes of Cholesky-QR, which equals Gram-Schmidt with a
+    positive-diagonal R in exact arithmetic)."""
+    nr = int(np.prod(n))
+    psi = rng.standard_normal((nb, nr)) + 1j * rng.standard_normal((nb, nr))
+    if not orthonormalize or nb == 0:
+        return psi
+    dv = volume / nr
+    for _ in range(2):
+        gram = dv * (psi.conj() @ psi.T)            # [nb, nb], Hermitian PD
+        lo = np.linalg.cholesky(gram)               # gram = lo lo^H
+        psi = scipy.linalg.solve_triangular(lo.conj(), psi, lower=True,
+                                            overwrite_b=True, check_finite=False)
+    return psi
+
+
+def band_energies(rng: np.random.Generator, nv: int, nc: int):
+    e_v = rng.uniform(-0.4, 0.0, nv)
+    e_c = rng.uniform(0.05, 1.1, nc)
+    return e_v, e_c
+
+
+def frequencies(kind: str, count: int, eta: float = 0.005, omega0: float = 1.0):
+    """Complex frequencies z for the recipes of the benchmark workloads."""
+    if kind == "static":
+        return np.zeros(count, dtype=np.complex128)
+    if kind == "real":
+        return np.linspace(0.0, 1.0, count) + 1j * eta
+    if kind == "imag":
+        x, _ = np.polynomial.legendre.leggauss(count)
+        omega = omega0 * (1.0 + x) / (1.0 - x)
+        return 1j * omega
+    raise ValueError(kind)
+
+
+def make_problem(n, nv: int, nc: int, *, r2=None, gvec=None, z=(0.0,), seed: int = 0,
+                 cell_l: float = CELL_L, pair_chunk: int = 4096, spin: float = SPIN,
+                 orthonormalize: bool = True) -> Problem:
+    """Generic seeded problem.  Draw order: psi (real parts, then imaginary
+    parts, valence rows first), orthonormalise, then E_v, then E_c."""
+    n = tuple(int(x) for x in n)
+    volume = cell_l ** 3
+    rng = np.random.default_rng(seed)
+    psi = orthonormal_bands(rng, nv + nc, n, volume, orthonormalize)
+    e_v, e_c = band_energies(rng, nv, nc)
+    if gvec is None:
+        gvec = gsphere(r2)
+    gvec = np.ascontiguousarray(gvec, dtype=np.int32)
+    return Problem(n=n, volume=volume,
+                   psi_v=np.ascontiguousarray(psi[:nv]), psi_c=np.ascontiguousarray(psi[nv:]),
+                   e_v=e_v, e_c=e_c, gvec=gvec,
+                   z=np.asarray(z, dtype=np.complex128).reshape(-1),
+                   spin=spin, pair_chunk=pair_chunk, meta=dict(seed=seed))
+
+
+def make_config(index: int, **overrides) -> Problem:
+    """Workloads 0-3 at their full sizes (seed = workload index)."""
+    s = dict(CONFIG_SHAPES[index])
+    s.update(overrides)
+    z = frequencies(*s["freq"])
+    p = make_problem(s["n"], s["nv"], s["nc"], r2=s["r2"], z=z, seed=index,
+                     pair_chunk=s["pair_chunk"])
+    p.meta["config"] = index
+    return p
+
+
+def batched_shapes(nq_side: int = 4):
+    """q-points of the shifted Monkhorst-Pack grid and the uneven per-q sizes
+    of the batched workload: N_G(q) = round(400*10**(j/63)) and
+    N_c(q) = round(300 + 600*j'/63), assigned by two seeded permutations."""
+    frac = (2.0 * np.arange(nq_side) - nq_side + 1) / (2.0 * nq_side)   # -3/8 .. 3/8
+    qs = np.stack(np.meshgrid(frac, frac, frac, indexing="ij"), -1).reshape(-1, 3)
+    nq = qs.shape[0]
+    rng = np.random.default_rng(4)
+    j_ng = rng.permutation(nq)
+    j_nc = rng.permutation(nq)
+    ng = np.rint(400.0 * 10.0 ** (j_ng / (nq - 1))).astype(int)
+    nc = np.rint(300.0 + 600.0 * j_nc / (nq - 1)).astype(int)
+    return qs, ng, nc
+
+
+def make_batched_config(q_indices=None, *, nv: int = 48, n=(40, 40, 40), nfreq: int = 16,
+                        orthonormalize: bool = True):
+    """The batched multi-q workload: one independent problem per q-point."""
+    qs, ng, nc = batched_shapes()
+    if q_indices is None:
+        q_indices = range(qs.shape[0])
+    z = frequencies("imag", nfreq)
+    probs = []
+    for qi in q_indices:
+        g = gsphere_shifted(qs[qi], int(ng[qi]))
+        p = make_problem(n, nv, int(nc[qi]), gvec=g, z=z, seed=4000 + int(qi),
+                         orthonormalize=orthonormalize)
+        p.meta.update(config=4, q_index=int(qi), q=qs[qi].tolist())
+        probs.append(p)
+    return probs
