@@ -1,0 +1,190 @@
+/*
+ * gw.h -- C ABI of libgw, the MI355X (gfx950) chi0 library.
+ *
+ * The library builds the independent-particle polarizability of Eq. (4) of
+ * the paper,
+ *
+ *     chi_GG'(z) = s * sum_{v,c} conj(M_vc(G)) * Delta_vc(z) * M_vc(G'),
+ *
+ * from real-space wavefunctions on an FFT grid, band energies, a list of
+ * G-vectors (Miller indices) and complex frequencies, in two parts:
+ *
+ *   MTXEL  the plane-wave matrix elements defined in the Overview section
+ *          (after Eq. (2)):  M_vc(G) = dV * sum_r conj(psi_v(r)) psi_c(r)
+ *          exp(+i G.r), read on the G-sphere;
+ *   CHI0   the dense complex contraction M^H * diag(s*Delta(z)) * M, summed
+ *          over chunks of pairs (the paper's NV-Block idea of splitting the
+ *          sum over bands so that M never exists whole).
+ *
+ * The energy factor, which the paper leaves as "a function of E_v, E_c and
+ * the frequency", is taken as the resonant plus anti-resonant form
+ *     Delta_vc(z) = 1/(E_v - E_c + z) + 1/(E_v - E_c - z),
+ * with z = w + i*eta (real axis), z = i*w (imaginary axis) or z = 0 (static).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are interleaved (re, im) doubles, bit-compatible with
+ *   C99 double _Complex, std::complex<double> and torch.complex128.
+ * - A real-space grid array has N1*N2*N3 elements, row-major with the third
+ *   index fastest: r = (j1*N2 + j2)*N3 + j3.  A band set is [nbands][N_r].
+ * - A Miller triple g = (g1, g2, g3) stands for G.r_j = 2*pi*(g1*j1/N1 +
+ *   g2*j2/N2 + g3*j3/N3); each g_i must lie in [-floor(N_i/2), ceil(N_i/2) - 1]
+ *   and the list must hold no duplicate.
+ * - Pairs are numbered p = v*nc + c.
+ * - dV = volume / (N1*N2*N3); the library applies no 1/Omega or 1/N_k factor.
+ * - Device pointers are HIP device memory of the current device; host
+ *   pointers are ordinary host memory, read before the call returns.
+ * - All work is enqueued on `stream` (a hipStream_t, NULL = legacy default
+ *   stream) and the call returns without synchronising.  The caller owns
+ *   every pointer it passes and must keep device buffers alive until the
+ *   stream reaches the end of the call's work.  The library owns only its
+ *   cached plans (gather tables) and scratch buffers, one set per device and
+ *   stream; gw_release() frees them.  Two calls that run concurrently on the
+ *   same stream are serialised by the stream; the host side is thread-safe.
+ * - Errors: every argument check runs on the host before anything is
+ *   enqueued; a non-OK status leaves every output untouched and
+ *   gw_last_error() returns a message (thread-local).  No C++ exception
+ *   crosses this interface.  A fault inside a kernel surfaces at the
+ *   caller's next synchronisation.  A singular energy factor (E_v - E_c = +-z)
+ *   is not detected (the energies live on the device) and propagates as
+ *   Inf/NaN.
+ */
+#ifndef GW_H
+#define GW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GW_ABI_VERSION 1
+
+typedef struct { double re, im; } gw_c128;
+
+/* FFT grid N1 x N2 x N3 and cell volume Omega (bohr^3). */
+typedef struct {
+    int32_t n[3];
+    double  volume;
+} gw_grid_t;
+
+typedef int32_t gw_status_t;
+enum {
+    GW_OK           = 0,
+    GW_EINVAL       = -1,   /* bad argument (message says which) */
+    GW_ENOMEM       = -2,   /* device allocation of library scratch failed */
+    GW_EHIP         = -3,   /* a HIP runtime call failed */
+    GW_EUNSUPPORTED = -4,   /* valid request this build does not implement */
+    GW_EINTERNAL    = -5
+};
+
+/* Arithmetic of the CHI0 contraction.  MTXEL, the energy factor, the slice
+ * recombination and the chi accumulation are FP64 in every mode. */
+typedef int32_t gw_precision_t;
+enum {
+    GW_FP64       = 0,      /* FP64 MFMA */
+    GW_FP32       = 1,      /* operands rounded to FP32, FP32 products */
+    GW_SPLIT_BF16 = 2,      /* fixed-point slices in BF16, FP32 accumulation */
+    GW_SPLIT_FP16 = 3       /* fixed-point slices in FP16, FP32 accumulation */
+};
+
+/* gw_opts_t.flags */
+#define GW_FLAG_NO_HERMITIAN  (1u << 0)  /* compute every tile even when Delta is real */
+#define GW_FLAG_ACCUMULATE    (1u << 1)  /* chi += result instead of chi = result */
+
+/* One chi0 problem (one q-point). */
+typedef struct {
+    gw_grid_t       grid;
+    const gw_c128*  psi_v;  /* device [nv][N_r] */
+    int32_t         nv;
+    const gw_c128*  psi_c;  /* device [nc][N_r] */
+    int32_t         nc;
+    const double*   e_v;    /* device [nv], Hartree */
+    const double*   e_c;    /* device [nc], Hartree */
+    const int32_t*  gvec;   /* HOST   [ng][3] Miller indices */
+    int32_t         ng;
+    const gw_c128*  z;      /* HOST   [nz] complex frequencies, Hartree */
+    int32_t         nz;
+    gw_c128*        chi;    /* device OUT [nz][ng][ng], row index = G, column = G' */
+} gw_problem_t;
+
+typedef struct {
+    gw_precision_t precision;   /* GW_FP64 ... */
+    int32_t        n_slices;    /* split modes: slices per operand (2..8); ignored otherwise */
+    int32_t        pair_chunk;  /* pairs per streamed M chunk; 0 = 4096 */
+    uint32_t       flags;       /* GW_FLAG_* */
+    double         spin;        /* spin factor s of Eq. (4); 0 = 2 */
+} gw_opts_t;
+
+/*
+ * gw_mtxel -- plane-wave matrix elements (Overview section, after Eq. (2)).
+ *
+ *   m_out[k][i] = dV * sum_r conj(psi_v[v](r)) * psi_c[c](r) * exp(+i G_i.r)
+ *   for k in [0, pair_count), p = pair_begin + k = v*nc + c.
+ *
+ * grid      host; N_i >= 1, N1*N2*N3 < 2^31.
+ * psi_v     device [nv][N_r];  psi_c device [nc][N_r] (may alias psi_v).
+ * gvec      HOST [ng][3], ng >= 1.
+ * m_out     device [pair_count][ng], overwritten.
+ * Returns GW_EINVAL for a NULL pointer with a non-zero size, a Miller index
+ * out of range, a duplicate G, or a pair range outside [0, nv*nc).
+ */
+gw_status_t gw_mtxel(const gw_grid_t* grid,
+                     const gw_c128* psi_v, int32_t nv,
+                     const gw_c128* psi_c, int32_t nc,
+                     const int32_t* gvec, int32_t ng,
+                     int64_t pair_begin, int64_t pair_count,
+                     gw_c128* m_out, void* stream);
+
+/*
+ * gw_chi0 -- polarizability of Eq. (4) for `nprob` independent problems
+ * (q-points), each with its own grid, bands, G list and frequencies.
+ *
+ *   probs[q].chi[w][i][j] (=, or += with GW_FLAG_ACCUMULATE)
+ *       s * sum_p Delta_p(z_w) * conj(M_p(G_i)) * M_p(G_j)
+ *
+ * M is streamed in chunks of opts->pair_chunk pairs through a library
+ * scratch buffer and never stored whole.  When every z_w of a problem has a
+ * zero real part, Delta is real, chi is Hermitian, and only the tiles on or
+ * above the diagonal are contracted; the rest are mirrored (unless
+ * GW_FLAG_NO_HERMITIAN).  nv*nc == 0 yields chi = 0.
+ * opts may be NULL (FP64, chunk 4096, s = 2).  Returns GW_EUNSUPPORTED for a
+ * precision this build does not implement.
+ */
+gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob,
+                    const gw_opts_t* opts, void* stream);
+
+/*
+ * gw_chi0_backward -- adjoint of gw_chi0 for one problem (FP64), for a real
+ * loss L in PyTorch's complex convention (grad of complex x =
+ * dL/dRe x + i dL/dIm x).  grad_chi = dL/dchi, device [nz][ng][ng].
+ *
+ *   g_M,p  = s * sum_w [conj(Delta_p) W_w^T m_p + Delta_p conj(W_w) m_p]
+ *   dL/dE_v = s * sum_w sum_c Re[dDelta/dE_v * m^H conj(W_w) m],
+ *   dL/dE_c = -(same summand) summed over v
+ *   g_rho(r) = dV * sum_G g_M(G) exp(-i G.r)
+ *   dL/dpsi_c = sum_v psi_v * g_rho,  dL/dpsi_v = sum_c psi_c * conj(g_rho)
+ *
+ * M chunks are recomputed, not stored.  Outputs (device, overwritten):
+ * grad_psi_v [nv][N_r], grad_psi_c [nc][N_r], grad_e_v [nv], grad_e_c [nc];
+ * any of them may be NULL to skip it.  prob->chi is not read.
+ */
+gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
+                             gw_c128* grad_psi_v, gw_c128* grad_psi_c,
+                             double* grad_e_v, double* grad_e_c,
+                             const gw_opts_t* opts, void* stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* gw_last_error(void);
+
+/* Frees cached plans and scratch on every device (synchronises the device). */
+gw_status_t gw_release(void);
+
+/* GW_ABI_VERSION of the built library. */
+int32_t gw_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GW_H */

@@ -1,0 +1,450 @@
+// Adjoint of the chi0 build on gfx950 (not in the paper: the chain rule
+// through Eq. (4) and through the plane-wave matrix elements, the quantity a
+// perturbation-theory variant of GW needs as the first-order change of M).
+//
+// Per chunk of pairs (M recomputed, never stored):
+//   P1 = M W_w, P2 = M W_w^H                    FP64 MFMA, fused epilogue:
+//   g_M  = sum_w conj(s Delta_w) P1 + (s Delta_w) P2
+//   q_wp = m_p^H conj(W_w) m_p = sum_i conj(M[p][i]) P2[p][i]   (partials per tile)
+//   dL/dE_v = s sum_w sum_c Re[dDelta/dE_v q],  dL/dE_c = -(same) over v
+//   g_rho = dV sum_G g_M(G) e^{-i G.r}           pruned inverse transform
+//   dL/dpsi_c += psi_v g_rho,  dL/dpsi_v += psi_c conj(g_rho)  (ordered sums)
+// Every reduction runs in a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cstdint>
+
+#include "backward.hpp"
+#include "chi0.hpp"
+#include "common.hpp"
+
+namespace gw {
+
+namespace {
+
+__global__ __launch_bounds__(256) void ddelta_kernel(const double* __restrict__ e_v,
+                                                     const double* __restrict__ e_c, PairMap pm,
+                                                     int64_t npairs, ZArgs za, int w0,
+                                                     double2* __restrict__ dd) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= npairs) return;
+    const int64_t lin = pm.k_off + k;
+    const double de = e_v[pm.v0 + lin / pm.cw] - e_c[pm.c0 + lin % pm.cw];
+    for (int w = 0; w < za.nz; ++w) {
+        const double zr = za.re[w], zi = za.im[w];
+        // -(de + z)^-2 - (de - z)^-2 with (x)^-1 = conj(x)/|x|^2
+        const double ar = de + zr, br = de - zr;
+        const double na = ar * ar + zi * zi, nb = br * br + zi * zi;
+        const double2 ia = make_double2(ar / na, -zi / na);
+        const double2 ib = make_double2(br / nb, zi / nb);
+        const double2 a2 = cmul(ia, ia), b2 = cmul(ib, ib);
+        dd[static_cast<int64_t>(w0 + w) * npairs + k] = make_double2(-a2.x - b2.x, -a2.y - b2.y);
+    }
+}
+
+// P1 = M W and P2 = M W^H for one 64 (pairs) x 64 (G) tile; fused epilogue.
+__global__ __launch_bounds__(256) void bwd_gm_kernel(const double2* __restrict__ m, int64_t kc,
+                                                     int ng, const double2* __restrict__ w,
+                                                     const double2* __restrict__ delta,
+                                                     double2* __restrict__ gm,
+                                                     double2* __restrict__ qpart, int mode) {
+    __shared__ double2 s_a[64][17];
+    __shared__ double2 s_b1[16][64];
+    __shared__ double2 s_b2[16][64];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * 64;
+    const int i0 = blockIdx.x * 64;
+
+    dbl4 p1r[2][2], p1i[2][2], p2r[2][2], p2i[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) p1r[x][y] = p1i[x][y] = p2r[x][y] = p2i[x][y] = zero4();
+
+    for (int j0 = 0; j0 < ng; j0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            {
+                const int rr = e >> 4, jj = e & 15;
+                const int64_t k = k0 + rr;
+                s_a[rr][jj] = (k < kc && j0 + jj < ng) ? m[k * ng + j0 + jj] : make_double2(0.0, 0.0);
+            }
+            {
+                const int jj = e >> 6, ii = e & 63;
+                s_b1[jj][ii] = (j0 + jj < ng && i0 + ii < ng)
+                                   ? w[static_cast<int64_t>(j0 + jj) * ng + i0 + ii]
+                                   : make_double2(0.0, 0.0);
+            }
+            {
+                const int ii = e >> 4, jj = e & 15;
+                double2 val = make_double2(0.0, 0.0);
+                if (i0 + ii < ng && j0 + jj < ng) {
+                    const double2 x = w[static_cast<int64_t>(i0 + ii) * ng + j0 + jj];
+                    val = make_double2(x.x, -x.y);
+                }
+                s_b2[jj][ii] = val;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double2 a[2], b1[2], b2[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                a[x] = s_a[wi * 32 + x * 16 + row][s * 4 + kq];
+                b1[x] = s_b1[s * 4 + kq][wj * 32 + x * 16 + row];
+                b2[x] = s_b2[s * 4 + kq][wj * 32 + x * 16 + row];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    cmfma(p1r[x][y], p1i[x][y], a[x].x, a[x].y, b1[y].x, b1[y].y);
+                    cmfma(p2r[x][y], p2i[x][y], a[x].x, a[x].y, b2[y].x, b2[y].y);
+                }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t r = k0 + wi * 32 + x * 16 + 4 * t + kq;
+            const bool rok = r < kc;
+            const double2 d = rok ? delta[r] : make_double2(0.0, 0.0);
+            double qre = 0.0, qim = 0.0;
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int c = i0 + wj * 32 + y * 16 + row;
+                if (rok && c < ng) {
+                    const double2 a = make_double2(p1r[x][y][t], p1i[x][y][t]);
+                    const double2 b = make_double2(p2r[x][y][t], p2i[x][y][t]);
+                    double2 g = cmul_conj_a(d, a);
+                    const double2 h = cmul(d, b);
+                    g.x += h.x;
+                    g.y += h.y;
+                    double2* dst = gm + r * ng + c;
+                    if (mode) {
+                        const double2 o = *dst;
+                        g.x += o.x;
+                        g.y += o.y;
+                    }
+                    *dst = g;
+                    const double2 q = cmul_conj_a(m[r * ng + c], b);
+                    qre += q.x;
+                    qim += q.y;
+                }
+            }
+            // sum over the 16 lanes that share this row (same kq)
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                qre += __shfl_xor(qre, off, 64);
+                qim += __shfl_xor(qim, off, 64);
+            }
+            if (row == 0 && rok)
+                qpart[static_cast<int64_t>(blockIdx.x * 2 + wj) * kc + r] = make_double2(qre, qim);
+        }
+}
+
+__global__ __launch_bounds__(256) void de_kernel(const double2* __restrict__ qpart, int nparts,
+                                                 int nz, int64_t kc, const double2* __restrict__ dd,
+                                                 double spin, double* __restrict__ de) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= kc) return;
+    double acc = 0.0;
+    for (int w = 0; w < nz; ++w) {
+        double qr = 0.0, qi = 0.0;
+        for (int p = 0; p < nparts; ++p) {
+            const double2 q = qpart[(static_cast<int64_t>(w) * nparts + p) * kc + k];
+            qr += q.x;
+            qi += q.y;
+        }
+        const double2 d = dd[static_cast<int64_t>(w) * kc + k];
+        acc += d.x * qr - d.y * qi;
+    }
+    de[k] = spin * acc;
+}
+
+__global__ __launch_bounds__(256) void de_reduce_kernel(const double* __restrict__ de, int vcount,
+                                                        int cw, int v0, int c0,
+                                                        double* __restrict__ g_ev,
+                                                        double* __restrict__ g_ec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g_ev && i < vcount) {
+        double acc = 0.0;
+        for (int c = 0; c < cw; ++c) acc += de[static_cast<int64_t>(i) * cw + c];
+        g_ev[v0 + i] += acc;
+    }
+    if (g_ec && i < cw) {
+        double acc = 0.0;
+        for (int v = 0; v < vcount; ++v) acc += de[static_cast<int64_t>(v) * cw + i];
+        g_ec[c0 + i] -= acc;
+    }
+}
+
+// U[k][j1][d] = sum_{G in disc d} e^{-2 pi i k1(G) j1/N1} gm[k][G]
+__global__ __launch_bounds__(256) void bx_kernel(const double2* __restrict__ gm, int ng, int n1,
+                                                 int n23, const double2* __restrict__ root1,
+                                                 const int* __restrict__ g_k1,
+                                                 const int* __restrict__ disc_ptr,
+                                                 const int* __restrict__ disc_g, int64_t pair0,
+                                                 double2* __restrict__ u) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n1 * n23) return;
+    const int64_t k = pair0 + blockIdx.y;
+    const int j1 = idx / n23, d = idx - j1 * n23;
+    double re = 0.0, im = 0.0;
+    const double2* src = gm + k * ng;
+    for (int e = disc_ptr[d]; e < disc_ptr[d + 1]; ++e) {
+        const int g = disc_g[e];
+        const double2 w = root1[(g_k1[g] * j1) % n1];
+        const double2 x = src[g];
+        re += w.x * x.x + w.y * x.y;  // conj(w) * x
+        im += w.x * x.y - w.y * x.x;
+    }
+    u[(k * n1 + j1) * n23 + d] = make_double2(re, im);
+}
+
+// V[k][j1][j2][k3i] = sum_{k2i} e^{-2 pi i k2 j2/N2} U[k][j1][disc(k2i, k3i)]
+__global__ __launch_bounds__(256) void by_kernel(const double2* __restrict__ u, int n1, int n2,
+                                                 int n23, int m2, int m3, int bw3,
+                                                 const int* __restrict__ boxmap,
+                                                 const int* __restrict__ k2val,
+                                                 const double2* __restrict__ root2, int64_t pair0,
+                                                 double2* __restrict__ vout) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= static_cast<int64_t>(n1) * n2 * m3) return;
+    const int64_t k = pair0 + blockIdx.y;
+    const int k3i = static_cast<int>(idx % m3);
+    const int j2 = static_cast<int>((idx / m3) % n2);
+    const int j1 = static_cast<int>(idx / (static_cast<int64_t>(m3) * n2));
+    const double2* src = u + (k * n1 + j1) * n23;
+    double re = 0.0, im = 0.0;
+    for (int k2i = 0; k2i < m2; ++k2i) {
+        const int d = boxmap[k2i * bw3 + k3i];
+        if (d < 0) continue;
+        const double2 w = root2[(k2val[k2i] * j2) % n2];
+        const double2 x = src[d];
+        re += w.x * x.x + w.y * x.y;
+        im += w.x * x.y - w.y * x.x;
+    }
+    vout[(k * n1 * n2 + static_cast<int64_t>(j1) * n2 + j2) * m3 + k3i] = make_double2(re, im);
+}
+
+// g_rho[k][r] = dV * sum_{k3i} e^{-2 pi i k3 j3/N3} V[k][j1][j2][k3i]
+__global__ __launch_bounds__(256) void bz_kernel(const double2* __restrict__ vin, int64_t nr,
+                                                 int n3, int m3, const int* __restrict__ k3val,
+                                                 const double2* __restrict__ root3, double dv,
+                                                 int64_t pair0, double2* __restrict__ grho) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int64_t k = pair0 + blockIdx.y;
+    const int j3 = static_cast<int>(r % n3);
+    const int64_t j12 = r / n3;
+    const double2* src = vin + (k * (nr / n3) + j12) * m3;
+    double re = 0.0, im = 0.0;
+    for (int k3i = 0; k3i < m3; ++k3i) {
+        const double2 w = root3[(k3val[k3i] * j3) % n3];
+        const double2 x = src[k3i];
+        re += w.x * x.x + w.y * x.y;
+        im += w.x * x.y - w.y * x.x;
+    }
+    grho[k * nr + r] = make_double2(dv * re, dv * im);
+}
+
+// grad_psi_c[c0 + cl] += sum_vl psi_v[v0 + vl] * g_rho[vl*cw + cl]
+__global__ __launch_bounds__(256) void reduce_c_kernel(const double2* __restrict__ grho,
+                                                       const double2* __restrict__ psi_v,
+                                                       int64_t nr, int v0, int c0, int cw,
+                                                       int vcount, int cl0,
+                                                       double2* __restrict__ gpc) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int cl = cl0 + blockIdx.y;
+    double re = 0.0, im = 0.0;
+    for (int vl = 0; vl < vcount; ++vl) {
+        const double2 a = psi_v[static_cast<int64_t>(v0 + vl) * nr + r];
+        const double2 b = grho[(static_cast<int64_t>(vl) * cw + cl) * nr + r];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+    }
+    double2* dst = gpc + static_cast<int64_t>(c0 + cl) * nr + r;
+    const double2 o = *dst;
+    *dst = make_double2(o.x + re, o.y + im);
+}
+
+// grad_psi_v[v0 + vl] += sum_cl psi_c[c0 + cl] * conj(g_rho[vl*cw + cl])
+__global__ __launch_bounds__(256) void reduce_v_kernel(const double2* __restrict__ grho,
+                                                       const double2* __restrict__ psi_c,
+                                                       int64_t nr, int v0, int c0, int cw,
+                                                       int vl0, double2* __restrict__ gpv) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int vl = vl0 + blockIdx.y;
+    double re = 0.0, im = 0.0;
+    for (int cl = 0; cl < cw; ++cl) {
+        const double2 a = psi_c[static_cast<int64_t>(c0 + cl) * nr + r];
+        const double2 b = grho[(static_cast<int64_t>(vl) * cw + cl) * nr + r];
+        re += a.x * b.x + a.y * b.y;  // a * conj(b)
+        im += a.y * b.x - a.x * b.y;
+    }
+    double2* dst = gpv + static_cast<int64_t>(v0 + vl) * nr + r;
+    const double2 o = *dst;
+    *dst = make_double2(o.x + re, o.y + im);
+}
+
+__global__ __launch_bounds__(256) void fill_zero_f64_kernel(double* __restrict__ p, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0.0;
+}
+
+void fill_zero_f64(double* p, int64_t n, hipStream_t s) {
+    if (!p || n <= 0) return;
+    const int64_t blocks = std::min<int64_t>(ceil_div64(n, 256), 65536);
+    hipLaunchKernelGGL(fill_zero_f64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       p, n);
+    GW_HIP_TRY(hipGetLastError());
+}
+
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~static_cast<size_t>(255);
+        return o;
+    }
+};
+
+constexpr int kYMax = 65535;  // gridDim.y limit
+
+}  // namespace
+
+void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const double2* grad_chi,
+                       double2* grad_psi_v, double2* grad_psi_c, double* grad_e_v,
+                       double* grad_e_c, double spin, int pair_chunk, hipStream_t s,
+                       const std::function<void*(size_t)>& get_scratch) {
+    const int64_t nr = plan.nr;
+    const int ng = p.ng, nz = p.nz;
+    const int n1 = plan.n[0], n2 = plan.n[1], n3 = plan.n[2];
+    launch_fill_zero(grad_psi_v, grad_psi_v ? static_cast<int64_t>(p.nv) * nr : 0, s);
+    launch_fill_zero(grad_psi_c, grad_psi_c ? static_cast<int64_t>(p.nc) * nr : 0, s);
+    fill_zero_f64(grad_e_v, p.nv, s);
+    fill_zero_f64(grad_e_c, p.nc, s);
+    const int64_t npairs = static_cast<int64_t>(p.nv) * p.nc;
+    const bool want_psi = grad_psi_v || grad_psi_c;
+    const bool want_e = grad_e_v || grad_e_c;
+    if (npairs == 0 || (!want_psi && !want_e)) return;
+
+    // chunk rectangle, capped so that the per-pair grids stay within 2 GiB
+    const int64_t per_pair = std::max<int64_t>(
+        nr, static_cast<int64_t>(n1) * n2 * plan.m3) * static_cast<int64_t>(sizeof(double2));
+    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
+    const int chunk = static_cast<int>(std::min<int64_t>(pair_chunk, cap));
+    const int cwmax = std::min(p.nc, chunk);
+    const int vb = std::max(1, std::min(p.nv, chunk / std::max(1, cwmax)));
+    const int64_t kmax = static_cast<int64_t>(vb) * cwmax;
+    const int nparts = 2 * ceil_div(ng, 64);
+
+    Carve cv;
+    const size_t o_m = cv.take(kmax * ng * sizeof(double2));
+    const size_t o_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
+    const size_t o_d = cv.take(kmax * nz * sizeof(double2));
+    const size_t o_dd = cv.take(kmax * nz * sizeof(double2));
+    const size_t o_gm = cv.take(kmax * ng * sizeof(double2));
+    const size_t o_q = cv.take(kmax * nz * nparts * sizeof(double2));
+    const size_t o_de = cv.take(kmax * sizeof(double));
+    const size_t o_v = cv.take(want_psi ? kmax * n1 * n2 * plan.m3 * sizeof(double2) : 0);
+    const size_t o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
+    char* base = static_cast<char*>(get_scratch(cv.off));
+    double2* mbuf = reinterpret_cast<double2*>(base + o_m);
+    double2* t2 = reinterpret_cast<double2*>(base + o_t2);
+    double2* dbuf = reinterpret_cast<double2*>(base + o_d);
+    double2* ddbuf = reinterpret_cast<double2*>(base + o_dd);
+    double2* gm = reinterpret_cast<double2*>(base + o_gm);
+    double2* qpart = reinterpret_cast<double2*>(base + o_q);
+    double* de = reinterpret_cast<double*>(base + o_de);
+    double2* vbuf = reinterpret_cast<double2*>(base + o_v);
+    double2* grho = reinterpret_cast<double2*>(base + o_rho);
+    const double2* z = reinterpret_cast<const double2*>(p.z);
+    const double2* psi_v = reinterpret_cast<const double2*>(p.psi_v);
+    const double2* psi_c = reinterpret_cast<const double2*>(p.psi_c);
+    const double dv = p.grid.volume / static_cast<double>(nr);
+
+    for (int v0 = 0; v0 < p.nv; v0 += vb) {
+        for (int c0 = 0; c0 < p.nc; c0 += cwmax) {
+            const int vcount = std::min(vb, p.nv - v0);
+            const int cw = std::min(cwmax, p.nc - c0);
+            const int64_t kc = static_cast<int64_t>(vcount) * cw;
+            PairMap pm{0, cw, v0, c0};
+            launch_mtxel(plan, psi_v, psi_c, pm, kc, p.grid.volume, t2, mbuf, s);
+            launch_delta(p.e_v, p.e_c, pm, kc, z, nz, spin, dbuf, s);
+            for (int w0 = 0; w0 < nz; w0 += kMaxZ) {
+                ZArgs za{};
+                za.nz = std::min(kMaxZ, nz - w0);
+                for (int w = 0; w < za.nz; ++w) {
+                    za.re[w] = z[w0 + w].x;
+                    za.im[w] = z[w0 + w].y;
+                }
+                hipLaunchKernelGGL(ddelta_kernel, dim3(static_cast<unsigned>(ceil_div64(kc, 256))),
+                                   dim3(256), 0, s, p.e_v, p.e_c, pm, kc, za, w0, ddbuf);
+                GW_HIP_TRY(hipGetLastError());
+            }
+            for (int w = 0; w < nz; ++w) {
+                hipLaunchKernelGGL(bwd_gm_kernel,
+                                   dim3(ceil_div(ng, 64), static_cast<unsigned>(ceil_div64(kc, 64))),
+                                   dim3(256), 0, s, mbuf, kc, ng,
+                                   grad_chi + static_cast<int64_t>(w) * ng * ng, dbuf + w * kc, gm,
+                                   qpart + static_cast<int64_t>(w) * nparts * kc, w > 0 ? 1 : 0);
+                GW_HIP_TRY(hipGetLastError());
+            }
+            if (want_e) {
+                hipLaunchKernelGGL(de_kernel, dim3(static_cast<unsigned>(ceil_div64(kc, 256))),
+                                   dim3(256), 0, s, qpart, nparts, nz, kc, ddbuf, spin, de);
+                GW_HIP_TRY(hipGetLastError());
+                hipLaunchKernelGGL(de_reduce_kernel, dim3(ceil_div(std::max(vcount, cw), 256)),
+                                   dim3(256), 0, s, de, vcount, cw, v0, c0, grad_e_v, grad_e_c);
+                GW_HIP_TRY(hipGetLastError());
+            }
+            if (!want_psi) continue;
+            for (int64_t k0 = 0; k0 < kc; k0 += kYMax) {
+                const unsigned kb = static_cast<unsigned>(std::min<int64_t>(kYMax, kc - k0));
+                hipLaunchKernelGGL(bx_kernel, dim3(ceil_div(n1 * plan.n23, 256), kb), dim3(256), 0,
+                                   s, gm, ng, n1, plan.n23, plan.root1, plan.g_k1, plan.disc_ptr,
+                                   plan.disc_g, k0, t2);
+                GW_HIP_TRY(hipGetLastError());
+                hipLaunchKernelGGL(by_kernel,
+                                   dim3(static_cast<unsigned>(ceil_div64(
+                                            static_cast<int64_t>(n1) * n2 * plan.m3, 256)),
+                                        kb),
+                                   dim3(256), 0, s, t2, n1, n2, plan.n23, plan.m2, plan.m3,
+                                   plan.nb3 * 16, plan.boxmap, plan.k2val, plan.root2, k0, vbuf);
+                GW_HIP_TRY(hipGetLastError());
+                hipLaunchKernelGGL(bz_kernel, dim3(static_cast<unsigned>(ceil_div64(nr, 256)), kb),
+                                   dim3(256), 0, s, vbuf, nr, n3, plan.m3, plan.k3val, plan.root3,
+                                   dv, k0, grho);
+                GW_HIP_TRY(hipGetLastError());
+            }
+            if (grad_psi_c)
+                for (int cl0 = 0; cl0 < cw; cl0 += kYMax)
+                    hipLaunchKernelGGL(reduce_c_kernel,
+                                       dim3(static_cast<unsigned>(ceil_div64(nr, 256)),
+                                            std::min(kYMax, cw - cl0)),
+                                       dim3(256), 0, s, grho, psi_v, nr, v0, c0, cw, vcount, cl0,
+                                       grad_psi_c);
+            if (grad_psi_v)
+                for (int vl0 = 0; vl0 < vcount; vl0 += kYMax)
+                    hipLaunchKernelGGL(reduce_v_kernel,
+                                       dim3(static_cast<unsigned>(ceil_div64(nr, 256)),
+                                            std::min(kYMax, vcount - vl0)),
+                                       dim3(256), 0, s, grho, psi_c, nr, v0, c0, cw, vl0,
+                                       grad_psi_v);
+            GW_HIP_TRY(hipGetLastError());
+        }
+    }
+}
+
+}  // namespace gw

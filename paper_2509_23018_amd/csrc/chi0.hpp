@@ -1,0 +1,37 @@
+// Host entry points of the CHI0 kernels (internal to libgw).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace gw {
+
+constexpr int kMaxZ = 32;  // frequencies per energy-factor launch
+
+struct ZArgs {
+    double re[kMaxZ];
+    double im[kMaxZ];
+    double spin;
+    int nz;
+};
+
+// delta[w][k] = s * (1/(E_v - E_c + z_w) + 1/(E_v - E_c - z_w)) for the pairs of pm.
+void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npairs,
+                  const double2* z, int nz, double spin, double2* delta, hipStream_t s);
+
+// chi (=|+=) M^H diag(delta) M for one frequency; M is [kc][ng].  With herm,
+// only tiles on or above the diagonal are written.
+void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta, double2* chi,
+                     bool herm, bool accumulate, hipStream_t s);
+
+// Fill the tiles strictly below the diagonal from the conjugate transpose.
+void launch_mirror(double2* chi, int ng, hipStream_t s);
+
+void launch_fill_zero(double2* p, int64_t n, hipStream_t s);
+
+int chi0_tile();
+
+}  // namespace gw

@@ -1,0 +1,69 @@
+// Per-(grid, G-list) plan of the pruned transform used by MTXEL and its
+// adjoint, and the host entry points of the kernels (internal to libgw).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+namespace gw {
+
+// Pairs handled by one launch: pair k (0-based within the launch) is
+// lin = k_off + k, v = v0 + lin / cw, c = c0 + lin % cw.
+struct PairMap {
+    int64_t k_off;
+    int32_t cw;
+    int32_t v0;
+    int32_t c0;
+};
+
+// Pruned 3D DFT on the G-sphere.  The transform of a pair density rho(j1,j2,j3)
+// is taken axis by axis, keeping on each axis only the frequencies some G
+// needs:
+//   stage z : T1[j1][j2][k3]  = sum_j3 e^{+2 pi i k3 j3/N3} rho[j1][j2][j3]
+//   stage y : T2[j1][k2][k3]  = sum_j2 e^{+2 pi i k2 j2/N2} T1[j1][j2][k3]
+//             (kept only on the "disc", the distinct (k2,k3) of the G list)
+//   stage x : M(G)            = dV * sum_j1 e^{+2 pi i k1 j1/N1} T2[j1][disc(G)]
+struct MtxelPlan {
+    int n[3] = {0, 0, 0};
+    int64_t nr = 0;
+    int ng = 0;
+    int m2 = 0, m3 = 0;   // distinct k2, k3 values
+    int nb2 = 0, nb3 = 0; // 16-wide blocks covering them
+    int n2p = 0, n3p = 0; // N2 rounded up to 16, N3 rounded up to 4
+    int n23 = 0;          // disc size
+    size_t lds_yz = 0;    // dynamic LDS of the fused product + z + y kernel
+
+    std::vector<int32_t> gvec;  // host copy (cache key)
+
+    // device tables (owned)
+    double2* w3tab = nullptr;   // [n3p/4][nb3][64]      stage-z MFMA B operand, lane layout
+    double2* w2tab = nullptr;   // [n2p/16][4][nb2][64]  stage-y MFMA A operand, lane layout
+    int* boxmap = nullptr;      // [nb2*16][nb3*16] -> disc index or -1
+    int* g_k1 = nullptr;        // [ng] g1 mod N1
+    int* g_disc = nullptr;      // [ng] disc index of G
+    double2* root1 = nullptr;   // [N1] e^{+2 pi i t/N1}
+    // used by the adjoint
+    double2* root2 = nullptr;   // [N2] e^{+2 pi i t/N2}
+    double2* root3 = nullptr;   // [N3] e^{+2 pi i t/N3}
+    int* k2val = nullptr;       // [m2] k2 value of each k2 index
+    int* k3val = nullptr;       // [m3] k3 value of each k3 index
+    int* disc_ptr = nullptr;    // [n23+1] CSR over the G list grouped by disc
+    int* disc_g = nullptr;      // [ng] G indices, grouped by disc
+
+    void release();
+};
+
+// Build (or fetch from the per-device cache) the plan for this grid and G list.
+// Throws gw::Error on invalid input or unsupported size.
+MtxelPlan* get_plan(const int n[3], const int32_t* gvec, int ng);
+void release_plans();
+
+// MTXEL launches: m_out[k][i] = M_{pair k}(G_i) for k in [0, npairs).
+// t2 is scratch of t2_elems(plan, npairs) double2.
+size_t t2_elems(const MtxelPlan& p, int64_t npairs);
+void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c, PairMap pm,
+                  int64_t npairs, double volume, double2* t2, double2* m_out, hipStream_t s);
+
+}  // namespace gw

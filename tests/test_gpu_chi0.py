@@ -1,0 +1,119 @@
+"""GPU parity of gw_chi0 (FP64) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_23018_amd as gw
+from gpu_helpers import FP64_TOL, device, rel_fro, run_chi0, to_dev
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_chi(p, **kw):
+    args = dict(spin=p.spin, pair_chunk=p.pair_chunk)
+    args.update(kw)
+    return oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, **args)
+
+
+def test_chi0_workload0_full():
+    """Static chi0 at q=0 on the 16^3 grid, 4 x 28 bands, 147 G."""
+    p = gen.make_config(0)
+    chi = run_chi0(p)
+    ref = _oracle_chi(p)
+    assert rel_fro(chi, ref) < FP64_TOL
+    assert np.abs(chi[0] - chi[0].conj().T).max() < 1e-13 * np.abs(chi).max()
+    assert np.linalg.eigvalsh(chi[0]).max() <= 1e-13 * np.abs(chi).max()
+
+
+@pytest.mark.parametrize("zs,chunk", [
+    ((0.0,), 37),                                  # static, ragged chunks
+    ((0.3j, 1.7j, 0.0), 64),                       # imaginary axis: Hermitian shortcut
+    ((0.0 + 0.005j, 0.4 + 0.005j, 0.9 + 0.01j), 50),  # real axis: every tile
+    ((0.2j, 0.5 + 0.005j), 1000),                  # mixed, one chunk
+])
+def test_chi0_medium_multichunk(zs, chunk):
+    """Several 64-wide tiles with a ragged edge (N_G = 257) and several chunks."""
+    p = gen.make_problem((20, 18, 24), 5, 23, r2=15, z=zs, seed=11, pair_chunk=chunk)
+    assert p.ng == 251          # three full 64-wide tiles and a ragged one
+    chi = run_chi0(p)
+    ref = _oracle_chi(p)
+    assert rel_fro(chi, ref) < FP64_TOL
+    for w, z in enumerate(p.z):
+        assert rel_fro(chi[w], ref[w]) < FP64_TOL
+
+
+def test_chi0_flags_no_hermitian_and_accumulate():
+    p = gen.make_problem((12, 12, 12), 3, 9, r2=12, z=(0.0, 0.6j), seed=5, pair_chunk=10)
+    ref = _oracle_chi(p)
+    full = run_chi0(p, flags=gw.GW_FLAG_NO_HERMITIAN)
+    assert rel_fro(full, ref) < FP64_TOL
+    dp = to_dev(p)
+    dp.chi = torch.full((2, p.ng, p.ng), 1.0 + 2.0j, dtype=torch.complex128, device=device())
+    gw.gw_chi0(dp, flags=gw.GW_FLAG_ACCUMULATE, pair_chunk=10)
+    acc = dp.chi.cpu().numpy()
+    assert rel_fro(acc - (1.0 + 2.0j), ref) < FP64_TOL
+
+
+def test_chi0_edge_cases():
+    # no pairs -> chi = 0
+    p = gen.make_problem((8, 8, 8), 2, 3, r2=3, z=(0.0,), seed=1)
+    p.psi_c, p.e_c = p.psi_c[:0], p.e_c[:0]
+    dp = to_dev(p)
+    dp.chi = torch.full((1, p.ng, p.ng), 3.0 + 0j, dtype=torch.complex128, device=device())
+    gw.gw_chi0(dp)
+    assert torch.all(dp.chi == 0)
+    # one G, one pair per chunk, a singleton axis
+    p = gen.make_problem((1, 6, 10), 2, 3, gvec=np.array([[0, 2, -3]], np.int32),
+                         z=(0.25j,), seed=2, pair_chunk=1)
+    assert rel_fro(run_chi0(p), _oracle_chi(p)) < FP64_TOL
+    # largest Miller index on a small grid
+    p = gen.make_problem((4, 5, 6), 2, 2, gvec=np.array([[-2, -2, -3], [1, 2, 2], [0, 0, 0]], np.int32),
+                         z=(0.0, 0.3 + 0.01j), seed=3, pair_chunk=3)
+    assert rel_fro(run_chi0(p), _oracle_chi(p)) < FP64_TOL
+
+
+def test_chi0_invariances_on_device():
+    p = gen.make_problem((12, 12, 12), 3, 8, r2=10, z=(0.0, 0.8j), seed=9, pair_chunk=7)
+    ref = run_chi0(p)
+    rng = np.random.default_rng(0)
+    q = gen.Problem(**{**p.__dict__})
+    q.psi_v = p.psi_v * np.exp(1j * rng.uniform(0, 6.3, p.nv))[:, None]
+    q.e_v, q.e_c = p.e_v + 0.05, p.e_c + 0.05
+    assert rel_fro(run_chi0(q), ref) < FP64_TOL
+    assert rel_fro(run_chi0(p, pair_chunk=1), ref) < FP64_TOL
+    assert np.abs(ref[:, 0, :]).max() < 1e-13 * np.abs(ref).max()   # head/wings at q = 0
+
+
+def test_chi0_rejects_bad_arguments():
+    p = gen.make_problem((8, 8, 8), 2, 3, r2=3, z=(0.0,), seed=1)
+    dp = to_dev(p)
+    dp.chi = torch.full((1, p.ng, p.ng), 5.0 + 0j, dtype=torch.complex128, device=device())
+    with pytest.raises(gw.GWError, match="pair_chunk"):
+        gw.gw_chi0(dp, pair_chunk=-3)
+    with pytest.raises(gw.GWError, match="n_slices"):
+        gw.gw_chi0(dp, precision="split_bf16", n_slices=1)
+    dp.z = np.array([np.inf])
+    with pytest.raises(gw.GWError, match="finite"):
+        gw.gw_chi0(dp)
+    torch.cuda.synchronize()
+    assert torch.all(dp.chi == 5.0)
+
+
+def test_chi0_workload1_full_size_sampled():
+    """48^3 grid, 64 x 960 bands (61,440 pairs in chunks of 4,096), 2,007 G,
+    4 real frequencies: sampled rows/columns against the oracle's direct sums."""
+    p = gen.make_config(1)
+    assert (p.ng, p.npairs, len(p.z)) == (2007, 61440, 4)
+    chi = run_chi0(p)
+    rng = np.random.default_rng(101)
+    rows = np.sort(rng.choice(p.ng, 4, replace=False))
+    cols = np.sort(np.concatenate([[0, p.ng - 1], rng.choice(p.ng, 3, replace=False)]))
+    ref = oracle.chi0_entries(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec[rows], p.gvec[cols], p.z,
+                              p.n, p.volume, p.spin)
+    got = chi[:, rows][:, :, cols]
+    assert rel_fro(got, ref) < FP64_TOL
+    # chi(z)^H = chi(conj z) cannot be checked within one call; check the
+    # structure that holds at any size: the G = 0 row vanishes at q = 0
+    assert np.abs(chi[:, 0, :]).max() < 1e-12 * np.abs(chi).max()
