@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the chi0 build (MTXEL + CHI0) on one MI355X.
+
+Workload (default): chi0 at q = 0 on a 48^3 grid (L = 10 bohr) with 64
+valence x 960 conduction bands (61,440 pairs streamed in chunks of at most
+4,096), the complete G-sphere |g|^2 <= 61 (2,007 vectors) and 4 real
+frequencies omega in [0, 1] Ha with eta = 0.005 Ha, FP64 throughout.
+Inputs are seeded synthetic orthonormal wavefunctions (no DFT data).
+
+One step = one gw_chi0 call: every chunk's MTXEL, energy factor and CHI0
+contraction for all frequencies, inputs already resident in HBM.  The JSON
+line reports canonical TFLOP/s (8 N_G^2 pairs N_omega per step, the complex
+GEMM count convention) and pairs/s, the roofline of the dominant kernel
+(chi0_f64, FP64 MFMA) from HIP events recorded on the stream it runs on, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --calibrate-copy     # plain copy kernel for counter scaling
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "χ0 build TFLOP/s + pairs/s, FP64 vs split-BF16 at ≤1e-10 rel err"
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (MFMA and vector)
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "chi0_f64_kernel_48cube_61440pairs_pmc.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_23018_amd", "csrc", f)
+                  for f in ("chi0.hip", "common.hpp")]
+
+
+def kernel_src_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(launch_count_per_step: int):
+    """HBM bytes per launch of chi0_f64 from the committed counter summary,
+    or None when the summary is missing or the kernel source changed since."""
+    try:
+        text = open(PROFILE_TRAFFIC).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", text, re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("src_sha256") != kernel_src_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 27                                   # 2^27 doubles = 1 GiB per buffer
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the chi0 build here runs on a single MI355X "
+              "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    dev = torch.device("cuda", 0)
+    t_gen = time.perf_counter()
+    p = gen.make_config(1)
+    print(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f} s: grid {p.n}, "
+          f"{p.nv}x{p.nc} bands, {p.ng} G, {len(p.z)} frequencies", file=sys.stderr, flush=True)
+    dp = gw.Chi0Problem(n=p.n, volume=p.volume,
+                        psi_v=torch.from_numpy(p.psi_v).to(dev),
+                        psi_c=torch.from_numpy(p.psi_c).to(dev),
+                        e_v=torch.from_numpy(p.e_v).to(dev), e_c=torch.from_numpy(p.e_c).to(dev),
+                        gvec=p.gvec, z=p.z)
+    chunk = p.pair_chunk
+
+    def step():
+        gw.gw_chi0(dp, precision="fp64", pair_chunk=chunk)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gw.profile_reset()
+    gw.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gw.profile_enable(False)
+    n_chi, t_chi = gw.profile_read("chi0_f64")
+    kernels = {k: gw.profile_read(k) for k in ("mtxel_zy", "mtxel_x", "delta", "chi0_f64")}
+    gw.profile_reset()
+    print(f"[bench] {args.steps} steps in {elapsed:.3f} s; per-kernel ms/step: " +
+          ", ".join(f"{k} {v[1] / args.steps:.2f}" for k, v in kernels.items()),
+          file=sys.stderr, flush=True)
+
+    ng, npairs, nz = p.ng, p.npairs, len(p.z)
+    flops_step = 8.0 * ng * ng * npairs * nz
+    value = flops_step * args.steps / elapsed / 1e12
+    pairs_s = npairs * args.steps / elapsed
+    # every chi0_f64 launch contracts one chunk for one frequency over all tiles
+    launches_per_step = n_chi // max(1, args.steps)
+    flops_per_launch = flops_step / max(1, launches_per_step)
+    avg_ms = t_chi / max(1, n_chi)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    traffic = read_traffic(launches_per_step)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "chi0 at q=0, 48^3 grid, 64x960 bands (61,440 pairs, chunks of 3,840), "
+                        "2,007 G, 4 real frequencies (eta 0.005 Ha), FP64",
+            "grid": list(p.n), "pairs": npairs, "n_g": ng, "n_freq": nz,
+            "pair_chunk": chunk, "precision": "fp64",
+        },
+        "pairs_per_s": round(pairs_s, 1),
+        "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in kernels.items()},
+        "roofline": {
+            "kernel": "chi0_f64_kernel",
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "launches": n_chi,
+            "avg_launch_ms": round(avg_ms, 4),
+            "flops_per_launch": flops_per_launch,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, dp, dev)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(p, dp, dev):
+    """The FP64 oracle on a bounded sample of the workload: the first two
+    valence bands against all conduction bands (1,920 pairs), every G and
+    frequency, timed on this host; the device result for the same sample is
+    compared with it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2509_23018_amd as gw
+
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                            if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        blas_threads = os.cpu_count() or 1
+    nv_s = 2
+    t0 = time.perf_counter()
+    ref = oracle.chi0(p.psi_v[:nv_s], p.psi_c, p.e_v[:nv_s], p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    dt = time.perf_counter() - t0
+    sub = gw.Chi0Problem(n=p.n, volume=p.volume, psi_v=dp.psi_v[:nv_s].contiguous(),
+                         psi_c=dp.psi_c, e_v=dp.e_v[:nv_s].contiguous(), e_c=dp.e_c,
+                         gvec=p.gvec, z=p.z)
+    got = gw.gw_chi0(sub, pair_chunk=p.pair_chunk).cpu().numpy()
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    pairs = nv_s * p.nc
+    flops = 8.0 * p.ng * p.ng * pairs * len(p.z)
+    return {
+        "value": round(flops / dt / 1e12, 5),
+        "unit": "TFLOP/s",
+        "cores": int(blas_threads),
+        "kind": "oracle",
+        "sample": f"{nv_s} of {p.nv} valence bands x all {p.nc} conduction bands "
+                  f"({pairs} of {p.npairs} pairs), all {p.ng} G and {len(p.z)} frequencies; "
+                  "numpy FFT per pair (one thread) + BLAS contraction",
+        "seconds": round(dt, 2),
+        "pairs_per_s": round(pairs / dt, 2),
+        "gpu_rel_err_on_sample": err,
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -184,6 +184,20 @@ gw_status_t gw_release(void);
 /* GW_ABI_VERSION of the built library. */
 int32_t gw_abi_version(void);
 
+/*
+ * Launch timing for measurement harnesses.  While enabled, the library
+ * records a HIP event on the caller's stream before and after each of its
+ * kernel launches and files the pair under the kernel's name ("mtxel_zy",
+ * "mtxel_x", "delta", "chi0_f64", "mirror", "bwd_gm", "bwd_transform").
+ * gw_profile_read waits for the recorded events of `kernel` and returns the
+ * number of launches and the summed duration in milliseconds (0 and 0.0 for
+ * an unknown name).  gw_profile_reset forgets every record.  Timing adds two
+ * event records per launch and nothing else.
+ */
+gw_status_t gw_profile_enable(int32_t on);
+gw_status_t gw_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+gw_status_t gw_profile_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

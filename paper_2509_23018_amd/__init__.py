@@ -25,7 +25,8 @@ import torch  # noqa: F401  (loads the HIP runtime that libgw binds to)
 __all__ = [
     "GWError", "lib", "library_path", "GW_FP64", "GW_FP32", "GW_SPLIT_BF16", "GW_SPLIT_FP16",
     "GW_FLAG_NO_HERMITIAN", "GW_FLAG_ACCUMULATE", "Chi0Problem", "gw_mtxel", "gw_chi0",
-    "gw_chi0_backward", "Chi0", "chi0", "release",
+    "gw_chi0_backward", "Chi0", "chi0", "release", "profile_enable", "profile_reset",
+    "profile_read",
 ]
 
 GW_FP64, GW_FP32, GW_SPLIT_BF16, GW_SPLIT_FP16 = 0, 1, 2, 3
@@ -92,6 +93,12 @@ def lib() -> ctypes.CDLL:
         L.gw_last_error.argtypes = []
         L.gw_release.restype = ctypes.c_int32
         L.gw_abi_version.restype = ctypes.c_int32
+        L.gw_profile_enable.restype = ctypes.c_int32
+        L.gw_profile_enable.argtypes = [ctypes.c_int32]
+        L.gw_profile_read.restype = ctypes.c_int32
+        L.gw_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.gw_profile_reset.restype = ctypes.c_int32
         _LIB = L
     return _LIB
 
@@ -283,3 +290,20 @@ def chi0(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, *, pair_chunk=4096, spin=2.
 
 def release():
     _check(lib().gw_release())
+
+
+def profile_enable(on: bool = True):
+    """Record HIP events around every library launch (see include/gw.h)."""
+    _check(lib().gw_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().gw_profile_reset())
+
+
+def profile_read(kernel: str):
+    """(launches, total_ms) recorded for `kernel` since the last reset."""
+    n = ctypes.c_int64(0)
+    t = ctypes.c_double(0.0)
+    _check(lib().gw_profile_read(kernel.encode(), ctypes.byref(n), ctypes.byref(t)))
+    return int(n.value), float(t.value)

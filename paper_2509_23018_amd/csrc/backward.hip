@@ -16,6 +16,7 @@
 #include "backward.hpp"
 #include "chi0.hpp"
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace gw {
 
@@ -394,6 +395,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                 GW_HIP_TRY(hipGetLastError());
             }
             for (int w = 0; w < nz; ++w) {
+                ProfScope ps("bwd_gm", s);
                 hipLaunchKernelGGL(bwd_gm_kernel,
                                    dim3(ceil_div(ng, 64), static_cast<unsigned>(ceil_div64(kc, 64))),
                                    dim3(256), 0, s, mbuf, kc, ng,
@@ -412,6 +414,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             if (!want_psi) continue;
             for (int64_t k0 = 0; k0 < kc; k0 += kYMax) {
                 const unsigned kb = static_cast<unsigned>(std::min<int64_t>(kYMax, kc - k0));
+                ProfScope ps("bwd_transform", s);
                 hipLaunchKernelGGL(bx_kernel, dim3(ceil_div(n1 * plan.n23, 256), kb), dim3(256), 0,
                                    s, gm, ng, n1, plan.n23, plan.root1, plan.g_k1, plan.disc_ptr,
                                    plan.disc_g, k0, t2);

@@ -5,6 +5,7 @@
 
 #include "chi0.hpp"
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace gw {
 
@@ -141,6 +142,7 @@ void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npai
             za.re[w] = z[w0 + w].x;
             za.im[w] = z[w0 + w].y;
         }
+        ProfScope ps("delta", s);
         hipLaunchKernelGGL(delta_kernel, dim3(static_cast<unsigned>(ceil_div64(npairs, 256))),
                            dim3(256), 0, s, e_v, e_c, pm, npairs, za, w0, delta);
         GW_HIP_TRY(hipGetLastError());
@@ -150,12 +152,14 @@ void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npai
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta, double2* chi,
                      bool herm, bool accumulate, hipStream_t s) {
     const int nb = ceil_div(ng, kTile);
+    ProfScope ps("chi0_f64", s);
     hipLaunchKernelGGL(chi0_f64_kernel, dim3(nb, nb), dim3(256), 0, s, m, kc, ng, delta, chi,
                        herm ? 1 : 0, accumulate ? 1 : 0);
     GW_HIP_TRY(hipGetLastError());
 }
 
 void launch_mirror(double2* chi, int ng, hipStream_t s) {
+    ProfScope ps("mirror", s);
     hipLaunchKernelGGL(mirror_kernel, dim3(ceil_div(ng, 16), ceil_div(ng, 16)), dim3(256), 0, s,
                        chi, ng);
     GW_HIP_TRY(hipGetLastError());

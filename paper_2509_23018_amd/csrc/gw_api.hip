@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "gw.h"
 #include "plan.hpp"
+#include "prof.hpp"
 
 namespace gw {
 namespace {
@@ -337,5 +338,20 @@ gw_status_t gw_release(void) {
 }
 
 int32_t gw_abi_version(void) { return GW_ABI_VERSION; }
+
+gw_status_t gw_profile_enable(int32_t on) {
+    return guarded([&] { prof_enable(on != 0); });
+}
+
+gw_status_t gw_profile_read(const char* kernel, int64_t* launches, double* total_ms) {
+    return guarded([&] {
+        if (!kernel) fail(GW_EINVAL, "kernel name is NULL");
+        prof_read(kernel, launches, total_ms);
+    });
+}
+
+gw_status_t gw_profile_reset(void) {
+    return guarded([&] { prof_reset(); });
+}
 
 }  // extern "C"

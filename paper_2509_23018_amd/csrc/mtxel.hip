@@ -20,6 +20,7 @@
 
 #include "common.hpp"
 #include "plan.hpp"
+#include "prof.hpp"
 
 namespace gw {
 
@@ -353,13 +354,17 @@ void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(p.lds_yz)));
     const int64_t nblk = ceil_div64(npairs, kWaves);
+    {
+    ProfScope ps("mtxel_zy", s);
     hipLaunchKernelGGL(kz, dim3(static_cast<unsigned>(nblk)), dim3(kThreads), p.lds_yz, s, psi_v,
                        psi_c, p.nr, pm, npairs, p.n[0], p.n[1], p.n[2], p.n2p, p.n3p, p.w3tab,
                        p.w2tab, p.boxmap, p.n23, t2);
     GW_HIP_TRY(hipGetLastError());
+    }
     const double dv = volume / static_cast<double>(p.nr);
     for (int64_t k0 = 0; k0 < npairs; k0 += 65535) {
         const int64_t kb = std::min<int64_t>(65535, npairs - k0);
+        ProfScope ps("mtxel_x", s);
         hipLaunchKernelGGL(mtxel_x_gather_kernel, dim3(ceil_div(p.ng, 256), static_cast<unsigned>(kb)),
                            dim3(256), p.n[0] * sizeof(double2), s, t2, p.n[0], p.n23, p.root1,
                            p.g_k1, p.g_disc, p.ng, dv, k0, m_out);
