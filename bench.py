@@ -133,9 +133,14 @@ def main():
     flops_step = 8.0 * ng * ng * npairs * nz
     value = flops_step * args.steps / elapsed / 1e12
     pairs_s = npairs * args.steps / elapsed
-    # every chi0_f64 launch contracts one chunk for one frequency over all tiles
+    # Algorithmic work of the chi0_f64 launches: 8 flops per pair per chi entry
+    # computed; a frequency with Re z = 0 has real Delta and Hermitian chi, for
+    # which only the N_G (N_G + 1) / 2 entries on or above the diagonal are work.
+    herm = np.real(p.z) == 0.0
+    entries = float(np.sum(np.where(herm, ng * (ng + 1) / 2.0, float(ng) * ng)))
+    alg_flops_step = 8.0 * npairs * entries
     launches_per_step = n_chi // max(1, args.steps)
-    flops_per_launch = flops_step / max(1, launches_per_step)
+    flops_per_launch = alg_flops_step / max(1, launches_per_step)
     avg_ms = t_chi / max(1, n_chi)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     traffic = read_traffic(launches_per_step)

@@ -381,7 +381,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             const int cw = std::min(cwmax, p.nc - c0);
             const int64_t kc = static_cast<int64_t>(vcount) * cw;
             PairMap pm{0, cw, v0, c0};
-            launch_mtxel(plan, psi_v, psi_c, pm, kc, p.grid.volume, t2, mbuf, s);
+            launch_mtxel(plan, psi_v, psi_c, Rect{v0, vcount, c0, cw}, p.grid.volume, t2, mbuf, s);
             launch_delta(p.e_v, p.e_c, pm, kc, z, nz, spin, dbuf, s);
             for (int w0 = 0; w0 < nz; w0 += kMaxZ) {
                 ZArgs za{};

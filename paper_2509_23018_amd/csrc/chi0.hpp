@@ -22,10 +22,18 @@ struct ZArgs {
 void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npairs,
                   const double2* z, int nz, double spin, double2* delta, hipStream_t s);
 
-// chi (=|+=) M^H diag(delta) M for one frequency; M is [kc][ng].  With herm,
-// only tiles on or above the diagonal are written.
-void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta, double2* chi,
-                     bool herm, bool accumulate, hipStream_t s);
+// Frequencies contracted by one launch: w[0 .. nh) use only the tiles on or
+// above the diagonal (Hermitian chi), w[nh .. nh+nf) use every tile.
+struct WList {
+    int w[kMaxZ];
+    int nh;
+    int nf;
+};
+
+// chi[w] (=|+=) M^H diag(delta[w]) M for every frequency w of wl; M is
+// [kc][ng], delta [nz][kc], chi [nz][ng][ng].
+void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
+                     const WList& wl, double2* chi, bool accumulate, hipStream_t s);
 
 // Fill the tiles strictly below the diagonal from the conjugate transpose.
 void launch_mirror(double2* chi, int ng, hipStream_t s);

@@ -227,7 +227,24 @@ void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     std::vector<bool> herm(pr.nz);
     for (int w = 0; w < pr.nz; ++w)
         herm[w] = pr.z[w].re == 0.0 && !(o.flags & GW_FLAG_NO_HERMITIAN) && !accumulate;
-
+    // launches cover at most kMaxZ frequencies each (Hermitian ones first)
+    std::vector<WList> wlists;
+    {
+        std::vector<int> order;
+        for (int w = 0; w < pr.nz; ++w)
+            if (herm[w]) order.push_back(w);
+        const int nherm = static_cast<int>(order.size());
+        for (int w = 0; w < pr.nz; ++w)
+            if (!herm[w]) order.push_back(w);
+        for (int i0 = 0; i0 < pr.nz; i0 += kMaxZ) {
+            WList wl{};
+            for (int i = i0; i < std::min(pr.nz, i0 + kMaxZ); ++i) {
+                wl.w[i - i0] = order[i];
+                if (i < nherm) ++wl.nh; else ++wl.nf;
+            }
+            wlists.push_back(wl);
+        }
+    }
     bool first = true;
     for (int iv = 0; iv < cs.ncv; ++iv) {
         for (int ic = 0; ic < cs.ncc; ++ic) {
@@ -239,13 +256,11 @@ void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
             const int vcount = std::min(cs.vb, pr.nv - pm.v0);
             const int64_t kc = static_cast<int64_t>(vcount) * pm.cw;
             launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
-                         reinterpret_cast<const double2*>(pr.psi_c), pm, kc, pr.grid.volume, t2,
-                         mbuf, s);
+                         reinterpret_cast<const double2*>(pr.psi_c),
+                         Rect{pm.v0, vcount, pm.c0, pm.cw}, pr.grid.volume, t2, mbuf, s);
             launch_delta(pr.e_v, pr.e_c, pm, kc, z, pr.nz, o.spin, dbuf, s);
-            for (int w = 0; w < pr.nz; ++w)
-                launch_chi0_f64(mbuf, kc, pr.ng, dbuf + static_cast<int64_t>(w) * kc,
-                                chi + static_cast<int64_t>(w) * ng * ng, herm[w],
-                                accumulate || !first, s);
+            for (const WList& wl : wlists)
+                launch_chi0_f64(mbuf, kc, pr.ng, dbuf, wl, chi, accumulate || !first, s);
             first = false;
         }
     }
@@ -277,15 +292,31 @@ gw_status_t gw_mtxel(const gw_grid_t* grid, const gw_c128* psi_v, int32_t nv,
         if (!m_out) fail(GW_EINVAL, "m_out is NULL");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const MtxelPlan& plan = *get_plan(grid->n, gvec, ng);
-        const int64_t batch = std::min<int64_t>(pair_count, 4096);
-        double2* t2 = static_cast<double2*>(scratch(t2_elems(plan, batch) * sizeof(double2), s));
-        for (int64_t k0 = 0; k0 < pair_count; k0 += batch) {
-            const int64_t kb = std::min(batch, pair_count - k0);
-            PairMap pm{pair_begin + k0, nc, 0, 0};
-            launch_mtxel(plan, reinterpret_cast<const double2*>(psi_v),
-                         reinterpret_cast<const double2*>(psi_c), pm, kb, grid->volume, t2,
-                         reinterpret_cast<double2*>(m_out) + k0 * ng, s);
+        // the linear pair range as rectangles of at most kBatch pairs
+        constexpr int64_t kBatch = 4096;
+        std::vector<std::pair<Rect, int64_t>> rects;  // (rectangle, first output row)
+        int64_t p0 = pair_begin;
+        const int64_t pend = pair_begin + pair_count;
+        while (p0 < pend) {
+            const int v = static_cast<int>(p0 / nc), c = static_cast<int>(p0 % nc);
+            Rect r;
+            if (c != 0 || pend - p0 < nc) {  // part of one row
+                const int64_t cnt = std::min<int64_t>({nc - c, pend - p0, kBatch});
+                r = Rect{v, 1, c, static_cast<int32_t>(cnt)};
+            } else if (nc > kBatch) {        // a long row, in pieces
+                r = Rect{v, 1, 0, static_cast<int32_t>(kBatch)};
+            } else {                          // whole rows
+                const int64_t rows = std::min<int64_t>((pend - p0) / nc, kBatch / nc);
+                r = Rect{v, static_cast<int32_t>(rows), 0, nc};
+            }
+            rects.push_back({r, p0 - pair_begin});
+            p0 += static_cast<int64_t>(r.nv) * r.nc;
         }
+        double2* t2 = static_cast<double2*>(scratch(t2_elems(plan, kBatch) * sizeof(double2), s));
+        for (const auto& rr : rects)
+            launch_mtxel(plan, reinterpret_cast<const double2*>(psi_v),
+                         reinterpret_cast<const double2*>(psi_c), rr.first, grid->volume, t2,
+                         reinterpret_cast<double2*>(m_out) + rr.second * ng, s);
     });
 }
 

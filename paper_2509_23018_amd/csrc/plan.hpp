@@ -18,6 +18,12 @@ struct PairMap {
     int32_t c0;
 };
 
+// A rectangle of pairs: v in [v0, v0+nv), c in [c0, c0+nc); pair row
+// k = (v - v0)*nc + (c - c0).
+struct Rect {
+    int32_t v0, nv, c0, nc;
+};
+
 // Pruned 3D DFT on the G-sphere.  The transform of a pair density rho(j1,j2,j3)
 // is taken axis by axis, keeping on each axis only the frequencies some G
 // needs:
@@ -29,15 +35,20 @@ struct MtxelPlan {
     int n[3] = {0, 0, 0};
     int64_t nr = 0;
     int ng = 0;
-    int m2 = 0, m3 = 0;   // distinct k2, k3 values
-    int nb2 = 0, nb3 = 0; // 16-wide blocks covering them
-    int n2p = 0, n3p = 0; // N2 rounded up to 16, N3 rounded up to 4
+    int m1 = 0, m2 = 0, m3 = 0;    // distinct k1, k2, k3 values
+    int nb1 = 0, nb2 = 0, nb3 = 0; // 16-wide blocks covering them
+    int n1p = 0;          // N1 rounded up to 4
+    int n23p = 0;         // disc size rounded up to 16
+    int n2p = 0, n3p = 0; // N2 rounded up to 16, N3 rounded up to 16
     int n23 = 0;          // disc size
     size_t lds_yz = 0;    // dynamic LDS of the fused product + z + y kernel
+    size_t lds_x = 0;     // dynamic LDS of the x-stage kernel
 
     std::vector<int32_t> gvec;  // host copy (cache key)
 
     // device tables (owned)
+    double2* w1tab = nullptr;   // [nb1][n1p/4][64]      stage-x MFMA A operand, lane layout
+    int* gmap = nullptr;        // [nb1*16][n23p] -> G index or -1
     double2* w3tab = nullptr;   // [n3p/4][nb3][64]      stage-z MFMA B operand, lane layout
     double2* w2tab = nullptr;   // [n2p/16][4][nb2][64]  stage-y MFMA A operand, lane layout
     int* boxmap = nullptr;      // [nb2*16][nb3*16] -> disc index or -1
@@ -60,10 +71,10 @@ struct MtxelPlan {
 MtxelPlan* get_plan(const int n[3], const int32_t* gvec, int ng);
 void release_plans();
 
-// MTXEL launches: m_out[k][i] = M_{pair k}(G_i) for k in [0, npairs).
-// t2 is scratch of t2_elems(plan, npairs) double2.
+// MTXEL launches: m_out[k][i] = M_{pair k}(G_i) for the pairs of rc, in row
+// order k = (v - v0)*nc + (c - c0).  t2 is scratch of t2_elems(plan, pairs).
 size_t t2_elems(const MtxelPlan& p, int64_t npairs);
-void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c, PairMap pm,
-                  int64_t npairs, double volume, double2* t2, double2* m_out, hipStream_t s);
+void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c, Rect rc,
+                  double volume, double2* t2, double2* m_out, hipStream_t s);
 
 }  // namespace gw
