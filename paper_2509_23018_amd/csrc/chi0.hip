@@ -2,6 +2,7 @@
 // pairs (Eq. (4) of the paper), FP64 MFMA 16x16x4 tiles, plus the energy
 // factor, the Hermitian mirror and the zero fill.
 #include <algorithm>
+#include <cstdlib>
 
 #include "chi0.hpp"
 #include "common.hpp"
@@ -35,7 +36,6 @@ __global__ __launch_bounds__(256) void delta_kernel(const double* __restrict__ e
 
 // ---------------------------------------------------------------- FP64 contraction
 
-constexpr int kTile = 64;   // output tile edge per workgroup
 constexpr int kKt = 16;     // pairs per LDS stage
 
 // Work item of workgroup b.  Items are frequency-major: first every
@@ -68,97 +68,114 @@ __device__ __forceinline__ void item_of_block(int b, const WList& wl, int nb, in
     }
 }
 
-// One workgroup = one 64x64 tile of chi_w; 4 waves in a 2x2 layout, each a
-// 32x32 sub-tile of 2x2 MFMA blocks.  Per stage of 16 pairs the rows of M
-// for the tile's G and G' are staged in LDS (double-buffered), the G' side
-// already multiplied by s*Delta_w(k); the MFMAs then accumulate
-// conj(M_i) (Delta M_j).  Loads are unconditional: pair rows past the chunk
-// end are clamped and carry Delta = 0, columns past N_G are clamped and only
-// feed outputs that are not stored.  mode: 0 overwrite, 1 accumulate.
-__global__ __launch_bounds__(256) void chi0_f64_kernel(const double2* __restrict__ m, int64_t kc,
-                                                       int ng, const double2* __restrict__ delta,
-                                                       WList wl, double2* __restrict__ chi,
-                                                       int mode, int nb) {
+// One workgroup = one T x T tile of chi_w, WI x WJ waves, each a
+// (T/WI) x (T/WJ) sub-tile of 16x16 MFMA blocks.  Per stage of kKt pairs the
+// rows of M for the tile's G and G' are staged in LDS (double-buffered; rows
+// padded by PAD elements), the G' side already multiplied by s*Delta_w(k);
+// the MFMAs accumulate conj(M_i) (Delta M_j).  Loads are unconditional: pair
+// rows past the chunk end are clamped and carry Delta = 0, columns past N_G
+// are clamped and only feed outputs that are not stored.
+// mode: 0 overwrite, 1 accumulate.
+template <int T, int WI, int WJ, int PAD>
+__global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
+    const double2* __restrict__ m, int64_t kc, int ng, const double2* __restrict__ delta,
+    WList wl, double2* __restrict__ chi, int mode, int nb) {
+    constexpr int NT = WI * WJ * 64;
+    constexpr int BX = T / WI / 16, BY = T / WJ / 16;
+    constexpr int LDR = T + PAD;                 // LDS row length (double2)
+    constexpr int NLOAD = kKt * T / NT;          // staged elements per thread per side
+    static_assert(NLOAD * NT == kKt * T && NT % T == 0, "tile / thread mismatch");
     int w, bi, bj;
     item_of_block(blockIdx.x, wl, nb, w, bi, bj);
-    __shared__ double2 s_a[2][kKt][kTile];
-    __shared__ double2 s_b[2][kKt][kTile];
+    extern __shared__ double2 lds[];
+    double2* s_a = lds;                  // [2][kKt][LDR]
+    double2* s_b = lds + 2 * kKt * LDR;  // [2][kKt][LDR]
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
-    const int wi = wave >> 1, wj = wave & 1;
-    const int i0 = bi * kTile, j0 = bj * kTile;
+    const int wi = wave / WJ, wj = wave % WJ;
+    const int i0 = bi * T, j0 = bj * T;
     const double2* dw = delta + static_cast<int64_t>(w) * kc;
 
-    // this thread's staging slots: rows kk = (tid >> 6) + 4u, column cc = tid & 63
-    const int cc = tid & 63, kk0 = tid >> 6;
+    // staging slots: element e = tid + NT*u -> row kk = e / T, column cc = e % T;
+    // NT is a multiple of T, so cc is the same for every u and kk steps by NT/T
+    constexpr int KSTEP = NT / T;
+    const int cc = tid % T, kk0 = tid / T;
     const int64_t ci = min(i0 + cc, ng - 1), cj = min(j0 + cc, ng - 1);
 
-    dbl4 accr[2][2], acci[2][2];
+    dbl4 accr[BX][BY], acci[BX][BY];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BX; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = zero4();
+        for (int b = 0; b < BY; ++b) accr[a][b] = acci[a][b] = zero4();
 
-    double2 ra[4], rb[4], rd[4];
-    auto gload = [&](int64_t k0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = k0 + kk0 + 4 * u;
-            const int64_t kr = k < kc ? k : kc - 1;
-            const double2* mr = m + kr * ng;
-            ra[u] = mr[ci];
-            rb[u] = mr[cj];
-            rd[u] = dw[kr];
-            if (k >= kc) rd[u] = make_double2(0.0, 0.0);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            s_a[buf][kk0 + 4 * u][cc] = ra[u];
-            s_b[buf][kk0 + 4 * u][cc] = cmul(rd[u], rb[u]);
-        }
-    };
+    double2 ra[NLOAD], rb[NLOAD];
 
-    gload(0);
-    sstore(0);
+    // stage 0
+#pragma unroll
+    for (int u = 0; u < NLOAD; ++u) {
+        const int64_t k = kk0 + KSTEP * u;
+        const int64_t kr = k < kc ? k : kc - 1;
+        const double2 d = k < kc ? dw[kr] : make_double2(0.0, 0.0);
+        s_a[(kk0 + KSTEP * u) * LDR + cc] = m[kr * ng + ci];
+        s_b[(kk0 + KSTEP * u) * LDR + cc] = cmul(d, m[kr * ng + cj]);
+    }
     __syncthreads();
     int buf = 0;
     const int nsteps = static_cast<int>((kc + kKt - 1) / kKt);
     for (int st = 0; st < nsteps; ++st) {
-        // unconditional (clamped) prefetch keeps the loop free of branches, so
-        // the compiler cannot merge the LDS stores into the load block
-        gload(static_cast<int64_t>(st + 1) * kKt);
+        // unconditional (clamped) prefetch of the next stage keeps the loop
+        // free of branches, so the compiler cannot merge the LDS stores into
+        // the load block
+        const int64_t k1 = static_cast<int64_t>(st + 1) * kKt;
+        double2 rd[NLOAD];
+#pragma unroll
+        for (int u = 0; u < NLOAD; ++u) {
+            const int64_t k = k1 + kk0 + KSTEP * u;
+            const int64_t kr = k < kc ? k : kc - 1;
+            rd[u] = dw[kr];
+            rb[u] = m[kr * ng + cj];
+            ra[u] = m[kr * ng + ci];
+        }
+        // loads first, then the MFMAs of the current stage (no reordering)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < kKt / 4; ++s) {
-            double2 a[2], b[2];
+            const double2* la = s_a + (buf * kKt + s * 4 + kq) * LDR + wi * (T / WI) + row;
+            const double2* lb = s_b + (buf * kKt + s * 4 + kq) * LDR + wj * (T / WJ) + row;
+            double2 a[BX], b[BY];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                a[x] = s_a[buf][s * 4 + kq][wi * 32 + x * 16 + row];
-                b[x] = s_b[buf][s * 4 + kq][wj * 32 + x * 16 + row];
-            }
+            for (int x = 0; x < BX; ++x) a[x] = la[x * 16];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < BY; ++y) b[y] = lb[y * 16];
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+            for (int x = 0; x < BX; ++x)
+#pragma unroll
+                for (int y = 0; y < BY; ++y)
                     cmfma_conj_a(accr[x][y], acci[x][y], a[x].x, a[x].y, b[y].x, b[y].y);
         }
         // keep the LDS stores of the next stage after this stage's MFMAs, so
         // the global loads issued above stay in flight during the compute
         __builtin_amdgcn_sched_barrier(0);
-        sstore(buf ^ 1);
+        const int nb2 = buf ^ 1;
+#pragma unroll
+        for (int u = 0; u < NLOAD; ++u) {
+            const int64_t k = k1 + kk0 + KSTEP * u;
+            s_a[(nb2 * kKt + kk0 + KSTEP * u) * LDR + cc] = ra[u];
+            s_b[(nb2 * kKt + kk0 + KSTEP * u) * LDR + cc] =
+                k < kc ? cmul(rd[u], rb[u]) : make_double2(0.0, 0.0);
+        }
         __syncthreads();
-        buf ^= 1;
+        buf = nb2;
     }
     double2* cw = chi + static_cast<int64_t>(w) * ng * ng;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < BX; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < BY; ++y)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int gi = i0 + wi * 32 + x * 16 + 4 * t + kq;
-                const int gj = j0 + wj * 32 + y * 16 + row;
+                const int gi = i0 + wi * (T / WI) + x * 16 + 4 * t + kq;
+                const int gj = j0 + wj * (T / WJ) + y * 16 + row;
                 if (gi < ng && gj < ng) {
                     double2* p = cw + static_cast<int64_t>(gi) * ng + gj;
                     double2 v = make_double2(accr[x][y][t], acci[x][y][t]);
@@ -172,13 +189,40 @@ __global__ __launch_bounds__(256) void chi0_f64_kernel(const double2* __restrict
             }
 }
 
+struct Chi0Variant {
+    const void* fn;
+    int tile, threads;
+    size_t lds;
+};
+
+template <int T, int WI, int WJ, int PAD>
+Chi0Variant chi0_variant() {
+    return {reinterpret_cast<const void*>(&chi0_f64_kernel<T, WI, WJ, PAD>), T, WI * WJ * 64,
+            2 * 2 * kKt * (T + PAD) * sizeof(double2)};
+}
+
+const Chi0Variant& chi0_selected() {
+    static const Chi0Variant v = [] {
+        const char* e = std::getenv("GW_CHI0_VARIANT");
+        const int id = e ? std::atoi(e) : 0;
+        switch (id) {
+            case 1: return chi0_variant<64, 2, 2, 1>();
+            case 2: return chi0_variant<128, 2, 4, 0>();
+            case 3: return chi0_variant<128, 2, 4, 1>();
+            case 4: return chi0_variant<128, 4, 2, 1>();
+            default: return chi0_variant<64, 2, 2, 0>();
+        }
+    }();
+    return v;
+}
+
 // chi[i][j] = conj(chi[j][i]) for every (i, j) in a tile strictly below the
-// diagonal of 64x64 tiles (those the Hermitian contraction skipped).
-__global__ __launch_bounds__(256) void mirror_kernel(double2* __restrict__ chi, int ng) {
+// diagonal of tile x tile blocks (those the Hermitian contraction skipped).
+__global__ __launch_bounds__(256) void mirror_kernel(double2* __restrict__ chi, int ng, int tile) {
     const int j = blockIdx.x * 16 + (threadIdx.x & 15);
     const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (i >= ng || j >= ng) return;
-    if (i / kTile <= j / kTile) return;
+    if (i / tile <= j / tile) return;
     const double2 u = chi[static_cast<int64_t>(j) * ng + i];
     chi[static_cast<int64_t>(i) * ng + j] = make_double2(u.x, -u.y);
 }
@@ -212,20 +256,25 @@ void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npai
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
                      const WList& wl, double2* chi, bool accumulate, hipStream_t s) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
-    const int nb = ceil_div(ng, kTile);
+    const Chi0Variant& v = chi0_selected();
+    const int nb = ceil_div(ng, v.tile);
     const int64_t nitems = static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
                            static_cast<int64_t>(wl.nf) * nb * nb;
     if (nitems >= (int64_t(1) << 31)) throw Error{-4, "too many chi tiles for one launch"};
+    GW_HIP_TRY(hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(v.lds)));
     ProfScope ps("chi0_f64", s);
-    hipLaunchKernelGGL(chi0_f64_kernel, dim3(static_cast<unsigned>(nitems)), dim3(256), 0, s, m,
-                       kc, ng, delta, wl, chi, accumulate ? 1 : 0, nb);
-    GW_HIP_TRY(hipGetLastError());
+    int mode = accumulate ? 1 : 0;
+    void* args[] = {const_cast<double2**>(&m), &kc, &ng, const_cast<double2**>(&delta),
+                    const_cast<WList*>(&wl), &chi, &mode, const_cast<int*>(&nb)};
+    GW_HIP_TRY(hipLaunchKernel(v.fn, dim3(static_cast<unsigned>(nitems)), dim3(v.threads), args,
+                               v.lds, s));
 }
 
 void launch_mirror(double2* chi, int ng, hipStream_t s) {
     ProfScope ps("mirror", s);
     hipLaunchKernelGGL(mirror_kernel, dim3(ceil_div(ng, 16), ceil_div(ng, 16)), dim3(256), 0, s,
-                       chi, ng);
+                       chi, ng, chi0_selected().tile);
     GW_HIP_TRY(hipGetLastError());
 }
 
@@ -236,7 +285,7 @@ void launch_fill_zero(double2* p, int64_t n, hipStream_t s) {
     GW_HIP_TRY(hipGetLastError());
 }
 
-int chi0_tile() { return kTile; }
+int chi0_tile() { return chi0_selected().tile; }
 
 
 

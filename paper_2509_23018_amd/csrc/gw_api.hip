@@ -77,6 +77,48 @@ void release_scratch() {
     p.by_key.clear();
 }
 
+// A library-owned companion stream of each caller stream (default priority),
+// with events used to fork work onto it and join it back.
+struct AuxCtx {
+    hipStream_t aux = nullptr;
+    hipEvent_t ev[6] = {};
+};
+
+struct AuxPool {
+    std::mutex mu;
+    std::map<std::pair<int, hipStream_t>, AuxCtx> by_key;
+};
+
+AuxPool& aux_pool() {
+    static AuxPool* p = new AuxPool();
+    return *p;
+}
+
+AuxCtx& aux_ctx(hipStream_t s) {
+    int dev = 0;
+    GW_HIP_TRY(hipGetDevice(&dev));
+    AuxPool& p = aux_pool();
+    std::lock_guard<std::mutex> lk(p.mu);
+    AuxCtx& a = p.by_key[{dev, s}];
+    if (!a.aux) {
+        GW_HIP_TRY(hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking));
+        for (auto& e : a.ev) GW_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    return a;
+}
+
+void release_aux() {
+    AuxPool& p = aux_pool();
+    std::lock_guard<std::mutex> lk(p.mu);
+    for (auto& kv : p.by_key) {
+        (void)hipSetDevice(kv.first.first);
+        (void)hipStreamSynchronize(kv.second.aux);
+        for (auto& e : kv.second.ev) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(kv.second.aux);
+    }
+    p.by_key.clear();
+}
+
 // Carves aligned sub-buffers out of one scratch allocation.
 struct Carver {
     size_t off = 0;
@@ -215,14 +257,21 @@ void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     }
     const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
     const int64_t kmax = static_cast<int64_t>(cs.vb) * cs.cw;
+    // two M / Delta buffers: MTXEL of chunk k+1 (companion stream) overlaps
+    // CHI0 of chunk k (caller stream)
     Carver cv;
-    const size_t off_m = cv.take(kmax * ng * sizeof(double2));
+    size_t off_m[2], off_d[2];
+    for (int b = 0; b < 2; ++b) {
+        off_m[b] = cv.take(kmax * ng * sizeof(double2));
+        off_d[b] = cv.take(kmax * pr.nz * sizeof(double2));
+    }
     const size_t off_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
-    const size_t off_d = cv.take(kmax * pr.nz * sizeof(double2));
     char* base = static_cast<char*>(scratch(cv.off, s));
-    double2* mbuf = reinterpret_cast<double2*>(base + off_m);
+    double2* mbuf[2] = {reinterpret_cast<double2*>(base + off_m[0]),
+                        reinterpret_cast<double2*>(base + off_m[1])};
+    double2* dbuf[2] = {reinterpret_cast<double2*>(base + off_d[0]),
+                        reinterpret_cast<double2*>(base + off_d[1])};
     double2* t2 = reinterpret_cast<double2*>(base + off_t2);
-    double2* dbuf = reinterpret_cast<double2*>(base + off_d);
     const double2* z = reinterpret_cast<const double2*>(pr.z);
     std::vector<bool> herm(pr.nz);
     for (int w = 0; w < pr.nz; ++w)
@@ -245,24 +294,46 @@ void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
             wlists.push_back(wl);
         }
     }
-    bool first = true;
-    for (int iv = 0; iv < cs.ncv; ++iv) {
+    struct Chunk {
+        PairMap pm;
+        int vcount;
+        int64_t kc;
+    };
+    std::vector<Chunk> chunks;
+    for (int iv = 0; iv < cs.ncv; ++iv)
         for (int ic = 0; ic < cs.ncc; ++ic) {
-            PairMap pm;
-            pm.v0 = iv * cs.vb;
-            pm.c0 = ic * cs.cw;
-            pm.cw = std::min(cs.cw, pr.nc - pm.c0);
-            pm.k_off = 0;
-            const int vcount = std::min(cs.vb, pr.nv - pm.v0);
-            const int64_t kc = static_cast<int64_t>(vcount) * pm.cw;
-            launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
-                         reinterpret_cast<const double2*>(pr.psi_c),
-                         Rect{pm.v0, vcount, pm.c0, pm.cw}, pr.grid.volume, t2, mbuf, s);
-            launch_delta(pr.e_v, pr.e_c, pm, kc, z, pr.nz, o.spin, dbuf, s);
-            for (const WList& wl : wlists)
-                launch_chi0_f64(mbuf, kc, pr.ng, dbuf, wl, chi, accumulate || !first, s);
-            first = false;
+            Chunk c;
+            c.pm.v0 = iv * cs.vb;
+            c.pm.c0 = ic * cs.cw;
+            c.pm.cw = std::min(cs.cw, pr.nc - c.pm.c0);
+            c.pm.k_off = 0;
+            c.vcount = std::min(cs.vb, pr.nv - c.pm.v0);
+            c.kc = static_cast<int64_t>(c.vcount) * c.pm.cw;
+            chunks.push_back(c);
         }
+    // events: ev[0] caller-stream start, ev[1+b] MTXEL into buffer b done,
+    // ev[3+b] CHI0 reading buffer b done
+    AuxCtx& ax = aux_ctx(s);
+    auto produce = [&](size_t k) {  // MTXEL + Delta of chunk k on the companion stream
+        const int b = static_cast<int>(k & 1);
+        if (k >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[3 + b], 0));
+        const Chunk& c = chunks[k];
+        launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
+                     reinterpret_cast<const double2*>(pr.psi_c),
+                     Rect{c.pm.v0, c.vcount, c.pm.c0, c.pm.cw}, pr.grid.volume, t2, mbuf[b], ax.aux);
+        launch_delta(pr.e_v, pr.e_c, c.pm, c.kc, z, pr.nz, o.spin, dbuf[b], ax.aux);
+        GW_HIP_TRY(hipEventRecord(ax.ev[1 + b], ax.aux));
+    };
+    GW_HIP_TRY(hipEventRecord(ax.ev[0], s));
+    GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[0], 0));
+    produce(0);
+    for (size_t k = 0; k < chunks.size(); ++k) {
+        const int b = static_cast<int>(k & 1);
+        if (k + 1 < chunks.size()) produce(k + 1);
+        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1 + b], 0));
+        for (const WList& wl : wlists)
+            launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, accumulate || k > 0, s);
+        GW_HIP_TRY(hipEventRecord(ax.ev[3 + b], s));
     }
     for (int w = 0; w < pr.nz; ++w)
         if (herm[w]) launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, pr.ng, s);
@@ -363,6 +434,7 @@ const char* gw_last_error(void) { return g_last_error.c_str(); }
 
 gw_status_t gw_release(void) {
     return guarded([&] {
+        release_aux();
         release_scratch();
         release_plans();
     });
