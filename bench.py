@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--split-slices", type=int, nargs="*", default=[3, 4, 5],
+                    help="slice counts of the split-BF16 runs (empty: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the chi0 build here runs on a single MI355X "
@@ -179,6 +181,44 @@ def main():
             "flops_per_launch": flops_per_launch,
         },
     }
+
+    # split-BF16 contraction on the same workload: the FP64 chi above is the
+    # reference for its error (FP64 parity with the oracle is tested separately)
+    ref = gw.gw_chi0(dp, precision="fp64", pair_chunk=chunk).clone()
+    splits = []
+    for ns in args.split_slices:
+        def sstep():
+            gw.gw_chi0(dp, precision="split_bf16", n_slices=ns, pair_chunk=chunk)
+        sstep()
+        torch.cuda.synchronize()
+        gw.profile_reset()
+        gw.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sstep()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        gw.profile_enable(False)
+        ks = {k: gw.profile_read(k) for k in ("mtxel_zy", "mtxel_x", "split_prep", "chi0_split")}
+        gw.profile_reset()
+        got = dp.chi
+        err = float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))
+        splits.append({
+            "n_slices": ns,
+            "value": round(flops_step * args.steps / el / 1e12, 3),
+            "unit": "TFLOP/s",
+            "pairs_per_s": round(npairs * args.steps / el, 1),
+            "ms_per_step": round(el / args.steps * 1e3, 3),
+            "speedup_vs_fp64": round(elapsed / el, 3),
+            "rel_err_vs_fp64": err,
+            "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in ks.items()},
+        })
+        print(f"[bench] split_bf16 S={ns}: {el / args.steps * 1e3:.1f} ms/step, rel err {err:.2e}",
+              file=sys.stderr, flush=True)
+    out["split_bf16"] = splits
+    ok = [x for x in splits if x["rel_err_vs_fp64"] <= 1e-10]
+    out["split_bf16_at_1e-10"] = min(ok, key=lambda x: x["n_slices"]) if ok else None
+    dp.chi = None
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, dp, dev)

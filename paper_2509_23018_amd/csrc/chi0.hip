@@ -3,8 +3,12 @@
 // factor, the Hermitian mirror and the zero fill.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "chi0.hpp"
+#include "items.hpp"
 #include "common.hpp"
 #include "prof.hpp"
 
@@ -38,36 +42,6 @@ __global__ __launch_bounds__(256) void delta_kernel(const double* __restrict__ e
 
 constexpr int kKt = 16;     // pairs per LDS stage
 
-// Work item of workgroup b.  Items are frequency-major: first every
-// Hermitian frequency over the nh tiles on or above the diagonal, then every
-// other frequency over all nb*nb tiles.  The 8 XCDs take workgroups
-// round-robin, so blocks are renumbered to give each XCD a contiguous range
-// of items (consecutive tiles of one frequency share M rows in its L2).
-__device__ __forceinline__ void item_of_block(int b, const WList& wl, int nb, int& w, int& bi,
-                                              int& bj) {
-    const int nh = nb * (nb + 1) / 2, nf = nb * nb;
-    const int nitems = wl.nh * nh + wl.nf * nf;
-    const int q = nitems >> 3, r = nitems & 7;
-    const int x = b & 7, i = b >> 3;
-    int t = x * q + (x < r ? x : r) + i;
-    if (t < wl.nh * nh) {
-        w = wl.w[t / nh];
-        t %= nh;
-        bi = 0;
-        while (t >= nb - bi) {
-            t -= nb - bi;
-            ++bi;
-        }
-        bj = bi + t;
-    } else {
-        t -= wl.nh * nh;
-        w = wl.w[wl.nh + t / nf];
-        t %= nf;
-        bi = t / nb;
-        bj = t - bi * nb;
-    }
-}
-
 // One workgroup = one T x T tile of chi_w, WI x WJ waves, each a
 // (T/WI) x (T/WJ) sub-tile of 16x16 MFMA blocks.  Per stage of kKt pairs the
 // rows of M for the tile's G and G' are staged in LDS (double-buffered; rows
@@ -79,14 +53,14 @@ __device__ __forceinline__ void item_of_block(int b, const WList& wl, int nb, in
 template <int T, int WI, int WJ, int PAD>
 __global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
     const double2* __restrict__ m, int64_t kc, int ng, const double2* __restrict__ delta,
-    WList wl, double2* __restrict__ chi, int mode, int nb) {
+    WList wl, double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
     constexpr int NT = WI * WJ * 64;
     constexpr int BX = T / WI / 16, BY = T / WJ / 16;
     constexpr int LDR = T + PAD;                 // LDS row length (double2)
     constexpr int NLOAD = kKt * T / NT;          // staged elements per thread per side
     static_assert(NLOAD * NT == kKt * T && NT % T == 0, "tile / thread mismatch");
     int w, bi, bj;
-    item_of_block(blockIdx.x, wl, nb, w, bi, bj);
+    decode_item(blockIdx.x, wl, nb, order, w, bi, bj);
     extern __shared__ double2 lds[];
     double2* s_a = lds;                  // [2][kKt][LDR]
     double2* s_b = lds + 2 * kKt * LDR;  // [2][kKt][LDR]
@@ -265,16 +239,18 @@ void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
                                    static_cast<int>(v.lds)));
     ProfScope ps("chi0_f64", s);
     int mode = accumulate ? 1 : 0;
+    const int* order = tile_order(nb);
     void* args[] = {const_cast<double2**>(&m), &kc, &ng, const_cast<double2**>(&delta),
-                    const_cast<WList*>(&wl), &chi, &mode, const_cast<int*>(&nb)};
+                    const_cast<WList*>(&wl), &chi, &mode, const_cast<int*>(&nb),
+                    const_cast<int**>(&order)};
     GW_HIP_TRY(hipLaunchKernel(v.fn, dim3(static_cast<unsigned>(nitems)), dim3(v.threads), args,
                                v.lds, s));
 }
 
-void launch_mirror(double2* chi, int ng, hipStream_t s) {
+void launch_mirror(double2* chi, int ng, int tile, hipStream_t s) {
     ProfScope ps("mirror", s);
     hipLaunchKernelGGL(mirror_kernel, dim3(ceil_div(ng, 16), ceil_div(ng, 16)), dim3(256), 0, s,
-                       chi, ng, chi0_selected().tile);
+                       chi, ng, tile);
     GW_HIP_TRY(hipGetLastError());
 }
 
@@ -286,6 +262,50 @@ void launch_fill_zero(double2* p, int64_t n, hipStream_t s) {
 }
 
 int chi0_tile() { return chi0_selected().tile; }
+
+namespace {
+struct OrderCache {
+    std::mutex mu;
+    std::map<std::pair<int, int>, int*> tables;  // (device, nb) -> device table
+};
+OrderCache& order_cache() {
+    static OrderCache* c = new OrderCache();
+    return *c;
+}
+}  // namespace
+
+const int* tile_order(int nb) {
+    int dev = 0;
+    GW_HIP_TRY(hipGetDevice(&dev));
+    OrderCache& oc = order_cache();
+    std::lock_guard<std::mutex> lk(oc.mu);
+    int*& t = oc.tables[{dev, nb}];
+    if (t) return t;
+    constexpr int kSuper = 8;
+    std::vector<int> h, f;
+    for (int si = 0; si < nb; si += kSuper)
+        for (int sj = 0; sj < nb; sj += kSuper)
+            for (int i = si; i < std::min(nb, si + kSuper); ++i)
+                for (int j = sj; j < std::min(nb, sj + kSuper); ++j) {
+                    f.push_back((i << 16) | j);
+                    if (j >= i) h.push_back((i << 16) | j);
+                }
+    h.insert(h.end(), f.begin(), f.end());
+    GW_HIP_TRY(hipMalloc(&t, h.size() * sizeof(int)));
+    GW_HIP_TRY(hipMemcpy(t, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+    return t;
+}
+
+void release_tile_orders() {
+    OrderCache& oc = order_cache();
+    std::lock_guard<std::mutex> lk(oc.mu);
+    for (auto& kv : oc.tables) {
+        (void)hipSetDevice(kv.first.first);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(kv.second);
+    }
+    oc.tables.clear();
+}
 
 
 

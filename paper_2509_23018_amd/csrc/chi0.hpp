@@ -35,8 +35,20 @@ struct WList {
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
                      const WList& wl, double2* chi, bool accumulate, hipStream_t s);
 
-// Fill the tiles strictly below the diagonal from the conjugate transpose.
-void launch_mirror(double2* chi, int ng, hipStream_t s);
+// Reduced-precision contractions (same semantics as launch_chi0_f64).
+// prec 2 = split BF16, 3 = split FP16 with S slices; scratch holds
+// split_scratch_bytes(kc, ng, nz, S) bytes.
+size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S);
+void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
+                       const double2* delta, int nz, const WList& wl, double2* chi,
+                       bool accumulate, void* scratch, hipStream_t s);
+void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta, const WList& wl,
+                     double2* chi, bool accumulate, hipStream_t s);
+constexpr int kSplitTile = 64;  // tile edge of the split and FP32 kernels
+
+// Fill the tiles strictly below the diagonal (tile x tile blocks) from the
+// conjugate transpose.
+void launch_mirror(double2* chi, int ng, int tile, hipStream_t s);
 
 void launch_fill_zero(double2* p, int64_t n, hipStream_t s);
 

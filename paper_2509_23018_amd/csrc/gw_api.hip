@@ -14,6 +14,7 @@
 #include "chi0.hpp"
 #include "common.hpp"
 #include "gw.h"
+#include "items.hpp"
 #include "plan.hpp"
 #include "prof.hpp"
 
@@ -245,7 +246,7 @@ gw_status_t guarded(F&& f) {
 
 // ---------------------------------------------------------------- forward pipeline
 
-void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
+void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     const MtxelPlan& plan = *get_plan(pr.grid.n, pr.gvec, pr.ng);
     const int64_t ng = pr.ng;
     const int64_t npairs = static_cast<int64_t>(pr.nv) * pr.nc;
@@ -266,6 +267,8 @@ void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
         off_d[b] = cv.take(kmax * pr.nz * sizeof(double2));
     }
     const size_t off_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
+    const bool split = o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16;
+    const size_t off_sp = cv.take(split ? split_scratch_bytes(kmax, pr.ng, pr.nz, o.n_slices) : 0);
     char* base = static_cast<char*>(scratch(cv.off, s));
     double2* mbuf[2] = {reinterpret_cast<double2*>(base + off_m[0]),
                         reinterpret_cast<double2*>(base + off_m[1])};
@@ -331,12 +334,22 @@ void run_chi0_fp64(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
         const int b = static_cast<int>(k & 1);
         if (k + 1 < chunks.size()) produce(k + 1);
         GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1 + b], 0));
-        for (const WList& wl : wlists)
-            launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, accumulate || k > 0, s);
+        for (const WList& wl : wlists) {
+            const bool acc = accumulate || k > 0;
+            if (o.precision == GW_FP64)
+                launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
+            else if (o.precision == GW_FP32)
+                launch_chi0_f32(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
+            else
+                launch_chi0_split(o.precision, o.n_slices, mbuf[b], chunks[k].kc, pr.ng, dbuf[b],
+                                  pr.nz, wl, chi, acc, base + off_sp, s);
+        }
         GW_HIP_TRY(hipEventRecord(ax.ev[3 + b], s));
     }
     for (int w = 0; w < pr.nz; ++w)
-        if (herm[w]) launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, pr.ng, s);
+        if (herm[w])
+            launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, pr.ng,
+                          o.precision == GW_FP64 ? chi0_tile() : kSplitTile, s);
 }
 
 }  // namespace
@@ -398,15 +411,14 @@ gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* o
         if (nprob > 0 && !probs) fail(GW_EINVAL, "probs is NULL");
         const Opts o = read_opts(opts);
         for (int q = 0; q < nprob; ++q) check_problem(probs[q], q);
-        if (o.precision != GW_FP64)
-            fail(GW_EUNSUPPORTED, "precision " + std::to_string(o.precision) +
-                                      " is not implemented in this build");
+        if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
+            fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
         hipStream_t s = static_cast<hipStream_t>(stream);
         for (int q = 0; q < nprob; ++q) {
             // plan construction may still reject the sizes; do it for all first
             (void)get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
         }
-        for (int q = 0; q < nprob; ++q) run_chi0_fp64(probs[q], o, s);
+        for (int q = 0; q < nprob; ++q) run_chi0(probs[q], o, s);
     });
 }
 
@@ -437,6 +449,7 @@ gw_status_t gw_release(void) {
         release_aux();
         release_scratch();
         release_plans();
+        release_tile_orders();
     });
 }
 

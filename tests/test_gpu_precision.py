@@ -1,0 +1,142 @@
+"""Reduced-precision CHI0 paths (FP32, split BF16/FP16) against the FP64 oracle.
+
+Every result is compared with the exact FP64 chi and with an a-posteriori
+bound derived from the slicing definition (fixed-point slices with a common
+exponent per block of 64 pairs and per G):
+
+* each operand element x of block b and column g satisfies
+  |Re x|, |Im x| < 2^e, and after S slices the residual of each component is
+  at most 2^(e - 8 S - 1), so |x - x~| <= eps = sqrt(2) 2^(e - 8 S - 1);
+* slice s carries at most |q_0| 2^(e-8) <= 2^e (s = 0) or 128 2^(e-8-8s)
+  (s >= 1) per component; products with sa + sb >= S are dropped;
+* the accumulators of the sa + sb >= 3 products round in FP32 (those of
+  sa + sb <= 2 hold integer sums below 2^24 and are exact).
+
+Per output, |chi~ - chi| <= s * sum_p [ |a_p| eps_b + eps_a |b~_p| + dropped_p ]
++ FP32 rounding of the small-term accumulator + FP64 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import FP64_TOL, rel_fro, run_chi0
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+KB = 64
+
+
+def _operands(p):
+    m = oracle.mtxel(p.psi_v, p.psi_c, p.gvec, p.n, p.volume)          # [K, ng]
+    d = oracle.energy_factor(p.e_v, p.e_c, p.z) * p.spin                 # [nz, K]
+    return m, d
+
+
+def _blocks(x):
+    """Per (block, column): exponent e with max(|Re|,|Im|) < 2^e."""
+    k = x.shape[0]
+    nkb = (k + KB - 1) // KB
+    e = np.zeros((nkb, x.shape[1]))
+    for b in range(nkb):
+        blk = x[b * KB:(b + 1) * KB]
+        mx = np.maximum(np.abs(blk.real), np.abs(blk.imag)).max(axis=0)
+        e[b] = np.where(mx > 0, np.frexp(mx)[1], 0)
+    return e
+
+
+def _chunk_ranges(nv, nc, chunk):
+    """The library streams pairs in rectangles of vb valence x cw conduction
+    bands; each is a consecutive range of p = v*nc + c."""
+    cw = min(nc, chunk)
+    vb = max(1, min(nv, chunk // cw))
+    out = []
+    for v0 in range(0, nv, vb):
+        for c0 in range(0, nc, cw):
+            vs = range(v0, min(nv, v0 + vb))
+            out.append(np.array([v * nc + c for v in vs for c in range(c0, min(nc, c0 + cw))]))
+    return out
+
+
+def split_bound(m, d, S, nv, nc, chunk):
+    """Elementwise bound on |chi_split - chi| for one frequency (d = s*Delta)."""
+    ng = m.shape[1]
+    bound = np.zeros((ng, ng))
+    amp = lambda e, s: np.where(s == 0, 2.0 ** e, 2.0 ** (e - 1 - 8 * s))
+    for idx in _chunk_ranges(nv, nc, chunk):
+        a = m[idx]
+        b = d[idx, None] * a
+        ea, eb = _blocks(a), _blocks(b)
+        for blk in range(ea.shape[0]):
+            sl = slice(blk * KB, (blk + 1) * KB)
+            aa, bb = np.abs(a[sl]), np.abs(b[sl])                         # [kb, ng]
+            n = aa.shape[0]
+            eps_a = np.sqrt(2) * 2.0 ** (ea[blk] - 8 * S - 1)
+            eps_b = np.sqrt(2) * 2.0 ** (eb[blk] - 8 * S - 1)
+            trunc = np.outer(aa.sum(0), eps_b) + np.outer(eps_a, bb.sum(0) + n * eps_b)
+            dropped = np.zeros((ng, ng))
+            small = np.zeros((ng, ng))
+            for sa in range(S):
+                for sb in range(S):
+                    # complex slice magnitudes <= 2 * amp_a * amp_b (two components each)
+                    w = 2.0 * np.outer(amp(ea[blk], sa), amp(eb[blk], sb))
+                    if sa + sb >= S:
+                        dropped += n * w
+                    elif sa + sb >= 3:
+                        small += n * w
+            # FP32 rounding of the accumulators with sa + sb >= 3: at most 4 n S^2
+            # adds, each off by 2^-24 of a running sum bounded by `small`
+            bound += trunc + dropped + 4 * n * S * S * 2.0 ** -24 * small
+    return bound
+
+
+def _problem(z, seed=31):
+    return gen.make_problem((20, 18, 24), 5, 41, r2=15, z=z, seed=seed, pair_chunk=150)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_error_within_bound_and_monotone(prec):
+    p = _problem((0.0, 0.4j, 0.35 + 0.005j))
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    m, d = _operands(p)
+    errs = []
+    for S in (2, 3, 4, 5, 6):
+        got = run_chi0(p, precision=prec, n_slices=S)
+        err = rel_fro(got, ref)
+        errs.append(err)
+        for w in range(len(p.z)):
+            bnd = split_bound(m, d[w], S, p.nv, p.nc, p.pair_chunk)
+            # Hermitian frequencies mirror the upper tiles: bound their transpose too
+            bnd = np.maximum(bnd, bnd.T)
+            excess = np.abs(got[w] - ref[w]) - bnd - 1e-15 * np.abs(ref[w]).max()
+            assert excess.max() <= 0, (prec, S, w, excess.max())
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[3] <= 1e-10, errs        # five slices meet 1e-10
+    assert errs[4] <= 1e-12, errs
+
+
+def test_fp32_path():
+    p = _problem((0.0, 0.6j, 0.2 + 0.005j))
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    got = run_chi0(p, precision="fp32")
+    err = rel_fro(got, ref)
+    assert 1e-9 < err < 1e-5, err        # FP32 products: clearly not FP64, clearly FP32-accurate
+    for w in range(len(p.z)):
+        assert rel_fro(got[w], ref[w]) < 1e-5
+
+
+def test_split_edge_shapes():
+    """Chunk smaller than a block, ragged blocks, a single G."""
+    p = gen.make_problem((8, 8, 8), 2, 3, gvec=np.array([[0, 1, -1]], np.int32), z=(0.3j,),
+                         seed=4, pair_chunk=5)
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=5)
+    got = run_chi0(p, precision="split_bf16", n_slices=6)
+    assert rel_fro(got, ref) < 1e-12
+    p = gen.make_problem((12, 12, 12), 3, 70, r2=9, z=(0.0, 0.2 + 0.01j), seed=5, pair_chunk=200)
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=200)
+    got = run_chi0(p, precision="split_fp16", n_slices=6)
+    assert rel_fro(got, ref) < 1e-12
