@@ -92,6 +92,11 @@ enum {
 /* gw_opts_t.flags */
 #define GW_FLAG_NO_HERMITIAN  (1u << 0)  /* compute every tile even when Delta is real */
 #define GW_FLAG_ACCUMULATE    (1u << 1)  /* chi += result instead of chi = result */
+#define GW_FLAG_GRAPH         (1u << 2)  /* capture the whole call into a HIP graph on first
+                                            use and replay it when called again with the same
+                                            problems (same pointers, sizes, G lists, z, opts) */
+#define GW_FLAG_AUTOTUNE      (1u << 3)  /* time the CHI0 tile shapes on this data once per
+                                            shape and keep the fastest (also GW_AUTOTUNE=1) */
 
 /* One chi0 problem (one q-point). */
 typedef struct {
@@ -145,12 +150,17 @@ gw_status_t gw_mtxel(const gw_grid_t* grid,
  *       s * sum_p Delta_p(z_w) * conj(M_p(G_i)) * M_p(G_j)
  *
  * M is streamed in chunks of opts->pair_chunk pairs through a library
- * scratch buffer and never stored whole.  When every z_w of a problem has a
- * zero real part, Delta is real, chi is Hermitian, and only the tiles on or
+ * scratch buffer and never stored whole.  When a frequency has a zero real
+ * part, its Delta is real, its chi is Hermitian, and only the tiles on or
  * above the diagonal are contracted; the rest are mirrored (unless
- * GW_FLAG_NO_HERMITIAN).  nv*nc == 0 yields chi = 0.
- * opts may be NULL (FP64, chunk 4096, s = 2).  Returns GW_EUNSUPPORTED for a
- * precision this build does not implement.
+ * GW_FLAG_NO_HERMITIAN or GW_FLAG_ACCUMULATE).  nv*nc == 0 yields chi = 0.
+ * With nprob > 1 and FP64, the chunks of all problems are processed in
+ * rounds, each round's contraction as one persistent launch over all
+ * (problem, frequency, tile) items, largest first; with GW_FLAG_GRAPH the
+ * whole call is captured once and replayed (the caller keeps every pointer
+ * valid and unchanged between replays; problems must not change size).
+ * opts may be NULL (FP64, chunk 4096, s = 2).  Split precision accepts
+ * 2..6 slices; returns GW_EUNSUPPORTED beyond that.
  */
 gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob,
                     const gw_opts_t* opts, void* stream);

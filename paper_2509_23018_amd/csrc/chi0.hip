@@ -51,24 +51,20 @@ constexpr int kKt = 16;     // pairs per LDS stage
 // are clamped and only feed outputs that are not stored.
 // mode: 0 overwrite, 1 accumulate.
 template <int T, int WI, int WJ, int PAD>
-__global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
-    const double2* __restrict__ m, int64_t kc, int ng, const double2* __restrict__ delta,
-    WList wl, double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
+__device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict__ m, int64_t kc,
+                                         int ng, const double2* __restrict__ dw,
+                                         double2* __restrict__ cw, int mode, int bi, int bj) {
     constexpr int NT = WI * WJ * 64;
     constexpr int BX = T / WI / 16, BY = T / WJ / 16;
     constexpr int LDR = T + PAD;                 // LDS row length (double2)
     constexpr int NLOAD = kKt * T / NT;          // staged elements per thread per side
     static_assert(NLOAD * NT == kKt * T && NT % T == 0, "tile / thread mismatch");
-    int w, bi, bj;
-    decode_item(blockIdx.x, wl, nb, order, w, bi, bj);
-    extern __shared__ double2 lds[];
     double2* s_a = lds;                  // [2][kKt][LDR]
     double2* s_b = lds + 2 * kKt * LDR;  // [2][kKt][LDR]
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
     const int wi = wave / WJ, wj = wave % WJ;
     const int i0 = bi * T, j0 = bj * T;
-    const double2* dw = delta + static_cast<int64_t>(w) * kc;
 
     // staging slots: element e = tid + NT*u -> row kk = e / T, column cc = e % T;
     // NT is a multiple of T, so cc is the same for every u and kk steps by NT/T
@@ -141,7 +137,6 @@ __global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
         __syncthreads();
         buf = nb2;
     }
-    double2* cw = chi + static_cast<int64_t>(w) * ng * ng;
 #pragma unroll
     for (int x = 0; x < BX; ++x)
 #pragma unroll
@@ -163,31 +158,61 @@ __global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
             }
 }
 
+
+template <int T, int WI, int WJ, int PAD>
+__global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
+    const double2* __restrict__ m, int64_t kc, int ng, const double2* __restrict__ delta,
+    WList wl, double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
+    int w, bi, bj;
+    decode_item(blockIdx.x, wl, nb, order, w, bi, bj);
+    extern __shared__ double2 lds[];
+    f64_tile<T, WI, WJ, PAD>(lds, m, kc, ng, delta + static_cast<int64_t>(w) * kc,
+                             chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj);
+}
+
+// Persistent form for batches of problems: every workgroup takes items
+// (problem, frequency, tile) from an atomic counter until the list is
+// exhausted, so problems of very different N_G share one launch without a
+// tail per problem.  Items are sorted by decreasing cost on the host.
+template <int T, int WI, int WJ, int PAD>
+__global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_batched_kernel(
+    const QDesc* __restrict__ qd, const int4* __restrict__ items, int nitems,
+    int* __restrict__ counter) {
+    extern __shared__ double2 lds[];
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const int4 itm = items[it];
+        const QDesc d = qd[itm.x];
+        f64_tile<T, WI, WJ, PAD>(lds, d.m, d.kc, d.ng, d.delta + static_cast<int64_t>(itm.y) * d.kc,
+                                 d.chi + static_cast<int64_t>(itm.y) * d.ng * d.ng, d.mode, itm.z,
+                                 itm.w);
+    }
+}
+
 struct Chi0Variant {
-    const void* fn;
+    const void* fn;       // per-launch kernel
+    const void* fn_batch; // persistent batched kernel
     int tile, threads;
     size_t lds;
 };
 
 template <int T, int WI, int WJ, int PAD>
 Chi0Variant chi0_variant() {
-    return {reinterpret_cast<const void*>(&chi0_f64_kernel<T, WI, WJ, PAD>), T, WI * WJ * 64,
-            2 * 2 * kKt * (T + PAD) * sizeof(double2)};
+    return {reinterpret_cast<const void*>(&chi0_f64_kernel<T, WI, WJ, PAD>),
+            reinterpret_cast<const void*>(&chi0_f64_batched_kernel<T, WI, WJ, PAD>), T,
+            WI * WJ * 64, 2 * 2 * kKt * (T + PAD) * sizeof(double2)};
 }
 
-const Chi0Variant& chi0_selected() {
-    static const Chi0Variant v = [] {
-        const char* e = std::getenv("GW_CHI0_VARIANT");
-        const int id = e ? std::atoi(e) : 0;
-        switch (id) {
-            case 1: return chi0_variant<64, 2, 2, 1>();
-            case 2: return chi0_variant<128, 2, 4, 0>();
-            case 3: return chi0_variant<128, 2, 4, 1>();
-            case 4: return chi0_variant<128, 4, 2, 1>();
-            default: return chi0_variant<64, 2, 2, 0>();
-        }
-    }();
-    return v;
+// Tile shapes of the FP64 contraction, indexed by variant id (the autotuner
+// chooses among them; GW_CHI0_VARIANT forces one).
+const Chi0Variant& chi0_variant_by_id(int id) {
+    static const Chi0Variant v[2] = {chi0_variant<64, 2, 2, 0>(), chi0_variant<128, 2, 4, 0>()};
+    return v[id == 1 ? 1 : 0];
 }
 
 // chi[i][j] = conj(chi[j][i]) for every (i, j) in a tile strictly below the
@@ -228,9 +253,9 @@ void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npai
 }
 
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
-                     const WList& wl, double2* chi, bool accumulate, hipStream_t s) {
+                     const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
-    const Chi0Variant& v = chi0_selected();
+    const Chi0Variant& v = chi0_variant_by_id(variant);
     const int nb = ceil_div(ng, v.tile);
     const int64_t nitems = static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
                            static_cast<int64_t>(wl.nf) * nb * nb;
@@ -247,6 +272,28 @@ void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
                                v.lds, s));
 }
 
+void launch_chi0_f64_batched(const QDesc* qd, const int4* items, int nitems, int* counter,
+                             hipStream_t s, int variant, int grid) {
+    if (nitems <= 0) return;
+    const Chi0Variant& v = chi0_variant_by_id(variant);
+    GW_HIP_TRY(hipFuncSetAttribute(v.fn_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(v.lds)));
+    ProfScope ps("chi0_f64_batched", s);
+    void* args[] = {const_cast<QDesc**>(&qd), const_cast<int4**>(&items), &nitems, &counter};
+    GW_HIP_TRY(hipLaunchKernel(v.fn_batch, dim3(static_cast<unsigned>(std::min(grid, nitems))),
+                               dim3(v.threads), args, v.lds, s));
+}
+
+int chi0_variant_tile(int variant) { return chi0_variant_by_id(variant).tile; }
+
+int chi0_forced_variant() {
+    static const int id = [] {
+        const char* e = std::getenv("GW_CHI0_VARIANT");
+        return e ? std::atoi(e) : -1;
+    }();
+    return id;
+}
+
 void launch_mirror(double2* chi, int ng, int tile, hipStream_t s) {
     ProfScope ps("mirror", s);
     hipLaunchKernelGGL(mirror_kernel, dim3(ceil_div(ng, 16), ceil_div(ng, 16)), dim3(256), 0, s,
@@ -261,7 +308,7 @@ void launch_fill_zero(double2* p, int64_t n, hipStream_t s) {
     GW_HIP_TRY(hipGetLastError());
 }
 
-int chi0_tile() { return chi0_selected().tile; }
+
 
 namespace {
 struct OrderCache {

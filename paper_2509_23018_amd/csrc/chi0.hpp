@@ -31,9 +31,28 @@ struct WList {
 };
 
 // chi[w] (=|+=) M^H diag(delta[w]) M for every frequency w of wl; M is
-// [kc][ng], delta [nz][kc], chi [nz][ng][ng].
+// [kc][ng], delta [nz][kc], chi [nz][ng][ng].  variant selects the tile
+// shape (0: 64x64, 4 waves; 1: 128x128, 8 waves).
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
-                     const WList& wl, double2* chi, bool accumulate, hipStream_t s);
+                     const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant);
+int chi0_variant_tile(int variant);
+int chi0_forced_variant();  // GW_CHI0_VARIANT, or -1
+constexpr int kNumChi0Variants = 2;
+
+// One problem's operands for the batched contraction.
+struct QDesc {
+    const double2* m;      // [kc][ng]
+    const double2* delta;  // [nz][kc]
+    double2* chi;          // [nz][ng][ng]
+    int64_t kc;
+    int ng;
+    int mode;              // 0 overwrite, 1 accumulate
+};
+
+// Persistent contraction over items (problem, frequency, tile row, tile col);
+// counter must be 0 on entry.  grid = number of workgroups to keep resident.
+void launch_chi0_f64_batched(const QDesc* qd, const int4* items, int nitems, int* counter,
+                             hipStream_t s, int variant, int grid);
 
 // Reduced-precision contractions (same semantics as launch_chi0_f64).
 // prec 2 = split BF16, 3 = split FP16 with S slices; scratch holds
@@ -52,6 +71,5 @@ void launch_mirror(double2* chi, int ng, int tile, hipStream_t s);
 
 void launch_fill_zero(double2* p, int64_t n, hipStream_t s);
 
-int chi0_tile();
 
 }  // namespace gw

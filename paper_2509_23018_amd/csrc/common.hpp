@@ -20,8 +20,10 @@ struct Error {
 #define GW_HIP_TRY(expr)                                                              \
     do {                                                                              \
         hipError_t e__ = (expr);                                                      \
-        if (e__ != hipSuccess)                                                        \
+        if (e__ != hipSuccess) {                                                      \
+            (void)hipGetLastError(); /* a reported error must not fail the next call */ \
             throw ::gw::Error{-3, std::string(#expr) + ": " + hipGetErrorString(e__)}; \
+        }                                                                             \
     } while (0)
 
 // ---------------------------------------------------------------- complex on double2

@@ -2,7 +2,10 @@
 // MTXEL -> energy factor -> CHI0 pipeline (declared in include/gw.h).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -83,6 +86,7 @@ void release_scratch() {
 struct AuxCtx {
     hipStream_t aux = nullptr;
     hipEvent_t ev[6] = {};
+    hipStream_t cap = nullptr;  // graphs are captured here (the null stream cannot capture)
 };
 
 struct AuxPool {
@@ -93,6 +97,15 @@ struct AuxPool {
 AuxPool& aux_pool() {
     static AuxPool* p = new AuxPool();
     return *p;
+}
+
+AuxCtx& aux_ctx(hipStream_t s);
+
+hipStream_t capture_stream(hipStream_t s) {
+    AuxCtx& a = aux_ctx(s);
+    std::lock_guard<std::mutex> lk(aux_pool().mu);
+    if (!a.cap) GW_HIP_TRY(hipStreamCreateWithFlags(&a.cap, hipStreamNonBlocking));
+    return a.cap;
 }
 
 AuxCtx& aux_ctx(hipStream_t s) {
@@ -116,6 +129,7 @@ void release_aux() {
         (void)hipStreamSynchronize(kv.second.aux);
         for (auto& e : kv.second.ev) (void)hipEventDestroy(e);
         (void)hipStreamDestroy(kv.second.aux);
+        if (kv.second.cap) (void)hipStreamDestroy(kv.second.cap);
     }
     p.by_key.clear();
 }
@@ -186,7 +200,7 @@ Opts read_opts(const gw_opts_t* o) {
     if ((r.precision == GW_SPLIT_BF16 || r.precision == GW_SPLIT_FP16) &&
         (r.n_slices < 2 || r.n_slices > 8))
         fail(GW_EINVAL, "n_slices must be in [2, 8] for split precision");
-    if (r.flags & ~(GW_FLAG_NO_HERMITIAN | GW_FLAG_ACCUMULATE))
+    if (r.flags & ~(GW_FLAG_NO_HERMITIAN | GW_FLAG_ACCUMULATE | GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE))
         fail(GW_EINVAL, "unknown flag bits");
     return r;
 }
@@ -246,6 +260,121 @@ gw_status_t guarded(F&& f) {
 
 // ---------------------------------------------------------------- forward pipeline
 
+struct Chunk {
+    PairMap pm;
+    int vcount;
+    int64_t kc;
+};
+
+std::vector<Chunk> make_chunks(const gw_problem_t& pr, const ChunkShape& cs) {
+    std::vector<Chunk> chunks;
+    for (int iv = 0; iv < cs.ncv; ++iv)
+        for (int ic = 0; ic < cs.ncc; ++ic) {
+            Chunk c;
+            c.pm.v0 = iv * cs.vb;
+            c.pm.c0 = ic * cs.cw;
+            c.pm.cw = std::min(cs.cw, pr.nc - c.pm.c0);
+            c.pm.k_off = 0;
+            c.vcount = std::min(cs.vb, pr.nv - c.pm.v0);
+            c.kc = static_cast<int64_t>(c.vcount) * c.pm.cw;
+            chunks.push_back(c);
+        }
+    return chunks;
+}
+
+// Frequencies whose Delta is real (Re z = 0) give Hermitian chi.
+std::vector<bool> hermitian_freqs(const gw_problem_t& pr, const Opts& o) {
+    std::vector<bool> herm(pr.nz);
+    const bool acc = (o.flags & GW_FLAG_ACCUMULATE) != 0;
+    for (int w = 0; w < pr.nz; ++w)
+        herm[w] = pr.z[w].re == 0.0 && !(o.flags & GW_FLAG_NO_HERMITIAN) && !acc;
+    return herm;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+bool autotune_enabled(const Opts& o) {
+    static const bool env = [] {
+        const char* e = std::getenv("GW_AUTOTUNE");
+        return e && std::atoi(e) != 0;
+    }();
+    return env || (o.flags & GW_FLAG_AUTOTUNE);
+}
+
+// Best FP64 tile variant per (N_G, chunk pairs), chosen by timing every
+// candidate on real data once; kept for the process and, when GW_AUTOTUNE_CACHE
+// names a file, in that file ("ng kc variant ms..." per line).
+struct TuneCache {
+    std::mutex mu;
+    std::map<std::pair<int, int64_t>, int> best;
+    bool loaded = false;
+};
+
+TuneCache& tune_cache() {
+    static TuneCache* c = new TuneCache();
+    return *c;
+}
+
+const char* tune_file() { return std::getenv("GW_AUTOTUNE_CACHE"); }
+
+int lookup_variant(int ng, int64_t kc) {
+    const int forced = chi0_forced_variant();
+    if (forced >= 0) return forced < kNumChi0Variants ? forced : 0;
+    TuneCache& tc = tune_cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    if (!tc.loaded) {
+        tc.loaded = true;
+        if (const char* f = tune_file()) {
+            if (FILE* fp = std::fopen(f, "r")) {
+                int a, v;
+                long long b;
+                char line[256];
+                while (std::fgets(line, sizeof line, fp))
+                    if (std::sscanf(line, "%d %lld %d", &a, &b, &v) == 3 && v >= 0 &&
+                        v < kNumChi0Variants)
+                        tc.best[{a, b}] = v;
+                std::fclose(fp);
+            }
+        }
+    }
+    auto it = tc.best.find({ng, kc});
+    return it == tc.best.end() ? -1 : it->second;
+}
+
+// trial(v) enqueues variant v's contraction of the same data on s.
+int tune_variant(int ng, int64_t kc, hipStream_t s, const std::function<void(int)>& trial) {
+    const int known = lookup_variant(ng, kc);
+    if (known >= 0) return known;
+    hipEvent_t e0, e1;
+    GW_HIP_TRY(hipEventCreate(&e0));
+    GW_HIP_TRY(hipEventCreate(&e1));
+    float ms[kNumChi0Variants];
+    int best = 0;
+    for (int v = 0; v < kNumChi0Variants; ++v) {
+        trial(v);  // warm-up (kernel load, caches)
+        GW_HIP_TRY(hipEventRecord(e0, s));
+        trial(v);
+        GW_HIP_TRY(hipEventRecord(e1, s));
+        GW_HIP_TRY(hipEventSynchronize(e1));
+        GW_HIP_TRY(hipEventElapsedTime(&ms[v], e0, e1));
+        if (ms[v] < ms[best]) best = v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TuneCache& tc = tune_cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    tc.best[{ng, kc}] = best;
+    if (const char* f = tune_file()) {
+        if (FILE* fp = std::fopen(f, "a")) {
+            std::fprintf(fp, "%d %lld %d", ng, static_cast<long long>(kc), best);
+            for (int v = 0; v < kNumChi0Variants; ++v) std::fprintf(fp, " %.4f", ms[v]);
+            std::fprintf(fp, "\n");
+            std::fclose(fp);
+        }
+    }
+    return best;
+}
+
 void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     const MtxelPlan& plan = *get_plan(pr.grid.n, pr.gvec, pr.ng);
     const int64_t ng = pr.ng;
@@ -297,23 +426,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
             wlists.push_back(wl);
         }
     }
-    struct Chunk {
-        PairMap pm;
-        int vcount;
-        int64_t kc;
-    };
-    std::vector<Chunk> chunks;
-    for (int iv = 0; iv < cs.ncv; ++iv)
-        for (int ic = 0; ic < cs.ncc; ++ic) {
-            Chunk c;
-            c.pm.v0 = iv * cs.vb;
-            c.pm.c0 = ic * cs.cw;
-            c.pm.cw = std::min(cs.cw, pr.nc - c.pm.c0);
-            c.pm.k_off = 0;
-            c.vcount = std::min(cs.vb, pr.nv - c.pm.v0);
-            c.kc = static_cast<int64_t>(c.vcount) * c.pm.cw;
-            chunks.push_back(c);
-        }
+    const std::vector<Chunk> chunks = make_chunks(pr, cs);
     // events: ev[0] caller-stream start, ev[1+b] MTXEL into buffer b done,
     // ev[3+b] CHI0 reading buffer b done
     AuxCtx& ax = aux_ctx(s);
@@ -330,6 +443,19 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     GW_HIP_TRY(hipEventRecord(ax.ev[0], s));
     GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[0], 0));
     produce(0);
+    int variant = 0;
+    if (o.precision == GW_FP64) {
+        variant = lookup_variant(pr.ng, chunks[0].kc);
+        if (variant < 0 && autotune_enabled(o)) {
+            // time the tile shapes on the first chunk (its results are overwritten below)
+            GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1], 0));
+            variant = tune_variant(pr.ng, chunks[0].kc, s, [&](int v) {
+                for (const WList& wl : wlists)
+                    launch_chi0_f64(mbuf[0], chunks[0].kc, pr.ng, dbuf[0], wl, chi, accumulate, s, v);
+            });
+        }
+        if (variant < 0) variant = 0;
+    }
     for (size_t k = 0; k < chunks.size(); ++k) {
         const int b = static_cast<int>(k & 1);
         if (k + 1 < chunks.size()) produce(k + 1);
@@ -337,7 +463,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
         for (const WList& wl : wlists) {
             const bool acc = accumulate || k > 0;
             if (o.precision == GW_FP64)
-                launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
+                launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s, variant);
             else if (o.precision == GW_FP32)
                 launch_chi0_f32(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
             else
@@ -349,9 +475,323 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     for (int w = 0; w < pr.nz; ++w)
         if (herm[w])
             launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, pr.ng,
-                          o.precision == GW_FP64 ? chi0_tile() : kSplitTile, s);
+                          o.precision == GW_FP64 ? chi0_variant_tile(variant) : kSplitTile, s);
 }
 
+
+// ---------------------------------------------------------------- batched problems
+
+// One problem of a batch: its plan, chunks and buffers (offsets into the
+// batch's scratch).
+struct BatchQ {
+    const MtxelPlan* plan = nullptr;
+    std::vector<Chunk> chunks;
+    std::vector<bool> herm;
+    int64_t kmax = 0;
+    size_t off_m[2] = {0, 0}, off_d[2] = {0, 0};
+};
+
+struct BatchPlan {
+    std::vector<BatchQ> q;
+    int rounds = 0;
+    int variant = 0;
+    int grid = 0;
+    size_t off_t2 = 0, off_desc = 0, off_items = 0, off_cnt = 0, bytes = 0;
+    std::vector<int> nitems;       // per round
+    std::vector<size_t> item_off;  // per round, in int4 units
+};
+
+int persistent_grid(int variant) {
+    int dev = 0, cus = 0;
+    GW_HIP_TRY(hipGetDevice(&dev));
+    GW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return cus * (chi0_variant_tile(variant) == 64 ? 2 : 1);  // workgroups resident per CU (LDS)
+}
+
+// Items of round r: (problem, frequency, tile row, tile col), all problems,
+// largest chunk first; tiles of one problem and frequency in super-tile order.
+std::vector<int4> round_items(const BatchPlan& bp, int r, const gw_problem_t* probs) {
+    const int tile = chi0_variant_tile(bp.variant);
+    std::vector<std::pair<int64_t, int4>> v;
+    for (size_t q = 0; q < bp.q.size(); ++q) {
+        const BatchQ& b = bp.q[q];
+        if (r >= static_cast<int>(b.chunks.size())) continue;
+        const int nb = ceil_div(probs[q].ng, tile);
+        for (int w = 0; w < probs[q].nz; ++w) {
+            constexpr int kSuper = 8;
+            for (int si = 0; si < nb; si += kSuper)
+                for (int sj = 0; sj < nb; sj += kSuper)
+                    for (int i = si; i < std::min(nb, si + kSuper); ++i)
+                        for (int j = sj; j < std::min(nb, sj + kSuper); ++j)
+                            if (!b.herm[w] || j >= i)
+                                v.push_back({b.chunks[r].kc,
+                                             make_int4(static_cast<int>(q), w, i, j)});
+        }
+    }
+    std::stable_sort(v.begin(), v.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    std::vector<int4> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].second;
+    return out;
+}
+
+BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int variant) {
+    BatchPlan bp;
+    bp.variant = variant;
+    bp.grid = persistent_grid(variant);
+    bp.q.resize(nprob);
+    Carver cv;
+    size_t t2max = 0;
+    for (int q = 0; q < nprob; ++q) {
+        BatchQ& b = bp.q[q];
+        const gw_problem_t& pr = probs[q];
+        b.plan = get_plan(pr.grid.n, pr.gvec, pr.ng);
+        b.herm = hermitian_freqs(pr, o);
+        if (static_cast<int64_t>(pr.nv) * pr.nc > 0) {
+            const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
+            b.chunks = make_chunks(pr, cs);
+            b.kmax = static_cast<int64_t>(cs.vb) * cs.cw;
+        }
+        for (int k = 0; k < 2; ++k) {
+            b.off_m[k] = cv.take(b.kmax * pr.ng * sizeof(double2));
+            b.off_d[k] = cv.take(b.kmax * pr.nz * sizeof(double2));
+        }
+        t2max = std::max(t2max, t2_elems(*b.plan, b.kmax) * sizeof(double2));
+        bp.rounds = std::max(bp.rounds, static_cast<int>(b.chunks.size()));
+    }
+    bp.off_t2 = cv.take(t2max);
+    bp.off_desc = cv.take(static_cast<size_t>(bp.rounds) * nprob * sizeof(QDesc));
+    size_t ntot = 0;
+    for (int r = 0; r < bp.rounds; ++r) {
+        bp.item_off.push_back(ntot);
+        bp.nitems.push_back(static_cast<int>(round_items(bp, r, probs).size()));
+        ntot += bp.nitems.back();
+    }
+    bp.off_items = cv.take(std::max<size_t>(1, ntot) * sizeof(int4));
+    bp.off_cnt = cv.take(std::max(1, bp.rounds) * sizeof(double2));
+    bp.bytes = cv.off;
+    return bp;
+}
+
+// Descriptor and item tables into the device buffer (synchronous copies).
+void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base) {
+    const int nprob = static_cast<int>(bp.q.size());
+    std::vector<QDesc> desc(static_cast<size_t>(bp.rounds) * nprob);
+    std::vector<int4> items;
+    for (int r = 0; r < bp.rounds; ++r) {
+        for (int q = 0; q < nprob; ++q) {
+            const BatchQ& b = bp.q[q];
+            QDesc& d = desc[static_cast<size_t>(r) * nprob + q];
+            d.m = reinterpret_cast<const double2*>(base + b.off_m[r & 1]);
+            d.delta = reinterpret_cast<const double2*>(base + b.off_d[r & 1]);
+            d.chi = reinterpret_cast<double2*>(probs[q].chi);
+            d.kc = r < static_cast<int>(b.chunks.size()) ? b.chunks[r].kc : 0;
+            d.ng = probs[q].ng;
+            d.mode = (r > 0 || (o.flags & GW_FLAG_ACCUMULATE)) ? 1 : 0;
+        }
+        const std::vector<int4> it = round_items(bp, r, probs);
+        items.insert(items.end(), it.begin(), it.end());
+    }
+    GW_HIP_TRY(hipMemcpy(base + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc),
+                         hipMemcpyHostToDevice));
+    if (!items.empty())
+        GW_HIP_TRY(hipMemcpy(base + bp.off_items, items.data(), items.size() * sizeof(int4),
+                             hipMemcpyHostToDevice));
+}
+
+void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base,
+                   hipStream_t s) {
+    const int nprob = static_cast<int>(bp.q.size());
+    double2* t2 = reinterpret_cast<double2*>(base + bp.off_t2);
+    // problems without pairs: chi = 0
+    for (int q = 0; q < nprob; ++q)
+        if (bp.q[q].chunks.empty() && !(o.flags & GW_FLAG_ACCUMULATE))
+            launch_fill_zero(reinterpret_cast<double2*>(probs[q].chi),
+                             static_cast<int64_t>(probs[q].ng) * probs[q].ng * probs[q].nz, s);
+    if (bp.rounds == 0) return;
+    launch_fill_zero(reinterpret_cast<double2*>(base + bp.off_cnt), bp.rounds, s);
+    AuxCtx& ax = aux_ctx(s);
+    auto produce = [&](int r) {  // MTXEL + Delta of round r, every problem, companion stream
+        const int b = r & 1;
+        if (r >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[3 + b], 0));
+        for (int q = 0; q < nprob; ++q) {
+            const BatchQ& bq = bp.q[q];
+            if (r >= static_cast<int>(bq.chunks.size())) continue;
+            const gw_problem_t& pr = probs[q];
+            const Chunk& c = bq.chunks[r];
+            launch_mtxel(*bq.plan, reinterpret_cast<const double2*>(pr.psi_v),
+                         reinterpret_cast<const double2*>(pr.psi_c),
+                         Rect{c.pm.v0, c.vcount, c.pm.c0, c.pm.cw}, pr.grid.volume, t2,
+                         reinterpret_cast<double2*>(base + bq.off_m[b]), ax.aux);
+            launch_delta(pr.e_v, pr.e_c, c.pm, c.kc, reinterpret_cast<const double2*>(pr.z), pr.nz,
+                         o.spin, reinterpret_cast<double2*>(base + bq.off_d[b]), ax.aux);
+        }
+        GW_HIP_TRY(hipEventRecord(ax.ev[1 + b], ax.aux));
+    };
+    GW_HIP_TRY(hipEventRecord(ax.ev[0], s));
+    GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[0], 0));
+    produce(0);
+    for (int r = 0; r < bp.rounds; ++r) {
+        const int b = r & 1;
+        if (r + 1 < bp.rounds) produce(r + 1);
+        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1 + b], 0));
+        launch_chi0_f64_batched(
+            reinterpret_cast<const QDesc*>(base + bp.off_desc) + static_cast<size_t>(r) * nprob,
+            reinterpret_cast<const int4*>(base + bp.off_items) + bp.item_off[r], bp.nitems[r],
+            reinterpret_cast<int*>(base + bp.off_cnt) + r, s, bp.variant, bp.grid);
+        GW_HIP_TRY(hipEventRecord(ax.ev[3 + b], s));
+    }
+    const int tile = chi0_variant_tile(bp.variant);
+    for (int q = 0; q < nprob; ++q)
+        for (int w = 0; w < probs[q].nz; ++w)
+            if (bp.q[q].herm[w] && !bp.q[q].chunks.empty())
+                launch_mirror(reinterpret_cast<double2*>(probs[q].chi) +
+                                  static_cast<int64_t>(w) * probs[q].ng * probs[q].ng,
+                              probs[q].ng, tile, s);
+}
+
+// Tile variant of a batch: forced, cached, or tuned on its largest problem's
+// first chunk (one frequency, into a scratch chi so no output is touched).
+int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+    int qmax = -1;
+    for (int q = 0; q < nprob; ++q)
+        if (static_cast<int64_t>(probs[q].nv) * probs[q].nc > 0 &&
+            (qmax < 0 || probs[q].ng > probs[qmax].ng))
+            qmax = q;
+    if (qmax < 0) return 0;
+    const gw_problem_t& pr = probs[qmax];
+    const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
+    const std::vector<Chunk> ch = make_chunks(pr, cs);
+    int v = lookup_variant(pr.ng, ch[0].kc);
+    if (v >= 0) return v;
+    if (!autotune_enabled(o)) return 0;
+    const MtxelPlan& plan = *get_plan(pr.grid.n, pr.gvec, pr.ng);
+    Carver cv;
+    const size_t om = cv.take(ch[0].kc * pr.ng * sizeof(double2));
+    const size_t od = cv.take(ch[0].kc * pr.nz * sizeof(double2));
+    const size_t ot = cv.take(t2_elems(plan, ch[0].kc) * sizeof(double2));
+    const size_t oc = cv.take(static_cast<size_t>(pr.ng) * pr.ng * sizeof(double2));
+    char* base = static_cast<char*>(scratch(cv.off, s));
+    launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
+                 reinterpret_cast<const double2*>(pr.psi_c),
+                 Rect{ch[0].pm.v0, ch[0].vcount, ch[0].pm.c0, ch[0].pm.cw}, pr.grid.volume,
+                 reinterpret_cast<double2*>(base + ot), reinterpret_cast<double2*>(base + om), s);
+    launch_delta(pr.e_v, pr.e_c, ch[0].pm, ch[0].kc, reinterpret_cast<const double2*>(pr.z), pr.nz,
+                 o.spin, reinterpret_cast<double2*>(base + od), s);
+    WList wl{};
+    wl.w[0] = 0;
+    wl.nf = 1;
+    return tune_variant(pr.ng, ch[0].kc, s, [&](int vv) {
+        launch_chi0_f64(reinterpret_cast<const double2*>(base + om), ch[0].kc, pr.ng,
+                        reinterpret_cast<const double2*>(base + od), wl,
+                        reinterpret_cast<double2*>(base + oc), false, s, vv);
+    });
+}
+
+// Captured batches: the graph and the device buffer it was captured with.
+struct GraphEntry {
+    std::string key;
+    int device = 0;
+    hipGraphExec_t exec = nullptr;
+    void* buffer = nullptr;
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::vector<GraphEntry> entries;
+};
+
+GraphCache& graph_cache() {
+    static GraphCache* c = new GraphCache();
+    return *c;
+}
+
+std::string batch_key(const gw_problem_t* probs, int nprob, const Opts& o) {
+    std::string k;
+    auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    put(&dev, sizeof dev);
+    put(&nprob, sizeof nprob);
+    put(&o, sizeof o);
+    for (int q = 0; q < nprob; ++q) {
+        const gw_problem_t& p = probs[q];
+        put(&p, sizeof p);  // pointers, sizes, grid
+        put(p.gvec, static_cast<size_t>(p.ng) * 3 * sizeof(int32_t));
+        put(p.z, static_cast<size_t>(p.nz) * sizeof(gw_c128));
+    }
+    return k;
+}
+
+void release_graphs() {
+    GraphCache& gc = graph_cache();
+    std::lock_guard<std::mutex> lk(gc.mu);
+    for (auto& e : gc.entries) {
+        (void)hipSetDevice(e.device);
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipFree(e.buffer);
+    }
+    gc.entries.clear();
+}
+
+void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+    if (!(o.flags & GW_FLAG_GRAPH)) {
+        const BatchPlan bp = build_batch(probs, nprob, o, batch_variant(probs, nprob, o, s));
+        char* base = static_cast<char*>(scratch(bp.bytes, s));
+        GW_HIP_TRY(hipStreamSynchronize(s));  // the tables below may still be read by earlier work
+        upload_batch(bp, probs, o, base);
+        enqueue_batch(bp, probs, o, base, s);
+        return;
+    }
+    const std::string key = batch_key(probs, nprob, o);
+    GraphCache& gc = graph_cache();
+    {
+        std::lock_guard<std::mutex> lk(gc.mu);
+        for (auto& e : gc.entries)
+            if (e.key == key) {
+                GW_HIP_TRY(hipGraphLaunch(e.exec, s));
+                return;
+            }
+    }
+    // first call: everything that allocates or copies happens before capture
+    const BatchPlan bp = build_batch(probs, nprob, o, batch_variant(probs, nprob, o, s));
+    for (int q = 0; q < nprob; ++q) (void)tile_order(ceil_div(probs[q].ng, chi0_variant_tile(bp.variant)));
+    const hipStream_t cs = capture_stream(s);
+    (void)aux_ctx(cs);
+    GraphEntry e;
+    e.key = key;
+    GW_HIP_TRY(hipGetDevice(&e.device));
+    if (hipMalloc(&e.buffer, std::max<size_t>(bp.bytes, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(GW_ENOMEM, "hipMalloc of the batch buffer failed");
+    }
+    try {
+        upload_batch(bp, probs, o, static_cast<char*>(e.buffer));
+        hipGraph_t g = nullptr;
+        GW_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        try {
+            enqueue_batch(bp, probs, o, static_cast<char*>(e.buffer), cs);
+        } catch (...) {
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            throw;
+        }
+        GW_HIP_TRY(hipStreamEndCapture(cs, &g));
+        const hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        GW_HIP_TRY(ie);
+    } catch (...) {
+        (void)hipFree(e.buffer);
+        throw;
+    }
+    {
+        std::lock_guard<std::mutex> lk(gc.mu);
+        gc.entries.push_back(e);
+    }
+    GW_HIP_TRY(hipGraphLaunch(e.exec, s));
+}
 }  // namespace
 }  // namespace gw
 
@@ -418,7 +858,10 @@ gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* o
             // plan construction may still reject the sizes; do it for all first
             (void)get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
         }
-        for (int q = 0; q < nprob; ++q) run_chi0(probs[q], o, s);
+        if (nprob > 1 && o.precision == GW_FP64)
+            run_chi0_batched(probs, nprob, o, s);
+        else
+            for (int q = 0; q < nprob; ++q) run_chi0(probs[q], o, s);
     });
 }
 
@@ -446,6 +889,7 @@ const char* gw_last_error(void) { return g_last_error.c_str(); }
 
 gw_status_t gw_release(void) {
     return guarded([&] {
+        release_graphs();
         release_aux();
         release_scratch();
         release_plans();

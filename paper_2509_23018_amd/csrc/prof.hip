@@ -81,6 +81,8 @@ void prof_read(const char* name, int64_t* launches, double* total_ms) {
 
 ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
     if (!prof_on()) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     Registry& r = reg();
     std::lock_guard<std::mutex> lk(r.mu);
     a_ = take_event(r);

@@ -1,0 +1,106 @@
+"""Batched problems (several q-points of uneven size) in one call: the
+persistent contraction, graph capture and replay, and the tile autotuner,
+each against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_23018_amd as gw
+from gpu_helpers import FP64_TOL, device, rel_fro, to_dev
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(p):
+    return oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                       spin=p.spin, pair_chunk=p.pair_chunk)
+
+
+def _batch(seed=0, chunk=40):
+    """Uneven shifted G-spheres, band counts and grids; mixed frequency kinds."""
+    zs = (0.0, 0.3j, 0.25 + 0.01j)
+    out = []
+    for i, (n, nv, nc, ng) in enumerate([((12, 12, 12), 3, 17, 60), ((16, 12, 14), 2, 31, 230),
+                                         ((12, 12, 12), 4, 9, 140), ((10, 12, 8), 2, 5, 33)]):
+        q = np.array([0.125, -0.375, 0.375]) * (i + 1) % 1.0 - 0.5
+        g = gen.gsphere_shifted(q, ng)
+        nn = np.array(n)
+        g = g[np.all((g >= -(nn // 2)) & (g <= (nn + 1) // 2 - 1), axis=1)]
+        out.append(gen.make_problem(n, nv, nc, gvec=g, z=zs, seed=seed + 10 * i, pair_chunk=chunk))
+    return out
+
+
+def _run(probs, **kw):
+    dps = [to_dev(p) for p in probs]
+    chis = gw.gw_chi0(dps, **kw)
+    torch.cuda.synchronize()
+    return dps, [c.cpu().numpy() for c in chis]
+
+
+@pytest.mark.parametrize("flags", [0, gw.GW_FLAG_AUTOTUNE])
+def test_batched_matches_oracle(flags):
+    probs = _batch()
+    _, got = _run(probs, pair_chunk=40, flags=flags)
+    for p, g in zip(probs, got):
+        assert rel_fro(g, _oracle(p)) < FP64_TOL
+
+
+def test_graph_capture_and_replay():
+    probs = _batch(seed=3)
+    dps = [to_dev(p) for p in probs]
+    flags = gw.GW_FLAG_GRAPH
+    refs = [_oracle(p) for p in probs]
+    for rep in range(3):
+        chis = gw.gw_chi0(dps, pair_chunk=40, flags=flags)
+        torch.cuda.synchronize()
+        for c, r in zip(chis, refs):
+            assert rel_fro(c.cpu().numpy(), r) < FP64_TOL
+        # eager work between replays, on the same stream
+        junk = torch.randn(1 << 20, device=device()).sum()
+        torch.cuda.synchronize()
+        del junk
+    # new data behind the same pointers: the replay recomputes
+    for p, d in zip(probs, dps):
+        p.e_v = p.e_v - 0.05
+        d.e_v.copy_(torch.from_numpy(p.e_v))
+    chis = gw.gw_chi0(dps, pair_chunk=40, flags=flags)
+    torch.cuda.synchronize()
+    for c, p in zip(chis, probs):
+        assert rel_fro(c.cpu().numpy(), _oracle(p)) < FP64_TOL
+
+
+def test_batched_with_empty_problem():
+    probs = _batch(seed=5)
+    probs[1].psi_c, probs[1].e_c = probs[1].psi_c[:0], probs[1].e_c[:0]
+    dps = [to_dev(p) for p in probs]
+    dps[1].chi = torch.full((3, probs[1].ng, probs[1].ng), 9.0 + 0j, dtype=torch.complex128,
+                            device=device())
+    chis = gw.gw_chi0(dps, pair_chunk=40)
+    torch.cuda.synchronize()
+    assert torch.all(chis[1] == 0)
+    for i in (0, 2, 3):
+        assert rel_fro(chis[i].cpu().numpy(), _oracle(probs[i])) < FP64_TOL
+
+
+def test_batched_workload_q_points_full_size_sampled():
+    """Four q-points of the 4x4x4 batched workload at full size (40^3 grid,
+    48 valence bands, 16 imaginary frequencies): the smallest and largest
+    G-spheres and the largest band window, in one graph-captured call;
+    sampled entries against the oracle's direct sums."""
+    qs, ng, nc = gen.batched_shapes()
+    pick = sorted({int(np.argmin(ng)), int(np.argmax(ng)), int(np.argmax(nc)), 7})
+    probs = gen.make_batched_config(pick)
+    dps = [to_dev(p) for p in probs]
+    chis = gw.gw_chi0(dps, pair_chunk=4096, flags=gw.GW_FLAG_GRAPH)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    for p, c in zip(probs, chis):
+        rows = rng.choice(p.ng, 2, replace=False)
+        cols = np.unique(np.concatenate([[p.ng - 1], rng.choice(p.ng, 2, replace=False)]))
+        wsel = [0, 7, 15]
+        ref = oracle.chi0_entries(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec[rows], p.gvec[cols],
+                                  p.z[wsel], p.n, p.volume, p.spin)
+        got = c[wsel][:, rows][:, :, cols].cpu().numpy()
+        assert rel_fro(got, ref) < FP64_TOL, (p.meta, rel_fro(got, ref))
