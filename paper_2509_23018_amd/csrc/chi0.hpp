@@ -63,7 +63,15 @@ void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        bool accumulate, void* scratch, hipStream_t s);
 void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta, const WList& wl,
                      double2* chi, bool accumulate, hipStream_t s);
-constexpr int kSplitTile = 64;  // tile edge of the split and FP32 kernels
+constexpr int kSplitTile = 64;  // tile edge of the FP16-split and FP32 kernels
+// Split BF16 on the 32x32 MFMA (grouped shifts, 128 x 64 workgroup tiles; the
+// Hermitian rule and mirror use 128-wide square blocks); same scratch layout
+// size as launch_chi0_split.
+void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
+                       const WList& wl, double2* chi, bool accumulate, void* scratch,
+                       hipStream_t s);
+// Tile edge whose on-or-above-diagonal blocks a reduced-precision mode computes.
+inline int split_tile(int prec) { return prec == 2 ? 128 : kSplitTile; }
 
 // Fill the tiles strictly below the diagonal (tile x tile blocks) from the
 // conjugate transpose.

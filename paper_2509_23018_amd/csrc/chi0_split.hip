@@ -403,7 +403,8 @@ void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta,
 size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S) {
     const int64_t nkb = (kmax + kBlk - 1) / kBlk;
     const size_t per = static_cast<size_t>(nkb) * S * 2 * ng * kBlk * 2 + 256;
-    const size_t sig = static_cast<size_t>(nkb) * ng * sizeof(double) + 256;
+    // sigma rows padded to a multiple of 128 (the split-BF16 layout)
+    const size_t sig = static_cast<size_t>(nkb) * ceil_div(ng, 128) * 128 * sizeof(double) + 256;
     return (per + sig) * static_cast<size_t>(1 + nz);
 }
 
@@ -412,6 +413,10 @@ void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        bool accumulate, void* scratch, hipStream_t s) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
+    if (prec == 2) {
+        launch_chi0_sbf16(S, m, kc, ng, delta, nz, wl, chi, accumulate, scratch, s);
+        return;
+    }
     const int nkb = static_cast<int>((kc + kBlk - 1) / kBlk);
     const size_t per = static_cast<size_t>(nkb) * S * 2 * ng * kBlk;  // elements
     const size_t per_b = (per * 2 + 255) & ~static_cast<size_t>(255);

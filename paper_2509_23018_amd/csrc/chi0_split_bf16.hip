@@ -1,0 +1,436 @@
+// Split-BF16 CHI0 contraction on the 32x32x16 BF16 MFMA of gfx950 (not in the
+// paper, which is FP64 only; the energy factor, the slice recombination and
+// chi stay FP64).
+//
+// Slicing.  Per block of 128 pairs and per G, every operand value x (M for the
+// G side, Delta_w M for the G' side, both FP64) gets the exponent e with
+// max(|Re x|, |Im x|) < 2^e over the block, and is cut into S slices
+//     x 2^(8-e) = q_0 + q_1 2^-8 + ... + q_{S-1} 2^(-8(S-1)) (+ residual),
+// rounding to nearest each time (|q_0| <= 256, |q_s| <= 128).  Slice s is
+// stored as the BF16 value q_s 2^(-8s): exact, since q_s has at most 8
+// significant bits.
+//
+// Products.  Slices a (G side) and b (G' side) with a + b <= S - 1 are
+// multiplied on MFMA with FP32 accumulation in three groups: t = a + b = 0,
+// t = 1 and t >= 2.  Over a block of 128 pairs (256 real products per complex
+// entry and shift) every partial sum of the t = 0 group is an integer of
+// magnitude at most 256 * 2^16 = 2^24, and of the t = 1 group an integer
+// multiple of 2^-8 of magnitude at most 512 * 2^7 = 2^16: both exact in FP32.
+// The t >= 2 group is at most 2^-16 of the result, so its FP32 rounding costs
+// about 2^-40 relative.
+// After each block, 2^(eA + eB - 16) (acc_0 + acc_1 + acc_2) is added in FP64.
+//
+// Complex arithmetic uses the real-stacked form: the K axis of one MFMA holds
+// 8 pairs with (Re, Im) interleaved, so conj(A) B = sum A'B' (Re) and
+// sum A' B'' (Im) with B'' = (Im B, -Re B) formed in registers.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <type_traits>
+
+#include "chi0.hpp"
+#include "common.hpp"
+#include "items.hpp"
+#include "prof.hpp"
+
+namespace gw {
+
+namespace {
+
+constexpr int kBlkB = 128;                   // pairs per exponent block
+constexpr int kStep = 8;                     // pairs per MFMA k-step (K = 16)
+constexpr int kStepsPerBlk = kBlkB / kStep;  // 16
+constexpr int kTI = 128, kTJ = 64;           // workgroup tile: rows G, columns G'
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- slicing
+
+// One workgroup per (block of 128 pairs, 32 columns of G).  Output layout, in
+// 32-bit words (Re in the low half, Im in the high half, both BF16):
+//   slices[kb][ks][s][g][p]   p = pair within the k-step (0..7),
+// i.e. per (block, k-step, slice) a [ng][8]-word array: a 128-row panel of a
+// tile is one contiguous 4 KB run.  sigma[kb][g] = 2^(e-8), rows padded to
+// ngp (a multiple of 128) so that a tile's sigma panel is whole.
+__global__ __launch_bounds__(256) void sbf16_prep_kernel(
+    const double2* __restrict__ m, const double2* __restrict__ delta, int64_t kc, int ng, int ngp,
+    int S, int nkb, WList wl, uint32_t* __restrict__ slices_a, double* __restrict__ sigma_a,
+    uint32_t* __restrict__ slices_b, double* __restrict__ sigma_b) {
+    constexpr int C = 32;  // columns per workgroup
+    __shared__ double2 s_m[kBlkB][C + 1];
+    __shared__ double s_part[8][C];
+    __shared__ int s_e[C];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g0 = blockIdx.x * C, kb = blockIdx.y;
+    const int64_t k0 = static_cast<int64_t>(kb) * kBlkB;
+    const int kn = static_cast<int>(std::min<int64_t>(kBlkB, kc - k0));
+    // stage M[k0 .. k0+128)[g0 .. g0+32): half-waves along g (coalesced)
+    for (int r = 2 * wave + (lane >> 5); r < kBlkB; r += 8) {
+        const int g = g0 + (lane & 31);
+        s_m[r][lane & 31] = (r < kn && g < ng) ? m[(k0 + r) * ng + g] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const size_t per_op = static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep;  // words
+    const int nop = 1 + wl.nh + wl.nf;
+    const int mc = tid & (C - 1), mp = tid >> 5;  // maxima: column, part of 16 pairs
+    for (int op = 0; op < nop; ++op) {
+        const double2* dw = op == 0 ? nullptr : delta + static_cast<int64_t>(wl.w[op - 1]) * kc;
+        auto value = [&](int p, int c) {
+            const double2 x = s_m[p][c];
+            return (dw && p < kn) ? cmul(dw[k0 + p], x) : x;
+        };
+        double mx = 0.0;
+        for (int p = mp * 16; p < mp * 16 + 16; ++p) {
+            const double2 x = value(p, mc);
+            mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
+        }
+        s_part[mp][mc] = mx;
+        __syncthreads();
+        if (tid < C) {
+            mx = s_part[0][tid];
+            for (int q = 1; q < 8; ++q) mx = fmax(mx, s_part[q][tid]);
+            int e = 0;
+            if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1): |x| < 2^e
+            s_e[tid] = e;
+            // rows past N_G (up to the padded stride) get 1.0: read, never used
+            const double sg = g0 + tid < ng ? ldexp(1.0, e - 8) : 1.0;
+            if (g0 + tid < ngp) {
+                if (op == 0)
+                    sigma_a[static_cast<size_t>(kb) * ngp + g0 + tid] = sg;
+                else
+                    sigma_b[(static_cast<size_t>(wl.w[op - 1]) * nkb + kb) * ngp + g0 + tid] = sg;
+            }
+        }
+        __syncthreads();
+        uint32_t* out = op == 0 ? slices_a : slices_b + static_cast<size_t>(wl.w[op - 1]) * per_op;
+        // a wave writes 8 consecutive G rows x 8 pairs = 256 contiguous bytes per slice
+        for (int u = wave; u < kStepsPerBlk * (C / 8); u += 4) {
+            const int ks = u / (C / 8), cg = u % (C / 8);
+            const int p = ks * kStep + (lane & 7), c = cg * 8 + (lane >> 3);
+            const int g = g0 + c;
+            if (g >= ng) continue;
+            const int e = s_e[c];
+            double rr = 0.0, ri = 0.0;
+            if (p < kn) {
+                const double2 x = value(p, c);
+                rr = ldexp(x.x, 8 - e);
+                ri = ldexp(x.y, 8 - e);
+            }
+            uint32_t* o = out + ((static_cast<size_t>(kb) * kStepsPerBlk + ks) * S * ng + g) * kStep +
+                          (lane & 7);
+            for (int sl = 0; sl < S; ++sl) {
+                const double qr = rint(rr), qi = rint(ri);
+                // q 2^(-8 sl) has at most 8 significant bits: the top half of its FP32 bits is
+                // its exact BF16 encoding
+                const uint32_t br = __float_as_uint(ldexpf(static_cast<float>(qr), -8 * sl)) >> 16;
+                const uint32_t bi = __float_as_uint(ldexpf(static_cast<float>(qi), -8 * sl)) & 0xffff0000u;
+                o[static_cast<size_t>(sl) * ng * kStep] = bi | br;
+                rr = (rr - qr) * 256.0;
+                ri = (ri - qi) * 256.0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- contraction
+
+// Item b -> frequency w, 128-row block bi, 64-column block bj.  Items come in
+// pairs (both 64-column halves of one 128 x 128 block) so that the square
+// tile order and the Hermitian rule (blocks on or above the diagonal) of the
+// FP64 kernels apply with a 128 tile; the XCD renumbering keeps each XCD on
+// a contiguous run of items.
+__device__ __forceinline__ void decode_item_rect(int b, const WList& wl, int nb,
+                                                 const int* __restrict__ order, int& w, int& bi,
+                                                 int& bj) {
+    const int nh = nb * (nb + 1) / 2, nf = nb * nb;
+    const int nitems = 2 * (wl.nh * nh + wl.nf * nf);
+    const int q = nitems >> 3, r = nitems & 7;
+    const int x = b & 7, i = b >> 3;
+    int t = x * q + (x < r ? x : r) + i;
+    const int half = t & 1;
+    t >>= 1;
+    int code;
+    if (t < wl.nh * nh) {
+        w = wl.w[t / nh];
+        code = order[t % nh];
+    } else {
+        t -= wl.nh * nh;
+        w = wl.w[wl.nh + t / nf];
+        code = order[nh + t % nf];
+    }
+    bi = code >> 16;
+    bj = 2 * (code & 0xffff) + half;
+}
+
+__device__ __forceinline__ f32x16 mfma32(u32x4 a, u32x4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// (Re, Im) -> (Im, -Re) in every 32-bit word of a fragment.
+__device__ __forceinline__ u32x4 swap_neg(u32x4 v) {
+    u32x4 r;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) r[d] = ((v[d] >> 16) | (v[d] << 16)) ^ 0x80000000u;
+    return r;
+}
+
+// LDS position of 16-byte half h of row r within a panel.  A 128-bit read by
+// 32 lanes on consecutive rows is served 8 or 16 lanes at a time; swapping
+// the halves of rows with bit 2 xor bit 3 set puts every such group of lanes
+// on distinct banks (32 or 64 banks of 4 bytes).
+__device__ __forceinline__ int swz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
+__device__ __forceinline__ int lds_slot(int r, int h) { return 2 * r + (h ^ swz(r)); }
+
+// vmcnt(n) alone (expcnt and lgkmcnt left at their no-wait maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Workgroup tile kTI x kTJ of chi_w, NWI x NWJ waves, each BI x BJ blocks of
+// 32 x 32.  Operands are staged per k-step of 8 pairs: both slice panels
+// ((kTI + kTJ) rows x S slices x 32 B) and the sigma of the step's 64-pair
+// block, written straight from global memory into LDS (no registers) in a
+// ring of kStages stages, two steps ahead of the MFMAs.  Every wave issues
+// the same number of 16-byte loads per step (spare lanes fetch a valid
+// address into padding), so "this step has landed" is vmcnt(loads per step)
+// after the next step's loads are in flight.
+template <int S, int NWI, int NWJ, int BI, int BJ>
+__global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
+    const u32x4* __restrict__ sa, const double* __restrict__ siga, const u32x4* __restrict__ sb_all,
+    const double* __restrict__ sigb_all, int ng, int ngp, int nkb, WList wl,
+    double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
+    static_assert(NWI * BI * 32 == kTI && NWJ * BJ * 32 == kTJ, "tile shape");
+    constexpr int NW = NWI * NWJ, NT = NW * 64;
+    constexpr int G = S < 3 ? S : 3;
+    constexpr int CA = kTI * 2 * S, CB = kTJ * 2 * S;  // slice chunks (16 B) per k-step
+    constexpr int CSA = kTI / 2, CSB = kTJ / 2;        // sigma chunks (two doubles each)
+    constexpr int NCH = CA + CB + CSA + CSB;
+    constexpr int NLD = (NCH + NT - 1) / NT;  // loads per thread per step
+    constexpr int NCHP = NLD * NT;            // padded stage, in chunks
+    constexpr int kStages = 3;
+    extern __shared__ u32x4 lds[];  // [kStages][NCHP]
+    int w, bi, bj;
+    decode_item_rect(blockIdx.x, wl, nb, order, w, bi, bj);
+    const int i0 = bi * kTI, j0 = bj * kTJ;
+    if (j0 >= ng) return;  // right half of the last block column lies past N_G
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wi = wave / NWJ, wj = wave % NWJ;
+    const int rl = lane & 31, hl = lane >> 5;
+    const size_t step_stride = static_cast<size_t>(S) * ng * 2;  // slice chunks per k-step
+    const u32x4* sb = sb_all + static_cast<size_t>(w) * nkb * kStepsPerBlk * step_stride;
+    const u32x4* sga = reinterpret_cast<const u32x4*>(siga);
+    const u32x4* sgb = reinterpret_cast<const u32x4*>(sigb_all + static_cast<size_t>(w) * nkb * ngp);
+
+    // Load u of this wave fills stage slots [(u*NW + wave)*64, +64); this lane's
+    // slot c holds: A slices, B slices, A sigma, B sigma, or padding.
+    const u32x4* src0[NLD];
+    int kind[NLD];  // 0: slices (advance per step), 1: sigma (advance per block), 2: padding
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int c = (u * NW + wave) * 64 + lane;
+        if (c < CA) {
+            const int sl = c / (2 * kTI), pp = c % (2 * kTI), rr = pp >> 1;
+            const int h = (pp & 1) ^ swz(rr);  // inverse of lds_slot
+            src0[u] = sa + (sl * ng + min(i0 + rr, ng - 1)) * 2 + h;
+            kind[u] = 0;
+        } else if (c < CA + CB) {
+            const int cb = c - CA;
+            const int sl = cb / (2 * kTJ), pp = cb % (2 * kTJ), rr = pp >> 1;
+            const int h = (pp & 1) ^ swz(rr);
+            src0[u] = sb + (sl * ng + min(j0 + rr, ng - 1)) * 2 + h;
+            kind[u] = 0;
+        } else if (c < CA + CB + CSA) {
+            src0[u] = sga + (i0 >> 1) + (c - CA - CB);
+            kind[u] = 1;
+        } else if (c < NCH) {
+            src0[u] = sgb + (j0 >> 1) + (c - CA - CB - CSA);
+            kind[u] = 1;
+        } else {
+            src0[u] = sa;
+            kind[u] = 2;
+        }
+    }
+    const int nsteps = nkb * kStepsPerBlk;
+    auto issue = [&](int st, int stage) {
+        const size_t so = static_cast<size_t>(st) * step_stride;
+        const size_t bo = static_cast<size_t>(st / kStepsPerBlk) * (ngp >> 1);
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const u32x4* g = src0[u] + (kind[u] == 0 ? so : kind[u] == 1 ? bo : 0);
+            __builtin_amdgcn_global_load_lds(g, &lds[stage * NCHP + (u * NW + wave) * 64], 16, 0, 0);
+        }
+    };
+
+    f32x16 accR[G][BI][BJ], accI[G][BI][BJ];  // set by each block's first step
+    double dr[BI][BJ][16], di[BI][BJ][16];
+#pragma unroll
+    for (int x = 0; x < BI; ++x)
+#pragma unroll
+        for (int y = 0; y < BJ; ++y)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) dr[x][y][t] = di[x][y][t] = 0.0;
+
+    const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                           0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // one k-step; on the block's first step (`first`) every group starts from zero
+    auto step = [&](int st, auto first) {
+        wait_vmcnt<NLD>();  // step st has landed (this wave's loads; the barrier makes it all)
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");  // keep the LDS reads below the barrier
+        // stage (st + 2) % 3 was last read at step st - 1, which every wave has finished
+        issue(min(st + 2, nsteps - 1), (st + 2) % kStages);
+        const u32x4* L = lds + (st % kStages) * NCHP;
+        u32x4 fa[S][BI];
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl)
+#pragma unroll
+            for (int x = 0; x < BI; ++x)
+                fa[sl][x] = L[sl * 2 * kTI + lds_slot(wi * BI * 32 + x * 32 + rl, hl)];
+#pragma unroll
+        for (int b = 0; b < S; ++b)
+#pragma unroll
+            for (int y = 0; y < BJ; ++y) {
+                const u32x4 fb = L[CA + b * 2 * kTJ + lds_slot(wj * BJ * 32 + y * 32 + rl, hl)];
+                const u32x4 fbi = swap_neg(fb);
+#pragma unroll
+                for (int a = 0; a < S - b; ++a) {
+                    const int g = a + b < G - 1 ? a + b : G - 1;
+                    // the first product of each group in the block (b = 0, a = g)
+                    const bool fresh = decltype(first)::value && b == 0 && a == g;
+#pragma unroll
+                    for (int x = 0; x < BI; ++x) {
+                        accR[g][x][y] = mfma32(fa[a][x], fb, fresh ? zero16 : accR[g][x][y]);
+                        accI[g][x][y] = mfma32(fa[a][x], fbi, fresh ? zero16 : accI[g][x][y]);
+                    }
+                }
+            }
+        return L;
+    };
+    issue(0, 0);
+    issue(min(1, nsteps - 1), 1);
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int st0 = kb * kStepsPerBlk;
+        step(st0, std::true_type{});
+        for (int ks = 1; ks < kStepsPerBlk - 1; ++ks) step(st0 + ks, std::false_type{});
+        const u32x4* L = step(st0 + kStepsPerBlk - 1, std::false_type{});
+        // end of the block: fold the FP32 groups into FP64 with this block's sigma
+        const double* sgl = reinterpret_cast<const double*>(L + CA + CB);
+#pragma unroll
+        for (int y = 0; y < BJ; ++y) {
+            const double sbj = sgl[kTI + wj * BJ * 32 + y * 32 + rl];
+#pragma unroll
+            for (int x = 0; x < BI; ++x)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const double sc =
+                        sgl[wi * BI * 32 + x * 32 + 8 * (t >> 2) + 4 * hl + (t & 3)] * sbj;
+                    double vr = static_cast<double>(accR[0][x][y][t]);
+                    double vi = static_cast<double>(accI[0][x][y][t]);
+#pragma unroll
+                    for (int g = 1; g < G; ++g) {
+                        vr += static_cast<double>(accR[g][x][y][t]);
+                        vi += static_cast<double>(accI[g][x][y][t]);
+                    }
+                    dr[x][y][t] = fma(sc, vr, dr[x][y][t]);
+                    di[x][y][t] = fma(sc, vi, di[x][y][t]);
+                }
+        }
+    }
+    wait_vmcnt<0>();  // no load into this workgroup's LDS may outlive it
+    double2* cw = chi + static_cast<int64_t>(w) * ng * ng;
+#pragma unroll
+    for (int x = 0; x < BI; ++x)
+#pragma unroll
+        for (int y = 0; y < BJ; ++y)
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int gi = i0 + wi * BI * 32 + x * 32 + 8 * (t >> 2) + 4 * hl + (t & 3);
+                const int gj = j0 + wj * BJ * 32 + y * 32 + rl;
+                if (gi < ng && gj < ng) {
+                    double2* p = cw + static_cast<int64_t>(gi) * ng + gj;
+                    double2 v = make_double2(dr[x][y][t], di[x][y][t]);
+                    if (mode) {
+                        const double2 o = *p;
+                        v.x += o.x;
+                        v.y += o.y;
+                    }
+                    *p = v;
+                }
+            }
+}
+
+template <int S, int NWI, int NWJ, int BI, int BJ>
+void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
+                    const double* sigb, int ng, int ngp, int nkb, const WList& wl, double2* chi,
+                    bool accumulate, int nb, int64_t nitems, hipStream_t s) {
+    constexpr int NT = NWI * NWJ * 64;
+    constexpr int NCH = (kTI + kTJ) * 2 * S + (kTI + kTJ) / 2;
+    constexpr int NCHP = (NCH + NT - 1) / NT * NT;
+    const size_t lds = 3 * NCHP * sizeof(u32x4);
+    auto fn = chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>;
+    GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(lds)));
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nitems)), dim3(NWI * NWJ * 64), lds, s,
+                       reinterpret_cast<const u32x4*>(sa), siga, reinterpret_cast<const u32x4*>(sb),
+                       sigb, ng, ngp, nkb, wl, chi, accumulate ? 1 : 0, nb, tile_order(nb));
+}
+
+template <int S>
+void launch_sbf16_s(const uint32_t* sa, const double* siga, const uint32_t* sb, const double* sigb,
+                    int ng, int ngp, int nkb, const WList& wl, double2* chi, bool accumulate, int nb,
+                    int64_t nitems, hipStream_t s) {
+    // 8 waves of 32 x 32 (two waves per SIMD, 256 registers each)
+    launch_sbf16_t<S, 4, 2, 1, 1>(sa, siga, sb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems,
+                                  s);
+}
+
+}  // namespace
+
+void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
+                       const WList& wl, double2* chi, bool accumulate, void* scratch,
+                       hipStream_t s) {
+    if (kc <= 0 || wl.nh + wl.nf == 0) return;
+    if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
+    const int nkb = static_cast<int>((kc + kBlkB - 1) / kBlkB);
+    const size_t per_b = (static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep * 4 + 255) &
+                         ~static_cast<size_t>(255);
+    const int ngp = ceil_div(ng, kTI) * kTI;
+    const size_t sig_b =
+        (static_cast<size_t>(nkb) * ngp * sizeof(double) + 255) & ~static_cast<size_t>(255);
+    char* base = static_cast<char*>(scratch);
+    uint32_t* pa = reinterpret_cast<uint32_t*>(base);
+    double* siga = reinterpret_cast<double*>(base + per_b);
+    char* pb = base + per_b + sig_b;
+    double* sigb = reinterpret_cast<double*>(pb + static_cast<size_t>(nz) * per_b);
+    {
+        ProfScope ps("split_prep", s);
+        hipLaunchKernelGGL(sbf16_prep_kernel, dim3(ceil_div(ng, 32), nkb), dim3(256), 0, s, m,
+                           delta, kc, ng, ngp, S, nkb, wl, pa, siga, reinterpret_cast<uint32_t*>(pb),
+                           sigb);
+        GW_HIP_TRY(hipGetLastError());
+    }
+    const int nb = ceil_div(ng, kTI);
+    const int64_t nitems = 2 * (static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
+                                static_cast<int64_t>(wl.nf) * nb * nb);
+    ProfScope ps("chi0_split", s);
+    const uint32_t* cpa = pa;
+    const uint32_t* cpb = reinterpret_cast<const uint32_t*>(pb);
+    switch (S) {
+        case 2: launch_sbf16_s<2>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 3: launch_sbf16_s<3>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 4: launch_sbf16_s<4>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 5: launch_sbf16_s<5>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
+        default: launch_sbf16_s<6>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
+    }
+    GW_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace gw

@@ -398,6 +398,16 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     const size_t off_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
     const bool split = o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16;
     const size_t off_sp = cv.take(split ? split_scratch_bytes(kmax, pr.ng, pr.nz, o.n_slices) : 0);
+    const std::vector<Chunk> chunks = make_chunks(pr, cs);
+    int variant = 0;
+    bool tune = false;
+    if (o.precision == GW_FP64) {
+        variant = lookup_variant(pr.ng, chunks[0].kc);
+        tune = variant < 0 && autotune_enabled(o);
+        if (variant < 0) variant = 0;
+    }
+    // the autotuner's trials write one frequency plane here, never into chi
+    const size_t off_tune = cv.take(tune ? ng * ng * sizeof(double2) : 0);
     char* base = static_cast<char*>(scratch(cv.off, s));
     double2* mbuf[2] = {reinterpret_cast<double2*>(base + off_m[0]),
                         reinterpret_cast<double2*>(base + off_m[1])};
@@ -426,7 +436,6 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
             wlists.push_back(wl);
         }
     }
-    const std::vector<Chunk> chunks = make_chunks(pr, cs);
     // events: ev[0] caller-stream start, ev[1+b] MTXEL into buffer b done,
     // ev[3+b] CHI0 reading buffer b done
     AuxCtx& ax = aux_ctx(s);
@@ -443,18 +452,16 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     GW_HIP_TRY(hipEventRecord(ax.ev[0], s));
     GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[0], 0));
     produce(0);
-    int variant = 0;
-    if (o.precision == GW_FP64) {
-        variant = lookup_variant(pr.ng, chunks[0].kc);
-        if (variant < 0 && autotune_enabled(o)) {
-            // time the tile shapes on the first chunk (its results are overwritten below)
-            GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1], 0));
-            variant = tune_variant(pr.ng, chunks[0].kc, s, [&](int v) {
-                for (const WList& wl : wlists)
-                    launch_chi0_f64(mbuf[0], chunks[0].kc, pr.ng, dbuf[0], wl, chi, accumulate, s, v);
-            });
-        }
-        if (variant < 0) variant = 0;
+    if (tune) {
+        // time the tile shapes on the first chunk and one frequency
+        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1], 0));
+        WList one{};
+        one.w[0] = 0;
+        one.nf = 1;
+        double2* trial_chi = reinterpret_cast<double2*>(base + off_tune);
+        variant = tune_variant(pr.ng, chunks[0].kc, s, [&](int v) {
+            launch_chi0_f64(mbuf[0], chunks[0].kc, pr.ng, dbuf[0], one, trial_chi, false, s, v);
+        });
     }
     for (size_t k = 0; k < chunks.size(); ++k) {
         const int b = static_cast<int>(k & 1);
@@ -475,7 +482,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     for (int w = 0; w < pr.nz; ++w)
         if (herm[w])
             launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, pr.ng,
-                          o.precision == GW_FP64 ? chi0_variant_tile(variant) : kSplitTile, s);
+                          o.precision == GW_FP64 ? chi0_variant_tile(variant) : split_tile(o.precision), s);
 }
 
 

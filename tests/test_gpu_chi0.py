@@ -56,6 +56,23 @@ def test_chi0_flags_no_hermitian_and_accumulate():
     assert rel_fro(acc - (1.0 + 2.0j), ref) < FP64_TOL
 
 
+@pytest.mark.parametrize("chunk", [1000, 40, 25])
+def test_chi0_autotune_and_accumulate(chunk):
+    """The tile autotuner times its trials into scratch: an accumulating call
+    that tunes first must still add exactly chi to what the output held.
+    One chunk (no second contraction stream), two chunks, and three."""
+    p = gen.make_problem((14, 12, 12), 5, 13, r2=14, z=(0.0, 0.4 + 0.02j), seed=8,
+                         pair_chunk=chunk)
+    ref = _oracle_chi(p)
+    dp = to_dev(p)
+    dp.chi = torch.full((2, p.ng, p.ng), -0.5 + 1.0j, dtype=torch.complex128, device=device())
+    gw.gw_chi0(dp, flags=gw.GW_FLAG_ACCUMULATE | gw.GW_FLAG_AUTOTUNE, pair_chunk=chunk)
+    torch.cuda.synchronize()
+    assert rel_fro(dp.chi.cpu().numpy() - (-0.5 + 1.0j), ref) < FP64_TOL
+    got = run_chi0(p, flags=gw.GW_FLAG_AUTOTUNE)
+    assert rel_fro(got, ref) < FP64_TOL
+
+
 def test_chi0_edge_cases():
     # no pairs -> chi = 0
     p = gen.make_problem((8, 8, 8), 2, 3, r2=3, z=(0.0,), seed=1)
