@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <vector>
 
@@ -313,7 +314,7 @@ void launch_fill_zero(double2* p, int64_t n, hipStream_t s) {
 namespace {
 struct OrderCache {
     std::mutex mu;
-    std::map<std::pair<int, int>, int*> tables;  // (device, nb) -> device table
+    std::map<std::tuple<int, int, int>, int*> tables;  // (device, nb, super) -> device table
 };
 OrderCache& order_cache() {
     static OrderCache* c = new OrderCache();
@@ -321,14 +322,13 @@ OrderCache& order_cache() {
 }
 }  // namespace
 
-const int* tile_order(int nb) {
+const int* tile_order(int nb, int kSuper) {
     int dev = 0;
     GW_HIP_TRY(hipGetDevice(&dev));
     OrderCache& oc = order_cache();
     std::lock_guard<std::mutex> lk(oc.mu);
-    int*& t = oc.tables[{dev, nb}];
+    int*& t = oc.tables[{dev, nb, kSuper}];
     if (t) return t;
-    constexpr int kSuper = 8;
     std::vector<int> h, f;
     for (int si = 0; si < nb; si += kSuper)
         for (int sj = 0; sj < nb; sj += kSuper)
@@ -347,7 +347,7 @@ void release_tile_orders() {
     OrderCache& oc = order_cache();
     std::lock_guard<std::mutex> lk(oc.mu);
     for (auto& kv : oc.tables) {
-        (void)hipSetDevice(kv.first.first);
+        (void)hipSetDevice(std::get<0>(kv.first));
         (void)hipDeviceSynchronize();
         (void)hipFree(kv.second);
     }

@@ -142,7 +142,8 @@ __global__ __launch_bounds__(256) void sbf16_prep_kernel(
 // pairs (both 64-column halves of one 128 x 128 block) so that the square
 // tile order and the Hermitian rule (blocks on or above the diagonal) of the
 // FP64 kernels apply with a 128 tile; the XCD renumbering keeps each XCD on
-// a contiguous run of items.
+// a contiguous run of items, and 4 x 4 super-blocks make the 32 workgroups
+// an XCD runs at once share 4 row panels and 8 column panels.
 __device__ __forceinline__ void decode_item_rect(int b, const WList& wl, int nb,
                                                  const int* __restrict__ order, int& w, int& bi,
                                                  int& bj) {
@@ -197,7 +198,7 @@ __device__ __forceinline__ void wait_vmcnt() {
 // 32 x 32.  Operands are staged per k-step of 8 pairs: both slice panels
 // ((kTI + kTJ) rows x S slices x 32 B) and the sigma of the step's 64-pair
 // block, written straight from global memory into LDS (no registers) in a
-// ring of kStages stages, two steps ahead of the MFMAs.  Every wave issues
+// ring of 3 or 4 stages, 2 or 3 steps ahead of the MFMAs.  Every wave issues
 // the same number of 16-byte loads per step (spare lanes fetch a valid
 // address into padding), so "this step has landed" is vmcnt(loads per step)
 // after the next step's loads are in flight.
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     constexpr int NCH = CA + CB + CSA + CSB;
     constexpr int NLD = (NCH + NT - 1) / NT;  // loads per thread per step
     constexpr int NCHP = NLD * NT;            // padded stage, in chunks
-    constexpr int kStages = 3;
+    // ring depth: as deep as 160 KB of LDS allows
+    constexpr int kStages = NCHP * 16 * 4 <= 160 * 1024 ? 4 : 3;
     extern __shared__ u32x4 lds[];  // [kStages][NCHP]
     int w, bi, bj;
     decode_item_rect(blockIdx.x, wl, nb, order, w, bi, bj);
@@ -228,43 +230,57 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     const u32x4* sga = reinterpret_cast<const u32x4*>(siga);
     const u32x4* sgb = reinterpret_cast<const u32x4*>(sigb_all + static_cast<size_t>(w) * nkb * ngp);
 
-    // Load u of this wave fills stage slots [(u*NW + wave)*64, +64); this lane's
-    // slot c holds: A slices, B slices, A sigma, B sigma, or padding.
-    const u32x4* src0[NLD];
-    int kind[NLD];  // 0: slices (advance per step), 1: sigma (advance per block), 2: padding
+    // Load u of this wave fills stage slots [(u*NW + wave)*64, +64).  Panel
+    // sizes are multiples of 64 chunks, so each load reads one kind of data
+    // from one wave-uniform base (advanced per step or per block in scalar
+    // registers) plus a fixed per-lane byte offset: A slices, B slices, A
+    // sigma, B sigma (32 lanes, the other 32 repeat them into padding) or
+    // padding.
+    static_assert(CA % 64 == 0 && CB % 64 == 0 && CSA == 64 && CSB == 32, "panel sizes");
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    uint32_t voff[NLD];
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-        const int c = (u * NW + wave) * 64 + lane;
+        const int c = (u * NW + wv) * 64 + lane;
+        int off;
         if (c < CA) {
             const int sl = c / (2 * kTI), pp = c % (2 * kTI), rr = pp >> 1;
             const int h = (pp & 1) ^ swz(rr);  // inverse of lds_slot
-            src0[u] = sa + (sl * ng + min(i0 + rr, ng - 1)) * 2 + h;
-            kind[u] = 0;
+            off = (sl * ng + min(i0 + rr, ng - 1)) * 2 + h;
         } else if (c < CA + CB) {
             const int cb = c - CA;
             const int sl = cb / (2 * kTJ), pp = cb % (2 * kTJ), rr = pp >> 1;
             const int h = (pp & 1) ^ swz(rr);
-            src0[u] = sb + (sl * ng + min(j0 + rr, ng - 1)) * 2 + h;
-            kind[u] = 0;
-        } else if (c < CA + CB + CSA) {
-            src0[u] = sga + (i0 >> 1) + (c - CA - CB);
-            kind[u] = 1;
-        } else if (c < NCH) {
-            src0[u] = sgb + (j0 >> 1) + (c - CA - CB - CSA);
-            kind[u] = 1;
+            off = (sl * ng + min(j0 + rr, ng - 1)) * 2 + h;
         } else {
-            src0[u] = sa;
-            kind[u] = 2;
+            off = lane & (c < CA + CB + CSA ? 63 : 31);
         }
+        voff[u] = static_cast<uint32_t>(off) * 16u;
     }
     const int nsteps = nkb * kStepsPerBlk;
+    // per load: base at step 0 and which advance applies (all wave-uniform)
+    const char* base0[NLD];
+    uint64_t step_mask[NLD], blk_mask[NLD];
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int c0 = (u * NW + wv) * 64;
+        const bool slices = c0 < CA + CB, sigma = !slices && c0 < NCH;
+        base0[u] = c0 < CA               ? reinterpret_cast<const char*>(sa)
+                   : c0 < CA + CB        ? reinterpret_cast<const char*>(sb)
+                   : c0 < CA + CB + CSA  ? reinterpret_cast<const char*>(sga + (i0 >> 1))
+                   : c0 < NCH            ? reinterpret_cast<const char*>(sgb + (j0 >> 1))
+                                         : reinterpret_cast<const char*>(sa);
+        step_mask[u] = slices ? ~uint64_t(0) : 0;
+        blk_mask[u] = sigma ? ~uint64_t(0) : 0;
+    }
     auto issue = [&](int st, int stage) {
-        const size_t so = static_cast<size_t>(st) * step_stride;
-        const size_t bo = static_cast<size_t>(st / kStepsPerBlk) * (ngp >> 1);
+        const uint64_t so = static_cast<uint64_t>(st) * step_stride * 16;
+        const uint64_t bo = static_cast<uint64_t>(st / kStepsPerBlk) * (ngp >> 1) * 16;
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
-            const u32x4* g = src0[u] + (kind[u] == 0 ? so : kind[u] == 1 ? bo : 0);
-            __builtin_amdgcn_global_load_lds(g, &lds[stage * NCHP + (u * NW + wave) * 64], 16, 0, 0);
+            const char* base = base0[u] + ((so & step_mask[u]) | (bo & blk_mask[u]));
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const u32x4*>(base + voff[u]),
+                                             &lds[stage * NCHP + (u * NW + wv) * 64], 16, 0, 0);
         }
     };
 
@@ -281,11 +297,13 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
                            0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     // one k-step; on the block's first step (`first`) every group starts from zero
     auto step = [&](int st, auto first) {
-        wait_vmcnt<NLD>();  // step st has landed (this wave's loads; the barrier makes it all)
+        // step st has landed once at most the kStages - 2 later steps' loads are
+        // outstanding (this wave's; the barrier extends it to the workgroup)
+        wait_vmcnt<(kStages - 2) * NLD>();
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");  // keep the LDS reads below the barrier
-        // stage (st + 2) % 3 was last read at step st - 1, which every wave has finished
-        issue(min(st + 2, nsteps - 1), (st + 2) % kStages);
+        // stage (st - 1) % kStages was last read at step st - 1, which every wave has finished
+        issue(min(st + kStages - 1, nsteps - 1), (st + kStages - 1) % kStages);
         const u32x4* L = lds + (st % kStages) * NCHP;
         u32x4 fa[S][BI];
 #pragma unroll
@@ -313,8 +331,8 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
             }
         return L;
     };
-    issue(0, 0);
-    issue(min(1, nsteps - 1), 1);
+#pragma unroll
+    for (int q = 0; q < kStages - 1; ++q) issue(min(q, nsteps - 1), q);
     for (int kb = 0; kb < nkb; ++kb) {
         const int st0 = kb * kStepsPerBlk;
         step(st0, std::true_type{});
@@ -373,14 +391,15 @@ void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
     constexpr int NT = NWI * NWJ * 64;
     constexpr int NCH = (kTI + kTJ) * 2 * S + (kTI + kTJ) / 2;
     constexpr int NCHP = (NCH + NT - 1) / NT * NT;
-    const size_t lds = 3 * NCHP * sizeof(u32x4);
+    constexpr int kStages = NCHP * 16 * 4 <= 160 * 1024 ? 4 : 3;
+    const size_t lds = kStages * NCHP * sizeof(u32x4);
     auto fn = chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>;
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nitems)), dim3(NWI * NWJ * 64), lds, s,
                        reinterpret_cast<const u32x4*>(sa), siga, reinterpret_cast<const u32x4*>(sb),
-                       sigb, ng, ngp, nkb, wl, chi, accumulate ? 1 : 0, nb, tile_order(nb));
+                       sigb, ng, ngp, nkb, wl, chi, accumulate ? 1 : 0, nb, tile_order(nb, 4));
 }
 
 template <int S>

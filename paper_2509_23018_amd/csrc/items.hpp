@@ -9,11 +9,11 @@ namespace gw {
 
 // Device table of tile coordinates (bi << 16 | bj) for nb x nb tiles: first
 // the nb(nb+1)/2 tiles on or above the diagonal, then all nb*nb tiles, each
-// list in super-tile order (8x8 blocks of tiles, row-major inside), so that
+// list in super-tile order (super x super blocks of tiles, row-major inside), so that
 // the workgroups one XCD runs at the same time cover a compact block of chi
 // and share the M rows of both its sides in that XCD's L2.  Cached per
 // device; freed by release_tile_orders().
-const int* tile_order(int nb);
+const int* tile_order(int nb, int super = 8);
 void release_tile_orders();
 
 // Frequency and tile of workgroup b.  Items are frequency-major: every
