@@ -154,11 +154,13 @@ gw_status_t gw_mtxel(const gw_grid_t* grid,
  * part, its Delta is real, its chi is Hermitian, and only the tiles on or
  * above the diagonal are contracted; the rest are mirrored (unless
  * GW_FLAG_NO_HERMITIAN or GW_FLAG_ACCUMULATE).  nv*nc == 0 yields chi = 0.
- * With nprob > 1 and FP64, the chunks of all problems are processed in
- * rounds, each round's contraction as one persistent launch over all
- * (problem, frequency, tile) items, largest first; with GW_FLAG_GRAPH the
- * whole call is captured once and replayed (the caller keeps every pointer
- * valid and unchanged between replays; problems must not change size).
+ * With nprob > 1 in FP64 or split BF16, the chunks of all problems are
+ * processed in rounds, each round's contraction as one persistent launch over
+ * all (problem, frequency, tile) items, largest first (split BF16: in groups
+ * of problems whose slice buffers fit GW_SPLIT_BATCH_BYTES, default 8 GiB);
+ * with GW_FLAG_GRAPH the whole call is captured once and replayed (the
+ * caller keeps every pointer valid and unchanged between replays; problems
+ * must not change size).  FP32 and split FP16 run the problems one by one.
  * opts may be NULL (FP64, chunk 4096, s = 2).  Split precision accepts
  * 2..6 slices; returns GW_EUNSUPPORTED beyond that.
  */
@@ -198,7 +200,9 @@ int32_t gw_abi_version(void);
  * Launch timing for measurement harnesses.  While enabled, the library
  * records a HIP event on the caller's stream before and after each of its
  * kernel launches and files the pair under the kernel's name ("mtxel_zy",
- * "mtxel_x", "delta", "chi0_f64", "mirror", "bwd_gm", "bwd_transform").
+ * "mtxel_x", "delta", "chi0_f64", "chi0_f64_batched", "split_prep",
+ * "chi0_split", "chi0_split_batched", "chi0_f32", "mirror", "bwd_gm",
+ * "bwd_transform").
  * gw_profile_read waits for the recorded events of `kernel` and returns the
  * number of launches and the summed duration in milliseconds (0 and 0.0 for
  * an unknown name).  gw_profile_reset forgets every record.  Timing adds two

@@ -70,6 +70,32 @@ constexpr int kSplitTile = 64;  // tile edge of the FP16-split and FP32 kernels
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
                        hipStream_t s);
+// Operands of one problem's chunk for the split-BF16 contraction (device
+// pointers into scratch; frequency w's B slices and sigma follow at fixed
+// strides).
+struct SbDesc {
+    const uint32_t* sa;
+    const double* siga;
+    const uint32_t* sb;
+    const double* sigb;
+    double2* chi;  // [nz][ng][ng]
+    int ng, ngp, nkb, mode;
+};
+// Bytes of that layout for a chunk of kc pairs (split_scratch_bytes covers it).
+size_t sbf16_scratch_bytes(int64_t kc, int ng, int nz, int S);
+// Descriptor of the slices of a chunk of kc pairs laid out in scratch (chi and
+// mode unset); the layout launch_sbf16_prep writes.
+SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch);
+// Slices of one chunk for the frequencies of wl (scratch as for
+// launch_chi0_split); returns the descriptor with chi and mode unset.
+SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const double2* delta,
+                         int nz, const WList& wl, void* scratch, hipStream_t s);
+// Persistent split-BF16 contraction over items (problem, frequency, 128-row
+// block, 64-column block); counter must be 0 on entry.
+void launch_chi0_sbf16_batched(int S, const SbDesc* qd, const int4* items, int nitems,
+                               int* counter, int grid, hipStream_t s);
+constexpr int kSbTileI = 128, kSbTileJ = 64;  // split-BF16 workgroup tile
+
 // Tile edge whose on-or-above-diagonal blocks a reduced-precision mode computes.
 inline int split_tile(int prec) { return prec == 2 ? 128 : kSplitTile; }
 

@@ -401,11 +401,11 @@ void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta,
 }
 
 size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S) {
+    // the FP16 layout (blocks of kBlk pairs) or the split-BF16 one, whichever is larger
     const int64_t nkb = (kmax + kBlk - 1) / kBlk;
     const size_t per = static_cast<size_t>(nkb) * S * 2 * ng * kBlk * 2 + 256;
-    // sigma rows padded to a multiple of 128 (the split-BF16 layout)
-    const size_t sig = static_cast<size_t>(nkb) * ceil_div(ng, 128) * 128 * sizeof(double) + 256;
-    return (per + sig) * static_cast<size_t>(1 + nz);
+    const size_t sig = static_cast<size_t>(nkb) * ng * sizeof(double) + 256;
+    return std::max((per + sig) * static_cast<size_t>(1 + nz), sbf16_scratch_bytes(kmax, ng, nz, S));
 }
 
 void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,

@@ -202,33 +202,44 @@ __device__ __forceinline__ void wait_vmcnt() {
 // the same number of 16-byte loads per step (spare lanes fetch a valid
 // address into padding), so "this step has landed" is vmcnt(loads per step)
 // after the next step's loads are in flight.
-template <int S, int NWI, int NWJ, int BI, int BJ>
-__global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
-    const u32x4* __restrict__ sa, const double* __restrict__ siga, const u32x4* __restrict__ sb_all,
-    const double* __restrict__ sigb_all, int ng, int ngp, int nkb, WList wl,
-    double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
-    static_assert(NWI * BI * 32 == kTI && NWJ * BJ * 32 == kTJ, "tile shape");
-    constexpr int NW = NWI * NWJ, NT = NW * 64;
-    constexpr int G = S < 3 ? S : 3;
-    constexpr int CA = kTI * 2 * S, CB = kTJ * 2 * S;  // slice chunks (16 B) per k-step
-    constexpr int CSA = kTI / 2, CSB = kTJ / 2;        // sigma chunks (two doubles each)
-    constexpr int NCH = CA + CB + CSA + CSB;
-    constexpr int NLD = (NCH + NT - 1) / NT;  // loads per thread per step
-    constexpr int NCHP = NLD * NT;            // padded stage, in chunks
+// Stage geometry of the contraction for S slices and NW waves.
+template <int S, int NW>
+struct SbGeom {
+    static constexpr int NT = NW * 64;
+    static constexpr int CA = kTI * 2 * S, CB = kTJ * 2 * S;  // slice chunks (16 B) per k-step
+    static constexpr int CSA = kTI / 2, CSB = kTJ / 2;        // sigma chunks (two doubles each)
+    static constexpr int NCH = CA + CB + CSA + CSB;
+    static constexpr int NLD = (NCH + NT - 1) / NT;  // loads per thread per step
+    static constexpr int NCHP = NLD * NT;            // padded stage, in chunks
     // ring depth: as deep as 160 KB of LDS allows
-    constexpr int kStages = NCHP * 16 * 4 <= 160 * 1024 ? 4 : 3;
-    extern __shared__ u32x4 lds[];  // [kStages][NCHP]
-    int w, bi, bj;
-    decode_item_rect(blockIdx.x, wl, nb, order, w, bi, bj);
+    static constexpr int kStages = NCHP * 16 * 4 <= 160 * 1024 ? 4 : 3;
+    static constexpr size_t lds_bytes = static_cast<size_t>(kStages) * NCHP * 16;
+};
+
+// One tile (rows bi*kTI.., columns bj*kTJ..) of one frequency plane chi_w:
+// sb and sigb are that frequency's B slices and sigma.  The caller has made
+// sure every wave of the workgroup calls this with the same arguments and
+// that no earlier reader of lds is still running.
+template <int S, int NWI, int NWJ, int BI, int BJ>
+__device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
+                                           const double* __restrict__ siga,
+                                           const u32x4* __restrict__ sb,
+                                           const double* __restrict__ sigb, int ng, int ngp,
+                                           int nkb, double2* __restrict__ cw, int mode, int bi,
+                                           int bj, u32x4* __restrict__ lds) {
+    static_assert(NWI * BI * 32 == kTI && NWJ * BJ * 32 == kTJ, "tile shape");
+    using Geo = SbGeom<S, NWI * NWJ>;
+    constexpr int NW = NWI * NWJ;
+    constexpr int G = S < 3 ? S : 3;
+    constexpr int CA = Geo::CA, CB = Geo::CB, CSA = Geo::CSA, CSB = Geo::CSB, NCH = Geo::NCH;
+    constexpr int NLD = Geo::NLD, NCHP = Geo::NCHP, kStages = Geo::kStages;
     const int i0 = bi * kTI, j0 = bj * kTJ;
-    if (j0 >= ng) return;  // right half of the last block column lies past N_G
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wi = wave / NWJ, wj = wave % NWJ;
     const int rl = lane & 31, hl = lane >> 5;
     const size_t step_stride = static_cast<size_t>(S) * ng * 2;  // slice chunks per k-step
-    const u32x4* sb = sb_all + static_cast<size_t>(w) * nkb * kStepsPerBlk * step_stride;
     const u32x4* sga = reinterpret_cast<const u32x4*>(siga);
-    const u32x4* sgb = reinterpret_cast<const u32x4*>(sigb_all + static_cast<size_t>(w) * nkb * ngp);
+    const u32x4* sgb = reinterpret_cast<const u32x4*>(sigb);
 
     // Load u of this wave fills stage slots [(u*NW + wave)*64, +64).  Panel
     // sizes are multiples of 64 chunks, so each load reads one kind of data
@@ -361,8 +372,7 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
                 }
         }
     }
-    wait_vmcnt<0>();  // no load into this workgroup's LDS may outlive it
-    double2* cw = chi + static_cast<int64_t>(w) * ng * ng;
+    wait_vmcnt<0>();  // no load into this workgroup's LDS may outlive the tile
 #pragma unroll
     for (int x = 0; x < BI; ++x)
 #pragma unroll
@@ -384,15 +394,53 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
             }
 }
 
+// One launch per chunk: workgroup b takes item b (frequency, tile).
+template <int S, int NWI, int NWJ, int BI, int BJ>
+__global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
+    const u32x4* __restrict__ sa, const double* __restrict__ siga, const u32x4* __restrict__ sb_all,
+    const double* __restrict__ sigb_all, int ng, int ngp, int nkb, WList wl,
+    double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
+    extern __shared__ u32x4 lds[];
+    int w, bi, bj;
+    decode_item_rect(blockIdx.x, wl, nb, order, w, bi, bj);
+    if (bj * kTJ >= ng) return;  // right half of the last block column lies past N_G
+    const size_t plane = static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * 2;  // chunks
+    sbf16_tile<S, NWI, NWJ, BI, BJ>(sa, siga, sb_all + w * plane,
+                                    sigb_all + static_cast<size_t>(w) * nkb * ngp, ng, ngp, nkb,
+                                    chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj, lds);
+}
+
+// Persistent: workgroups pull items (problem, frequency, 128-row block,
+// 64-column block) from *counter until none is left.
+template <int S, int NWI, int NWJ, int BI, int BJ>
+__global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
+    const SbDesc* __restrict__ qd, const int4* __restrict__ items, int nitems,
+    int* __restrict__ counter) {
+    extern __shared__ u32x4 lds[];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();  // every wave is done with the previous item's LDS
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= nitems) break;
+        const int4 t = items[it];
+        const SbDesc d = qd[t.x];
+        if (t.w * kTJ >= d.ng) continue;
+        const size_t plane = static_cast<size_t>(d.nkb) * kStepsPerBlk * S * d.ng * 2;
+        sbf16_tile<S, NWI, NWJ, BI, BJ>(
+            reinterpret_cast<const u32x4*>(d.sa), d.siga,
+            reinterpret_cast<const u32x4*>(d.sb) + t.y * plane,
+            d.sigb + static_cast<size_t>(t.y) * d.nkb * d.ngp, d.ng, d.ngp, d.nkb,
+            d.chi + static_cast<int64_t>(t.y) * d.ng * d.ng, d.mode, t.z, t.w, lds);
+    }
+}
+
 template <int S, int NWI, int NWJ, int BI, int BJ>
 void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
                     const double* sigb, int ng, int ngp, int nkb, const WList& wl, double2* chi,
                     bool accumulate, int nb, int64_t nitems, hipStream_t s) {
-    constexpr int NT = NWI * NWJ * 64;
-    constexpr int NCH = (kTI + kTJ) * 2 * S + (kTI + kTJ) / 2;
-    constexpr int NCHP = (NCH + NT - 1) / NT * NT;
-    constexpr int kStages = NCHP * 16 * 4 <= 160 * 1024 ? 4 : 3;
-    const size_t lds = kStages * NCHP * sizeof(u32x4);
+    const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
     auto fn = chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>;
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -413,41 +461,96 @@ void launch_sbf16_s(const uint32_t* sa, const double* siga, const uint32_t* sb, 
 
 }  // namespace
 
+// Bytes of the layout sbf16_desc describes: A slices, A sigma, nz B slices,
+// nz B sigma, each rounded up to 256 B.
+size_t sbf16_scratch_bytes(int64_t kc, int ng, int nz, int S) {
+    const int64_t nkb = (kc + kBlkB - 1) / kBlkB;
+    const int ngp = ceil_div(ng, kTI) * kTI;
+    const size_t per_b = (static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep * 4 + 255) &
+                         ~static_cast<size_t>(255);
+    const size_t sig_b =
+        (static_cast<size_t>(nkb) * ngp * sizeof(double) + 255) & ~static_cast<size_t>(255);
+    return (per_b + sig_b) * static_cast<size_t>(1 + nz);
+}
+
+SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch) {
+    const int nkb = static_cast<int>((kc + kBlkB - 1) / kBlkB);
+    const int ngp = ceil_div(ng, kTI) * kTI;
+    const size_t per_b = (static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep * 4 + 255) &
+                         ~static_cast<size_t>(255);
+    const size_t sig_b =
+        (static_cast<size_t>(nkb) * ngp * sizeof(double) + 255) & ~static_cast<size_t>(255);
+    char* base = static_cast<char*>(scratch);
+    SbDesc d{};
+    d.sa = reinterpret_cast<const uint32_t*>(base);
+    d.siga = reinterpret_cast<const double*>(base + per_b);
+    d.sb = reinterpret_cast<const uint32_t*>(base + per_b + sig_b);
+    d.sigb = reinterpret_cast<const double*>(base + per_b + sig_b + static_cast<size_t>(nz) * per_b);
+    d.ng = ng;
+    d.ngp = ngp;
+    d.nkb = nkb;
+    return d;
+}
+
+SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const double2* delta,
+                         int nz, const WList& wl, void* scratch, hipStream_t s) {
+    const SbDesc d = sbf16_desc(S, kc, ng, nz, scratch);
+    ProfScope ps("split_prep", s);
+    hipLaunchKernelGGL(sbf16_prep_kernel, dim3(ceil_div(ng, 32), d.nkb), dim3(256), 0, s, m, delta,
+                       kc, ng, d.ngp, S, d.nkb, wl, const_cast<uint32_t*>(d.sa),
+                       const_cast<double*>(d.siga), const_cast<uint32_t*>(d.sb),
+                       const_cast<double*>(d.sigb));
+    GW_HIP_TRY(hipGetLastError());
+    return d;
+}
+
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
                        hipStream_t s) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
-    const int nkb = static_cast<int>((kc + kBlkB - 1) / kBlkB);
-    const size_t per_b = (static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep * 4 + 255) &
-                         ~static_cast<size_t>(255);
-    const int ngp = ceil_div(ng, kTI) * kTI;
-    const size_t sig_b =
-        (static_cast<size_t>(nkb) * ngp * sizeof(double) + 255) & ~static_cast<size_t>(255);
-    char* base = static_cast<char*>(scratch);
-    uint32_t* pa = reinterpret_cast<uint32_t*>(base);
-    double* siga = reinterpret_cast<double*>(base + per_b);
-    char* pb = base + per_b + sig_b;
-    double* sigb = reinterpret_cast<double*>(pb + static_cast<size_t>(nz) * per_b);
-    {
-        ProfScope ps("split_prep", s);
-        hipLaunchKernelGGL(sbf16_prep_kernel, dim3(ceil_div(ng, 32), nkb), dim3(256), 0, s, m,
-                           delta, kc, ng, ngp, S, nkb, wl, pa, siga, reinterpret_cast<uint32_t*>(pb),
-                           sigb);
-        GW_HIP_TRY(hipGetLastError());
-    }
+    const SbDesc d = launch_sbf16_prep(S, m, kc, ng, delta, nz, wl, scratch, s);
     const int nb = ceil_div(ng, kTI);
     const int64_t nitems = 2 * (static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
                                 static_cast<int64_t>(wl.nf) * nb * nb);
     ProfScope ps("chi0_split", s);
-    const uint32_t* cpa = pa;
-    const uint32_t* cpb = reinterpret_cast<const uint32_t*>(pb);
     switch (S) {
-        case 2: launch_sbf16_s<2>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
-        case 3: launch_sbf16_s<3>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
-        case 4: launch_sbf16_s<4>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
-        case 5: launch_sbf16_s<5>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
-        default: launch_sbf16_s<6>(cpa, siga, cpb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 2: launch_sbf16_s<2>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 3: launch_sbf16_s<3>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 4: launch_sbf16_s<4>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
+        case 5: launch_sbf16_s<5>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
+        default: launch_sbf16_s<6>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
+    }
+    GW_HIP_TRY(hipGetLastError());
+}
+
+namespace {
+template <int S>
+void launch_sbf16_batched_s(const SbDesc* qd, const int4* items, int nitems, int* counter, int grid,
+                            hipStream_t s) {
+    constexpr int NWI = 4, NWJ = 2;
+    const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
+    auto fn = chi0_sbf16_batched_kernel<S, NWI, NWJ, 1, 1>;
+    GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(lds)));
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(grid)), dim3(NWI * NWJ * 64), lds, s, qd,
+                       items, nitems, counter);
+}
+}  // namespace
+
+void launch_chi0_sbf16_batched(int S, const SbDesc* qd, const int4* items, int nitems,
+                               int* counter, int grid, hipStream_t s) {
+    if (nitems <= 0) return;
+    if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
+    grid = std::max(1, std::min(grid, nitems));
+    ProfScope ps("chi0_split_batched", s);
+    switch (S) {
+        case 2: launch_sbf16_batched_s<2>(qd, items, nitems, counter, grid, s); break;
+        case 3: launch_sbf16_batched_s<3>(qd, items, nitems, counter, grid, s); break;
+        case 4: launch_sbf16_batched_s<4>(qd, items, nitems, counter, grid, s); break;
+        case 5: launch_sbf16_batched_s<5>(qd, items, nitems, counter, grid, s); break;
+        default: launch_sbf16_batched_s<6>(qd, items, nitems, counter, grid, s); break;
     }
     GW_HIP_TRY(hipGetLastError());
 }

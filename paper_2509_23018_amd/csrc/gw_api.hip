@@ -83,6 +83,10 @@ void release_scratch() {
 
 // A library-owned companion stream of each caller stream (default priority),
 // with events used to fork work onto it and join it back.
+// Events of a companion context: ev[kEvStart] forks from the caller's stream,
+// ev[kEvMade + b] marks buffer b written, ev[kEvUsed + b] buffer b read.
+constexpr int kEvStart = 0, kEvMade = 1, kEvUsed = 3;
+
 struct AuxCtx {
     hipStream_t aux = nullptr;
     hipEvent_t ev[6] = {};
@@ -375,6 +379,27 @@ int tune_variant(int ng, int64_t kc, hipStream_t s, const std::function<void(int
     return best;
 }
 
+// Frequencies grouped into launches of at most kMaxZ, Hermitian ones first.
+std::vector<WList> freq_lists(const std::vector<bool>& herm) {
+    const int nz = static_cast<int>(herm.size());
+    std::vector<int> order;
+    for (int w = 0; w < nz; ++w)
+        if (herm[w]) order.push_back(w);
+    const int nherm = static_cast<int>(order.size());
+    for (int w = 0; w < nz; ++w)
+        if (!herm[w]) order.push_back(w);
+    std::vector<WList> out;
+    for (int i0 = 0; i0 < nz; i0 += kMaxZ) {
+        WList wl{};
+        for (int i = i0; i < std::min(nz, i0 + kMaxZ); ++i) {
+            wl.w[i - i0] = order[i];
+            if (i < nherm) ++wl.nh; else ++wl.nf;
+        }
+        out.push_back(wl);
+    }
+    return out;
+}
+
 void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     const MtxelPlan& plan = *get_plan(pr.grid.n, pr.gvec, pr.ng);
     const int64_t ng = pr.ng;
@@ -419,23 +444,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     for (int w = 0; w < pr.nz; ++w)
         herm[w] = pr.z[w].re == 0.0 && !(o.flags & GW_FLAG_NO_HERMITIAN) && !accumulate;
     // launches cover at most kMaxZ frequencies each (Hermitian ones first)
-    std::vector<WList> wlists;
-    {
-        std::vector<int> order;
-        for (int w = 0; w < pr.nz; ++w)
-            if (herm[w]) order.push_back(w);
-        const int nherm = static_cast<int>(order.size());
-        for (int w = 0; w < pr.nz; ++w)
-            if (!herm[w]) order.push_back(w);
-        for (int i0 = 0; i0 < pr.nz; i0 += kMaxZ) {
-            WList wl{};
-            for (int i = i0; i < std::min(pr.nz, i0 + kMaxZ); ++i) {
-                wl.w[i - i0] = order[i];
-                if (i < nherm) ++wl.nh; else ++wl.nf;
-            }
-            wlists.push_back(wl);
-        }
-    }
+    const std::vector<WList> wlists = freq_lists(herm);
     // events: ev[0] caller-stream start, ev[1+b] MTXEL into buffer b done,
     // ev[3+b] CHI0 reading buffer b done
     AuxCtx& ax = aux_ctx(s);
@@ -496,10 +505,17 @@ struct BatchQ {
     std::vector<bool> herm;
     int64_t kmax = 0;
     size_t off_m[2] = {0, 0}, off_d[2] = {0, 0};
+    size_t off_sp = 0;  // split-BF16 slices of the current round
 };
 
+// A batch advances every problem by one chunk per round; each round's
+// contraction is one persistent launch over all (problem, frequency, tile)
+// items.  FP64 uses QDesc items on square tiles; split BF16 uses SbDesc
+// items on 128 x 64 tiles (Hermitian rule on 128 x 128 blocks).
 struct BatchPlan {
     std::vector<BatchQ> q;
+    bool split = false;
+    int S = 0;
     int rounds = 0;
     int variant = 0;
     int grid = 0;
@@ -508,31 +524,44 @@ struct BatchPlan {
     std::vector<size_t> item_off;  // per round, in int4 units
 };
 
-int persistent_grid(int variant) {
+int resident_cus() {
     int dev = 0, cus = 0;
     GW_HIP_TRY(hipGetDevice(&dev));
     GW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    return cus * (chi0_variant_tile(variant) == 64 ? 2 : 1);  // workgroups resident per CU (LDS)
+    return cus;
+}
+
+int persistent_grid(const BatchPlan& bp) {
+    if (bp.split) return resident_cus();  // one workgroup per CU (LDS ring)
+    return resident_cus() * (chi0_variant_tile(bp.variant) == 64 ? 2 : 1);
 }
 
 // Items of round r: (problem, frequency, tile row, tile col), all problems,
 // largest chunk first; tiles of one problem and frequency in super-tile order.
 std::vector<int4> round_items(const BatchPlan& bp, int r, const gw_problem_t* probs) {
-    const int tile = chi0_variant_tile(bp.variant);
+    const int tile = bp.split ? kSbTileI : chi0_variant_tile(bp.variant);
+    const int kSuper = bp.split ? 4 : 8;
     std::vector<std::pair<int64_t, int4>> v;
     for (size_t q = 0; q < bp.q.size(); ++q) {
         const BatchQ& b = bp.q[q];
         if (r >= static_cast<int>(b.chunks.size())) continue;
-        const int nb = ceil_div(probs[q].ng, tile);
+        const int ng = probs[q].ng;
+        const int nb = ceil_div(ng, tile);
         for (int w = 0; w < probs[q].nz; ++w) {
-            constexpr int kSuper = 8;
             for (int si = 0; si < nb; si += kSuper)
                 for (int sj = 0; sj < nb; sj += kSuper)
                     for (int i = si; i < std::min(nb, si + kSuper); ++i)
-                        for (int j = sj; j < std::min(nb, sj + kSuper); ++j)
-                            if (!b.herm[w] || j >= i)
-                                v.push_back({b.chunks[r].kc,
-                                             make_int4(static_cast<int>(q), w, i, j)});
+                        for (int j = sj; j < std::min(nb, sj + kSuper); ++j) {
+                            if (b.herm[w] && j < i) continue;
+                            if (!bp.split) {
+                                v.push_back({b.chunks[r].kc, make_int4(static_cast<int>(q), w, i, j)});
+                                continue;
+                            }
+                            for (int h = 0; h < 2; ++h)  // the two 64-column halves
+                                if ((2 * j + h) * kSbTileJ < ng)
+                                    v.push_back({b.chunks[r].kc,
+                                                 make_int4(static_cast<int>(q), w, i, 2 * j + h)});
+                        }
         }
     }
     std::stable_sort(v.begin(), v.end(),
@@ -544,8 +573,10 @@ std::vector<int4> round_items(const BatchPlan& bp, int r, const gw_problem_t* pr
 
 BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int variant) {
     BatchPlan bp;
+    bp.split = o.precision == GW_SPLIT_BF16;
+    bp.S = o.n_slices;
     bp.variant = variant;
-    bp.grid = persistent_grid(variant);
+    bp.grid = persistent_grid(bp);
     bp.q.resize(nprob);
     Carver cv;
     size_t t2max = 0;
@@ -563,11 +594,14 @@ BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int v
             b.off_m[k] = cv.take(b.kmax * pr.ng * sizeof(double2));
             b.off_d[k] = cv.take(b.kmax * pr.nz * sizeof(double2));
         }
+        if (bp.split && b.kmax > 0)
+            b.off_sp = cv.take(split_scratch_bytes(b.kmax, pr.ng, pr.nz, bp.S));
         t2max = std::max(t2max, t2_elems(*b.plan, b.kmax) * sizeof(double2));
         bp.rounds = std::max(bp.rounds, static_cast<int>(b.chunks.size()));
     }
     bp.off_t2 = cv.take(t2max);
-    bp.off_desc = cv.take(static_cast<size_t>(bp.rounds) * nprob * sizeof(QDesc));
+    const size_t desc_size = bp.split ? sizeof(SbDesc) : sizeof(QDesc);
+    bp.off_desc = cv.take(static_cast<size_t>(bp.rounds) * nprob * desc_size);
     size_t ntot = 0;
     for (int r = 0; r < bp.rounds; ++r) {
         bp.item_off.push_back(ntot);
@@ -583,24 +617,40 @@ BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int v
 // Descriptor and item tables into the device buffer (synchronous copies).
 void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base) {
     const int nprob = static_cast<int>(bp.q.size());
-    std::vector<QDesc> desc(static_cast<size_t>(bp.rounds) * nprob);
+    std::vector<QDesc> desc;
+    std::vector<SbDesc> sdesc;
     std::vector<int4> items;
     for (int r = 0; r < bp.rounds; ++r) {
         for (int q = 0; q < nprob; ++q) {
             const BatchQ& b = bp.q[q];
-            QDesc& d = desc[static_cast<size_t>(r) * nprob + q];
-            d.m = reinterpret_cast<const double2*>(base + b.off_m[r & 1]);
-            d.delta = reinterpret_cast<const double2*>(base + b.off_d[r & 1]);
-            d.chi = reinterpret_cast<double2*>(probs[q].chi);
-            d.kc = r < static_cast<int>(b.chunks.size()) ? b.chunks[r].kc : 0;
-            d.ng = probs[q].ng;
-            d.mode = (r > 0 || (o.flags & GW_FLAG_ACCUMULATE)) ? 1 : 0;
+            const int64_t kc = r < static_cast<int>(b.chunks.size()) ? b.chunks[r].kc : 0;
+            const int mode = (r > 0 || (o.flags & GW_FLAG_ACCUMULATE)) ? 1 : 0;
+            if (bp.split) {
+                SbDesc d = sbf16_desc(bp.S, std::max<int64_t>(kc, 1), probs[q].ng, probs[q].nz,
+                                      base + b.off_sp);
+                d.chi = reinterpret_cast<double2*>(probs[q].chi);
+                d.mode = mode;
+                sdesc.push_back(d);
+            } else {
+                QDesc d;
+                d.m = reinterpret_cast<const double2*>(base + b.off_m[r & 1]);
+                d.delta = reinterpret_cast<const double2*>(base + b.off_d[r & 1]);
+                d.chi = reinterpret_cast<double2*>(probs[q].chi);
+                d.kc = kc;
+                d.ng = probs[q].ng;
+                d.mode = mode;
+                desc.push_back(d);
+            }
         }
         const std::vector<int4> it = round_items(bp, r, probs);
         items.insert(items.end(), it.begin(), it.end());
     }
-    GW_HIP_TRY(hipMemcpy(base + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc),
-                         hipMemcpyHostToDevice));
+    if (bp.split)
+        GW_HIP_TRY(hipMemcpy(base + bp.off_desc, sdesc.data(), sdesc.size() * sizeof(SbDesc),
+                             hipMemcpyHostToDevice));
+    else
+        GW_HIP_TRY(hipMemcpy(base + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc),
+                             hipMemcpyHostToDevice));
     if (!items.empty())
         GW_HIP_TRY(hipMemcpy(base + bp.off_items, items.data(), items.size() * sizeof(int4),
                              hipMemcpyHostToDevice));
@@ -620,7 +670,7 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
     AuxCtx& ax = aux_ctx(s);
     auto produce = [&](int r) {  // MTXEL + Delta of round r, every problem, companion stream
         const int b = r & 1;
-        if (r >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[3 + b], 0));
+        if (r >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[kEvUsed + b], 0));
         for (int q = 0; q < nprob; ++q) {
             const BatchQ& bq = bp.q[q];
             if (r >= static_cast<int>(bq.chunks.size())) continue;
@@ -633,22 +683,41 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
             launch_delta(pr.e_v, pr.e_c, c.pm, c.kc, reinterpret_cast<const double2*>(pr.z), pr.nz,
                          o.spin, reinterpret_cast<double2*>(base + bq.off_d[b]), ax.aux);
         }
-        GW_HIP_TRY(hipEventRecord(ax.ev[1 + b], ax.aux));
+        GW_HIP_TRY(hipEventRecord(ax.ev[kEvMade + b], ax.aux));
     };
-    GW_HIP_TRY(hipEventRecord(ax.ev[0], s));
-    GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[0], 0));
+    GW_HIP_TRY(hipEventRecord(ax.ev[kEvStart], s));
+    GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[kEvStart], 0));
     produce(0);
     for (int r = 0; r < bp.rounds; ++r) {
         const int b = r & 1;
         if (r + 1 < bp.rounds) produce(r + 1);
-        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1 + b], 0));
-        launch_chi0_f64_batched(
-            reinterpret_cast<const QDesc*>(base + bp.off_desc) + static_cast<size_t>(r) * nprob,
-            reinterpret_cast<const int4*>(base + bp.off_items) + bp.item_off[r], bp.nitems[r],
-            reinterpret_cast<int*>(base + bp.off_cnt) + r, s, bp.variant, bp.grid);
-        GW_HIP_TRY(hipEventRecord(ax.ev[3 + b], s));
+        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[kEvMade + b], 0));
+        const int4* items = reinterpret_cast<const int4*>(base + bp.off_items) + bp.item_off[r];
+        int* counter = reinterpret_cast<int*>(base + bp.off_cnt) + r;
+        if (bp.split) {
+            // slices of every problem's chunk (the previous round's launch, on this
+            // stream, has finished reading them), then one persistent contraction
+            for (int q = 0; q < nprob; ++q) {
+                const BatchQ& bq = bp.q[q];
+                if (r >= static_cast<int>(bq.chunks.size())) continue;
+                const gw_problem_t& pr = probs[q];
+                for (const WList& wl : freq_lists(bq.herm))
+                    (void)launch_sbf16_prep(bp.S, reinterpret_cast<const double2*>(base + bq.off_m[b]),
+                                            bq.chunks[r].kc, pr.ng,
+                                            reinterpret_cast<const double2*>(base + bq.off_d[b]),
+                                            pr.nz, wl, base + bq.off_sp, s);
+            }
+            launch_chi0_sbf16_batched(
+                bp.S, reinterpret_cast<const SbDesc*>(base + bp.off_desc) + static_cast<size_t>(r) * nprob,
+                items, bp.nitems[r], counter, bp.grid, s);
+        } else {
+            launch_chi0_f64_batched(
+                reinterpret_cast<const QDesc*>(base + bp.off_desc) + static_cast<size_t>(r) * nprob,
+                items, bp.nitems[r], counter, s, bp.variant, bp.grid);
+        }
+        GW_HIP_TRY(hipEventRecord(ax.ev[kEvUsed + b], s));
     }
-    const int tile = chi0_variant_tile(bp.variant);
+    const int tile = bp.split ? kSbTileI : chi0_variant_tile(bp.variant);
     for (int q = 0; q < nprob; ++q)
         for (int w = 0; w < probs[q].nz; ++w)
             if (bp.q[q].herm[w] && !bp.q[q].chunks.empty())
@@ -660,6 +729,7 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
 // Tile variant of a batch: forced, cached, or tuned on its largest problem's
 // first chunk (one frequency, into a scratch chi so no output is touched).
 int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+    if (o.precision != GW_FP64) return 0;
     int qmax = -1;
     for (int q = 0; q < nprob; ++q)
         if (static_cast<int64_t>(probs[q].nv) * probs[q].nc > 0 &&
@@ -695,12 +765,12 @@ int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream
     });
 }
 
-// Captured batches: the graph and the device buffer it was captured with.
+// Captured batches: the graph and the device buffers it was captured with.
 struct GraphEntry {
     std::string key;
     int device = 0;
     hipGraphExec_t exec = nullptr;
-    void* buffer = nullptr;
+    std::vector<void*> buffers;
 };
 
 struct GraphCache {
@@ -737,18 +807,53 @@ void release_graphs() {
         (void)hipSetDevice(e.device);
         (void)hipDeviceSynchronize();
         (void)hipGraphExecDestroy(e.exec);
-        (void)hipFree(e.buffer);
+        for (void* b : e.buffers) (void)hipFree(b);
     }
     gc.entries.clear();
 }
 
+// Problems of one batch call in groups processed one after another: FP64 in a
+// single group; split BF16 in groups whose slice buffers (one chunk of every
+// problem, all frequencies) fit GW_SPLIT_BATCH_BYTES (default 8 GiB).
+std::vector<std::vector<gw_problem_t>> batch_groups(const gw_problem_t* probs, int nprob,
+                                                    const Opts& o) {
+    std::vector<std::vector<gw_problem_t>> groups(1);
+    if (o.precision != GW_SPLIT_BF16) {
+        groups[0].assign(probs, probs + nprob);
+        return groups;
+    }
+    const char* env = std::getenv("GW_SPLIT_BATCH_BYTES");
+    const long long v = env ? std::atoll(env) : 0;
+    const size_t budget = v > 0 ? static_cast<size_t>(v) : (size_t(8) << 30);
+    size_t used = 0;
+    for (int q = 0; q < nprob; ++q) {
+        const gw_problem_t& pr = probs[q];
+        size_t need = 0;
+        if (static_cast<int64_t>(pr.nv) * pr.nc > 0) {
+            const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
+            need = split_scratch_bytes(static_cast<int64_t>(cs.vb) * cs.cw, pr.ng, pr.nz, o.n_slices);
+        }
+        if (!groups.back().empty() && used + need > budget) {
+            groups.emplace_back();
+            used = 0;
+        }
+        groups.back().push_back(pr);
+        used += need;
+    }
+    return groups;
+}
+
 void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+    const std::vector<std::vector<gw_problem_t>> groups = batch_groups(probs, nprob, o);
     if (!(o.flags & GW_FLAG_GRAPH)) {
-        const BatchPlan bp = build_batch(probs, nprob, o, batch_variant(probs, nprob, o, s));
-        char* base = static_cast<char*>(scratch(bp.bytes, s));
-        GW_HIP_TRY(hipStreamSynchronize(s));  // the tables below may still be read by earlier work
-        upload_batch(bp, probs, o, base);
-        enqueue_batch(bp, probs, o, base, s);
+        for (const auto& g : groups) {
+            const int n = static_cast<int>(g.size());
+            const BatchPlan bp = build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s));
+            char* base = static_cast<char*>(scratch(bp.bytes, s));
+            GW_HIP_TRY(hipStreamSynchronize(s));  // the tables below may still be read by earlier work
+            upload_batch(bp, g.data(), o, base);
+            enqueue_batch(bp, g.data(), o, base, s);
+        }
         return;
     }
     const std::string key = batch_key(probs, nprob, o);
@@ -762,23 +867,38 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
             }
     }
     // first call: everything that allocates or copies happens before capture
-    const BatchPlan bp = build_batch(probs, nprob, o, batch_variant(probs, nprob, o, s));
-    for (int q = 0; q < nprob; ++q) (void)tile_order(ceil_div(probs[q].ng, chi0_variant_tile(bp.variant)));
+    std::vector<BatchPlan> plans;
+    for (const auto& g : groups) {
+        const int n = static_cast<int>(g.size());
+        plans.push_back(build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s)));
+        for (const gw_problem_t& pr : g) {
+            const int tile = plans.back().split ? kSbTileI : chi0_variant_tile(plans.back().variant);
+            (void)tile_order(ceil_div(pr.ng, tile), plans.back().split ? 4 : 8);
+        }
+    }
     const hipStream_t cs = capture_stream(s);
     (void)aux_ctx(cs);
     GraphEntry e;
     e.key = key;
     GW_HIP_TRY(hipGetDevice(&e.device));
-    if (hipMalloc(&e.buffer, std::max<size_t>(bp.bytes, 256)) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(GW_ENOMEM, "hipMalloc of the batch buffer failed");
-    }
+    auto free_buffers = [&] {
+        for (void* b : e.buffers) (void)hipFree(b);
+    };
     try {
-        upload_batch(bp, probs, o, static_cast<char*>(e.buffer));
+        for (size_t i = 0; i < groups.size(); ++i) {
+            void* buf = nullptr;
+            if (hipMalloc(&buf, std::max<size_t>(plans[i].bytes, 256)) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(GW_ENOMEM, "hipMalloc of the batch buffer failed");
+            }
+            e.buffers.push_back(buf);
+            upload_batch(plans[i], groups[i].data(), o, static_cast<char*>(buf));
+        }
         hipGraph_t g = nullptr;
         GW_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         try {
-            enqueue_batch(bp, probs, o, static_cast<char*>(e.buffer), cs);
+            for (size_t i = 0; i < groups.size(); ++i)
+                enqueue_batch(plans[i], groups[i].data(), o, static_cast<char*>(e.buffers[i]), cs);
         } catch (...) {
             (void)hipStreamEndCapture(cs, &g);
             if (g) (void)hipGraphDestroy(g);
@@ -790,7 +910,7 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
         (void)hipGraphDestroy(g);
         GW_HIP_TRY(ie);
     } catch (...) {
-        (void)hipFree(e.buffer);
+        free_buffers();
         throw;
     }
     {
@@ -865,7 +985,7 @@ gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* o
             // plan construction may still reject the sizes; do it for all first
             (void)get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
         }
-        if (nprob > 1 && o.precision == GW_FP64)
+        if (nprob > 1 && (o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16))
             run_chi0_batched(probs, nprob, o, s);
         else
             for (int q = 0; q < nprob; ++q) run_chi0(probs[q], o, s);

@@ -1,6 +1,8 @@
 """Batched problems (several q-points of uneven size) in one call: the
 persistent contraction, graph capture and replay, and the tile autotuner,
 each against the FP64 oracle."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -104,3 +106,51 @@ def test_batched_workload_q_points_full_size_sampled():
                                   p.z[wsel], p.n, p.volume, p.spin)
         got = c[wsel][:, rows][:, :, cols].cpu().numpy()
         assert rel_fro(got, ref) < FP64_TOL, (p.meta, rel_fro(got, ref))
+
+
+def _run_each(probs, **kw):
+    out = []
+    for p in probs:
+        d = to_dev(p)
+        out.append(gw.gw_chi0(d, **kw).cpu().numpy())
+    return out
+
+
+@pytest.mark.parametrize("budget", [None, "1"])
+def test_batched_split_bf16(budget):
+    """Split BF16 (5 slices) over uneven problems in one persistent launch per
+    round: identical to the per-problem launches (same tiles, same order of
+    operations) and within 1e-10 of the FP64 oracle.  A 1-byte slice budget
+    puts every problem in a group of its own."""
+    probs = _batch(seed=7)
+    kw = dict(precision="split_bf16", n_slices=5, pair_chunk=40)
+    if budget:
+        os.environ["GW_SPLIT_BATCH_BYTES"] = budget
+    try:
+        _, got = _run(probs, **kw)
+    finally:
+        os.environ.pop("GW_SPLIT_BATCH_BYTES", None)
+    ref_each = _run_each(probs, **kw)
+    for p, g, e in zip(probs, got, ref_each):
+        o = _oracle(p)
+        assert np.array_equal(g, e), (p.ng, rel_fro(g, e), rel_fro(g, o), rel_fro(e, o))
+        assert rel_fro(g, o) < 1e-10
+
+
+def test_batched_split_bf16_graph_replay():
+    probs = _batch(seed=9)
+    dps = [to_dev(p) for p in probs]
+    kw = dict(precision="split_bf16", n_slices=4, pair_chunk=40, flags=gw.GW_FLAG_GRAPH)
+    first = None
+    for rep in range(3):
+        chis = [c.cpu().numpy() for c in gw.gw_chi0(dps, **kw)]
+        torch.cuda.synchronize()
+        if first is None:
+            first = chis
+            for p, c in zip(probs, chis):
+                assert rel_fro(c, _oracle(p)) < 1e-8
+        else:
+            for a, b in zip(first, chis):
+                assert np.array_equal(a, b)
+        torch.randn(1 << 20, device=device()).sum()
+        torch.cuda.synchronize()
