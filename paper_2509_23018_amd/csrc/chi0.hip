@@ -287,6 +287,15 @@ void launch_chi0_f64_batched(const QDesc* qd, const int4* items, int nitems, int
 
 int chi0_variant_tile(int variant) { return chi0_variant_by_id(variant).tile; }
 
+int chi0_f64_batched_blocks_per_cu(int variant) {
+    const Chi0Variant& v = chi0_variant_by_id(variant);
+    GW_HIP_TRY(hipFuncSetAttribute(v.fn_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(v.lds)));
+    int n = 0;
+    GW_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, v.fn_batch, v.threads, v.lds));
+    return std::max(1, n);
+}
+
 int chi0_forced_variant() {
     static const int id = [] {
         const char* e = std::getenv("GW_CHI0_VARIANT");

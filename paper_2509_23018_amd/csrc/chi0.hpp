@@ -36,6 +36,7 @@ struct WList {
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
                      const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant);
 int chi0_variant_tile(int variant);
+int chi0_f64_batched_blocks_per_cu(int variant);  // resident workgroups of the persistent kernel
 int chi0_forced_variant();  // GW_CHI0_VARIANT, or -1
 constexpr int kNumChi0Variants = 2;
 

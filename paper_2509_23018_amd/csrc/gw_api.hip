@@ -533,7 +533,7 @@ int resident_cus() {
 
 int persistent_grid(const BatchPlan& bp) {
     if (bp.split) return resident_cus();  // one workgroup per CU (LDS ring)
-    return resident_cus() * (chi0_variant_tile(bp.variant) == 64 ? 2 : 1);
+    return resident_cus() * chi0_f64_batched_blocks_per_cu(bp.variant);
 }
 
 // Items of round r: (problem, frequency, tile row, tile col), all problems,
