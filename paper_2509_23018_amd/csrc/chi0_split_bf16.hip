@@ -210,10 +210,16 @@ struct SbGeom {
     static constexpr int CSA = kTI / 2, CSB = kTJ / 2;        // sigma chunks (two doubles each)
     static constexpr int NCH = CA + CB + CSA + CSB;
     static constexpr int NLD = (NCH + NT - 1) / NT;  // loads per thread per step
-    static constexpr int NCHP = NLD * NT;            // padded stage, in chunks
-    // ring depth: as deep as 160 KB of LDS allows
-    static constexpr int kStages = NCHP * 16 * 4 <= 160 * 1024 ? 4 : 3;
-    static constexpr size_t lds_bytes = static_cast<size_t>(kStages) * NCHP * 16;
+    static constexpr int NCHP = NLD * NT;            // padded k-step slot, in chunks
+    // A ring stage holds KSUB k-steps (one barrier per stage); kStages stages.
+    // Preference: two k-steps per stage, then depth; all within 159 KB of LDS.
+    static constexpr size_t kSlot = static_cast<size_t>(NCHP) * 16;
+    static constexpr size_t kMax = 159 * 1024;
+    static constexpr int KSUB = 6 * kSlot <= kMax || 4 * kSlot <= kMax ? 2 : 1;
+    static constexpr int kStages = KSUB == 2 ? (6 * kSlot <= kMax ? 3 : 2) : (4 * kSlot <= kMax ? 4 : 3);
+    static constexpr int NSLOT = KSUB * kStages;
+    static constexpr size_t lds_bytes = NSLOT * kSlot;
+    static_assert(lds_bytes <= kMax, "LDS ring");
 };
 
 // One tile (rows bi*kTI.., columns bj*kTJ..) of one frequency plane chi_w:
@@ -233,6 +239,8 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
     constexpr int G = S < 3 ? S : 3;
     constexpr int CA = Geo::CA, CB = Geo::CB, CSA = Geo::CSA, CSB = Geo::CSB, NCH = Geo::NCH;
     constexpr int NLD = Geo::NLD, NCHP = Geo::NCHP, kStages = Geo::kStages;
+    constexpr int KSUB = Geo::KSUB, NSLOT = Geo::NSLOT;
+    static_assert(kStepsPerBlk % KSUB == 0, "stages within a block");
     const int i0 = bi * kTI, j0 = bj * kTJ;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wi = wave / NWJ, wj = wave % NWJ;
@@ -306,17 +314,26 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
 
     const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                            0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    // one k-step; on the block's first step (`first`) every group starts from zero
-    auto step = [&](int st, auto first) {
-        // step st has landed once at most the kStages - 2 later steps' loads are
-        // outstanding (this wave's; the barrier extends it to the workgroup)
-        wait_vmcnt<(kStages - 2) * NLD>();
+    // Every KSUB k-steps: wait until this stage has landed (at most the
+    // kStages - 2 later stages' loads of this wave still outstanding; the
+    // barrier extends it to the workgroup), then refill the stage that the
+    // previous KSUB k-steps read, which every wave has finished.
+    auto sync = [&](int st) {
+        wait_vmcnt<(kStages - 2) * KSUB * NLD>();
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");  // keep the LDS reads below the barrier
-        // stage (st - 1) % kStages was last read at step st - 1, which every wave has finished
-        issue(min(st + kStages - 1, nsteps - 1), (st + kStages - 1) % kStages);
-        const u32x4* L = lds + (st % kStages) * NCHP;
-        u32x4 fa[S][BI];
+#pragma unroll
+        for (int i = 0; i < KSUB; ++i) {
+            const int nx = st + (kStages - 1) * KSUB + i;
+            issue(min(nx, nsteps - 1), nx % NSLOT);
+        }
+    };
+    // one k-step; on the block's first step (`first`) every group starts from zero
+    auto step = [&](int st, auto first) {
+        const u32x4* L = lds + (st % NSLOT) * NCHP;
+        // every fragment of the k-step is read up front: the waits for them
+        // then overlap the MFMA stream instead of stalling it once per slice
+        u32x4 fa[S][BI], fbs[S][BJ];
 #pragma unroll
         for (int sl = 0; sl < S; ++sl)
 #pragma unroll
@@ -325,8 +342,14 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
 #pragma unroll
         for (int b = 0; b < S; ++b)
 #pragma unroll
+            for (int y = 0; y < BJ; ++y)
+                fbs[b][y] = L[CA + b * 2 * kTJ + lds_slot(wj * BJ * 32 + y * 32 + rl, hl)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < S; ++b)
+#pragma unroll
             for (int y = 0; y < BJ; ++y) {
-                const u32x4 fb = L[CA + b * 2 * kTJ + lds_slot(wj * BJ * 32 + y * 32 + rl, hl)];
+                const u32x4 fb = fbs[b][y];
                 const u32x4 fbi = swap_neg(fb);
 #pragma unroll
                 for (int a = 0; a < S - b; ++a) {
@@ -343,11 +366,21 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
         return L;
     };
 #pragma unroll
-    for (int q = 0; q < kStages - 1; ++q) issue(min(q, nsteps - 1), q);
+    for (int q = 0; q < (kStages - 1) * KSUB; ++q) issue(min(q, nsteps - 1), q);
     for (int kb = 0; kb < nkb; ++kb) {
         const int st0 = kb * kStepsPerBlk;
+        sync(st0);
         step(st0, std::true_type{});
-        for (int ks = 1; ks < kStepsPerBlk - 1; ++ks) step(st0 + ks, std::false_type{});
+#pragma unroll
+        for (int i = 1; i < KSUB; ++i) step(st0 + i, std::false_type{});
+        for (int ks = KSUB; ks < kStepsPerBlk - KSUB; ks += KSUB) {
+            sync(st0 + ks);
+#pragma unroll
+            for (int i = 0; i < KSUB; ++i) step(st0 + ks + i, std::false_type{});
+        }
+        sync(st0 + kStepsPerBlk - KSUB);
+#pragma unroll
+        for (int i = 0; i < KSUB - 1; ++i) step(st0 + kStepsPerBlk - KSUB + i, std::false_type{});
         const u32x4* L = step(st0 + kStepsPerBlk - 1, std::false_type{});
         // end of the block: fold the FP32 groups into FP64 with this block's sigma
         const double* sgl = reinterpret_cast<const double*>(L + CA + CB);
