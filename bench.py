@@ -82,6 +82,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--split-slices", type=int, nargs="*", default=[3, 4, 5],
                     help="slice counts of the split-BF16 runs (empty: none)")
+    ap.add_argument("--workload", default="chi0_48cube",
+                    choices=["chi0_48cube", "batched_40cube_64q", "precision_72cube"],
+                    help="chi0_48cube: the contract line (default); the others print a "
+                         "measurement line of their own")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the chi0 build here runs on a single MI355X "
@@ -89,6 +93,12 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "batched_40cube_64q":
+        bench_batched(args)
+        return
+    if args.workload == "precision_72cube":
+        bench_precision(args)
         return
 
     import numpy as np
@@ -222,6 +232,149 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, dp, dev)
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_batched(args):
+    """64 q-points (4x4x4 shifted grid) on a 40^3 grid, 48 valence bands and
+    300-900 conduction bands each, G-spheres of 400-4,000 vectors, 16
+    imaginary frequencies: one graph-captured gw_chi0 call over all problems,
+    FP64 and split BF16.  Band sets are drawn on the GPU (timing only; parity
+    of this workload is tested on four q-points at full size)."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    dev = torch.device("cuda", 0)
+    qs, ngs, ncs = gen.batched_shapes()
+    z = gen.frequencies("imag", 16)
+    n, nv = (40, 40, 40), 48
+    nr = int(np.prod(n))
+    volume = gen.CELL_L ** 3
+    t_gen = time.perf_counter()
+    probs, flops, pairs = [], 0.0, 0
+    for qi in range(qs.shape[0]):
+        nc, ng = int(ncs[qi]), int(ngs[qi])
+        rng = np.random.default_rng(4000 + qi)
+        e_v, e_c = gen.band_energies(rng, nv, nc)
+        psi = gen.device_bands(nv + nc, nr, seed=4000 + qi, volume=volume, device=dev)
+        probs.append(gw.Chi0Problem(n=n, volume=volume, psi_v=psi[:nv], psi_c=psi[nv:],
+                                    e_v=torch.from_numpy(e_v).to(dev),
+                                    e_c=torch.from_numpy(e_c).to(dev),
+                                    gvec=gen.gsphere_shifted(qs[qi], ng), z=z))
+        flops += 8.0 * ng * ng * nv * nc * len(z)
+        pairs += nv * nc
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # hand cached blocks back: the library allocates outside torch
+    free, total = torch.cuda.mem_get_info()
+    print(f"[bench] device memory free {free / 2**30:.1f} of {total / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
+    print(f"[bench] 64 problems generated in {time.perf_counter() - t_gen:.1f} s "
+          f"({pairs} pairs, {flops:.3e} canonical flops per call)", file=sys.stderr, flush=True)
+    out = {"workload": "batched_40cube_64q", "problems": len(probs), "pairs": pairs,
+           "n_freq": len(z), "canonical_flops": flops, "data": "synthetic (device Gaussian bands)",
+           "runs": []}
+    ref = None
+    keep = [int(np.argmin(ngs)), int(np.argmax(ngs)), int(np.argmax(ncs))]
+    for prec, ns in [("fp64", 0)] + [("split_bf16", k) for k in args.split_slices]:
+        def call():
+            gw.gw_chi0(probs, precision=prec, n_slices=ns, flags=gw.GW_FLAG_GRAPH)
+        t_cap = time.perf_counter()
+        call()  # builds plans, captures the graph, runs once
+        torch.cuda.synchronize()
+        t_cap = time.perf_counter() - t_cap
+        gw.profile_reset()
+        gw.profile_enable(True)
+        dt = _timed(call, max(1, args.steps))
+        gw.profile_enable(False)
+        gw.profile_reset()
+        run = {"precision": prec, "n_slices": ns or None, "s_per_call": round(dt, 4),
+               "first_call_s": round(t_cap, 3), "tflops": round(flops / dt / 1e12, 3),
+               "pairs_per_s": round(pairs / dt, 1)}
+        if prec == "fp64":
+            ref = [probs[q].chi.clone() for q in keep]
+        else:
+            num = sum(float(torch.linalg.vector_norm(probs[q].chi - r) ** 2) for q, r in zip(keep, ref))
+            den = sum(float(torch.linalg.vector_norm(r) ** 2) for r in ref)
+            run["rel_err_vs_fp64"] = (num / den) ** 0.5
+            run["speedup_vs_fp64"] = round(out["runs"][0]["s_per_call"] / dt, 3)
+        out["runs"].append(run)
+        free, total = torch.cuda.mem_get_info()
+        print(f"[bench] batched {prec} S={ns}: {dt:.3f} s per call; device memory free "
+              f"{free / 2**30:.1f} of {total / 2**30:.1f} GiB, torch reserved "
+              f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    out["err_sample_q"] = keep
+    gw.release()
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """chi0 on a 72^3 grid, 256 x 3,840 bands (983,040 pairs), 6,031 G, 8
+    imaginary frequencies, in FP64, FP32 and split BF16; errors against the
+    FP64 result on the 32 G rows drawn with seed 1002.  Band sets are drawn
+    on the GPU (timing only)."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    dev = torch.device("cuda", 0)
+    sh = gen.CONFIG_SHAPES[2]
+    n, nv, nc = sh["n"], sh["nv"], sh["nc"]
+    nr = int(np.prod(n))
+    volume = gen.CELL_L ** 3
+    z = gen.frequencies(*sh["freq"])
+    gvec = gen.gsphere(sh["r2"])
+    rng = np.random.default_rng(2)
+    e_v, e_c = gen.band_energies(rng, nv, nc)
+    psi = gen.device_bands(nv + nc, nr, seed=2, volume=volume, device=dev)
+    torch.cuda.empty_cache()
+    ng = gvec.shape[0]
+    rows = np.sort(np.random.default_rng(1002).choice(ng, 32, replace=False))
+    flops = 8.0 * ng * ng * nv * nc * len(z)
+    prob = gw.Chi0Problem(n=n, volume=volume, psi_v=psi[:nv], psi_c=psi[nv:],
+                          e_v=torch.from_numpy(e_v).to(dev), e_c=torch.from_numpy(e_c).to(dev),
+                          gvec=gvec, z=z)
+    # plans and tables of this grid and G list, built outside the timed calls
+    warm = gw.Chi0Problem(n=n, volume=volume, psi_v=psi[:1], psi_c=psi[nv:nv + 64],
+                          e_v=prob.e_v[:1], e_c=prob.e_c[:64], gvec=gvec, z=z)
+    out = {"workload": "precision_72cube", "pairs": nv * nc, "n_g": ng, "n_freq": len(z),
+           "canonical_flops": flops, "data": "synthetic (device Gaussian bands)",
+           "err_rows": "32 rows, numpy default_rng(1002)", "runs": []}
+    ref = None
+    modes = [("fp64", 0), ("fp32", 0)] + [("split_bf16", k) for k in args.split_slices]
+    for prec, ns in modes:
+        gw.gw_chi0(warm, precision=prec, n_slices=ns)
+        torch.cuda.synchronize()
+        dt = _timed(lambda: gw.gw_chi0(prob, precision=prec, n_slices=ns), 1)
+        sub = prob.chi[:, torch.from_numpy(rows).to(dev)].clone()
+        run = {"precision": prec, "n_slices": ns or None, "s_per_call": round(dt, 3),
+               "tflops": round(flops / dt / 1e12, 3), "pairs_per_s": round(nv * nc / dt, 1)}
+        if prec == "fp64":
+            ref = sub
+        else:
+            run["rel_err_vs_fp64"] = float(torch.linalg.vector_norm(sub - ref) /
+                                           torch.linalg.vector_norm(ref))
+            run["rel_err_per_freq"] = [float(torch.linalg.vector_norm(sub[w] - ref[w]) /
+                                             torch.linalg.vector_norm(ref[w]))
+                                       for w in range(len(z))]
+            run["speedup_vs_fp64"] = round(out["runs"][0]["s_per_call"] / dt, 3)
+        out["runs"].append(run)
+        print(f"[bench] precision {prec} S={ns}: {dt:.2f} s", file=sys.stderr, flush=True)
+    gw.release()
     print(json.dumps(out), flush=True)
 
 

@@ -64,7 +64,10 @@ void* scratch(size_t bytes, hipStream_t s) {
     if (hipMalloc(&sc.ptr, want) != hipSuccess) {
         (void)hipGetLastError();
         sc.ptr = nullptr;
-        fail(GW_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes of scratch failed");
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        fail(GW_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes of scratch failed (" +
+                            std::to_string(fr) + " of " + std::to_string(tot) + " bytes free)");
     }
     sc.bytes = want;
     return sc.ptr;
@@ -519,7 +522,10 @@ struct BatchPlan {
     int rounds = 0;
     int variant = 0;
     int grid = 0;
-    size_t off_t2 = 0, off_desc = 0, off_items = 0, off_cnt = 0, bytes = 0;
+    // work region (M, Delta, t2, slices: reusable by the next group) and
+    // tables region (descriptors, items, counters: one per group)
+    size_t off_t2 = 0, work_bytes = 0;
+    size_t off_desc = 0, off_items = 0, off_cnt = 0, table_bytes = 0;
     std::vector<int> nitems;       // per round
     std::vector<size_t> item_off;  // per round, in int4 units
 };
@@ -578,7 +584,7 @@ BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int v
     bp.variant = variant;
     bp.grid = persistent_grid(bp);
     bp.q.resize(nprob);
-    Carver cv;
+    Carver cv, ct;
     size_t t2max = 0;
     for (int q = 0; q < nprob; ++q) {
         BatchQ& b = bp.q[q];
@@ -600,22 +606,25 @@ BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int v
         bp.rounds = std::max(bp.rounds, static_cast<int>(b.chunks.size()));
     }
     bp.off_t2 = cv.take(t2max);
+    bp.work_bytes = cv.off;
     const size_t desc_size = bp.split ? sizeof(SbDesc) : sizeof(QDesc);
-    bp.off_desc = cv.take(static_cast<size_t>(bp.rounds) * nprob * desc_size);
+    bp.off_desc = ct.take(static_cast<size_t>(bp.rounds) * nprob * desc_size);
     size_t ntot = 0;
     for (int r = 0; r < bp.rounds; ++r) {
         bp.item_off.push_back(ntot);
         bp.nitems.push_back(static_cast<int>(round_items(bp, r, probs).size()));
         ntot += bp.nitems.back();
     }
-    bp.off_items = cv.take(std::max<size_t>(1, ntot) * sizeof(int4));
-    bp.off_cnt = cv.take(std::max(1, bp.rounds) * sizeof(double2));
-    bp.bytes = cv.off;
+    bp.off_items = ct.take(std::max<size_t>(1, ntot) * sizeof(int4));
+    bp.off_cnt = ct.take(std::max(1, bp.rounds) * sizeof(double2));
+    bp.table_bytes = ct.off;
     return bp;
 }
 
-// Descriptor and item tables into the device buffer (synchronous copies).
-void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base) {
+// Descriptor and item tables into the tables buffer (synchronous copies);
+// descriptors point into the work buffer.
+void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base,
+                  char* tab) {
     const int nprob = static_cast<int>(bp.q.size());
     std::vector<QDesc> desc;
     std::vector<SbDesc> sdesc;
@@ -646,18 +655,18 @@ void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o,
         items.insert(items.end(), it.begin(), it.end());
     }
     if (bp.split)
-        GW_HIP_TRY(hipMemcpy(base + bp.off_desc, sdesc.data(), sdesc.size() * sizeof(SbDesc),
+        GW_HIP_TRY(hipMemcpy(tab + bp.off_desc, sdesc.data(), sdesc.size() * sizeof(SbDesc),
                              hipMemcpyHostToDevice));
     else
-        GW_HIP_TRY(hipMemcpy(base + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc),
+        GW_HIP_TRY(hipMemcpy(tab + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc),
                              hipMemcpyHostToDevice));
     if (!items.empty())
-        GW_HIP_TRY(hipMemcpy(base + bp.off_items, items.data(), items.size() * sizeof(int4),
+        GW_HIP_TRY(hipMemcpy(tab + bp.off_items, items.data(), items.size() * sizeof(int4),
                              hipMemcpyHostToDevice));
 }
 
 void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base,
-                   hipStream_t s) {
+                   char* tab, hipStream_t s) {
     const int nprob = static_cast<int>(bp.q.size());
     double2* t2 = reinterpret_cast<double2*>(base + bp.off_t2);
     // problems without pairs: chi = 0
@@ -666,7 +675,7 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
             launch_fill_zero(reinterpret_cast<double2*>(probs[q].chi),
                              static_cast<int64_t>(probs[q].ng) * probs[q].ng * probs[q].nz, s);
     if (bp.rounds == 0) return;
-    launch_fill_zero(reinterpret_cast<double2*>(base + bp.off_cnt), bp.rounds, s);
+    launch_fill_zero(reinterpret_cast<double2*>(tab + bp.off_cnt), bp.rounds, s);
     AuxCtx& ax = aux_ctx(s);
     auto produce = [&](int r) {  // MTXEL + Delta of round r, every problem, companion stream
         const int b = r & 1;
@@ -692,8 +701,8 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
         const int b = r & 1;
         if (r + 1 < bp.rounds) produce(r + 1);
         GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[kEvMade + b], 0));
-        const int4* items = reinterpret_cast<const int4*>(base + bp.off_items) + bp.item_off[r];
-        int* counter = reinterpret_cast<int*>(base + bp.off_cnt) + r;
+        const int4* items = reinterpret_cast<const int4*>(tab + bp.off_items) + bp.item_off[r];
+        int* counter = reinterpret_cast<int*>(tab + bp.off_cnt) + r;
         if (bp.split) {
             // slices of every problem's chunk (the previous round's launch, on this
             // stream, has finished reading them), then one persistent contraction
@@ -708,11 +717,11 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
                                             pr.nz, wl, base + bq.off_sp, s);
             }
             launch_chi0_sbf16_batched(
-                bp.S, reinterpret_cast<const SbDesc*>(base + bp.off_desc) + static_cast<size_t>(r) * nprob,
+                bp.S, reinterpret_cast<const SbDesc*>(tab + bp.off_desc) + static_cast<size_t>(r) * nprob,
                 items, bp.nitems[r], counter, bp.grid, s);
         } else {
             launch_chi0_f64_batched(
-                reinterpret_cast<const QDesc*>(base + bp.off_desc) + static_cast<size_t>(r) * nprob,
+                reinterpret_cast<const QDesc*>(tab + bp.off_desc) + static_cast<size_t>(r) * nprob,
                 items, bp.nitems[r], counter, s, bp.variant, bp.grid);
         }
         GW_HIP_TRY(hipEventRecord(ax.ev[kEvUsed + b], s));
@@ -849,10 +858,11 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
         for (const auto& g : groups) {
             const int n = static_cast<int>(g.size());
             const BatchPlan bp = build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s));
-            char* base = static_cast<char*>(scratch(bp.bytes, s));
+            const size_t tab_off = (bp.work_bytes + 255) & ~static_cast<size_t>(255);
+            char* base = static_cast<char*>(scratch(tab_off + bp.table_bytes, s));
             GW_HIP_TRY(hipStreamSynchronize(s));  // the tables below may still be read by earlier work
-            upload_batch(bp, g.data(), o, base);
-            enqueue_batch(bp, g.data(), o, base, s);
+            upload_batch(bp, g.data(), o, base, base + tab_off);
+            enqueue_batch(bp, g.data(), o, base, base + tab_off, s);
         }
         return;
     }
@@ -884,21 +894,33 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
     auto free_buffers = [&] {
         for (void* b : e.buffers) (void)hipFree(b);
     };
-    try {
-        for (size_t i = 0; i < groups.size(); ++i) {
-            void* buf = nullptr;
-            if (hipMalloc(&buf, std::max<size_t>(plans[i].bytes, 256)) != hipSuccess) {
-                (void)hipGetLastError();
-                fail(GW_ENOMEM, "hipMalloc of the batch buffer failed");
-            }
-            e.buffers.push_back(buf);
-            upload_batch(plans[i], groups[i].data(), o, static_cast<char*>(buf));
+    // groups run one after another: one work buffer serves them all (buffers[0]);
+    // each group keeps its own tables (buffers[1 + i])
+    auto alloc = [&](size_t bytes) {
+        void* buf = nullptr;
+        if (hipMalloc(&buf, std::max<size_t>(bytes, 256)) != hipSuccess) {
+            (void)hipGetLastError();
+            size_t fr = 0, tot = 0;
+            (void)hipMemGetInfo(&fr, &tot);
+            fail(GW_ENOMEM, "hipMalloc of " + std::to_string(bytes) +
+                                " bytes for a captured batch failed (" + std::to_string(fr) +
+                                " of " + std::to_string(tot) + " bytes free)");
         }
+        e.buffers.push_back(buf);
+        return static_cast<char*>(buf);
+    };
+    try {
+        size_t work = 0;
+        for (const BatchPlan& bp : plans) work = std::max(work, bp.work_bytes);
+        char* wbuf = alloc(work);
+        for (size_t i = 0; i < groups.size(); ++i)
+            upload_batch(plans[i], groups[i].data(), o, wbuf, alloc(plans[i].table_bytes));
         hipGraph_t g = nullptr;
         GW_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         try {
             for (size_t i = 0; i < groups.size(); ++i)
-                enqueue_batch(plans[i], groups[i].data(), o, static_cast<char*>(e.buffers[i]), cs);
+                enqueue_batch(plans[i], groups[i].data(), o, wbuf,
+                              static_cast<char*>(e.buffers[1 + i]), cs);
         } catch (...) {
             (void)hipStreamEndCapture(cs, &g);
             if (g) (void)hipGraphDestroy(g);

@@ -193,3 +193,16 @@ def make_batched_config(q_indices=None, *, nv: int = 48, n=(40, 40, 40), nfreq: 
         p.meta.update(config=4, q_index=int(qi), q=qs[qi].tolist())
         probs.append(p)
     return probs
+
+
+def device_bands(nb: int, nr: int, *, seed: int, volume: float = CELL_L ** 3, device="cuda"):
+    """Timing-only band sets generated on the GPU: ``nb`` rows of iid complex
+    Gaussians scaled to unit norm on the grid on average (dV sum |psi|^2 ~ 1),
+    not orthonormalised.  For throughput runs whose inputs are too large to
+    generate on the host; the work done does not depend on the values."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    # complex normal: real and imaginary parts of variance 1/2 each
+    psi = torch.randn((nb, nr), generator=g, device=device, dtype=torch.complex128)
+    return psi.mul_((1.0 / volume) ** 0.5)
