@@ -134,3 +134,21 @@ def test_chi0_workload1_full_size_sampled():
     # chi(z)^H = chi(conj z) cannot be checked within one call; check the
     # structure that holds at any size: the G = 0 row vanishes at q = 0
     assert np.abs(chi[:, 0, :]).max() < 1e-12 * np.abs(chi).max()
+
+
+@pytest.mark.parametrize("prec,ns,tol", [("fp64", 0, FP64_TOL), ("split_bf16", 5, 1e-10)])
+def test_chi0_precision_workload_grid_and_sphere(prec, ns, tol):
+    """The 72^3 grid and its complete G-sphere (6,031 vectors) with the 8
+    imaginary frequencies of the precision study, on 2 x 40 bands: the 32
+    rows drawn with seed 1002 (all columns, all frequencies) against the
+    oracle's Eq. (4) on those rows."""
+    s = gen.CONFIG_SHAPES[2]
+    z = gen.frequencies(*s["freq"])
+    p = gen.make_problem(s["n"], 2, 40, r2=s["r2"], z=z, seed=2, pair_chunk=48)
+    assert p.ng == 6031 and len(p.z) == 8
+    rows = np.sort(np.random.default_rng(1002).choice(p.ng, 32, replace=False))
+    ref = _oracle_chi(p)[:, rows]
+    dp = to_dev(p)
+    chi = gw.gw_chi0(dp, precision=prec, n_slices=ns, pair_chunk=48)
+    got = chi[:, torch.from_numpy(rows).to(device())].cpu().numpy()
+    assert rel_fro(got, ref) < tol, rel_fro(got, ref)
