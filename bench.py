@@ -171,7 +171,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "chi0 at q=0, 48^3 grid, 64x960 bands (61,440 pairs, chunks of 3,840), "
+            "workload": "chi0 at q=0, 48^3 grid, 64x960 bands (61,440 pairs, chunks of 4x960), "
                         "2,007 G, 4 real frequencies (eta 0.005 Ha), FP64",
             "grid": list(p.n), "pairs": npairs, "n_g": ng, "n_freq": nz,
             "pair_chunk": chunk, "precision": "fp64",

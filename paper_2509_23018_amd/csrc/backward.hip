@@ -345,8 +345,9 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
         nr, static_cast<int64_t>(n1) * n2 * plan.m3) * static_cast<int64_t>(sizeof(double2));
     const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
     const int chunk = static_cast<int>(std::min<int64_t>(pair_chunk, cap));
-    const int cwmax = std::min(p.nc, chunk);
-    const int vb = std::max(1, std::min(p.nv, chunk / std::max(1, cwmax)));
+    // 4 valence bands per MTXEL tile: conduction width capped at chunk / 4
+    const int cwmax = std::max(1, std::min(p.nc, chunk / std::max(1, std::min(p.nv, 4))));
+    const int vb = std::max(1, std::min(p.nv, chunk / cwmax));
     const int64_t kmax = static_cast<int64_t>(vb) * cwmax;
     const int nparts = 2 * ceil_div(ng, 64);
 

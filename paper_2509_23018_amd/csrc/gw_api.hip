@@ -233,6 +233,9 @@ void check_problem(const gw_problem_t& p, int idx) {
 }
 
 // Chunks of pairs are rectangles of bands: vb valence x cw conduction bands.
+// The MTXEL tiles take 4 valence bands at a time, so the conduction width is
+// capped at pair_chunk / 4 (when there are 4 valence bands), then the valence
+// height fills the chunk.
 struct ChunkShape {
     int cw, vb;
     int ncv, ncc;  // number of chunks along v and c
@@ -240,8 +243,8 @@ struct ChunkShape {
 
 ChunkShape chunk_shape(int nv, int nc, int pair_chunk) {
     ChunkShape cs;
-    cs.cw = std::min(nc, pair_chunk);
-    cs.vb = std::max(1, std::min(nv, pair_chunk / std::max(1, cs.cw)));
+    cs.cw = std::max(1, std::min(nc, pair_chunk / std::max(1, std::min(nv, 4))));
+    cs.vb = std::max(1, std::min(nv, pair_chunk / cs.cw));
     cs.ncv = ceil_div(nv, cs.vb);
     cs.ncc = ceil_div(nc, cs.cw);
     return cs;

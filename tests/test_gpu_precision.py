@@ -50,7 +50,7 @@ def _blocks(x, kb):
 def _chunk_ranges(nv, nc, chunk):
     """The library streams pairs in rectangles of vb valence x cw conduction
     bands; each is a consecutive range of p = v*nc + c."""
-    cw = min(nc, chunk)
+    cw = max(1, min(nc, chunk // max(1, min(nv, 4))))
     vb = max(1, min(nv, chunk // cw))
     out = []
     for v0 in range(0, nv, vb):
