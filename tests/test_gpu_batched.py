@@ -154,3 +154,28 @@ def test_batched_split_bf16_graph_replay():
                 assert np.array_equal(a, b)
         torch.randn(1 << 20, device=device()).sum()
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec,ns,flags,tol", [
+    ("fp64", 0, 0, FP64_TOL),
+    ("fp64", 0, gw.GW_FLAG_GRAPH, FP64_TOL),
+    ("split_bf16", 5, 0, 1e-10),
+    ("split_bf16", 5, gw.GW_FLAG_GRAPH, 1e-10),
+])
+def test_batched_accumulate(prec, ns, flags, tol):
+    """GW_FLAG_ACCUMULATE over a batch adds chi to what each output held
+    (every tile contracted: no Hermitian shortcut when accumulating); under
+    graph capture the replay accumulates again."""
+    probs = _batch(seed=11)
+    dps = [to_dev(p) for p in probs]
+    init = [np.full((len(p.z), p.ng, p.ng), 0.25 - 0.5j) for p in probs]
+    for d, i in zip(dps, init):
+        d.chi = torch.from_numpy(i).to(device())
+    kw = dict(precision=prec, n_slices=ns, pair_chunk=40, flags=flags | gw.GW_FLAG_ACCUMULATE)
+    reps = 2 if flags & gw.GW_FLAG_GRAPH else 1
+    for _ in range(reps):
+        gw.gw_chi0(dps, **kw)
+    torch.cuda.synchronize()
+    for p, d, i in zip(probs, dps, init):
+        got = d.chi.cpu().numpy() - i
+        assert rel_fro(got, reps * _oracle(p)) < tol
