@@ -49,90 +49,92 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- slicing
 
-// One workgroup per (block of 128 pairs, 32 columns of G).  Output layout, in
-// 32-bit words (Re in the low half, Im in the high half, both BF16):
+// One workgroup per (block of 128 pairs, 16 columns of G); thread (k-step
+// ks, column c) keeps the 8 pairs of its k-step in registers.  Output layout,
+// in 32-bit words (Re in the low half, Im in the high half, both BF16):
 //   slices[kb][ks][s][g][p]   p = pair within the k-step (0..7),
 // i.e. per (block, k-step, slice) a [ng][8]-word array: a 128-row panel of a
-// tile is one contiguous 4 KB run.  sigma[kb][g] = 2^(e-8), rows padded to
-// ngp (a multiple of 128) so that a tile's sigma panel is whole.
+// tile is one contiguous 4 KB run, and a thread writes its 8 pairs as one
+// 32-byte run.  sigma[kb][g] = 2^(e-8), rows padded to ngp (a multiple of
+// 128, which the grid covers) with 1.0 so that a tile's sigma panel is whole.
+constexpr int kPrepCols = 16;
+
 __global__ __launch_bounds__(256) void sbf16_prep_kernel(
     const double2* __restrict__ m, const double2* __restrict__ delta, int64_t kc, int ng, int ngp,
     int S, int nkb, WList wl, uint32_t* __restrict__ slices_a, double* __restrict__ sigma_a,
     uint32_t* __restrict__ slices_b, double* __restrict__ sigma_b) {
-    constexpr int C = 32;  // columns per workgroup
-    __shared__ double2 s_m[kBlkB][C + 1];
-    __shared__ double s_part[8][C];
-    __shared__ int s_e[C];
+    __shared__ double s_part[4][kPrepCols];  // per-wave column maxima
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g0 = blockIdx.x * C, kb = blockIdx.y;
-    const int64_t k0 = static_cast<int64_t>(kb) * kBlkB;
-    const int kn = static_cast<int>(std::min<int64_t>(kBlkB, kc - k0));
-    // stage M[k0 .. k0+128)[g0 .. g0+32): half-waves along g (coalesced)
-    for (int r = 2 * wave + (lane >> 5); r < kBlkB; r += 8) {
-        const int g = g0 + (lane & 31);
-        s_m[r][lane & 31] = (r < kn && g < ng) ? m[(k0 + r) * ng + g] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
+    const int c = lane & (kPrepCols - 1), ks = wave * 4 + (lane >> 4);
+    const int g = blockIdx.x * kPrepCols + c, kb = blockIdx.y;
+    const int64_t k0 = static_cast<int64_t>(kb) * kBlkB + ks * kStep;
+    const int kn = static_cast<int>(std::max<int64_t>(0, std::min<int64_t>(kStep, kc - k0)));
+    const bool gv = g < ng;
+    // lanes of one k-step read 16 consecutive G: 256-byte runs of a row of M
+    double2 x[kStep];
+#pragma unroll
+    for (int p = 0; p < kStep; ++p)
+        x[p] = (gv && p < kn) ? m[(k0 + p) * ng + g] : make_double2(0.0, 0.0);
     const size_t per_op = static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep;  // words
     const int nop = 1 + wl.nh + wl.nf;
-    const int mc = tid & (C - 1), mp = tid >> 5;  // maxima: column, part of 16 pairs
     for (int op = 0; op < nop; ++op) {
-        const double2* dw = op == 0 ? nullptr : delta + static_cast<int64_t>(wl.w[op - 1]) * kc;
-        auto value = [&](int p, int c) {
-            const double2 x = s_m[p][c];
-            return (dw && p < kn) ? cmul(dw[k0 + p], x) : x;
-        };
+        double2 y[kStep];
+        if (op == 0) {
+#pragma unroll
+            for (int p = 0; p < kStep; ++p) y[p] = x[p];
+        } else {
+            const double2* dw = delta + static_cast<int64_t>(wl.w[op - 1]) * kc;
+#pragma unroll
+            for (int p = 0; p < kStep; ++p)
+                y[p] = p < kn ? cmul(dw[k0 + p], x[p]) : make_double2(0.0, 0.0);
+        }
         double mx = 0.0;
-        for (int p = mp * 16; p < mp * 16 + 16; ++p) {
-            const double2 x = value(p, mc);
-            mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
-        }
-        s_part[mp][mc] = mx;
+#pragma unroll
+        for (int p = 0; p < kStep; ++p) mx = fmax(mx, fmax(fabs(y[p].x), fabs(y[p].y)));
+        // over the 4 k-steps of this wave (lanes c, c+16, c+32, c+48), then the 4 waves
+        mx = fmax(mx, __shfl_xor(mx, 16));
+        mx = fmax(mx, __shfl_xor(mx, 32));
+        if (lane < kPrepCols) s_part[wave][c] = mx;
         __syncthreads();
-        if (tid < C) {
-            mx = s_part[0][tid];
-            for (int q = 1; q < 8; ++q) mx = fmax(mx, s_part[q][tid]);
-            int e = 0;
-            if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1): |x| < 2^e
-            s_e[tid] = e;
-            // rows past N_G (up to the padded stride) get 1.0: read, never used
-            const double sg = g0 + tid < ng ? ldexp(1.0, e - 8) : 1.0;
-            if (g0 + tid < ngp) {
-                if (op == 0)
-                    sigma_a[static_cast<size_t>(kb) * ngp + g0 + tid] = sg;
-                else
-                    sigma_b[(static_cast<size_t>(wl.w[op - 1]) * nkb + kb) * ngp + g0 + tid] = sg;
-            }
+        mx = fmax(fmax(s_part[0][c], s_part[1][c]), fmax(s_part[2][c], s_part[3][c]));
+        int e = 0;
+        if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1): |x| < 2^e
+        if (tid < kPrepCols && g < ngp) {
+            const double sg = gv ? ldexp(1.0, e - 8) : 1.0;
+            if (op == 0)
+                sigma_a[static_cast<size_t>(kb) * ngp + g] = sg;
+            else
+                sigma_b[(static_cast<size_t>(wl.w[op - 1]) * nkb + kb) * ngp + g] = sg;
         }
-        __syncthreads();
-        uint32_t* out = op == 0 ? slices_a : slices_b + static_cast<size_t>(wl.w[op - 1]) * per_op;
-        // a wave writes 8 consecutive G rows x 8 pairs = 256 contiguous bytes per slice
-        for (int u = wave; u < kStepsPerBlk * (C / 8); u += 4) {
-            const int ks = u / (C / 8), cg = u % (C / 8);
-            const int p = ks * kStep + (lane & 7), c = cg * 8 + (lane >> 3);
-            const int g = g0 + c;
-            if (g >= ng) continue;
-            const int e = s_e[c];
-            double rr = 0.0, ri = 0.0;
-            if (p < kn) {
-                const double2 x = value(p, c);
-                rr = ldexp(x.x, 8 - e);
-                ri = ldexp(x.y, 8 - e);
+        if (gv) {
+            double rr[kStep], ri[kStep];
+#pragma unroll
+            for (int p = 0; p < kStep; ++p) {
+                rr[p] = ldexp(y[p].x, 8 - e);
+                ri[p] = ldexp(y[p].y, 8 - e);
             }
-            uint32_t* o = out + ((static_cast<size_t>(kb) * kStepsPerBlk + ks) * S * ng + g) * kStep +
-                          (lane & 7);
+            uint32_t* out = op == 0 ? slices_a : slices_b + static_cast<size_t>(wl.w[op - 1]) * per_op;
+            uint32_t* o = out + ((static_cast<size_t>(kb) * kStepsPerBlk + ks) * S * ng + g) * kStep;
             for (int sl = 0; sl < S; ++sl) {
-                const double qr = rint(rr), qi = rint(ri);
-                // q 2^(-8 sl) has at most 8 significant bits: the top half of its FP32 bits is
-                // its exact BF16 encoding
-                const uint32_t br = __float_as_uint(ldexpf(static_cast<float>(qr), -8 * sl)) >> 16;
-                const uint32_t bi = __float_as_uint(ldexpf(static_cast<float>(qi), -8 * sl)) & 0xffff0000u;
-                o[static_cast<size_t>(sl) * ng * kStep] = bi | br;
-                rr = (rr - qr) * 256.0;
-                ri = (ri - qi) * 256.0;
+                uint32_t word[kStep];
+#pragma unroll
+                for (int p = 0; p < kStep; ++p) {
+                    const double qr = rint(rr[p]), qi = rint(ri[p]);
+                    // q 2^(-8 sl) has at most 8 significant bits: the top half of its FP32 bits
+                    // is its exact BF16 encoding
+                    const uint32_t br = __float_as_uint(ldexpf(static_cast<float>(qr), -8 * sl)) >> 16;
+                    const uint32_t bi =
+                        __float_as_uint(ldexpf(static_cast<float>(qi), -8 * sl)) & 0xffff0000u;
+                    word[p] = bi | br;
+                    rr[p] = (rr[p] - qr) * 256.0;
+                    ri[p] = (ri[p] - qi) * 256.0;
+                }
+                u32x4* dst = reinterpret_cast<u32x4*>(o + static_cast<size_t>(sl) * ng * kStep);
+                dst[0] = u32x4{word[0], word[1], word[2], word[3]};
+                dst[1] = u32x4{word[4], word[5], word[6], word[7]};
             }
         }
-        __syncthreads();
+        __syncthreads();  // s_part is rewritten by the next operand
     }
 }
 
@@ -192,6 +194,13 @@ template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
     static_assert(N >= 0 && N < 64, "vmcnt range");
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// vmcnt(n) and lgkmcnt(0): also every LDS read of this wave has returned.
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
 }
 
 // Workgroup tile kTI x kTJ of chi_w, NWI x NWJ waves, each BI x BJ blocks of
@@ -315,11 +324,11 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
     const f32x16 zero16 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                            0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     // Every KSUB k-steps: wait until this stage has landed (at most the
-    // kStages - 2 later stages' loads of this wave still outstanding; the
-    // barrier extends it to the workgroup), then refill the stage that the
-    // previous KSUB k-steps read, which every wave has finished.
+    // kStages - 2 later stages' loads of this wave still outstanding) and this
+    // wave's fragment reads have returned; the barrier extends both to the
+    // workgroup.  Then refill the stage that the previous KSUB k-steps read.
     auto sync = [&](int st) {
-        wait_vmcnt<(kStages - 2) * KSUB * NLD>();
+        wait_vm_lgkm0<(kStages - 2) * KSUB * NLD>();
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");  // keep the LDS reads below the barrier
 #pragma unroll
@@ -328,28 +337,38 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
             issue(min(nx, nsteps - 1), nx % NSLOT);
         }
     };
-    // one k-step; on the block's first step (`first`) every group starts from zero
-    auto step = [&](int st, auto first) {
+    // Fragments of one k-step: S slices of this wave's rows of A (FA) and
+    // columns of B (FB).
+    struct FA {
+        u32x4 v[S][BI];
+    };
+    struct FB {
+        u32x4 v[S][BJ];
+    };
+    auto read_a = [&](int st, FA& f) {
         const u32x4* L = lds + (st % NSLOT) * NCHP;
-        // every fragment of the k-step is read up front: the waits for them
-        // then overlap the MFMA stream instead of stalling it once per slice
-        u32x4 fa[S][BI], fbs[S][BJ];
 #pragma unroll
         for (int sl = 0; sl < S; ++sl)
 #pragma unroll
             for (int x = 0; x < BI; ++x)
-                fa[sl][x] = L[sl * 2 * kTI + lds_slot(wi * BI * 32 + x * 32 + rl, hl)];
+                f.v[sl][x] = L[sl * 2 * kTI + lds_slot(wi * BI * 32 + x * 32 + rl, hl)];
+    };
+    auto read_b = [&](int st, FB& f) {
+        const u32x4* L = lds + (st % NSLOT) * NCHP;
 #pragma unroll
-        for (int b = 0; b < S; ++b)
+        for (int sl = 0; sl < S; ++sl)
 #pragma unroll
             for (int y = 0; y < BJ; ++y)
-                fbs[b][y] = L[CA + b * 2 * kTJ + lds_slot(wj * BJ * 32 + y * 32 + rl, hl)];
-        __builtin_amdgcn_sched_barrier(0);
+                f.v[sl][y] = L[CA + sl * 2 * kTJ + lds_slot(wj * BJ * 32 + y * 32 + rl, hl)];
+    };
+    // The MFMAs of one k-step for B slices [B0, B1); on the block's first step
+    // (`first`) every group starts from zero.
+    auto compute = [&](const FA& fa, const FB& fbs, auto first, auto b0, auto b1) {
 #pragma unroll
-        for (int b = 0; b < S; ++b)
+        for (int b = decltype(b0)::value; b < decltype(b1)::value; ++b)
 #pragma unroll
             for (int y = 0; y < BJ; ++y) {
-                const u32x4 fb = fbs[b][y];
+                const u32x4 fb = fbs.v[b][y];
                 const u32x4 fbi = swap_neg(fb);
 #pragma unroll
                 for (int a = 0; a < S - b; ++a) {
@@ -358,32 +377,90 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                     const bool fresh = decltype(first)::value && b == 0 && a == g;
 #pragma unroll
                     for (int x = 0; x < BI; ++x) {
-                        accR[g][x][y] = mfma32(fa[a][x], fb, fresh ? zero16 : accR[g][x][y]);
-                        accI[g][x][y] = mfma32(fa[a][x], fbi, fresh ? zero16 : accI[g][x][y]);
+                        accR[g][x][y] = mfma32(fa.v[a][x], fb, fresh ? zero16 : accR[g][x][y]);
+                        accI[g][x][y] = mfma32(fa.v[a][x], fbi, fresh ? zero16 : accI[g][x][y]);
                     }
                 }
             }
-        return L;
+    };
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    using BS = std::integral_constant<int, S>;
+    const std::true_type yes{};
+    const std::false_type no{};
+    // How far ahead the fragments are read, as far as registers allow (two
+    // waves of 256 registers per SIMD):
+    //   2: both operands of step st + 1 are requested before the MFMAs of step
+    //      st, so their LDS reads run under them;
+    //   1: the A fragments of step st + 1 are requested after the first B
+    //      slice's MFMAs of step st, and step st's own B fragments at its start
+    //      (only the first of them is waited for before MFMAs begin);
+    //   0: each step reads its fragments just before its MFMAs.
+    // A stage sync (which refills the stage of the k-steps just read) comes
+    // right before the first read of a step that opens a stage.
+    constexpr int kPipe = S <= 3 ? 2 : S <= 5 ? 1 : 0;
+    FA a0, a1;
+    FB b0, b1;
+    // step st with A fragments ca (read earlier) and B fragments cb; with
+    // `prefetch`, also reads step st + 1 into na (and nb)
+    auto pstep = [&](int st, FA& ca, FB& cb, FA& na, FB& nb, auto first, auto prefetch) {
+        constexpr bool pf = decltype(prefetch)::value;
+        if constexpr (kPipe == 2) {
+            if constexpr (pf) {
+                if ((st + 1) % KSUB == 0) sync(st + 1);
+                read_a(st + 1, na);
+                read_b(st + 1, nb);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            compute(ca, cb, first, B0{}, BS{});
+        } else {
+            read_b(st, cb);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(ca, cb, first, B0{}, B1{});
+            if constexpr (pf) {
+                if ((st + 1) % KSUB == 0) sync(st + 1);
+                read_a(st + 1, na);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            compute(ca, cb, first, B1{}, BS{});
+        }
     };
 #pragma unroll
     for (int q = 0; q < (kStages - 1) * KSUB; ++q) issue(min(q, nsteps - 1), q);
+    if constexpr (kPipe > 0) {
+        sync(0);
+        read_a(0, a0);
+        if constexpr (kPipe == 2) read_b(0, b0);
+    }
     for (int kb = 0; kb < nkb; ++kb) {
         const int st0 = kb * kStepsPerBlk;
-        sync(st0);
-        step(st0, std::true_type{});
-#pragma unroll
-        for (int i = 1; i < KSUB; ++i) step(st0 + i, std::false_type{});
-        for (int ks = KSUB; ks < kStepsPerBlk - KSUB; ks += KSUB) {
-            sync(st0 + ks);
-#pragma unroll
-            for (int i = 0; i < KSUB; ++i) step(st0 + ks + i, std::false_type{});
+        if constexpr (kPipe > 0) {
+            // kPipe 1 reads each step's B into its own buffer and never uses nb
+            FB& b1x = kPipe == 2 ? b1 : b0;
+            pstep(st0, a0, b0, a1, b1x, yes, yes);
+            pstep(st0 + 1, a1, b1x, a0, b0, no, yes);
+            for (int ks = 2; ks < kStepsPerBlk - 2; ks += 2) {
+                pstep(st0 + ks, a0, b0, a1, b1x, no, yes);
+                pstep(st0 + ks + 1, a1, b1x, a0, b0, no, yes);
+            }
+            pstep(st0 + kStepsPerBlk - 2, a0, b0, a1, b1x, no, yes);
+            // The block's last step prefetches nothing: the stage sync that the
+            // next step needs would refill the stage that holds this block's sigma.
+            pstep(st0 + kStepsPerBlk - 1, a1, b1x, a0, b0, no, no);
+        } else {
+            auto step = [&](int st, auto first) {
+                if (st % KSUB == 0) sync(st);
+                read_a(st, a0);
+                read_b(st, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(a0, b0, first, B0{}, BS{});
+            };
+            step(st0, yes);
+            for (int ks = 1; ks < kStepsPerBlk; ++ks) step(st0 + ks, no);
         }
-        sync(st0 + kStepsPerBlk - KSUB);
-#pragma unroll
-        for (int i = 0; i < KSUB - 1; ++i) step(st0 + kStepsPerBlk - KSUB + i, std::false_type{});
-        const u32x4* L = step(st0 + kStepsPerBlk - 1, std::false_type{});
         // end of the block: fold the FP32 groups into FP64 with this block's sigma
-        const double* sgl = reinterpret_cast<const double*>(L + CA + CB);
+        const double* sgl = reinterpret_cast<const double*>(
+            lds + ((st0 + kStepsPerBlk - 1) % NSLOT) * NCHP + CA + CB);
 #pragma unroll
         for (int y = 0; y < BJ; ++y) {
             const double sbj = sgl[kTI + wj * BJ * 32 + y * 32 + rl];
@@ -403,6 +480,11 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                     dr[x][y][t] = fma(sc, vr, dr[x][y][t]);
                     di[x][y][t] = fma(sc, vi, di[x][y][t]);
                 }
+        }
+        if (kPipe > 0 && kb + 1 < nkb) {
+            sync(st0 + kStepsPerBlk);
+            read_a(st0 + kStepsPerBlk, a0);
+            if constexpr (kPipe == 2) read_b(st0 + kStepsPerBlk, b0);
         }
     }
     wait_vmcnt<0>();  // no load into this workgroup's LDS may outlive the tile
@@ -529,7 +611,7 @@ SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const doub
                          int nz, const WList& wl, void* scratch, hipStream_t s) {
     const SbDesc d = sbf16_desc(S, kc, ng, nz, scratch);
     ProfScope ps("split_prep", s);
-    hipLaunchKernelGGL(sbf16_prep_kernel, dim3(ceil_div(ng, 32), d.nkb), dim3(256), 0, s, m, delta,
+    hipLaunchKernelGGL(sbf16_prep_kernel, dim3(d.ngp / kPrepCols, d.nkb), dim3(256), 0, s, m, delta,
                        kc, ng, d.ngp, S, d.nkb, wl, const_cast<uint32_t*>(d.sa),
                        const_cast<double*>(d.siga), const_cast<uint32_t*>(d.sb),
                        const_cast<double*>(d.sigb));
