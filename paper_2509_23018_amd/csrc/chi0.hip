@@ -50,8 +50,9 @@ constexpr int kKt = 16;     // pairs per LDS stage
 // the MFMAs accumulate conj(M_i) (Delta M_j).  Loads are unconditional: pair
 // rows past the chunk end are clamped and carry Delta = 0, columns past N_G
 // are clamped and only feed outputs that are not stored.
-// mode: 0 overwrite, 1 accumulate.
-template <int T, int WI, int WJ, int PAD>
+// mode: 0 overwrite, 1 accumulate.  PART: store the whole T x T tile instead,
+// unmasked, row-major at cw (a partial sum over a range of pairs).
+template <int T, int WI, int WJ, int PAD, bool PART = false>
 __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict__ m, int64_t kc,
                                          int ng, const double2* __restrict__ dw,
                                          double2* __restrict__ cw, int mode, int bi, int bj) {
@@ -144,8 +145,13 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
         for (int y = 0; y < BY; ++y)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int gi = i0 + wi * (T / WI) + x * 16 + 4 * t + kq;
-                const int gj = j0 + wj * (T / WJ) + y * 16 + row;
+                const int li = wi * (T / WI) + x * 16 + 4 * t + kq;
+                const int lj = wj * (T / WJ) + y * 16 + row;
+                if constexpr (PART) {
+                    cw[li * T + lj] = make_double2(accr[x][y][t], acci[x][y][t]);
+                    continue;
+                }
+                const int gi = i0 + li, gj = j0 + lj;
                 if (gi < ng && gj < ng) {
                     double2* p = cw + static_cast<int64_t>(gi) * ng + gj;
                     double2 v = make_double2(accr[x][y][t], acci[x][y][t]);
@@ -160,15 +166,62 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
 }
 
 
+// The first n_main items, one per workgroup, over all pairs of the chunk.
+// Each of the remaining items (the last, partial round of workgroups) is cut
+// into `parts` ranges of whole stages; workgroup n_main + j*parts + p writes
+// item n_main + j's partial sum over range p to ws[j*parts + p] (T x T), and
+// tail_reduce_kernel adds the parts into chi.
 template <int T, int WI, int WJ, int PAD>
 __global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_kernel(
     const double2* __restrict__ m, int64_t kc, int ng, const double2* __restrict__ delta,
-    WList wl, double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
-    int w, bi, bj;
-    decode_item(blockIdx.x, wl, nb, order, w, bi, bj);
+    WList wl, double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order,
+    int n_main, int parts, double2* __restrict__ ws) {
     extern __shared__ double2 lds[];
-    f64_tile<T, WI, WJ, PAD>(lds, m, kc, ng, delta + static_cast<int64_t>(w) * kc,
-                             chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj);
+    const int b = blockIdx.x;
+    int w, bi, bj;
+    if (b < n_main) {
+        item_tile(xcd_item(b, n_main), wl, nb, order, w, bi, bj);
+        f64_tile<T, WI, WJ, PAD>(lds, m, kc, ng, delta + static_cast<int64_t>(w) * kc,
+                                 chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj);
+        return;
+    }
+    const int u = b - n_main, j = u / parts, p = u % parts;
+    item_tile(n_main + j, wl, nb, order, w, bi, bj);
+    const int64_t nst = (kc + kKt - 1) / kKt;
+    const int64_t k0 = p * nst / parts * kKt;
+    const int64_t k1 = std::min<int64_t>(kc, (p + 1) * nst / parts * kKt);
+    f64_tile<T, WI, WJ, PAD, true>(lds, m + k0 * ng, k1 - k0, ng,
+                                   delta + static_cast<int64_t>(w) * kc + k0,
+                                   ws + static_cast<int64_t>(u) * T * T, 0, bi, bj);
+}
+
+// chi_w[tile] (=|+=) the sum of the parts of tail item n_main + blockIdx.y,
+// added in part order.
+template <int T>
+__global__ __launch_bounds__(256) void tail_reduce_kernel(const double2* __restrict__ ws,
+                                                          int parts, int n_main, WList wl, int nb,
+                                                          const int* __restrict__ order,
+                                                          double2* __restrict__ chi, int ng,
+                                                          int mode) {
+    const int j = blockIdx.y, e = blockIdx.x * 256 + threadIdx.x;
+    int w, bi, bj;
+    item_tile(n_main + j, wl, nb, order, w, bi, bj);
+    const int gi = bi * T + e / T, gj = bj * T + e % T;
+    if (gi >= ng || gj >= ng) return;
+    const double2* src = ws + static_cast<int64_t>(j) * parts * T * T + e;
+    double2 acc = src[0];
+    for (int p = 1; p < parts; ++p) {
+        const double2 v = src[static_cast<int64_t>(p) * T * T];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    double2* dst = chi + static_cast<int64_t>(w) * ng * ng + static_cast<int64_t>(gi) * ng + gj;
+    if (mode) {
+        const double2 o = *dst;
+        acc.x += o.x;
+        acc.y += o.y;
+    }
+    *dst = acc;
 }
 
 // Persistent form for batches of problems: every workgroup takes items
@@ -198,6 +251,7 @@ __global__ __launch_bounds__(WI * WJ * 64) void chi0_f64_batched_kernel(
 struct Chi0Variant {
     const void* fn;       // per-launch kernel
     const void* fn_batch; // persistent batched kernel
+    const void* fn_tail;  // tail_reduce_kernel<T>
     int tile, threads;
     size_t lds;
 };
@@ -205,8 +259,9 @@ struct Chi0Variant {
 template <int T, int WI, int WJ, int PAD>
 Chi0Variant chi0_variant() {
     return {reinterpret_cast<const void*>(&chi0_f64_kernel<T, WI, WJ, PAD>),
-            reinterpret_cast<const void*>(&chi0_f64_batched_kernel<T, WI, WJ, PAD>), T,
-            WI * WJ * 64, 2 * 2 * kKt * (T + PAD) * sizeof(double2)};
+            reinterpret_cast<const void*>(&chi0_f64_batched_kernel<T, WI, WJ, PAD>),
+            reinterpret_cast<const void*>(&tail_reduce_kernel<T>), T, WI * WJ * 64,
+            2 * 2 * kKt * (T + PAD) * sizeof(double2)};
 }
 
 // Tile shapes of the FP64 contraction, indexed by variant id (the autotuner
@@ -253,24 +308,80 @@ void launch_delta(const double* e_v, const double* e_c, PairMap pm, int64_t npai
     }
 }
 
+namespace {
+// Workgroups of variant v resident on the current device at once.
+int f64_slots(int variant) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;  // (device, variant) -> slots
+    int dev = 0;
+    GW_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    int& n = cache[{dev, variant}];
+    if (n > 0) return n;
+    const Chi0Variant& v = chi0_variant_by_id(variant);
+    GW_HIP_TRY(hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(v.lds)));
+    int per_cu = 0, cus = 0;
+    GW_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, v.fn, v.threads, v.lds));
+    GW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    n = std::max(1, per_cu) * std::max(1, cus);
+    return n;
+}
+}  // namespace
+
+size_t chi0_f64_tail_bytes() {
+    size_t b = 0;
+    for (int v = 0; v < kNumChi0Variants; ++v) {
+        const size_t t = static_cast<size_t>(chi0_variant_by_id(v).tile);
+        b = std::max(b, static_cast<size_t>(f64_slots(v)) * t * t * sizeof(double2));
+    }
+    return b;
+}
+
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
-                     const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant) {
+                     const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant,
+                     double2* tail_ws) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     const Chi0Variant& v = chi0_variant_by_id(variant);
     const int nb = ceil_div(ng, v.tile);
     const int64_t nitems = static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
                            static_cast<int64_t>(wl.nf) * nb * nb;
-    if (nitems >= (int64_t(1) << 31)) throw Error{-4, "too many chi tiles for one launch"};
+    if (nitems >= (int64_t(1) << 30)) throw Error{-4, "too many chi tiles for one launch"};
     GW_HIP_TRY(hipFuncSetAttribute(v.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(v.lds)));
-    ProfScope ps("chi0_f64", s);
+    // A last round of workgroups that fills at most half the chip is cut
+    // along the pairs: each of its items becomes `parts` workgroups over
+    // ranges of stages, which together fill the round.
+    int n_main = static_cast<int>(nitems), parts = 1, n_tail = 0;
+    if (tail_ws) {
+        const int slots = f64_slots(variant);
+        const int rem = static_cast<int>(nitems % slots);
+        const int64_t nst = (kc + kKt - 1) / kKt;
+        const int pc = static_cast<int>(std::min<int64_t>(rem > 0 ? slots / rem : 0, nst));
+        if (rem > 0 && 2 * rem <= slots && pc >= 2) {
+            n_tail = rem;
+            parts = pc;
+            n_main = static_cast<int>(nitems) - rem;
+        }
+    }
     int mode = accumulate ? 1 : 0;
     const int* order = tile_order(nb);
-    void* args[] = {const_cast<double2**>(&m), &kc, &ng, const_cast<double2**>(&delta),
-                    const_cast<WList*>(&wl), &chi, &mode, const_cast<int*>(&nb),
-                    const_cast<int**>(&order)};
-    GW_HIP_TRY(hipLaunchKernel(v.fn, dim3(static_cast<unsigned>(nitems)), dim3(v.threads), args,
-                               v.lds, s));
+    {
+        ProfScope ps("chi0_f64", s);
+        void* args[] = {const_cast<double2**>(&m), &kc, &ng, const_cast<double2**>(&delta),
+                        const_cast<WList*>(&wl), &chi, &mode, const_cast<int*>(&nb),
+                        const_cast<int**>(&order), &n_main, &parts, &tail_ws};
+        const unsigned grid = static_cast<unsigned>(n_main + n_tail * parts);
+        GW_HIP_TRY(hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), args, v.lds, s));
+    }
+    if (n_tail > 0) {
+        ProfScope ps("chi0_tail", s);
+        void* args[] = {&tail_ws, &parts, &n_main, const_cast<WList*>(&wl),
+                        const_cast<int*>(&nb), const_cast<int**>(&order), &chi, &ng, &mode};
+        const unsigned gx = static_cast<unsigned>(v.tile * v.tile / 256);
+        GW_HIP_TRY(hipLaunchKernel(v.fn_tail, dim3(gx, static_cast<unsigned>(n_tail)), dim3(256),
+                                   args, 0, s));
+    }
 }
 
 void launch_chi0_f64_batched(const QDesc* qd, const int4* items, int nitems, int* counter,

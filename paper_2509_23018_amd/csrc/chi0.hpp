@@ -32,9 +32,13 @@ struct WList {
 
 // chi[w] (=|+=) M^H diag(delta[w]) M for every frequency w of wl; M is
 // [kc][ng], delta [nz][kc], chi [nz][ng][ng].  variant selects the tile
-// shape (0: 64x64, 4 waves; 1: 128x128, 8 waves).
+// shape (0: 64x64, 4 waves; 1: 128x128, 8 waves).  With tail_ws (device,
+// chi0_f64_tail_bytes() bytes) a last partial round of tiles is cut along the
+// pairs and reduced by a second launch; without it every tile is whole.
 void launch_chi0_f64(const double2* m, int64_t kc, int ng, const double2* delta,
-                     const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant);
+                     const WList& wl, double2* chi, bool accumulate, hipStream_t s, int variant,
+                     double2* tail_ws = nullptr);
+size_t chi0_f64_tail_bytes();  // for the current device
 int chi0_variant_tile(int variant);
 int chi0_f64_batched_blocks_per_cu(int variant);  // resident workgroups of the persistent kernel
 int chi0_forced_variant();  // GW_CHI0_VARIANT, or -1

@@ -439,12 +439,15 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     }
     // the autotuner's trials write one frequency plane here, never into chi
     const size_t off_tune = cv.take(tune ? ng * ng * sizeof(double2) : 0);
+    // partial sums of the FP64 contraction's last round of tiles
+    const size_t off_tail = cv.take(o.precision == GW_FP64 ? chi0_f64_tail_bytes() : 0);
     char* base = static_cast<char*>(scratch(cv.off, s));
     double2* mbuf[2] = {reinterpret_cast<double2*>(base + off_m[0]),
                         reinterpret_cast<double2*>(base + off_m[1])};
     double2* dbuf[2] = {reinterpret_cast<double2*>(base + off_d[0]),
                         reinterpret_cast<double2*>(base + off_d[1])};
     double2* t2 = reinterpret_cast<double2*>(base + off_t2);
+    double2* tail_ws = o.precision == GW_FP64 ? reinterpret_cast<double2*>(base + off_tail) : nullptr;
     const double2* z = reinterpret_cast<const double2*>(pr.z);
     std::vector<bool> herm(pr.nz);
     for (int w = 0; w < pr.nz; ++w)
@@ -475,7 +478,8 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
         one.nf = 1;
         double2* trial_chi = reinterpret_cast<double2*>(base + off_tune);
         variant = tune_variant(pr.ng, chunks[0].kc, s, [&](int v) {
-            launch_chi0_f64(mbuf[0], chunks[0].kc, pr.ng, dbuf[0], one, trial_chi, false, s, v);
+            launch_chi0_f64(mbuf[0], chunks[0].kc, pr.ng, dbuf[0], one, trial_chi, false, s, v,
+                            tail_ws);
         });
     }
     for (size_t k = 0; k < chunks.size(); ++k) {
@@ -485,7 +489,8 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
         for (const WList& wl : wlists) {
             const bool acc = accumulate || k > 0;
             if (o.precision == GW_FP64)
-                launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s, variant);
+                launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s, variant,
+                                tail_ws);
             else if (o.precision == GW_FP32)
                 launch_chi0_f32(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
             else

@@ -16,18 +16,21 @@ namespace gw {
 const int* tile_order(int nb, int super = 8);
 void release_tile_orders();
 
-// Frequency and tile of workgroup b.  Items are frequency-major: every
-// Hermitian frequency over the tiles on or above the diagonal, then every
-// other frequency over all tiles.  The 8 XCDs take workgroups round-robin,
+// Item of workgroup b among n items.  The 8 XCDs take workgroups round-robin,
 // so blocks are renumbered to give each XCD a contiguous range of items.
-__device__ __forceinline__ void decode_item(int b, const WList& wl, int nb,
-                                            const int* __restrict__ order, int& w, int& bi,
-                                            int& bj) {
-    const int nh = nb * (nb + 1) / 2, nf = nb * nb;
-    const int nitems = wl.nh * nh + wl.nf * nf;
-    const int q = nitems >> 3, r = nitems & 7;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+    const int q = n >> 3, r = n & 7;
     const int x = b & 7, i = b >> 3;
-    int t = x * q + (x < r ? x : r) + i;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Frequency and tile of item t.  Items are frequency-major: every Hermitian
+// frequency over the tiles on or above the diagonal, then every other
+// frequency over all tiles.
+__device__ __forceinline__ void item_tile(int t, const WList& wl, int nb,
+                                          const int* __restrict__ order, int& w, int& bi,
+                                          int& bj) {
+    const int nh = nb * (nb + 1) / 2, nf = nb * nb;
     int code;
     if (t < wl.nh * nh) {
         w = wl.w[t / nh];
@@ -39,6 +42,14 @@ __device__ __forceinline__ void decode_item(int b, const WList& wl, int nb,
     }
     bi = code >> 16;
     bj = code & 0xffff;
+}
+
+// Frequency and tile of workgroup b when one workgroup takes each item.
+__device__ __forceinline__ void decode_item(int b, const WList& wl, int nb,
+                                            const int* __restrict__ order, int& w, int& bi,
+                                            int& bj) {
+    const int nitems = wl.nh * (nb * (nb + 1) / 2) + wl.nf * nb * nb;
+    item_tile(xcd_item(b, nitems), wl, nb, order, w, bi, bj);
 }
 
 }  // namespace gw

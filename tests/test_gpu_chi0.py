@@ -152,3 +152,34 @@ def test_chi0_precision_workload_grid_and_sphere(prec, ns, tol):
     chi = gw.gw_chi0(dp, precision=prec, n_slices=ns, pair_chunk=48)
     got = chi[:, torch.from_numpy(rows).to(device())].cpu().numpy()
     assert rel_fro(got, ref) < tol, rel_fro(got, ref)
+
+
+def test_chi0_tail_round_split():
+    """Launches whose last round of workgroups is partial.  11 x 11 tiles of 64
+    (N_G = 691) over 1 Hermitian and 4 other frequencies are 550 items, 38 past
+    the 512 workgroups an MI355X holds at once: those tiles are cut into 13
+    pair ranges each and a second launch adds the ranges.  Accumulating, every
+    frequency takes all tiles (605 items, 93 cut into 5 ranges).  Two chunks of
+    200 pairs, so the second chunk's partial tiles add onto the first's.
+    Parity with the oracle and the same bits on a second run."""
+    zs = (0.4j, 0.1 + 0.01j, 0.5 + 0.02j, 0.9 + 0.005j, 1.3 + 0.01j)
+    p = gen.make_problem((16, 16, 16), 4, 100, r2=29, z=zs, seed=21, pair_chunk=200)
+    assert p.ng == 691, p.ng
+    ref = _oracle_chi(p)
+    gw.profile_enable(True)
+    gw.profile_reset()
+    try:
+        chi = run_chi0(p)
+        n_tail, _ = gw.profile_read("chi0_tail")
+    finally:
+        gw.profile_enable(False)
+    assert n_tail == 2  # one per chunk
+    assert rel_fro(chi, ref) < FP64_TOL
+    for w in range(len(zs)):
+        assert rel_fro(chi[w], ref[w]) < FP64_TOL
+    assert np.array_equal(run_chi0(p), chi)
+    dp = to_dev(p)
+    dp.chi = torch.full((len(zs), p.ng, p.ng), 0.25 - 1.0j, dtype=torch.complex128, device=device())
+    gw.gw_chi0(dp, flags=gw.GW_FLAG_ACCUMULATE, pair_chunk=200)
+    torch.cuda.synchronize()
+    assert rel_fro(dp.chi.cpu().numpy() - (0.25 - 1.0j), ref) < FP64_TOL
