@@ -213,7 +213,8 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         gw.profile_enable(False)
-        ks = {k: gw.profile_read(k) for k in ("mtxel_zy", "mtxel_x", "split_prep", "chi0_split")}
+        ks = {k: gw.profile_read(k)
+              for k in ("mtxel_zy", "mtxel_x", "split_prep", "chi0_split", "chi0_split_tail")}
         gw.profile_reset()
         got = dp.chi
         err = float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))

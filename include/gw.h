@@ -161,10 +161,10 @@ gw_status_t gw_mtxel(const gw_grid_t* grid,
  * with GW_FLAG_GRAPH the whole call is captured once and replayed (the
  * caller keeps every pointer valid and unchanged between replays; problems
  * must not change size).  FP32 and split FP16 run the problems one by one.
- * A single FP64 problem cuts the tiles of a contraction's last, partial round
- * of workgroups along the pairs and adds the parts in a fixed order: results
- * are the same on every run on the same device, but not bitwise those of the
- * batched path.
+ * A single FP64 or split-BF16 problem cuts the tiles of a contraction's last,
+ * partial round of workgroups along the pairs and adds the parts in a fixed
+ * order: results are the same on every run on the same device, but not
+ * bitwise those of the batched path.
  * opts may be NULL (FP64, chunk 4096, s = 2).  Split precision accepts
  * 2..6 slices; returns GW_EUNSUPPORTED beyond that.
  */
@@ -204,9 +204,9 @@ int32_t gw_abi_version(void);
  * Launch timing for measurement harnesses.  While enabled, the library
  * records a HIP event on the caller's stream before and after each of its
  * kernel launches and files the pair under the kernel's name ("mtxel_zy",
- * "mtxel_x", "delta", "chi0_f64", "chi0_tail", "chi0_f64_batched", "split_prep",
- * "chi0_split", "chi0_split_batched", "chi0_f32", "mirror", "bwd_gm",
- * "bwd_transform").
+ * "mtxel_x", "delta", "chi0_f64", "chi0_tail", "chi0_f64_batched",
+ * "split_prep", "chi0_split", "chi0_split_tail", "chi0_split_batched",
+ * "chi0_f32", "mirror", "bwd_gm", "bwd_transform").
  * gw_profile_read waits for the recorded events of `kernel` and returns the
  * number of launches and the summed duration in milliseconds (0 and 0.0 for
  * an unknown name).  gw_profile_reset forgets every record.  Timing adds two

@@ -65,16 +65,20 @@ void launch_chi0_f64_batched(const QDesc* qd, const int4* items, int nitems, int
 size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S);
 void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        const double2* delta, int nz, const WList& wl, double2* chi,
-                       bool accumulate, void* scratch, hipStream_t s);
+                       bool accumulate, void* scratch, hipStream_t s,
+                       double2* tail_ws = nullptr);  // split BF16 only (launch_chi0_sbf16)
 void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta, const WList& wl,
                      double2* chi, bool accumulate, hipStream_t s);
 constexpr int kSplitTile = 64;  // tile edge of the FP16-split and FP32 kernels
 // Split BF16 on the 32x32 MFMA (grouped shifts, 128 x 64 workgroup tiles; the
 // Hermitian rule and mirror use 128-wide square blocks); same scratch layout
 // size as launch_chi0_split.
+// With tail_ws (device, sbf16_tail_bytes() bytes) a last partial round of
+// tiles is cut along the 128-pair blocks and reduced by a second launch.
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
-                       hipStream_t s);
+                       hipStream_t s, double2* tail_ws = nullptr);
+size_t sbf16_tail_bytes();  // for the current device
 // Operands of one problem's chunk for the split-BF16 contraction (device
 // pointers into scratch; frequency w's B slices and sigma follow at fixed
 // strides).

@@ -27,6 +27,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "chi0.hpp"
@@ -140,20 +142,17 @@ __global__ __launch_bounds__(256) void sbf16_prep_kernel(
 
 // ---------------------------------------------------------------- contraction
 
-// Item b -> frequency w, 128-row block bi, 64-column block bj.  Items come in
+// Item t -> frequency w, 128-row block bi, 64-column block bj.  Items come in
 // pairs (both 64-column halves of one 128 x 128 block) so that the square
 // tile order and the Hermitian rule (blocks on or above the diagonal) of the
-// FP64 kernels apply with a 128 tile; the XCD renumbering keeps each XCD on
-// a contiguous run of items, and 4 x 4 super-blocks make the 32 workgroups
-// an XCD runs at once share 4 row panels and 8 column panels.
-__device__ __forceinline__ void decode_item_rect(int b, const WList& wl, int nb,
-                                                 const int* __restrict__ order, int& w, int& bi,
-                                                 int& bj) {
+// FP64 kernels apply with a 128 tile; workgroups reach items through the XCD
+// renumbering (xcd_item), which keeps each XCD on a contiguous run of items,
+// and 4 x 4 super-blocks make the 32 workgroups an XCD runs at once share 4
+// row panels and 8 column panels.
+__device__ __forceinline__ void rect_item_tile(int t, const WList& wl, int nb,
+                                               const int* __restrict__ order, int& w, int& bi,
+                                               int& bj) {
     const int nh = nb * (nb + 1) / 2, nf = nb * nb;
-    const int nitems = 2 * (wl.nh * nh + wl.nf * nf);
-    const int q = nitems >> 3, r = nitems & 7;
-    const int x = b & 7, i = b >> 3;
-    int t = x * q + (x < r ? x : r) + i;
     const int half = t & 1;
     t >>= 1;
     int code;
@@ -235,7 +234,7 @@ struct SbGeom {
 // sb and sigb are that frequency's B slices and sigma.  The caller has made
 // sure every wave of the workgroup calls this with the same arguments and
 // that no earlier reader of lds is still running.
-template <int S, int NWI, int NWJ, int BI, int BJ>
+template <int S, int NWI, int NWJ, int BI, int BJ, bool PART = false>
 __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                                            const double* __restrict__ siga,
                                            const u32x4* __restrict__ sb,
@@ -494,8 +493,14 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
         for (int y = 0; y < BJ; ++y)
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
-                const int gi = i0 + wi * BI * 32 + x * 32 + 8 * (t >> 2) + 4 * hl + (t & 3);
-                const int gj = j0 + wj * BJ * 32 + y * 32 + rl;
+                const int li = wi * BI * 32 + x * 32 + 8 * (t >> 2) + 4 * hl + (t & 3);
+                const int lj = wj * BJ * 32 + y * 32 + rl;
+                if constexpr (PART) {
+                    // a partial sum: the whole tile, unmasked, row-major
+                    cw[li * kTJ + lj] = make_double2(dr[x][y][t], di[x][y][t]);
+                    continue;
+                }
+                const int gi = i0 + li, gj = j0 + lj;
                 if (gi < ng && gj < ng) {
                     double2* p = cw + static_cast<int64_t>(gi) * ng + gj;
                     double2 v = make_double2(dr[x][y][t], di[x][y][t]);
@@ -509,20 +514,65 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
             }
 }
 
-// One launch per chunk: workgroup b takes item b (frequency, tile).
+// One launch per chunk.  The first n_main items take one workgroup each over
+// all blocks of the chunk.  Each remaining item (the last, partial round) is
+// cut into `parts` ranges of 128-pair blocks: workgroup n_main + j*parts + p
+// writes item n_main + j's partial sum over range p to ws[j*parts + p]
+// (kTI x kTJ), and sbf16_tail_reduce_kernel adds the parts into chi.
 template <int S, int NWI, int NWJ, int BI, int BJ>
 __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     const u32x4* __restrict__ sa, const double* __restrict__ siga, const u32x4* __restrict__ sb_all,
     const double* __restrict__ sigb_all, int ng, int ngp, int nkb, WList wl,
-    double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order) {
+    double2* __restrict__ chi, int mode, int nb, const int* __restrict__ order, int n_main,
+    int parts, double2* __restrict__ ws) {
     extern __shared__ u32x4 lds[];
+    const int b = blockIdx.x;
+    const size_t blk = static_cast<size_t>(kStepsPerBlk) * S * ng * 2;  // chunks per block
+    const size_t plane = static_cast<size_t>(nkb) * blk;
     int w, bi, bj;
-    decode_item_rect(blockIdx.x, wl, nb, order, w, bi, bj);
-    if (bj * kTJ >= ng) return;  // right half of the last block column lies past N_G
-    const size_t plane = static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * 2;  // chunks
-    sbf16_tile<S, NWI, NWJ, BI, BJ>(sa, siga, sb_all + w * plane,
-                                    sigb_all + static_cast<size_t>(w) * nkb * ngp, ng, ngp, nkb,
-                                    chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj, lds);
+    if (b < n_main) {
+        rect_item_tile(xcd_item(b, n_main), wl, nb, order, w, bi, bj);
+        if (bj * kTJ >= ng) return;  // right half of the last block column lies past N_G
+        sbf16_tile<S, NWI, NWJ, BI, BJ>(sa, siga, sb_all + w * plane,
+                                        sigb_all + static_cast<size_t>(w) * nkb * ngp, ng, ngp,
+                                        nkb, chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj,
+                                        lds);
+        return;
+    }
+    const int u = b - n_main, j = u / parts, p = u % parts;
+    rect_item_tile(n_main + j, wl, nb, order, w, bi, bj);
+    if (bj * kTJ >= ng) return;  // nothing of it is ever read
+    const int kb0 = p * nkb / parts, kb1 = (p + 1) * nkb / parts;
+    sbf16_tile<S, NWI, NWJ, BI, BJ, true>(
+        sa + kb0 * blk, siga + static_cast<size_t>(kb0) * ngp, sb_all + w * plane + kb0 * blk,
+        sigb_all + (static_cast<size_t>(w) * nkb + kb0) * ngp, ng, ngp, kb1 - kb0,
+        ws + static_cast<int64_t>(u) * kTI * kTJ, 0, bi, bj, lds);
+}
+
+// chi_w[tile] (=|+=) the sum of the parts of tail item n_main + blockIdx.y,
+// added in part order.
+__global__ __launch_bounds__(256) void sbf16_tail_reduce_kernel(
+    const double2* __restrict__ ws, int parts, int n_main, WList wl, int nb,
+    const int* __restrict__ order, double2* __restrict__ chi, int ng, int mode) {
+    const int j = blockIdx.y, e = blockIdx.x * 256 + threadIdx.x;
+    int w, bi, bj;
+    rect_item_tile(n_main + j, wl, nb, order, w, bi, bj);
+    const int gi = bi * kTI + e / kTJ, gj = bj * kTJ + e % kTJ;
+    if (gi >= ng || gj >= ng) return;
+    const double2* src = ws + static_cast<int64_t>(j) * parts * kTI * kTJ + e;
+    double2 acc = src[0];
+    for (int p = 1; p < parts; ++p) {
+        const double2 v = src[static_cast<int64_t>(p) * kTI * kTJ];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    double2* dst = chi + static_cast<int64_t>(w) * ng * ng + static_cast<int64_t>(gi) * ng + gj;
+    if (mode) {
+        const double2 o = *dst;
+        acc.x += o.x;
+        acc.y += o.y;
+    }
+    *dst = acc;
 }
 
 // Persistent: workgroups pull items (problem, frequency, 128-row block,
@@ -554,24 +604,51 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
 template <int S, int NWI, int NWJ, int BI, int BJ>
 void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
                     const double* sigb, int ng, int ngp, int nkb, const WList& wl, double2* chi,
-                    bool accumulate, int nb, int64_t nitems, hipStream_t s) {
+                    bool accumulate, int nb, int n_main, int parts, double2* ws, int grid,
+                    hipStream_t s) {
     const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
     auto fn = chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>;
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
-    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(nitems)), dim3(NWI * NWJ * 64), lds, s,
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(grid)), dim3(NWI * NWJ * 64), lds, s,
                        reinterpret_cast<const u32x4*>(sa), siga, reinterpret_cast<const u32x4*>(sb),
-                       sigb, ng, ngp, nkb, wl, chi, accumulate ? 1 : 0, nb, tile_order(nb, 4));
+                       sigb, ng, ngp, nkb, wl, chi, accumulate ? 1 : 0, nb, tile_order(nb, 4),
+                       n_main, parts, ws);
 }
 
-template <int S>
-void launch_sbf16_s(const uint32_t* sa, const double* siga, const uint32_t* sb, const double* sigb,
-                    int ng, int ngp, int nkb, const WList& wl, double2* chi, bool accumulate, int nb,
-                    int64_t nitems, hipStream_t s) {
-    // 8 waves of 32 x 32 (two waves per SIMD, 256 registers each)
-    launch_sbf16_t<S, 4, 2, 1, 1>(sa, siga, sb, sigb, ng, ngp, nkb, wl, chi, accumulate, nb, nitems,
-                                  s);
+// Workgroups of the S-slice contraction resident on one CU.
+template <int S, int NWI, int NWJ, int BI, int BJ>
+int sbf16_per_cu_t() {
+    const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
+    const void* fn = reinterpret_cast<const void*>(chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>);
+    GW_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(lds)));
+    int n = 0;
+    GW_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, NWI * NWJ * 64, lds));
+    return std::max(1, n);
+}
+
+// Workgroups of the S-slice contraction resident on the current device.
+int sbf16_slots(int S) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;  // (device, S) -> slots
+    int dev = 0;
+    GW_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    int& n = cache[{dev, S}];
+    if (n > 0) return n;
+    int per_cu = 1, cus = 0;
+    switch (S) {
+        case 2: per_cu = sbf16_per_cu_t<2, 4, 2, 1, 1>(); break;
+        case 3: per_cu = sbf16_per_cu_t<3, 4, 2, 1, 1>(); break;
+        case 4: per_cu = sbf16_per_cu_t<4, 4, 2, 1, 1>(); break;
+        case 5: per_cu = sbf16_per_cu_t<5, 4, 2, 1, 1>(); break;
+        default: per_cu = sbf16_per_cu_t<6, 4, 2, 1, 1>(); break;
+    }
+    GW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    n = per_cu * std::max(1, cus);
+    return n;
 }
 
 }  // namespace
@@ -619,24 +696,60 @@ SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const doub
     return d;
 }
 
+size_t sbf16_tail_bytes() {
+    int slots = 0;
+    for (int S = 2; S <= 6; ++S) slots = std::max(slots, sbf16_slots(S));
+    return static_cast<size_t>(slots) * kTI * kTJ * sizeof(double2);
+}
+
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
-                       hipStream_t s) {
+                       hipStream_t s, double2* tail_ws) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
     const SbDesc d = launch_sbf16_prep(S, m, kc, ng, delta, nz, wl, scratch, s);
     const int nb = ceil_div(ng, kTI);
     const int64_t nitems = 2 * (static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
                                 static_cast<int64_t>(wl.nf) * nb * nb);
-    ProfScope ps("chi0_split", s);
-    switch (S) {
-        case 2: launch_sbf16_s<2>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
-        case 3: launch_sbf16_s<3>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
-        case 4: launch_sbf16_s<4>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
-        case 5: launch_sbf16_s<5>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
-        default: launch_sbf16_s<6>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, nitems, s); break;
+    if (nitems >= (int64_t(1) << 30)) throw Error{-4, "too many chi tiles for one launch"};
+    // A last round of workgroups that fills at most half the chip is cut
+    // along the 128-pair blocks (as in launch_chi0_f64).
+    int n_main = static_cast<int>(nitems), parts = 1, n_tail = 0;
+    if (tail_ws) {
+        const int slots = sbf16_slots(S);
+        const int rem = static_cast<int>(nitems % slots);
+        const int pc = std::min(rem > 0 ? slots / rem : 0, d.nkb);
+        if (rem > 0 && 2 * rem <= slots && pc >= 2) {
+            n_tail = rem;
+            parts = pc;
+            n_main = static_cast<int>(nitems) - rem;
+        }
     }
-    GW_HIP_TRY(hipGetLastError());
+    const int grid = n_main + n_tail * parts;
+    {
+        ProfScope ps("chi0_split", s);
+        switch (S) {
+#define GW_SB_LAUNCH(SS)                                                                      \
+    case SS:                                                                                  \
+        launch_sbf16_t<SS, 4, 2, 1, 1>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, \
+                                       accumulate, nb, n_main, parts, tail_ws, grid, s);      \
+        break;
+            GW_SB_LAUNCH(2)
+            GW_SB_LAUNCH(3)
+            GW_SB_LAUNCH(4)
+            GW_SB_LAUNCH(5)
+            GW_SB_LAUNCH(6)
+#undef GW_SB_LAUNCH
+        }
+        GW_HIP_TRY(hipGetLastError());
+    }
+    if (n_tail > 0) {
+        ProfScope ps("chi0_split_tail", s);
+        hipLaunchKernelGGL(sbf16_tail_reduce_kernel, dim3(kTI * kTJ / 256, n_tail), dim3(256), 0,
+                           s, tail_ws, parts, n_main, wl, nb, tile_order(nb, 4), chi, ng,
+                           accumulate ? 1 : 0);
+        GW_HIP_TRY(hipGetLastError());
+    }
 }
 
 namespace {

@@ -439,15 +439,19 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     }
     // the autotuner's trials write one frequency plane here, never into chi
     const size_t off_tune = cv.take(tune ? ng * ng * sizeof(double2) : 0);
-    // partial sums of the FP64 contraction's last round of tiles
-    const size_t off_tail = cv.take(o.precision == GW_FP64 ? chi0_f64_tail_bytes() : 0);
+    // partial sums of the contraction's last round of tiles (FP64, split BF16)
+    const size_t off_tail = cv.take(o.precision == GW_FP64        ? chi0_f64_tail_bytes()
+                                    : o.precision == GW_SPLIT_BF16 ? sbf16_tail_bytes()
+                                                                   : 0);
     char* base = static_cast<char*>(scratch(cv.off, s));
     double2* mbuf[2] = {reinterpret_cast<double2*>(base + off_m[0]),
                         reinterpret_cast<double2*>(base + off_m[1])};
     double2* dbuf[2] = {reinterpret_cast<double2*>(base + off_d[0]),
                         reinterpret_cast<double2*>(base + off_d[1])};
     double2* t2 = reinterpret_cast<double2*>(base + off_t2);
-    double2* tail_ws = o.precision == GW_FP64 ? reinterpret_cast<double2*>(base + off_tail) : nullptr;
+    double2* tail_ws = o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16
+                           ? reinterpret_cast<double2*>(base + off_tail)
+                           : nullptr;
     const double2* z = reinterpret_cast<const double2*>(pr.z);
     std::vector<bool> herm(pr.nz);
     for (int w = 0; w < pr.nz; ++w)
@@ -495,7 +499,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
                 launch_chi0_f32(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
             else
                 launch_chi0_split(o.precision, o.n_slices, mbuf[b], chunks[k].kc, pr.ng, dbuf[b],
-                                  pr.nz, wl, chi, acc, base + off_sp, s);
+                                  pr.nz, wl, chi, acc, base + off_sp, s, tail_ws);
         }
         GW_HIP_TRY(hipEventRecord(ax.ev[3 + b], s));
     }

@@ -154,32 +154,39 @@ def test_chi0_precision_workload_grid_and_sphere(prec, ns, tol):
     assert rel_fro(got, ref) < tol, rel_fro(got, ref)
 
 
-def test_chi0_tail_round_split():
-    """Launches whose last round of workgroups is partial.  11 x 11 tiles of 64
-    (N_G = 691) over 1 Hermitian and 4 other frequencies are 550 items, 38 past
-    the 512 workgroups an MI355X holds at once: those tiles are cut into 13
-    pair ranges each and a second launch adds the ranges.  Accumulating, every
-    frequency takes all tiles (605 items, 93 cut into 5 ranges).  Two chunks of
-    200 pairs, so the second chunk's partial tiles add onto the first's.
-    Parity with the oracle and the same bits on a second run."""
+@pytest.mark.parametrize("prec,ns,chunk,tol,kernel,launches", [
+    ("fp64", 0, 200, FP64_TOL, "chi0_tail", 2),
+    ("split_bf16", 5, 400, 1e-10, "chi0_split_tail", 1),
+])
+def test_chi0_tail_round_split(prec, ns, chunk, tol, kernel, launches):
+    """Launches whose last round of workgroups is partial, N_G = 691 over 1
+    Hermitian and 4 other frequencies.  FP64 (tiles of 64, 512 workgroups
+    resident on an MI355X): 550 items, the last 38 cut into 13 pair ranges
+    each, reduced by a second launch; two chunks of 200 pairs, so the second
+    chunk's parts add onto the first's.  Split BF16 (128 x 64 tiles, 256
+    resident): 330 items, the last 74 cut into 3 ranges of 128-pair blocks;
+    one chunk of 400 pairs.  Accumulating, every frequency takes all tiles
+    (FP64: 605 items, 93 cut into 5; split: 360, 104 cut into 2).  Parity with
+    the oracle and the same bits on a second run."""
     zs = (0.4j, 0.1 + 0.01j, 0.5 + 0.02j, 0.9 + 0.005j, 1.3 + 0.01j)
-    p = gen.make_problem((16, 16, 16), 4, 100, r2=29, z=zs, seed=21, pair_chunk=200)
+    p = gen.make_problem((16, 16, 16), 4, 100, r2=29, z=zs, seed=21, pair_chunk=chunk)
     assert p.ng == 691, p.ng
     ref = _oracle_chi(p)
+    kw = dict(precision=prec, n_slices=ns)
     gw.profile_enable(True)
     gw.profile_reset()
     try:
-        chi = run_chi0(p)
-        n_tail, _ = gw.profile_read("chi0_tail")
+        chi = run_chi0(p, **kw)
+        n_tail, _ = gw.profile_read(kernel)
     finally:
         gw.profile_enable(False)
-    assert n_tail == 2  # one per chunk
-    assert rel_fro(chi, ref) < FP64_TOL
+    assert n_tail == launches
+    assert rel_fro(chi, ref) < tol, rel_fro(chi, ref)
     for w in range(len(zs)):
-        assert rel_fro(chi[w], ref[w]) < FP64_TOL
-    assert np.array_equal(run_chi0(p), chi)
+        assert rel_fro(chi[w], ref[w]) < tol
+    assert np.array_equal(run_chi0(p, **kw), chi)
     dp = to_dev(p)
     dp.chi = torch.full((len(zs), p.ng, p.ng), 0.25 - 1.0j, dtype=torch.complex128, device=device())
-    gw.gw_chi0(dp, flags=gw.GW_FLAG_ACCUMULATE, pair_chunk=200)
+    gw.gw_chi0(dp, flags=gw.GW_FLAG_ACCUMULATE, pair_chunk=chunk, **kw)
     torch.cuda.synchronize()
-    assert rel_fro(dp.chi.cpu().numpy() - (0.25 - 1.0j), ref) < FP64_TOL
+    assert rel_fro(dp.chi.cpu().numpy() - (0.25 - 1.0j), ref) < tol
