@@ -35,7 +35,7 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (MFMA and vector)
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "chi0_f64_kernel_48cube_61440pairs_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_23018_amd", "csrc", f)
-                  for f in ("chi0.hip", "common.hpp")]
+                  for f in ("chi0.hip", "common.hpp", "items.hpp")]
 
 
 def kernel_src_sha() -> str:
