@@ -186,74 +186,92 @@ __global__ __launch_bounds__(256) void de_reduce_kernel(const double* __restrict
     }
 }
 
-// U[k][j1][d] = sum_{G in disc d} e^{-2 pi i k1(G) j1/N1} gm[k][G]
-__global__ __launch_bounds__(256) void bx_kernel(const double2* __restrict__ gm, int ng, int n1,
-                                                 int n23, const double2* __restrict__ root1,
-                                                 const int* __restrict__ g_k1,
-                                                 const int* __restrict__ disc_ptr,
-                                                 const int* __restrict__ disc_g, int64_t pair0,
-                                                 double2* __restrict__ u) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n1 * n23) return;
-    const int64_t k = pair0 + blockIdx.y;
-    const int j1 = idx / n23, d = idx - j1 * n23;
-    double re = 0.0, im = 0.0;
+// The inverse of the pruned transform, g_rho(r) = dV sum_G e^{-i G.r} g_M(G),
+// taken as the forward stages transposed, on FP64 MFMA 16x16x4 with twiddle
+// operands read in lane order from the plan (A lane l: [row l%16][k l/16];
+// B lane l: [k l/16][col l%16]; D element t of lane l: [4t + l/16][l%16]).
+
+// Stage x, one workgroup per pair: U[k][j1][d] = sum_k1 conj(e^{2 pi i k1 j1/N1})
+// B[k1][d], with B[k1][d] = g_M[k][G] for the G at (k1, disc d), else 0.  The
+// 4 waves take (16 j1) x (16 d) output blocks in turn.
+__global__ __launch_bounds__(256) void bwd_x_kernel(const double2* __restrict__ gm, int ng, int n1,
+                                                    int n1b, int ks1, int n23, int n23p,
+                                                    const double2* __restrict__ w1inv,
+                                                    const int* __restrict__ gmap,
+                                                    double2* __restrict__ u) {
+    const int64_t k = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
     const double2* src = gm + k * ng;
-    for (int e = disc_ptr[d]; e < disc_ptr[d + 1]; ++e) {
-        const int g = disc_g[e];
-        const double2 w = root1[(g_k1[g] * j1) % n1];
-        const double2 x = src[g];
-        re += w.x * x.x + w.y * x.y;  // conj(w) * x
-        im += w.x * x.y - w.y * x.x;
+    double2* dst = u + k * n1 * n23;
+    const int ndb = n23p >> 4;
+    for (int tile = wave; tile < n1b * ndb; tile += 4) {
+        const int rb = tile / ndb, db = tile - rb * ndb;
+        dbl4 ar = zero4(), ai = zero4();
+        for (int s = 0; s < ks1; ++s) {
+            const double2 a = w1inv[(rb * ks1 + s) * 64 + lane];
+            const int g = gmap[(4 * s + kq) * n23p + db * 16 + row];
+            const double2 b = g >= 0 ? src[g] : make_double2(0.0, 0.0);
+            cmfma(ar, ai, a.x, a.y, b.x, b.y);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j1 = rb * 16 + 4 * t + kq, d = db * 16 + row;
+            if (j1 < n1 && d < n23) dst[j1 * n23 + d] = make_double2(ar[t], ai[t]);
+        }
     }
-    u[(k * n1 + j1) * n23 + d] = make_double2(re, im);
 }
 
-// V[k][j1][j2][k3i] = sum_{k2i} e^{-2 pi i k2 j2/N2} U[k][j1][disc(k2i, k3i)]
-__global__ __launch_bounds__(256) void by_kernel(const double2* __restrict__ u, int n1, int n2,
-                                                 int n23, int m2, int m3, int bw3,
-                                                 const int* __restrict__ boxmap,
-                                                 const int* __restrict__ k2val,
-                                                 const double2* __restrict__ root2, int64_t pair0,
-                                                 double2* __restrict__ vout) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= static_cast<int64_t>(n1) * n2 * m3) return;
-    const int64_t k = pair0 + blockIdx.y;
-    const int k3i = static_cast<int>(idx % m3);
-    const int j2 = static_cast<int>((idx / m3) % n2);
-    const int j1 = static_cast<int>(idx / (static_cast<int64_t>(m3) * n2));
-    const double2* src = u + (k * n1 + j1) * n23;
-    double re = 0.0, im = 0.0;
-    for (int k2i = 0; k2i < m2; ++k2i) {
-        const int d = boxmap[k2i * bw3 + k3i];
-        if (d < 0) continue;
-        const double2 w = root2[(k2val[k2i] * j2) % n2];
-        const double2 x = src[d];
-        re += w.x * x.x + w.y * x.y;
-        im += w.x * x.y - w.y * x.x;
+// Stages z and y, one workgroup per pair, wave w taking the planes j1 = w,
+// w + 4, ...  Per plane and 16-wide block of j3:
+//   T[k2][j3]     = sum_k3 Ubox[k2][k3] conj(e^{2 pi i k3 j3/N3})
+//                   (Ubox = this plane's U placed on the (k2, k3) box)
+//   g_rho[j2][j3] = dV sum_k2 conj(e^{2 pi i k2 j2/N2}) T[k2][j3]
+// The accumulators of T (rows k2 = 4t + l/16) are the B operands of the
+// second product as they stand.
+template <int NB2>
+__global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__ u, int n1, int n2,
+                                                     int n3, int n23, int nb3, int nj2, int nj3,
+                                                     const double2* __restrict__ w2inv,
+                                                     const double2* __restrict__ w3inv,
+                                                     const int* __restrict__ boxmap, int64_t nr,
+                                                     double dv, double2* __restrict__ grho) {
+    const int64_t k = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+    const int bw3 = nb3 * 16, ks3 = nb3 * 4;
+    constexpr int KS2 = NB2 * 4;
+    for (int j1 = wave; j1 < n1; j1 += 4) {
+        const double2* urow = u + (k * n1 + j1) * n23;
+        double2* out = grho + k * nr + static_cast<int64_t>(j1) * n2 * n3;
+        for (int nb = 0; nb < nj3; ++nb) {
+            dbl4 tr[NB2], ti[NB2];
+#pragma unroll
+            for (int b2 = 0; b2 < NB2; ++b2) tr[b2] = ti[b2] = zero4();
+            for (int s = 0; s < ks3; ++s) {
+                const double2 b = w3inv[(s * nj3 + nb) * 64 + lane];
+#pragma unroll
+                for (int b2 = 0; b2 < NB2; ++b2) {
+                    const int d = boxmap[(b2 * 16 + row) * bw3 + 4 * s + kq];
+                    const double2 a = d >= 0 ? urow[d] : make_double2(0.0, 0.0);
+                    cmfma(tr[b2], ti[b2], a.x, a.y, b.x, b.y);
+                }
+            }
+            for (int rb = 0; rb < nj2; ++rb) {
+                dbl4 gr = zero4(), gi = zero4();
+#pragma unroll
+                for (int b2 = 0; b2 < NB2; ++b2)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const double2 a = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
+                        cmfma(gr, gi, a.x, a.y, tr[b2][t], ti[b2][t]);
+                    }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int j2 = rb * 16 + 4 * t + kq, j3 = nb * 16 + row;
+                    if (j2 < n2 && j3 < n3) out[j2 * n3 + j3] = make_double2(dv * gr[t], dv * gi[t]);
+                }
+            }
+        }
     }
-    vout[(k * n1 * n2 + static_cast<int64_t>(j1) * n2 + j2) * m3 + k3i] = make_double2(re, im);
-}
-
-// g_rho[k][r] = dV * sum_{k3i} e^{-2 pi i k3 j3/N3} V[k][j1][j2][k3i]
-__global__ __launch_bounds__(256) void bz_kernel(const double2* __restrict__ vin, int64_t nr,
-                                                 int n3, int m3, const int* __restrict__ k3val,
-                                                 const double2* __restrict__ root3, double dv,
-                                                 int64_t pair0, double2* __restrict__ grho) {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    const int64_t k = pair0 + blockIdx.y;
-    const int j3 = static_cast<int>(r % n3);
-    const int64_t j12 = r / n3;
-    const double2* src = vin + (k * (nr / n3) + j12) * m3;
-    double re = 0.0, im = 0.0;
-    for (int k3i = 0; k3i < m3; ++k3i) {
-        const double2 w = root3[(k3val[k3i] * j3) % n3];
-        const double2 x = src[k3i];
-        re += w.x * x.x + w.y * x.y;
-        im += w.x * x.y - w.y * x.x;
-    }
-    grho[k * nr + r] = make_double2(dv * re, dv * im);
 }
 
 // grad_psi_c[c0 + cl] += sum_vl psi_v[v0 + vl] * g_rho[vl*cw + cl]
@@ -340,9 +358,8 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     const bool want_e = grad_e_v || grad_e_c;
     if (npairs == 0 || (!want_psi && !want_e)) return;
 
-    // chunk rectangle, capped so that the per-pair grids stay within 2 GiB
-    const int64_t per_pair = std::max<int64_t>(
-        nr, static_cast<int64_t>(n1) * n2 * plan.m3) * static_cast<int64_t>(sizeof(double2));
+    // chunk rectangle, capped so that the per-pair grids g_rho stay within 2 GiB
+    const int64_t per_pair = nr * static_cast<int64_t>(sizeof(double2));
     const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
     const int chunk = static_cast<int>(std::min<int64_t>(pair_chunk, cap));
     // 4 valence bands per MTXEL tile: conduction width capped at chunk / 4
@@ -359,7 +376,6 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     const size_t o_gm = cv.take(kmax * ng * sizeof(double2));
     const size_t o_q = cv.take(kmax * nz * nparts * sizeof(double2));
     const size_t o_de = cv.take(kmax * sizeof(double));
-    const size_t o_v = cv.take(want_psi ? kmax * n1 * n2 * plan.m3 * sizeof(double2) : 0);
     const size_t o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
     char* base = static_cast<char*>(get_scratch(cv.off));
     double2* mbuf = reinterpret_cast<double2*>(base + o_m);
@@ -369,7 +385,6 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     double2* gm = reinterpret_cast<double2*>(base + o_gm);
     double2* qpart = reinterpret_cast<double2*>(base + o_q);
     double* de = reinterpret_cast<double*>(base + o_de);
-    double2* vbuf = reinterpret_cast<double2*>(base + o_v);
     double2* grho = reinterpret_cast<double2*>(base + o_rho);
     const double2* z = reinterpret_cast<const double2*>(p.z);
     const double2* psi_v = reinterpret_cast<const double2*>(p.psi_v);
@@ -405,48 +420,57 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                 GW_HIP_TRY(hipGetLastError());
             }
             if (want_e) {
-                hipLaunchKernelGGL(de_kernel, dim3(static_cast<unsigned>(ceil_div64(kc, 256))),
-                                   dim3(256), 0, s, qpart, nparts, nz, kc, ddbuf, spin, de);
-                GW_HIP_TRY(hipGetLastError());
+                {
+                    ProfScope ps("bwd_de", s);
+                    hipLaunchKernelGGL(de_kernel, dim3(static_cast<unsigned>(ceil_div64(kc, 256))),
+                                       dim3(256), 0, s, qpart, nparts, nz, kc, ddbuf, spin, de);
+                    GW_HIP_TRY(hipGetLastError());
+                }
+                ProfScope ps("bwd_de_reduce", s);
                 hipLaunchKernelGGL(de_reduce_kernel, dim3(ceil_div(std::max(vcount, cw), 256)),
                                    dim3(256), 0, s, de, vcount, cw, v0, c0, grad_e_v, grad_e_c);
                 GW_HIP_TRY(hipGetLastError());
             }
             if (!want_psi) continue;
-            for (int64_t k0 = 0; k0 < kc; k0 += kYMax) {
-                const unsigned kb = static_cast<unsigned>(std::min<int64_t>(kYMax, kc - k0));
-                ProfScope ps("bwd_transform", s);
-                hipLaunchKernelGGL(bx_kernel, dim3(ceil_div(n1 * plan.n23, 256), kb), dim3(256), 0,
-                                   s, gm, ng, n1, plan.n23, plan.root1, plan.g_k1, plan.disc_ptr,
-                                   plan.disc_g, k0, t2);
+            {
+                ProfScope ps("bwd_x", s);
+                hipLaunchKernelGGL(bwd_x_kernel, dim3(static_cast<unsigned>(kc)), dim3(256), 0, s,
+                                   gm, ng, n1, plan.n1p16 / 16, plan.nb1 * 4, plan.n23, plan.n23p,
+                                   plan.w1inv, plan.gmap, t2);
                 GW_HIP_TRY(hipGetLastError());
-                hipLaunchKernelGGL(by_kernel,
-                                   dim3(static_cast<unsigned>(ceil_div64(
-                                            static_cast<int64_t>(n1) * n2 * plan.m3, 256)),
-                                        kb),
-                                   dim3(256), 0, s, t2, n1, n2, plan.n23, plan.m2, plan.m3,
-                                   plan.nb3 * 16, plan.boxmap, plan.k2val, plan.root2, k0, vbuf);
-                GW_HIP_TRY(hipGetLastError());
-                hipLaunchKernelGGL(bz_kernel, dim3(static_cast<unsigned>(ceil_div64(nr, 256)), kb),
-                                   dim3(256), 0, s, vbuf, nr, n3, plan.m3, plan.k3val, plan.root3,
-                                   dv, k0, grho);
+            }
+            {
+                ProfScope ps("bwd_yz", s);
+                const int nj2 = plan.n2p / 16, nj3 = plan.n3p / 16;
+                auto yz = plan.nb2 == 1   ? bwd_yz_kernel<1>
+                          : plan.nb2 == 2 ? bwd_yz_kernel<2>
+                          : plan.nb2 == 3 ? bwd_yz_kernel<3>
+                                          : bwd_yz_kernel<4>;
+                hipLaunchKernelGGL(yz, dim3(static_cast<unsigned>(kc)), dim3(256), 0, s, t2, n1, n2,
+                                   n3, plan.n23, plan.nb3, nj2, nj3, plan.w2inv, plan.w3inv,
+                                   plan.boxmap, nr, dv, grho);
                 GW_HIP_TRY(hipGetLastError());
             }
             if (grad_psi_c)
-                for (int cl0 = 0; cl0 < cw; cl0 += kYMax)
+                for (int cl0 = 0; cl0 < cw; cl0 += kYMax) {
+                    ProfScope ps("bwd_reduce_c", s);
                     hipLaunchKernelGGL(reduce_c_kernel,
                                        dim3(static_cast<unsigned>(ceil_div64(nr, 256)),
                                             std::min(kYMax, cw - cl0)),
                                        dim3(256), 0, s, grho, psi_v, nr, v0, c0, cw, vcount, cl0,
                                        grad_psi_c);
+                    GW_HIP_TRY(hipGetLastError());
+                }
             if (grad_psi_v)
-                for (int vl0 = 0; vl0 < vcount; vl0 += kYMax)
+                for (int vl0 = 0; vl0 < vcount; vl0 += kYMax) {
+                    ProfScope ps("bwd_reduce_v", s);
                     hipLaunchKernelGGL(reduce_v_kernel,
                                        dim3(static_cast<unsigned>(ceil_div64(nr, 256)),
                                             std::min(kYMax, vcount - vl0)),
                                        dim3(256), 0, s, grho, psi_c, nr, v0, c0, cw, vl0,
                                        grad_psi_v);
-            GW_HIP_TRY(hipGetLastError());
+                    GW_HIP_TRY(hipGetLastError());
+                }
         }
     }
 }

@@ -386,7 +386,7 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
     for (int i = 0; i < p->m2; ++i) i2[l2[i]] = i;
     for (int i = 0; i < p->m3; ++i) i3[l3[i]] = i;
     std::vector<int> box(static_cast<size_t>(bw2) * bw3, -1);
-    std::vector<int> g_disc(ng), g_k1(ng);
+    std::vector<int> g_disc(ng);
     int nd = 0;
     // disc numbered in (k2 index, k3 index) order
     std::set<std::pair<int, int>> disc;
@@ -399,7 +399,6 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
     std::vector<int> gmap(static_cast<size_t>(p->nb1) * 16 * p->n23p, -1);
     for (int i = 0; i < ng; ++i) {
         g_disc[i] = box[i2[k2[i]] * bw3 + i3[k3[i]]];
-        g_k1[i] = k1[i];
         gmap[static_cast<size_t>(i1[k1[i]]) * p->n23p + g_disc[i]] = i;
     }
     const int q1 = p->n1p / 4;
@@ -436,32 +435,53 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
                             ? host_root(static_cast<int64_t>(l2[kk]) * j2, n[1])
                             : make_double2(0.0, 0.0);
                 }
-    std::vector<double2> r1(n[0]), r2(n[1]), r3(n[2]);
-    for (int t = 0; t < n[0]; ++t) r1[t] = host_root(t, n[0]);
-    for (int t = 0; t < n[1]; ++t) r2[t] = host_root(t, n[1]);
-    for (int t = 0; t < n[2]; ++t) r3[t] = host_root(t, n[2]);
-    std::vector<int> dptr(nd + 1, 0), dg(ng);
-    for (int i = 0; i < ng; ++i) dptr[g_disc[i] + 1]++;
-    for (int d = 0; d < nd; ++d) dptr[d + 1] += dptr[d];
-    {
-        std::vector<int> fill(dptr.begin(), dptr.end() - 1);
-        for (int i = 0; i < ng; ++i) dg[fill[g_disc[i]]++] = i;
-    }
+    // adjoint tables, in the lane layouts of the transposed stages:
+    //   x: U[j1][d]   = sum_k1 conj(e^{2 pi i k1 j1/N1}) B[k1][d]   (A = W1inv[j1][k1])
+    //   z: T[k2][j3]  = sum_k3 Ubox[k2][k3] conj(e^{2 pi i k3 j3/N3}) (B = W3inv[k3][j3])
+    //   y: R[j2][j3]  = sum_k2 conj(e^{2 pi i k2 j2/N2}) T[k2][j3]   (A = W2inv[j2][k2])
+    p->n1p16 = ceil_div(n[0], 16) * 16;
+    auto conj_root = [](int64_t num, int64_t den) {
+        const double2 w = host_root(num, den);
+        return make_double2(w.x, -w.y);
+    };
+    const int ks1 = p->nb1 * 4, ks2 = p->nb2 * 4, ks3 = p->nb3 * 4;
+    std::vector<double2> w1i(static_cast<size_t>(p->n1p16 / 16) * ks1 * 64);
+    for (int rb = 0; rb < p->n1p16 / 16; ++rb)
+        for (int s = 0; s < ks1; ++s)
+            for (int l = 0; l < 64; ++l) {
+                const int j1 = rb * 16 + (l & 15), kk = 4 * s + (l >> 4);
+                w1i[(static_cast<size_t>(rb) * ks1 + s) * 64 + l] =
+                    (j1 < n[0] && kk < p->m1) ? conj_root(static_cast<int64_t>(l1[kk]) * j1, n[0])
+                                             : make_double2(0.0, 0.0);
+            }
+    std::vector<double2> w2i(static_cast<size_t>(nrb1) * ks2 * 64);
+    for (int rb = 0; rb < nrb1; ++rb)
+        for (int s = 0; s < ks2; ++s)
+            for (int l = 0; l < 64; ++l) {
+                const int j2 = rb * 16 + (l & 15), kk = 4 * s + (l >> 4);
+                w2i[(static_cast<size_t>(rb) * ks2 + s) * 64 + l] =
+                    (j2 < n[1] && kk < p->m2) ? conj_root(static_cast<int64_t>(l2[kk]) * j2, n[1])
+                                             : make_double2(0.0, 0.0);
+            }
+    const int nj3 = p->n3p / 16;
+    std::vector<double2> w3i(static_cast<size_t>(ks3) * nj3 * 64);
+    for (int s = 0; s < ks3; ++s)
+        for (int nb = 0; nb < nj3; ++nb)
+            for (int l = 0; l < 64; ++l) {
+                const int kk = 4 * s + (l >> 4), j3 = nb * 16 + (l & 15);
+                w3i[(static_cast<size_t>(s) * nj3 + nb) * 64 + l] =
+                    (j3 < n[2] && kk < p->m3) ? conj_root(static_cast<int64_t>(l3[kk]) * j3, n[2])
+                                             : make_double2(0.0, 0.0);
+            }
 
     p->w1tab = upload(w1);
     p->gmap = upload(gmap);
     p->w3tab = upload(w3);
     p->w2tab = upload(w2);
     p->boxmap = upload(box);
-    p->g_k1 = upload(g_k1);
-    p->g_disc = upload(g_disc);
-    p->root1 = upload(r1);
-    p->root2 = upload(r2);
-    p->root3 = upload(r3);
-    p->k2val = upload(l2);
-    p->k3val = upload(l3);
-    p->disc_ptr = upload(dptr);
-    p->disc_g = upload(dg);
+    p->w1inv = upload(w1i);
+    p->w2inv = upload(w2i);
+    p->w3inv = upload(w3i);
     return p;
 }
 
@@ -473,17 +493,11 @@ void MtxelPlan::release() {
     (void)hipFree(w3tab);
     (void)hipFree(w2tab);
     (void)hipFree(boxmap);
-    (void)hipFree(g_k1);
-    (void)hipFree(g_disc);
-    (void)hipFree(root1);
-    (void)hipFree(root2);
-    (void)hipFree(root3);
-    (void)hipFree(k2val);
-    (void)hipFree(k3val);
-    (void)hipFree(disc_ptr);
-    (void)hipFree(disc_g);
-    w1tab = w3tab = w2tab = root1 = root2 = root3 = nullptr;
-    gmap = boxmap = g_k1 = g_disc = k2val = k3val = disc_ptr = disc_g = nullptr;
+    (void)hipFree(w1inv);
+    (void)hipFree(w2inv);
+    (void)hipFree(w3inv);
+    w1tab = w3tab = w2tab = w1inv = w2inv = w3inv = nullptr;
+    gmap = boxmap = nullptr;
 }
 
 MtxelPlan* get_plan(const int n[3], const int32_t* gvec, int ng) {

@@ -52,16 +52,11 @@ struct MtxelPlan {
     double2* w3tab = nullptr;   // [n3p/4][nb3][64]      stage-z MFMA B operand, lane layout
     double2* w2tab = nullptr;   // [n2p/16][4][nb2][64]  stage-y MFMA A operand, lane layout
     int* boxmap = nullptr;      // [nb2*16][nb3*16] -> disc index or -1
-    int* g_k1 = nullptr;        // [ng] g1 mod N1
-    int* g_disc = nullptr;      // [ng] disc index of G
-    double2* root1 = nullptr;   // [N1] e^{+2 pi i t/N1}
-    // used by the adjoint
-    double2* root2 = nullptr;   // [N2] e^{+2 pi i t/N2}
-    double2* root3 = nullptr;   // [N3] e^{+2 pi i t/N3}
-    int* k2val = nullptr;       // [m2] k2 value of each k2 index
-    int* k3val = nullptr;       // [m3] k3 value of each k3 index
-    int* disc_ptr = nullptr;    // [n23+1] CSR over the G list grouped by disc
-    int* disc_g = nullptr;      // [ng] G indices, grouped by disc
+    // used by the adjoint (the transposed stages, conjugate twiddles)
+    int n1p16 = 0;              // N1 rounded up to 16
+    double2* w1inv = nullptr;   // [n1p16/16][nb1*4][64]  adjoint stage-x MFMA A operand
+    double2* w2inv = nullptr;   // [n2p/16][nb2*4][64]    adjoint stage-y MFMA A operand
+    double2* w3inv = nullptr;   // [nb3*4][n3p/16][64]    adjoint stage-z MFMA B operand
 
     void release();
 };
