@@ -42,41 +42,51 @@ __global__ __launch_bounds__(256) void ddelta_kernel(const double* __restrict__ 
     }
 }
 
-// P1 = M W and P2 = M W^H for one 64 (pairs) x 64 (G) tile; fused epilogue.
-__global__ __launch_bounds__(256) void bwd_gm_kernel(const double2* __restrict__ m, int64_t kc,
+// P1 = M W and P2 = M W^H for one TM (pairs) x 64 (G) tile; fused epilogue.
+// 4 waves of (TM/2) x 32.  TM = 32 keeps three workgroups on a CU and cuts
+// the last partial round of a launch to a third of what 64 x 64 tiles leave.
+template <int TM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void bwd_gm_kernel(const double2* __restrict__ m, int64_t kc,
                                                      int ng, const double2* __restrict__ w,
                                                      const double2* __restrict__ delta,
                                                      double2* __restrict__ gm,
                                                      double2* __restrict__ qpart, int mode) {
-    __shared__ double2 s_a[64][17];
+    constexpr int BX = TM / 32, NA = TM * 16 / 256;
+    __shared__ double2 s_a[TM][17];
     __shared__ double2 s_b1[16][64];
     __shared__ double2 s_b2[16][64];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
     const int wi = wave >> 1, wj = wave & 1;
-    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * 64;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * TM;
     const int i0 = blockIdx.x * 64;
 
-    dbl4 p1r[2][2], p1i[2][2], p2r[2][2], p2i[2][2];
+    dbl4 p1r[BX][2], p1i[BX][2], p2r[BX][2], p2i[BX][2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < BX; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) p1r[x][y] = p1i[x][y] = p2r[x][y] = p2i[x][y] = zero4();
 
-    for (int j0 = 0; j0 < ng; j0 += 16) {
+    // Stage j0 (16 G) of the three operands: fetched into registers one stage
+    // ahead, so that the global loads of stage j0 + 16 run under the MFMAs of
+    // stage j0.
+    double2 ra[NA], rb1[4], rb2[4];
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = e >> 4, jj = e & 15;
+            const int64_t k = k0 + rr;
+            ra[u] = (k < kc && j0 + jj < ng) ? m[k * ng + j0 + jj] : make_double2(0.0, 0.0);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = tid + 256 * u;
             {
-                const int rr = e >> 4, jj = e & 15;
-                const int64_t k = k0 + rr;
-                s_a[rr][jj] = (k < kc && j0 + jj < ng) ? m[k * ng + j0 + jj] : make_double2(0.0, 0.0);
-            }
-            {
                 const int jj = e >> 6, ii = e & 63;
-                s_b1[jj][ii] = (j0 + jj < ng && i0 + ii < ng)
-                                   ? w[static_cast<int64_t>(j0 + jj) * ng + i0 + ii]
-                                   : make_double2(0.0, 0.0);
+                rb1[u] = (j0 + jj < ng && i0 + ii < ng)
+                             ? w[static_cast<int64_t>(j0 + jj) * ng + i0 + ii]
+                             : make_double2(0.0, 0.0);
             }
             {
                 const int ii = e >> 4, jj = e & 15;
@@ -85,35 +95,53 @@ __global__ __launch_bounds__(256) void bwd_gm_kernel(const double2* __restrict__
                     const double2 x = w[static_cast<int64_t>(i0 + ii) * ng + j0 + jj];
                     val = make_double2(x.x, -x.y);
                 }
-                s_b2[jj][ii] = val;
+                rb2[u] = val;
             }
         }
+    };
+    fetch(0);
+    for (int j0 = 0; j0 < ng; j0 += 16) {
+        __syncthreads();  // every wave is done with the previous stage
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + 256 * u;
+            s_a[e >> 4][e & 15] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            s_b1[e >> 6][e & 63] = rb1[u];
+            s_b2[e & 15][e >> 4] = rb2[u];
+        }
         __syncthreads();
+        if (j0 + 16 < ng) fetch(j0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            double2 a[2], b1[2], b2[2];
+            double2 a[BX], b1[2], b2[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                a[x] = s_a[wi * 32 + x * 16 + row][s * 4 + kq];
-                b1[x] = s_b1[s * 4 + kq][wj * 32 + x * 16 + row];
-                b2[x] = s_b2[s * 4 + kq][wj * 32 + x * 16 + row];
+            for (int x = 0; x < BX; ++x) a[x] = s_a[wi * (TM / 2) + x * 16 + row][s * 4 + kq];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                b1[y] = s_b1[s * 4 + kq][wj * 32 + y * 16 + row];
+                b2[y] = s_b2[s * 4 + kq][wj * 32 + y * 16 + row];
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < BX; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y) {
                     cmfma(p1r[x][y], p1i[x][y], a[x].x, a[x].y, b1[y].x, b1[y].y);
                     cmfma(p2r[x][y], p2i[x][y], a[x].x, a[x].y, b2[y].x, b2[y].y);
                 }
         }
-        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
     }
 
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < BX; ++x)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int64_t r = k0 + wi * 32 + x * 16 + 4 * t + kq;
+            const int64_t r = k0 + wi * (TM / 2) + x * 16 + 4 * t + kq;
             const bool rok = r < kc;
             const double2 d = rok ? delta[r] : make_double2(0.0, 0.0);
             double qre = 0.0, qim = 0.0;
@@ -412,8 +440,8 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             }
             for (int w = 0; w < nz; ++w) {
                 ProfScope ps("bwd_gm", s);
-                hipLaunchKernelGGL(bwd_gm_kernel,
-                                   dim3(ceil_div(ng, 64), static_cast<unsigned>(ceil_div64(kc, 64))),
+                hipLaunchKernelGGL(bwd_gm_kernel<32>,
+                                   dim3(ceil_div(ng, 64), static_cast<unsigned>(ceil_div64(kc, 32))),
                                    dim3(256), 0, s, mbuf, kc, ng,
                                    grad_chi + static_cast<int64_t>(w) * ng * ng, dbuf + w * kc, gm,
                                    qpart + static_cast<int64_t>(w) * nparts * kc, w > 0 ? 1 : 0);
