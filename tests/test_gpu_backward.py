@@ -115,3 +115,36 @@ def test_differentiation_workload_full_size():
     # derivative of a group
     rel = {k: worst[k] / scale[k] for k in worst}
     assert all(v < 2e-6 for v in rel.values()), rel
+
+
+def _ellipsoid(semi):
+    """Miller indices inside an axis-aligned ellipsoid with the given semi-axes."""
+    r = [np.arange(-int(a), int(a) + 1) for a in semi]
+    g = np.stack(np.meshgrid(*r, indexing="ij"), -1).reshape(-1, 3)
+    keep = np.sum((g / np.asarray(semi, float)) ** 2, axis=1) <= 1.0
+    return np.ascontiguousarray(g[keep], dtype=np.int32)
+
+
+@pytest.mark.parametrize("n,semi", [
+    ((8, 44, 14), (2.5, 20.5, 5.5)),    # 41 k2 values: three 16-wide blocks on y
+    ((12, 10, 64), (4.5, 3.5, 30.5)),   # 61 k3 values: four blocks on z, N3 = 64
+    ((40, 12, 12), (19.5, 4.5, 4.5)),   # 39 k1 values, N1 = 40: three row blocks on x
+])
+def test_backward_wide_g_lists(n, semi):
+    """G lists spanning several 16-wide blocks along one axis (the adjoint's
+    transposed stages then run several k-blocks and output blocks), against
+    the oracle adjoint; the forward chi0 of the same problem too."""
+    gvec = _ellipsoid(semi)
+    p = gen.make_problem(n, 2, 5, gvec=gvec, z=(0.2j, 0.5 + 0.01j), seed=31, pair_chunk=7)
+    rng = np.random.default_rng(6)
+    w = _herm(rng, len(p.z), p.ng)
+    dp = to_dev(p)
+    chi = gw.gw_chi0(dp, pair_chunk=7).cpu().numpy()
+    ref_chi = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                          spin=p.spin, pair_chunk=7)
+    assert rel_fro(chi, ref_chi) < FP64_TOL
+    got = gw.gw_chi0_backward(dp, torch.from_numpy(w).to(device()), pair_chunk=7)
+    ref = oracle.chi0_backward(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, w,
+                               spin=p.spin, pair_chunk=7)
+    for g, r in zip(got, ref):
+        assert rel_fro(g.cpu().numpy(), r) < FP64_TOL, rel_fro(g.cpu().numpy(), r)
