@@ -207,7 +207,7 @@ int32_t gw_abi_version(void);
  * "mtxel_x", "delta", "chi0_f64", "chi0_tail", "chi0_f64_batched",
  * "split_prep", "chi0_split", "chi0_split_tail", "chi0_split_batched",
  * "chi0_f32", "mirror", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x", "bwd_yz",
- * "bwd_reduce_c", "bwd_reduce_v").
+ * "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v").
  * gw_profile_read waits for the recorded events of `kernel` and returns the
  * number of launches and the summed duration in milliseconds (0 and 0.0 for
  * an unknown name).  gw_profile_reset forgets every record.  Timing adds two

@@ -343,6 +343,71 @@ __global__ __launch_bounds__(256) void reduce_v_kernel(const double2* __restrict
     *dst = make_double2(o.x + re, o.y + im);
 }
 
+constexpr int kFuseV = 8;   // valence bands of a chunk the fused band reduction holds in registers
+constexpr int kFuseC = 16;  // conduction bands per thread of the fused band reduction
+
+// Both band reductions in one pass over g_rho, for chunks of at most kFuseV
+// valence bands: thread (r, conduction block cb) adds sum_vl psi_v g_rho to
+// grad_psi_c of the block's kFuseC conduction bands, and writes the block's
+// share of sum_cl psi_c conj(g_rho) for every valence band to vpart[cb][vl][r]
+// (added up by vpart_reduce_kernel).  gpc or vpart may be null.
+template <int VB>
+__global__ __launch_bounds__(256) void reduce_cv_kernel(const double2* __restrict__ grho,
+                                                        const double2* __restrict__ psi_v,
+                                                        const double2* __restrict__ psi_c,
+                                                        int64_t nr, int v0, int c0, int cw,
+                                                        double2* __restrict__ gpc,
+                                                        double2* __restrict__ vpart) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int cb = blockIdx.y, cl0 = cb * kFuseC, cl1 = min(cw, cl0 + kFuseC);
+    double2 pv[VB], av[VB];
+#pragma unroll
+    for (int vl = 0; vl < VB; ++vl) {
+        pv[vl] = psi_v[static_cast<int64_t>(v0 + vl) * nr + r];
+        av[vl] = make_double2(0.0, 0.0);
+    }
+    for (int cl = cl0; cl < cl1; ++cl) {
+        const double2 pc = psi_c[static_cast<int64_t>(c0 + cl) * nr + r];
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int vl = 0; vl < VB; ++vl) {
+            const double2 g = grho[(static_cast<int64_t>(vl) * cw + cl) * nr + r];
+            re += pv[vl].x * g.x - pv[vl].y * g.y;
+            im += pv[vl].x * g.y + pv[vl].y * g.x;
+            av[vl].x += pc.x * g.x + pc.y * g.y;  // pc * conj(g)
+            av[vl].y += pc.y * g.x - pc.x * g.y;
+        }
+        if (gpc) {
+            double2* dst = gpc + static_cast<int64_t>(c0 + cl) * nr + r;
+            const double2 o = *dst;
+            *dst = make_double2(o.x + re, o.y + im);
+        }
+    }
+    if (vpart)
+#pragma unroll
+        for (int vl = 0; vl < VB; ++vl)
+            vpart[(static_cast<int64_t>(cb) * VB + vl) * nr + r] = av[vl];
+}
+
+// grad_psi_v[v0 + vl][r] += sum_cb vpart[cb][vl][r], in block order.
+__global__ __launch_bounds__(256) void vpart_reduce_kernel(const double2* __restrict__ vpart,
+                                                           int ncb, int vb, int64_t nr, int v0,
+                                                           double2* __restrict__ gpv) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const int vl = blockIdx.y;
+    double re = 0.0, im = 0.0;
+    for (int cb = 0; cb < ncb; ++cb) {
+        const double2 x = vpart[(static_cast<int64_t>(cb) * vb + vl) * nr + r];
+        re += x.x;
+        im += x.y;
+    }
+    double2* dst = gpv + static_cast<int64_t>(v0 + vl) * nr + r;
+    const double2 o = *dst;
+    *dst = make_double2(o.x + re, o.y + im);
+}
+
 __global__ __launch_bounds__(256) void fill_zero_f64_kernel(double* __restrict__ p, int64_t n) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -405,6 +470,12 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     const size_t o_q = cv.take(kmax * nz * nparts * sizeof(double2));
     const size_t o_de = cv.take(kmax * sizeof(double));
     const size_t o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
+    // fused band reduction: chunks of at most kFuseV valence bands
+    const bool fuse = vb <= kFuseV;
+    const int ncb_max = ceil_div(cwmax, kFuseC);
+    const size_t o_vp = cv.take(want_psi && fuse && grad_psi_v
+                                    ? static_cast<size_t>(ncb_max) * vb * nr * sizeof(double2)
+                                    : 0);
     char* base = static_cast<char*>(get_scratch(cv.off));
     double2* mbuf = reinterpret_cast<double2*>(base + o_m);
     double2* t2 = reinterpret_cast<double2*>(base + o_t2);
@@ -414,6 +485,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     double2* qpart = reinterpret_cast<double2*>(base + o_q);
     double* de = reinterpret_cast<double*>(base + o_de);
     double2* grho = reinterpret_cast<double2*>(base + o_rho);
+    double2* vpart = grad_psi_v && fuse ? reinterpret_cast<double2*>(base + o_vp) : nullptr;
     const double2* z = reinterpret_cast<const double2*>(p.z);
     const double2* psi_v = reinterpret_cast<const double2*>(p.psi_v);
     const double2* psi_c = reinterpret_cast<const double2*>(p.psi_c);
@@ -478,6 +550,32 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                                    n3, plan.n23, plan.nb3, nj2, nj3, plan.w2inv, plan.w3inv,
                                    plan.boxmap, nr, dv, grho);
                 GW_HIP_TRY(hipGetLastError());
+            }
+            if (fuse) {
+                const int ncb = ceil_div(cw, kFuseC);
+                {
+                    ProfScope ps("bwd_reduce_cv", s);
+                    const dim3 grid(static_cast<unsigned>(ceil_div64(nr, 256)),
+                                    static_cast<unsigned>(ncb));
+                    switch (vcount) {
+#define GW_CV(VB)                                                                              \
+    case VB:                                                                                   \
+        hipLaunchKernelGGL(reduce_cv_kernel<VB>, grid, dim3(256), 0, s, grho, psi_v, psi_c, nr, \
+                           v0, c0, cw, grad_psi_c, vpart);                                     \
+        break;
+                        GW_CV(1) GW_CV(2) GW_CV(3) GW_CV(4) GW_CV(5) GW_CV(6) GW_CV(7) GW_CV(8)
+#undef GW_CV
+                    }
+                    GW_HIP_TRY(hipGetLastError());
+                }
+                if (vpart) {
+                    ProfScope ps("bwd_reduce_v", s);
+                    hipLaunchKernelGGL(vpart_reduce_kernel,
+                                       dim3(static_cast<unsigned>(ceil_div64(nr, 256)), vcount),
+                                       dim3(256), 0, s, vpart, ncb, vcount, nr, v0, grad_psi_v);
+                    GW_HIP_TRY(hipGetLastError());
+                }
+                continue;
             }
             if (grad_psi_c)
                 for (int cl0 = 0; cl0 < cw; cl0 += kYMax) {

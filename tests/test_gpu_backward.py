@@ -16,9 +16,15 @@ def _herm(rng, nz, ng):
     return np.ascontiguousarray(0.5 * (x + np.conj(np.transpose(x, (0, 2, 1)))))
 
 
-@pytest.mark.parametrize("zs,chunk", [((0.0,), 17), ((0.4j, 0.3 + 0.01j), 1000)])
-def test_backward_matches_oracle_adjoint(zs, chunk):
-    p = gen.make_problem((12, 10, 14), 4, 11, r2=9, z=zs, seed=21, pair_chunk=chunk)
+@pytest.mark.parametrize("zs,chunk,nv,nc", [
+    ((0.0,), 17, 4, 11),
+    ((0.4j, 0.3 + 0.01j), 1000, 4, 11),
+    # 12 valence x 3 conduction bands in one chunk: more valence bands than
+    # the fused band reduction holds, so the two separate reductions run
+    ((0.2j,), 1000, 12, 3),
+])
+def test_backward_matches_oracle_adjoint(zs, chunk, nv, nc):
+    p = gen.make_problem((12, 10, 14), nv, nc, r2=9, z=zs, seed=21, pair_chunk=chunk)
     rng = np.random.default_rng(5)
     w = _herm(rng, len(p.z), p.ng)
     dp = to_dev(p)
