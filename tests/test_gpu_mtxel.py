@@ -94,3 +94,29 @@ def test_mtxel_rejects_bad_arguments():
         gw.gw_mtxel(psi, psi, np.array([[0, 0, 0], [1, 0, 0]]), n, VOL, 3, 2, out=out)
     torch.cuda.synchronize()
     assert torch.all(out == 7.0)        # untouched on error
+
+
+def _box_g(r1, r2, r3):
+    """Miller indices of the box r1 x r2 x r3 (inclusive ranges)."""
+    axes = [np.arange(lo, hi + 1) for lo, hi in (r1, r2, r3)]
+    return np.array(list(itertools.product(*axes)), dtype=np.int32)
+
+
+@pytest.mark.parametrize("n,g", [
+    ((6, 10, 16), _box_g((-2, 2), (-4, 3), (-8, 7))),     # N3 = 16: the whole k3 window
+    ((5, 9, 32), _box_g((-2, 2), (-4, 4), (-7, 7))),      # N3 = 32
+    ((7, 12, 48), _box_g((-3, 3), (-6, 5), (-8, 5))),     # N3 = 48, window not centred
+    ((4, 24, 64), _box_g((-1, 1), (-10, 10), (-6, 6))),   # N3 = 64, 21 k2 values: two y blocks
+])
+def test_mtxel_box_g_lists(n, g):
+    """Box-shaped G lists with holes on grids with N3 a multiple of 16 (up to
+    64), the k3 values filling the window [-8, 7] or part of it off centre,
+    and 21 k2 values (two y-stage blocks): against the oracle, with ragged
+    pair tiles (3 valence x 37 conduction bands)."""
+    keep = np.ones(len(g), bool)
+    keep[::7] = False                    # holes in the disc
+    g = np.ascontiguousarray(g[keep])
+    p = gen.make_problem(n, 3, 37, gvec=g, seed=sum(n))
+    m = gw.gw_mtxel(_dev(p.psi_v), _dev(p.psi_c), g, n, p.volume).cpu().numpy()
+    ref = oracle.mtxel(p.psi_v, p.psi_c, g, n, p.volume)
+    assert rel_fro(m, ref) < FP64_TOL
