@@ -47,7 +47,8 @@ constexpr int kKt = 16;     // pairs per LDS stage
 // (T/WI) x (T/WJ) sub-tile of 16x16 MFMA blocks.  Per stage of kKt pairs the
 // rows of M for the tile's G and G' are staged in LDS (double-buffered; rows
 // padded by PAD elements), the G' side already multiplied by s*Delta_w(k);
-// the MFMAs accumulate conj(M_i) (Delta M_j).  Loads are unconditional: pair
+// the MFMAs accumulate conj(M_i) (Delta M_j), with three real products per
+// complex one on the 64x64 tile.  Loads are unconditional: pair
 // rows past the chunk end are clamped and carry Delta = 0, columns past N_G
 // are clamped and only feed outputs that are not stored.
 // mode: 0 overwrite, 1 accumulate.  PART: store the whole T x T tile instead,
@@ -74,11 +75,16 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
     const int cc = tid % T, kk0 = tid / T;
     const int64_t ci = min(i0 + cc, ng - 1), cj = min(j0 + cc, ng - 1);
 
-    dbl4 accr[BX][BY], acci[BX][BY];
+    // conj(a) b with three real products where the registers allow
+    // (Karatsuba, K3): p1 = ar br, p2 = ai bi, p3 = (ar - ai)(br + bi);
+    // Re = p1 + p2, Im = p3 - p1 + p2.  Otherwise four: p1 = Re, p2 = Im
+    // (p3 unused).
+    constexpr bool K3 = BX * BY <= 4;
+    dbl4 p1[BX][BY], p2[BX][BY], p3[BX][BY];
 #pragma unroll
     for (int a = 0; a < BX; ++a)
 #pragma unroll
-        for (int b = 0; b < BY; ++b) accr[a][b] = acci[a][b] = zero4();
+        for (int b = 0; b < BY; ++b) p1[a][b] = p2[a][b] = p3[a][b] = zero4();
 
     double2 ra[NLOAD], rb[NLOAD];
 
@@ -119,11 +125,27 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
             for (int x = 0; x < BX; ++x) a[x] = la[x * 16];
 #pragma unroll
             for (int y = 0; y < BY; ++y) b[y] = lb[y * 16];
+            if constexpr (K3) {
+                double as[BX], bs[BY];
 #pragma unroll
-            for (int x = 0; x < BX; ++x)
+                for (int x = 0; x < BX; ++x) as[x] = a[x].x - a[x].y;
 #pragma unroll
-                for (int y = 0; y < BY; ++y)
-                    cmfma_conj_a(accr[x][y], acci[x][y], a[x].x, a[x].y, b[y].x, b[y].y);
+                for (int y = 0; y < BY; ++y) bs[y] = b[y].x + b[y].y;
+#pragma unroll
+                for (int x = 0; x < BX; ++x)
+#pragma unroll
+                    for (int y = 0; y < BY; ++y) {
+                        p1[x][y] = mfma_f64(a[x].x, b[y].x, p1[x][y]);
+                        p2[x][y] = mfma_f64(a[x].y, b[y].y, p2[x][y]);
+                        p3[x][y] = mfma_f64(as[x], bs[y], p3[x][y]);
+                    }
+            } else {
+#pragma unroll
+                for (int x = 0; x < BX; ++x)
+#pragma unroll
+                    for (int y = 0; y < BY; ++y)
+                        cmfma_conj_a(p1[x][y], p2[x][y], a[x].x, a[x].y, b[y].x, b[y].y);
+            }
         }
         // keep the LDS stores of the next stage after this stage's MFMAs, so
         // the global loads issued above stay in flight during the compute
@@ -147,14 +169,16 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
             for (int t = 0; t < 4; ++t) {
                 const int li = wi * (T / WI) + x * 16 + 4 * t + kq;
                 const int lj = wj * (T / WJ) + y * 16 + row;
+                const double re = K3 ? p1[x][y][t] + p2[x][y][t] : p1[x][y][t];
+                const double im = K3 ? p3[x][y][t] - p1[x][y][t] + p2[x][y][t] : p2[x][y][t];
                 if constexpr (PART) {
-                    cw[li * T + lj] = make_double2(accr[x][y][t], acci[x][y][t]);
+                    cw[li * T + lj] = make_double2(re, im);
                     continue;
                 }
                 const int gi = i0 + li, gj = j0 + lj;
                 if (gi < ng && gj < ng) {
                     double2* p = cw + static_cast<int64_t>(gi) * ng + gj;
-                    double2 v = make_double2(accr[x][y][t], acci[x][y][t]);
+                    double2 v = make_double2(re, im);
                     if (mode) {
                         const double2 o = *p;
                         v.x += o.x;
