@@ -112,7 +112,11 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
             const int64_t kr = k < kc ? k : kc - 1;
             rd[u] = dw[kr];
             rb[u] = m[kr * ng + cj];
-            ra[u] = m[kr * ng + ci];
+            // component loads: a whole-struct copy into LDS would be fused
+            // into one global-to-LDS copy placed after the MFMAs, exposing
+            // the load latency at every stage
+            ra[u].x = m[kr * ng + ci].x;
+            ra[u].y = m[kr * ng + ci].y;
         }
         // loads first, then the MFMAs of the current stage (no reordering)
         __builtin_amdgcn_sched_barrier(0);
@@ -154,7 +158,7 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
 #pragma unroll
         for (int u = 0; u < NLOAD; ++u) {
             const int64_t k = k1 + kk0 + KSTEP * u;
-            s_a[(nb2 * kKt + kk0 + KSTEP * u) * LDR + cc] = ra[u];
+            s_a[(nb2 * kKt + kk0 + KSTEP * u) * LDR + cc] = make_double2(ra[u].x, ra[u].y);
             s_b[(nb2 * kKt + kk0 + KSTEP * u) * LDR + cc] =
                 k < kc ? cmul(rd[u], rb[u]) : make_double2(0.0, 0.0);
         }
