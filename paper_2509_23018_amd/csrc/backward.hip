@@ -43,10 +43,14 @@ __global__ __launch_bounds__(256) void ddelta_kernel(const double* __restrict__ 
 }
 
 // P1 = M W and P2 = M W^H for one TM (pairs) x 64 (G) tile; fused epilogue.
-// 4 waves of (TM/2) x 32.  TM = 32 keeps three workgroups on a CU and cuts
-// the last partial round of a launch to a third of what 64 x 64 tiles leave.
+// 4 waves of (TM/2) x 32.  TM = 32 cuts the last partial round of a launch
+// to half of what 64 x 64 tiles leave.
+// Each complex product a b is three real MFMA products (Karatsuba,
+// p1 = ar br, p2 = ai bi, p3 = (ar + ai)(br + bi); Re = p1 - p2,
+// Im = p3 - p1 - p2); the third accumulator set leaves registers for two
+// workgroups per CU.
 template <int TM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void bwd_gm_kernel(const double2* __restrict__ m, int64_t kc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void bwd_gm_kernel(const double2* __restrict__ m, int64_t kc,
                                                      int ng, const double2* __restrict__ w,
                                                      const double2* __restrict__ delta,
                                                      double2* __restrict__ gm,
@@ -61,57 +65,62 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
     const int64_t k0 = static_cast<int64_t>(blockIdx.y) * TM;
     const int i0 = blockIdx.x * 64;
 
-    dbl4 p1r[BX][2], p1i[BX][2], p2r[BX][2], p2i[BX][2];
+    // p?r = Re a Re b, p?i = Im a Im b, p?s = (Re a + Im a)(Re b + Im b)
+    dbl4 p1r[BX][2], p1i[BX][2], p1s[BX][2], p2r[BX][2], p2i[BX][2], p2s[BX][2];
 #pragma unroll
     for (int x = 0; x < BX; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) p1r[x][y] = p1i[x][y] = p2r[x][y] = p2i[x][y] = zero4();
+        for (int y = 0; y < 2; ++y)
+            p1r[x][y] = p1i[x][y] = p1s[x][y] = p2r[x][y] = p2i[x][y] = p2s[x][y] = zero4();
 
     // Stage j0 (16 G) of the three operands: fetched into registers one stage
     // ahead, so that the global loads of stage j0 + 16 run under the MFMAs of
-    // stage j0.
+    // stage j0.  The loads are unconditional (addresses clamped into the
+    // arrays) and nothing uses a loaded value before the stage is written to
+    // LDS: the bounds masks and the conjugation of the W^H operand are applied
+    // there, after the MFMAs, so no wait on a load lands before them.
     double2 ra[NA], rb1[4], rb2[4];
+    const int64_t klast = kc - 1;
+    const int glast = ng - 1;
     auto fetch = [&](int j0) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + 256 * u;
-            const int rr = e >> 4, jj = e & 15;
-            const int64_t k = k0 + rr;
-            ra[u] = (k < kc && j0 + jj < ng) ? m[k * ng + j0 + jj] : make_double2(0.0, 0.0);
+            const int64_t k = std::min<int64_t>(k0 + (e >> 4), klast);
+            const double2* src = m + k * ng + std::min(j0 + (e & 15), glast);
+            ra[u].x = src->x;  // component loads (a struct copy into LDS may be
+            ra[u].y = src->y;  // fused into one copy issued after the MFMAs)
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = tid + 256 * u;
-            {
-                const int jj = e >> 6, ii = e & 63;
-                rb1[u] = (j0 + jj < ng && i0 + ii < ng)
-                             ? w[static_cast<int64_t>(j0 + jj) * ng + i0 + ii]
-                             : make_double2(0.0, 0.0);
-            }
-            {
-                const int ii = e >> 4, jj = e & 15;
-                double2 val = make_double2(0.0, 0.0);
-                if (i0 + ii < ng && j0 + jj < ng) {
-                    const double2 x = w[static_cast<int64_t>(i0 + ii) * ng + j0 + jj];
-                    val = make_double2(x.x, -x.y);
-                }
-                rb2[u] = val;
-            }
+            const double2* s1 = w + static_cast<int64_t>(std::min(j0 + (e >> 6), glast)) * ng +
+                                std::min(i0 + (e & 63), glast);
+            const double2* s2 = w + static_cast<int64_t>(std::min(i0 + (e >> 4), glast)) * ng +
+                                std::min(j0 + (e & 15), glast);
+            rb1[u].x = s1->x;
+            rb1[u].y = s1->y;
+            rb2[u].x = s2->x;
+            rb2[u].y = s2->y;
         }
     };
+    const double2 zero = make_double2(0.0, 0.0);
     fetch(0);
     for (int j0 = 0; j0 < ng; j0 += 16) {
         __syncthreads();  // every wave is done with the previous stage
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + 256 * u;
-            s_a[e >> 4][e & 15] = ra[u];
+            const bool ok = k0 + (e >> 4) < kc && j0 + (e & 15) < ng;
+            s_a[e >> 4][e & 15] = ok ? make_double2(ra[u].x, ra[u].y) : zero;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = tid + 256 * u;
-            s_b1[e >> 6][e & 63] = rb1[u];
-            s_b2[e & 15][e >> 4] = rb2[u];
+            const bool ok1 = j0 + (e >> 6) < ng && i0 + (e & 63) < ng;
+            const bool ok2 = i0 + (e >> 4) < ng && j0 + (e & 15) < ng;
+            s_b1[e >> 6][e & 63] = ok1 ? make_double2(rb1[u].x, rb1[u].y) : zero;
+            s_b2[e & 15][e >> 4] = ok2 ? make_double2(rb2[u].x, -rb2[u].y) : zero;
         }
         __syncthreads();
         if (j0 + 16 < ng) fetch(j0 + 16);
@@ -126,12 +135,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
                 b1[y] = s_b1[s * 4 + kq][wj * 32 + y * 16 + row];
                 b2[y] = s_b2[s * 4 + kq][wj * 32 + y * 16 + row];
             }
+            double as[BX], bs1[2], bs2[2];
+#pragma unroll
+            for (int x = 0; x < BX; ++x) as[x] = a[x].x + a[x].y;
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                bs1[y] = b1[y].x + b1[y].y;
+                bs2[y] = b2[y].x + b2[y].y;
+            }
 #pragma unroll
             for (int x = 0; x < BX; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y) {
-                    cmfma(p1r[x][y], p1i[x][y], a[x].x, a[x].y, b1[y].x, b1[y].y);
-                    cmfma(p2r[x][y], p2i[x][y], a[x].x, a[x].y, b2[y].x, b2[y].y);
+                    p1r[x][y] = mfma_f64(a[x].x, b1[y].x, p1r[x][y]);
+                    p1i[x][y] = mfma_f64(a[x].y, b1[y].y, p1i[x][y]);
+                    p1s[x][y] = mfma_f64(as[x], bs1[y], p1s[x][y]);
+                    p2r[x][y] = mfma_f64(a[x].x, b2[y].x, p2r[x][y]);
+                    p2i[x][y] = mfma_f64(a[x].y, b2[y].y, p2i[x][y]);
+                    p2s[x][y] = mfma_f64(as[x], bs2[y], p2s[x][y]);
                 }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -149,8 +170,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
             for (int y = 0; y < 2; ++y) {
                 const int c = i0 + wj * 32 + y * 16 + row;
                 if (rok && c < ng) {
-                    const double2 a = make_double2(p1r[x][y][t], p1i[x][y][t]);
-                    const double2 b = make_double2(p2r[x][y][t], p2i[x][y][t]);
+                    const double2 a = make_double2(p1r[x][y][t] - p1i[x][y][t],
+                                                   p1s[x][y][t] - p1r[x][y][t] - p1i[x][y][t]);
+                    const double2 b = make_double2(p2r[x][y][t] - p2i[x][y][t],
+                                                   p2s[x][y][t] - p2r[x][y][t] - p2i[x][y][t]);
                     double2 g = cmul_conj_a(d, a);
                     const double2 h = cmul(d, b);
                     g.x += h.x;
