@@ -292,16 +292,22 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
 // 64x64 tile per workgroup, 4 waves (2x2) of 32x32.  Operands rounded to
 // FP32 when staged (the G' side after the FP64 energy factor); FP32 MFMA
 // 16x16x4 (lane l: A[l%16][l/16], B[l/16][l%16], D[4*(l/16)+t][l%16]);
-// every kBlk32 pairs the FP32 accumulators are added into FP64.
+// every kBlk32 pairs the FP32 accumulators are added into FP64.  Stages of
+// KT pairs are double-buffered in LDS: the global loads of stage st + 1 are
+// issued before the MFMAs of stage st and converted and written to the other
+// buffer after them.  Loads are unconditional (pair rows past the chunk end
+// clamped, their G' side zeroed at the write; columns past N_G clamped and
+// only feeding outputs that are not stored).
 __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict__ m, int64_t kc,
                                                        int ng, const double2* __restrict__ delta,
                                                        WList wl, double2* __restrict__ chi,
                                                        int mode, int nb,
                                                        const int* __restrict__ order) {
-    constexpr int T = 64, KT = 16;
+    constexpr int T = 64, KT = 16, NL = KT * T / 256;
+    static_assert(kBlk32 % KT == 0, "FP32 blocks must hold whole stages");
     int w, bi, bj;
     decode_item(blockIdx.x, wl, nb, order, w, bi, bj);
-    __shared__ float2 s_a[KT][T], s_b[KT][T];
+    __shared__ float2 s_a[2][KT][T], s_b[2][KT][T];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
     const int wi = wave >> 1, wj = wave & 1;
@@ -319,26 +325,51 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict
             accr[a][b] = acci[a][b] = zero4();
             fr[a][b] = fi[a][b] = zf4();
         }
-    const int nsteps = static_cast<int>((kc + KT - 1) / KT);
-    for (int st = 0; st < nsteps; ++st) {
-        __syncthreads();
+
+    // stage registers: the G row, the G' row and Delta for NL pair rows
+    double ar[NL], ai[NL], br[NL], bim[NL], dr[NL], di[NL];
+    auto fetch = [&](int64_t kbase) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = static_cast<int64_t>(st) * KT + kk0 + 4 * u;
+        for (int u = 0; u < NL; ++u) {
+            const int64_t k = kbase + kk0 + 4 * u;
             const int64_t kr = k < kc ? k : kc - 1;
-            const double2 a = m[kr * ng + ci];
-            const double2 b = k < kc ? cmul(dw[kr], m[kr * ng + cj]) : make_double2(0.0, 0.0);
-            s_a[kk0 + 4 * u][cc] = make_float2(static_cast<float>(a.x), static_cast<float>(a.y));
-            s_b[kk0 + 4 * u][cc] = make_float2(static_cast<float>(b.x), static_cast<float>(b.y));
+            const double2* pa = m + kr * ng + ci;
+            const double2* pb = m + kr * ng + cj;
+            ar[u] = pa->x;  // component loads: no fused global-to-LDS copy
+            ai[u] = pa->y;
+            br[u] = pb->x;
+            bim[u] = pb->y;
+            dr[u] = dw[kr].x;
+            di[u] = dw[kr].y;
         }
-        __syncthreads();
+    };
+    auto stage = [&](int buf, int64_t kbase) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const bool ok = kbase + kk0 + 4 * u < kc;
+            const double bx = ok ? dr[u] * br[u] - di[u] * bim[u] : 0.0;
+            const double by = ok ? dr[u] * bim[u] + di[u] * br[u] : 0.0;
+            s_a[buf][kk0 + 4 * u][cc] = make_float2(static_cast<float>(ar[u]), static_cast<float>(ai[u]));
+            s_b[buf][kk0 + 4 * u][cc] = make_float2(static_cast<float>(bx), static_cast<float>(by));
+        }
+    };
+
+    fetch(0);
+    stage(0, 0);
+    __syncthreads();
+    const int nsteps = static_cast<int>((kc + KT - 1) / KT);
+    int buf = 0;
+    for (int st = 0; st < nsteps; ++st) {
+        const int64_t knext = static_cast<int64_t>(st + 1) * KT;
+        fetch(knext);  // clamped: harmless past the last stage
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < KT / 4; ++s) {
             float2 a[2], b[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                a[x] = s_a[s * 4 + kq][wi * 32 + x * 16 + row];
-                b[x] = s_b[s * 4 + kq][wj * 32 + x * 16 + row];
+                a[x] = s_a[buf][s * 4 + kq][wi * 32 + x * 16 + row];
+                b[x] = s_b[buf][s * 4 + kq][wj * 32 + x * 16 + row];
             }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -350,6 +381,7 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict
                     fi[x][y] = mfma_f32(-a[x].y, b[y].x, fi[x][y]);
                 }
         }
+        __builtin_amdgcn_sched_barrier(0);
         if (((st + 1) * KT) % kBlk32 == 0 || st + 1 == nsteps) {
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -363,6 +395,9 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict
                     fr[x][y] = fi[x][y] = zf4();
                 }
         }
+        stage(buf ^ 1, knext);
+        __syncthreads();
+        buf ^= 1;
     }
     double2* cw = chi + static_cast<int64_t>(w) * ng * ng;
 #pragma unroll

@@ -138,6 +138,44 @@ def test_fp32_path():
         assert rel_fro(got[w], ref[w]) < 1e-5
 
 
+def fp32_bound(m, d, kblk=64):
+    """Elementwise bound on |chi_fp32 - chi| for one frequency (d = s*Delta).
+    Operands are rounded to FP32 (relative 2^-24 per component, the G' side
+    after the FP64 product d*m); each FP32 partial sum runs over at most kblk
+    pairs, i.e. 4 kblk real products per component, and rounds at most once
+    per addition (gamma_n with n = 4 kblk + 2); the FP64 sums of the partials
+    are below 1e-15 of the result.  With W = sum_p (|Re a| + |Im a|)
+    (|Re b| + |Im b|), which bounds the summed magnitudes of the real products
+    in either component: |err| <= sqrt(2) (2u + u^2 + gamma_n) W."""
+    u = 2.0 ** -24
+    n = 4 * kblk + 2
+    gam = n * u / (1 - n * u)
+    b = d[:, None] * m
+    wa = np.abs(m.real) + np.abs(m.imag)
+    wb = np.abs(b.real) + np.abs(b.imag)
+    wsum = wa.T @ wb
+    return np.sqrt(2) * (2 * u + u * u + gam) * wsum
+
+
+def test_fp32_error_within_bound():
+    """FP32 path against an a-posteriori bound from its rounding model, on two
+    chunkings (the bound does not depend on them: partial sums restart per
+    FP32 block and chunk)."""
+    p = _problem((0.0, 0.6j, 0.2 + 0.005j), seed=37)
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    m, d = _operands(p)
+    for chunk in (150, 1000):
+        got = run_chi0(p, precision="fp32", pair_chunk=chunk)
+        for w in range(len(p.z)):
+            bnd = fp32_bound(m, d[w])
+            bnd = np.maximum(bnd, bnd.T)   # mirrored Hermitian tiles
+            excess = np.abs(got[w] - ref[w]) - bnd - 1e-15 * np.abs(ref[w]).max()
+            assert excess.max() <= 0, (chunk, w, excess.max())
+            # and the bound is not vacuous: the error uses a real share of it
+            assert np.abs(got[w] - ref[w]).max() > 1e-3 * bnd.max()
+
+
 def test_split_edge_shapes():
     """Chunk smaller than a block, ragged blocks, a single G."""
     p = gen.make_problem((8, 8, 8), 2, 3, gvec=np.array([[0, 1, -1]], np.int32), z=(0.3j,),
