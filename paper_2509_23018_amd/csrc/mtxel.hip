@@ -63,7 +63,11 @@ constexpr int kRowStride = kSlab + 1;  // padded LDS row: column reads hit disti
 // (j1 plane, 16-row block of j2, 16-wide slab of j3) the tile's band rows are
 // staged once in LDS and shared by all the pairs that use them; the next
 // slab's global loads are in flight while the current one is contracted.
-template <int NB2, int NB3, int PPW>
+// K3: the z stage takes each complex product rho w as three real MFMA
+// products (Karatsuba: rho.x w.x, rho.y w.y, (rho.x + rho.y)(w.x + w.y);
+// Re = p1 - p2, Im = p3 - p1 - p2), its third accumulator set paid for by
+// one pair fewer per wave.
+template <int NB2, int NB3, int PPW, bool K3>
 __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const double2* __restrict__ psi_v, const double2* __restrict__ psi_c, int64_t nr, Rect rc,
     int n1, int planes_per_group, int n2, int n3, int n2p, int n3p,
@@ -129,12 +133,13 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
     for (int p = 0; p < PPW; ++p) pok[p] = tv0 + vl < rc.nv && tc0 + cl0 + p < rc.nc;
 
-    dbl4 a1r[PPW][NB3], a1i[PPW][NB3], a2r[PPW][NB2][NB3], a2i[PPW][NB2][NB3];
+    // z accumulators: Re, Im (a1s unused), or with K3 the three products
+    dbl4 a1r[PPW][NB3], a1i[PPW][NB3], a1s[PPW][NB3], a2r[PPW][NB2][NB3], a2i[PPW][NB2][NB3];
 #pragma unroll
     for (int p = 0; p < PPW; ++p)
 #pragma unroll
         for (int b3 = 0; b3 < NB3; ++b3) {
-            a1r[p][b3] = a1i[p][b3] = zero4();
+            a1r[p][b3] = a1i[p][b3] = a1s[p][b3] = zero4();
 #pragma unroll
             for (int b2 = 0; b2 < NB2; ++b2) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
         }
@@ -170,15 +175,29 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
             const int ks = sl * 4 + kk;
             const double2 xv = s_slab[(vl * 16 + row) * kRowStride + 4 * kk + kq];
             double2 w3[NB3];
+            double w3s[NB3];
 #pragma unroll
-            for (int b3 = 0; b3 < NB3; ++b3) w3[b3] = s_w3[(ks * NB3 + b3) * 64 + lane];
+            for (int b3 = 0; b3 < NB3; ++b3) {
+                w3[b3] = s_w3[(ks * NB3 + b3) * 64 + lane];
+                w3s[b3] = w3[b3].x + w3[b3].y;
+            }
 #pragma unroll
             for (int p = 0; p < PPW; ++p) {
                 const double2 xc = s_slab[((TV + cl0 + p) * 16 + row) * kRowStride + 4 * kk + kq];
                 const double2 rho = cmul_conj_a(xv, xc);
+                if constexpr (K3) {
+                    const double rs = rho.x + rho.y;
 #pragma unroll
-                for (int b3 = 0; b3 < NB3; ++b3)
-                    cmfma(a1r[p][b3], a1i[p][b3], rho.x, rho.y, w3[b3].x, w3[b3].y);
+                    for (int b3 = 0; b3 < NB3; ++b3) {
+                        a1r[p][b3] = mfma_f64(rho.x, w3[b3].x, a1r[p][b3]);
+                        a1i[p][b3] = mfma_f64(rho.y, w3[b3].y, a1i[p][b3]);
+                        a1s[p][b3] = mfma_f64(rs, w3s[b3], a1s[p][b3]);
+                    }
+                } else {
+#pragma unroll
+                    for (int b3 = 0; b3 < NB3; ++b3)
+                        cmfma(a1r[p][b3], a1i[p][b3], rho.x, rho.y, w3[b3].x, w3[b3].y);
+                }
             }
         }
         if (sl == nslab - 1) {
@@ -192,15 +211,19 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
                     for (int p = 0; p < PPW; ++p)
 #pragma unroll
-                        for (int b3 = 0; b3 < NB3; ++b3)
-                            cmfma(a2r[p][b2][b3], a2i[p][b2][b3], w.x, w.y, a1r[p][b3][t],
-                                  a1i[p][b3][t]);
+                        for (int b3 = 0; b3 < NB3; ++b3) {
+                            const double tr =
+                                K3 ? a1r[p][b3][t] - a1i[p][b3][t] : a1r[p][b3][t];
+                            const double ti = K3 ? a1s[p][b3][t] - a1r[p][b3][t] - a1i[p][b3][t]
+                                                 : a1i[p][b3][t];
+                            cmfma(a2r[p][b2][b3], a2i[p][b2][b3], w.x, w.y, tr, ti);
+                        }
                 }
             }
 #pragma unroll
             for (int p = 0; p < PPW; ++p)
 #pragma unroll
-                for (int b3 = 0; b3 < NB3; ++b3) a1r[p][b3] = a1i[p][b3] = zero4();
+                for (int b3 = 0; b3 < NB3; ++b3) a1r[p][b3] = a1i[p][b3] = a1s[p][b3] = zero4();
             if (rb1 == nrb1 - 1) {
 #pragma unroll
                 for (int p = 0; p < PPW; ++p) {
@@ -294,16 +317,18 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
 using ZyKernel = void (*)(const double2*, const double2*, int64_t, Rect, int, int, int, int, int,
                           int, const double2*, const double2*, const int*, int, double2*);
 
+// Pairs per wave by the widest box axis (in 16-wide blocks), within the
+// registers of two waves per SIMD; the single-block case uses K3.
 template <int NB2, int NB3>
 ZyKernel zy_ptr() {
     constexpr int nb = NB2 > NB3 ? NB2 : NB3;
-    constexpr int ppw = nb == 1 ? 4 : (nb == 2 ? 2 : 1);
-    return &mtxel_zy_kernel<NB2, NB3, ppw>;
+    constexpr int ppw = nb == 1 ? 3 : (nb == 2 ? 2 : 1);
+    return &mtxel_zy_kernel<NB2, NB3, ppw, nb == 1>;
 }
 
 int zy_pairs_per_wave(int nb2, int nb3) {
     const int nb = std::max(nb2, nb3);
-    return nb == 1 ? 4 : (nb == 2 ? 2 : 1);
+    return nb == 1 ? 3 : (nb == 2 ? 2 : 1);
 }
 
 ZyKernel select_zy(int nb2, int nb3) {
