@@ -63,9 +63,9 @@ constexpr int kRowStride = kSlab + 1;  // padded LDS row: column reads hit disti
 // (j1 plane, 16-row block of j2, 16-wide slab of j3) the tile's band rows are
 // staged once in LDS and shared by all the pairs that use them; the next
 // slab's global loads are in flight while the current one is contracted.
-// K3: the z stage takes each complex product rho w as three real MFMA
-// products (Karatsuba: rho.x w.x, rho.y w.y, (rho.x + rho.y)(w.x + w.y);
-// Re = p1 - p2, Im = p3 - p1 - p2), its third accumulator set paid for by
+// K3: both stages take each complex product a b as three real MFMA
+// products (Karatsuba: a.x b.x, a.y b.y, (a.x + a.y)(b.x + b.y);
+// Re = p1 - p2, Im = p3 - p1 - p2), the third accumulator sets paid for by
 // one pair fewer per wave.
 template <int NB2, int NB3, int PPW, bool K3>
 __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
@@ -133,15 +133,16 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
     for (int p = 0; p < PPW; ++p) pok[p] = tv0 + vl < rc.nv && tc0 + cl0 + p < rc.nc;
 
-    // z accumulators: Re, Im (a1s unused), or with K3 the three products
-    dbl4 a1r[PPW][NB3], a1i[PPW][NB3], a1s[PPW][NB3], a2r[PPW][NB2][NB3], a2i[PPW][NB2][NB3];
+    // accumulators: Re, Im (a?s unused), or with K3 the three products
+    dbl4 a1r[PPW][NB3], a1i[PPW][NB3], a1s[PPW][NB3];
+    dbl4 a2r[PPW][NB2][NB3], a2i[PPW][NB2][NB3], a2s[PPW][NB2][NB3];
 #pragma unroll
     for (int p = 0; p < PPW; ++p)
 #pragma unroll
         for (int b3 = 0; b3 < NB3; ++b3) {
             a1r[p][b3] = a1i[p][b3] = a1s[p][b3] = zero4();
 #pragma unroll
-            for (int b2 = 0; b2 < NB2; ++b2) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
+            for (int b2 = 0; b2 < NB2; ++b2) a2r[p][b2][b3] = a2i[p][b2][b3] = a2s[p][b2][b3] = zero4();
         }
 
     // this workgroup's planes: j1 in [j1b, j1e)
@@ -208,15 +209,23 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
                 for (int b2 = 0; b2 < NB2; ++b2) {
                     const double2 w = s_w2[((rb1 * 4 + t) * NB2 + b2) * 64 + lane];
+                    const double ws = w.x + w.y;
 #pragma unroll
                     for (int p = 0; p < PPW; ++p)
 #pragma unroll
                         for (int b3 = 0; b3 < NB3; ++b3) {
-                            const double tr =
-                                K3 ? a1r[p][b3][t] - a1i[p][b3][t] : a1r[p][b3][t];
-                            const double ti = K3 ? a1s[p][b3][t] - a1r[p][b3][t] - a1i[p][b3][t]
-                                                 : a1i[p][b3][t];
-                            cmfma(a2r[p][b2][b3], a2i[p][b2][b3], w.x, w.y, tr, ti);
+                            if constexpr (K3) {
+                                // T1 = (p1 - p2, p3 - p1 - p2); Re T1 + Im T1 = p3 - 2 p2
+                                const double p1 = a1r[p][b3][t], p2 = a1i[p][b3][t],
+                                             p3 = a1s[p][b3][t];
+                                const double tr = p1 - p2, ti = p3 - p1 - p2, ts = p3 - 2.0 * p2;
+                                a2r[p][b2][b3] = mfma_f64(w.x, tr, a2r[p][b2][b3]);
+                                a2i[p][b2][b3] = mfma_f64(w.y, ti, a2i[p][b2][b3]);
+                                a2s[p][b2][b3] = mfma_f64(ws, ts, a2s[p][b2][b3]);
+                            } else {
+                                cmfma(a2r[p][b2][b3], a2i[p][b2][b3], w.x, w.y, a1r[p][b3][t],
+                                      a1i[p][b3][t]);
+                            }
                         }
                 }
             }
@@ -238,14 +247,18 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
                                 for (int t = 0; t < 4; ++t) {
                                     const int d = s_box[(b2 * 16 + 4 * t + kq) * (NB3 * 16) +
                                                         b3 * 16 + row];
-                                    if (d >= 0)
-                                        o[d] = make_double2(a2r[p][b2][b3][t], a2i[p][b2][b3][t]);
+                                    if (d >= 0) {
+                                        const double p1 = a2r[p][b2][b3][t], p2 = a2i[p][b2][b3][t];
+                                        o[d] = K3 ? make_double2(p1 - p2, a2s[p][b2][b3][t] - p1 - p2)
+                                                  : make_double2(p1, p2);
+                                    }
                                 }
                     }
 #pragma unroll
                     for (int b2 = 0; b2 < NB2; ++b2)
 #pragma unroll
-                        for (int b3 = 0; b3 < NB3; ++b3) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
+                        for (int b3 = 0; b3 < NB3; ++b3)
+                            a2r[p][b2][b3] = a2i[p][b2][b3] = a2s[p][b2][b3] = zero4();
                 }
             }
         }
