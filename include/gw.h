@@ -97,6 +97,11 @@ enum {
                                             problems (same pointers, sizes, G lists, z, opts) */
 #define GW_FLAG_AUTOTUNE      (1u << 3)  /* time the CHI0 tile shapes on this data once per
                                             shape and keep the fastest (also GW_AUTOTUNE=1) */
+#define GW_FLAG_FP64_TILE128  (1u << 4)  /* FP64: contract on 128x128 tiles (8 waves, four
+                                            real MFMA products per complex one) instead of the
+                                            default 64x64 tiles; takes precedence over the
+                                            autotuner and over GW_CHI0_VARIANT; ignored by the
+                                            other precisions */
 
 /* One chi0 problem (one q-point). */
 typedef struct {

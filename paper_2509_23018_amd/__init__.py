@@ -25,6 +25,7 @@ import torch  # noqa: F401  (loads the HIP runtime that libgw binds to)
 __all__ = [
     "GWError", "lib", "library_path", "GW_FP64", "GW_FP32", "GW_SPLIT_BF16", "GW_SPLIT_FP16",
     "GW_FLAG_NO_HERMITIAN", "GW_FLAG_ACCUMULATE", "GW_FLAG_GRAPH", "GW_FLAG_AUTOTUNE",
+    "GW_FLAG_FP64_TILE128",
     "Chi0Problem", "gw_mtxel", "gw_chi0",
     "gw_chi0_backward", "Chi0", "chi0", "release", "profile_enable", "profile_reset",
     "profile_read",
@@ -35,6 +36,7 @@ GW_FLAG_NO_HERMITIAN = 1 << 0
 GW_FLAG_ACCUMULATE = 1 << 1
 GW_FLAG_GRAPH = 1 << 2
 GW_FLAG_AUTOTUNE = 1 << 3
+GW_FLAG_FP64_TILE128 = 1 << 4
 PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "split_bf16": GW_SPLIT_BF16,
               "split_fp16": GW_SPLIT_FP16}
 

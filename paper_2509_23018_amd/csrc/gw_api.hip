@@ -207,7 +207,8 @@ Opts read_opts(const gw_opts_t* o) {
     if ((r.precision == GW_SPLIT_BF16 || r.precision == GW_SPLIT_FP16) &&
         (r.n_slices < 2 || r.n_slices > 8))
         fail(GW_EINVAL, "n_slices must be in [2, 8] for split precision");
-    if (r.flags & ~(GW_FLAG_NO_HERMITIAN | GW_FLAG_ACCUMULATE | GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE))
+    if (r.flags & ~(GW_FLAG_NO_HERMITIAN | GW_FLAG_ACCUMULATE | GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE |
+                    GW_FLAG_FP64_TILE128))
         fail(GW_EINVAL, "unknown flag bits");
     return r;
 }
@@ -432,7 +433,9 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
     const std::vector<Chunk> chunks = make_chunks(pr, cs);
     int variant = 0;
     bool tune = false;
-    if (o.precision == GW_FP64) {
+    if (o.precision == GW_FP64 && (o.flags & GW_FLAG_FP64_TILE128)) {
+        variant = 1;
+    } else if (o.precision == GW_FP64) {
         variant = lookup_variant(pr.ng, chunks[0].kc);
         tune = variant < 0 && autotune_enabled(o);
         if (variant < 0) variant = 0;
@@ -751,6 +754,7 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
 // first chunk (one frequency, into a scratch chi so no output is touched).
 int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
     if (o.precision != GW_FP64) return 0;
+    if (o.flags & GW_FLAG_FP64_TILE128) return 1;
     int qmax = -1;
     for (int q = 0; q < nprob; ++q)
         if (static_cast<int64_t>(probs[q].nv) * probs[q].nc > 0 &&

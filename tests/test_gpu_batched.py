@@ -41,7 +41,7 @@ def _run(probs, **kw):
     return dps, [c.cpu().numpy() for c in chis]
 
 
-@pytest.mark.parametrize("flags", [0, gw.GW_FLAG_AUTOTUNE])
+@pytest.mark.parametrize("flags", [0, gw.GW_FLAG_AUTOTUNE, gw.GW_FLAG_FP64_TILE128])
 def test_batched_matches_oracle(flags):
     probs = _batch()
     _, got = _run(probs, pair_chunk=40, flags=flags)

@@ -27,17 +27,20 @@ def test_chi0_workload0_full():
     assert np.linalg.eigvalsh(chi[0]).max() <= 1e-13 * np.abs(chi).max()
 
 
+@pytest.mark.parametrize("flags", [0, gw.GW_FLAG_FP64_TILE128], ids=["tile64", "tile128"])
 @pytest.mark.parametrize("zs,chunk", [
     ((0.0,), 37),                                  # static, ragged chunks
     ((0.3j, 1.7j, 0.0), 64),                       # imaginary axis: Hermitian shortcut
     ((0.0 + 0.005j, 0.4 + 0.005j, 0.9 + 0.01j), 50),  # real axis: every tile
     ((0.2j, 0.5 + 0.005j), 1000),                  # mixed, one chunk
 ])
-def test_chi0_medium_multichunk(zs, chunk):
-    """Several 64-wide tiles with a ragged edge (N_G = 257) and several chunks."""
+def test_chi0_medium_multichunk(zs, chunk, flags):
+    """Several tiles with a ragged edge (N_G = 251: three full 64-wide tiles
+    and a ragged one, or one full 128-wide tile and a ragged one) and several
+    chunks, on both FP64 tile shapes."""
     p = gen.make_problem((20, 18, 24), 5, 23, r2=15, z=zs, seed=11, pair_chunk=chunk)
-    assert p.ng == 251          # three full 64-wide tiles and a ragged one
-    chi = run_chi0(p)
+    assert p.ng == 251
+    chi = run_chi0(p, flags=flags)
     ref = _oracle_chi(p)
     assert rel_fro(chi, ref) < FP64_TOL
     for w, z in enumerate(p.z):
@@ -152,6 +155,29 @@ def test_chi0_precision_workload_grid_and_sphere(prec, ns, tol):
     chi = gw.gw_chi0(dp, precision=prec, n_slices=ns, pair_chunk=48)
     got = chi[:, torch.from_numpy(rows).to(device())].cpu().numpy()
     assert rel_fro(got, ref) < tol, rel_fro(got, ref)
+
+
+def test_chi0_tile128_tail_round_split():
+    """The 128 x 128 FP64 tile (8 waves, one workgroup per CU: 256 resident
+    on an MI355X) with a partial last round: N_G = 1,189 (10 tiles a side) and
+    three real-axis frequencies give 300 items, the last 44 cut into 5 pair
+    ranges; two chunks of 200 pairs.  Parity with the oracle, one tail
+    reduction per chunk, and the same bits on a second run."""
+    zs = (0.1 + 0.01j, 0.5 + 0.02j, 0.9 + 0.005j)
+    p = gen.make_problem((16, 16, 16), 4, 100, r2=42, z=zs, seed=23, pair_chunk=200)
+    assert p.ng == 1189, p.ng
+    ref = _oracle_chi(p)
+    gw.profile_enable(True)
+    gw.profile_reset()
+    try:
+        chi = run_chi0(p, flags=gw.GW_FLAG_FP64_TILE128)
+        n_tail, _ = gw.profile_read("chi0_tail")
+    finally:
+        gw.profile_enable(False)
+    assert n_tail == 2
+    for w in range(len(zs)):
+        assert rel_fro(chi[w], ref[w]) < FP64_TOL
+    assert np.array_equal(run_chi0(p, flags=gw.GW_FLAG_FP64_TILE128), chi)
 
 
 @pytest.mark.parametrize("prec,ns,chunk,tol,kernel,launches", [
