@@ -121,19 +121,37 @@ def test_chi0_rejects_bad_arguments():
     assert torch.all(dp.chi == 5.0)
 
 
-def test_chi0_workload1_full_size_sampled():
+_W1 = {}
+
+
+def _workload1_sample():
+    """Workload 1 and the oracle's direct sums on 4 rows x 5 columns (cached:
+    the sums over 61,440 pairs are the slow part)."""
+    if not _W1:
+        p = gen.make_config(1)
+        assert (p.ng, p.npairs, len(p.z)) == (2007, 61440, 4)
+        rng = np.random.default_rng(101)
+        rows = np.sort(rng.choice(p.ng, 4, replace=False))
+        cols = np.sort(np.concatenate([[0, p.ng - 1], rng.choice(p.ng, 3, replace=False)]))
+        ref = oracle.chi0_entries(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec[rows], p.gvec[cols],
+                                  p.z, p.n, p.volume, p.spin)
+        _W1.update(p=p, rows=rows, cols=cols, ref=ref)
+    return _W1["p"], _W1["rows"], _W1["cols"], _W1["ref"]
+
+
+@pytest.mark.parametrize("prec,ns,tol", [
+    ("fp64", 0, FP64_TOL),
+    ("split_bf16", 5, 1e-10),     # the slice count the bench reports at 1e-10
+    ("fp32", 0, 1e-5),
+])
+def test_chi0_workload1_full_size_sampled(prec, ns, tol):
     """48^3 grid, 64 x 960 bands (61,440 pairs in chunks of 4,096), 2,007 G,
-    4 real frequencies: sampled rows/columns against the oracle's direct sums."""
-    p = gen.make_config(1)
-    assert (p.ng, p.npairs, len(p.z)) == (2007, 61440, 4)
-    chi = run_chi0(p)
-    rng = np.random.default_rng(101)
-    rows = np.sort(rng.choice(p.ng, 4, replace=False))
-    cols = np.sort(np.concatenate([[0, p.ng - 1], rng.choice(p.ng, 3, replace=False)]))
-    ref = oracle.chi0_entries(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec[rows], p.gvec[cols], p.z,
-                              p.n, p.volume, p.spin)
+    4 real frequencies, in the launch configuration the bench times:
+    sampled rows/columns against the oracle's direct sums."""
+    p, rows, cols, ref = _workload1_sample()
+    chi = run_chi0(p, precision=prec, n_slices=ns)
     got = chi[:, rows][:, :, cols]
-    assert rel_fro(got, ref) < FP64_TOL
+    assert rel_fro(got, ref) < tol, rel_fro(got, ref)
     # chi(z)^H = chi(conj z) cannot be checked within one call; check the
     # structure that holds at any size: the G = 0 row vanishes at q = 0
     assert np.abs(chi[:, 0, :]).max() < 1e-12 * np.abs(chi).max()
