@@ -118,8 +118,13 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
             ra[u].x = m[kr * ng + ci].x;
             ra[u].y = m[kr * ng + ci].y;
         }
-        // loads first, then the MFMAs of the current stage (no reordering)
+        // loads first, then the MFMAs of the current stage (no reordering).
+        // The wave raises its issue priority for the MFMA block: of the two
+        // waves on a SIMD, the one in its MFMA phase goes first, the other
+        // does its loads, LDS stores and barrier in the gaps (6.2 -> 5.8 ms
+        // per 48^3 chunk).
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int s = 0; s < kKt / 4; ++s) {
             const double2* la = s_a + (buf * kKt + s * 4 + kq) * LDR + wi * (T / WI) + row;
@@ -154,6 +159,7 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
         // keep the LDS stores of the next stage after this stage's MFMAs, so
         // the global loads issued above stay in flight during the compute
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
         const int nb2 = buf ^ 1;
 #pragma unroll
         for (int u = 0; u < NLOAD; ++u) {
