@@ -363,6 +363,7 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict
         const int64_t knext = static_cast<int64_t>(st + 1) * KT;
         fetch(knext);  // clamped: harmless past the last stage
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(1);  // the MFMA phase goes first on the SIMD
 #pragma unroll
         for (int s = 0; s < KT / 4; ++s) {
             float2 a[2], b[2];
@@ -382,6 +383,7 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict
                 }
         }
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
         if (((st + 1) * KT) % kBlk32 == 0 || st + 1 == nsteps) {
 #pragma unroll
             for (int x = 0; x < 2; ++x)
