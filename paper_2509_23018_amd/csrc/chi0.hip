@@ -104,6 +104,11 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
         // unconditional (clamped) prefetch of the next stage keeps the loop
         // free of branches, so the compiler cannot merge the LDS stores into
         // the load block
+        // issue priority: 1 while the next stage's loads are issued, 2 over
+        // the MFMA block, 0 for the LDS stores and the barrier; of the two
+        // waves on a SIMD the one with MFMAs to issue goes first, the other
+        // fills the gaps (6.20 -> 5.59 ms per 48^3 chunk)
+        __builtin_amdgcn_s_setprio(1);
         const int64_t k1 = static_cast<int64_t>(st + 1) * kKt;
         double2 rd[NLOAD];
 #pragma unroll
@@ -118,13 +123,9 @@ __device__ __forceinline__ void f64_tile(double2* lds, const double2* __restrict
             ra[u].x = m[kr * ng + ci].x;
             ra[u].y = m[kr * ng + ci].y;
         }
-        // loads first, then the MFMAs of the current stage (no reordering).
-        // The wave raises its issue priority for the MFMA block: of the two
-        // waves on a SIMD, the one in its MFMA phase goes first, the other
-        // does its loads, LDS stores and barrier in the gaps (6.2 -> 5.8 ms
-        // per 48^3 chunk).
+        // loads first, then the MFMAs of the current stage (no reordering)
         __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_s_setprio(1);
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int s = 0; s < kKt / 4; ++s) {
             const double2* la = s_a + (buf * kKt + s * 4 + kq) * LDR + wi * (T / WI) + row;
