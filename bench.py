@@ -163,6 +163,18 @@ def main():
     avg_ms = (t_chi + t_tail) / max(1, n_chi)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     traffic = read_traffic(launches_per_step)
+    # What the MFMAs execute: the default 64 x 64 tile takes each complex
+    # multiply-add as three real products (6 flops, not 8) over whole tiles
+    # and 16-pair stages, padding included.
+    nb = -(-ng // 64)
+    tiles = float(np.sum(np.where(herm, nb * (nb + 1) / 2.0, float(nb) * nb)))
+    cw = max(1, min(p.nc, chunk // max(1, min(p.nv, 4))))
+    vb = max(1, min(p.nv, chunk // cw))
+    kcs = [min(vb, p.nv - v0) * min(cw, p.nc - c0)
+           for v0 in range(0, p.nv, vb) for c0 in range(0, p.nc, cw)]
+    exec_step = sum(6.0 * tiles * 64 * 64 * (-(-k // 16) * 16) for k in kcs)
+    exec_per_launch = exec_step / max(1, launches_per_step)
+    executed = exec_per_launch / (avg_ms * 1e-3) / 1e12
 
     out = {
         "metric": METRIC,
@@ -194,6 +206,9 @@ def main():
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
             "traffic": traffic,
             "launches": n_chi,
+            "executed_tflops": round(executed, 3),
+            "executed_frac": round(executed / FP64_PEAK_TFLOPS, 4),
+            "executed_flops_per_launch": exec_per_launch,
             "avg_launch_ms": round(avg_ms, 4),
             "tail_reduce_ms_per_launch": round(t_tail / max(1, n_chi), 4),
             "flops_per_launch": flops_per_launch,
