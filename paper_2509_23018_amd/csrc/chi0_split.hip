@@ -361,9 +361,12 @@ __global__ __launch_bounds__(256) void chi0_f32_kernel(const double2* __restrict
     int buf = 0;
     for (int st = 0; st < nsteps; ++st) {
         const int64_t knext = static_cast<int64_t>(st + 1) * KT;
+        // issue priority 1 for the loads, 2 over the MFMAs, 0 for the stores
+        // and the barrier: the wave with MFMAs to issue goes first on the SIMD
+        __builtin_amdgcn_s_setprio(1);
         fetch(knext);  // clamped: harmless past the last stage
         __builtin_amdgcn_sched_barrier(0);
-        __builtin_amdgcn_s_setprio(1);  // the MFMA phase goes first on the SIMD
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int s = 0; s < KT / 4; ++s) {
             float2 a[2], b[2];
