@@ -123,8 +123,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
             s_b2[e & 15][e >> 4] = ok2 ? make_double2(rb2[u].x, -rb2[u].y) : zero;
         }
         __syncthreads();
+        // issue priority 1 for the loads, 2 over the MFMAs, 0 for the stores
+        // and barriers: the wave with MFMAs to issue goes first on the SIMD
+        __builtin_amdgcn_s_setprio(1);
         if (j0 + 16 < ng) fetch(j0 + 16);
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             double2 a[BX], b1[2], b2[2];
@@ -156,6 +160,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
                 }
         }
         __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
     }
 
 #pragma unroll
