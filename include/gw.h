@@ -16,8 +16,8 @@
  *          over chunks of pairs (the paper's NV-Block idea of splitting the
  *          sum over bands so that M never exists whole).
  *
- * The energy factor, which the paper leaves as "a function of E_v, E_c and
- * the frequency", is taken as the resonant plus anti-resonant form
+ * The paper specifies the energy factor only as depending on E_v, E_c and
+ * the frequency; it is taken here as the resonant plus anti-resonant form
  *     Delta_vc(z) = 1/(E_v - E_c + z) + 1/(E_v - E_c - z),
  * with z = w + i*eta (real axis), z = i*w (imaginary axis) or z = 0 (static).
  *
