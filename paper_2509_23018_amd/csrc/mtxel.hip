@@ -3,13 +3,14 @@
 // e^{+i G.r}, taken as a pruned 3D DFT that only produces the frequencies the
 // G-sphere needs.
 //
-// Kernel 1 (fused; one workgroup per pair, its 4 waves taking every 4th j1
-// plane): for each plane it forms rho = conj(psi_v) psi_c while loading the
-// MFMA A operand (8 k-steps of loads in flight per lane), contracts over j3
-// against the z twiddles (FP64 MFMA 16x16x4), feeds the accumulators straight
-// back into a second MFMA contraction over j2 against the y twiddles, and
-// writes the (k2,k3) values the G list uses.  Twiddle operands live in LDS in
-// MFMA lane order.
+// Kernel 1 (fused; one workgroup of 8 waves per tile of 4 valence x 2*PPW
+// conduction bands and group of j1 planes): per (plane, 16-row block of j2,
+// 16-wide slab of j3) the tile's band rows are staged in LDS once; each wave
+// forms rho = conj(psi_v) psi_c for its pairs from them, contracts over j3
+// against the z twiddles (FP64 MFMA 16x16x4), feeds the accumulators
+// straight back into a second MFMA contraction over j2 against the y
+// twiddles, and writes the (k2,k3) values the G list uses.  Twiddle operands
+// live in LDS in MFMA lane order.
 // Kernel 2 (one workgroup per pair): contracts over j1 with the x twiddles on
 // MFMA, reading the stage-y output with coalesced rows, and scatters the
 // (k1, disc) box entries that are G vectors to their place in the G list.
