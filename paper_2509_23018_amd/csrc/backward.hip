@@ -299,31 +299,43 @@ __global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__
         const double2* urow = u + (k * n1 + j1) * n23;
         double2* out = grho + k * nr + static_cast<int64_t>(j1) * n2 * n3;
         for (int nb = 0; nb < nj3; ++nb) {
-            dbl4 tr[NB2], ti[NB2];
+            // both products take each complex a b as three real MFMA products
+            // (Karatsuba: p1 = a.x b.x, p2 = a.y b.y, p3 = (a.x + a.y)(b.x + b.y);
+            // Re = p1 - p2, Im = p3 - p1 - p2)
+            dbl4 t1[NB2], t2[NB2], t3[NB2];
 #pragma unroll
-            for (int b2 = 0; b2 < NB2; ++b2) tr[b2] = ti[b2] = zero4();
+            for (int b2 = 0; b2 < NB2; ++b2) t1[b2] = t2[b2] = t3[b2] = zero4();
             for (int s = 0; s < ks3; ++s) {
                 const double2 b = w3inv[(s * nj3 + nb) * 64 + lane];
+                const double bs = b.x + b.y;
 #pragma unroll
                 for (int b2 = 0; b2 < NB2; ++b2) {
                     const int d = boxmap[(b2 * 16 + row) * bw3 + 4 * s + kq];
                     const double2 a = d >= 0 ? urow[d] : make_double2(0.0, 0.0);
-                    cmfma(tr[b2], ti[b2], a.x, a.y, b.x, b.y);
+                    t1[b2] = mfma_f64(a.x, b.x, t1[b2]);
+                    t2[b2] = mfma_f64(a.y, b.y, t2[b2]);
+                    t3[b2] = mfma_f64(a.x + a.y, bs, t3[b2]);
                 }
             }
             for (int rb = 0; rb < nj2; ++rb) {
-                dbl4 gr = zero4(), gi = zero4();
+                dbl4 g1 = zero4(), g2 = zero4(), g3 = zero4();
 #pragma unroll
                 for (int b2 = 0; b2 < NB2; ++b2)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const double2 a = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
-                        cmfma(gr, gi, a.x, a.y, tr[b2][t], ti[b2][t]);
+                        // T = (p1 - p2, p3 - p1 - p2), Re T + Im T = p3 - 2 p2
+                        const double p1 = t1[b2][t], p2 = t2[b2][t], p3 = t3[b2][t];
+                        g1 = mfma_f64(a.x, p1 - p2, g1);
+                        g2 = mfma_f64(a.y, p3 - p1 - p2, g2);
+                        g3 = mfma_f64(a.x + a.y, p3 - 2.0 * p2, g3);
                     }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int j2 = rb * 16 + 4 * t + kq, j3 = nb * 16 + row;
-                    if (j2 < n2 && j3 < n3) out[j2 * n3 + j3] = make_double2(dv * gr[t], dv * gi[t]);
+                    if (j2 < n2 && j3 < n3)
+                        out[j2 * n3 + j3] =
+                            make_double2(dv * (g1[t] - g2[t]), dv * (g3[t] - g1[t] - g2[t]));
                 }
             }
         }
