@@ -21,6 +21,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2509_23018_amd as gw
 from gpu_helpers import FP64_TOL, rel_fro, run_chi0
 from workloads import gen
 
@@ -189,3 +190,30 @@ def test_split_edge_shapes():
                       spin=p.spin, pair_chunk=200)
     got = run_chi0(p, precision="split_fp16", n_slices=6)
     assert rel_fro(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("S", [3, 4, 5])
+def test_split_bf16_matches_arithmetic_model(S):
+    """The split-BF16 path against a CPU emulation of its arithmetic (block
+    exponents, slices rounded to nearest, exact FP32 sums of the shift-0 and
+    shift-1 groups, FP32 sums of the rest, FP64 recombination): the method
+    error at 3 slices is 1e-7, but device and model differ only by the order
+    of the FP32 additions of the shift >= 2 group.
+    Every tile is contracted (no Hermitian mirror), so each entry comes from
+    the same slices on both sides."""
+    from test_precision_bounds_cpu import _split_model, _split_problem
+    p = _split_problem()
+    m, d = _operands(p)
+    model = _split_model(m, d[0], S, p.nv, p.nc, p.pair_chunk)
+    got = run_chi0(p, precision="split_bf16", n_slices=S, flags=gw.GW_FLAG_NO_HERMITIAN)[0]
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin)[0]
+    # the shift >= 2 group is at most 2^-16 of the result and each FP32
+    # addition to it rounds at 2^-24 of its running sum: over a block of 256
+    # real products that is about 2^-36 relative, summed in a different order
+    # on the two sides
+    assert rel_fro(got, model) < 5e-11, (S, rel_fro(got, model), rel_fro(got, ref))
+    # far inside the method error where that is large (3 and 4 slices), so a
+    # different slicing or grouping would show
+    if S < 5:
+        assert rel_fro(got, model) < 0.1 * rel_fro(got, ref), (S, rel_fro(got, ref))
