@@ -21,4 +21,5 @@ from .chi0_oracle import (  # noqa: F401
     chi0,
     chi0_entries,
     chi0_backward,
+    pseudobands,
 )

@@ -193,3 +193,28 @@ def chi0_backward(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, grad_chi, spin=2.0
             g_psi_c[c] += psi_v[v] * g_rho
             g_psi_v[v] += psi_c[c] * np.conj(g_rho)
     return g_psi_v, g_psi_c, g_e_v, g_e_c
+
+
+def pseudobands(psi, e, keep, slices, n_xi, theta):
+    """Stochastic pseudobands (Reduced Cost and Scaling section): the bands of
+    each slice S are replaced by n_xi random-phase combinations
+    ``xi_j^S = (1/sqrt(n_xi)) sum_{n in S} exp(2 pi i theta_n^j) psi_n``, each
+    given the mean energy of the slice; the protected bands ``keep`` pass
+    through unchanged.
+
+    psi [nb][N_r], e [nb]; keep: band indices; slices: list of band-index
+    arrays; theta: list (one per slice) of [n_xi][len(S)] arrays in [0, 1)
+    (the random numbers are inputs).  Returns (psi_out, e_out) with the kept
+    bands first, then the pseudobands slice by slice, j fastest.
+    """
+    rows = [psi[i] for i in keep]
+    ens = [e[i] for i in keep]
+    for s, th in zip(slices, theta):
+        s = np.asarray(s)
+        for j in range(n_xi):
+            ph = np.exp(2j * np.pi * np.asarray(th[j], dtype=np.float64))
+            rows.append((ph[:, None] * psi[s]).sum(axis=0) / np.sqrt(n_xi))
+            ens.append(float(np.mean(e[s])))
+    nr = psi.shape[1]
+    out = np.array(rows, dtype=np.complex128).reshape(len(rows), nr)
+    return out, np.array(ens, dtype=np.float64)

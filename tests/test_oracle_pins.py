@@ -452,3 +452,57 @@ def test_adjoint_plane_wave_energy_gradient():
             want_c[c] -= val
     assert np.abs(gev - want_v).max() < 1e-12 * np.abs(want_v).max()
     assert np.abs(gec - want_c).max() < 1e-12 * np.abs(want_v).max()
+
+
+# ---------------------------------------------------------------- pseudobands
+
+def _orthonormal_bands(nb, n=(6, 5, 4), seed=3):
+    p = gen.make_problem(n, 1, nb, r2=1, z=(0.0,), seed=seed)
+    return p.psi_c, p.e_c, p.volume / np.prod(n)
+
+
+def test_pseudobands_norm_identity():
+    """For orthonormal bands, dV ||xi_j^S||^2 = |S| / n_xi for every draw of
+    the phases: the cross terms vanish by orthogonality."""
+    psi, e, dv = _orthonormal_bands(9)
+    rng = np.random.default_rng(11)
+    slices = [np.array([0, 3, 4, 8]), np.array([1, 2]), np.array([5, 6, 7])]
+    n_xi = 3
+    theta = [rng.random((n_xi, len(s))) for s in slices]
+    out, eo = oracle.pseudobands(psi, e, [], slices, n_xi, theta)
+    norms = dv * np.sum(np.abs(out) ** 2, axis=1)
+    expect = np.repeat([len(s) / n_xi for s in slices], n_xi)
+    assert np.allclose(norms, expect, rtol=0, atol=1e-12)
+    assert np.allclose(eo, np.repeat([e[s].mean() for s in slices], n_xi), rtol=0, atol=0)
+
+
+def test_pseudobands_phase_average_is_slice_projector():
+    """Averaged over every pattern of quarter-turn phases (4^|S| of them), the
+    single pseudoband's outer product xi xi^H is exactly the slice projector
+    sum_{n in S} psi_n psi_n^H: sum_k exp(2 pi i k a / 4) over k vanishes
+    unless a = 0 mod 4."""
+    psi, e, dv = _orthonormal_bands(5, n=(3, 2, 2))
+    s = np.array([0, 2, 3])
+    proj = sum(np.outer(psi[i], np.conj(psi[i])) for i in s)
+    acc = np.zeros_like(proj)
+    pats = list(itertools.product(range(4), repeat=len(s)))
+    for pat in pats:
+        th = [np.array([[q / 4.0 for q in pat]])]
+        xi, _ = oracle.pseudobands(psi, e, [], [s], 1, th)
+        acc += np.outer(xi[0], np.conj(xi[0]))
+    assert np.abs(acc / len(pats) - proj).max() < 1e-13 * np.abs(proj).max()
+
+
+def test_pseudobands_singletons_leave_chi0_unchanged():
+    """Slices of one band with one pseudoband each only rephase the bands,
+    and chi0 depends on conj(M) M: it is unchanged; protected bands pass
+    through."""
+    p = gen.make_problem((8, 6, 6), 2, 7, r2=4, z=(0.0, 0.3 + 0.01j), seed=12)
+    rng = np.random.default_rng(4)
+    slices = [np.array([i]) for i in range(2, 7)]
+    theta = [rng.random((1, 1)) for _ in slices]
+    pc, ec = oracle.pseudobands(p.psi_c, p.e_c, [0, 1], slices, 1, theta)
+    assert np.array_equal(pc[:2], p.psi_c[:2]) and np.array_equal(ec, p.e_c)
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume)
+    got = oracle.chi0(p.psi_v, pc, p.e_v, ec, p.gvec, p.z, p.n, p.volume)
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
