@@ -196,6 +196,35 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
                              double* grad_e_v, double* grad_e_c,
                              const gw_opts_t* opts, void* stream);
 
+/*
+ * gw_pseudobands -- stochastic pseudobands (Reduced Cost and Scaling section
+ * of the paper): a band set compressed into
+ *   the protected bands keep[0..nkeep), copied as they are, then for each
+ *   slice s (bands slice_idx[slice_off[s] .. slice_off[s+1])) n_xi bands
+ *     xi_{s,j}(r) = (1/sqrt(n_xi)) sum_{n in s} exp(2 pi i theta_{s,j,n}) psi_n(r)
+ *   with the mean energy of the slice's bands.
+ *
+ * psi       device [nb][nr]; e device [nb] (Hartree).
+ * keep      HOST [nkeep] band indices; slice_idx HOST [slice_off[nslices]]
+ *           band indices; slice_off HOST [nslices + 1], slice_off[0] = 0,
+ *           strictly increasing (no empty slice).  A band may appear in
+ *           several places; the caller chooses the partition.
+ * theta     HOST, per slice s in order, [n_xi][|s|] phases in turns (the
+ *           random numbers are the caller's, so results are reproducible).
+ * n_xi      1..8 pseudobands per slice.
+ * out_psi   device [nkeep + nslices*n_xi][nr], out_e device [same] (overwritten):
+ *           the protected bands first, then slice by slice, j fastest.
+ * The host tables are staged through host memory, so this call returns once
+ * its work on `stream` has completed.  Returns GW_EINVAL for an index out of
+ * range, an empty slice, n_xi outside 1..8 or a non-finite theta, and
+ * GW_EUNSUPPORTED for more than 65535 protected bands or slices.
+ */
+gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int64_t nr,
+                           const int32_t* keep, int32_t nkeep,
+                           const int32_t* slice_idx, const int32_t* slice_off, int32_t nslices,
+                           int32_t n_xi, const double* theta,
+                           gw_c128* out_psi, double* out_e, void* stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* gw_last_error(void);
 
@@ -212,7 +241,8 @@ int32_t gw_abi_version(void);
  * "mtxel_x", "delta", "chi0_f64", "chi0_tail", "chi0_f64_batched",
  * "split_prep", "chi0_split", "chi0_split_tail", "chi0_split_batched",
  * "chi0_f32", "mirror", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x", "bwd_yz",
- * "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v").
+ * "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v", "pseudo_energy", "pseudo_keep",
+ * "pseudo_mix").
  * gw_profile_read waits for the recorded events of `kernel` and returns the
  * number of launches and the summed duration in milliseconds (0 and 0.0 for
  * an unknown name).  gw_profile_reset forgets every record.  Timing adds two

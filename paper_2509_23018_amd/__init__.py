@@ -27,7 +27,8 @@ __all__ = [
     "GW_FLAG_NO_HERMITIAN", "GW_FLAG_ACCUMULATE", "GW_FLAG_GRAPH", "GW_FLAG_AUTOTUNE",
     "GW_FLAG_FP64_TILE128",
     "Chi0Problem", "gw_mtxel", "gw_chi0",
-    "gw_chi0_backward", "Chi0", "chi0", "release", "profile_enable", "profile_reset",
+    "gw_chi0_backward", "gw_pseudobands", "Chi0", "chi0", "release", "profile_enable",
+    "profile_reset",
     "profile_read",
 ]
 
@@ -94,6 +95,12 @@ def lib() -> ctypes.CDLL:
         L.gw_chi0_backward.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(_Opts), ctypes.c_void_p]
+        L.gw_pseudobands.restype = ctypes.c_int32
+        L.gw_pseudobands.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_release.restype = ctypes.c_int32
@@ -179,6 +186,33 @@ def gw_mtxel(psi_v: torch.Tensor, psi_c: torch.Tensor, gvec, n, volume: float,
                               g.ctypes.data, g.shape[0], int(pair_begin), int(pair_count),
                               out.data_ptr(), _stream(psi_v.device, stream)))
     return out
+
+
+def gw_pseudobands(psi: torch.Tensor, e: torch.Tensor, keep, slices, n_xi: int, theta,
+                   stream=None):
+    """Stochastic pseudobands: returns (psi_out, e_out) with the bands `keep`
+    first, then n_xi random-phase combinations of each slice (a sequence of
+    band-index arrays), with phases theta[s] of shape [n_xi][len(slices[s])]
+    in turns."""
+    _dev(psi, "psi", torch.complex128)
+    _dev(e, "e", torch.float64)
+    nb, nr = psi.shape[0], psi.shape[1]
+    i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int64).reshape(-1), np.int32)
+    k = i32(keep)
+    sl = [np.asarray(x, dtype=np.int64).reshape(-1) for x in slices]
+    idx = i32(np.concatenate(sl) if sl else np.zeros(0, np.int64))
+    off = i32(np.concatenate([[0], np.cumsum([len(x) for x in sl])]))
+    th = np.ascontiguousarray(np.concatenate(
+        [np.asarray(t, dtype=np.float64).reshape(-1) for t in theta]) if sl else np.zeros(0))
+    nout = len(k) + len(sl) * int(n_xi)
+    out = torch.empty((nout, nr), dtype=torch.complex128, device=psi.device)
+    out_e = torch.empty(nout, dtype=torch.float64, device=psi.device)
+    with torch.cuda.device(psi.device):
+        _check(lib().gw_pseudobands(psi.data_ptr(), e.data_ptr(), nb, nr, k.ctypes.data, len(k),
+                                    idx.ctypes.data, off.ctypes.data, len(sl), int(n_xi),
+                                    th.ctypes.data, out.data_ptr(), out_e.data_ptr(),
+                                    _stream(psi.device, stream)))
+    return out, out_e
 
 
 @dataclass

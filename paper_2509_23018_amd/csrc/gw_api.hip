@@ -20,6 +20,7 @@
 #include "items.hpp"
 #include "plan.hpp"
 #include "prof.hpp"
+#include "pseudobands.hpp"
 
 namespace gw {
 namespace {
@@ -1027,6 +1028,71 @@ gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* o
             run_chi0_batched(probs, nprob, o, s);
         else
             for (int q = 0; q < nprob; ++q) run_chi0(probs[q], o, s);
+    });
+}
+
+gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int64_t nr,
+                           const int32_t* keep, int32_t nkeep, const int32_t* slice_idx,
+                           const int32_t* slice_off, int32_t nslices, int32_t n_xi,
+                           const double* theta, gw_c128* out_psi, double* out_e,
+                           void* stream) {
+    return guarded([&] {
+        if (nb < 0 || nr < 1) fail(GW_EINVAL, "nb must be >= 0 and nr >= 1");
+        if (nkeep < 0 || nslices < 0) fail(GW_EINVAL, "nkeep and nslices must be >= 0");
+        if (nkeep > 65535 || nslices > 65535)
+            fail(GW_EUNSUPPORTED, "at most 65535 protected bands and 65535 slices per call");
+        if (nkeep > 0 && !keep) fail(GW_EINVAL, "keep is NULL");
+        if (nslices > 0) {
+            if (!slice_idx || !slice_off || !theta) fail(GW_EINVAL, "slice tables are NULL");
+            if (n_xi < 1 || n_xi > kMaxPseudoXi)
+                fail(GW_EINVAL, "n_xi must lie in [1, " + std::to_string(kMaxPseudoXi) + "]");
+            if (slice_off[0] != 0) fail(GW_EINVAL, "slice_off[0] must be 0");
+            for (int sl = 0; sl < nslices; ++sl)
+                if (slice_off[sl + 1] <= slice_off[sl])
+                    fail(GW_EINVAL, "slice " + std::to_string(sl) + " is empty");
+        }
+        const int64_t nidx = nslices > 0 ? slice_off[nslices] : 0;
+        for (int i = 0; i < nkeep; ++i)
+            if (keep[i] < 0 || keep[i] >= nb) fail(GW_EINVAL, "keep index out of range");
+        for (int64_t i = 0; i < nidx; ++i)
+            if (slice_idx[i] < 0 || slice_idx[i] >= nb) fail(GW_EINVAL, "slice index out of range");
+        const int64_t ntheta = nidx * (nslices > 0 ? n_xi : 0);
+        for (int64_t i = 0; i < ntheta; ++i)
+            if (!std::isfinite(theta[i])) fail(GW_EINVAL, "theta must be finite");
+        const int nout = nkeep + nslices * (nslices > 0 ? n_xi : 0);
+        if (nout == 0) return;
+        if (!psi || !e) fail(GW_EINVAL, "psi / e is NULL");
+        if (!out_psi || !out_e) fail(GW_EINVAL, "out_psi / out_e is NULL");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // the host tables, packed and copied in stream order into scratch
+        std::vector<int64_t> toff(nslices);
+        for (int sl = 0; sl < nslices; ++sl) toff[sl] = static_cast<int64_t>(slice_off[sl]) * n_xi;
+        Carver cv;
+        const size_t o_keep = cv.take(static_cast<size_t>(nkeep) * sizeof(int32_t));
+        const size_t o_idx = cv.take(static_cast<size_t>(nidx) * sizeof(int32_t));
+        const size_t o_off = cv.take(static_cast<size_t>(nslices + 1) * sizeof(int32_t));
+        const size_t o_toff = cv.take(static_cast<size_t>(nslices) * sizeof(int64_t));
+        const size_t o_th = cv.take(static_cast<size_t>(ntheta) * sizeof(double));
+        std::vector<char> host(cv.off, 0);
+        auto put = [&](size_t o, const void* src, size_t n) {
+            if (n) std::memcpy(host.data() + o, src, n);
+        };
+        put(o_keep, keep, static_cast<size_t>(nkeep) * sizeof(int32_t));
+        put(o_idx, slice_idx, static_cast<size_t>(nidx) * sizeof(int32_t));
+        if (nslices > 0) put(o_off, slice_off, static_cast<size_t>(nslices + 1) * sizeof(int32_t));
+        put(o_toff, toff.data(), toff.size() * sizeof(int64_t));
+        put(o_th, theta, static_cast<size_t>(ntheta) * sizeof(double));
+        char* dev = static_cast<char*>(scratch(cv.off, s));
+        GW_HIP_TRY(hipMemcpyAsync(dev, host.data(), cv.off, hipMemcpyHostToDevice, s));
+        PseudoTables t{reinterpret_cast<const int*>(dev + o_keep),
+                       reinterpret_cast<const int*>(dev + o_idx),
+                       reinterpret_cast<const int*>(dev + o_off),
+                       reinterpret_cast<const double*>(dev + o_th),
+                       reinterpret_cast<const int64_t*>(dev + o_toff)};
+        launch_pseudobands(reinterpret_cast<const double2*>(psi), e, nr, t, nkeep, nslices,
+                           nslices > 0 ? n_xi : 1, reinterpret_cast<double2*>(out_psi), out_e, s);
+        // the staging vector must outlive the copy
+        GW_HIP_TRY(hipStreamSynchronize(s));
     });
 }
 
