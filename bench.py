@@ -84,7 +84,7 @@ def main():
                     help="slice counts of the split-BF16 runs (empty: none)")
     ap.add_argument("--workload", default="chi0_48cube",
                     choices=["chi0_48cube", "batched_40cube_64q", "precision_72cube",
-                             "adjoint_32cube"],
+                             "adjoint_32cube", "pseudobands_48cube"],
                     help="chi0_48cube: the contract line (default); the others print a "
                          "measurement line of their own")
     args = ap.parse_args()
@@ -103,6 +103,9 @@ def main():
         return
     if args.workload == "adjoint_32cube":
         bench_adjoint(args)
+        return
+    if args.workload == "pseudobands_48cube":
+        bench_pseudobands(args)
         return
 
     import numpy as np
@@ -491,6 +494,124 @@ def bench_adjoint(args):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_adjoint(p, a_np, dev)
+    gw.release()
+    print(json.dumps(out), flush=True)
+
+
+PB_SIZES = [16, 32, 64, 128, 256, 400]   # slices of the 896 unprotected conduction bands
+PB_PROTECT, PB_XI = 64, 4
+
+
+def bench_pseudobands(args):
+    """Stochastic pseudobands on workload 1 (48^3 grid, 64 x 960 bands, 2,007 G,
+    4 real frequencies): the 64 lowest conduction bands are protected and the
+    other 896 become 4 pseudobands per slice of 16, 32, 64, 128, 256 and 400
+    bands (88 conduction bands in all), then chi0 is built in FP64 on the
+    compressed set.  Reports the mixing kernel against the HBM roofline, the
+    chi0 time and its error against chi0 on all 960 bands, and the oracle's
+    pseudobands timed on the host."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    dev = torch.device("cuda", 0)
+    p = gen.make_config(1)
+    keep, slices, theta = gen.pseudoband_recipe(p.e_c, PB_PROTECT, PB_SIZES, PB_XI, seed=1005)
+    chunk = p.pair_chunk
+
+    def prob(psi_c, e_c):
+        return gw.Chi0Problem(n=p.n, volume=p.volume, psi_v=torch.from_numpy(p.psi_v).to(dev),
+                              psi_c=psi_c, e_v=torch.from_numpy(p.e_v).to(dev), e_c=e_c,
+                              gvec=p.gvec, z=p.z)
+
+    pc_full = torch.from_numpy(p.psi_c).to(dev)
+    ec_full = torch.from_numpy(p.e_c).to(dev)
+    full = gw.gw_chi0(prob(pc_full, ec_full), precision="fp64", pair_chunk=chunk)
+    t_full = _timed(lambda: gw.gw_chi0(prob(pc_full, ec_full), precision="fp64",
+                                       pair_chunk=chunk), max(1, args.steps))
+
+    def make_pb():
+        return gw.gw_pseudobands(pc_full, ec_full, keep, slices, PB_XI, theta)
+
+    for _ in range(max(1, args.warmup)):
+        make_pb()
+    steps = max(1, args.steps)
+    gw.profile_reset()
+    gw.profile_enable(True)
+    t_pb = _timed(make_pb, steps)
+    gw.profile_enable(False)
+    n_mix, t_mix = gw.profile_read("pseudo_mix")
+    n_keep, t_keep = gw.profile_read("pseudo_keep")
+    n_prep, t_prep = gw.profile_read("pseudo_prep")
+    gw.profile_reset()
+    pc, ec = make_pb()
+    dq = prob(pc, ec)
+    chi_c = gw.gw_chi0(dq, precision="fp64", pair_chunk=chunk)
+    t_chi = _timed(lambda: gw.gw_chi0(dq, precision="fp64", pair_chunk=chunk), steps)
+    diff = (chi_c - full).cpu().numpy()
+    ref = full.cpu().numpy()
+    err = float(np.linalg.norm(diff) / np.linalg.norm(ref))
+    err_w = [float(np.linalg.norm(diff[w]) / np.linalg.norm(ref[w])) for w in range(len(p.z))]
+    # the diagonal and the trace keep their expectation term by term (the
+    # cross terms of a slice average out there); off-diagonal entries of
+    # white-noise bands do not decay, so their stochastic error is of the
+    # order of the entries themselves
+    dg_c = np.diagonal(chi_c.cpu().numpy(), axis1=1, axis2=2)
+    dg_f = np.diagonal(ref, axis1=1, axis2=2)
+    err_diag = [float(np.linalg.norm(dg_c[w] - dg_f[w]) / np.linalg.norm(dg_f[w]))
+                for w in range(len(p.z))]
+    err_trace = [float(abs(dg_c[w].sum() - dg_f[w].sum()) / abs(dg_f[w].sum()))
+                 for w in range(len(p.z))]
+    nr = int(np.prod(p.n))
+    nmixed = sum(len(s) for s in slices)
+    # algorithmic bytes of one mixing launch: every slice band read once, the
+    # pseudobands written once
+    mix_bytes = 16.0 * nr * (nmixed + len(slices) * PB_XI)
+    mix_ms = t_mix / max(1, n_mix)
+    achieved = mix_bytes / (mix_ms * 1e-3) / 1e9
+    nc_out = PB_PROTECT + len(slices) * PB_XI
+    out = {
+        "workload": "pseudobands_48cube",
+        "config": {"grid": list(p.n), "n_v": p.nv, "n_c": p.nc, "n_g": p.ng,
+                   "n_freq": len(p.z), "protected": PB_PROTECT, "slices": PB_SIZES,
+                   "n_xi": PB_XI, "n_c_compressed": nc_out, "theta_seed": 1005},
+        "data": "synthetic",
+        "s_per_pseudobands": round(t_pb, 5),
+        "pseudo_mix_ms": round(mix_ms, 4),
+        "pseudo_keep_ms": round(t_keep / max(1, n_keep), 4),
+        "pseudo_prep_ms": round(t_prep / max(1, n_prep), 4),
+        "s_per_chi0_compressed": round(t_chi, 5),
+        "s_per_chi0_full": round(t_full, 5),
+        "speedup_chi0": round(t_full / (t_chi + t_pb), 3),
+        "rel_err_vs_full": err,
+        "rel_err_per_freq": err_w,
+        "rel_err_diagonal_per_freq": err_diag,
+        "rel_err_trace_per_freq": err_trace,
+        "roofline": {
+            "kernel": "pseudo_mix_kernel",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "launches": n_mix,
+            "avg_launch_ms": round(mix_ms, 4),
+            "bytes_per_launch": mix_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        opc, oec = oracle.pseudobands(p.psi_c, p.e_c, keep, slices, PB_XI, theta)
+        dt = time.perf_counter() - t0
+        dev_err = float(np.abs(pc.cpu().numpy() - opc).max() / np.abs(opc).max())
+        out["cpu_baseline"] = {"value": round(mix_bytes / dt / 1e9, 2), "unit": "GB/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "the whole compression (all slices), numpy",
+                               "seconds": round(dt, 2), "gpu_max_rel_diff": dev_err}
     gw.release()
     print(json.dumps(out), flush=True)
 

@@ -216,8 +216,8 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
  *           the protected bands first, then slice by slice, j fastest.
  * The host tables are staged through host memory, so this call returns once
  * its work on `stream` has completed.  Returns GW_EINVAL for an index out of
- * range, an empty slice, n_xi outside 1..8 or a non-finite theta, and
- * GW_EUNSUPPORTED for more than 65535 protected bands or slices.
+ * range, an empty slice, n_xi outside 1..8, a non-finite theta or nr of 2^31
+ * or more, and GW_EUNSUPPORTED for more than 65535 protected bands or slices.
  */
 gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int64_t nr,
                            const int32_t* keep, int32_t nkeep,
@@ -241,7 +241,7 @@ int32_t gw_abi_version(void);
  * "mtxel_x", "delta", "chi0_f64", "chi0_tail", "chi0_f64_batched",
  * "split_prep", "chi0_split", "chi0_split_tail", "chi0_split_batched",
  * "chi0_f32", "mirror", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x", "bwd_yz",
- * "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v", "pseudo_energy", "pseudo_keep",
+ * "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v", "pseudo_prep", "pseudo_keep",
  * "pseudo_mix").
  * gw_profile_read waits for the recorded events of `kernel` and returns the
  * number of launches and the summed duration in milliseconds (0 and 0.0 for

@@ -1038,6 +1038,7 @@ gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int6
                            void* stream) {
     return guarded([&] {
         if (nb < 0 || nr < 1) fail(GW_EINVAL, "nb must be >= 0 and nr >= 1");
+        if (nr >= (int64_t(1) << 31)) fail(GW_EINVAL, "grid has 2^31 or more points");
         if (nkeep < 0 || nslices < 0) fail(GW_EINVAL, "nkeep and nslices must be >= 0");
         if (nkeep > 65535 || nslices > 65535)
             fail(GW_EUNSUPPORTED, "at most 65535 protected bands and 65535 slices per call");
@@ -1067,28 +1068,40 @@ gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int6
         // the host tables, packed and copied in stream order into scratch
         std::vector<int64_t> toff(nslices);
         for (int sl = 0; sl < nslices; ++sl) toff[sl] = static_cast<int64_t>(slice_off[sl]) * n_xi;
+        // largest slices first, so that the longest workgroups start early
+        std::vector<int32_t> order(nslices);
+        for (int sl = 0; sl < nslices; ++sl) order[sl] = sl;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return slice_off[a + 1] - slice_off[a] > slice_off[b + 1] - slice_off[b];
+        });
         Carver cv;
         const size_t o_keep = cv.take(static_cast<size_t>(nkeep) * sizeof(int32_t));
         const size_t o_idx = cv.take(static_cast<size_t>(nidx) * sizeof(int32_t));
         const size_t o_off = cv.take(static_cast<size_t>(nslices + 1) * sizeof(int32_t));
+        const size_t o_ord = cv.take(static_cast<size_t>(nslices) * sizeof(int32_t));
         const size_t o_toff = cv.take(static_cast<size_t>(nslices) * sizeof(int64_t));
         const size_t o_th = cv.take(static_cast<size_t>(ntheta) * sizeof(double));
-        std::vector<char> host(cv.off, 0);
+        const size_t staged = cv.off;  // the tables above come from the host
+        const size_t o_ph = cv.take(static_cast<size_t>(ntheta) * sizeof(double2));
+        std::vector<char> host(staged, 0);
         auto put = [&](size_t o, const void* src, size_t n) {
             if (n) std::memcpy(host.data() + o, src, n);
         };
         put(o_keep, keep, static_cast<size_t>(nkeep) * sizeof(int32_t));
         put(o_idx, slice_idx, static_cast<size_t>(nidx) * sizeof(int32_t));
         if (nslices > 0) put(o_off, slice_off, static_cast<size_t>(nslices + 1) * sizeof(int32_t));
+        put(o_ord, order.data(), order.size() * sizeof(int32_t));
         put(o_toff, toff.data(), toff.size() * sizeof(int64_t));
         put(o_th, theta, static_cast<size_t>(ntheta) * sizeof(double));
         char* dev = static_cast<char*>(scratch(cv.off, s));
-        GW_HIP_TRY(hipMemcpyAsync(dev, host.data(), cv.off, hipMemcpyHostToDevice, s));
+        GW_HIP_TRY(hipMemcpyAsync(dev, host.data(), staged, hipMemcpyHostToDevice, s));
         PseudoTables t{reinterpret_cast<const int*>(dev + o_keep),
                        reinterpret_cast<const int*>(dev + o_idx),
                        reinterpret_cast<const int*>(dev + o_off),
+                       reinterpret_cast<const int*>(dev + o_ord),
                        reinterpret_cast<const double*>(dev + o_th),
-                       reinterpret_cast<const int64_t*>(dev + o_toff)};
+                       reinterpret_cast<const int64_t*>(dev + o_toff),
+                       reinterpret_cast<double2*>(dev + o_ph)};
         launch_pseudobands(reinterpret_cast<const double2*>(psi), e, nr, t, nkeep, nslices,
                            nslices > 0 ? n_xi : 1, reinterpret_cast<double2*>(out_psi), out_e, s);
         // the staging vector must outlive the copy

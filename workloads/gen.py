@@ -206,3 +206,20 @@ def device_bands(nb: int, nr: int, *, seed: int, volume: float = CELL_L ** 3, de
     # complex normal: real and imaginary parts of variance 1/2 each
     psi = torch.randn((nb, nr), generator=g, device=device, dtype=torch.complex128)
     return psi.mul_((1.0 / volume) ** 0.5)
+
+
+def pseudoband_recipe(e_c, n_protect: int, sizes, n_xi: int, seed: int):
+    """Pseudoband inputs for a conduction set: the n_protect lowest bands are
+    protected, the rest (in energy order) are cut into consecutive slices of
+    the given sizes (growing with energy), and the phases in turns are drawn
+    uniform in [0, 1).  Returns (keep, slices, theta)."""
+    order = np.argsort(np.asarray(e_c), kind="stable")
+    keep = order[:n_protect]
+    rest = order[n_protect:]
+    if sum(sizes) != len(rest):
+        raise ValueError("slice sizes must cover the unprotected bands")
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    slices = [rest[bounds[i]:bounds[i + 1]] for i in range(len(sizes))]
+    rng = np.random.default_rng(seed)
+    theta = [rng.random((n_xi, len(s))) for s in slices]
+    return keep, slices, theta
