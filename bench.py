@@ -87,6 +87,8 @@ def main():
                              "adjoint_32cube", "pseudobands_48cube"],
                     help="chi0_48cube: the contract line (default); the others print a "
                          "measurement line of their own")
+    ap.add_argument("--pb-xi", type=int, default=4,
+                    help="pseudobands per slice of the pseudobands_48cube workload (1..8)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the chi0 build here runs on a single MI355X "
@@ -499,14 +501,14 @@ def bench_adjoint(args):
 
 
 PB_SIZES = [16, 32, 64, 128, 256, 400]   # slices of the 896 unprotected conduction bands
-PB_PROTECT, PB_XI = 64, 4
+PB_PROTECT = 64
 
 
 def bench_pseudobands(args):
     """Stochastic pseudobands on workload 1 (48^3 grid, 64 x 960 bands, 2,007 G,
     4 real frequencies): the 64 lowest conduction bands are protected and the
-    other 896 become 4 pseudobands per slice of 16, 32, 64, 128, 256 and 400
-    bands (88 conduction bands in all), then chi0 is built in FP64 on the
+    other 896 become n_xi pseudobands (4 by default) per slice of 16, 32, 64, 128, 256 and 400
+    bands (88 conduction bands in all at n_xi = 4), then chi0 is built in FP64 on the
     compressed set.  Reports the mixing kernel against the HBM roofline, the
     chi0 time and its error against chi0 on all 960 bands, and the oracle's
     pseudobands timed on the host."""
@@ -517,8 +519,9 @@ def bench_pseudobands(args):
     from workloads import gen
 
     dev = torch.device("cuda", 0)
+    xi = args.pb_xi
     p = gen.make_config(1)
-    keep, slices, theta = gen.pseudoband_recipe(p.e_c, PB_PROTECT, PB_SIZES, PB_XI, seed=1005)
+    keep, slices, theta = gen.pseudoband_recipe(p.e_c, PB_PROTECT, PB_SIZES, xi, seed=1005)
     chunk = p.pair_chunk
 
     def prob(psi_c, e_c):
@@ -533,7 +536,7 @@ def bench_pseudobands(args):
                                        pair_chunk=chunk), max(1, args.steps))
 
     def make_pb():
-        return gw.gw_pseudobands(pc_full, ec_full, keep, slices, PB_XI, theta)
+        return gw.gw_pseudobands(pc_full, ec_full, keep, slices, xi, theta)
 
     for _ in range(max(1, args.warmup)):
         make_pb()
@@ -568,15 +571,15 @@ def bench_pseudobands(args):
     nmixed = sum(len(s) for s in slices)
     # algorithmic bytes of one mixing launch: every slice band read once, the
     # pseudobands written once
-    mix_bytes = 16.0 * nr * (nmixed + len(slices) * PB_XI)
+    mix_bytes = 16.0 * nr * (nmixed + len(slices) * xi)
     mix_ms = t_mix / max(1, n_mix)
     achieved = mix_bytes / (mix_ms * 1e-3) / 1e9
-    nc_out = PB_PROTECT + len(slices) * PB_XI
+    nc_out = PB_PROTECT + len(slices) * xi
     out = {
         "workload": "pseudobands_48cube",
         "config": {"grid": list(p.n), "n_v": p.nv, "n_c": p.nc, "n_g": p.ng,
                    "n_freq": len(p.z), "protected": PB_PROTECT, "slices": PB_SIZES,
-                   "n_xi": PB_XI, "n_c_compressed": nc_out, "theta_seed": 1005},
+                   "n_xi": xi, "n_c_compressed": nc_out, "theta_seed": 1005},
         "data": "synthetic",
         "s_per_pseudobands": round(t_pb, 5),
         "pseudo_mix_ms": round(mix_ms, 4),
@@ -605,7 +608,7 @@ def bench_pseudobands(args):
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
-        opc, oec = oracle.pseudobands(p.psi_c, p.e_c, keep, slices, PB_XI, theta)
+        opc, oec = oracle.pseudobands(p.psi_c, p.e_c, keep, slices, xi, theta)
         dt = time.perf_counter() - t0
         dev_err = float(np.abs(pc.cpu().numpy() - opc).max() / np.abs(opc).max())
         out["cpu_baseline"] = {"value": round(mix_bytes / dt / 1e9, 2), "unit": "GB/s",

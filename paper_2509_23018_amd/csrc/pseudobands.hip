@@ -8,10 +8,10 @@
 // writes n_xi rows: it is bound by HBM bandwidth.  A workgroup owns 64
 // consecutive grid points of one slice (one per lane, so each band row is
 // read as 1 KiB runs) and its four waves take every fourth band of the
-// slice, which keeps many loads in flight even for the largest slice; the
-// phase and band index of a step are the same across a wave (scalar loads),
-// the waves' n_xi sums meet in LDS at the end, and the slices are launched
-// largest first.
+// slice, which keeps many loads in flight even for the largest slice.  The
+// band index and phases of a step are the same across a wave (scalar loads
+// of adjacent words), the waves' n_xi sums meet in LDS at the end, and the
+// slices are launched largest first.
 #include <algorithm>
 
 #include "common.hpp"
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kPbThreads) void pseudo_mix_kernel(
     __shared__ double2 s_part[kPbGroups - 1][NX][kPbPoints];
     const int sl = order[blockIdx.y];
     const int b0 = off[sl], nbs = off[sl + 1] - b0;
-    const double2* ph = phase + theta_off[sl];  // [NX][nbs]
+    const double2* ph = phase + theta_off[sl];  // [nbs][NX]
     const int* ix = idx + b0;
     const int lane = threadIdx.x % kPbPoints;
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kPbPoints);
@@ -48,11 +48,11 @@ __global__ __launch_bounds__(kPbThreads) void pseudo_mix_kernel(
 #pragma unroll 8
         for (int n = grp; n < nbs; n += kPbGroups) {
             const double2 p = psi[static_cast<int64_t>(ix[n]) * nr + r];
+            const double2* w = ph + static_cast<int64_t>(n) * NX;  // the NX phases of band n
 #pragma unroll
             for (int j = 0; j < NX; ++j) {
-                const double2 w = ph[static_cast<int64_t>(j) * nbs + n];
-                acc[j].x += w.x * p.x - w.y * p.y;
-                acc[j].y += w.x * p.y + w.y * p.x;
+                acc[j].x += w[j].x * p.x - w[j].y * p.y;
+                acc[j].y += w[j].x * p.y + w[j].y * p.x;
             }
         }
     }
@@ -88,8 +88,9 @@ __global__ __launch_bounds__(kPbThreads) void pseudo_keep_kernel(
         out[static_cast<int64_t>(i) * nr + r] = psi[src + r];
 }
 
-// Workgroup sl < nslices: slice sl's phase table exp(2 pi i theta) (laid out
-// as theta) and the mean of its energies, written to its n_xi rows; the
+// Workgroup sl < nslices: slice sl's phase table exp(2 pi i theta), band-major
+// ([|S|][n_xi], so the phases a mixing step needs are adjacent), and the mean
+// of its energies, written to its n_xi rows; the
 // workgroups after those copy the energies of the protected bands.
 __global__ __launch_bounds__(kPbThreads) void pseudo_prep_kernel(
     const double* __restrict__ e, const int* __restrict__ keep, int nkeep,
@@ -106,9 +107,10 @@ __global__ __launch_bounds__(kPbThreads) void pseudo_prep_kernel(
     const int b0 = off[b], nbs = off[b + 1] - b0;
     const int64_t t0 = theta_off[b];
     for (int t = threadIdx.x; t < n_xi * nbs; t += kPbThreads) {
+        const int j = t / nbs, n = t - j * nbs;
         double sn, cs;
         sincospi(2.0 * theta[t0 + t], &sn, &cs);
-        phase[t0 + t] = make_double2(cs, sn);
+        phase[t0 + static_cast<int64_t>(n) * n_xi + j] = make_double2(cs, sn);
     }
     double sum = 0.0;
     for (int n = threadIdx.x; n < nbs; n += kPbThreads) sum += e[idx[b0 + n]];

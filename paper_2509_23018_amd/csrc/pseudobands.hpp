@@ -17,7 +17,7 @@ struct PseudoTables {
     const int* order;         // [nslices] the slices in launch order (largest first)
     const double* theta;      // per slice [n_xi][|S|] phases in turns
     const int64_t* theta_off; // [nslices] start of slice s in theta and phase
-    double2* phase;           // like theta: exp(2 pi i theta), written by the prep kernel
+    double2* phase;           // per slice [|S|][n_xi] exp(2 pi i theta), written by the prep kernel
 };
 
 void launch_pseudobands(const double2* psi, const double* e, int64_t nr, const PseudoTables& t,
