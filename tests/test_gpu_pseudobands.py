@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 def _bands(nb, n=(9, 8, 7), seed=5):
     """nb orthonormal bands on a ragged grid (504 points: not a multiple of
-    the 256-thread workgroup) with uniform energies."""
+    the 64 points of a mixing workgroup or the 256 of a copy workgroup) with
+    uniform energies."""
     p = gen.make_problem(n, 1, nb, r2=2, z=(0.0,), seed=seed)
     return p.psi_c, p.e_c
 
@@ -25,13 +26,14 @@ def _dev(x):
 
 @pytest.mark.parametrize("n_xi", [1, 3, 8])
 def test_pseudobands_match_oracle(n_xi):
-    """Protected bands, slices of 1 to 300 bands (more than the 256 phases a
-    workgroup stages at once), bands out of order within a slice."""
+    """Protected bands, slices of 1 to 300 bands (fewer than the four waves
+    that split a slice's bands, a count they do not divide, and long ones),
+    bands out of order within a slice, slices not in size order."""
     psi, e = _bands(420)
     rng = np.random.default_rng(n_xi)
     perm = rng.permutation(420)
     keep = perm[:5]
-    slices = [perm[5:6], perm[6:13], perm[13:113], perm[113:413]]
+    slices = [perm[5:6], perm[113:413], perm[6:13], perm[13:113]]
     theta = [rng.random((n_xi, len(s))) for s in slices]
     got, ge = gw.gw_pseudobands(_dev(psi), _dev(e), keep, slices, n_xi, theta)
     ref, re = oracle.pseudobands(psi, e, keep, slices, n_xi, theta)
@@ -60,6 +62,21 @@ def test_chi0_from_pseudobands():
     ref = oracle.chi0(p.psi_v, opc, p.e_v, oec, p.gvec, p.z, p.n, p.volume,
                       pair_chunk=p.pair_chunk)
     assert rel_fro(got, ref) < FP64_TOL
+
+
+def test_pseudobands_workload1_full_size():
+    """The 48^3 workload's 960 conduction bands at full size, compressed as
+    the bench does (64 protected, slices of 16 to 400 bands, 4 pseudobands
+    each): every element against the oracle."""
+    p = gen.make_config(1)
+    keep, slices, theta = gen.pseudoband_recipe(p.e_c, 64, [16, 32, 64, 128, 256, 400], 4,
+                                                seed=1005)
+    got, ge = gw.gw_pseudobands(_dev(p.psi_c), _dev(p.e_c), keep, slices, 4, theta)
+    ref, re = oracle.pseudobands(p.psi_c, p.e_c, keep, slices, 4, theta)
+    g = got.cpu().numpy()
+    assert g.shape == ref.shape == (88, int(np.prod(p.n)))
+    assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.allclose(ge.cpu().numpy(), re, rtol=1e-15, atol=0)
 
 
 def test_pseudobands_rejects_bad_arguments():
