@@ -9,9 +9,10 @@
 // consecutive grid points of one slice (one per lane, so each band row is
 // read as 1 KiB runs) and its four waves take every fourth band of the
 // slice, which keeps many loads in flight even for the largest slice.  The
-// band index and phases of a step are the same across a wave (scalar loads
-// of adjacent words), the waves' n_xi sums meet in LDS at the end, and the
-// slices are launched largest first.
+// band rows are read with non-temporal loads; the band index and phases of a
+// step are the same across a wave (scalar loads of adjacent words); the
+// waves' n_xi sums meet in LDS at the end; the slices are launched largest
+// first.
 #include <algorithm>
 
 #include "common.hpp"
@@ -47,7 +48,12 @@ __global__ __launch_bounds__(kPbThreads) void pseudo_mix_kernel(
     if (live) {
 #pragma unroll 8
         for (int n = grp; n < nbs; n += kPbGroups) {
-            const double2 p = psi[static_cast<int64_t>(ix[n]) * nr + r];
+            // each band row is read once: non-temporal loads keep it from
+            // displacing reusable lines in the caches
+            const double* q =
+                reinterpret_cast<const double*>(psi + static_cast<int64_t>(ix[n]) * nr + r);
+            const double2 p = make_double2(__builtin_nontemporal_load(q),
+                                           __builtin_nontemporal_load(q + 1));
             const double2* w = ph + static_cast<int64_t>(n) * NX;  // the NX phases of band n
 #pragma unroll
             for (int j = 0; j < NX; ++j) {
