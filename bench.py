@@ -36,28 +36,32 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "chi0_f64_kernel_48cube_61440pairs_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_23018_amd", "csrc", f)
                   for f in ("chi0.hip", "common.hpp", "items.hpp")]
+PROFILE_TRAFFIC_PB = os.path.join(ROOT, "profiles", "pseudo_mix_kernel_48cube_960bands_pmc.md")
+KERNEL_SOURCES_PB = [os.path.join(ROOT, "paper_2509_23018_amd", "csrc", f)
+                     for f in ("pseudobands.hip", "pseudobands.hpp", "common.hpp")]
 
 
-def kernel_src_sha() -> str:
+def kernel_src_sha(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(launch_count_per_step: int):
-    """HBM bytes per launch of chi0_f64 from the committed counter summary,
-    or None when the summary is missing or the kernel source changed since."""
+def read_traffic(launch_count_per_step: int = 0, profile=None, sources=None):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (chi0_f64 by default), or None when the summary is missing or the
+    kernel's sources changed since the counters were taken."""
     try:
-        text = open(PROFILE_TRAFFIC).read()
+        text = open(profile or PROFILE_TRAFFIC).read()
     except OSError:
         return None
     m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", text, re.M)
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("src_sha256") != kernel_src_sha():
+    if d.get("src_sha256") != kernel_src_sha(sources):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -599,7 +603,7 @@ def bench_pseudobands(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": read_traffic(profile=PROFILE_TRAFFIC_PB, sources=KERNEL_SOURCES_PB),
             "launches": n_mix,
             "avg_launch_ms": round(mix_ms, 4),
             "bytes_per_launch": mix_bytes,
