@@ -412,7 +412,11 @@ __global__ __launch_bounds__(256) void reduce_cv_kernel(const double2* __restric
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int vl = 0; vl < VB; ++vl) {
-            const double2 g = grho[(static_cast<int64_t>(vl) * cw + cl) * nr + r];
+            // g_rho is read once (non-temporal: it should not displace psi)
+            const int64_t gi = (static_cast<int64_t>(vl) * cw + cl) * nr + r;
+            const double* gq = reinterpret_cast<const double*>(grho + gi);
+            const double2 g =
+                make_double2(__builtin_nontemporal_load(gq), __builtin_nontemporal_load(gq + 1));
             re += pv[vl].x * g.x - pv[vl].y * g.y;
             im += pv[vl].x * g.y + pv[vl].y * g.x;
             av[vl].x += pc.x * g.x + pc.y * g.y;  // pc * conj(g)
