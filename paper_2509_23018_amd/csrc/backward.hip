@@ -333,9 +333,13 @@ __global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int j2 = rb * 16 + 4 * t + kq, j3 = nb * 16 + row;
-                    if (j2 < n2 && j3 < n3)
-                        out[j2 * n3 + j3] =
-                            make_double2(dv * (g1[t] - g2[t]), dv * (g3[t] - g1[t] - g2[t]));
+                    if (j2 < n2 && j3 < n3) {
+                        // g_rho is read back by a later kernel, from HBM: the
+                        // stores are non-temporal
+                        double* q = reinterpret_cast<double*>(out + j2 * n3 + j3);
+                        __builtin_nontemporal_store(dv * (g1[t] - g2[t]), q);
+                        __builtin_nontemporal_store(dv * (g3[t] - g1[t] - g2[t]), q + 1);
+                    }
                 }
             }
         }
