@@ -89,3 +89,60 @@ def test_chi0_argument_checks(lib):
     assert lib.gw_chi0(ctypes.byref(p), 1, ctypes.byref(o), None) == -1
     assert lib.gw_chi0(None, 1, ctypes.byref(o), None) == -1
     assert lib.gw_chi0_backward(None, None, None, None, None, None, None, None) == -1
+
+
+def _pb(lib, nb=4, nr=16, keep=(), idx=(0, 1, 2), off=(0, 3), n_xi=2, theta=None):
+    """gw_pseudobands with host tables and dummy device pointers (the
+    argument checks run on the host before anything touches them)."""
+    k = np.asarray(keep, np.int32)
+    ix = np.asarray(idx, np.int32)
+    of = np.asarray(off, np.int32)
+    th = np.zeros(max(1, len(ix) * n_xi)) if theta is None else np.asarray(theta, np.float64)
+    st = lib.gw_pseudobands(16, 16, nb, nr, k.ctypes.data if len(k) else None, len(k),
+                            ix.ctypes.data, of.ctypes.data, len(of) - 1, n_xi, th.ctypes.data,
+                            16, 16, None)
+    return st, lib.gw_last_error().decode()
+
+
+def test_pseudobands_argument_checks(lib):
+    assert _pb(lib, off=(0, 3, 3), idx=(0, 1, 2)) == (-1, "slice 1 is empty")
+    assert _pb(lib, off=(1, 3))[0] == -1
+    st, msg = _pb(lib, idx=(0, 1, 4))
+    assert st == -1 and "out of range" in msg
+    st, msg = _pb(lib, keep=(7,))
+    assert st == -1 and "out of range" in msg
+    st, msg = _pb(lib, n_xi=9)
+    assert st == -1 and "n_xi" in msg
+    st, msg = _pb(lib, theta=[0.0, np.nan, 0.0, 0.0, 0.0, 0.0])
+    assert st == -1 and "finite" in msg
+    st, msg = _pb(lib, nr=1 << 31)
+    assert st == -1 and "2^31" in msg
+    n = 65536
+    st, msg = _pb(lib, nb=n, idx=np.arange(n), off=np.arange(n + 1), n_xi=1)
+    assert st == -4 and "65535" in msg
+    # nothing to produce: returns before any device work
+    z = np.zeros(1, np.int32)
+    assert lib.gw_pseudobands(None, None, 0, 1, None, 0, None, z.ctypes.data, 0, 2, None,
+                              None, None, None) == 0
+
+
+def test_pseudoband_recipe():
+    """The recipe protects the lowest energies and cuts the rest, in energy
+    order, into consecutive slices of the given sizes; the phases are in
+    [0, 1) with one row per pseudoband."""
+    from workloads import gen
+    rng = np.random.default_rng(2)
+    e = rng.random(40)
+    keep, slices, theta = gen.pseudoband_recipe(e, 6, [4, 10, 20], 3, seed=9)
+    order = np.argsort(e, kind="stable")
+    assert np.array_equal(keep, order[:6])
+    assert np.array_equal(np.concatenate(slices), order[6:])
+    assert [len(s) for s in slices] == [4, 10, 20]
+    for a, b in zip(slices[:-1], slices[1:]):
+        assert e[a].max() <= e[b].min()
+    assert [t.shape for t in theta] == [(3, 4), (3, 10), (3, 20)]
+    assert all(((t >= 0) & (t < 1)).all() for t in theta)
+    _, _, again = gen.pseudoband_recipe(e, 6, [4, 10, 20], 3, seed=9)
+    assert all(np.array_equal(a, b) for a, b in zip(theta, again))
+    with pytest.raises(ValueError):
+        gen.pseudoband_recipe(e, 6, [4, 10], 3, seed=9)
