@@ -22,4 +22,6 @@ from .chi0_oracle import (  # noqa: F401
     chi0_entries,
     chi0_backward,
     pseudobands,
+    static_subspace_basis,
+    chi0_subspace,
 )

@@ -14,7 +14,11 @@ What it computes (Overview of the Problem; Eq. (4) of the paper):
   ``Delta_vc(z) = 1/(E_v - E_c + z) + 1/(E_v - E_c - z)`` (the paper only
   says that Delta contains E_v, E_c and the frequency);
 * its adjoint with respect to psi_v, psi_c, E_v and E_c (not in the paper;
-  derived from the two definitions above by the chain rule).
+  derived from the two definitions above by the chain rule);
+* the static subspace of the Fast Full-Frequency GW section: the eigenvectors
+  of chi(0) with the largest |eigenvalue| as the columns of C_s, and Eq. (6),
+  chi0 in that subspace from the transformed matrix elements M^B = M C_s;
+* stochastic pseudobands (Reduced Cost and Scaling section).
 
 The sum over pairs is taken in chunks of pairs, the way the paper's NV-Block
 scheme splits the sum over valence bands (Fast Full-Frequency GW section);
@@ -218,3 +222,45 @@ def pseudobands(psi, e, keep, slices, n_xi, theta):
     nr = psi.shape[1]
     out = np.array(rows, dtype=np.complex128).reshape(len(rows), nr)
     return out, np.array(ens, dtype=np.float64)
+
+
+def static_subspace_basis(chi_static, n_eig):
+    """Diag of the static subspace method (Fast Full-Frequency GW section): the
+    static polarizability is diagonalised and its ``n_eig`` most significant
+    eigenvectors, read as those of largest |eigenvalue|, become the columns of
+    C_s.  Returns ``(C_s [N_G, n_eig], eigenvalues [n_eig])`` in decreasing
+    |eigenvalue| (for the negative semidefinite chi0(0): most negative first).
+    A library Hermitian eigensolver is the step.
+
+    Parity: pinned by a matrix built from a known spectrum, by plane waves
+    (diagonal chi, unit-vector basis) and by the diagonal static chi in the
+    subspace."""
+    lam, vec = np.linalg.eigh(np.asarray(chi_static, np.complex128))
+    order = np.argsort(-np.abs(lam), kind="stable")[:int(n_eig)]
+    return vec[:, order], lam[order]
+
+
+def chi0_subspace(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, basis, spin=2.0,
+                  pair_chunk=4096) -> np.ndarray:
+    """Eq. (6): chi_BB'(z) = s * sum_vc conj(M^B_vc) Delta_vc(z) M^B'_vc, with
+    the subspace matrix elements M^B_vc = sum_G M^G_vc C_s^{GB} (the transform
+    the paper states after Eq. (6)), summed over chunks of pairs.  ``basis`` is
+    C_s, ``[N_G, n_eig]``.  Returns ``[N_z, n_eig, n_eig]``.
+
+    Parity: pinned by the full basis (C_s chi_B C_s^H = chi of Eq. (4)), by
+    the paper's identity chi_BB' = C_s^H chi C_s on a partial basis, and by
+    plane waves."""
+    nv, nc = psi_v.shape[0], psi_c.shape[0]
+    z = np.asarray(z, np.complex128).reshape(-1)
+    basis = np.asarray(basis, np.complex128)
+    nb = basis.shape[1]
+    delta = energy_factor(e_v, e_c, z)
+    chi = np.zeros((z.size, nb, nb), dtype=np.complex128)
+    npairs = nv * nc
+    step = max(1, int(pair_chunk))
+    for k0 in range(0, npairs, step):
+        k1 = min(npairs, k0 + step)
+        mb = mtxel(psi_v, psi_c, gvec, n, volume, pairs=range(k0, k1)) @ basis
+        for w in range(z.size):
+            chi[w] += spin * ((np.conj(mb).T * delta[w, k0:k1][None, :]) @ mb)
+    return chi

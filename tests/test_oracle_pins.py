@@ -506,3 +506,102 @@ def test_pseudobands_singletons_leave_chi0_unchanged():
     ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume)
     got = oracle.chi0(p.psi_v, pc, p.e_v, ec, p.gvec, p.z, p.n, p.volume)
     assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- static subspace (Eq. (6))
+
+def _subspace_problem(seed=31, z=(0.0, 0.9j, 0.35 + 0.01j)):
+    return gen.make_problem((6, 6, 6), 3, 14, r2=6, z=z, seed=seed, pair_chunk=7)
+
+
+def test_subspace_basis_from_known_spectrum():
+    """A Hermitian matrix built from a chosen spectrum (mixed magnitudes,
+    non-positive, one degenerate pair below the cut): the basis spans the
+    eigenvectors of the largest |eigenvalues|, in decreasing |eigenvalue|."""
+    rng = np.random.default_rng(5)
+    ng = 12
+    x = rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng))
+    u, _ = np.linalg.qr(x)
+    lam = -np.array([9.0, 0.1, 4.0, 7.5, 0.0, 2.0, 0.3, 6.0, 1.0, 0.3, 5.0, 0.05])
+    a = (u * lam[None, :]) @ u.conj().T
+    cs, ev = oracle.static_subspace_basis(a, 5)
+    assert np.allclose(ev, [-9.0, -7.5, -6.0, -5.0, -4.0], rtol=0, atol=1e-12)
+    keep = [0, 3, 7, 10, 2]
+    proj = cs @ cs.conj().T
+    want = u[:, keep] @ u[:, keep].conj().T
+    assert np.abs(proj - want).max() < 1e-12
+    assert np.abs(cs.conj().T @ cs - np.eye(5)).max() < 1e-12
+    assert np.abs(a @ cs - cs * ev[None, :]).max() < 1e-12
+
+
+def test_subspace_full_basis_reproduces_chi():
+    """With n_eig = N_G the basis is unitary and C_s chi_B C_s^H is the chi of
+    Eq. (4) at every frequency."""
+    p = _subspace_problem()
+    chi = _chi(p)
+    cs, _ = oracle.static_subspace_basis(chi[0], p.ng)
+    assert np.abs(cs.conj().T @ cs - np.eye(p.ng)).max() < 1e-12
+    chib = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                                spin=p.spin, pair_chunk=p.pair_chunk)
+    back = np.einsum("gb,wbc,hc->wgh", cs, chib, cs.conj())
+    assert np.abs(back - chi).max() < 1e-12 * np.abs(chi).max()
+
+
+def test_subspace_static_chi_is_diagonal():
+    """In its own eigenbasis the static chi is diagonal with the eigenvalues,
+    and the subspace chi is Hermitian and negative semidefinite on the
+    imaginary axis, not Hermitian on the real axis."""
+    p = _subspace_problem(seed=32)
+    chi0 = _chi(p)[0]
+    cs, ev = oracle.static_subspace_basis(chi0, 9)
+    chib = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                                spin=p.spin, pair_chunk=p.pair_chunk)
+    scale = np.abs(ev).max()
+    assert np.abs(chib[0] - np.diag(ev)).max() < 1e-12 * scale
+    for w in (0, 1):
+        assert np.abs(chib[w] - chib[w].conj().T).max() < 1e-13 * scale
+        assert np.linalg.eigvalsh(chib[w]).max() <= 1e-13 * scale
+    assert np.abs(chib[2] - chib[2].conj().T).max() > 1e-6 * scale
+
+
+def test_subspace_matches_projection_identity():
+    """The paper's identity chi_BB' = sum_GG' conj(C_s^GB) chi_GG' C_s^G'B' on a
+    partial basis, the two sides computed along different routes (transformed
+    matrix elements vs the projected full chi)."""
+    p = _subspace_problem(seed=33)
+    chi = _chi(p)
+    cs, _ = oracle.static_subspace_basis(chi[0], 7)
+    chib = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                                spin=p.spin, pair_chunk=3)
+    proj = np.einsum("gb,wgh,hc->wbc", cs.conj(), chi, cs)
+    assert np.abs(chib - proj).max() < 1e-12 * np.abs(proj).max()
+
+
+def test_subspace_plane_waves():
+    """Plane waves make chi diagonal: the basis is the unit vectors of the G
+    with the largest |chi_GG(0)| (up to phase) and chi_B(z) is diagonal with
+    those chi_GG(z), the plane-wave closed form."""
+    n = (8, 8, 8)
+    kv = [(0, 0, 0), (1, 0, 0)]
+    kc = [(1, 0, 0), (2, 0, 0), (0, 1, 0), (0, 0, 2), (-1, 0, 0)]
+    pv, pc = _plane_waves(kv, n), _plane_waves(kc, n)
+    e_v = np.array([-0.2, -0.35])
+    e_c = np.array([0.1, 0.3, 0.45, 0.8, 1.05])
+    z = np.array([0.0, 0.6j, 0.25 + 0.005j])
+    gl = gen.gsphere(6)
+    want = np.zeros((3, gl.shape[0]), dtype=np.complex128)   # closed-form diagonal
+    for w, zz in enumerate(z):
+        for v, c in itertools.product(range(2), range(5)):
+            hit = np.where(np.all(gl == np.array(kv[v]) - np.array(kc[c]), axis=1))[0]
+            de = e_v[v] - e_c[c]
+            if hit.size:
+                want[w, hit[0]] += 2.0 * (1 / (de + zz) + 1 / (de - zz))
+    chi_static = np.diag(want[0])
+    n_eig = 4
+    cs, ev = oracle.static_subspace_basis(chi_static, n_eig)
+    top = np.argsort(-np.abs(want[0].real), kind="stable")[:n_eig]
+    assert len(set(np.abs(want[0].real[top]).round(12))) == n_eig   # distinct: unique basis
+    assert np.allclose(np.abs(cs[top, range(n_eig)]), 1.0, atol=1e-14)
+    chib = oracle.chi0_subspace(pv, pc, e_v, e_c, gl, z, n, VOL, cs, spin=2.0, pair_chunk=4)
+    for w in range(3):
+        assert np.abs(chib[w] - np.diag(want[w, top])).max() < 1e-12 * np.abs(want).max()
