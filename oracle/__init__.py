@@ -24,4 +24,6 @@ from .chi0_oracle import (  # noqa: F401
     pseudobands,
     static_subspace_basis,
     chi0_subspace,
+    coulomb,
+    epsilon_inverse,
 )

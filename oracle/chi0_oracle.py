@@ -18,6 +18,8 @@ What it computes (Overview of the Problem; Eq. (4) of the paper):
 * the static subspace of the Fast Full-Frequency GW section: the eigenvectors
   of chi(0) with the largest |eigenvalue| as the columns of C_s, and Eq. (6),
   chi0 in that subspace from the transformed matrix elements M^B = M C_s;
+* the inverse dielectric matrix of Eq. (3), eps^-1 = [I - v chi]^-1, with the
+  Coulomb interaction v_G = 4 pi / |q + G|^2 on the diagonal;
 * stochastic pseudobands (Reduced Cost and Scaling section).
 
 The sum over pairs is taken in chunks of pairs, the way the paper's NV-Block
@@ -264,3 +266,33 @@ def chi0_subspace(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, basis, spin=2.0,
         for w in range(z.size):
             chi[w] += spin * ((np.conj(mb).T * delta[w, k0:k1][None, :]) @ mb)
     return chi
+
+
+def coulomb(gvec, q=(0.0, 0.0, 0.0), cell_l=10.0) -> np.ndarray:
+    """Diagonal of the Coulomb matrix of Eq. (3) in the plane-wave basis,
+    ``v_G = 4 pi / |q + G|^2`` (Hartree atomic units) with G = 2 pi g / L for
+    the cubic cell of edge L and q in units of 2 pi / L.  Where q + G = 0 (the
+    G = 0 term at q = 0) the paper is silent; it is read as excluded, v = 0, so
+    that the head and wings of eps^-1 reduce to the identity there.
+
+    Parity: pinned by its closed form on axis vectors and the q = 0 head."""
+    k = (np.asarray(gvec, np.float64) + np.asarray(q, np.float64)[None, :]) * (2.0 * np.pi / cell_l)
+    k2 = np.sum(k * k, axis=1)
+    v = np.zeros_like(k2)
+    nz = k2 > 0.0
+    v[nz] = 4.0 * np.pi / k2[nz]
+    return v
+
+
+def epsilon_inverse(chi, v) -> np.ndarray:
+    """Eq. (3): eps^-1(z) = [I - v chi(z)]^-1 for every frequency, v the
+    diagonal Coulomb matrix (``v`` its diagonal, ``[N_G]``), chi
+    ``[N_z, N_G, N_G]``.  A library matrix inverse is the step.
+
+    Parity: pinned by v = 0 (identity), a diagonal chi, a rank-one chi
+    (Sherman-Morrison closed form) and the symmetrised form."""
+    chi = np.asarray(chi, np.complex128)
+    v = np.asarray(v, np.float64)
+    ng = chi.shape[-1]
+    eye = np.eye(ng, dtype=np.complex128)
+    return np.stack([np.linalg.inv(eye - v[:, None] * c) for c in chi.reshape(-1, ng, ng)])

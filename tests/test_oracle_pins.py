@@ -605,3 +605,65 @@ def test_subspace_plane_waves():
     chib = oracle.chi0_subspace(pv, pc, e_v, e_c, gl, z, n, VOL, cs, spin=2.0, pair_chunk=4)
     for w in range(3):
         assert np.abs(chib[w] - np.diag(want[w, top])).max() < 1e-12 * np.abs(want).max()
+
+
+# ---------------------------------------------------------------- inverse dielectric matrix (Eq. (3))
+
+def test_coulomb_closed_form():
+    g = np.array([[0, 0, 0], [1, 0, 0], [0, -2, 0], [1, 1, 1]], np.int32)
+    v = oracle.coulomb(g, cell_l=L)
+    b = 2 * np.pi / L
+    assert v[0] == 0.0                                   # the q = 0 head, read as excluded
+    assert np.allclose(v[1:], 4 * np.pi / (b * b * np.array([1.0, 4.0, 3.0])), rtol=1e-15)
+    vq = oracle.coulomb(g, q=(0.25, 0.0, 0.0), cell_l=L)
+    assert np.isclose(vq[0], 4 * np.pi / (0.25 * b) ** 2, rtol=1e-15)
+    assert np.isclose(vq[1], 4 * np.pi / (1.25 * b) ** 2, rtol=1e-15)
+
+
+def test_epsilon_inverse_identity_and_diagonal():
+    rng = np.random.default_rng(8)
+    ng = 9
+    chi = rng.standard_normal((2, ng, ng)) + 1j * rng.standard_normal((2, ng, ng))
+    assert np.abs(oracle.epsilon_inverse(chi, np.zeros(ng)) - np.eye(ng)).max() == 0.0
+    d = -rng.uniform(0.1, 2.0, ng)
+    v = rng.uniform(0.5, 3.0, ng)
+    got = oracle.epsilon_inverse(np.diag(d)[None], v)[0]
+    assert np.abs(got - np.diag(1.0 / (1.0 - v * d))).max() < 1e-15
+
+
+def test_epsilon_inverse_rank_one_sherman_morrison():
+    """chi = a u u^H: [I - v a u u^H]^-1 = I + a (v u) u^H / (1 - a u^H v u)."""
+    rng = np.random.default_rng(9)
+    ng = 11
+    u = rng.standard_normal(ng) + 1j * rng.standard_normal(ng)
+    v = rng.uniform(0.2, 1.5, ng)
+    for a in (-0.7, 0.3 + 0.2j):
+        chi = a * np.outer(u, u.conj())
+        x = a * v * u
+        want = np.eye(ng) + np.outer(x, u.conj()) / (1.0 - u.conj() @ x)
+        got = oracle.epsilon_inverse(chi[None], v)[0]
+        assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+
+
+def test_epsilon_inverse_symmetrised_form():
+    """For a Hermitian negative semidefinite chi (imaginary axis) the
+    symmetrised eps~ = I - v^1/2 chi v^1/2 is Hermitian with eigenvalues >= 1,
+    and eps^-1 = v^1/2 eps~^-1 v^-1/2: eps^-1 is similar to a Hermitian
+    matrix with eigenvalues in (0, 1]."""
+    p = _small_problem(z=(0.0, 0.7j))
+    chi = _chi(p)
+    v = oracle.coulomb(p.gvec, cell_l=p.volume ** (1 / 3))
+    einv = oracle.epsilon_inverse(chi, v)
+    sq = np.sqrt(v)
+    keep = v > 0
+    for w in range(2):
+        et = np.eye(p.ng) - sq[:, None] * chi[w] * sq[None, :]
+        lam = np.linalg.eigvalsh(et)
+        assert lam.min() >= 1.0 - 1e-12
+        sym = sq[keep, None] * np.linalg.inv(et)[np.ix_(keep, keep)] / sq[None, keep]
+        assert np.abs(einv[w][np.ix_(keep, keep)] - sym).max() < 1e-12 * np.abs(sym).max()
+        # the excluded head: row and column of G = 0 are those of the identity
+        assert np.abs(einv[w][0] - np.eye(p.ng)[0]).max() < 1e-12
+        assert np.abs(einv[w][:, 0] - np.eye(p.ng)[:, 0]).max() < 1e-12
+        ev = np.linalg.eigvals(einv[w])
+        assert np.all(ev.real > 0) and ev.real.max() <= 1.0 + 1e-12
