@@ -26,4 +26,6 @@ from .chi0_oracle import (  # noqa: F401
     chi0_subspace,
     coulomb,
     epsilon_inverse,
+    gpp_inner,
+    gpp_sigma_offdiag,
 )

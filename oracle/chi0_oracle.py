@@ -20,7 +20,10 @@ What it computes (Overview of the Problem; Eq. (4) of the paper):
   chi0 in that subspace from the transformed matrix elements M^B = M C_s;
 * the inverse dielectric matrix of Eq. (3), eps^-1 = [I - v chi]^-1, with the
   Coulomb interaction v_G = 4 pi / |q + G|^2 on the diagonal;
-* stochastic pseudobands (Reduced Cost and Scaling section).
+* stochastic pseudobands (Reduced Cost and Scaling section);
+* the full self-energy matrix of the GPP off-diagonal kernel: per band n and
+  energy E one matrix P^{nE}_{GG'} and the product of Eq. (1)'s matrix
+  elements around it, as the two complex GEMMs the paper counts in Eq. (8).
 
 The sum over pairs is taken in chunks of pairs, the way the paper's NV-Block
 scheme splits the sum over valence bands (Fast Full-Frequency GW section);
@@ -296,3 +299,42 @@ def epsilon_inverse(chi, v) -> np.ndarray:
     ng = chi.shape[-1]
     eye = np.eye(ng, dtype=np.complex128)
     return np.stack([np.linalg.inv(eye - v[:, None] * c) for c in chi.reshape(-1, ng, ng)])
+
+
+def gpp_inner(e, e_n, occupied, omega2, wtilde, v) -> np.ndarray:
+    """The GPP inner matrix P^{nE}_{GG'} of the off-diagonal kernel (Optimized
+    GPP Kernel for Off-Diagonal Self-Energy Matrix Elements section).  The
+    paper names the band- and energy-dependent matrices P and the generalized
+    plasmon-pole model, but prints no formula; it is read as the plasmon-pole
+    correlation term of that model,
+        P_GG' = Omega2_GG' v_G' / (2 wt_GG' (E - E_n - s_n wt_GG')),
+    s_n = -1 for an occupied band and +1 for an empty one, with E complex (its
+    imaginary part a broadening).  ``omega2`` [N_G, N_G] complex, ``wtilde``
+    [N_G, N_G] positive, ``v`` [N_G]."""
+    s_n = -1.0 if occupied else 1.0
+    wt = np.asarray(wtilde, np.float64)
+    return (np.asarray(omega2, np.complex128) * np.asarray(v, np.float64)[None, :]
+            / (2.0 * wt * (complex(e) - float(e_n) - s_n * wt)))
+
+
+def gpp_sigma_offdiag(m, e_n, occupied, energies, omega2, wtilde, v) -> np.ndarray:
+    """Full GPP self-energy matrix on an energy grid (the off-diagonal kernel):
+        Sigma_lm(E) = sum_n sum_GG' conj(M_ln(G)) P^{nE}_GG' M_mn(G'),
+    for every E of the grid, taken as the paper describes it: for each (n, E)
+    one GEMM N_Sigma x N_G x N_G (conj(M_n) P) and one N_Sigma x N_G x N_Sigma
+    (that product times M_n^T).  ``m`` [N_b, N_Sigma, N_G] (M_ln(G) for the
+    states l of interest and bands n), ``e_n`` [N_b], ``occupied`` [N_b]
+    booleans, ``energies`` [N_E] complex.  Returns [N_E, N_Sigma, N_Sigma].
+
+    Parity: pinned by a brute-force loop over n, G and G' and by linearity in
+    the bands."""
+    m = np.asarray(m, np.complex128)
+    nb, ns, _ = m.shape
+    energies = np.asarray(energies, np.complex128).reshape(-1)
+    out = np.zeros((energies.size, ns, ns), dtype=np.complex128)
+    for i, e in enumerate(energies):
+        for n in range(nb):
+            p = gpp_inner(e, e_n[n], bool(occupied[n]), omega2, wtilde, v)
+            t = np.conj(m[n]) @ p          # N_Sigma x N_G x N_G
+            out[i] += t @ m[n].T           # N_Sigma x N_G x N_Sigma
+    return out

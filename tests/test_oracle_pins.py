@@ -667,3 +667,57 @@ def test_epsilon_inverse_symmetrised_form():
         assert np.abs(einv[w][:, 0] - np.eye(p.ng)[:, 0]).max() < 1e-12
         ev = np.linalg.eigvals(einv[w])
         assert np.all(ev.real > 0) and ev.real.max() <= 1.0 + 1e-12
+
+
+# ---------------------------------------------------------------- GPP off-diagonal self-energy
+
+def _gpp_inputs(seed=5, nb=3, ns=4, ng=6, ne=3):
+    rng = np.random.default_rng(seed)
+    m = rng.standard_normal((nb, ns, ng)) + 1j * rng.standard_normal((nb, ns, ng))
+    e_n = np.sort(rng.uniform(-0.5, 1.0, nb))
+    occ = e_n < 0.1
+    x = rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng))
+    omega2 = 0.5 * (x + x.conj().T)
+    wt = rng.uniform(0.3, 1.5, (ng, ng))
+    wt = 0.5 * (wt + wt.T)
+    v = rng.uniform(0.1, 2.0, ng)
+    energies = np.linspace(-0.6, 1.2, ne) + 0.05j
+    return m, e_n, occ, energies, omega2, wt, v
+
+
+def test_gpp_offdiag_brute_force():
+    """Scalar loops over E, l, m, n, G, G' with the plasmon-pole term written
+    out, against the GEMM-pair form."""
+    m, e_n, occ, energies, omega2, wt, v = _gpp_inputs()
+    got = oracle.gpp_sigma_offdiag(m, e_n, occ, energies, omega2, wt, v)
+    nb, ns, ng = m.shape
+    for i, e in enumerate(energies):
+        for l, mm in itertools.product(range(ns), range(ns)):
+            acc = 0j
+            for n in range(nb):
+                sgn = -1.0 if occ[n] else 1.0
+                for g, h in itertools.product(range(ng), range(ng)):
+                    pole = e - e_n[n] - sgn * wt[g, h]
+                    acc += (m[n, l, g].conjugate() * omega2[g, h] * v[h] * m[n, mm, h]
+                            / (2.0 * wt[g, h] * pole))
+            assert abs(got[i, l, mm] - acc) < 1e-12 * max(1.0, abs(acc))
+
+
+def test_gpp_offdiag_band_additivity_and_occupation():
+    """The bands add; flipping a band's occupation moves its pole from
+    E_n + wt to E_n - wt (a different result)."""
+    m, e_n, occ, energies, omega2, wt, v = _gpp_inputs(seed=6, nb=4)
+    full = oracle.gpp_sigma_offdiag(m, e_n, occ, energies, omega2, wt, v)
+    a = oracle.gpp_sigma_offdiag(m[:2], e_n[:2], occ[:2], energies, omega2, wt, v)
+    b = oracle.gpp_sigma_offdiag(m[2:], e_n[2:], occ[2:], energies, omega2, wt, v)
+    assert np.abs(full - a - b).max() < 1e-13 * np.abs(full).max()
+    flip = oracle.gpp_sigma_offdiag(m, e_n, ~occ, energies, omega2, wt, v)
+    assert np.abs(flip - full).max() > 1e-3 * np.abs(full).max()
+    # a single G: Sigma = sum_n conj(M_n) M_n^T * Omega2 v / (2 wt (E - E_n - s wt))
+    one = oracle.gpp_sigma_offdiag(m[:, :, :1], e_n, occ, energies, omega2[:1, :1], wt[:1, :1],
+                                   v[:1])
+    for i, e in enumerate(energies):
+        want = sum(np.outer(m[n, :, 0].conj(), m[n, :, 0]) * omega2[0, 0] * v[0]
+                   / (2 * wt[0, 0] * (e - e_n[n] - (-1.0 if occ[n] else 1.0) * wt[0, 0]))
+                   for n in range(m.shape[0]))
+        assert np.abs(one[i] - want).max() < 1e-13 * np.abs(want).max()
