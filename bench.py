@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the chi0 build (MTXEL + CHI0) on one MI355X.
 
-Workload (default): chi0 at q = 0 on a 48^3 grid (L = 10 bohr) with 64
-valence x 960 conduction bands (61,440 pairs streamed in chunks of at most
-4,096), the complete G-sphere |g|^2 <= 61 (2,007 vectors) and 4 real
-frequencies omega in [0, 1] Ha with eta = 0.005 Ha, FP64 throughout.
-Inputs are seeded synthetic orthonormal wavefunctions (no DFT data).
+Contract workload (default, ``--workload chi0_72cube``): the precision study
+of chi0 at q = 0 on a 72^3 grid (L = 10 bohr) with 256 valence x 3,840
+conduction bands (983,040 pairs), the complete G-sphere |g|^2 <= 126 (6,031
+vectors) and 8 imaginary frequencies on a Gauss-Legendre grid.  Inputs are
+seeded Gaussian wavefunctions orthonormalised on the grid (no DFT data).
 
-One step = one gw_chi0 call: every chunk's MTXEL, energy factor and CHI0
-contraction for all frequencies, inputs already resident in HBM.  The JSON
-line reports canonical TFLOP/s (8 N_G^2 pairs N_omega per step, the complex
-GEMM count convention) and pairs/s, the roofline of the dominant kernel
-(chi0_f64, FP64 MFMA) from HIP events recorded on the stream it runs on, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+One step = one gw_chi0 call over one NV block (16 valence bands x all
+conduction bands, 61,440 pairs, streamed in chunks of 4 x 1,024 pairs)
+accumulated into the full chi with the Hermitian shortcut kept; 16 steps
+build the whole chi0, inputs already resident in HBM.  The JSON line reports
+canonical TFLOP/s (8 N_G^2 pairs N_omega per step, the complex GEMM count
+convention) and pairs/s, the roofline of the dominant kernel (chi0_f64, FP64
+MFMA, executed flops) from HIP events recorded on the stream it runs on,
+MTXEL's share and rate, one whole build in FP64, FP32 and split BF16 with
+errors against the device FP64 build (32 rows), every precision on a
+4 x 256-band sample against the FP64 oracle, and the oracle's time on that
+sample (the CPU baseline).
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-legs]
+    python bench.py --workload {chi0_48cube,batched_40cube_64q,adjoint_32cube,
+                                pseudobands_48cube}
     python bench.py --calibrate-copy     # plain copy kernel for counter scaling
 """
 from __future__ import annotations
@@ -80,20 +87,24 @@ def calibrate_copy():
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="chi0_72cube: time FP64 only (no FP32 / split legs, no error sample)")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--split-slices", type=int, nargs="*", default=[3, 4, 5],
-                    help="slice counts of the split-BF16 runs (empty: none)")
-    ap.add_argument("--workload", default="chi0_48cube",
-                    choices=["chi0_48cube", "batched_40cube_64q", "precision_72cube",
+    ap.add_argument("--split-slices", type=int, nargs="*", default=None,
+                    help="slice counts of the split-BF16 runs (default 3 4 5; empty: none)")
+    ap.add_argument("--workload", default="chi0_72cube",
+                    choices=["chi0_72cube", "chi0_48cube", "batched_40cube_64q",
                              "adjoint_32cube", "pseudobands_48cube"],
-                    help="chi0_48cube: the contract line (default); the others print a "
+                    help="chi0_72cube: the contract line (default); the others print a "
                          "measurement line of their own")
     ap.add_argument("--pb-xi", type=int, default=4,
                     help="pseudobands per slice of the pseudobands_48cube workload (1..8)")
     args = ap.parse_args()
+    if args.split_slices is None:
+        args.split_slices = [3, 4, 5]
     if args.gpus != 1:
         print("bench.py measures one GPU: the chi0 build here runs on a single MI355X "
               "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
@@ -101,19 +112,321 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload == "batched_40cube_64q":
-        bench_batched(args)
-        return
-    if args.workload == "precision_72cube":
-        bench_precision(args)
-        return
-    if args.workload == "adjoint_32cube":
-        bench_adjoint(args)
-        return
-    if args.workload == "pseudobands_48cube":
-        bench_pseudobands(args)
+    {"chi0_72cube": bench_chi0_72cube, "chi0_48cube": bench_chi0_48cube,
+     "batched_40cube_64q": bench_batched, "adjoint_32cube": bench_adjoint,
+     "pseudobands_48cube": bench_pseudobands}[args.workload](args)
+
+
+W2_BLOCK_NV = 16        # valence bands per step of the 72^3 workload (one NV block)
+W2_SAMPLE = (4, 256)    # valence x conduction bands of its oracle sample
+PROFILE_TRAFFIC_72 = os.path.join(ROOT, "profiles", "chi0_f64_kernel_72cube_983040pairs_pmc.md")
+
+
+def _log(t_start, msg):
+    print(f"[bench +{time.perf_counter() - t_start:6.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
+def host_info():
+    """Cores this process may use, the CPU model and the BLAS numpy calls."""
+    info = {"cores_available": len(os.sched_getaffinity(0)), "cpu_model": None, "blas": None,
+            "blas_threads": None}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = f"{blas[0].get('internal_api')} {blas[0].get('version')}"
+            info["blas_threads"] = max(int(i.get("num_threads", 1)) for i in blas)
+    except Exception:
+        pass
+    return info
+
+
+def chunk_pairs(nv, nc, chunk):
+    """Pairs of each streamed chunk: the library cuts the pairs into rectangles
+    of vb valence x cw conduction bands (at least 4 valence bands high)."""
+    cw = max(1, min(nc, chunk // max(1, min(nv, 4))))
+    vb = max(1, min(nv, chunk // cw))
+    return [min(vb, nv - v0) * min(cw, nc - c0)
+            for v0 in range(0, nv, vb) for c0 in range(0, nc, cw)]
+
+
+def f64_flops(kcs, ng, herm):
+    """(executed, algorithmic) flops of the chi0_f64 launches over chunks of
+    kcs pairs.  Executed: the default 64x64 tile takes a complex multiply-add
+    as three real MFMA products (6 flops) over whole tiles and 16-pair stages;
+    algorithmic: 8 flops per (pair, entry), a Hermitian frequency counting the
+    N_G (N_G + 1) / 2 entries on or above the diagonal."""
+    import numpy as np
+    herm = np.asarray(herm, bool)
+    nb = -(-ng // 64)
+    tiles = float(np.sum(np.where(herm, nb * (nb + 1) / 2.0, float(nb) * nb)))
+    entries = float(np.sum(np.where(herm, ng * (ng + 1) / 2.0, float(ng) * ng)))
+    executed = sum(6.0 * tiles * 64 * 64 * (-(-k // 16) * 16) for k in kcs)
+    algorithmic = sum(8.0 * k * entries for k in kcs)
+    return executed, algorithmic
+
+
+def bench_chi0_72cube(args):
+    """The contract line: chi0 of the 72^3 precision-study workload (256 x 3,840
+    bands = 983,040 pairs, 6,031 G, 8 imaginary frequencies), seeded recipe
+    bands orthonormalised on the device.  One step = one gw_chi0 call over one
+    NV block of 16 valence bands x all 3,840 conduction bands (61,440 pairs,
+    16 chunks of at most 4 x 1,024), accumulated into the full chi (the first
+    block of every cycle overwrites it): 16 steps build the whole chi0.  Also
+    times one whole build in FP64, FP32 and split BF16 (3, 4, 5 slices) with
+    their 32-row errors against the device FP64 build, and every precision on
+    a 4 x 256-band sample against the FP64 oracle, which is the CPU baseline."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    t_start = time.perf_counter()
+    dev = torch.device("cuda", 0)
+    w = gen.make_config_device(2, device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    n, nv, nc, ng, nz = w.n, w.nv, w.nc, w.ng, len(w.z)
+    _log(t_start, f"inputs ready: grid {n}, {nv}x{nc} recipe bands (orthonormalised on the "
+                  f"device), {ng} G, {nz} imaginary frequencies")
+    ev_d = torch.from_numpy(w.e_v).to(dev)
+    ec_d = torch.from_numpy(w.e_c).to(dev)
+    vbk = W2_BLOCK_NV
+    nblk = nv // vbk
+    chi = torch.empty((nz, ng, ng), dtype=torch.complex128, device=dev)
+    psi_c = w.psi_c
+    probs = [gw.Chi0Problem(n=n, volume=w.volume, psi_v=w.psi[b * vbk:(b + 1) * vbk],
+                            psi_c=psi_c, e_v=ev_d[b * vbk:(b + 1) * vbk], e_c=ec_d,
+                            gvec=w.gvec, z=w.z, chi=chi) for b in range(nblk)]
+    acc = gw.GW_FLAG_ACCUMULATE | gw.GW_FLAG_ACC_HERMITIAN
+
+    def step(k, prec="fp64", ns=0):
+        b = k % nblk
+        gw.gw_chi0(probs[b], precision=prec, n_slices=ns, pair_chunk=w.pair_chunk,
+                   flags=0 if b == 0 else acc)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    _log(t_start, f"{args.warmup} warm-up steps done")
+    kern_names = ("mtxel_zy", "mtxel_x", "delta", "chi0_f64", "chi0_tail", "mirror")
+    gw.profile_reset()
+    gw.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gw.profile_enable(False)
+    kernels = {k: gw.profile_read(k) for k in kern_names}
+    gw.profile_reset()
+    _log(t_start, f"{args.steps} timed steps in {elapsed:.3f} s; per-kernel ms/step: " +
+         ", ".join(f"{k} {v[1] / args.steps:.2f}" for k, v in kernels.items()))
+
+    pairs_step = vbk * nc
+    flops_step = 8.0 * ng * ng * pairs_step * nz
+    value = flops_step * args.steps / elapsed / 1e12
+    herm = np.real(w.z) == 0.0
+    kcs = chunk_pairs(vbk, nc, w.pair_chunk)
+    exec_step, alg_step = f64_flops(kcs, ng, herm)
+    n_chi, t_chi = kernels["chi0_f64"]
+    t_tail = kernels["chi0_tail"][1]
+    launches_per_step = max(1, n_chi // max(1, args.steps))
+    avg_ms = (t_chi + t_tail) / max(1, n_chi)
+    executed = exec_step / launches_per_step / (avg_ms * 1e-3) / 1e12
+    algorithmic = alg_step / launches_per_step / (avg_ms * 1e-3) / 1e12
+    mt_ms = (kernels["mtxel_zy"][1] + kernels["mtxel_x"][1]) / args.steps
+    # MTXEL's algorithmic bytes per step: every band of the step read once and
+    # M written once
+    mt_bytes = 16.0 * int(np.prod(n)) * (vbk + nc) + 16.0 * pairs_step * ng
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian bands orthonormalised on the grid)",
+        "config": {
+            "workload": "chi0 precision study at q=0: 72^3 grid, 256x3,840 bands (983,040 "
+                        "pairs), 6,031 G, 8 imaginary Gauss-Legendre frequencies, FP64; one "
+                        "step = one NV block of 16 valence bands (61,440 pairs, chunks of "
+                        "4x1,024) accumulated into chi, 16 steps = the whole chi0",
+            "grid": list(n), "pairs": nv * nc, "pairs_per_step": pairs_step, "n_g": ng,
+            "n_freq": nz, "pair_chunk": w.pair_chunk, "precision": "fp64",
+            "steps_per_build": nblk,
+        },
+        "pairs_per_s": round(pairs_step * args.steps / elapsed, 1),
+        "canonical_flops_per_step": flops_step,
+        "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in kernels.items()},
+        "roofline": {
+            "kernel": "chi0_f64_kernel",
+            "bound": "mfma",
+            "achieved": round(executed, 3),
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(executed / FP64_PEAK_TFLOPS, 4),
+            "traffic": read_traffic(profile=PROFILE_TRAFFIC_72),
+            "flops": "executed: 6 per complex multiply-add on the MFMAs (three real products), "
+                     "whole 64x64 tiles on or above the diagonal and 16-pair stages",
+            "launches": n_chi,
+            "flops_per_launch": exec_step / launches_per_step,
+            "avg_launch_ms": round(avg_ms, 4),
+            "tail_reduce_ms_per_launch": round(t_tail / max(1, n_chi), 4),
+            "algorithmic_tflops": round(algorithmic, 3),
+            "algorithmic_flops_per_launch": alg_step / launches_per_step,
+        },
+        "mtxel": {
+            "ms_per_step": round(mt_ms, 3),
+            "share_of_step": round(mt_ms / (elapsed / args.steps * 1e3), 4),
+            "pairs_per_s": round(pairs_step / (mt_ms * 1e-3), 1),
+            "algorithmic_bytes_per_step": mt_bytes,
+            "achieved_gbs": round(mt_bytes / (mt_ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(mt_bytes / (mt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bound": "FP64 MFMA (pruned DFT), not HBM",
+        },
+    }
+    if args.no_legs:
+        gw.release()
+        print(json.dumps(out), flush=True)
         return
 
+    rows = np.sort(np.random.default_rng(1002).choice(ng, 32, replace=False))
+    rows_d = torch.from_numpy(rows).to(dev)
+
+    def build(prec, ns):
+        """One whole chi0 (all 16 NV blocks); returns seconds and the 32 rows."""
+        step(0, prec, ns)                      # warm-up (plans, slice buffers)
+        torch.cuda.synchronize()
+        gw.profile_reset()
+        gw.profile_enable(True)
+        t = time.perf_counter()
+        for k in range(nblk):
+            step(k, prec, ns)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        gw.profile_enable(False)
+        ks = {k: round(gw.profile_read(k)[1] / nblk, 3)
+              for k in ("mtxel_zy", "mtxel_x", "split_prep", "chi0_split", "chi0_split_tail",
+                        "chi0_f32", "chi0_f64", "chi0_tail")
+              if gw.profile_read(k)[0] > 0}
+        gw.profile_reset()
+        return dt, chi[:, rows_d].clone(), ks
+
+    flops_build = 8.0 * ng * ng * nv * nc * nz
+    t64, ref_rows, ks64 = build("fp64", 0)
+    full = {"fp64": {"s_per_build": round(t64, 3), "tflops": round(flops_build / t64 / 1e12, 3),
+                     "pairs_per_s": round(nv * nc / t64, 1), "kernel_ms_per_step": ks64}}
+    _log(t_start, f"whole FP64 build {t64:.2f} s")
+    modes = [("fp32", 0)] + [("split_bf16", S) for S in args.split_slices]
+    for prec, ns in modes:
+        dt, got, ks = build(prec, ns)
+        err = float(torch.linalg.vector_norm(got - ref_rows) / torch.linalg.vector_norm(ref_rows))
+        errw = [float(torch.linalg.vector_norm(got[i] - ref_rows[i]) /
+                      torch.linalg.vector_norm(ref_rows[i])) for i in range(nz)]
+        full[f"{prec}{ns or ''}"] = {
+            "precision": prec, "n_slices": ns or None, "s_per_build": round(dt, 3),
+            "tflops": round(flops_build / dt / 1e12, 3), "pairs_per_s": round(nv * nc / dt, 1),
+            "speedup_vs_fp64": round(t64 / dt, 3), "rel_err_vs_device_fp64_32rows": err,
+            "rel_err_per_freq": errw, "kernel_ms_per_step": ks}
+        _log(t_start, f"whole {prec} S={ns} build {dt:.2f} s, 32-row error vs device FP64 "
+                      f"{err:.2e}")
+    out["whole_build"] = full
+    del ref_rows
+
+    # every precision on a 4 x 256-band sample of the same bands against the
+    # FP64 oracle (which is also the CPU baseline)
+    sv, sc = W2_SAMPLE
+    sp = gw.Chi0Problem(n=n, volume=w.volume, psi_v=w.psi[:sv], psi_c=psi_c[:sc],
+                        e_v=ev_d[:sv], e_c=ec_d[:sc], gvec=w.gvec, z=w.z)
+    dev_rows, dev_full = {}, None
+    for prec, ns in [("fp64", 0)] + modes:
+        gw.gw_chi0(sp, precision=prec, n_slices=ns, pair_chunk=w.pair_chunk)
+        torch.cuda.synchronize()
+        dev_rows[f"{prec}{ns or ''}"] = sp.chi[:, rows_d].cpu().numpy()
+        if prec == "fp64":
+            dev_full = sp.chi.cpu().numpy()
+    sp.chi = None
+    chi = None
+    for pr in probs:
+        pr.chi = None
+    torch.cuda.empty_cache()
+    hv = w.psi[:sv].cpu().numpy()
+    hc = psi_c[:sc].cpu().numpy()
+    _log(t_start, "device sample results taken; running the oracle on the sample")
+    cpu = cpu_baseline_sample(hv, hc, w.e_v[:sv], w.e_c[:sc], w.gvec, w.z, n, w.volume,
+                              w.spin, w.pair_chunk, dev_full, dev_rows, rows, nv * nc)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu["baseline"]
+    out["oracle_sample"] = cpu["errors"]
+    ok = [v for k, v in full.items() if k.startswith("split_bf16") and
+          cpu["errors"][k]["rel_err_32rows"] <= 1e-10 and v["rel_err_vs_device_fp64_32rows"] <= 1e-10]
+    out["split_bf16_at_1e-10"] = min(ok, key=lambda x: x["n_slices"]) if ok else None
+    _log(t_start, "done")
+    gw.release()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_sample(hv, hc, e_v, e_c, gvec, z, n, volume, spin, chunk, dev_full, dev_rows,
+                        rows, pairs_total):
+    """The FP64 oracle on the sample bands (hv x hc), timed on this host; the
+    device results of the same sample are compared with it: FP64 in full, every
+    precision on the 32 rows."""
+    import numpy as np
+
+    import oracle
+    info = host_info()
+    t0 = time.perf_counter()
+    ref = oracle.chi0(hv, hc, e_v, e_c, gvec, z, n, volume, spin=spin, pair_chunk=chunk)
+    dt = time.perf_counter() - t0
+    pairs = hv.shape[0] * hc.shape[0]
+    ng, nz = gvec.shape[0], len(z)
+    flops = 8.0 * ng * ng * pairs * nz
+    errors = {}
+    ref_rows = ref[:, rows]
+    for k, got in dev_rows.items():
+        errors[k] = {"rel_err_32rows": float(np.linalg.norm(got - ref_rows) /
+                                             np.linalg.norm(ref_rows))}
+    errors["fp64"]["rel_err_full"] = float(np.linalg.norm(dev_full - ref) / np.linalg.norm(ref))
+    errors["sample"] = (f"valence bands 0-{hv.shape[0] - 1} x conduction bands 0-{hc.shape[0] - 1} "
+                        f"({pairs} pairs), all {ng} G and {nz} frequencies; rows: 32 G indices "
+                        "drawn with numpy default_rng(1002)")
+    baseline = {
+        "value": round(flops / dt / 1e12, 5),
+        "unit": "TFLOP/s",
+        "cores": int(info["blas_threads"] or 1),
+        "kind": "oracle",
+        "sample": f"{pairs} of {pairs_total} pairs (valence 0-{hv.shape[0] - 1} x conduction "
+                  f"0-{hc.shape[0] - 1}), all {ng} G and {nz} frequencies; numpy FFT per pair "
+                  "(one thread) + BLAS contraction",
+        "seconds": round(dt, 2),
+        "pairs_per_s": round(pairs / dt, 2),
+        "cpu_model": info["cpu_model"],
+        "blas": info["blas"],
+        "cores_available": info["cores_available"],
+        "gpu_rel_err_on_sample": errors["fp64"]["rel_err_full"],
+    }
+    return {"baseline": baseline, "errors": errors}
+
+
+def bench_chi0_48cube(args):
+    """Workload 1 (48^3 grid, 64 x 960 bands, 2,007 G, 4 real frequencies);
+    one step = one gw_chi0 call over all 61,440 pairs."""
     import numpy as np
     import torch
 
@@ -209,18 +522,19 @@ def main():
         "roofline": {
             "kernel": "chi0_f64_kernel",
             "bound": "mfma",
-            "achieved": round(achieved, 3),
+            "achieved": round(executed, 3),
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "frac": round(executed / FP64_PEAK_TFLOPS, 4),
             "traffic": traffic,
+            "flops": "executed: 6 per complex multiply-add on the MFMAs (three real products), "
+                     "whole 64x64 tiles and 16-pair stages",
             "launches": n_chi,
-            "executed_tflops": round(executed, 3),
-            "executed_frac": round(executed / FP64_PEAK_TFLOPS, 4),
-            "executed_flops_per_launch": exec_per_launch,
+            "flops_per_launch": exec_per_launch,
             "avg_launch_ms": round(avg_ms, 4),
             "tail_reduce_ms_per_launch": round(t_tail / max(1, n_chi), 4),
-            "flops_per_launch": flops_per_launch,
+            "algorithmic_tflops": round(achieved, 3),
+            "algorithmic_flops_per_launch": flops_per_launch,
         },
     }
 
@@ -330,7 +644,7 @@ def bench_batched(args):
         t_cap = time.perf_counter() - t_cap
         gw.profile_reset()
         gw.profile_enable(True)
-        dt = _timed(call, max(1, args.steps))
+        dt = _timed(call, max(1, min(args.steps, 3)))
         gw.profile_enable(False)
         gw.profile_reset()
         run = {"precision": prec, "n_slices": ns or None, "s_per_call": round(dt, 4),
@@ -349,64 +663,6 @@ def bench_batched(args):
               f"{free / 2**30:.1f} of {total / 2**30:.1f} GiB, torch reserved "
               f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     out["err_sample_q"] = keep
-    gw.release()
-    print(json.dumps(out), flush=True)
-
-
-def bench_precision(args):
-    """chi0 on a 72^3 grid, 256 x 3,840 bands (983,040 pairs), 6,031 G, 8
-    imaginary frequencies, in FP64, FP32 and split BF16; errors against the
-    FP64 result on the 32 G rows drawn with seed 1002.  Band sets are drawn
-    on the GPU (timing only)."""
-    import numpy as np
-    import torch
-
-    import paper_2509_23018_amd as gw
-    from workloads import gen
-
-    dev = torch.device("cuda", 0)
-    sh = gen.CONFIG_SHAPES[2]
-    n, nv, nc = sh["n"], sh["nv"], sh["nc"]
-    nr = int(np.prod(n))
-    volume = gen.CELL_L ** 3
-    z = gen.frequencies(*sh["freq"])
-    gvec = gen.gsphere(sh["r2"])
-    rng = np.random.default_rng(2)
-    e_v, e_c = gen.band_energies(rng, nv, nc)
-    psi = gen.device_bands(nv + nc, nr, seed=2, volume=volume, device=dev)
-    torch.cuda.empty_cache()
-    ng = gvec.shape[0]
-    rows = np.sort(np.random.default_rng(1002).choice(ng, 32, replace=False))
-    flops = 8.0 * ng * ng * nv * nc * len(z)
-    prob = gw.Chi0Problem(n=n, volume=volume, psi_v=psi[:nv], psi_c=psi[nv:],
-                          e_v=torch.from_numpy(e_v).to(dev), e_c=torch.from_numpy(e_c).to(dev),
-                          gvec=gvec, z=z)
-    # plans and tables of this grid and G list, built outside the timed calls
-    warm = gw.Chi0Problem(n=n, volume=volume, psi_v=psi[:1], psi_c=psi[nv:nv + 64],
-                          e_v=prob.e_v[:1], e_c=prob.e_c[:64], gvec=gvec, z=z)
-    out = {"workload": "precision_72cube", "pairs": nv * nc, "n_g": ng, "n_freq": len(z),
-           "canonical_flops": flops, "data": "synthetic (device Gaussian bands)",
-           "err_rows": "32 rows, numpy default_rng(1002)", "runs": []}
-    ref = None
-    modes = [("fp64", 0), ("fp32", 0)] + [("split_bf16", k) for k in args.split_slices]
-    for prec, ns in modes:
-        gw.gw_chi0(warm, precision=prec, n_slices=ns)
-        torch.cuda.synchronize()
-        dt = _timed(lambda: gw.gw_chi0(prob, precision=prec, n_slices=ns), 1)
-        sub = prob.chi[:, torch.from_numpy(rows).to(dev)].clone()
-        run = {"precision": prec, "n_slices": ns or None, "s_per_call": round(dt, 3),
-               "tflops": round(flops / dt / 1e12, 3), "pairs_per_s": round(nv * nc / dt, 1)}
-        if prec == "fp64":
-            ref = sub
-        else:
-            run["rel_err_vs_fp64"] = float(torch.linalg.vector_norm(sub - ref) /
-                                           torch.linalg.vector_norm(ref))
-            run["rel_err_per_freq"] = [float(torch.linalg.vector_norm(sub[w] - ref[w]) /
-                                             torch.linalg.vector_norm(ref[w]))
-                                       for w in range(len(z))]
-            run["speedup_vs_fp64"] = round(out["runs"][0]["s_per_call"] / dt, 3)
-        out["runs"].append(run)
-        print(f"[bench] precision {prec} S={ns}: {dt:.2f} s", file=sys.stderr, flush=True)
     gw.release()
     print(json.dumps(out), flush=True)
 

@@ -35,12 +35,26 @@
  * - Device pointers are HIP device memory of the current device; host
  *   pointers are ordinary host memory, read before the call returns.
  * - All work is enqueued on `stream` (a hipStream_t, NULL = legacy default
- *   stream) and the call returns without synchronising.  The caller owns
- *   every pointer it passes and must keep device buffers alive until the
- *   stream reaches the end of the call's work.  The library owns only its
- *   cached plans (gather tables) and scratch buffers, one set per device and
- *   stream; gw_release() frees them.  Two calls that run concurrently on the
- *   same stream are serialised by the stream; the host side is thread-safe.
+ *   stream).  The caller owns every pointer it passes and must keep device
+ *   buffers alive until the stream reaches the end of the call's work.
+ * - Device scratch.  gw_chi0, gw_chi0_backward and gw_pseudobands take their
+ *   scratch (streamed M chunks, energy factors, slices, tables) from a
+ *   caller-owned `workspace` of at least gw_workspace_bytes() bytes when one
+ *   is given; such a call enqueues its work and returns, with no device
+ *   allocation and no wait on the device.  A workspace that is too small is
+ *   GW_EINVAL, with every output untouched.  Without a workspace the library
+ *   uses a scratch buffer of its own per device and stream, which it grows
+ *   on demand (growing waits for the stream).  One workspace may serve
+ *   consecutive calls on one stream; calls that overlap (other streams) need
+ *   workspaces of their own.
+ * - Library-owned state, created on first use and kept until gw_release():
+ *   one plan (gather and twiddle tables) per device, grid and G list (at most
+ *   256 per device; a dropped plan is freed once the work that reads it has
+ *   completed), tile-order tables, a companion stream per caller stream,
+ *   pinned host buffers that stage host tables without blocking, captured
+ *   graphs (GW_FLAG_GRAPH) and autotuning results.  Creating them allocates
+ *   and uploads once; a first call with a new grid, G list or tile shape may
+ *   therefore wait for its own table upload.  The host side is thread-safe.
  * - Errors: every argument check runs on the host before anything is
  *   enqueued; a non-OK status leaves every output untouched and
  *   gw_last_error() returns a message (thread-local).  No C++ exception
@@ -59,7 +73,7 @@
 extern "C" {
 #endif
 
-#define GW_ABI_VERSION 1
+#define GW_ABI_VERSION 2
 
 typedef struct { double re, im; } gw_c128;
 
@@ -102,6 +116,15 @@ enum {
                                             default 64x64 tiles; takes precedence over the
                                             autotuner and over GW_CHI0_VARIANT; ignored by the
                                             other precisions */
+#define GW_FLAG_ACC_HERMITIAN (1u << 5)  /* with GW_FLAG_ACCUMULATE: the caller states that
+                                            chi[w] is already Hermitian for every frequency with
+                                            Re z = 0 (for instance the sum of earlier calls over
+                                            other valence bands, as in the paper's NV-Block
+                                            split of the band sum); those frequencies keep the
+                                            Hermitian shortcut: only tiles on or above the
+                                            diagonal are accumulated and the rest is mirrored
+                                            from them (what the lower triangle held is
+                                            overwritten).  GW_EINVAL without GW_FLAG_ACCUMULATE */
 
 /* One chi0 problem (one q-point). */
 typedef struct {
@@ -125,6 +148,9 @@ typedef struct {
     int32_t        pair_chunk;  /* pairs per streamed M chunk; 0 = 4096 */
     uint32_t       flags;       /* GW_FLAG_* */
     double         spin;        /* spin factor s of Eq. (4); 0 = 2 */
+    void*          workspace;   /* device scratch owned by the caller, 256-byte aligned, or NULL
+                                   for the library's own; read and written by the call's work */
+    size_t         workspace_bytes;  /* its size; at least gw_workspace_bytes() for the call */
 } gw_opts_t;
 
 /*
@@ -197,6 +223,19 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
                              const gw_opts_t* opts, void* stream);
 
 /*
+ * gw_workspace_bytes -- device scratch, in bytes, that gw_chi0 (backward = 0)
+ * or gw_chi0_backward (backward = 1; probs[0] only, every gradient wanted)
+ * needs in opts->workspace for these problems and options (opts->workspace
+ * itself is ignored).  The same arguments are checked as by those calls; on an
+ * invalid argument it returns (size_t)-1 and gw_last_error() says why.  It may
+ * build the plans of the problems' G lists (library-owned, kept for the
+ * calls).  With GW_FLAG_GRAPH the workspace serves every replay of the
+ * captured graph, so the caller keeps it for as long as it replays.
+ */
+size_t gw_workspace_bytes(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* opts,
+                          int32_t backward);
+
+/*
  * gw_pseudobands -- stochastic pseudobands (Reduced Cost and Scaling section
  * of the paper): a band set compressed into
  *   the protected bands keep[0..nkeep), copied as they are, then for each
@@ -214,21 +253,125 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
  * n_xi      1..8 pseudobands per slice.
  * out_psi   device [nkeep + nslices*n_xi][nr], out_e device [same] (overwritten):
  *           the protected bands first, then slice by slice, j fastest.
- * The host tables are staged through host memory, so this call returns once
- * its work on `stream` has completed.  Returns GW_EINVAL for an index out of
- * range, an empty slice, n_xi outside 1..8, a non-finite theta or nr of 2^31
- * or more, and GW_EUNSUPPORTED for more than 65535 protected bands or slices.
+ * workspace device scratch owned by the caller (256-byte aligned) of at least
+ *           gw_pseudobands_workspace_bytes(nkeep, slice_off[nslices], nslices,
+ *           n_xi) bytes, or NULL for the library's own.
+ * The host tables are copied into the call's scratch through the library's
+ * pinned staging buffers, in stream order, so the call returns without
+ * waiting and the host arrays may be reused at once.  Returns GW_EINVAL for an
+ * index out of range, an empty slice, n_xi outside 1..8, a non-finite theta,
+ * nr of 2^31 or more or a workspace that is too small, and GW_EUNSUPPORTED for
+ * more than 65535 protected bands or slices.
  */
 gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int64_t nr,
                            const int32_t* keep, int32_t nkeep,
                            const int32_t* slice_idx, const int32_t* slice_off, int32_t nslices,
                            int32_t n_xi, const double* theta,
-                           gw_c128* out_psi, double* out_e, void* stream);
+                           gw_c128* out_psi, double* out_e,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* Scratch bytes gw_pseudobands needs for nkeep protected bands, nidx slice
+ * entries in nslices slices and n_xi pseudobands per slice. */
+size_t gw_pseudobands_workspace_bytes(int32_t nkeep, int64_t nidx, int32_t nslices,
+                                      int32_t n_xi);
+
+/*
+ * Static subspace (Fast Full-Frequency GW section of the paper, Eq. (6)).
+ * The static polarizability chi(0) of Eq. (4) is diagonalised and its n_eig
+ * most significant eigenvectors, the columns of the N_G x n_eig matrix C_s,
+ * span the subspace in which the polarizability at the other frequencies is
+ * built: M^B_vc = sum_G M^G_vc C_s^{GB} and
+ *     chi_BB'(z) = s * sum_vc conj(M^B_vc) Delta_vc(z) M^B'_vc,
+ * which equals C_s^H chi(z) C_s.
+ */
+typedef struct {
+    double   tol;         /* residual |chi x - lambda x| / b of every kept pair, b a bound of
+                             |chi| (largest absolute row sum); 0 = 1e-10 */
+    int32_t  max_iter;    /* filtered subspace iterations; 0 = 60 */
+    int32_t  guard;       /* block columns beyond n_eig; 0 = max(16, n_eig / 8) */
+    int32_t  max_degree;  /* Chebyshev filter degree cap; 0 = 16 */
+    uint64_t seed;        /* start block (a counter-based hash of seed and index) */
+    void*    workspace;   /* device scratch owned by the caller (256-byte aligned) or NULL */
+    size_t   workspace_bytes;
+} gw_diag_opts_t;
+
+typedef struct {
+    int32_t iterations;   /* filtered iterations made */
+    int32_t degree;       /* filter degree of the last one */
+    double  residual;     /* largest relative residual of the kept pairs */
+    double  bound;        /* the bound b */
+} gw_diag_info_t;
+
+/*
+ * gw_subspace_basis -- Diag: the n_eig eigenvectors of the Hermitian static
+ * polarizability with the largest |eigenvalue|.  chi0(0) is negative
+ * semidefinite (every valence energy below every conduction energy), so those
+ * are its most negative eigenvalues; the matrix must be Hermitian and negative
+ * semidefinite (positive eigenvalues are treated as insignificant).
+ * Chebyshev-filtered subspace iteration with Rayleigh-Ritz steps on FP64
+ * MFMA GEMMs, Ritz problems by Jacobi rotations, all on the device.
+ *
+ * chi_static  device [ng][ng], read only.
+ * basis       device OUT [ng][n_eig] row-major: column j is the j-th
+ *             eigenvector (orthonormal columns); a column's phase, and the
+ *             basis of a degenerate eigenspace, are arbitrary.
+ * eigenvalues device OUT [n_eig], increasing (most negative first).
+ * info        HOST OUT, may be NULL.
+ * The iteration reads convergence data back, so the call waits for `stream`.
+ * Not converging within max_iter is not an error: info->residual says how far
+ * it got.  GW_EINVAL for n_eig outside [1, ng], NULL pointers, bad options or
+ * a workspace smaller than gw_subspace_basis_workspace_bytes().
+ */
+gw_status_t gw_subspace_basis(const gw_c128* chi_static, int32_t ng, int32_t n_eig,
+                              gw_c128* basis, double* eigenvalues, const gw_diag_opts_t* opts,
+                              gw_diag_info_t* info, void* stream);
+size_t gw_subspace_basis_workspace_bytes(int32_t ng, int32_t n_eig, const gw_diag_opts_t* opts);
+
+/*
+ * gw_chi0_subspace -- Transf and CHI-Freq: chi_BB'(z) of Eq. (6) for one
+ * problem, M streamed in chunks as in gw_chi0, each chunk transformed to the
+ * subspace (M^B = M C_s, FP64 MFMA GEMM) before the contraction over n_eig
+ * columns.  prob->chi is device OUT [nz][n_eig][n_eig]; basis is device
+ * [ng][n_eig] (for instance from gw_subspace_basis).  The options, flags
+ * (except GW_FLAG_GRAPH, GW_EUNSUPPORTED), precisions and workspace rules are
+ * those of gw_chi0; the workspace size is
+ * gw_chi0_subspace_workspace_bytes().
+ */
+gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis, int32_t n_eig,
+                             const gw_opts_t* opts, void* stream);
+size_t gw_chi0_subspace_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
+                                        const gw_opts_t* opts);
+
+/*
+ * Dense building blocks of the subspace, dielectric and self-energy paths.
+ *
+ * gw_zgemm -- C = alpha op(A) op(B) + beta C for `batch` products (pointers
+ * advanced by the strides, in elements), complex FP64 on MFMA, row-major:
+ * op(A) is m x k, op(B) k x n, C m x n; op 'N' (as stored), 'T' (transposed:
+ * A stored k x m) or 'C' (conjugate transposed).  All pointers are device
+ * memory.  beta = 0 never reads C.  Asynchronous.
+ */
+gw_status_t gw_zgemm(char opa, char opb, int32_t m, int32_t n, int32_t k, gw_c128 alpha,
+                     const gw_c128* a, int64_t lda, int64_t stride_a, const gw_c128* b,
+                     int64_t ldb, int64_t stride_b, gw_c128 beta, gw_c128* c, int64_t ldc,
+                     int64_t stride_c, int32_t batch, void* stream);
+
+/*
+ * gw_heev -- eigenvalues w [batch][n] (increasing) and eigenvectors v
+ * [batch][n][n] (columns) of `batch` Hermitian n x n matrices a (device,
+ * read only), by cyclic Jacobi rotations in parallel order until the
+ * off-diagonal norm is below tol (0 = 1e-15) of the norm.  Waits for
+ * `stream`.  workspace: NULL or gw_heev_workspace_bytes(n, batch) bytes.
+ */
+gw_status_t gw_heev(const gw_c128* a, int32_t n, int32_t batch, double* w, gw_c128* v,
+                    double tol, void* workspace, size_t workspace_bytes, void* stream);
+size_t gw_heev_workspace_bytes(int32_t n, int32_t batch);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* gw_last_error(void);
 
-/* Frees cached plans and scratch on every device (synchronises the device). */
+/* Frees cached plans, graphs, staging buffers and scratch on every device
+ * (waits for the work that uses them). */
 gw_status_t gw_release(void);
 
 /* GW_ABI_VERSION of the built library. */

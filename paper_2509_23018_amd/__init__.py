@@ -25,9 +25,11 @@ import torch  # noqa: F401  (loads the HIP runtime that libgw binds to)
 __all__ = [
     "GWError", "lib", "library_path", "GW_FP64", "GW_FP32", "GW_SPLIT_BF16", "GW_SPLIT_FP16",
     "GW_FLAG_NO_HERMITIAN", "GW_FLAG_ACCUMULATE", "GW_FLAG_GRAPH", "GW_FLAG_AUTOTUNE",
-    "GW_FLAG_FP64_TILE128",
-    "Chi0Problem", "gw_mtxel", "gw_chi0",
-    "gw_chi0_backward", "gw_pseudobands", "Chi0", "chi0", "release", "profile_enable",
+    "GW_FLAG_FP64_TILE128", "GW_FLAG_ACC_HERMITIAN",
+    "Chi0Problem", "gw_mtxel", "gw_chi0", "workspace_bytes", "new_workspace",
+    "pseudobands_workspace_bytes",
+    "gw_chi0_backward", "gw_pseudobands", "gw_subspace_basis", "gw_chi0_subspace",
+    "subspace_basis_workspace_bytes", "chi0_subspace_workspace_bytes", "gw_zgemm", "gw_heev", "Chi0", "chi0", "release", "profile_enable",
     "profile_reset",
     "profile_read",
 ]
@@ -38,6 +40,7 @@ GW_FLAG_ACCUMULATE = 1 << 1
 GW_FLAG_GRAPH = 1 << 2
 GW_FLAG_AUTOTUNE = 1 << 3
 GW_FLAG_FP64_TILE128 = 1 << 4
+GW_FLAG_ACC_HERMITIAN = 1 << 5
 PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "split_bf16": GW_SPLIT_BF16,
               "split_fp16": GW_SPLIT_FP16}
 
@@ -70,7 +73,24 @@ class _Problem(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_slices", ctypes.c_int32),
                 ("pair_chunk", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("spin", ctypes.c_double)]
+                ("spin", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class _C128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class _DiagOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("guard", ctypes.c_int32), ("max_degree", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class _DiagInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("bound", ctypes.c_double)]
 
 
 _LIB = None
@@ -100,7 +120,40 @@ def lib() -> ctypes.CDLL:
                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                     ctypes.c_void_p, ctypes.c_void_p]
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]
+        L.gw_pseudobands_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_pseudobands_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64,
+                                                     ctypes.c_int32, ctypes.c_int32]
+        L.gw_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32,
+                                         ctypes.POINTER(_Opts), ctypes.c_int32]
+        L.gw_subspace_basis.restype = ctypes.c_int32
+        L.gw_subspace_basis.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(_DiagOpts), ctypes.POINTER(_DiagInfo),
+                                        ctypes.c_void_p]
+        L.gw_subspace_basis_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_subspace_basis_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                                        ctypes.POINTER(_DiagOpts)]
+        L.gw_chi0_subspace.restype = ctypes.c_int32
+        L.gw_chi0_subspace.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(_Opts), ctypes.c_void_p]
+        L.gw_chi0_subspace_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_chi0_subspace_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32,
+                                                       ctypes.POINTER(_Opts)]
+        L.gw_zgemm.restype = ctypes.c_int32
+        L.gw_zgemm.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, _C128, ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                               _C128, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                               ctypes.c_int32, ctypes.c_void_p]
+        L.gw_heev.restype = ctypes.c_int32
+        L.gw_heev.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                              ctypes.c_size_t, ctypes.c_void_p]
+        L.gw_heev_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_heev_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_release.restype = ctypes.c_int32
@@ -155,14 +208,32 @@ def _grid(n, volume) -> _Grid:
     return g
 
 
-def _opts(precision="fp64", n_slices=0, pair_chunk=4096, flags=0, spin=2.0) -> _Opts:
+def _workspace(ws):
+    """(pointer, bytes) of a caller workspace: a device tensor or None."""
+    if ws is None:
+        return None, 0
+    if not isinstance(ws, torch.Tensor) or ws.device.type != "cuda" or not ws.is_contiguous():
+        raise TypeError("workspace must be a contiguous ROCm device tensor")
+    return ws.data_ptr(), ws.numel() * ws.element_size()
+
+
+def _opts(precision="fp64", n_slices=0, pair_chunk=4096, flags=0, spin=2.0,
+          workspace=None) -> _Opts:
     o = _Opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.n_slices = int(n_slices)
     o.pair_chunk = int(pair_chunk)
     o.flags = int(flags)
     o.spin = float(spin)
+    o.workspace, o.workspace_bytes = _workspace(workspace)
     return o
+
+
+def new_workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A device buffer usable as a caller workspace (torch allocations are
+    at least 256-byte aligned)."""
+    device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    return torch.empty(max(1, int(nbytes)), dtype=torch.uint8, device=device)
 
 
 def gw_mtxel(psi_v: torch.Tensor, psi_c: torch.Tensor, gvec, n, volume: float,
@@ -188,8 +259,13 @@ def gw_mtxel(psi_v: torch.Tensor, psi_c: torch.Tensor, gvec, n, volume: float,
     return out
 
 
+def pseudobands_workspace_bytes(nkeep: int, nidx: int, nslices: int, n_xi: int) -> int:
+    return int(lib().gw_pseudobands_workspace_bytes(int(nkeep), int(nidx), int(nslices),
+                                                    int(n_xi)))
+
+
 def gw_pseudobands(psi: torch.Tensor, e: torch.Tensor, keep, slices, n_xi: int, theta,
-                   stream=None):
+                   stream=None, workspace=None):
     """Stochastic pseudobands: returns (psi_out, e_out) with the bands `keep`
     first, then n_xi random-phase combinations of each slice (a sequence of
     band-index arrays), with phases theta[s] of shape [n_xi][len(slices[s])]
@@ -208,9 +284,10 @@ def gw_pseudobands(psi: torch.Tensor, e: torch.Tensor, keep, slices, n_xi: int, 
     out = torch.empty((nout, nr), dtype=torch.complex128, device=psi.device)
     out_e = torch.empty(nout, dtype=torch.float64, device=psi.device)
     with torch.cuda.device(psi.device):
+        wp, wb = _workspace(workspace)
         _check(lib().gw_pseudobands(psi.data_ptr(), e.data_ptr(), nb, nr, k.ctypes.data, len(k),
                                     idx.ctypes.data, off.ctypes.data, len(sl), int(n_xi),
-                                    th.ctypes.data, out.data_ptr(), out_e.data_ptr(),
+                                    th.ctypes.data, out.data_ptr(), out_e.data_ptr(), wp, wb,
                                     _stream(psi.device, stream)))
     return out, out_e
 
@@ -228,7 +305,7 @@ class Chi0Problem:
     z: np.ndarray
     chi: Optional[torch.Tensor] = None
 
-    def _fill(self, p: _Problem, keep: list):
+    def _fill(self, p: _Problem, keep: list, alloc_chi: bool = True):
         for name, t, dt in (("psi_v", self.psi_v, torch.complex128),
                             ("psi_c", self.psi_c, torch.complex128),
                             ("e_v", self.e_v, torch.float64), ("e_c", self.e_c, torch.float64)):
@@ -236,22 +313,41 @@ class Chi0Problem:
         g, z = _host_i32(self.gvec), _host_c128(self.z)
         keep += [g, z]
         ng, nz = g.shape[0], z.shape[0]
-        if self.chi is None:
+        if self.chi is None and alloc_chi:
             self.chi = torch.empty((nz, ng, ng), dtype=torch.complex128, device=self.psi_v.device)
-        _dev(self.chi, "chi", torch.complex128)
-        if tuple(self.chi.shape) != (nz, ng, ng):
-            raise ValueError(f"chi must have shape {(nz, ng, ng)}")
+        if self.chi is not None:
+            _dev(self.chi, "chi", torch.complex128)
+            if tuple(self.chi.shape) != (nz, ng, ng):
+                raise ValueError(f"chi must have shape {(nz, ng, ng)}")
         p.grid = _grid(self.n, self.volume)
         p.psi_v, p.nv = self.psi_v.data_ptr(), self.psi_v.shape[0]
         p.psi_c, p.nc = self.psi_c.data_ptr(), self.psi_c.shape[0]
         p.e_v, p.e_c = self.e_v.data_ptr(), self.e_c.data_ptr()
         p.gvec, p.ng = g.ctypes.data, ng
         p.z, p.nz = z.ctypes.data, nz
-        p.chi = self.chi.data_ptr()
+        p.chi = self.chi.data_ptr() if self.chi is not None else None
+
+
+def workspace_bytes(problems, *, precision="fp64", n_slices=0, pair_chunk=4096, flags=0,
+                    spin=2.0, backward=False) -> int:
+    """Device scratch (bytes) gw_chi0 (or, with backward=True, gw_chi0_backward
+    on the first problem) needs in a caller workspace for these arguments."""
+    probs = [problems] if isinstance(problems, Chi0Problem) else list(problems)
+    arr = (_Problem * max(1, len(probs)))()
+    keep: list = []
+    for i, pr in enumerate(probs):
+        pr._fill(arr[i], keep, alloc_chi=not backward)
+    o = _opts(precision, n_slices, pair_chunk, flags, spin)
+    dev = probs[0].psi_v.device if probs else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        n = lib().gw_workspace_bytes(arr, len(probs), ctypes.byref(o), 1 if backward else 0)
+    if n == ctypes.c_size_t(-1).value:
+        raise GWError(-1, lib().gw_last_error().decode())
+    return int(n)
 
 
 def gw_chi0(problems, *, precision="fp64", n_slices=0, pair_chunk=4096, flags=0, spin=2.0,
-            stream=None):
+            stream=None, workspace=None):
     """Run gw_chi0 on one Chi0Problem or a list of them; returns the chi tensor(s)."""
     single = isinstance(problems, Chi0Problem)
     probs = [problems] if single else list(problems)
@@ -259,7 +355,7 @@ def gw_chi0(problems, *, precision="fp64", n_slices=0, pair_chunk=4096, flags=0,
     keep: list = []
     for i, pr in enumerate(probs):
         pr._fill(arr[i], keep)
-    o = _opts(precision, n_slices, pair_chunk, flags, spin)
+    o = _opts(precision, n_slices, pair_chunk, flags, spin, workspace)
     dev = probs[0].psi_v.device if probs else torch.device("cuda", torch.cuda.current_device())
     with torch.cuda.device(dev):
         _check(lib().gw_chi0(arr, len(probs), ctypes.byref(o), _stream(dev, stream)))
@@ -267,7 +363,7 @@ def gw_chi0(problems, *, precision="fp64", n_slices=0, pair_chunk=4096, flags=0,
 
 
 def gw_chi0_backward(problem: Chi0Problem, grad_chi: torch.Tensor, *, pair_chunk=4096,
-                     spin=2.0, need=(True, True, True, True), stream=None):
+                     spin=2.0, need=(True, True, True, True), stream=None, workspace=None):
     """Returns (grad_psi_v, grad_psi_c, grad_e_v, grad_e_c); entries not in `need` are None."""
     pr = problem
     _dev(grad_chi, "grad_chi", torch.complex128)
@@ -284,11 +380,131 @@ def gw_chi0_backward(problem: Chi0Problem, grad_chi: torch.Tensor, *, pair_chunk
             torch.empty_like(pr.e_v) if need[2] else None,
             torch.empty_like(pr.e_c) if need[3] else None]
     ptr = [o.data_ptr() if o is not None else None for o in outs]
-    o = _opts("fp64", 0, pair_chunk, 0, spin)
+    o = _opts("fp64", 0, pair_chunk, 0, spin, workspace)
     with torch.cuda.device(pr.psi_v.device):
         _check(lib().gw_chi0_backward(ctypes.byref(p), grad_chi.data_ptr(), ptr[0], ptr[1], ptr[2],
                                       ptr[3], ctypes.byref(o), _stream(pr.psi_v.device, stream)))
     return tuple(outs)
+
+
+def _diag_opts(tol=0.0, max_iter=0, guard=0, max_degree=0, seed=0, workspace=None):
+    o = _DiagOpts()
+    o.tol, o.max_iter, o.guard, o.max_degree = float(tol), int(max_iter), int(guard), int(max_degree)
+    o.seed = int(seed)
+    o.workspace, o.workspace_bytes = _workspace(workspace)
+    return o
+
+
+def subspace_basis_workspace_bytes(ng: int, n_eig: int, guard: int = 0) -> int:
+    o = _diag_opts(guard=guard)
+    return int(lib().gw_subspace_basis_workspace_bytes(int(ng), int(n_eig), ctypes.byref(o)))
+
+
+def gw_subspace_basis(chi_static: torch.Tensor, n_eig: int, *, tol=0.0, max_iter=0, guard=0,
+                      max_degree=0, seed=0, workspace=None, stream=None):
+    """Diag: (basis [ng, n_eig], eigenvalues [n_eig], info) of the Hermitian,
+    negative semidefinite static polarizability chi_static [ng, ng]."""
+    _dev(chi_static, "chi_static", torch.complex128)
+    ng = chi_static.shape[0]
+    if tuple(chi_static.shape) != (ng, ng):
+        raise ValueError("chi_static must be square")
+    basis = torch.empty((ng, int(n_eig)), dtype=torch.complex128, device=chi_static.device)
+    ev = torch.empty(int(n_eig), dtype=torch.float64, device=chi_static.device)
+    o = _diag_opts(tol, max_iter, guard, max_degree, seed, workspace)
+    info = _DiagInfo()
+    with torch.cuda.device(chi_static.device):
+        _check(lib().gw_subspace_basis(chi_static.data_ptr(), ng, int(n_eig), basis.data_ptr(),
+                                       ev.data_ptr(), ctypes.byref(o), ctypes.byref(info),
+                                       _stream(chi_static.device, stream)))
+    return basis, ev, {"iterations": info.iterations, "degree": info.degree,
+                       "residual": info.residual, "bound": info.bound}
+
+
+def chi0_subspace_workspace_bytes(problem, n_eig: int, *, precision="fp64", n_slices=0,
+                                  pair_chunk=4096, flags=0, spin=2.0) -> int:
+    arr = _Problem()
+    keep: list = []
+    problem._fill(arr, keep, alloc_chi=False)
+    o = _opts(precision, n_slices, pair_chunk, flags, spin)
+    with torch.cuda.device(problem.psi_v.device):
+        n = lib().gw_chi0_subspace_workspace_bytes(ctypes.byref(arr), int(n_eig), ctypes.byref(o))
+    if n == ctypes.c_size_t(-1).value:
+        raise GWError(-1, lib().gw_last_error().decode())
+    return int(n)
+
+
+def gw_chi0_subspace(problem, basis: torch.Tensor, *, precision="fp64", n_slices=0,
+                     pair_chunk=4096, flags=0, spin=2.0, out=None, workspace=None, stream=None):
+    """Transf + CHI-Freq (Eq. (6)): chi_BB'(z) [nz, n_eig, n_eig] of one problem
+    in the subspace spanned by the columns of basis [ng, n_eig]."""
+    _dev(basis, "basis", torch.complex128)
+    n_eig = basis.shape[1]
+    nz = _host_c128(problem.z).shape[0]
+    if out is None:
+        out = torch.empty((nz, n_eig, n_eig), dtype=torch.complex128, device=basis.device)
+    _dev(out, "out", torch.complex128)
+    if tuple(out.shape) != (nz, n_eig, n_eig):
+        raise ValueError(f"out must have shape {(nz, n_eig, n_eig)}")
+    arr = _Problem()
+    keep: list = []
+    problem._fill(arr, keep, alloc_chi=False)
+    arr.chi = out.data_ptr()
+    o = _opts(precision, n_slices, pair_chunk, flags, spin, workspace)
+    with torch.cuda.device(basis.device):
+        _check(lib().gw_chi0_subspace(ctypes.byref(arr), basis.data_ptr(), int(n_eig),
+                                      ctypes.byref(o), _stream(basis.device, stream)))
+    return out
+
+
+def _c128(x) -> _C128:
+    x = complex(x)
+    return _C128(x.real, x.imag)
+
+
+def gw_zgemm(opa: str, opb: str, a: torch.Tensor, b: torch.Tensor, *, alpha=1.0, beta=0.0,
+             c: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """C = alpha op(A) op(B) + beta C for complex128 device matrices [m, k]
+    (or batches [batch, m, k]); op in 'N', 'T', 'C'."""
+    _dev(a, "a", torch.complex128)
+    _dev(b, "b", torch.complex128)
+    batched = a.dim() == 3
+    A = a if batched else a[None]
+    B = b if batched else b[None]
+    if A.shape[0] != B.shape[0]:
+        raise ValueError("batch sizes differ")
+    m = A.shape[1] if opa.upper() == "N" else A.shape[2]
+    k = A.shape[2] if opa.upper() == "N" else A.shape[1]
+    kb = B.shape[1] if opb.upper() == "N" else B.shape[2]
+    n = B.shape[2] if opb.upper() == "N" else B.shape[1]
+    if k != kb:
+        raise ValueError("inner dimensions differ")
+    batch = A.shape[0]
+    if c is None:
+        c = torch.zeros((batch, m, n) if batched else (m, n), dtype=torch.complex128,
+                        device=a.device)
+    _dev(c, "c", torch.complex128)
+    with torch.cuda.device(a.device):
+        _check(lib().gw_zgemm(opa.encode(), opb.encode(), m, n, k, _c128(alpha), A.data_ptr(),
+                              A.shape[2], A.shape[1] * A.shape[2], B.data_ptr(), B.shape[2],
+                              B.shape[1] * B.shape[2], _c128(beta), c.data_ptr(), n, m * n,
+                              batch, _stream(a.device, stream)))
+    return c
+
+
+def gw_heev(a: torch.Tensor, *, tol=0.0, workspace=None, stream=None):
+    """(w, v): eigenvalues (increasing) and eigenvector columns of Hermitian
+    a [n, n] or [batch, n, n] (Jacobi rotations on the device)."""
+    _dev(a, "a", torch.complex128)
+    batched = a.dim() == 3
+    A = a if batched else a[None]
+    batch, n = A.shape[0], A.shape[1]
+    w = torch.empty((batch, n), dtype=torch.float64, device=a.device)
+    v = torch.empty((batch, n, n), dtype=torch.complex128, device=a.device)
+    wp, wb = _workspace(workspace)
+    with torch.cuda.device(a.device):
+        _check(lib().gw_heev(A.data_ptr(), n, batch, w.data_ptr(), v.data_ptr(), float(tol), wp,
+                             wb, _stream(a.device, stream)))
+    return (w, v) if batched else (w[0], v[0])
 
 
 class Chi0(torch.autograd.Function):

@@ -481,12 +481,64 @@ struct Carve {
 
 constexpr int kYMax = 65535;  // gridDim.y limit
 
+// Chunking and scratch layout of one adjoint call.
+struct BwdLayout {
+    int vb = 1, cwmax = 1;
+    int64_t kmax = 0;
+    int nparts = 0;
+    bool fuse = false;
+    size_t o_m = 0, o_t2 = 0, o_d = 0, o_dd = 0, o_gm = 0, o_q = 0, o_de = 0, o_rho = 0, o_vp = 0;
+    size_t total = 0;
+};
+
+BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi, bool want_psi_v,
+                     int pair_chunk) {
+    BwdLayout L;
+    const int64_t nr = plan.nr;
+    const int ng = p.ng, nz = p.nz;
+    // chunk rectangle, capped so that the per-pair grids g_rho stay within 2 GiB
+    const int64_t per_pair = nr * static_cast<int64_t>(sizeof(double2));
+    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
+    const int chunk = static_cast<int>(std::min<int64_t>(pair_chunk, cap));
+    // 4 valence bands per MTXEL tile: conduction width capped at chunk / 4
+    L.cwmax = std::max(1, std::min(p.nc, chunk / std::max(1, std::min(p.nv, 4))));
+    L.vb = std::max(1, std::min(p.nv, chunk / L.cwmax));
+    L.kmax = static_cast<int64_t>(L.vb) * L.cwmax;
+    L.nparts = 2 * ceil_div(ng, 64);
+    const int64_t kmax = L.kmax;
+    Carve cv;
+    L.o_m = cv.take(kmax * ng * sizeof(double2));
+    L.o_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
+    L.o_d = cv.take(kmax * nz * sizeof(double2));
+    L.o_dd = cv.take(kmax * nz * sizeof(double2));
+    L.o_gm = cv.take(kmax * ng * sizeof(double2));
+    L.o_q = cv.take(kmax * nz * L.nparts * sizeof(double2));
+    L.o_de = cv.take(kmax * sizeof(double));
+    L.o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
+    // fused band reduction: chunks of at most kFuseV valence bands
+    L.fuse = L.vb <= kFuseV;
+    const int ncb_max = ceil_div(L.cwmax, kFuseC);
+    L.o_vp = cv.take(want_psi && L.fuse && want_psi_v
+                         ? static_cast<size_t>(ncb_max) * L.vb * nr * sizeof(double2)
+                         : 0);
+    L.total = cv.off;
+    return L;
+}
+
 }  // namespace
+
+size_t chi0_backward_bytes(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi_v,
+                           bool want_psi_c, bool want_e, int pair_chunk) {
+    const int64_t npairs = static_cast<int64_t>(p.nv) * p.nc;
+    const bool want_psi = want_psi_v || want_psi_c;
+    if (npairs == 0 || (!want_psi && !want_e)) return 0;
+    return bwd_layout(plan, p, want_psi, want_psi_v, pair_chunk).total;
+}
 
 void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const double2* grad_chi,
                        double2* grad_psi_v, double2* grad_psi_c, double* grad_e_v,
                        double* grad_e_c, double spin, int pair_chunk, hipStream_t s,
-                       const std::function<void*(size_t)>& get_scratch) {
+                       char* base) {
     const int64_t nr = plan.nr;
     const int ng = p.ng, nz = p.nz;
     const int n1 = plan.n[0], n2 = plan.n[1], n3 = plan.n[2];
@@ -499,32 +551,11 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     const bool want_e = grad_e_v || grad_e_c;
     if (npairs == 0 || (!want_psi && !want_e)) return;
 
-    // chunk rectangle, capped so that the per-pair grids g_rho stay within 2 GiB
-    const int64_t per_pair = nr * static_cast<int64_t>(sizeof(double2));
-    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
-    const int chunk = static_cast<int>(std::min<int64_t>(pair_chunk, cap));
-    // 4 valence bands per MTXEL tile: conduction width capped at chunk / 4
-    const int cwmax = std::max(1, std::min(p.nc, chunk / std::max(1, std::min(p.nv, 4))));
-    const int vb = std::max(1, std::min(p.nv, chunk / cwmax));
-    const int64_t kmax = static_cast<int64_t>(vb) * cwmax;
-    const int nparts = 2 * ceil_div(ng, 64);
-
-    Carve cv;
-    const size_t o_m = cv.take(kmax * ng * sizeof(double2));
-    const size_t o_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
-    const size_t o_d = cv.take(kmax * nz * sizeof(double2));
-    const size_t o_dd = cv.take(kmax * nz * sizeof(double2));
-    const size_t o_gm = cv.take(kmax * ng * sizeof(double2));
-    const size_t o_q = cv.take(kmax * nz * nparts * sizeof(double2));
-    const size_t o_de = cv.take(kmax * sizeof(double));
-    const size_t o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
-    // fused band reduction: chunks of at most kFuseV valence bands
-    const bool fuse = vb <= kFuseV;
-    const int ncb_max = ceil_div(cwmax, kFuseC);
-    const size_t o_vp = cv.take(want_psi && fuse && grad_psi_v
-                                    ? static_cast<size_t>(ncb_max) * vb * nr * sizeof(double2)
-                                    : 0);
-    char* base = static_cast<char*>(get_scratch(cv.off));
+    const BwdLayout L = bwd_layout(plan, p, want_psi, grad_psi_v != nullptr, pair_chunk);
+    const int vb = L.vb, cwmax = L.cwmax, nparts = L.nparts;
+    const bool fuse = L.fuse;
+    const size_t o_m = L.o_m, o_t2 = L.o_t2, o_d = L.o_d, o_dd = L.o_dd, o_gm = L.o_gm,
+                 o_q = L.o_q, o_de = L.o_de, o_rho = L.o_rho, o_vp = L.o_vp;
     double2* mbuf = reinterpret_cast<double2*>(base + o_m);
     double2* t2 = reinterpret_cast<double2*>(base + o_t2);
     double2* dbuf = reinterpret_cast<double2*>(base + o_d);

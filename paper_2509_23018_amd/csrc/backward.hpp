@@ -4,7 +4,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
-#include <functional>
 
 #include "gw.h"
 #include "plan.hpp"
@@ -13,10 +12,12 @@ namespace gw {
 
 // Gradients of a real loss with respect to psi_v, psi_c, E_v and E_c given
 // grad_chi = dL/dchi (PyTorch complex convention).  Outputs are overwritten;
-// any may be NULL.  `get_scratch(bytes)` returns device scratch valid on s.
+// any may be NULL.  `base` is device scratch of chi0_backward_bytes(...)
+// bytes for the same problem, outputs wanted and pair_chunk, valid on s.
 void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const double2* grad_chi,
                        double2* grad_psi_v, double2* grad_psi_c, double* grad_e_v,
-                       double* grad_e_c, double spin, int pair_chunk, hipStream_t s,
-                       const std::function<void*(size_t)>& get_scratch);
+                       double* grad_e_c, double spin, int pair_chunk, hipStream_t s, char* base);
+size_t chi0_backward_bytes(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi_v,
+                           bool want_psi_c, bool want_e, int pair_chunk);
 
 }  // namespace gw

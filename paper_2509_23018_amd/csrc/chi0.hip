@@ -10,6 +10,7 @@
 
 #include "chi0.hpp"
 #include "items.hpp"
+#include "lifetime.hpp"
 #include "common.hpp"
 #include "prof.hpp"
 
@@ -493,6 +494,7 @@ const int* tile_order(int nb, int kSuper) {
                     if (j >= i) h.push_back((i << 16) | j);
                 }
     h.insert(h.end(), f.begin(), f.end());
+    require_alloc("tile-order table for this G-list size");
     GW_HIP_TRY(hipMalloc(&t, h.size() * sizeof(int)));
     GW_HIP_TRY(hipMemcpy(t, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
     return t;

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -18,9 +19,12 @@
 #include "common.hpp"
 #include "gw.h"
 #include "items.hpp"
+#include "lifetime.hpp"
+#include "linalg.hpp"
 #include "plan.hpp"
 #include "prof.hpp"
 #include "pseudobands.hpp"
+#include "subspace.hpp"
 
 namespace gw {
 namespace {
@@ -55,6 +59,7 @@ void* scratch(size_t bytes, hipStream_t s) {
     std::lock_guard<std::mutex> lk(p.mu);
     Scratch& sc = p.by_key[{dev, s}];
     if (sc.bytes >= bytes && sc.ptr) return sc.ptr;
+    require_alloc("scratch buffer");
     if (sc.ptr) {
         GW_HIP_TRY(hipStreamSynchronize(s));
         GW_HIP_TRY(hipFree(sc.ptr));
@@ -123,6 +128,7 @@ AuxCtx& aux_ctx(hipStream_t s) {
     std::lock_guard<std::mutex> lk(p.mu);
     AuxCtx& a = p.by_key[{dev, s}];
     if (!a.aux) {
+        require_alloc("companion stream");
         GW_HIP_TRY(hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking));
         for (auto& e : a.ev) GW_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
@@ -191,6 +197,8 @@ struct Opts {
     int pair_chunk = 4096;
     uint32_t flags = 0;
     double spin = 2.0;
+    char* ws = nullptr;      // caller's workspace, or null for the library's scratch
+    size_t ws_bytes = 0;
 };
 
 Opts read_opts(const gw_opts_t* o) {
@@ -201,6 +209,10 @@ Opts read_opts(const gw_opts_t* o) {
     r.pair_chunk = o->pair_chunk == 0 ? 4096 : o->pair_chunk;
     r.flags = o->flags;
     r.spin = o->spin == 0.0 ? 2.0 : o->spin;
+    r.ws = static_cast<char*>(o->workspace);
+    r.ws_bytes = o->workspace ? o->workspace_bytes : 0;
+    if (r.ws && (reinterpret_cast<uintptr_t>(r.ws) & 255))
+        fail(GW_EINVAL, "workspace must be 256-byte aligned");
     if (r.pair_chunk < 1) fail(GW_EINVAL, "pair_chunk must be >= 1 (or 0 for the default)");
     if (!std::isfinite(r.spin)) fail(GW_EINVAL, "spin must be finite");
     if (r.precision < GW_FP64 || r.precision > GW_SPLIT_FP16)
@@ -209,8 +221,10 @@ Opts read_opts(const gw_opts_t* o) {
         (r.n_slices < 2 || r.n_slices > 8))
         fail(GW_EINVAL, "n_slices must be in [2, 8] for split precision");
     if (r.flags & ~(GW_FLAG_NO_HERMITIAN | GW_FLAG_ACCUMULATE | GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE |
-                    GW_FLAG_FP64_TILE128))
+                    GW_FLAG_FP64_TILE128 | GW_FLAG_ACC_HERMITIAN))
         fail(GW_EINVAL, "unknown flag bits");
+    if ((r.flags & GW_FLAG_ACC_HERMITIAN) && !(r.flags & GW_FLAG_ACCUMULATE))
+        fail(GW_EINVAL, "GW_FLAG_ACC_HERMITIAN needs GW_FLAG_ACCUMULATE");
     return r;
 }
 
@@ -294,10 +308,11 @@ std::vector<Chunk> make_chunks(const gw_problem_t& pr, const ChunkShape& cs) {
     return chunks;
 }
 
-// Frequencies whose Delta is real (Re z = 0) give Hermitian chi.
+// Frequencies whose Delta is real (Re z = 0) give Hermitian chi.  Accumulating
+// keeps the shortcut only when the caller states that chi is Hermitian already.
 std::vector<bool> hermitian_freqs(const gw_problem_t& pr, const Opts& o) {
     std::vector<bool> herm(pr.nz);
-    const bool acc = (o.flags & GW_FLAG_ACCUMULATE) != 0;
+    const bool acc = (o.flags & GW_FLAG_ACCUMULATE) && !(o.flags & GW_FLAG_ACC_HERMITIAN);
     for (int w = 0; w < pr.nz; ++w)
         herm[w] = pr.z[w].re == 0.0 && !(o.flags & GW_FLAG_NO_HERMITIAN) && !acc;
     return herm;
@@ -408,9 +423,84 @@ std::vector<WList> freq_lists(const std::vector<bool>& herm) {
     return out;
 }
 
-void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
-    const MtxelPlan& plan = *get_plan(pr.grid.n, pr.gvec, pr.ng);
-    const int64_t ng = pr.ng;
+// Scratch of one call: the caller's workspace, checked against `need` before
+// anything is enqueued, or the library's buffer for (device, stream).
+char* call_scratch(size_t need, const Opts& o, hipStream_t s) {
+    if (o.ws) {
+        if (need > o.ws_bytes)
+            fail(GW_EINVAL, "workspace of " + std::to_string(o.ws_bytes) +
+                                " bytes is too small: this call needs " + std::to_string(need));
+        return o.ws;
+    }
+    if (need == 0) return nullptr;
+    return static_cast<char*>(scratch(need, s));
+}
+
+// The autotuner may time tile shapes inside this call (FP64, default tile).
+bool tune_candidate(const Opts& o) {
+    return o.precision == GW_FP64 && !(o.flags & GW_FLAG_FP64_TILE128) && autotune_enabled(o);
+}
+
+// Scratch layout of one problem's pipeline.  nbuf M/Delta buffers (2: MTXEL
+// of chunk k+1 on the companion stream under CHI0 of chunk k; 1: both on the
+// caller's stream), room for the autotuner's trial plane, and for the partial
+// tiles of a contraction's last round (tail).
+// With n_eig > 0 (the static subspace), every chunk's M is transformed to the
+// subspace basis, M^B = M C_s, before the contraction, which then runs over
+// n_eig columns instead of N_G.
+struct Chi0Layout {
+    ChunkShape cs{};
+    int64_t kmax = 0;
+    int nbuf = 2;
+    bool tail = true;
+    int ncols = 0;  // columns of the contracted operand (N_G, or n_eig)
+    size_t off_m[2] = {0, 0}, off_d[2] = {0, 0};
+    size_t off_mfull = 0;  // M on the G-sphere before the transform (subspace only)
+    size_t off_t2 = 0, off_sp = 0, off_tune = 0, off_tail = 0;
+    size_t total = 0;
+};
+
+Chi0Layout chi0_layout(const gw_problem_t& pr, const Opts& o, const MtxelPlan& plan, int nbuf,
+                       bool tail, int n_eig = 0) {
+    Chi0Layout L;
+    L.nbuf = nbuf;
+    L.tail = tail;
+    L.ncols = n_eig > 0 ? n_eig : pr.ng;
+    if (static_cast<int64_t>(pr.nv) * pr.nc == 0) return L;
+    L.cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
+    L.kmax = static_cast<int64_t>(L.cs.vb) * L.cs.cw;
+    const int64_t nw = L.ncols;
+    Carver cv;
+    for (int b = 0; b < nbuf; ++b) {
+        L.off_m[b] = cv.take(L.kmax * nw * sizeof(double2));
+        L.off_d[b] = cv.take(L.kmax * pr.nz * sizeof(double2));
+    }
+    if (nbuf == 1) {
+        L.off_m[1] = L.off_m[0];
+        L.off_d[1] = L.off_d[0];
+    }
+    L.off_mfull = cv.take(n_eig > 0 ? L.kmax * pr.ng * sizeof(double2) : 0);
+    L.off_t2 = cv.take(t2_elems(plan, L.kmax) * sizeof(double2));
+    const bool split = o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16;
+    L.off_sp = cv.take(split ? split_scratch_bytes(L.kmax, L.ncols, pr.nz, o.n_slices) : 0);
+    L.off_tune = cv.take(tune_candidate(o) ? nw * nw * sizeof(double2) : 0);
+    L.off_tail = cv.take(!tail                          ? 0
+                         : o.precision == GW_FP64        ? chi0_f64_tail_bytes()
+                         : o.precision == GW_SPLIT_BF16 ? sbf16_tail_bytes()
+                                                        : 0);
+    L.total = cv.off;
+    return L;
+}
+
+// One problem: MTXEL (+ the subspace transform) + Delta + CHI0 per chunk, then
+// the Hermitian mirror.  base holds L.total bytes (L from chi0_layout with the
+// same arguments); with basis (device [N_G][n_eig], L.ncols = n_eig) chi is
+// [nz][n_eig][n_eig].
+void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
+              const Chi0Layout& L, const double2* basis = nullptr) {
+    const PlanRef plan_ref = get_plan(pr.grid.n, pr.gvec, pr.ng);
+    const MtxelPlan& plan = *plan_ref;
+    const int64_t ng = L.ncols;  // the contraction's width
     const int64_t npairs = static_cast<int64_t>(pr.nv) * pr.nc;
     const bool accumulate = (o.flags & GW_FLAG_ACCUMULATE) != 0;
     double2* chi = reinterpret_cast<double2*>(pr.chi);
@@ -418,99 +508,99 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
         if (!accumulate) launch_fill_zero(chi, ng * ng * pr.nz, s);
         return;
     }
-    const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
-    const int64_t kmax = static_cast<int64_t>(cs.vb) * cs.cw;
-    // two M / Delta buffers: MTXEL of chunk k+1 (companion stream) overlaps
-    // CHI0 of chunk k (caller stream)
-    Carver cv;
-    size_t off_m[2], off_d[2];
-    for (int b = 0; b < 2; ++b) {
-        off_m[b] = cv.take(kmax * ng * sizeof(double2));
-        off_d[b] = cv.take(kmax * pr.nz * sizeof(double2));
-    }
-    const size_t off_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
-    const bool split = o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16;
-    const size_t off_sp = cv.take(split ? split_scratch_bytes(kmax, pr.ng, pr.nz, o.n_slices) : 0);
-    const std::vector<Chunk> chunks = make_chunks(pr, cs);
+    const bool two_streams = L.nbuf == 2;
+    double2* mbuf[2] = {reinterpret_cast<double2*>(base + L.off_m[0]),
+                        reinterpret_cast<double2*>(base + L.off_m[1])};
+    double2* dbuf[2] = {reinterpret_cast<double2*>(base + L.off_d[0]),
+                        reinterpret_cast<double2*>(base + L.off_d[1])};
+    double2* t2 = reinterpret_cast<double2*>(base + L.off_t2);
+    double2* tail_ws = L.tail && (o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16)
+                           ? reinterpret_cast<double2*>(base + L.off_tail)
+                           : nullptr;
+    const std::vector<Chunk> chunks = make_chunks(pr, L.cs);
     int variant = 0;
     bool tune = false;
     if (o.precision == GW_FP64 && (o.flags & GW_FLAG_FP64_TILE128)) {
         variant = 1;
     } else if (o.precision == GW_FP64) {
-        variant = lookup_variant(pr.ng, chunks[0].kc);
+        variant = lookup_variant(L.ncols, chunks[0].kc);
         tune = variant < 0 && autotune_enabled(o);
         if (variant < 0) variant = 0;
     }
-    // the autotuner's trials write one frequency plane here, never into chi
-    const size_t off_tune = cv.take(tune ? ng * ng * sizeof(double2) : 0);
-    // partial sums of the contraction's last round of tiles (FP64, split BF16)
-    const size_t off_tail = cv.take(o.precision == GW_FP64        ? chi0_f64_tail_bytes()
-                                    : o.precision == GW_SPLIT_BF16 ? sbf16_tail_bytes()
-                                                                   : 0);
-    char* base = static_cast<char*>(scratch(cv.off, s));
-    double2* mbuf[2] = {reinterpret_cast<double2*>(base + off_m[0]),
-                        reinterpret_cast<double2*>(base + off_m[1])};
-    double2* dbuf[2] = {reinterpret_cast<double2*>(base + off_d[0]),
-                        reinterpret_cast<double2*>(base + off_d[1])};
-    double2* t2 = reinterpret_cast<double2*>(base + off_t2);
-    double2* tail_ws = o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16
-                           ? reinterpret_cast<double2*>(base + off_tail)
-                           : nullptr;
     const double2* z = reinterpret_cast<const double2*>(pr.z);
-    std::vector<bool> herm(pr.nz);
-    for (int w = 0; w < pr.nz; ++w)
-        herm[w] = pr.z[w].re == 0.0 && !(o.flags & GW_FLAG_NO_HERMITIAN) && !accumulate;
+    const std::vector<bool> herm = hermitian_freqs(pr, o);
     // launches cover at most kMaxZ frequencies each (Hermitian ones first)
     const std::vector<WList> wlists = freq_lists(herm);
     // events: ev[0] caller-stream start, ev[1+b] MTXEL into buffer b done,
     // ev[3+b] CHI0 reading buffer b done
-    AuxCtx& ax = aux_ctx(s);
-    auto produce = [&](size_t k) {  // MTXEL + Delta of chunk k on the companion stream
+    AuxCtx* ax = two_streams ? &aux_ctx(s) : nullptr;
+    auto produce = [&](size_t k) {  // MTXEL + Delta of chunk k
         const int b = static_cast<int>(k & 1);
-        if (k >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[3 + b], 0));
+        const hipStream_t ps = two_streams ? ax->aux : s;
+        if (two_streams && k >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax->aux, ax->ev[3 + b], 0));
         const Chunk& c = chunks[k];
+        double2* mout = basis ? reinterpret_cast<double2*>(base + L.off_mfull) : mbuf[b];
         launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
                      reinterpret_cast<const double2*>(pr.psi_c),
-                     Rect{c.pm.v0, c.vcount, c.pm.c0, c.pm.cw}, pr.grid.volume, t2, mbuf[b], ax.aux);
-        launch_delta(pr.e_v, pr.e_c, c.pm, c.kc, z, pr.nz, o.spin, dbuf[b], ax.aux);
-        GW_HIP_TRY(hipEventRecord(ax.ev[1 + b], ax.aux));
+                     Rect{c.pm.v0, c.vcount, c.pm.c0, c.pm.cw}, pr.grid.volume, t2, mout, ps);
+        if (basis) {  // Transf: M^B = M C_s
+            ZGemm g;
+            g.m = static_cast<int>(c.kc);
+            g.n = L.ncols;
+            g.k = pr.ng;
+            g.a = mout;
+            g.lda = pr.ng;
+            g.b = basis;
+            g.ldb = L.ncols;
+            g.c = mbuf[b];
+            g.ldc = L.ncols;
+            launch_zgemm(kOpN, kOpN, g, ps);
+        }
+        launch_delta(pr.e_v, pr.e_c, c.pm, c.kc, z, pr.nz, o.spin, dbuf[b], ps);
+        if (two_streams) GW_HIP_TRY(hipEventRecord(ax->ev[1 + b], ax->aux));
     };
-    GW_HIP_TRY(hipEventRecord(ax.ev[0], s));
-    GW_HIP_TRY(hipStreamWaitEvent(ax.aux, ax.ev[0], 0));
+    if (two_streams) {
+        GW_HIP_TRY(hipEventRecord(ax->ev[0], s));
+        GW_HIP_TRY(hipStreamWaitEvent(ax->aux, ax->ev[0], 0));
+    }
     produce(0);
     if (tune) {
         // time the tile shapes on the first chunk and one frequency
-        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1], 0));
+        if (two_streams) GW_HIP_TRY(hipStreamWaitEvent(s, ax->ev[1], 0));
         WList one{};
         one.w[0] = 0;
         one.nf = 1;
-        double2* trial_chi = reinterpret_cast<double2*>(base + off_tune);
-        variant = tune_variant(pr.ng, chunks[0].kc, s, [&](int v) {
-            launch_chi0_f64(mbuf[0], chunks[0].kc, pr.ng, dbuf[0], one, trial_chi, false, s, v,
+        double2* trial_chi = reinterpret_cast<double2*>(base + L.off_tune);
+        variant = tune_variant(L.ncols, chunks[0].kc, s, [&](int v) {
+            launch_chi0_f64(mbuf[0], chunks[0].kc, L.ncols, dbuf[0], one, trial_chi, false, s, v,
                             tail_ws);
         });
     }
     for (size_t k = 0; k < chunks.size(); ++k) {
         const int b = static_cast<int>(k & 1);
-        if (k + 1 < chunks.size()) produce(k + 1);
-        GW_HIP_TRY(hipStreamWaitEvent(s, ax.ev[1 + b], 0));
+        if (!two_streams && k > 0) produce(k);
+        if (two_streams) {
+            if (k + 1 < chunks.size()) produce(k + 1);
+            GW_HIP_TRY(hipStreamWaitEvent(s, ax->ev[1 + b], 0));
+        }
         for (const WList& wl : wlists) {
             const bool acc = accumulate || k > 0;
             if (o.precision == GW_FP64)
-                launch_chi0_f64(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s, variant,
+                launch_chi0_f64(mbuf[b], chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s, variant,
                                 tail_ws);
             else if (o.precision == GW_FP32)
-                launch_chi0_f32(mbuf[b], chunks[k].kc, pr.ng, dbuf[b], wl, chi, acc, s);
+                launch_chi0_f32(mbuf[b], chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s);
             else
-                launch_chi0_split(o.precision, o.n_slices, mbuf[b], chunks[k].kc, pr.ng, dbuf[b],
-                                  pr.nz, wl, chi, acc, base + off_sp, s, tail_ws);
+                launch_chi0_split(o.precision, o.n_slices, mbuf[b], chunks[k].kc, L.ncols, dbuf[b],
+                                  pr.nz, wl, chi, acc, base + L.off_sp, s, tail_ws);
         }
-        GW_HIP_TRY(hipEventRecord(ax.ev[3 + b], s));
+        if (two_streams) GW_HIP_TRY(hipEventRecord(ax->ev[3 + b], s));
     }
     for (int w = 0; w < pr.nz; ++w)
         if (herm[w])
-            launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, pr.ng,
+            launch_mirror(chi + static_cast<int64_t>(w) * ng * ng, L.ncols,
                           o.precision == GW_FP64 ? chi0_variant_tile(variant) : split_tile(o.precision), s);
+    mark_plan_used(*plan_ref, s);
 }
 
 
@@ -519,7 +609,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s) {
 // One problem of a batch: its plan, chunks and buffers (offsets into the
 // batch's scratch).
 struct BatchQ {
-    const MtxelPlan* plan = nullptr;
+    PlanRef plan;
     std::vector<Chunk> chunks;
     std::vector<bool> herm;
     int64_t kmax = 0;
@@ -637,10 +727,10 @@ BatchPlan build_batch(const gw_problem_t* probs, int nprob, const Opts& o, int v
     return bp;
 }
 
-// Descriptor and item tables into the tables buffer (synchronous copies);
-// descriptors point into the work buffer.
+// Descriptor and item tables into the tables buffer, copied in stream order
+// through the pinned staging buffers; descriptors point into the work buffer.
 void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base,
-                  char* tab) {
+                  char* tab, hipStream_t s) {
     const int nprob = static_cast<int>(bp.q.size());
     std::vector<QDesc> desc;
     std::vector<SbDesc> sdesc;
@@ -671,14 +761,10 @@ void upload_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o,
         items.insert(items.end(), it.begin(), it.end());
     }
     if (bp.split)
-        GW_HIP_TRY(hipMemcpy(tab + bp.off_desc, sdesc.data(), sdesc.size() * sizeof(SbDesc),
-                             hipMemcpyHostToDevice));
+        stage_h2d(tab + bp.off_desc, sdesc.data(), sdesc.size() * sizeof(SbDesc), s);
     else
-        GW_HIP_TRY(hipMemcpy(tab + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc),
-                             hipMemcpyHostToDevice));
-    if (!items.empty())
-        GW_HIP_TRY(hipMemcpy(tab + bp.off_items, items.data(), items.size() * sizeof(int4),
-                             hipMemcpyHostToDevice));
+        stage_h2d(tab + bp.off_desc, desc.data(), desc.size() * sizeof(QDesc), s);
+    if (!items.empty()) stage_h2d(tab + bp.off_items, items.data(), items.size() * sizeof(int4), s);
 }
 
 void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o, char* base,
@@ -749,11 +835,41 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
                 launch_mirror(reinterpret_cast<double2*>(probs[q].chi) +
                                   static_cast<int64_t>(w) * probs[q].ng * probs[q].ng,
                               probs[q].ng, tile, s);
+    for (int q = 0; q < nprob; ++q) mark_plan_used(*bp.q[q].plan, s);
+}
+
+// Scratch the autotuner of a batch needs: the largest problem's first chunk
+// (M, Delta, t2) and one trial frequency plane.
+struct TuneLayout {
+    int qmax = -1;
+    size_t om = 0, od = 0, ot = 0, oc = 0, total = 0;
+};
+
+TuneLayout batch_tune_layout(const gw_problem_t* probs, int nprob, const Opts& o) {
+    TuneLayout t;
+    if (!tune_candidate(o)) return t;
+    for (int q = 0; q < nprob; ++q)
+        if (static_cast<int64_t>(probs[q].nv) * probs[q].nc > 0 &&
+            (t.qmax < 0 || probs[q].ng > probs[t.qmax].ng))
+            t.qmax = q;
+    if (t.qmax < 0) return t;
+    const gw_problem_t& pr = probs[t.qmax];
+    const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
+    const std::vector<Chunk> ch = make_chunks(pr, cs);
+    const PlanRef plan = get_plan(pr.grid.n, pr.gvec, pr.ng);
+    Carver cv;
+    t.om = cv.take(ch[0].kc * pr.ng * sizeof(double2));
+    t.od = cv.take(ch[0].kc * pr.nz * sizeof(double2));
+    t.ot = cv.take(t2_elems(*plan, ch[0].kc) * sizeof(double2));
+    t.oc = cv.take(static_cast<size_t>(pr.ng) * pr.ng * sizeof(double2));
+    t.total = cv.off;
+    return t;
 }
 
 // Tile variant of a batch: forced, cached, or tuned on its largest problem's
-// first chunk (one frequency, into a scratch chi so no output is touched).
-int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+// first chunk (one frequency, into the call's scratch so no output is touched).
+int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s,
+                  char* base) {
     if (o.precision != GW_FP64) return 0;
     if (o.flags & GW_FLAG_FP64_TILE128) return 1;
     int qmax = -1;
@@ -768,40 +884,45 @@ int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream
     int v = lookup_variant(pr.ng, ch[0].kc);
     if (v >= 0) return v;
     if (!autotune_enabled(o)) return 0;
-    const MtxelPlan& plan = *get_plan(pr.grid.n, pr.gvec, pr.ng);
-    Carver cv;
-    const size_t om = cv.take(ch[0].kc * pr.ng * sizeof(double2));
-    const size_t od = cv.take(ch[0].kc * pr.nz * sizeof(double2));
-    const size_t ot = cv.take(t2_elems(plan, ch[0].kc) * sizeof(double2));
-    const size_t oc = cv.take(static_cast<size_t>(pr.ng) * pr.ng * sizeof(double2));
-    char* base = static_cast<char*>(scratch(cv.off, s));
-    launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
+    const TuneLayout t = batch_tune_layout(probs, nprob, o);
+    const PlanRef plan = get_plan(pr.grid.n, pr.gvec, pr.ng);
+    launch_mtxel(*plan, reinterpret_cast<const double2*>(pr.psi_v),
                  reinterpret_cast<const double2*>(pr.psi_c),
                  Rect{ch[0].pm.v0, ch[0].vcount, ch[0].pm.c0, ch[0].pm.cw}, pr.grid.volume,
-                 reinterpret_cast<double2*>(base + ot), reinterpret_cast<double2*>(base + om), s);
+                 reinterpret_cast<double2*>(base + t.ot), reinterpret_cast<double2*>(base + t.om), s);
     launch_delta(pr.e_v, pr.e_c, ch[0].pm, ch[0].kc, reinterpret_cast<const double2*>(pr.z), pr.nz,
-                 o.spin, reinterpret_cast<double2*>(base + od), s);
+                 o.spin, reinterpret_cast<double2*>(base + t.od), s);
     WList wl{};
     wl.w[0] = 0;
     wl.nf = 1;
-    return tune_variant(pr.ng, ch[0].kc, s, [&](int vv) {
-        launch_chi0_f64(reinterpret_cast<const double2*>(base + om), ch[0].kc, pr.ng,
-                        reinterpret_cast<const double2*>(base + od), wl,
-                        reinterpret_cast<double2*>(base + oc), false, s, vv);
+    v = tune_variant(pr.ng, ch[0].kc, s, [&](int vv) {
+        launch_chi0_f64(reinterpret_cast<const double2*>(base + t.om), ch[0].kc, pr.ng,
+                        reinterpret_cast<const double2*>(base + t.od), wl,
+                        reinterpret_cast<double2*>(base + t.oc), false, s, vv);
     });
+    mark_plan_used(*plan, s);
+    return v;
 }
 
-// Captured batches: the graph and the device buffers it was captured with.
+// Captured batches, most recently used first: the graph, the library-owned
+// buffers it was captured with (the work buffer unless the caller gave a
+// workspace, and the tables), the plans whose tables it reads, and an event
+// recorded after its last replay.  The cache holds at most GW_GRAPH_CACHE_MAX
+// graphs (default 16) and GW_GRAPH_CACHE_BYTES of buffers (default 64 GiB);
+// an evicted graph is destroyed once its last replay has completed.
 struct GraphEntry {
     std::string key;
     int device = 0;
     hipGraphExec_t exec = nullptr;
     std::vector<void*> buffers;
+    size_t bytes = 0;
+    std::vector<PlanRef> plans;
+    hipEvent_t last_use = nullptr;
 };
 
 struct GraphCache {
     std::mutex mu;
-    std::vector<GraphEntry> entries;
+    std::list<GraphEntry> lru;
 };
 
 GraphCache& graph_cache() {
@@ -809,17 +930,62 @@ GraphCache& graph_cache() {
     return *c;
 }
 
+size_t env_size(const char* name, size_t dflt) {
+    const char* e = std::getenv(name);
+    const long long v = e ? std::atoll(e) : 0;
+    return v > 0 ? static_cast<size_t>(v) : dflt;
+}
+
+void retire_graph(GraphEntry& e) {
+    hipGraphExec_t exec = e.exec;
+    hipEvent_t ev = e.last_use;
+    std::vector<void*> bufs = std::move(e.buffers);
+    std::vector<PlanRef> plans = std::move(e.plans);
+    retire(e.device, ev, [exec, ev, bufs, plans]() mutable {
+        (void)hipGraphExecDestroy(exec);
+        for (void* b : bufs) (void)hipFree(b);
+        if (ev) (void)hipEventDestroy(ev);
+        plans.clear();
+    });
+    e.exec = nullptr;
+    e.last_use = nullptr;
+}
+
+// Cache key: every field that the captured work depends on, written field by
+// field (no struct padding).
 std::string batch_key(const gw_problem_t* probs, int nprob, const Opts& o) {
     std::string k;
     auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+    auto put_i = [&](int64_t v) { put(&v, sizeof v); };
+    auto put_d = [&](double v) { put(&v, sizeof v); };
+    auto put_p = [&](const void* p) {
+        const uintptr_t v = reinterpret_cast<uintptr_t>(p);
+        put(&v, sizeof v);
+    };
     int dev = 0;
     (void)hipGetDevice(&dev);
-    put(&dev, sizeof dev);
-    put(&nprob, sizeof nprob);
-    put(&o, sizeof o);
+    put_i(dev);
+    put_i(nprob);
+    put_i(o.precision);
+    put_i(o.n_slices);
+    put_i(o.pair_chunk);
+    put_i(o.flags);
+    put_d(o.spin);
+    put_p(o.ws);
+    put_i(static_cast<int64_t>(o.ws_bytes));
     for (int q = 0; q < nprob; ++q) {
         const gw_problem_t& p = probs[q];
-        put(&p, sizeof p);  // pointers, sizes, grid
+        for (int a = 0; a < 3; ++a) put_i(p.grid.n[a]);
+        put_d(p.grid.volume);
+        put_p(p.psi_v);
+        put_i(p.nv);
+        put_p(p.psi_c);
+        put_i(p.nc);
+        put_p(p.e_v);
+        put_p(p.e_c);
+        put_i(p.ng);
+        put_i(p.nz);
+        put_p(p.chi);
         put(p.gvec, static_cast<size_t>(p.ng) * 3 * sizeof(int32_t));
         put(p.z, static_cast<size_t>(p.nz) * sizeof(gw_c128));
     }
@@ -829,13 +995,8 @@ std::string batch_key(const gw_problem_t* probs, int nprob, const Opts& o) {
 void release_graphs() {
     GraphCache& gc = graph_cache();
     std::lock_guard<std::mutex> lk(gc.mu);
-    for (auto& e : gc.entries) {
-        (void)hipSetDevice(e.device);
-        (void)hipDeviceSynchronize();
-        (void)hipGraphExecDestroy(e.exec);
-        for (void* b : e.buffers) (void)hipFree(b);
-    }
-    gc.entries.clear();
+    for (auto& e : gc.lru) retire_graph(e);
+    gc.lru.clear();
 }
 
 // Problems of one batch call in groups processed one after another: FP64 in a
@@ -848,9 +1009,7 @@ std::vector<std::vector<gw_problem_t>> batch_groups(const gw_problem_t* probs, i
         groups[0].assign(probs, probs + nprob);
         return groups;
     }
-    const char* env = std::getenv("GW_SPLIT_BATCH_BYTES");
-    const long long v = env ? std::atoll(env) : 0;
-    const size_t budget = v > 0 ? static_cast<size_t>(v) : (size_t(8) << 30);
+    const size_t budget = env_size("GW_SPLIT_BATCH_BYTES", size_t(8) << 30);
     size_t used = 0;
     for (int q = 0; q < nprob; ++q) {
         const gw_problem_t& pr = probs[q];
@@ -869,16 +1028,44 @@ std::vector<std::vector<gw_problem_t>> batch_groups(const gw_problem_t* probs, i
     return groups;
 }
 
-void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// Tile variants the batch may run with (the layout of its tables depends on it).
+std::vector<int> possible_variants(const Opts& o) {
+    if (o.precision != GW_FP64) return {0};
+    if (o.flags & GW_FLAG_FP64_TILE128) return {1};
+    const int forced = chi0_forced_variant();
+    if (forced >= 0) return {forced < kNumChi0Variants ? forced : 0};
+    std::vector<int> v;
+    for (int i = 0; i < kNumChi0Variants; ++i) v.push_back(i);
+    return v;
+}
+
+// Call scratch of a batched call: the autotuner's trial, and per group the
+// work buffer and the tables (non-graph), or the work buffer only when a
+// captured graph runs in the caller's workspace.
+size_t batched_bytes(const gw_problem_t* probs, int nprob, const Opts& o, bool in_workspace) {
+    size_t need = batch_tune_layout(probs, nprob, o).total;
+    const bool graph = (o.flags & GW_FLAG_GRAPH) != 0;
+    if (graph && !in_workspace) return need;
+    for (const auto& g : batch_groups(probs, nprob, o))
+        for (int v : possible_variants(o)) {
+            const BatchPlan bp = build_batch(g.data(), static_cast<int>(g.size()), o, v);
+            need = std::max(need, graph ? bp.work_bytes : align256(bp.work_bytes) + bp.table_bytes);
+        }
+    return need;
+}
+
+void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s,
+                      char* base) {
     const std::vector<std::vector<gw_problem_t>> groups = batch_groups(probs, nprob, o);
     if (!(o.flags & GW_FLAG_GRAPH)) {
         for (const auto& g : groups) {
             const int n = static_cast<int>(g.size());
-            const BatchPlan bp = build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s));
-            const size_t tab_off = (bp.work_bytes + 255) & ~static_cast<size_t>(255);
-            char* base = static_cast<char*>(scratch(tab_off + bp.table_bytes, s));
-            GW_HIP_TRY(hipStreamSynchronize(s));  // the tables below may still be read by earlier work
-            upload_batch(bp, g.data(), o, base, base + tab_off);
+            const BatchPlan bp = build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s, base));
+            const size_t tab_off = align256(bp.work_bytes);
+            // in stream order: the previous group's launches have read the tables
+            upload_batch(bp, g.data(), o, base, base + tab_off, s);
             enqueue_batch(bp, g.data(), o, base, base + tab_off, s);
         }
         return;
@@ -887,17 +1074,21 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
     GraphCache& gc = graph_cache();
     {
         std::lock_guard<std::mutex> lk(gc.mu);
-        for (auto& e : gc.entries)
-            if (e.key == key) {
+        for (auto it = gc.lru.begin(); it != gc.lru.end(); ++it)
+            if (it->key == key) {
+                gc.lru.splice(gc.lru.begin(), gc.lru, it);
+                GraphEntry& e = gc.lru.front();
                 GW_HIP_TRY(hipGraphLaunch(e.exec, s));
+                GW_HIP_TRY(hipEventRecord(e.last_use, s));
                 return;
             }
     }
+    require_alloc("captured graph");
     // first call: everything that allocates or copies happens before capture
     std::vector<BatchPlan> plans;
     for (const auto& g : groups) {
         const int n = static_cast<int>(g.size());
-        plans.push_back(build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s)));
+        plans.push_back(build_batch(g.data(), n, o, batch_variant(g.data(), n, o, s, base)));
         for (const gw_problem_t& pr : g) {
             const int tile = plans.back().split ? kSbTileI : chi0_variant_tile(plans.back().variant);
             (void)tile_order(ceil_div(pr.ng, tile), plans.back().split ? 4 : 8);
@@ -908,11 +1099,14 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
     GraphEntry e;
     e.key = key;
     GW_HIP_TRY(hipGetDevice(&e.device));
+    for (const BatchPlan& bp : plans)
+        for (const BatchQ& q : bp.q) e.plans.push_back(q.plan);
     auto free_buffers = [&] {
         for (void* b : e.buffers) (void)hipFree(b);
+        if (e.last_use) (void)hipEventDestroy(e.last_use);
     };
-    // groups run one after another: one work buffer serves them all (buffers[0]);
-    // each group keeps its own tables (buffers[1 + i])
+    // groups run one after another: one work buffer serves them all (the
+    // caller's workspace if given); each group keeps its own tables
     auto alloc = [&](size_t bytes) {
         void* buf = nullptr;
         if (hipMalloc(&buf, std::max<size_t>(bytes, 256)) != hipSuccess) {
@@ -924,20 +1118,24 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
                                 " of " + std::to_string(tot) + " bytes free)");
         }
         e.buffers.push_back(buf);
+        e.bytes += bytes;
         return static_cast<char*>(buf);
     };
     try {
+        GW_HIP_TRY(hipEventCreateWithFlags(&e.last_use, hipEventDisableTiming));
         size_t work = 0;
         for (const BatchPlan& bp : plans) work = std::max(work, bp.work_bytes);
-        char* wbuf = alloc(work);
-        for (size_t i = 0; i < groups.size(); ++i)
-            upload_batch(plans[i], groups[i].data(), o, wbuf, alloc(plans[i].table_bytes));
+        char* wbuf = o.ws ? o.ws : alloc(work);
+        std::vector<char*> tabs;
+        for (size_t i = 0; i < groups.size(); ++i) {
+            tabs.push_back(alloc(plans[i].table_bytes));
+            upload_batch(plans[i], groups[i].data(), o, wbuf, tabs.back(), s);
+        }
         hipGraph_t g = nullptr;
         GW_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         try {
             for (size_t i = 0; i < groups.size(); ++i)
-                enqueue_batch(plans[i], groups[i].data(), o, wbuf,
-                              static_cast<char*>(e.buffers[1 + i]), cs);
+                enqueue_batch(plans[i], groups[i].data(), o, wbuf, tabs[i], cs);
         } catch (...) {
             (void)hipStreamEndCapture(cs, &g);
             if (g) (void)hipGraphDestroy(g);
@@ -948,20 +1146,110 @@ void run_chi0_batched(const gw_problem_t* probs, int nprob, const Opts& o, hipSt
         const hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         GW_HIP_TRY(ie);
+        // the table uploads are on s; the replay follows them there
+        GW_HIP_TRY(hipGraphLaunch(e.exec, s));
+        GW_HIP_TRY(hipEventRecord(e.last_use, s));
     } catch (...) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
         free_buffers();
         throw;
     }
-    {
-        std::lock_guard<std::mutex> lk(gc.mu);
-        gc.entries.push_back(e);
+    std::lock_guard<std::mutex> lk(gc.mu);
+    gc.lru.push_front(std::move(e));
+    const size_t max_n = env_size("GW_GRAPH_CACHE_MAX", 16);
+    const size_t max_b = env_size("GW_GRAPH_CACHE_BYTES", size_t(64) << 30);
+    size_t total = 0;
+    for (const auto& x : gc.lru) total += x.bytes;
+    while (gc.lru.size() > 1 && (gc.lru.size() > max_n || total > max_b)) {
+        total -= gc.lru.back().bytes;
+        retire_graph(gc.lru.back());
+        gc.lru.pop_back();
     }
-    GW_HIP_TRY(hipGraphLaunch(e.exec, s));
 }
+
 }  // namespace
 }  // namespace gw
 
 using namespace gw;
+
+namespace gw {
+namespace {
+
+// Checks of gw_chi0's arguments (host only, before anything is enqueued);
+// builds the plans, which may still reject a size.
+Opts check_chi0_args(const gw_problem_t* probs, int nprob, const gw_opts_t* opts) {
+    if (nprob < 0) fail(GW_EINVAL, "nprob must be >= 0");
+    if (nprob > 0 && !probs) fail(GW_EINVAL, "probs is NULL");
+    const Opts o = read_opts(opts);
+    for (int q = 0; q < nprob; ++q) check_problem(probs[q], q);
+    if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
+        fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+    for (int q = 0; q < nprob; ++q) (void)get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
+    return o;
+}
+
+bool batched_call(int nprob, const Opts& o) {
+    return nprob > 1 && (o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16);
+}
+
+// Scratch of a gw_chi0 call; in_workspace: as the call needs it in a caller
+// workspace (a captured graph then keeps its work buffer there).
+size_t chi0_call_bytes(const gw_problem_t* probs, int nprob, const Opts& o, bool in_workspace) {
+    if (batched_call(nprob, o)) return batched_bytes(probs, nprob, o, in_workspace);
+    size_t need = 0;
+    for (int q = 0; q < nprob; ++q) {
+        const PlanRef plan = get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
+        need = std::max(need, chi0_layout(probs[q], o, *plan, 2, true).total);
+    }
+    return need;
+}
+
+void chi0_call(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s) {
+    char* base = call_scratch(chi0_call_bytes(probs, nprob, o, o.ws != nullptr), o, s);
+    if (batched_call(nprob, o)) {
+        run_chi0_batched(probs, nprob, o, s, base);
+        return;
+    }
+    for (int q = 0; q < nprob; ++q) {
+        const PlanRef plan = get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
+        run_chi0(probs[q], o, s, base, chi0_layout(probs[q], o, *plan, 2, true));
+    }
+}
+
+// The adjoint's problem with chi defaulted (it is not read) and its checks.
+gw_problem_t backward_problem(const gw_problem_t* prob, const void* grad_chi) {
+    if (!prob) fail(GW_EINVAL, "prob is NULL");
+    gw_problem_t p = *prob;
+    if (!p.chi) p.chi = reinterpret_cast<gw_c128*>(const_cast<void*>(grad_chi));
+    check_problem(p, 0);
+    return p;
+}
+
+// Scratch layout of gw_pseudobands: the host tables (copied in), then the
+// phase table the prep kernel writes.
+struct PbLayout {
+    size_t o_keep = 0, o_idx = 0, o_off = 0, o_ord = 0, o_toff = 0, o_th = 0, staged = 0, o_ph = 0;
+    size_t total = 0;
+};
+
+PbLayout pb_layout(int64_t nkeep, int64_t nidx, int64_t nslices, int64_t n_xi) {
+    PbLayout L;
+    const int64_t ntheta = nidx * (nslices > 0 ? n_xi : 0);
+    Carver cv;
+    L.o_keep = cv.take(static_cast<size_t>(nkeep) * sizeof(int32_t));
+    L.o_idx = cv.take(static_cast<size_t>(nidx) * sizeof(int32_t));
+    L.o_off = cv.take(static_cast<size_t>(nslices + 1) * sizeof(int32_t));
+    L.o_ord = cv.take(static_cast<size_t>(nslices) * sizeof(int32_t));
+    L.o_toff = cv.take(static_cast<size_t>(nslices) * sizeof(int64_t));
+    L.o_th = cv.take(static_cast<size_t>(ntheta) * sizeof(double));
+    L.staged = cv.off;
+    L.o_ph = cv.take(static_cast<size_t>(ntheta) * sizeof(double2));
+    L.total = cv.off;
+    return L;
+}
+
+}  // namespace
+}  // namespace gw
 
 extern "C" {
 
@@ -969,6 +1257,7 @@ gw_status_t gw_mtxel(const gw_grid_t* grid, const gw_c128* psi_v, int32_t nv,
                      const gw_c128* psi_c, int32_t nc, const int32_t* gvec, int32_t ng,
                      int64_t pair_begin, int64_t pair_count, gw_c128* m_out, void* stream) {
     return guarded([&] {
+        sweep_retired();
         check_grid(grid);
         if (nv < 0 || nc < 0) fail(GW_EINVAL, "nv and nc must be >= 0");
         check_gvec(gvec, ng, grid->n);
@@ -981,7 +1270,7 @@ gw_status_t gw_mtxel(const gw_grid_t* grid, const gw_c128* psi_v, int32_t nv,
         if (!psi_v || !psi_c) fail(GW_EINVAL, "psi_v / psi_c is NULL");
         if (!m_out) fail(GW_EINVAL, "m_out is NULL");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const MtxelPlan& plan = *get_plan(grid->n, gvec, ng);
+        const PlanRef plan = get_plan(grid->n, gvec, ng);
         // the linear pair range as rectangles of at most kBatch pairs
         constexpr int64_t kBatch = 4096;
         std::vector<std::pair<Rect, int64_t>> rects;  // (rectangle, first output row)
@@ -1002,41 +1291,56 @@ gw_status_t gw_mtxel(const gw_grid_t* grid, const gw_c128* psi_v, int32_t nv,
             rects.push_back({r, p0 - pair_begin});
             p0 += static_cast<int64_t>(r.nv) * r.nc;
         }
-        double2* t2 = static_cast<double2*>(scratch(t2_elems(plan, kBatch) * sizeof(double2), s));
+        double2* t2 = static_cast<double2*>(scratch(t2_elems(*plan, kBatch) * sizeof(double2), s));
         for (const auto& rr : rects)
-            launch_mtxel(plan, reinterpret_cast<const double2*>(psi_v),
+            launch_mtxel(*plan, reinterpret_cast<const double2*>(psi_v),
                          reinterpret_cast<const double2*>(psi_c), rr.first, grid->volume, t2,
                          reinterpret_cast<double2*>(m_out) + rr.second * ng, s);
+        mark_plan_used(*plan, s);
     });
 }
 
 gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* opts,
                     void* stream) {
     return guarded([&] {
-        if (nprob < 0) fail(GW_EINVAL, "nprob must be >= 0");
-        if (nprob > 0 && !probs) fail(GW_EINVAL, "probs is NULL");
-        const Opts o = read_opts(opts);
-        for (int q = 0; q < nprob; ++q) check_problem(probs[q], q);
-        if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
-            fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        for (int q = 0; q < nprob; ++q) {
-            // plan construction may still reject the sizes; do it for all first
-            (void)get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
-        }
-        if (nprob > 1 && (o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16))
-            run_chi0_batched(probs, nprob, o, s);
-        else
-            for (int q = 0; q < nprob; ++q) run_chi0(probs[q], o, s);
+        sweep_retired();
+        const Opts o = check_chi0_args(probs, nprob, opts);
+        chi0_call(probs, nprob, o, static_cast<hipStream_t>(stream));
     });
+}
+
+size_t gw_workspace_bytes(const gw_problem_t* probs, int32_t nprob, const gw_opts_t* opts,
+                          int32_t backward) {
+    size_t out = 0;
+    const gw_status_t st = guarded([&] {
+        if (!backward) {
+            const Opts o = check_chi0_args(probs, nprob, opts);
+            out = chi0_call_bytes(probs, nprob, o, true);
+            return;
+        }
+        if (nprob < 1) fail(GW_EINVAL, "the adjoint takes one problem");
+        const Opts o = read_opts(opts);
+        static const gw_c128 dummy{0.0, 0.0};
+        const gw_problem_t p = backward_problem(probs, &dummy);
+        const PlanRef plan = get_plan(p.grid.n, p.gvec, p.ng);
+        out = chi0_backward_bytes(*plan, p, true, true, true, o.pair_chunk);
+    });
+    return st == GW_OK ? out : static_cast<size_t>(-1);
+}
+
+size_t gw_pseudobands_workspace_bytes(int32_t nkeep, int64_t nidx, int32_t nslices,
+                                      int32_t n_xi) {
+    if (nkeep < 0 || nidx < 0 || nslices < 0 || n_xi < 0) return static_cast<size_t>(-1);
+    return pb_layout(nkeep, nidx, nslices, n_xi).total;
 }
 
 gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int64_t nr,
                            const int32_t* keep, int32_t nkeep, const int32_t* slice_idx,
                            const int32_t* slice_off, int32_t nslices, int32_t n_xi,
                            const double* theta, gw_c128* out_psi, double* out_e,
-                           void* stream) {
+                           void* workspace, size_t workspace_bytes, void* stream) {
     return guarded([&] {
+        sweep_retired();
         if (nb < 0 || nr < 1) fail(GW_EINVAL, "nb must be >= 0 and nr >= 1");
         if (nr >= (int64_t(1) << 31)) fail(GW_EINVAL, "grid has 2^31 or more points");
         if (nkeep < 0 || nslices < 0) fail(GW_EINVAL, "nkeep and nslices must be >= 0");
@@ -1064,7 +1368,14 @@ gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int6
         if (nout == 0) return;
         if (!psi || !e) fail(GW_EINVAL, "psi / e is NULL");
         if (!out_psi || !out_e) fail(GW_EINVAL, "out_psi / out_e is NULL");
+        if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255))
+            fail(GW_EINVAL, "workspace must be 256-byte aligned");
         hipStream_t s = static_cast<hipStream_t>(stream);
+        const PbLayout L = pb_layout(nkeep, nidx, nslices, nslices > 0 ? n_xi : 0);
+        Opts o;
+        o.ws = static_cast<char*>(workspace);
+        o.ws_bytes = workspace ? workspace_bytes : 0;
+        char* dev = call_scratch(L.total, o, s);
         // the host tables, packed and copied in stream order into scratch
         std::vector<int64_t> toff(nslices);
         for (int sl = 0; sl < nslices; ++sl) toff[sl] = static_cast<int64_t>(slice_off[sl]) * n_xi;
@@ -1074,38 +1385,26 @@ gw_status_t gw_pseudobands(const gw_c128* psi, const double* e, int32_t nb, int6
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
             return slice_off[a + 1] - slice_off[a] > slice_off[b + 1] - slice_off[b];
         });
-        Carver cv;
-        const size_t o_keep = cv.take(static_cast<size_t>(nkeep) * sizeof(int32_t));
-        const size_t o_idx = cv.take(static_cast<size_t>(nidx) * sizeof(int32_t));
-        const size_t o_off = cv.take(static_cast<size_t>(nslices + 1) * sizeof(int32_t));
-        const size_t o_ord = cv.take(static_cast<size_t>(nslices) * sizeof(int32_t));
-        const size_t o_toff = cv.take(static_cast<size_t>(nslices) * sizeof(int64_t));
-        const size_t o_th = cv.take(static_cast<size_t>(ntheta) * sizeof(double));
-        const size_t staged = cv.off;  // the tables above come from the host
-        const size_t o_ph = cv.take(static_cast<size_t>(ntheta) * sizeof(double2));
-        std::vector<char> host(staged, 0);
-        auto put = [&](size_t o, const void* src, size_t n) {
-            if (n) std::memcpy(host.data() + o, src, n);
+        std::vector<char> host(L.staged, 0);
+        auto put = [&](size_t off, const void* src, size_t n) {
+            if (n) std::memcpy(host.data() + off, src, n);
         };
-        put(o_keep, keep, static_cast<size_t>(nkeep) * sizeof(int32_t));
-        put(o_idx, slice_idx, static_cast<size_t>(nidx) * sizeof(int32_t));
-        if (nslices > 0) put(o_off, slice_off, static_cast<size_t>(nslices + 1) * sizeof(int32_t));
-        put(o_ord, order.data(), order.size() * sizeof(int32_t));
-        put(o_toff, toff.data(), toff.size() * sizeof(int64_t));
-        put(o_th, theta, static_cast<size_t>(ntheta) * sizeof(double));
-        char* dev = static_cast<char*>(scratch(cv.off, s));
-        GW_HIP_TRY(hipMemcpyAsync(dev, host.data(), staged, hipMemcpyHostToDevice, s));
-        PseudoTables t{reinterpret_cast<const int*>(dev + o_keep),
-                       reinterpret_cast<const int*>(dev + o_idx),
-                       reinterpret_cast<const int*>(dev + o_off),
-                       reinterpret_cast<const int*>(dev + o_ord),
-                       reinterpret_cast<const double*>(dev + o_th),
-                       reinterpret_cast<const int64_t*>(dev + o_toff),
-                       reinterpret_cast<double2*>(dev + o_ph)};
+        put(L.o_keep, keep, static_cast<size_t>(nkeep) * sizeof(int32_t));
+        put(L.o_idx, slice_idx, static_cast<size_t>(nidx) * sizeof(int32_t));
+        if (nslices > 0) put(L.o_off, slice_off, static_cast<size_t>(nslices + 1) * sizeof(int32_t));
+        put(L.o_ord, order.data(), order.size() * sizeof(int32_t));
+        put(L.o_toff, toff.data(), toff.size() * sizeof(int64_t));
+        put(L.o_th, theta, static_cast<size_t>(ntheta) * sizeof(double));
+        stage_h2d(dev, host.data(), L.staged, s);
+        PseudoTables t{reinterpret_cast<const int*>(dev + L.o_keep),
+                       reinterpret_cast<const int*>(dev + L.o_idx),
+                       reinterpret_cast<const int*>(dev + L.o_off),
+                       reinterpret_cast<const int*>(dev + L.o_ord),
+                       reinterpret_cast<const double*>(dev + L.o_th),
+                       reinterpret_cast<const int64_t*>(dev + L.o_toff),
+                       reinterpret_cast<double2*>(dev + L.o_ph)};
         launch_pseudobands(reinterpret_cast<const double2*>(psi), e, nr, t, nkeep, nslices,
                            nslices > 0 ? n_xi : 1, reinterpret_cast<double2*>(out_psi), out_e, s);
-        // the staging vector must outlive the copy
-        GW_HIP_TRY(hipStreamSynchronize(s));
     });
 }
 
@@ -1113,19 +1412,212 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
                              gw_c128* grad_psi_v, gw_c128* grad_psi_c, double* grad_e_v,
                              double* grad_e_c, const gw_opts_t* opts, void* stream) {
     return guarded([&] {
-        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        sweep_retired();
         const Opts o = read_opts(opts);
-        gw_problem_t p = *prob;
-        if (!p.chi) p.chi = reinterpret_cast<gw_c128*>(const_cast<gw_c128*>(grad_chi));
-        check_problem(p, 0);
+        const gw_problem_t p = backward_problem(prob, grad_chi);
         if (!grad_chi) fail(GW_EINVAL, "grad_chi is NULL");
         if (o.precision != GW_FP64) fail(GW_EUNSUPPORTED, "the adjoint is FP64 only");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const MtxelPlan& plan = *get_plan(p.grid.n, p.gvec, p.ng);
-        run_chi0_backward(plan, p, reinterpret_cast<const double2*>(grad_chi),
+        const PlanRef plan = get_plan(p.grid.n, p.gvec, p.ng);
+        const size_t need = chi0_backward_bytes(*plan, p, grad_psi_v != nullptr,
+                                                grad_psi_c != nullptr,
+                                                grad_e_v != nullptr || grad_e_c != nullptr,
+                                                o.pair_chunk);
+        char* base = call_scratch(need, o, s);
+        run_chi0_backward(*plan, p, reinterpret_cast<const double2*>(grad_chi),
                           reinterpret_cast<double2*>(grad_psi_v),
                           reinterpret_cast<double2*>(grad_psi_c), grad_e_v, grad_e_c, o.spin,
-                          o.pair_chunk, s, [&](size_t bytes) { return scratch(bytes, s); });
+                          o.pair_chunk, s, base);
+        mark_plan_used(*plan, s);
+    });
+}
+
+// ---------------------------------------------------------------- static subspace
+
+size_t gw_subspace_basis_workspace_bytes(int32_t ng, int32_t n_eig, const gw_diag_opts_t* opts) {
+    if (ng < 1 || n_eig < 1 || n_eig > ng) return static_cast<size_t>(-1);
+    return subspace_basis_bytes(ng, n_eig, opts ? opts->guard : 0);
+}
+
+gw_status_t gw_subspace_basis(const gw_c128* chi_static, int32_t ng, int32_t n_eig,
+                              gw_c128* basis, double* eigenvalues, const gw_diag_opts_t* opts,
+                              gw_diag_info_t* info, void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (ng < 1) fail(GW_EINVAL, "ng must be >= 1");
+        if (n_eig < 1 || n_eig > ng) fail(GW_EINVAL, "n_eig must lie in [1, ng]");
+        if (!chi_static || !basis || !eigenvalues) fail(GW_EINVAL, "a device pointer is NULL");
+        DiagParams prm;
+        Opts o;
+        if (opts) {
+            if (opts->tol < 0.0 || !std::isfinite(opts->tol)) fail(GW_EINVAL, "tol must be >= 0");
+            if (opts->max_iter < 0 || opts->guard < 0 || opts->max_degree < 0)
+                fail(GW_EINVAL, "max_iter, guard and max_degree must be >= 0");
+            if (opts->tol > 0.0) prm.tol = opts->tol;
+            if (opts->max_iter > 0) prm.max_iter = opts->max_iter;
+            if (opts->max_degree > 0) prm.max_degree = opts->max_degree;
+            prm.guard = opts->guard;
+            prm.seed = opts->seed;
+            o.ws = static_cast<char*>(opts->workspace);
+            o.ws_bytes = opts->workspace ? opts->workspace_bytes : 0;
+            if (o.ws && (reinterpret_cast<uintptr_t>(o.ws) & 255))
+                fail(GW_EINVAL, "workspace must be 256-byte aligned");
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char* base = call_scratch(subspace_basis_bytes(ng, n_eig, prm.guard), o, s);
+        const DiagResult r = run_subspace_basis(reinterpret_cast<const double2*>(chi_static), ng,
+                                                n_eig, reinterpret_cast<double2*>(basis),
+                                                eigenvalues, prm, base, s);
+        if (info) {
+            info->iterations = r.iterations;
+            info->degree = r.degree;
+            info->residual = r.residual;
+            info->bound = r.bound;
+        }
+    });
+}
+
+size_t gw_chi0_subspace_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
+                                        const gw_opts_t* opts) {
+    size_t out = 0;
+    const gw_status_t st = guarded([&] {
+        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        if (n_eig < 1) fail(GW_EINVAL, "n_eig must be >= 1");
+        const Opts o = read_opts(opts);
+        gw_problem_t p = *prob;
+        static gw_c128 dummy{0.0, 0.0};
+        if (!p.chi) p.chi = &dummy;
+        check_problem(p, 0);
+        const PlanRef plan = get_plan(p.grid.n, p.gvec, p.ng);
+        out = chi0_layout(p, o, *plan, 2, true, n_eig).total;
+    });
+    return st == GW_OK ? out : static_cast<size_t>(-1);
+}
+
+gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis, int32_t n_eig,
+                             const gw_opts_t* opts, void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        const Opts o = read_opts(opts);
+        check_problem(*prob, 0);
+        if (n_eig < 1 || n_eig > prob->ng) fail(GW_EINVAL, "n_eig must lie in [1, ng]");
+        if (!basis) fail(GW_EINVAL, "basis is NULL");
+        if (o.flags & GW_FLAG_GRAPH) fail(GW_EUNSUPPORTED, "GW_FLAG_GRAPH is for batched gw_chi0");
+        if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
+            fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const PlanRef plan = get_plan(prob->grid.n, prob->gvec, prob->ng);
+        const Chi0Layout L = chi0_layout(*prob, o, *plan, 2, true, n_eig);
+        char* base = call_scratch(L.total, o, s);
+        run_chi0(*prob, o, s, base, L, reinterpret_cast<const double2*>(basis));
+    });
+}
+
+// ---------------------------------------------------------------- dense building blocks
+
+gw_status_t gw_zgemm(char opa, char opb, int32_t m, int32_t n, int32_t k, gw_c128 alpha,
+                     const gw_c128* a, int64_t lda, int64_t stride_a, const gw_c128* b,
+                     int64_t ldb, int64_t stride_b, gw_c128 beta, gw_c128* c, int64_t ldc,
+                     int64_t stride_c, int32_t batch, void* stream) {
+    return guarded([&] {
+        auto op = [](char x) {
+            switch (x) {
+                case 'N': case 'n': return kOpN;
+                case 'T': case 't': return kOpT;
+                case 'C': case 'c': return kOpC;
+                default: fail(GW_EINVAL, std::string("op must be N, T or C, got ") + x);
+            }
+        };
+        const ZOp oa = op(opa), ob = op(opb);
+        if (m < 0 || n < 0 || k < 0 || batch < 0) fail(GW_EINVAL, "sizes must be >= 0");
+        if (m == 0 || n == 0 || batch == 0) return;
+        const int64_t acols = oa == kOpN ? k : m, bcols = ob == kOpN ? n : k;
+        const int64_t arows = oa == kOpN ? m : k, brows = ob == kOpN ? k : n;
+        if (!c) fail(GW_EINVAL, "c is NULL");
+        if (ldc < n) fail(GW_EINVAL, "ldc < n");
+        if (k > 0) {
+            if (!a || !b) fail(GW_EINVAL, "a / b is NULL");
+            if (lda < acols || ldb < bcols) fail(GW_EINVAL, "lda / ldb below the row length");
+        }
+        (void)arows;
+        (void)brows;
+        if (batch > 1 && stride_c < static_cast<int64_t>(m - 1) * ldc + n)
+            fail(GW_EINVAL, "stride_c must hold a whole C (products must not overlap)");
+        if (batch > 65535) fail(GW_EUNSUPPORTED, "at most 65535 products per call");
+        ZGemm g;
+        g.m = m;
+        g.n = n;
+        g.k = k;
+        g.a = reinterpret_cast<const double2*>(a);
+        g.lda = lda;
+        g.stride_a = stride_a;
+        g.b = reinterpret_cast<const double2*>(b);
+        g.ldb = ldb;
+        g.stride_b = stride_b;
+        g.c = reinterpret_cast<double2*>(c);
+        g.ldc = ldc;
+        g.stride_c = stride_c;
+        g.alpha = make_double2(alpha.re, alpha.im);
+        g.beta = make_double2(beta.re, beta.im);
+        g.batch = batch;
+        launch_zgemm(oa, ob, g, static_cast<hipStream_t>(stream));
+    });
+}
+
+size_t gw_heev_workspace_bytes(int32_t n, int32_t batch) {
+    if (n < 1 || batch < 1) return static_cast<size_t>(-1);
+    const size_t nn = static_cast<size_t>(n) * n * batch * sizeof(double2);
+    return ((nn + 255) & ~size_t(255)) + jacobi_work_bytes(n, batch) +
+           ((static_cast<size_t>(n) * batch * sizeof(int) + 255) & ~size_t(255));
+}
+
+gw_status_t gw_heev(const gw_c128* a, int32_t n, int32_t batch, double* w, gw_c128* v,
+                    double tol, void* workspace, size_t workspace_bytes, void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (n < 1 || batch < 1) fail(GW_EINVAL, "n and batch must be >= 1");
+        if (batch > 65535) fail(GW_EUNSUPPORTED, "at most 65535 matrices per call");
+        if (!a || !w || !v) fail(GW_EINVAL, "a device pointer is NULL");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(GW_EINVAL, "tol must be >= 0");
+        Opts o;
+        o.ws = static_cast<char*>(workspace);
+        o.ws_bytes = workspace ? workspace_bytes : 0;
+        if (o.ws && (reinterpret_cast<uintptr_t>(o.ws) & 255))
+            fail(GW_EINVAL, "workspace must be 256-byte aligned");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char* base = call_scratch(gw_heev_workspace_bytes(n, batch), o, s);
+        const size_t nn = static_cast<size_t>(n) * n;
+        const size_t abytes = (nn * batch * sizeof(double2) + 255) & ~size_t(255);
+        double2* ac = reinterpret_cast<double2*>(base);
+        void* jw = base + abytes;
+        int* perm_d = reinterpret_cast<int*>(base + abytes + jacobi_work_bytes(n, batch));
+        GW_HIP_TRY(hipMemcpyAsync(ac, a, nn * batch * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        double2* vtmp = reinterpret_cast<double2*>(v);
+        (void)jacobi_eigh(ac, vtmp, n, batch, tol > 0.0 ? tol : 1e-15, 100, jw, s);
+        // eigenvalues in increasing order, eigenvectors to match
+        std::vector<double2> dg(static_cast<size_t>(n) * batch);
+        for (int b = 0; b < batch; ++b)
+            GW_HIP_TRY(hipMemcpy2DAsync(dg.data() + static_cast<size_t>(b) * n, sizeof(double2),
+                                        ac + b * nn, (n + 1) * sizeof(double2), sizeof(double2), n,
+                                        hipMemcpyDeviceToHost, s));
+        GW_HIP_TRY(hipStreamSynchronize(s));
+        std::vector<int> perm(static_cast<size_t>(n) * batch);
+        std::vector<double> wv(static_cast<size_t>(n) * batch);
+        for (int b = 0; b < batch; ++b) {
+            int* pb = perm.data() + static_cast<size_t>(b) * n;
+            const double2* db = dg.data() + static_cast<size_t>(b) * n;
+            for (int i = 0; i < n; ++i) pb[i] = i;
+            std::stable_sort(pb, pb + n, [&](int x, int y) { return db[x].x < db[y].x; });
+            for (int i = 0; i < n; ++i) wv[static_cast<size_t>(b) * n + i] = db[pb[i]].x;
+        }
+        GW_HIP_TRY(hipMemcpyAsync(perm_d, perm.data(), perm.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, s));
+        GW_HIP_TRY(hipMemcpyAsync(w, wv.data(), wv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        // v <- v[:, perm] through the matrix buffer
+        GW_HIP_TRY(hipMemcpyAsync(ac, vtmp, nn * batch * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        launch_gather_cols(ac, vtmp, n, n, n, perm_d, batch, s);
+        GW_HIP_TRY(hipStreamSynchronize(s));  // the host vectors above are read by now
     });
 }
 
@@ -1134,10 +1626,12 @@ const char* gw_last_error(void) { return g_last_error.c_str(); }
 gw_status_t gw_release(void) {
     return guarded([&] {
         release_graphs();
+        release_plans();
+        drain_retired();
         release_aux();
         release_scratch();
-        release_plans();
         release_tile_orders();
+        release_staging();
     });
 }
 

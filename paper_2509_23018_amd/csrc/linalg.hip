@@ -1,0 +1,472 @@
+// Dense complex FP64 linear algebra on gfx950 (linalg.hpp): a GEMM on the
+// FP64 matrix cores, an elementwise axpby and a Hermitian Jacobi eigensolver.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "linalg.hpp"
+#include "prof.hpp"
+
+namespace gw {
+namespace {
+
+// ---------------------------------------------------------------- GEMM
+//
+// One workgroup of 4 waves per 64 x 64 tile of C; each wave owns a 32 x 32
+// quarter as 2 x 2 blocks of the 16x16x4 FP64 MFMA.  The k dimension is
+// staged through LDS 16 at a time; the next stage's global loads are issued
+// into registers before the current stage's MFMAs (loads unconditional on
+// clamped addresses, masks and conjugation applied at the LDS write).  Each
+// complex multiply-add takes three real products (p1 = ar br, p2 = ai bi,
+// p3 = (ar + ai)(br + bi); Re = p1 - p2, Im = p3 - p1 - p2).
+
+template <int OPA, int OPB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zgemm_kernel(
+    ZGemm g) {
+    __shared__ double2 s_a[64][17];  // [m][k]
+    __shared__ double2 s_b[16][65];  // [k][n]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int64_t bz = blockIdx.z;
+    const double2* A = g.a + bz * g.stride_a;
+    const double2* B = g.b + bz * g.stride_b;
+    double2* C = g.c + bz * g.stride_c;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int mlast = g.m - 1, nlast = g.n - 1, klast = g.k - 1;
+
+    dbl4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) p1[x][y] = p2[x][y] = p3[x][y] = zero4();
+
+    double2 ra[4], rb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            const double2* sa;
+            if (OPA == kOpN)
+                sa = A + static_cast<int64_t>(min(i0 + (e >> 4), mlast)) * g.lda +
+                     min(k0 + (e & 15), klast);
+            else
+                sa = A + static_cast<int64_t>(min(k0 + (e >> 6), klast)) * g.lda +
+                     min(i0 + (e & 63), mlast);
+            ra[u].x = sa->x;
+            ra[u].y = sa->y;
+            const double2* sb;
+            if (OPB == kOpN)
+                sb = B + static_cast<int64_t>(min(k0 + (e >> 6), klast)) * g.ldb +
+                     min(j0 + (e & 63), nlast);
+            else
+                sb = B + static_cast<int64_t>(min(j0 + (e >> 4), nlast)) * g.ldb +
+                     min(k0 + (e & 15), klast);
+            rb[u].x = sb->x;
+            rb[u].y = sb->y;
+        }
+    };
+    if (g.k > 0) fetch(0);
+    for (int k0 = 0; k0 < g.k; k0 += 16) {
+        __syncthreads();  // every wave is done with the previous stage
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            int mm, kk;
+            if (OPA == kOpN) {
+                mm = e >> 4;
+                kk = e & 15;
+            } else {
+                kk = e >> 6;
+                mm = e & 63;
+            }
+            const bool oka = i0 + mm < g.m && k0 + kk < g.k;
+            s_a[mm][kk] = oka ? make_double2(ra[u].x, OPA == kOpC ? -ra[u].y : ra[u].y)
+                              : make_double2(0.0, 0.0);
+            int nn;
+            if (OPB == kOpN) {
+                kk = e >> 6;
+                nn = e & 63;
+            } else {
+                nn = e >> 4;
+                kk = e & 15;
+            }
+            const bool okb = j0 + nn < g.n && k0 + kk < g.k;
+            s_b[kk][nn] = okb ? make_double2(rb[u].x, OPB == kOpC ? -rb[u].y : rb[u].y)
+                              : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        __builtin_amdgcn_s_setprio(1);
+        if (k0 + 16 < g.k) fetch(k0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(2);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double2 a[2], b[2];
+            double as[2], bs[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                a[x] = s_a[wi * 32 + x * 16 + row][s * 4 + kq];
+                as[x] = a[x].x + a[x].y;
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                b[y] = s_b[s * 4 + kq][wj * 32 + y * 16 + row];
+                bs[y] = b[y].x + b[y].y;
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    p1[x][y] = mfma_f64(a[x].x, b[y].x, p1[x][y]);
+                    p2[x][y] = mfma_f64(a[x].y, b[y].y, p2[x][y]);
+                    p3[x][y] = mfma_f64(as[x], bs[y], p3[x][y]);
+                }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
+    }
+    const bool use_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int r = i0 + wi * 32 + x * 16 + 4 * t + kq;
+                const int c = j0 + wj * 32 + y * 16 + row;
+                if (r >= g.m || c >= g.n) continue;
+                const double2 acc = make_double2(p1[x][y][t] - p2[x][y][t],
+                                                 p3[x][y][t] - p1[x][y][t] - p2[x][y][t]);
+                double2 v = cmul(g.alpha, acc);
+                double2* dst = C + static_cast<int64_t>(r) * g.ldc + c;
+                if (use_beta) {
+                    const double2 o = cmul(g.beta, *dst);
+                    v.x += o.x;
+                    v.y += o.y;
+                }
+                *dst = v;
+            }
+}
+
+template <int OPA, int OPB>
+void zgemm_launch(const ZGemm& g, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(ceil_div(g.n, 64)),
+                    static_cast<unsigned>(ceil_div(g.m, 64)), static_cast<unsigned>(g.batch));
+    ProfScope ps("zgemm", s);
+    hipLaunchKernelGGL((zgemm_kernel<OPA, OPB>), grid, dim3(256), 0, s, g);
+    GW_HIP_TRY(hipGetLastError());
+}
+
+// z may alias x or y (elementwise), so the pointers are not restrict
+__global__ __launch_bounds__(256) void zaxpby_kernel(int64_t n, double2 a, const double2* x,
+                                                     double2 b, const double2* y, double2* z) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double2 u = cmul(a, x[i]);
+        const double2 v = cmul(b, y[i]);
+        z[i] = make_double2(u.x + v.x, u.y + v.y);
+    }
+}
+
+// ---------------------------------------------------------------- Jacobi
+//
+// Round-robin order on n' = n rounded up to even: in step r (r < n' - 1) the
+// n'/2 pairs are (L[k], L[n'-1-k]) with L[0] = 0 and
+// L[j] = 1 + (j - 1 + r) mod (n' - 1); every pair meets once per sweep.  An
+// index n (odd n) is a phantom: its pair does not rotate.
+//
+// Rotation of pair (p, q) (p < q), from h_pp, h_qq and b = h_pq = |b| e^{i phi}:
+// tau = (h_qq - h_pp) / (2 |b|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// c = 1 / sqrt(1 + t^2), S = t c e^{i phi}; J = [[c, S], [-conj(S), c]] on
+// (p, q) makes (J^H H J)_pq = 0.  One step applies the n'/2 disjoint
+// rotations at once: A <- J^H A J and V <- V J.  A and V are read from one
+// buffer and written to the other (the rotation of every pair is computed from
+// the read buffer by each thread that needs it), so a step is one launch.
+
+__device__ __forceinline__ int rr_index(int j, int r, int np) {
+    return j == 0 ? 0 : 1 + (j - 1 + r) % (np - 1);
+}
+
+__device__ __forceinline__ void rr_pair(int k, int r, int np, int& p, int& q) {
+    const int a = rr_index(k, r, np), b = rr_index(np - 1 - k, r, np);
+    p = min(a, b);
+    q = max(a, b);
+}
+
+struct Rot {
+    double c;
+    double2 s;  // S
+};
+
+__device__ __forceinline__ Rot rotation(const double2* __restrict__ a, int n, int p, int q) {
+    Rot r{1.0, make_double2(0.0, 0.0)};
+    if (q >= n) return r;
+    const double2 b = a[static_cast<int64_t>(p) * n + q];
+    const double ab = hypot(b.x, b.y);
+    if (ab == 0.0) return r;
+    const double hpp = a[static_cast<int64_t>(p) * n + p].x;
+    const double hqq = a[static_cast<int64_t>(q) * n + q].x;
+    const double tau = (hqq - hpp) / (2.0 * ab);
+    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double c = 1.0 / sqrt(1.0 + t * t);
+    const double sc = t * c / ab;  // S = t c b / |b|
+    r.c = c;
+    r.s = make_double2(sc * b.x, sc * b.y);
+    return r;
+}
+
+// blocks [0, na): 2 x 2 blocks (k1, k2) of A; blocks [na, ...): (row, pair) of V
+__global__ __launch_bounds__(256) void jacobi_step_kernel(const double2* __restrict__ a_in,
+                                                          double2* __restrict__ a_out,
+                                                          const double2* __restrict__ v_in,
+                                                          double2* __restrict__ v_out, int n,
+                                                          int np, int r, int64_t na_threads,
+                                                          int64_t batch_stride) {
+    const int64_t bz = blockIdx.z;
+    a_in += bz * batch_stride;
+    a_out += bz * batch_stride;
+    v_in += bz * batch_stride;
+    v_out += bz * batch_stride;
+    const int half = np / 2;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < na_threads) {
+        const int k1 = static_cast<int>(t / half), k2 = static_cast<int>(t % half);
+        int p1, q1, p2, q2;
+        rr_pair(k1, r, np, p1, q1);
+        rr_pair(k2, r, np, p2, q2);
+        const Rot r1 = rotation(a_in, n, p1, q1);
+        const Rot r2 = k2 == k1 ? r1 : rotation(a_in, n, p2, q2);
+        const bool q1ok = q1 < n, q2ok = q2 < n;
+        auto ld = [&](int i, int j, bool ok) {
+            return ok ? a_in[static_cast<int64_t>(i) * n + j] : make_double2(0.0, 0.0);
+        };
+        const double2 app = ld(p1, p2, true), apq = ld(p1, q2, q2ok);
+        const double2 aqp = ld(q1, p2, q1ok), aqq = ld(q1, q2, q1ok && q2ok);
+        // right: [x_p, x_q] <- [c x_p - conj(S) x_q, S x_p + c x_q]
+        const double2 s2 = r2.s, s2c = make_double2(s2.x, -s2.y);
+        auto right = [&](double2 xp, double2 xq, double2& op, double2& oq) {
+            const double2 u = cmul(s2c, xq), w = cmul(s2, xp);
+            op = make_double2(r2.c * xp.x - u.x, r2.c * xp.y - u.y);
+            oq = make_double2(w.x + r2.c * xq.x, w.y + r2.c * xq.y);
+        };
+        double2 bpp, bpq, bqp, bqq;
+        right(app, apq, bpp, bpq);
+        right(aqp, aqq, bqp, bqq);
+        // left: rows p' = c row_p - S row_q, q' = conj(S) row_p + c row_q
+        const double2 s1 = r1.s, s1c = make_double2(s1.x, -s1.y);
+        auto left = [&](double2 xp, double2 xq, double2& op, double2& oq) {
+            const double2 u = cmul(s1, xq), w = cmul(s1c, xp);
+            op = make_double2(r1.c * xp.x - u.x, r1.c * xp.y - u.y);
+            oq = make_double2(w.x + r1.c * xq.x, w.y + r1.c * xq.y);
+        };
+        double2 cpp, cqp, cpq, cqq;
+        left(bpp, bqp, cpp, cqp);
+        left(bpq, bqq, cpq, cqq);
+        if (k1 == k2) {  // the rotated pair: exact zeros off the diagonal, real diagonal
+            cpq = cqp = make_double2(0.0, 0.0);
+            cpp.y = 0.0;
+            cqq.y = 0.0;
+        }
+        a_out[static_cast<int64_t>(p1) * n + p2] = cpp;
+        if (q2ok) a_out[static_cast<int64_t>(p1) * n + q2] = cpq;
+        if (q1ok) a_out[static_cast<int64_t>(q1) * n + p2] = cqp;
+        if (q1ok && q2ok) a_out[static_cast<int64_t>(q1) * n + q2] = cqq;
+        return;
+    }
+    const int64_t tv = t - na_threads;
+    if (tv >= static_cast<int64_t>(n) * half) return;
+    const int i = static_cast<int>(tv / half), k = static_cast<int>(tv % half);
+    int p, q;
+    rr_pair(k, r, np, p, q);
+    const Rot ro = rotation(a_in, n, p, q);
+    const double2 xp = v_in[static_cast<int64_t>(i) * n + p];
+    if (q >= n) {
+        v_out[static_cast<int64_t>(i) * n + p] = xp;
+        return;
+    }
+    const double2 xq = v_in[static_cast<int64_t>(i) * n + q];
+    const double2 sc = make_double2(ro.s.x, -ro.s.y);
+    const double2 u = cmul(sc, xq), w = cmul(ro.s, xp);
+    v_out[static_cast<int64_t>(i) * n + p] = make_double2(ro.c * xp.x - u.x, ro.c * xp.y - u.y);
+    v_out[static_cast<int64_t>(i) * n + q] = make_double2(w.x + ro.c * xq.x, w.y + ro.c * xq.y);
+}
+
+__global__ __launch_bounds__(256) void eye_kernel(double2* __restrict__ v, int n, int64_t stride) {
+    const int64_t bz = blockIdx.z;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nn;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        v[bz * stride + i] = make_double2(i / n == i % n ? 1.0 : 0.0, 0.0);
+}
+
+// Partial sums of (off-diagonal |a|^2, all |a|^2) per workgroup, then one
+// workgroup adds the partials: out[2*b], out[2*b + 1] per batch entry b.
+constexpr int kRedBlocks = 256;
+
+__global__ __launch_bounds__(256) void offnorm_partial_kernel(const double2* __restrict__ a,
+                                                              int n, int64_t stride,
+                                                              double* __restrict__ part) {
+    const int64_t bz = blockIdx.z;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    double off = 0.0, all = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nn;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double2 x = a[bz * stride + i];
+        const double m2 = x.x * x.x + x.y * x.y;
+        all += m2;
+        if (i / n != i % n) off += m2;
+    }
+    __shared__ double s_off[256], s_all[256];
+    s_off[threadIdx.x] = off;
+    s_all[threadIdx.x] = all;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s_off[threadIdx.x] += s_off[threadIdx.x + w];
+            s_all[threadIdx.x] += s_all[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[(bz * kRedBlocks + blockIdx.x) * 2] = s_off[0];
+        part[(bz * kRedBlocks + blockIdx.x) * 2 + 1] = s_all[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void offnorm_final_kernel(const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+    const int64_t bz = blockIdx.x;
+    __shared__ double s_off[256], s_all[256];
+    s_off[threadIdx.x] = part[(bz * kRedBlocks + threadIdx.x) * 2];
+    s_all[threadIdx.x] = part[(bz * kRedBlocks + threadIdx.x) * 2 + 1];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s_off[threadIdx.x] += s_off[threadIdx.x + w];
+            s_all[threadIdx.x] += s_all[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * bz] = s_off[0];
+        out[2 * bz + 1] = s_all[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void gather_cols_batched_kernel(
+    const double2* __restrict__ in, double2* __restrict__ out, int rows, int n_in, int n_out,
+    const int* __restrict__ perm) {
+    const int64_t bz = blockIdx.z;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(rows) * n_out) return;
+    const int64_t i = t / n_out;
+    const int j = static_cast<int>(t % n_out);
+    out[bz * rows * n_out + t] = in[bz * rows * n_in + i * n_in + perm[bz * n_out + j]];
+}
+
+}  // namespace
+
+void launch_gather_cols(const double2* in, double2* out, int rows, int n_in, int n_out,
+                        const int* perm, int batch, hipStream_t s) {
+    const int64_t n = static_cast<int64_t>(rows) * n_out;
+    if (n <= 0 || batch <= 0) return;
+    hipLaunchKernelGGL(gather_cols_batched_kernel,
+                       dim3(static_cast<unsigned>(ceil_div64(n, 256)), 1, batch), dim3(256), 0, s,
+                       in, out, rows, n_in, n_out, perm);
+    GW_HIP_TRY(hipGetLastError());
+}
+
+void launch_zgemm(ZOp opa, ZOp opb, const ZGemm& g, hipStream_t s) {
+    if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return;
+    switch (opa * 3 + opb) {
+        case 0: zgemm_launch<kOpN, kOpN>(g, s); break;
+        case 1: zgemm_launch<kOpN, kOpT>(g, s); break;
+        case 2: zgemm_launch<kOpN, kOpC>(g, s); break;
+        case 3: zgemm_launch<kOpT, kOpN>(g, s); break;
+        case 4: zgemm_launch<kOpT, kOpT>(g, s); break;
+        case 5: zgemm_launch<kOpT, kOpC>(g, s); break;
+        case 6: zgemm_launch<kOpC, kOpN>(g, s); break;
+        case 7: zgemm_launch<kOpC, kOpT>(g, s); break;
+        default: zgemm_launch<kOpC, kOpC>(g, s); break;
+    }
+}
+
+void launch_zaxpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y,
+                   double2* z, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>(ceil_div64(n, 256), 8192);
+    hipLaunchKernelGGL(zaxpby_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, n, a,
+                       x, b, y, z);
+    GW_HIP_TRY(hipGetLastError());
+}
+
+size_t jacobi_work_bytes(int n, int batch) {
+    const size_t nn = static_cast<size_t>(n) * n * batch * sizeof(double2);
+    // second A and V buffers, reduction partials and the two results per entry
+    return 2 * ((nn + 255) & ~size_t(255)) + static_cast<size_t>(batch) * kRedBlocks * 2 * 8 +
+           static_cast<size_t>(batch) * 2 * 8 + 512;
+}
+
+int jacobi_eigh(double2* a, double2* v, int n, int batch, double tol, int max_sweeps, void* work,
+                hipStream_t s) {
+    if (n <= 0 || batch <= 0) return 0;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    const size_t nnb = (static_cast<size_t>(nn) * batch * sizeof(double2) + 255) & ~size_t(255);
+    char* w = static_cast<char*>(work);
+    double2* a2 = reinterpret_cast<double2*>(w);
+    double2* v2 = reinterpret_cast<double2*>(w + nnb);
+    double* part = reinterpret_cast<double*>(w + 2 * nnb);
+    double* res = part + static_cast<size_t>(batch) * kRedBlocks * 2;
+    const unsigned eb = static_cast<unsigned>(std::min<int64_t>(ceil_div64(nn, 256), 4096));
+    hipLaunchKernelGGL(eye_kernel, dim3(eb, 1, batch), dim3(256), 0, s, v, n, nn);
+    GW_HIP_TRY(hipGetLastError());
+    if (n == 1) return 0;
+    const int np = n + (n & 1), half = np / 2;
+    const int64_t na = static_cast<int64_t>(half) * half;
+    const int64_t total = na + static_cast<int64_t>(n) * half;
+    const dim3 grid(static_cast<unsigned>(ceil_div64(total, 256)), 1, batch);
+    std::vector<double> h(2 * static_cast<size_t>(batch));
+    std::vector<double> prev(batch, -1.0);
+    double2 *ac = a, *an = a2, *vc = v, *vn = v2;
+    int sweeps = 0;
+    for (; sweeps < max_sweeps; ++sweeps) {
+        hipLaunchKernelGGL(offnorm_partial_kernel, dim3(kRedBlocks, 1, batch), dim3(256), 0, s, ac,
+                           n, nn, part);
+        hipLaunchKernelGGL(offnorm_final_kernel, dim3(batch), dim3(256), 0, s, part, res);
+        GW_HIP_TRY(hipGetLastError());
+        GW_HIP_TRY(hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        GW_HIP_TRY(hipStreamSynchronize(s));
+        // done when the off-diagonal norm is below tol of the norm, or when it
+        // has stopped falling (the convergence is quadratic until rounding
+        // re-creates off-diagonal entries at the level of the unit roundoff)
+        bool done = true;
+        for (int b = 0; b < batch; ++b) {
+            const double off = std::sqrt(h[2 * b]), all = std::sqrt(h[2 * b + 1]);
+            const bool small = off <= tol * all;
+            const bool stalled = sweeps >= 3 && prev[b] >= 0.0 && off >= 0.25 * prev[b] &&
+                                 off <= 1e-12 * all;
+            if (!small && !stalled) done = false;
+            prev[b] = off;
+        }
+        if (done) break;
+        ProfScope ps("jacobi_sweep", s);
+        for (int r = 0; r < np - 1; ++r) {
+            hipLaunchKernelGGL(jacobi_step_kernel, grid, dim3(256), 0, s, ac, an, vc, vn, n, np, r,
+                               na, nn);
+            std::swap(ac, an);
+            std::swap(vc, vn);
+        }
+        GW_HIP_TRY(hipGetLastError());
+    }
+    if (ac != a) {  // results back into the caller's buffers
+        GW_HIP_TRY(hipMemcpyAsync(a, ac, static_cast<size_t>(nn) * batch * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s));
+        GW_HIP_TRY(hipMemcpyAsync(v, vc, static_cast<size_t>(nn) * batch * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s));
+    }
+    return sweeps;
+}
+
+}  // namespace gw

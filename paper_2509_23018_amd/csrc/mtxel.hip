@@ -24,6 +24,7 @@
 
 #include "common.hpp"
 #include "plan.hpp"
+#include "lifetime.hpp"
 #include "prof.hpp"
 
 namespace gw {
@@ -368,7 +369,7 @@ XKernel select_x(int nb1) {
 
 struct PlanCache {
     std::mutex mu;
-    std::map<int, std::vector<std::unique_ptr<MtxelPlan>>> by_device;
+    std::map<int, std::vector<PlanRef>> by_device;
 };
 
 PlanCache& cache() {
@@ -537,37 +538,57 @@ void MtxelPlan::release() {
     (void)hipFree(w3inv);
     w1tab = w3tab = w2tab = w1inv = w2inv = w3inv = nullptr;
     gmap = boxmap = nullptr;
+    if (last_use) (void)hipEventDestroy(last_use);
+    last_use = nullptr;
 }
 
-MtxelPlan* get_plan(const int n[3], const int32_t* gvec, int ng) {
+namespace {
+
+// Deleter of a cached plan: the tables are retired, freed once the last work
+// that read them has completed.
+void retire_plan(MtxelPlan* p) {
+    const hipEvent_t ev = p->last_use;
+    retire(p->device, ev, [p] {
+        p->release();
+        delete p;
+    });
+}
+
+}  // namespace
+
+PlanRef get_plan(const int n[3], const int32_t* gvec, int ng) {
     int dev = 0;
     GW_HIP_TRY(hipGetDevice(&dev));
     PlanCache& pc = cache();
+    PlanRef evicted;  // released after the cache lock
     std::lock_guard<std::mutex> lk(pc.mu);
     auto& plans = pc.by_device[dev];
     for (auto& p : plans) {
         if (p->n[0] == n[0] && p->n[1] == n[1] && p->n[2] == n[2] && p->ng == ng &&
             std::equal(p->gvec.begin(), p->gvec.end(), gvec))
-            return p.get();
+            return p;
     }
+    require_alloc("plan (gather and twiddle tables) for this grid and G list");
     if (plans.size() >= 256) {  // bound the cache: drop the oldest plan
-        GW_HIP_TRY(hipDeviceSynchronize());
-        plans.front()->release();
+        evicted = std::move(plans.front());
         plans.erase(plans.begin());
     }
-    plans.push_back(build_plan(n, gvec, ng));
-    return plans.back().get();
+    std::unique_ptr<MtxelPlan> built = build_plan(n, gvec, ng);
+    built->device = dev;
+    GW_HIP_TRY(hipEventCreateWithFlags(&built->last_use, hipEventDisableTiming));
+    plans.push_back(PlanRef(built.release(), retire_plan));
+    return plans.back();
+}
+
+void mark_plan_used(MtxelPlan& p, hipStream_t s) {
+    if (stream_capturing(s)) return;
+    GW_HIP_TRY(hipEventRecord(p.last_use, s));
 }
 
 void release_plans() {
     PlanCache& pc = cache();
     std::lock_guard<std::mutex> lk(pc.mu);
-    for (auto& kv : pc.by_device) {
-        (void)hipSetDevice(kv.first);
-        (void)hipDeviceSynchronize();
-        for (auto& p : kv.second) p->release();
-        kv.second.clear();
-    }
+    pc.by_device.clear();  // every plan not held elsewhere is retired
 }
 
 size_t t2_elems(const MtxelPlan& p, int64_t npairs) {

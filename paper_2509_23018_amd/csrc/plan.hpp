@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 namespace gw {
@@ -58,12 +59,23 @@ struct MtxelPlan {
     double2* w2inv = nullptr;   // [n2p/16][nb2*4][64]    adjoint stage-y MFMA A operand
     double2* w3inv = nullptr;   // [nb3*4][n3p/16][64]    adjoint stage-z MFMA B operand
 
-    void release();
+    int device = 0;
+    hipEvent_t last_use = nullptr;  // recorded after the last enqueued work that read the tables
+
+    void release();  // frees the tables now (the caller knows no work reads them)
 };
 
+using PlanRef = std::shared_ptr<MtxelPlan>;
+
 // Build (or fetch from the per-device cache) the plan for this grid and G list.
-// Throws gw::Error on invalid input or unsupported size.
-MtxelPlan* get_plan(const int n[3], const int32_t* gvec, int ng);
+// Throws gw::Error on invalid input or unsupported size, and in no-allocation
+// mode when the plan does not exist yet.  The cache keeps at most 256 plans
+// per device; a plan dropped from it stays alive while a PlanRef holds it and
+// its tables are freed once the work recorded in last_use has completed.
+PlanRef get_plan(const int n[3], const int32_t* gvec, int ng);
+// Record that work just enqueued on s reads the plan's tables (no-op while s
+// is capturing a graph: a captured graph holds its own PlanRefs).
+void mark_plan_used(MtxelPlan& p, hipStream_t s);
 void release_plans();
 
 // MTXEL launches: m_out[k][i] = M_{pair k}(G_i) for the pairs of rc, in row

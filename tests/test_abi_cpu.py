@@ -28,7 +28,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for want in ("gw_mtxel", "gw_chi0", "gw_chi0_backward", "gw_last_error", "gw_release",
+    for want in ("gw_mtxel", "gw_chi0", "gw_chi0_backward", "gw_workspace_bytes",
+                 "gw_pseudobands_workspace_bytes", "gw_last_error", "gw_release",
                  "gw_abi_version"):
         assert want in names
 
@@ -36,7 +37,7 @@ def test_header_declares_the_boundary():
 def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.gw_abi_version() == 1
+    assert lib.gw_abi_version() == 2
 
 
 def _grid(gw, n, vol=1000.0):
@@ -85,13 +86,18 @@ def test_chi0_argument_checks(lib):
     assert lib.gw_chi0(ctypes.byref(p), 1, ctypes.byref(o), None) == -1
     assert "nz" in lib.gw_last_error().decode()
     p.nz = 1
+    o = gw._opts(flags=gw.GW_FLAG_ACC_HERMITIAN)
+    assert lib.gw_chi0(ctypes.byref(p), 1, ctypes.byref(o), None) == -1
+    assert "GW_FLAG_ACCUMULATE" in lib.gw_last_error().decode()
+    o = gw._opts()
     p.psi_v = None
     assert lib.gw_chi0(ctypes.byref(p), 1, ctypes.byref(o), None) == -1
     assert lib.gw_chi0(None, 1, ctypes.byref(o), None) == -1
     assert lib.gw_chi0_backward(None, None, None, None, None, None, None, None) == -1
 
 
-def _pb(lib, nb=4, nr=16, keep=(), idx=(0, 1, 2), off=(0, 3), n_xi=2, theta=None):
+def _pb(lib, nb=4, nr=16, keep=(), idx=(0, 1, 2), off=(0, 3), n_xi=2, theta=None,
+        ws=None, ws_bytes=0):
     """gw_pseudobands with host tables and dummy device pointers (the
     argument checks run on the host before anything touches them)."""
     k = np.asarray(keep, np.int32)
@@ -100,7 +106,7 @@ def _pb(lib, nb=4, nr=16, keep=(), idx=(0, 1, 2), off=(0, 3), n_xi=2, theta=None
     th = np.zeros(max(1, len(ix) * n_xi)) if theta is None else np.asarray(theta, np.float64)
     st = lib.gw_pseudobands(16, 16, nb, nr, k.ctypes.data if len(k) else None, len(k),
                             ix.ctypes.data, of.ctypes.data, len(of) - 1, n_xi, th.ctypes.data,
-                            16, 16, None)
+                            16, 16, ws, ws_bytes, None)
     return st, lib.gw_last_error().decode()
 
 
@@ -123,7 +129,50 @@ def test_pseudobands_argument_checks(lib):
     # nothing to produce: returns before any device work
     z = np.zeros(1, np.int32)
     assert lib.gw_pseudobands(None, None, 0, 1, None, 0, None, z.ctypes.data, 0, 2, None,
-                              None, None, None) == 0
+                              None, None, None, 0, None) == 0
+
+
+def test_pseudobands_workspace(lib):
+    """The workspace size grows with the tables, and a workspace one byte too
+    small, or not 256-byte aligned, is rejected on the host before any
+    device work."""
+    need = lib.gw_pseudobands_workspace_bytes(0, 3, 1, 2)
+    assert 0 < need < 4096
+    assert lib.gw_pseudobands_workspace_bytes(5, 300, 7, 4) > need
+    assert lib.gw_pseudobands_workspace_bytes(-1, 3, 1, 2) == ctypes.c_size_t(-1).value
+    st, msg = _pb(lib, ws=1 << 20, ws_bytes=need - 1)
+    assert st == -1 and "too small" in msg
+    st, msg = _pb(lib, ws=(1 << 20) + 64, ws_bytes=need)
+    assert st == -1 and "aligned" in msg
+
+
+def test_workspace_query_argument_checks(lib):
+    """gw_workspace_bytes runs the same host checks as gw_chi0 and returns
+    SIZE_MAX with a message when they fail."""
+    import paper_2509_23018_amd as gw
+    bad = ctypes.c_size_t(-1).value
+    p = gw._Problem()
+    p.grid = _grid(gw, (8, 8, 8))
+    g = np.array([[0, 0, 0], [0, 0, 0]], np.int32)
+    z = np.zeros(1, np.complex128)
+    p.psi_v = p.psi_c = p.e_v = p.e_c = p.chi = 16
+    p.nv, p.nc = 2, 2
+    p.gvec, p.ng, p.z, p.nz = g.ctypes.data, 2, z.ctypes.data, 1
+    o = gw._opts()
+    assert lib.gw_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), 0) == bad
+    assert "duplicate" in lib.gw_last_error().decode()
+    assert lib.gw_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), 1) == bad
+    assert lib.gw_workspace_bytes(None, 1, ctypes.byref(o), 0) == bad
+    assert lib.gw_workspace_bytes(ctypes.byref(p), 0, ctypes.byref(o), 1) == bad
+    o = gw._opts(precision=7)
+    p.ng = 1
+    assert lib.gw_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), 0) == bad
+    assert "precision" in lib.gw_last_error().decode()
+    # a misaligned workspace is an argument error of gw_chi0 itself
+    o = gw._opts()
+    o.workspace, o.workspace_bytes = (1 << 20) + 8, 1 << 20
+    assert lib.gw_chi0(ctypes.byref(p), 1, ctypes.byref(o), None) == -1
+    assert "aligned" in lib.gw_last_error().decode()
 
 
 def test_pseudoband_recipe():

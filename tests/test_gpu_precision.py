@@ -61,16 +61,19 @@ def _chunk_ranges(nv, nc, chunk):
     return out
 
 
-def split_bound(m, d, S, nv, nc, chunk, first_rounded=3, kb=KB):
+def split_bound(m, d, S, nv, nc, chunk, first_rounded=3, kb=KB, m_cols=None):
     """Elementwise bound on |chi_split - chi| for one frequency (d = s*Delta).
     Products with sa + sb >= first_rounded share FP32 accumulators that round
-    (BF16: t >= 2 in one group; FP16: one group per t, t >= 3 rounding)."""
-    ng = m.shape[1]
-    bound = np.zeros((ng, ng))
+    (BF16: t >= 2 in one group; FP16: one group per t, t >= 3 rounding).
+    m holds M at the rows' G; m_cols, if given, M at the columns' G (the
+    bound of entry (i, j) depends only on columns i of m and j of m_cols)."""
+    m_cols = m if m_cols is None else m_cols
+    shape = (m.shape[1], m_cols.shape[1])
+    bound = np.zeros(shape)
     amp = lambda e, s: np.where(s == 0, 2.0 ** e, 2.0 ** (e - 1 - 8 * s))
     for idx in _chunk_ranges(nv, nc, chunk):
         a = m[idx]
-        b = d[idx, None] * a
+        b = d[idx, None] * m_cols[idx]
         ea, eb = _blocks(a, kb), _blocks(b, kb)
         for blk in range(ea.shape[0]):
             sl = slice(blk * kb, (blk + 1) * kb)
@@ -79,8 +82,8 @@ def split_bound(m, d, S, nv, nc, chunk, first_rounded=3, kb=KB):
             eps_a = np.sqrt(2) * 2.0 ** (ea[blk] - 8 * S - 1)
             eps_b = np.sqrt(2) * 2.0 ** (eb[blk] - 8 * S - 1)
             trunc = np.outer(aa.sum(0), eps_b) + np.outer(eps_a, bb.sum(0) + n * eps_b)
-            dropped = np.zeros((ng, ng))
-            small = np.zeros((ng, ng))
+            dropped = np.zeros(shape)
+            small = np.zeros(shape)
             for sa in range(S):
                 for sb in range(S):
                     # complex slice magnitudes <= 2 * amp_a * amp_b (two components each)
@@ -139,7 +142,7 @@ def test_fp32_path():
         assert rel_fro(got[w], ref[w]) < 1e-5
 
 
-def fp32_bound(m, d, kblk=64):
+def fp32_bound(m, d, kblk=64, m_cols=None):
     """Elementwise bound on |chi_fp32 - chi| for one frequency (d = s*Delta).
     Operands are rounded to FP32 (relative 2^-24 per component, the G' side
     after the FP64 product d*m); each FP32 partial sum runs over at most kblk
@@ -151,7 +154,7 @@ def fp32_bound(m, d, kblk=64):
     u = 2.0 ** -24
     n = 4 * kblk + 2
     gam = n * u / (1 - n * u)
-    b = d[:, None] * m
+    b = d[:, None] * (m if m_cols is None else m_cols)
     wa = np.abs(m.real) + np.abs(m.imag)
     wb = np.abs(b.real) + np.abs(b.imag)
     wsum = wa.T @ wb

@@ -1,0 +1,179 @@
+"""The static subspace (Diag, Transf, CHI-Freq of Eq. (6)) and the dense
+building blocks under it (complex FP64 GEMM on MFMA, Jacobi eigensolver),
+against the FP64 oracle and plain NumPy.
+
+Eigenvectors carry a phase, and a degenerate or nearly degenerate eigenspace
+any rotation, so the device basis is compared through what is unique: the
+eigenvalues, the projector C_s C_s^H where the spectrum has a gap at n_eig,
+and C_s chi_B C_s^H; chi_B itself is compared element by element when both
+sides use the same basis."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_23018_amd as gw
+from gpu_helpers import FP64_TOL, device, rel_fro, to_dev
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _crand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _op(x, o):
+    return x if o == "N" else (x.swapaxes(-1, -2) if o == "T" else x.conj().swapaxes(-1, -2))
+
+
+@pytest.mark.parametrize("opa", ["N", "T", "C"])
+@pytest.mark.parametrize("opb", ["N", "T", "C"])
+def test_zgemm_ops_ragged_batched(opa, opb):
+    rng = np.random.default_rng(7)
+    m, n, k, batch = 70, 45, 37, 3
+    a = _crand(rng, batch, *((m, k) if opa == "N" else (k, m)))
+    b = _crand(rng, batch, *((k, n) if opb == "N" else (n, k)))
+    c0 = _crand(rng, batch, m, n)
+    alpha, beta = 0.7 - 0.2j, -0.3 + 1.1j
+    c = torch.from_numpy(c0.copy()).to(device())
+    gw.gw_zgemm(opa, opb, torch.from_numpy(a).to(device()), torch.from_numpy(b).to(device()),
+                alpha=alpha, beta=beta, c=c)
+    want = alpha * (_op(a, opa) @ _op(b, opb)) + beta * c0
+    assert rel_fro(c.cpu().numpy(), want) < 1e-14
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (64, 64, 16), (129, 3, 200), (5, 130, 0)])
+def test_zgemm_shapes(m, n, k):
+    rng = np.random.default_rng(m + n + k)
+    a, b = _crand(rng, m, k), _crand(rng, k, n)
+    got = gw.gw_zgemm("N", "N", torch.from_numpy(a).to(device()),
+                      torch.from_numpy(b).to(device())).cpu().numpy()
+    assert rel_fro(got, a @ b) < 1e-14 if k else np.all(got == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 129])
+def test_heev_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    x = _crand(rng, 2, n, n)
+    a = 0.5 * (x + x.conj().swapaxes(-1, -2))
+    a[1] *= 1e-3                              # a second, differently scaled matrix
+    w, v = gw.gw_heev(torch.from_numpy(a).to(device()))
+    w, v = w.cpu().numpy(), v.cpu().numpy()
+    for i in range(2):
+        scale = np.abs(np.linalg.eigvalsh(a[i])).max()
+        assert np.abs(w[i] - np.linalg.eigvalsh(a[i])).max() < 1e-13 * scale
+        assert np.abs(v[i].conj().T @ v[i] - np.eye(n)).max() < 1e-13
+        assert np.abs(a[i] @ v[i] - v[i] * w[i][None, :]).max() < 1e-13 * scale
+
+
+def test_heev_degenerate_spectrum():
+    rng = np.random.default_rng(3)
+    n = 40
+    u, _ = np.linalg.qr(_crand(rng, n, n))
+    lam = np.repeat([-2.0, 0.5, 3.0, 3.0 + 1e-9], 10)
+    a = (u * lam) @ u.conj().T
+    w, v = gw.gw_heev(torch.from_numpy(a).to(device()))
+    w, v = w.cpu().numpy(), v.cpu().numpy()
+    assert np.abs(w - np.sort(lam)).max() < 1e-13 * 3
+    assert np.abs(a @ v - v * w[None, :]).max() < 1e-13 * 3
+
+
+def _known_spectrum(ng, lam, seed):
+    rng = np.random.default_rng(seed)
+    u, _ = np.linalg.qr(_crand(rng, ng, ng))
+    return (u * lam[None, :]) @ u.conj().T
+
+
+def test_subspace_basis_known_spectrum():
+    """A negative semidefinite matrix of known spectrum with a gap after the
+    40 most negative eigenvalues: eigenvalues to 1e-12 of the norm, the
+    projector to the residual over the gap, orthonormal columns."""
+    ng, n_eig = 300, 40
+    rng = np.random.default_rng(11)
+    lam = -np.concatenate([np.sort(rng.uniform(2.0, 10.0, n_eig))[::-1],
+                           rng.uniform(0.0, 1.0, ng - n_eig)])
+    a = _known_spectrum(ng, lam, 12)
+    basis, ev, info = gw.gw_subspace_basis(torch.from_numpy(a).to(device()), n_eig, tol=1e-12)
+    basis, ev = basis.cpu().numpy(), ev.cpu().numpy()
+    cs, want = oracle.static_subspace_basis(a, n_eig)
+    assert info["residual"] <= 1e-12, info
+    assert np.abs(ev - want).max() < 1e-12 * 10.0
+    assert np.abs(basis.conj().T @ basis - np.eye(n_eig)).max() < 1e-12
+    assert np.abs(basis @ basis.conj().T - cs @ cs.conj().T).max() < 1e-10
+
+
+def _chi_static_problem(seed=41, nv=2, nc=10, r2=10, n=(12, 12, 12)):
+    z = (0.0, 0.4j, 1.7j, 0.3 + 0.01j)
+    p = gen.make_problem(n, nv, nc, r2=r2, z=z, seed=seed, pair_chunk=7)
+    chi = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    return p, chi
+
+
+@pytest.mark.parametrize("n_eig", [20, 12])
+def test_subspace_basis_of_chi0(n_eig):
+    """Diag of the oracle's chi0(0) (147 G, 20 pairs: rank 20): the kept
+    eigenvalues against numpy's, the static chi in the device basis diagonal;
+    at n_eig = rank the gap to zero is complete and the projector must agree."""
+    p, chi = _chi_static_problem()
+    a = torch.from_numpy(np.ascontiguousarray(chi[0])).to(device())
+    basis, ev, info = gw.gw_subspace_basis(a, n_eig, tol=1e-12)
+    basis, ev = basis.cpu().numpy(), ev.cpu().numpy()
+    cs, want = oracle.static_subspace_basis(chi[0], n_eig)
+    scale = np.abs(want).max()
+    assert np.abs(ev - want).max() < 1e-11 * scale, (ev, want, info)
+    diag = basis.conj().T @ chi[0] @ basis
+    assert np.abs(diag - np.diag(ev)).max() < 1e-10 * scale
+    if n_eig == 20:
+        assert np.abs(basis @ basis.conj().T - cs @ cs.conj().T).max() < 1e-9
+
+
+@pytest.mark.parametrize("prec,ns,tol", [("fp64", 0, FP64_TOL), ("split_bf16", 5, 1e-10),
+                                         ("fp32", 0, 1e-5)])
+@pytest.mark.parametrize("chunk", [7, 4096])
+def test_chi0_subspace_matches_oracle(prec, ns, tol, chunk):
+    """Transf + CHI-Freq with the oracle's basis on both sides: element by
+    element against Eq. (6), every frequency kind, several chunks or one."""
+    p, chi = _chi_static_problem(seed=42, nv=3, nc=17)
+    cs, _ = oracle.static_subspace_basis(chi[0], 24)
+    want = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                                spin=p.spin, pair_chunk=chunk)
+    dp = to_dev(p)
+    got = gw.gw_chi0_subspace(dp, torch.from_numpy(np.ascontiguousarray(cs)).to(device()),
+                              precision=prec, n_slices=ns, pair_chunk=chunk).cpu().numpy()
+    assert rel_fro(got, want) < tol, rel_fro(got, want)
+    for w in range(len(p.z)):
+        assert rel_fro(got[w], want[w]) < tol
+
+
+def test_subspace_pipeline_on_device():
+    """Diag, Transf and CHI-Freq all on the device: C_s chi_B(z) C_s^H equals
+    P chi(z) P of the oracle (P the oracle's projector, unique at n_eig = the
+    rank of chi0(0)), and chi_B(0) is diagonal with the device eigenvalues."""
+    p, chi = _chi_static_problem(seed=43)
+    n_eig = 20
+    dp = to_dev(p)
+    chi_d = gw.gw_chi0(dp, pair_chunk=p.pair_chunk)
+    basis, ev, _ = gw.gw_subspace_basis(chi_d[0].contiguous(), n_eig, tol=1e-12)
+    chib = gw.gw_chi0_subspace(dp, basis, pair_chunk=p.pair_chunk).cpu().numpy()
+    b = basis.cpu().numpy()
+    cs, _ = oracle.static_subspace_basis(chi[0], n_eig)
+    proj = cs @ cs.conj().T
+    for w in range(len(p.z)):
+        want = proj @ chi[w] @ proj
+        got = b @ chib[w] @ b.conj().T
+        assert rel_fro(got, want) < 1e-10, (w, rel_fro(got, want))
+    assert np.abs(chib[0] - np.diag(ev.cpu().numpy())).max() < 1e-11 * np.abs(chib[0]).max()
+
+
+def test_subspace_argument_errors():
+    a = torch.zeros((8, 8), dtype=torch.complex128, device=device())
+    with pytest.raises(gw.GWError):
+        gw.gw_subspace_basis(a, 9)
+    with pytest.raises(gw.GWError):
+        gw.gw_subspace_basis(a, 0)
+    basis, ev, info = gw.gw_subspace_basis(a, 3)      # chi = 0: unit vectors, zero eigenvalues
+    assert torch.all(ev == 0)
+    b = basis.cpu().numpy()
+    assert np.abs(b.conj().T @ b - np.eye(3)).max() == 0

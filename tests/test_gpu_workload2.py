@@ -1,0 +1,157 @@
+"""The 72^3 precision-study workload against the FP64 oracle, and the NV-block
+accumulation the benchmark times on it.
+
+Workload 2 has 256 x 3,840 bands on a 72^3 grid, 6,031 G (|g|^2 <= 126) and
+8 imaginary Gauss-Legendre frequencies.  Its full oracle (983,040 FFTs of
+373,248 points) does not fit a test, so the tests here keep the grid, the
+sphere, the frequencies and the chunk rectangle (4 valence x 1,024 conduction
+bands) and take 4 x 1,024 recipe bands: the 32 G rows drawn with
+default_rng(1002) against 32 sampled columns, from the oracle's direct sums
+(Eq. (4) on those entries).  FP64 must agree to 1e-12; FP32 and split BF16
+(3 and 5 slices) must stay inside the elementwise a-posteriori bound of their
+arithmetic on every sampled entry.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_23018_amd as gw
+from gpu_helpers import FP64_TOL, device, rel_fro, to_dev
+from test_gpu_precision import fp32_bound, split_bound
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+_W2 = {}
+
+
+def _workload2_sample():
+    """4 x 1,024 recipe bands on the workload-2 grid (orthonormalised on the
+    device), its rows and sampled columns, the oracle's entries and M at those
+    G (cached for the module)."""
+    if not _W2:
+        s = gen.CONFIG_SHAPES[2]
+        dp = gen.make_problem_device(s["n"], 4, 1024, r2=s["r2"], z=gen.frequencies(*s["freq"]),
+                                     seed=2, device=device())
+        assert dp.ng == 6031 and len(dp.z) == 8
+        p = gen.Problem(n=dp.n, volume=dp.volume, psi_v=dp.psi_v.cpu().numpy(),
+                        psi_c=dp.psi_c.cpu().numpy(), e_v=dp.e_v, e_c=dp.e_c, gvec=dp.gvec,
+                        z=dp.z, spin=dp.spin, pair_chunk=4096)
+        rows = np.sort(np.random.default_rng(1002).choice(p.ng, 32, replace=False))
+        cols = np.sort(np.concatenate([[0, p.ng - 1],
+                                       np.random.default_rng(1012).choice(p.ng, 30, replace=False)]))
+        ref = oracle.chi0_entries(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec[rows], p.gvec[cols],
+                                  p.z, p.n, p.volume, p.spin)
+        m_r = np.stack([oracle.mtxel_direct(p.psi_v, p.psi_c, g, p.n, p.volume).reshape(-1)
+                        for g in p.gvec[rows]], axis=1)                       # [K, 32]
+        m_c = np.stack([oracle.mtxel_direct(p.psi_v, p.psi_c, g, p.n, p.volume).reshape(-1)
+                        for g in p.gvec[cols]], axis=1)
+        d = oracle.energy_factor(p.e_v, p.e_c, p.z) * p.spin                  # [nz, K]
+        _W2.update(p=p, dp=dp, rows=rows, cols=cols, ref=ref, m_r=m_r, m_c=m_c, d=d)
+    return _W2
+
+
+def _run_sampled(w, chunk, **kw):
+    dp = w["dp"]
+    prob = gw.Chi0Problem(n=dp.n, volume=dp.volume, psi_v=dp.psi_v, psi_c=dp.psi_c,
+                          e_v=torch.from_numpy(dp.e_v).to(device()),
+                          e_c=torch.from_numpy(dp.e_c).to(device()), gvec=dp.gvec, z=dp.z)
+    chi = gw.gw_chi0(prob, pair_chunk=chunk, **kw)
+    r = torch.from_numpy(w["rows"]).to(device())
+    c = torch.from_numpy(w["cols"]).to(device())
+    got = chi[:, r][:, :, c].cpu().numpy()
+    # structure that holds at any size: the G = 0 row and column vanish at q = 0
+    assert torch.abs(chi[:, 0, :]).max() <= 1e-11 * torch.abs(chi).max()
+    return got
+
+
+@pytest.mark.parametrize("chunk", [4096, 2048], ids=["rect4x1024", "chunk2048"])
+def test_workload2_fp64(chunk):
+    """FP64 on the real 4 x 1,024 chunk rectangle (one chunk) and on chunks
+    of 2,048 pairs (two chunks accumulated)."""
+    w = _workload2_sample()
+    got = _run_sampled(w, chunk, precision="fp64")
+    assert rel_fro(got, w["ref"]) < FP64_TOL, rel_fro(got, w["ref"])
+
+
+def _bound_both_ways(bound_fn):
+    """Bound of each sampled entry: every frequency of this workload is on the
+    imaginary axis (real Delta, Hermitian chi), so an entry below the diagonal
+    is the mirror of one computed above it; take the larger of the two."""
+    return np.maximum(bound_fn(False), bound_fn(True).T)
+
+
+@pytest.mark.parametrize("chunk", [4096, 2048], ids=["rect4x1024", "chunk2048"])
+@pytest.mark.parametrize("prec,ns", [("fp32", 0), ("split_bf16", 3), ("split_bf16", 5)])
+def test_workload2_reduced_precision_within_bound(prec, ns, chunk):
+    """FP32 and split BF16 (the 3 slices of the precision study, and 5) on the
+    workload-2 shape: every sampled entry inside the a-posteriori bound of its
+    arithmetic, and the relative error of the right order."""
+    w = _workload2_sample()
+    p, ref = w["p"], w["ref"]
+    got = _run_sampled(w, chunk, precision=prec, n_slices=ns)
+    err = rel_fro(got, ref)
+    for iw in range(len(p.z)):
+        d = w["d"][iw]
+        if prec == "fp32":
+            bnd = _bound_both_ways(lambda t: fp32_bound(w["m_c"], d, m_cols=w["m_r"]) if t
+                                   else fp32_bound(w["m_r"], d, m_cols=w["m_c"]))
+        else:
+            bnd = _bound_both_ways(
+                lambda t: split_bound(w["m_c"] if t else w["m_r"], d, ns, p.nv, p.nc, chunk,
+                                      first_rounded=2, kb=128,
+                                      m_cols=w["m_r"] if t else w["m_c"]))
+        excess = np.abs(got[iw] - ref[iw]) - bnd - 1e-15 * np.abs(ref[iw]).max()
+        assert excess.max() <= 0, (prec, ns, iw, excess.max())
+    if prec == "fp32":
+        assert 1e-10 < err < 1e-5, err
+    elif ns == 3:
+        assert 1e-10 < err < 1e-6, err     # reported as measured, never as 1e-10
+    else:
+        assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("prec,ns,tol", [("fp64", 0, FP64_TOL), ("fp32", 0, 1e-5),
+                                         ("split_bf16", 5, 1e-10)])
+def test_nv_block_accumulation(prec, ns, tol):
+    """chi built as the benchmark builds it: one call per block of valence
+    bands, the first overwriting and the rest accumulating with the Hermitian
+    shortcut kept (GW_FLAG_ACC_HERMITIAN).  Imaginary-axis and static
+    frequencies (Hermitian) with one real-axis frequency (every tile, plain
+    accumulation), against the oracle over all bands."""
+    p = gen.make_problem((20, 18, 24), 9, 40, r2=15, z=(0.0, 0.7j, 0.3 + 0.01j, 2.5j), seed=41,
+                         pair_chunk=64)
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    dp = to_dev(p)
+    chi = torch.empty((len(p.z), p.ng, p.ng), dtype=torch.complex128, device=device())
+    acc = gw.GW_FLAG_ACCUMULATE | gw.GW_FLAG_ACC_HERMITIAN
+    for b, (v0, v1) in enumerate([(0, 4), (4, 5), (5, 9)]):
+        blk = gw.Chi0Problem(n=p.n, volume=p.volume, psi_v=dp.psi_v[v0:v1], psi_c=dp.psi_c,
+                             e_v=dp.e_v[v0:v1], e_c=dp.e_c, gvec=p.gvec, z=p.z, chi=chi)
+        gw.gw_chi0(blk, precision=prec, n_slices=ns, pair_chunk=p.pair_chunk,
+                   flags=0 if b == 0 else acc)
+    got = chi.cpu().numpy()
+    assert rel_fro(got, ref) < tol, rel_fro(got, ref)
+    herm_tol = 1e-13 if prec == "fp64" else tol
+    for iw in (0, 1, 3):
+        assert np.abs(got[iw] - got[iw].conj().T).max() <= herm_tol * np.abs(got[iw]).max()
+
+
+def test_acc_hermitian_batched():
+    """The same accumulation through the batched path (two problems per call)."""
+    ps = [gen.make_problem((12, 12, 12), 6, 20, r2=12, z=(0.4j, 0.0), seed=s, pair_chunk=40)
+          for s in (51, 52)]
+    refs = [oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                        spin=p.spin, pair_chunk=p.pair_chunk) for p in ps]
+    dps = [to_dev(p) for p in ps]
+    chis = [torch.empty((2, p.ng, p.ng), dtype=torch.complex128, device=device()) for p in ps]
+    acc = gw.GW_FLAG_ACCUMULATE | gw.GW_FLAG_ACC_HERMITIAN
+    for b, (v0, v1) in enumerate([(0, 2), (2, 6)]):
+        blks = [gw.Chi0Problem(n=p.n, volume=p.volume, psi_v=d.psi_v[v0:v1], psi_c=d.psi_c,
+                               e_v=d.e_v[v0:v1], e_c=d.e_c, gvec=p.gvec, z=p.z, chi=c)
+                for p, d, c in zip(ps, dps, chis)]
+        gw.gw_chi0(blks, pair_chunk=40, flags=0 if b == 0 else acc)
+    for c, r in zip(chis, refs):
+        assert rel_fro(c.cpu().numpy(), r) < FP64_TOL

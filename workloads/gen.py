@@ -195,6 +195,99 @@ def make_batched_config(q_indices=None, *, nv: int = 48, n=(40, 40, 40), nfreq: 
     return probs
 
 
+@dataclass
+class DeviceProblem:
+    """A seeded problem whose band set lives on the device (torch tensors);
+    energies, G list and frequencies stay on the host."""
+    n: tuple
+    volume: float
+    psi: "object"              # torch complex128 [nv + nc, N_r], valence rows first
+    nv: int
+    e_v: np.ndarray
+    e_c: np.ndarray
+    gvec: np.ndarray
+    z: np.ndarray
+    spin: float = SPIN
+    pair_chunk: int = 4096
+
+    @property
+    def nc(self):
+        return self.psi.shape[0] - self.nv
+
+    @property
+    def ng(self):
+        return self.gvec.shape[0]
+
+    @property
+    def psi_v(self):
+        return self.psi[:self.nv]
+
+    @property
+    def psi_c(self):
+        return self.psi[self.nv:]
+
+
+def orthonormal_bands_device(rng: np.random.Generator, nb: int, n, volume: float,
+                             device="cuda", row_block: int = 64):
+    """The bands of ``orthonormal_bands`` built for problems too large to
+    orthonormalise on the host: the same normals, drawn from ``rng`` in the
+    same order (all real parts, then all imaginary parts, row blocks drawn in
+    sequence give the same stream as one draw) and copied to the device block
+    by block; then two passes of Cholesky-QR there with torch.  Equal to the
+    host recipe up to rounding."""
+    import torch
+    nr = int(np.prod(n))
+    psi = torch.empty((nb, nr), dtype=torch.complex128, device=device)
+    view = torch.view_as_real(psi)                   # [nb, nr, 2]
+    for part in (0, 1):
+        for r0 in range(0, nb, row_block):
+            r1 = min(nb, r0 + row_block)
+            blk = torch.from_numpy(rng.standard_normal((r1 - r0, nr)))
+            view[r0:r1, :, part].copy_(blk.to(device))
+    if nb == 0:
+        return psi
+    dv = volume / nr
+    for _ in range(2):
+        # conj(psi) psi^T = conj(psi psi^H): the conjugate-transposed view maps
+        # to the BLAS conjugate-transpose operand, no copy of the bands
+        gram = torch.matmul(psi, psi.mH).conj() * dv
+        lo = torch.linalg.cholesky(gram)
+        # psi <- conj(lo)^-1 psi through the explicit inverse of the small
+        # triangular factor (a triangular solve with 10^5-10^6 right-hand
+        # sides asks the BLAS for more workspace than it will allocate)
+        eye = torch.eye(nb, dtype=psi.dtype, device=psi.device)
+        linv = torch.linalg.solve_triangular(lo.conj(), eye, upper=False)
+        psi = torch.matmul(linv, psi)
+        del gram, lo, eye, linv
+    return psi
+
+
+def make_problem_device(n, nv: int, nc: int, *, r2=None, gvec=None, z=(0.0,), seed: int = 0,
+                        device="cuda", pair_chunk: int = 4096) -> DeviceProblem:
+    """``make_problem`` with the band set orthonormalised on the device (same
+    draw order: psi, then E_v, then E_c)."""
+    n = tuple(int(x) for x in n)
+    volume = CELL_L ** 3
+    rng = np.random.default_rng(seed)
+    psi = orthonormal_bands_device(rng, nv + nc, n, volume, device)
+    e_v, e_c = band_energies(rng, nv, nc)
+    if gvec is None:
+        gvec = gsphere(r2)
+    return DeviceProblem(n=n, volume=volume, psi=psi, nv=nv, e_v=e_v, e_c=e_c,
+                         gvec=np.ascontiguousarray(gvec, dtype=np.int32),
+                         z=np.asarray(z, dtype=np.complex128).reshape(-1), pair_chunk=pair_chunk)
+
+
+def make_config_device(index: int, device="cuda", **overrides) -> DeviceProblem:
+    """Workload ``index`` with its band set drawn as in ``make_config`` and
+    orthonormalised on the device (for the 72^3 workload: 4,096 bands of
+    373,248 points, 24.5 GB)."""
+    s = dict(CONFIG_SHAPES[index])
+    s.update(overrides)
+    return make_problem_device(s["n"], s["nv"], s["nc"], r2=s["r2"], z=frequencies(*s["freq"]),
+                               seed=index, device=device, pair_chunk=s["pair_chunk"])
+
+
 def device_bands(nb: int, nr: int, *, seed: int, volume: float = CELL_L ** 3, device="cuda"):
     """Timing-only band sets generated on the GPU: ``nb`` rows of iid complex
     Gaussians scaled to unit norm on the grid on average (dV sum |psi|^2 ~ 1),
