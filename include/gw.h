@@ -276,6 +276,33 @@ size_t gw_pseudobands_workspace_bytes(int32_t nkeep, int64_t nidx, int32_t nslic
                                       int32_t n_xi);
 
 /*
+ * gw_chi0_fixed -- gw_chi0 for one problem with no allocation at all, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid it).  Its scratch is a fixed
+ * device array of gw_chi0_fixed_scratch_bytes() bytes (128 MiB) that the
+ * library holds on every device it runs on until the process ends.
+ *
+ * Same problem, options and result as gw_chi0 with nprob = 1, except:
+ * - the pair chunk is the largest one up to opts->pair_chunk whose buffers fit
+ *   the fixed scratch (MTXEL and the contraction alternate on `stream`, every
+ *   tile whole), so results agree with gw_chi0 to rounding, not bit for bit;
+ * - the plan of the grid and G list and the contraction's tile-order table
+ *   must exist on the device: make one ordinary gw_chi0 (or gw_mtxel) call with
+ *   the same grid, G list and precision first; otherwise GW_EINVAL before
+ *   anything is enqueued;
+ * - opts->workspace must be NULL, and GW_FLAG_GRAPH and GW_FLAG_AUTOTUNE are
+ *   GW_EINVAL (both allocate);
+ * - a problem whose buffers exceed the fixed scratch even at one pair per
+ *   chunk is GW_EUNSUPPORTED.
+ * Every call on a device shares that device's fixed scratch, which keeps what
+ * the last call wrote (every buffer is written before it is read, so nothing
+ * needs clearing): calls that overlap on one device (other streams, other
+ * threads) race; serialise them.  No allocation, no wait on the device.
+ */
+gw_status_t gw_chi0_fixed(const gw_problem_t* prob, const gw_opts_t* opts, void* stream);
+size_t gw_chi0_fixed_scratch_bytes(void);
+
+/*
  * Static subspace (Fast Full-Frequency GW section of the paper, Eq. (6)).
  * The static polarizability chi(0) of Eq. (4) is diagonalised and its n_eig
  * most significant eigenvectors, the columns of the N_G x n_eig matrix C_s,

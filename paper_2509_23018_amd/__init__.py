@@ -26,7 +26,7 @@ __all__ = [
     "GWError", "lib", "library_path", "GW_FP64", "GW_FP32", "GW_SPLIT_BF16", "GW_SPLIT_FP16",
     "GW_FLAG_NO_HERMITIAN", "GW_FLAG_ACCUMULATE", "GW_FLAG_GRAPH", "GW_FLAG_AUTOTUNE",
     "GW_FLAG_FP64_TILE128", "GW_FLAG_ACC_HERMITIAN",
-    "Chi0Problem", "gw_mtxel", "gw_chi0", "workspace_bytes", "new_workspace",
+    "Chi0Problem", "gw_mtxel", "gw_chi0", "gw_chi0_fixed", "workspace_bytes", "new_workspace",
     "pseudobands_workspace_bytes",
     "gw_chi0_backward", "gw_pseudobands", "gw_subspace_basis", "gw_chi0_subspace",
     "subspace_basis_workspace_bytes", "chi0_subspace_workspace_bytes", "gw_zgemm", "gw_heev", "Chi0", "chi0", "release", "profile_enable",
@@ -154,6 +154,11 @@ def lib() -> ctypes.CDLL:
                               ctypes.c_size_t, ctypes.c_void_p]
         L.gw_heev_workspace_bytes.restype = ctypes.c_size_t
         L.gw_heev_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.gw_chi0_fixed.restype = ctypes.c_int32
+        L.gw_chi0_fixed.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Opts),
+                                    ctypes.c_void_p]
+        L.gw_chi0_fixed_scratch_bytes.restype = ctypes.c_size_t
+        L.gw_chi0_fixed_scratch_bytes.argtypes = []
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_release.restype = ctypes.c_int32
@@ -360,6 +365,20 @@ def gw_chi0(problems, *, precision="fp64", n_slices=0, pair_chunk=4096, flags=0,
     with torch.cuda.device(dev):
         _check(lib().gw_chi0(arr, len(probs), ctypes.byref(o), _stream(dev, stream)))
     return probs[0].chi if single else [p.chi for p in probs]
+
+
+def gw_chi0_fixed(problem: Chi0Problem, *, precision="fp64", n_slices=0, pair_chunk=4096,
+                  flags=0, spin=2.0, stream=None) -> torch.Tensor:
+    """gw_chi0 of one problem through the library's fixed device scratch (no
+    allocation; the problem's plan must exist, see include/gw.h)."""
+    arr = _Problem()
+    keep: list = []
+    problem._fill(arr, keep)
+    o = _opts(precision, n_slices, pair_chunk, flags, spin)
+    with torch.cuda.device(problem.psi_v.device):
+        _check(lib().gw_chi0_fixed(ctypes.byref(arr), ctypes.byref(o),
+                                   _stream(problem.psi_v.device, stream)))
+    return problem.chi
 
 
 def gw_chi0_backward(problem: Chi0Problem, grad_chi: torch.Tensor, *, pair_chunk=4096,

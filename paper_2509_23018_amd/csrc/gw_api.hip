@@ -1432,6 +1432,98 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
     });
 }
 
+// ---------------------------------------------------------------- fixed scratch
+
+}  // extern "C"
+
+namespace gw {
+namespace {
+
+// Device scratch of gw_chi0_fixed: a file-scope array that every device the
+// library runs on holds from module load until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): fixed_scratch() looks its device address up once
+// per device, with that device current, and every use goes through it.
+constexpr size_t kFixedScratchBytes = size_t(128) << 20;
+__device__ __align__(256) char g_fixed_scratch[kFixedScratchBytes];
+
+char* fixed_scratch() {
+    static std::mutex mu;
+    static std::map<int, char*> by_device;
+    int dev = 0;
+    GW_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = by_device.find(dev);
+    if (it != by_device.end()) return it->second;
+    void* ptr = nullptr;
+    GW_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_fixed_scratch)));
+    if (!ptr) fail(GW_EINTERNAL, "no device address for the fixed scratch");
+    by_device[dev] = static_cast<char*>(ptr);
+    return static_cast<char*>(ptr);
+}
+
+// Throws in no-allocation mode when the tile-order table a contraction of
+// `ncols` columns would use does not exist yet.
+void require_tile_orders(const Opts& o, int ncols, int variant) {
+    if (o.precision == GW_SPLIT_BF16)
+        (void)tile_order(ceil_div(ncols, kSbTileI), 4);
+    else if (o.precision == GW_FP64)
+        (void)tile_order(ceil_div(ncols, chi0_variant_tile(variant)));
+    else
+        (void)tile_order(ceil_div(ncols, kSplitTile));
+}
+
+}  // namespace
+}  // namespace gw
+
+extern "C" {
+
+size_t gw_chi0_fixed_scratch_bytes(void) { return kFixedScratchBytes; }
+
+gw_status_t gw_chi0_fixed(const gw_problem_t* prob, const gw_opts_t* opts, void* stream) {
+    return guarded([&] {
+        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        Opts o = read_opts(opts);
+        check_problem(*prob, 0);
+        if (o.ws) fail(GW_EINVAL, "gw_chi0_fixed uses its fixed scratch: workspace must be NULL");
+        if (o.flags & (GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE))
+            fail(GW_EINVAL, "GW_FLAG_GRAPH and GW_FLAG_AUTOTUNE allocate: not with gw_chi0_fixed");
+        if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
+            fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char* base = fixed_scratch();  // once per device; no allocation
+        NoAllocScope no_alloc;
+        const PlanRef plan = get_plan(prob->grid.n, prob->gvec, prob->ng);  // must exist
+        // the largest chunk up to the requested one whose buffers (one M/Delta
+        // buffer, everything on the caller's stream, whole tiles) fit
+        auto need = [&](int chunk) {
+            Opts oc = o;
+            oc.pair_chunk = chunk;
+            return chi0_layout(*prob, oc, *plan, 1, false).total;
+        };
+        if (need(1) > kFixedScratchBytes)
+            fail(GW_EUNSUPPORTED, "this problem needs " + std::to_string(need(1)) +
+                                      " bytes of scratch at one pair per chunk; the fixed scratch "
+                                      "holds " + std::to_string(kFixedScratchBytes));
+        int lo = 1, hi = o.pair_chunk;
+        while (lo < hi) {
+            const int mid = lo + (hi - lo + 1) / 2;
+            if (need(mid) <= kFixedScratchBytes) lo = mid; else hi = mid - 1;
+        }
+        o.pair_chunk = lo;
+        const Chi0Layout L = chi0_layout(*prob, o, *plan, 1, false);
+        if (static_cast<int64_t>(prob->nv) * prob->nc > 0) {
+            int variant = 0;
+            if (o.precision == GW_FP64) {
+                const std::vector<Chunk> ch = make_chunks(*prob, L.cs);
+                variant = (o.flags & GW_FLAG_FP64_TILE128) ? 1 : std::max(0, lookup_variant(prob->ng, ch[0].kc));
+            }
+            require_tile_orders(o, prob->ng, variant);
+        }
+        run_chi0(*prob, o, s, base, L);
+    });
+}
+
 // ---------------------------------------------------------------- static subspace
 
 size_t gw_subspace_basis_workspace_bytes(int32_t ng, int32_t n_eig, const gw_diag_opts_t* opts) {
