@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="chi0_72cube: time FP64 only (no FP32 / split legs, no error sample)")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--profile-inputs", action="store_true",
+                    help="chi0_72cube: Gaussian bands drawn on the device, not orthonormalised "
+                         "(counter runs only: the work does not depend on the values)")
     ap.add_argument("--split-slices", type=int, nargs="*", default=None,
                     help="slice counts of the split-BF16 runs (default 3 4 5; empty: none)")
     ap.add_argument("--workload", default="chi0_72cube",
@@ -192,7 +195,17 @@ def bench_chi0_72cube(args):
 
     t_start = time.perf_counter()
     dev = torch.device("cuda", 0)
-    w = gen.make_config_device(2, device=dev)
+    if args.profile_inputs:
+        sh = gen.CONFIG_SHAPES[2]
+        rng = np.random.default_rng(2)
+        e_v, e_c = gen.band_energies(rng, sh["nv"], sh["nc"])
+        w = gen.DeviceProblem(n=sh["n"], volume=gen.CELL_L ** 3,
+                              psi=gen.device_bands(sh["nv"] + sh["nc"], int(np.prod(sh["n"])),
+                                                   seed=2, device=dev),
+                              nv=sh["nv"], e_v=e_v, e_c=e_c, gvec=gen.gsphere(sh["r2"]),
+                              z=gen.frequencies(*sh["freq"]), pair_chunk=sh["pair_chunk"])
+    else:
+        w = gen.make_config_device(2, device=dev)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     n, nv, nc, ng, nz = w.n, w.nv, w.nc, w.ng, len(w.z)
