@@ -370,6 +370,55 @@ size_t gw_chi0_subspace_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
                                         const gw_opts_t* opts);
 
 /*
+ * gw_epsinv -- the inverse dielectric matrix of Eq. (3),
+ *     eps^-1(z) = [I - v chi(z)]^-1,
+ * for nz frequencies, with v the diagonal Coulomb matrix.  Block Gauss-Jordan
+ * elimination without pivoting (64 columns per step, the updates as FP64
+ * MFMA GEMMs), on the device.
+ *
+ * chi     device [nz][ng][ng] (for instance gw_chi0's output), read only.
+ * vcoul   device [ng], v_G = 4 pi / |q + G|^2 in Hartree atomic units, >= 0;
+ *         at q = 0 the G = 0 entry is the caller's choice (0 excludes the head:
+ *         eps^-1 then has the identity's row and column there).
+ * epsinv  device OUT [nz][ng][ng], row index G, column G'; not chi.
+ * Without pivoting every leading block must be nonsingular: true for the
+ * zero and imaginary frequencies, where eps = v^1/2 eps~ v^-1/2 with eps~
+ * Hermitian positive definite (every eigenvalue >= 1); on the real axis the
+ * caller relies on it (a singular block propagates Inf/NaN, not an error).
+ * Asynchronous; workspace NULL or gw_epsinv_workspace_bytes(ng, nz) bytes.
+ */
+gw_status_t gw_epsinv(const gw_c128* chi, int32_t ng, int32_t nz, const double* vcoul,
+                      gw_c128* epsinv, void* workspace, size_t workspace_bytes, void* stream);
+size_t gw_epsinv_workspace_bytes(int32_t ng, int32_t nz);
+
+/*
+ * gw_gpp_sigma -- the full GPP self-energy matrix on an energy grid, the
+ * paper's off-diagonal kernel (Optimized GPP Kernel for Off-Diagonal
+ * Self-Energy Matrix Elements section; flop count of Eq. (8)):
+ *     Sigma_lm(E) = sum_n sum_GG' conj(M_ln(G)) P^{nE}_GG' M_mn(G'),
+ *     P^{nE}_GG' = Omega2_GG' v_G' / (2 wt_GG' (E - E_n - s_n wt_GG')),
+ * s_n = -1 for an occupied band, +1 for an empty one (the plasmon-pole term
+ * of the model the paper cites; the paper does not print it).  Per band and
+ * energy two complex GEMMs on FP64 MFMA, T = conj(M_n) P (N_Sigma x N_G x
+ * N_G, P formed inside the GEMM, never stored) and Sigma(E) += T M_n^T
+ * (N_Sigma x N_G x N_Sigma).
+ *
+ * m         device [nb][ns][ng]: M_ln(G) for the ns states l and the nb bands n.
+ * e_n       HOST [nb] band energies (Hartree); occupied HOST [nb] (0 / 1).
+ * energies  HOST [ne] complex energies E (the imaginary part broadens).
+ * omega2    device [ng][ng] complex; wtilde device [ng][ng] (> 0); vcoul device [ng].
+ * sigma     device OUT [ne][ns][ns], overwritten (row l, column m).
+ * Asynchronous (the energies are staged in stream order); workspace NULL or
+ * gw_gpp_sigma_workspace_bytes(ns, ng, ne) bytes.
+ */
+gw_status_t gw_gpp_sigma(const gw_c128* m, int32_t nb, int32_t ns, int32_t ng,
+                         const double* e_n, const int32_t* occupied, const gw_c128* energies,
+                         int32_t ne, const gw_c128* omega2, const double* wtilde,
+                         const double* vcoul, gw_c128* sigma, void* workspace,
+                         size_t workspace_bytes, void* stream);
+size_t gw_gpp_sigma_workspace_bytes(int32_t ns, int32_t ng, int32_t ne);
+
+/*
  * Dense building blocks of the subspace, dielectric and self-energy paths.
  *
  * gw_zgemm -- C = alpha op(A) op(B) + beta C for `batch` products (pointers

@@ -29,7 +29,8 @@ __all__ = [
     "Chi0Problem", "gw_mtxel", "gw_chi0", "gw_chi0_fixed", "workspace_bytes", "new_workspace",
     "pseudobands_workspace_bytes",
     "gw_chi0_backward", "gw_pseudobands", "gw_subspace_basis", "gw_chi0_subspace",
-    "subspace_basis_workspace_bytes", "chi0_subspace_workspace_bytes", "gw_zgemm", "gw_heev", "Chi0", "chi0", "release", "profile_enable",
+    "subspace_basis_workspace_bytes", "chi0_subspace_workspace_bytes", "gw_zgemm", "gw_heev",
+    "gw_epsinv", "gw_gpp_sigma", "Chi0", "chi0", "release", "profile_enable",
     "profile_reset",
     "profile_read",
 ]
@@ -159,6 +160,21 @@ def lib() -> ctypes.CDLL:
                                     ctypes.c_void_p]
         L.gw_chi0_fixed_scratch_bytes.restype = ctypes.c_size_t
         L.gw_chi0_fixed_scratch_bytes.argtypes = []
+        L.gw_epsinv.restype = ctypes.c_int32
+        L.gw_epsinv.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                ctypes.c_void_p]
+        L.gw_epsinv_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_epsinv_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.gw_gpp_sigma.restype = ctypes.c_int32
+        L.gw_gpp_sigma.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.gw_gpp_sigma_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_gpp_sigma_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.c_int32]
         L.gw_last_error.restype = ctypes.c_char_p
         L.gw_last_error.argtypes = []
         L.gw_release.restype = ctypes.c_int32
@@ -524,6 +540,57 @@ def gw_heev(a: torch.Tensor, *, tol=0.0, workspace=None, stream=None):
         _check(lib().gw_heev(A.data_ptr(), n, batch, w.data_ptr(), v.data_ptr(), float(tol), wp,
                              wb, _stream(a.device, stream)))
     return (w, v) if batched else (w[0], v[0])
+
+
+def gw_epsinv(chi: torch.Tensor, vcoul: torch.Tensor, *, out=None, workspace=None,
+              stream=None) -> torch.Tensor:
+    """eps^-1(z) = [I - v chi(z)]^-1 (Eq. (3)) for chi [nz, ng, ng] (or
+    [ng, ng]) and the Coulomb diagonal vcoul [ng], on the device."""
+    _dev(chi, "chi", torch.complex128)
+    _dev(vcoul, "vcoul", torch.float64)
+    single = chi.dim() == 2
+    c = chi[None] if single else chi
+    nz, ng = c.shape[0], c.shape[1]
+    if c.shape[2] != ng or vcoul.shape != (ng,):
+        raise ValueError("chi must be [nz, ng, ng] and vcoul [ng]")
+    if out is None:
+        out = torch.empty_like(c)
+    _dev(out, "out", torch.complex128)
+    wp, wb = _workspace(workspace)
+    with torch.cuda.device(chi.device):
+        _check(lib().gw_epsinv(c.data_ptr(), ng, nz, vcoul.data_ptr(), out.data_ptr(), wp, wb,
+                               _stream(chi.device, stream)))
+    return out[0] if single else out
+
+
+def gw_gpp_sigma(m: torch.Tensor, e_n, occupied, energies, omega2: torch.Tensor,
+                 wtilde: torch.Tensor, vcoul: torch.Tensor, *, out=None, workspace=None,
+                 stream=None) -> torch.Tensor:
+    """Full GPP self-energy matrix Sigma[e, l, m] on the energy grid: m
+    [nb, ns, ng] device, e_n / occupied [nb] host, energies [ne] host complex,
+    omega2 [ng, ng], wtilde [ng, ng], vcoul [ng] device."""
+    _dev(m, "m", torch.complex128)
+    _dev(omega2, "omega2", torch.complex128)
+    _dev(wtilde, "wtilde", torch.float64)
+    _dev(vcoul, "vcoul", torch.float64)
+    nb, ns, ng = m.shape
+    en = np.ascontiguousarray(np.asarray(e_n, dtype=np.float64).reshape(-1))
+    oc = np.ascontiguousarray(np.asarray(occupied, dtype=np.int32).reshape(-1))
+    ee = _host_c128(energies)
+    if en.shape[0] != nb or oc.shape[0] != nb:
+        raise ValueError("e_n and occupied must have one entry per band")
+    if omega2.shape != (ng, ng) or wtilde.shape != (ng, ng) or vcoul.shape != (ng,):
+        raise ValueError("omega2, wtilde must be [ng, ng] and vcoul [ng]")
+    if out is None:
+        out = torch.empty((ee.shape[0], ns, ns), dtype=torch.complex128, device=m.device)
+    _dev(out, "out", torch.complex128)
+    wp, wb = _workspace(workspace)
+    with torch.cuda.device(m.device):
+        _check(lib().gw_gpp_sigma(m.data_ptr(), nb, ns, ng, en.ctypes.data, oc.ctypes.data,
+                                  ee.ctypes.data, ee.shape[0], omega2.data_ptr(),
+                                  wtilde.data_ptr(), vcoul.data_ptr(), out.data_ptr(), wp, wb,
+                                  _stream(m.device, stream)))
+    return out
 
 
 class Chi0(torch.autograd.Function):

@@ -17,6 +17,8 @@
 #include "backward.hpp"
 #include "chi0.hpp"
 #include "common.hpp"
+#include "epsinv.hpp"
+#include "gpp.hpp"
 #include "gw.h"
 #include "items.hpp"
 #include "lifetime.hpp"
@@ -1603,6 +1605,76 @@ gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis, int
         const Chi0Layout L = chi0_layout(*prob, o, *plan, 2, true, n_eig);
         char* base = call_scratch(L.total, o, s);
         run_chi0(*prob, o, s, base, L, reinterpret_cast<const double2*>(basis));
+    });
+}
+
+// ---------------------------------------------------------------- inverse dielectric matrix
+
+size_t gw_epsinv_workspace_bytes(int32_t ng, int32_t nz) {
+    if (ng < 1 || nz < 1) return static_cast<size_t>(-1);
+    return epsinv_bytes(ng, nz);
+}
+
+gw_status_t gw_epsinv(const gw_c128* chi, int32_t ng, int32_t nz, const double* vcoul,
+                      gw_c128* epsinv, void* workspace, size_t workspace_bytes, void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (ng < 1 || nz < 1) fail(GW_EINVAL, "ng and nz must be >= 1");
+        if (nz > 65535) fail(GW_EUNSUPPORTED, "at most 65535 frequencies per call");
+        if (!chi || !vcoul || !epsinv) fail(GW_EINVAL, "a device pointer is NULL");
+        if (static_cast<const void*>(chi) == static_cast<const void*>(epsinv))
+            fail(GW_EINVAL, "chi and epsinv must not be the same buffer");
+        Opts o;
+        o.ws = static_cast<char*>(workspace);
+        o.ws_bytes = workspace ? workspace_bytes : 0;
+        if (o.ws && (reinterpret_cast<uintptr_t>(o.ws) & 255))
+            fail(GW_EINVAL, "workspace must be 256-byte aligned");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char* base = call_scratch(epsinv_bytes(ng, nz), o, s);
+        run_epsinv(reinterpret_cast<const double2*>(chi), ng, nz, vcoul,
+                   reinterpret_cast<double2*>(epsinv), base, s);
+    });
+}
+
+// ---------------------------------------------------------------- GPP off-diagonal self-energy
+
+size_t gw_gpp_sigma_workspace_bytes(int32_t ns, int32_t ng, int32_t ne) {
+    if (ns < 0 || ng < 0 || ne < 1) return static_cast<size_t>(-1);
+    return gpp_bytes(ns, ng, ne);
+}
+
+gw_status_t gw_gpp_sigma(const gw_c128* m, int32_t nb, int32_t ns, int32_t ng,
+                         const double* e_n, const int32_t* occupied, const gw_c128* energies,
+                         int32_t ne, const gw_c128* omega2, const double* wtilde,
+                         const double* vcoul, gw_c128* sigma, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (nb < 0 || ns < 1 || ng < 1 || ne < 1) fail(GW_EINVAL, "need nb >= 0, ns, ng, ne >= 1");
+        if (ne > 65535) fail(GW_EUNSUPPORTED, "at most 65535 energies per call");
+        if (!sigma || !energies) fail(GW_EINVAL, "sigma / energies is NULL");
+        if (nb > 0 && (!m || !e_n || !occupied || !omega2 || !wtilde || !vcoul))
+            fail(GW_EINVAL, "an input pointer is NULL");
+        for (int32_t i = 0; i < ne; ++i)
+            if (!std::isfinite(energies[i].re) || !std::isfinite(energies[i].im))
+                fail(GW_EINVAL, "energies must be finite");
+        for (int32_t n = 0; n < nb; ++n)
+            if (!std::isfinite(e_n[n])) fail(GW_EINVAL, "e_n must be finite");
+        Opts o;
+        o.ws = static_cast<char*>(workspace);
+        o.ws_bytes = workspace ? workspace_bytes : 0;
+        if (o.ws && (reinterpret_cast<uintptr_t>(o.ws) & 255))
+            fail(GW_EINVAL, "workspace must be 256-byte aligned");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t need = gpp_bytes(ns, ng, ne);
+        char* base = call_scratch(need, o, s);
+        // the energies follow the first-GEMM buffer, staged in stream order
+        const size_t e_off = need - ((static_cast<size_t>(ne) * sizeof(double2) + 255) & ~size_t(255));
+        stage_h2d(base + e_off, energies, static_cast<size_t>(ne) * sizeof(double2), s);
+        run_gpp_sigma(reinterpret_cast<const double2*>(m), nb, ns, ng, e_n, occupied,
+                      reinterpret_cast<const double2*>(base + e_off), ne,
+                      reinterpret_cast<const double2*>(omega2), wtilde, vcoul,
+                      reinterpret_cast<double2*>(sigma), base, s);
     });
 }
 
