@@ -278,6 +278,81 @@ def make_problem_device(n, nv: int, nc: int, *, r2=None, gvec=None, z=(0.0,), se
                          z=np.asarray(z, dtype=np.complex128).reshape(-1), pair_chunk=pair_chunk)
 
 
+def shell_bands_device(rng: np.random.Generator, nb: int, n, volume: float, width: float,
+                       device="cuda", row_block: int = 64):
+    """Bands with the momentum structure of free-electron-like states, for the
+    static-subspace workloads: band j's plane-wave coefficients are the
+    recipe's normals (same draw order) damped to a shell around
+    |g| = k_j = (3 (j + 1/2) / (4 pi))^(1/3), the radius below which j grid
+    wave vectors lie, of Gaussian width ``width`` (g the integer wave vector
+    of a grid frequency); brought to the grid and orthonormalised in band order
+    as in ``orthonormal_bands_device``.  With free-electron energies
+    (``shell_energies``), a large momentum transfer G needs pairs far apart in
+    energy, so |chi_GG(0)| falls off with |G| and the spectrum of chi0(0)
+    decays, as for the DFT states the paper works with; white bands with the
+    recipe's energies give a nearly flat one."""
+    import torch
+    n = tuple(int(x) for x in n)
+    nr = int(np.prod(n))
+    ax = [np.fft.fftfreq(k, 1.0 / k) for k in n]            # integer frequencies
+    gabs = np.sqrt(ax[0][:, None, None] ** 2 + ax[1][None, :, None] ** 2 +
+                   ax[2][None, None, :] ** 2).reshape(-1)
+    gabs = torch.from_numpy(gabs).to(device)
+    psi = torch.empty((nb, nr), dtype=torch.complex128, device=device)
+    view = torch.view_as_real(psi)
+    for part in (0, 1):
+        for r0 in range(0, nb, row_block):
+            r1 = min(nb, r0 + row_block)
+            view[r0:r1, :, part].copy_(torch.from_numpy(rng.standard_normal((r1 - r0, nr))).to(device))
+    kj = torch.from_numpy((3.0 * (np.arange(nb) + 0.5) / (4.0 * np.pi)) ** (1.0 / 3.0)).to(device)
+    for r0 in range(0, nb, row_block):
+        r1 = min(nb, r0 + row_block)
+        env = torch.exp(-((gabs[None, :] - kj[r0:r1, None]) ** 2) / (2.0 * width * width))
+        blk = (psi[r0:r1] * env).reshape(r1 - r0, *n)
+        psi[r0:r1] = torch.fft.ifftn(blk, dim=(1, 2, 3)).reshape(r1 - r0, nr)
+    if nb == 0:
+        return psi
+    dv = volume / nr
+    for _ in range(2):
+        gram = torch.matmul(psi, psi.mH).conj() * dv
+        lo = torch.linalg.cholesky(gram)
+        eye = torch.eye(nb, dtype=psi.dtype, device=psi.device)
+        linv = torch.linalg.solve_triangular(lo.conj(), eye, upper=False)
+        psi = torch.matmul(linv, psi)
+        del gram, lo, eye, linv
+    return psi
+
+
+def shell_energies(nv: int, nc: int, gap: float = 0.05, cell_l: float = CELL_L):
+    """Free-electron energies of the shell bands: band j at
+    (2 pi k_j / L)^2 / 2 with k_j as in ``shell_bands_device``, shifted so
+    that the valence bands lie below zero and the conduction bands from
+    ``gap`` Ha up."""
+    nb = nv + nc
+    kj = (3.0 * (np.arange(nb) + 0.5) / (4.0 * np.pi)) ** (1.0 / 3.0)
+    e = 0.5 * (2.0 * np.pi * kj / cell_l) ** 2
+    e_v = e[:nv] - (e[nv - 1] if nv else 0.0)
+    e_c = e[nv:] - (e[nv] if nc else 0.0) + gap
+    return e_v, e_c
+
+
+def make_shell_config_device(index: int, width: float = 1.0, device="cuda",
+                             **overrides) -> DeviceProblem:
+    """Workload ``index``'s shape, seed, G-sphere and frequencies with shell
+    bands (``shell_bands_device``) and their free-electron energies
+    (``shell_energies``)."""
+    s = dict(CONFIG_SHAPES[index])
+    s.update(overrides)
+    n = tuple(int(x) for x in s["n"])
+    volume = CELL_L ** 3
+    rng = np.random.default_rng(index)
+    psi = shell_bands_device(rng, s["nv"] + s["nc"], n, volume, width, device)
+    e_v, e_c = shell_energies(s["nv"], s["nc"])
+    return DeviceProblem(n=n, volume=volume, psi=psi, nv=s["nv"], e_v=e_v, e_c=e_c,
+                         gvec=gsphere(s["r2"]), z=frequencies(*s["freq"]),
+                         pair_chunk=s["pair_chunk"])
+
+
 def make_config_device(index: int, device="cuda", **overrides) -> DeviceProblem:
     """Workload ``index`` with its band set drawn as in ``make_config`` and
     orthonormalised on the device (for the 72^3 workload: 4,096 bands of
@@ -316,3 +391,26 @@ def pseudoband_recipe(e_c, n_protect: int, sizes, n_xi: int, seed: int):
     rng = np.random.default_rng(seed)
     theta = [rng.random((n_xi, len(s))) for s in slices]
     return keep, slices, theta
+
+
+def gpp_inputs(nb: int, ns: int, ng: int, ne: int, seed: int):
+    """Seeded inputs of the GPP off-diagonal self-energy: matrix elements
+    M[n][l][G] (complex Gaussian, variance 1/N_G per part, as for normalised
+    random states), band energies uniform in [-0.5, 1.5] Ha (sorted; occupied
+    below 0), an energy grid of ne points evenly over [-0.5, 1.0] Ha with a
+    0.01 Ha imaginary broadening, plasmon-pole parameters Omega2 (Hermitian,
+    N(0, 1/2) entries) and wtilde (symmetric, uniform in [0.3, 2.0] Ha), and a
+    positive Coulomb-like diagonal v uniform in [0.1, 2.0]."""
+    rng = np.random.default_rng(seed)
+    sd = (0.5 / max(ng, 1)) ** 0.5
+    m = sd * (rng.standard_normal((nb, ns, ng)) + 1j * rng.standard_normal((nb, ns, ng)))
+    e_n = np.sort(rng.uniform(-0.5, 1.5, nb))
+    occupied = (e_n < 0.0).astype(np.int32)
+    energies = np.linspace(-0.5, 1.0, ne) + 0.01j if ne > 1 else np.array([0.25 + 0.01j])
+    x = rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng))
+    omega2 = 0.5 * (x + x.conj().T)
+    wt = rng.uniform(0.3, 2.0, (ng, ng))
+    wtilde = 0.5 * (wt + wt.T)
+    v = rng.uniform(0.1, 2.0, ng)
+    return dict(m=m, e_n=e_n, occupied=occupied, energies=np.asarray(energies, np.complex128),
+                omega2=omega2, wtilde=wtilde, v=v)
