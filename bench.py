@@ -100,7 +100,8 @@ def main():
                     help="slice counts of the split-BF16 runs (default 3 4 5; empty: none)")
     ap.add_argument("--workload", default="chi0_72cube",
                     choices=["chi0_72cube", "chi0_48cube", "batched_40cube_64q",
-                             "adjoint_32cube", "pseudobands_48cube"],
+                             "adjoint_32cube", "pseudobands_48cube", "subspace_72cube",
+                             "epsinv_72cube", "gpp_offdiag"],
                     help="chi0_72cube: the contract line (default); the others print a "
                          "measurement line of their own")
     ap.add_argument("--pb-xi", type=int, default=4,
@@ -117,7 +118,8 @@ def main():
         return
     {"chi0_72cube": bench_chi0_72cube, "chi0_48cube": bench_chi0_48cube,
      "batched_40cube_64q": bench_batched, "adjoint_32cube": bench_adjoint,
-     "pseudobands_48cube": bench_pseudobands}[args.workload](args)
+     "pseudobands_48cube": bench_pseudobands, "subspace_72cube": bench_subspace,
+     "epsinv_72cube": bench_epsinv, "gpp_offdiag": bench_gpp}[args.workload](args)
 
 
 W2_BLOCK_NV = 16        # valence bands per step of the 72^3 workload (one NV block)
@@ -735,13 +737,21 @@ def bench_adjoint(args):
     gw.profile_enable(False)
     kernels = {k: gw.profile_read(k) for k in ADJOINT_KERNELS}
     gw.profile_reset()
-    # The adjoint's GEMMs P1 = M W and P2 = M W^H: 2 x 8 flops per (pair, G, G')
-    # per frequency, twice the forward contraction.
-    gemm_flops = 2.0 * 8.0 * npairs * ng * ng * nz
+    # The adjoint's GEMMs: g_M = s (conj(Delta) M W + Delta M W^H), two products
+    # of 8 flops per (pair, G, G'); where Delta is real (this static workload,
+    # and every imaginary or real frequency) one product M (W + W^H).
+    nprod = [1 if (complex(zz).real == 0.0 or complex(zz).imag == 0.0) else 2 for zz in p.z]
+    gemm_flops = 8.0 * npairs * ng * ng * sum(nprod)
     n_gm, t_gm = kernels["bwd_gm"]
-    gm_per_launch = gemm_flops / max(1, n_gm // steps)
+    launches_per_call = max(1, n_gm // steps)
+    gm_per_launch = gemm_flops / launches_per_call
     gm_avg_ms = t_gm / max(1, n_gm)
-    achieved = gm_per_launch / (gm_avg_ms * 1e-3) / 1e12
+    # executed on the MFMAs: 6 flops per complex multiply-add (three real
+    # products), on whole 32 x 64 tiles and 16-wide stages of G
+    kc = npairs * nz // launches_per_call
+    exec_per_launch = (6.0 * (-(-kc // 32) * 32) * (-(-ng // 64) * 64) * (-(-ng // 16) * 16) *
+                       sum(nprod) / nz)
+    achieved = exec_per_launch / (gm_avg_ms * 1e-3) / 1e12
     out = {
         "workload": "adjoint_32cube",
         "config": {"grid": list(p.n), "pairs": npairs, "n_g": ng, "n_freq": nz,
@@ -762,9 +772,13 @@ def bench_adjoint(args):
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
             "traffic": None,
+            "flops": "executed: 6 per complex multiply-add, whole tiles and stages; one "
+                     "product per launch where Delta is real",
             "launches": n_gm,
             "avg_launch_ms": round(gm_avg_ms, 4),
-            "flops_per_launch": gm_per_launch,
+            "flops_per_launch": exec_per_launch,
+            "algorithmic_flops_per_launch": gm_per_launch,
+            "algorithmic_tflops": round(gm_per_launch / (gm_avg_ms * 1e-3) / 1e12, 3),
         },
     }
     if not args.no_cpu_baseline:
@@ -888,6 +902,284 @@ def bench_pseudobands(args):
                                "cores": 1, "kind": "oracle",
                                "sample": "the whole compression (all slices), numpy",
                                "seconds": round(dt, 2), "gpu_max_rel_diff": dev_err}
+    gw.release()
+    print(json.dumps(out), flush=True)
+
+
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def _coulomb_q0(gvec):
+    """v_G = 4 pi / |G|^2 of the cubic cell at q = 0, the head (G = 0)
+    excluded (input preparation)."""
+    import numpy as np
+
+    from workloads import gen
+    k = np.asarray(gvec, np.float64) * (2.0 * np.pi / gen.CELL_L)
+    k2 = (k * k).sum(1)
+    return np.where(k2 > 0, 4.0 * np.pi / np.where(k2 > 0, k2, 1.0), 0.0)
+
+
+def bench_subspace(args):
+    """The static subspace (Fast Full-Frequency GW section, Eq. (6)) on the 72^3
+    workload's shape and frequencies (256 x 3,840 bands, 6,031 G, 8 imaginary
+    frequencies) with shell bands (free-electron-like momentum shells and
+    energies): chi0(0) in full plane waves, Diag of the symmetrised
+    v^1/2 chi0(0) v^1/2 (q = 0, head excluded), then chi_BB'(z) at 10 % and
+    20 % of N_G, against v^1/2 chi v^1/2 of the full plane-wave chi0 at the 8
+    frequencies."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    t_start = time.perf_counter()
+    dev = torch.device("cuda", 0)
+    w = gen.make_shell_config_device(2, width=1.0, device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ng, nz = w.ng, len(w.z)
+    ev_d = torch.from_numpy(w.e_v).to(dev)
+    ec_d = torch.from_numpy(w.e_c).to(dev)
+    _log(t_start, f"shell bands ready: {w.nv}x{w.nc}, {ng} G")
+
+    def prob(z, chi=None):
+        return gw.Chi0Problem(n=w.n, volume=w.volume, psi_v=w.psi_v, psi_c=w.psi_c, e_v=ev_d,
+                              e_c=ec_d, gvec=w.gvec, z=z, chi=chi)
+
+    pairs = w.nv * w.nc
+    gv = w.gvec.cpu().numpy() if hasattr(w.gvec, "cpu") else np.asarray(w.gvec)
+    wt = torch.from_numpy(np.sqrt(_coulomb_q0(gv))).to(dev)
+    full, t_full = _sync_time(lambda: gw.gw_chi0(prob(w.z), pair_chunk=w.pair_chunk))
+    _log(t_start, f"full plane-wave chi0 at {nz} frequencies: {t_full:.2f} s")
+    rows = torch.from_numpy(np.sort(np.random.default_rng(1002).choice(ng, 32, replace=False))).to(dev)
+    # the 32 rows of W chi(z) W
+    ref_rows = (wt[rows][None, :, None] * full[:, rows] * wt[None, None, :]).contiguous()
+    del full
+    torch.cuda.empty_cache()
+    stat, t_static = _sync_time(lambda: gw.gw_chi0(prob(np.zeros(1, np.complex128)),
+                                                  pair_chunk=w.pair_chunk))
+    _log(t_start, f"static chi0(0): {t_static:.2f} s")
+    chi_s = stat[0].contiguous()
+    del stat
+    runs = []
+    for frac in (0.1, 0.2):
+        n_eig = int(round(frac * ng))
+        (basis, evals, info), t_diag = _sync_time(
+            lambda: gw.gw_subspace_basis(chi_s, n_eig, weight=wt, tol=1e-8, seed=7))
+        chib, t_sub = _sync_time(lambda: gw.gw_chi0_subspace(prob(w.z), basis, weight=wt,
+                                                               pair_chunk=w.pair_chunk))
+        # W chi(z) W ~ C_s chi_B(z) C_s^H on the 32 rows
+        crow = basis[rows].contiguous()
+        t1 = gw.gw_zgemm("N", "N", crow[None].expand(nz, -1, -1).contiguous(), chib)
+        approx = gw.gw_zgemm("N", "C", t1, basis[None].expand(nz, -1, -1).contiguous())
+        err = [float(torch.linalg.vector_norm(approx[i] - ref_rows[i]) /
+                     torch.linalg.vector_norm(ref_rows[i])) for i in range(nz)]
+        # Diag against the projection of W chi0(0) W on the basis
+        wb = (wt[:, None] * basis).contiguous()
+        proj = gw.gw_zgemm("C", "N", wb, gw.gw_zgemm("N", "N", chi_s, wb))
+        off = float(torch.linalg.vector_norm(proj - torch.diag(evals.to(torch.complex128))) /
+                    torch.linalg.vector_norm(evals))
+        sub_flops = 8.0 * n_eig * n_eig * pairs * nz
+        transf_flops = 8.0 * pairs * ng * n_eig
+        runs.append({
+            "n_eig": n_eig, "fraction": frac,
+            "diag_s": round(t_diag, 3), "diag_info": info,
+            "diag_offdiagonal_rel": off,
+            "chi_freq_s": round(t_sub, 3),
+            "transf_plus_chi_freq_tflops": round((sub_flops + transf_flops) / t_sub / 1e12, 3),
+            "subspace_path_s": round(t_static + t_diag + t_sub, 3),
+            "speedup_vs_full_plane_waves": round(t_full / (t_static + t_diag + t_sub), 3),
+            "rel_err_32rows_per_freq": err,
+            "eigenvalue_range": [float(evals[0]), float(evals[-1])],
+        })
+        _log(t_start, f"n_eig {n_eig}: Diag {t_diag:.2f} s ({info['iterations']} iterations, "
+                      f"residual {info['residual']:.1e}), CHI-Freq {t_sub:.2f} s, "
+                      f"errors {min(err):.2e}..{max(err):.2e}")
+        del basis, chib, crow, t1, approx, proj, wb
+        torch.cuda.empty_cache()
+    out = {"workload": "subspace_72cube",
+           "config": {"grid": list(w.n), "pairs": pairs, "n_g": ng, "n_freq": nz,
+                      "bands": "shell bands (width 1.0), free-electron energies",
+                      "metric": "v^1/2 chi v^1/2, q = 0, head excluded"},
+           "data": "synthetic",
+           "full_plane_waves_s": round(t_full, 3),
+           "full_tflops": round(8.0 * ng * ng * pairs * nz / t_full / 1e12, 3),
+           "static_chi0_s": round(t_static, 3),
+           "runs": runs}
+    if not args.no_cpu_baseline:
+        # the oracle's Diag step (a library Hermitian eigensolver) on the same
+        # chi0(0), eigenvalues only, against the device's kept eigenvalues
+        import oracle
+        wh = wt.cpu().numpy()
+        cs = wh[:, None] * chi_s.cpu().numpy() * wh[None, :]
+        info = host_info()
+        t0 = time.perf_counter()
+        lam = np.linalg.eigvalsh(cs)
+        dt = time.perf_counter() - t0
+        _, want = oracle.static_subspace_basis(np.diag(lam), runs[-1]["n_eig"])
+        (bb, ev2, _), _ = _sync_time(lambda: gw.gw_subspace_basis(chi_s, runs[-1]["n_eig"],
+                                                                   weight=wt, tol=1e-8, seed=7))
+        got = ev2.cpu().numpy()
+        out["cpu_baseline"] = {
+            "value": round(dt, 2), "unit": "s", "cores": int(info["blas_threads"] or 1),
+            "kind": "oracle",
+            "sample": f"all eigenvalues of the {ng} x {ng} v^1/2 chi0(0) v^1/2 (numpy eigvalsh)",
+            "cpu_model": info["cpu_model"], "blas": info["blas"],
+            "gpu_eigenvalue_max_rel_err": float(np.abs(got - want).max() / np.abs(want).max())}
+    gw.release()
+    print(json.dumps(out), flush=True)
+
+
+def bench_epsinv(args):
+    """The inverse dielectric matrix of Eq. (3) for the 72^3 workload's full
+    plane-wave chi0 (6,031 G, 8 imaginary frequencies, seeded recipe bands),
+    v_G = 4 pi / |G|^2 with the q = 0 head excluded: block Gauss-Jordan on
+    FP64 MFMA GEMMs, 8 N_G^3 flops per frequency."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    t_start = time.perf_counter()
+    dev = torch.device("cuda", 0)
+    w = gen.make_config_device(2, device=dev)
+    ng, nz = w.ng, len(w.z)
+    prob = gw.Chi0Problem(n=w.n, volume=w.volume, psi_v=w.psi_v, psi_c=w.psi_c,
+                          e_v=torch.from_numpy(w.e_v).to(dev), e_c=torch.from_numpy(w.e_c).to(dev),
+                          gvec=w.gvec, z=w.z)
+    chi, t_chi = _sync_time(lambda: gw.gw_chi0(prob, pair_chunk=w.pair_chunk))
+    _log(t_start, f"chi0 built in {t_chi:.2f} s")
+    del w, prob
+    torch.cuda.empty_cache()
+    vd = torch.from_numpy(_coulomb_q0(gen.gsphere(gen.CONFIG_SHAPES[2]["r2"]))).to(dev)
+    out_t = torch.empty_like(chi)
+    gw.gw_epsinv(chi, vd, out=out_t)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    gw.profile_reset()
+    gw.profile_enable(True)
+    _, dt = _sync_time(lambda: [gw.gw_epsinv(chi, vd, out=out_t) for _ in range(steps)])
+    gw.profile_enable(False)
+    n_inv, t_inv = gw.profile_read("eps_invert")
+    n_zg, t_zg = gw.profile_read("zgemm")
+    gw.profile_reset()
+    dt /= steps
+    flops = 8.0 * ng ** 3 * nz
+    # eps eps^-1 = I, on the device
+    eps = torch.eye(ng, dtype=torch.complex128, device=dev)[None] - vd[None, :, None] * chi
+    prod = gw.gw_zgemm("N", "N", eps, out_t)
+    resid = float((prod - torch.eye(ng, dtype=torch.complex128, device=dev)[None]).abs().max())
+    del eps, prod
+    out = {"workload": "epsinv_72cube",
+           "config": {"n_g": ng, "n_freq": nz, "method": "block Gauss-Jordan, 64 columns per step"},
+           "data": "synthetic", "chi0_build_s": round(t_chi, 3),
+           "s_per_call": round(dt, 4), "tflops": round(flops / dt / 1e12, 3),
+           "flops_per_call": flops, "residual_max_abs_eps_epsinv_minus_I": resid,
+           "roofline": {"kernel": "block Gauss-Jordan (zgemm updates)", "bound": "mfma",
+                        "achieved": round(flops / dt / 1e12, 3), "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(flops / dt / 1e12 / FP64_PEAK_TFLOPS, 4),
+                        "traffic": None, "flops": "8 N_G^3 per frequency (algorithmic)",
+                        "launches_zgemm": n_zg, "invert_ms_per_call": round(t_inv / max(1, n_inv), 3)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        info = host_info()
+        c0 = chi[:1].cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.epsilon_inverse(c0, v)
+        tc = time.perf_counter() - t0
+        got = out_t[0].cpu().numpy()
+        out["cpu_baseline"] = {
+            "value": round(8.0 * ng ** 3 / tc / 1e12, 5), "unit": "TFLOP/s",
+            "cores": int(info["blas_threads"] or 1), "kind": "oracle",
+            "sample": "frequency 0 of 8 (numpy inverse of the 6,031 x 6,031 eps)",
+            "seconds": round(tc, 2), "cpu_model": info["cpu_model"], "blas": info["blas"],
+            "gpu_rel_err_on_sample": float(np.linalg.norm(got - ref[0]) / np.linalg.norm(ref[0]))}
+    gw.release()
+    print(json.dumps(out), flush=True)
+
+
+GPP_SHAPE = dict(nb=512, ns=128, ng=2007, ne=32)
+
+
+def bench_gpp(args):
+    """The GPP off-diagonal self-energy kernel: Sigma_lm(E) for N_Sigma = 128
+    states on 32 energies, 512 bands, 2,007 G (the 48^3 sphere): per (band,
+    energy) one GEMM of 128 x 2,007 x 2,007 with the plasmon-pole matrix formed
+    inside it and one of 128 x 2,007 x 128.  Flops as the paper counts them
+    (Eq. (8), ZGEMM only): 8 (N_Sigma N_G^2 + N_G N_Sigma^2) per (band,
+    energy), with the paper's leading factor 2 reported beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2509_23018_amd as gw
+    from workloads import gen
+
+    sh = GPP_SHAPE
+    dev = torch.device("cuda", 0)
+    inp = gen.gpp_inputs(sh["nb"], sh["ns"], sh["ng"], sh["ne"], seed=1006)
+    d = {k: torch.from_numpy(np.ascontiguousarray(inp[k])).to(dev)
+         for k in ("m", "omega2", "wtilde", "v")}
+
+    def call():
+        return gw.gw_gpp_sigma(d["m"], inp["e_n"], inp["occupied"], inp["energies"], d["omega2"],
+                               d["wtilde"], d["v"])
+
+    sig = call()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 5))
+    gw.profile_reset()
+    gw.profile_enable(True)
+    _, dt = _sync_time(lambda: [call() for _ in range(steps)])
+    gw.profile_enable(False)
+    n_t, t_t = gw.profile_read("gpp_t")
+    gw.profile_reset()
+    dt /= steps
+    nb, ns, ng, ne = sh["nb"], sh["ns"], sh["ng"], sh["ne"]
+    canon = nb * ne * 8.0 * (ns * ng * ng + ng * ns * ns)
+    # gpp_t executes 6 flops per complex multiply-add on whole 64 x 64 tiles and
+    # 16-wide stages of G
+    tiles = -(-ns // 64) * -(-ng // 64)
+    exec_t = 6.0 * tiles * 64 * 64 * (-(-ng // 16) * 16) * ne      # per launch (one band)
+    t_avg = t_t / max(1, n_t)
+    out = {"workload": "gpp_offdiag", "config": dict(sh), "data": "synthetic",
+           "s_per_call": round(dt, 4),
+           "tflops": round(canon / dt / 1e12, 3),
+           "paper_eq8_tflops": round(2.0 * canon / dt / 1e12, 3),
+           "canonical_flops_per_call": canon,
+           "roofline": {"kernel": "gpp_t_kernel", "bound": "mfma",
+                        "achieved": round(exec_t / (t_avg * 1e-3) / 1e12, 3),
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(exec_t / (t_avg * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                        "traffic": None,
+                        "flops": "executed: 6 per complex multiply-add, whole tiles and stages",
+                        "launches": n_t, "avg_launch_ms": round(t_avg, 4),
+                        "flops_per_launch": exec_t}}
+    if not args.no_cpu_baseline:
+        import oracle
+        info = host_info()
+        sb, se = 8, 2
+        t0 = time.perf_counter()
+        ref = oracle.gpp_sigma_offdiag(inp["m"][:sb], inp["e_n"][:sb], inp["occupied"][:sb],
+                                       inp["energies"][:se], inp["omega2"], inp["wtilde"], inp["v"])
+        tc = time.perf_counter() - t0
+        sub = gw.gw_gpp_sigma(d["m"][:sb].contiguous(), inp["e_n"][:sb], inp["occupied"][:sb],
+                              inp["energies"][:se], d["omega2"], d["wtilde"], d["v"]).cpu().numpy()
+        cflops = sb * se * 8.0 * (ns * ng * ng + ng * ns * ns)
+        out["cpu_baseline"] = {
+            "value": round(cflops / tc / 1e12, 5), "unit": "TFLOP/s",
+            "cores": int(info["blas_threads"] or 1), "kind": "oracle",
+            "sample": f"{sb} of {nb} bands x {se} of {ne} energies",
+            "seconds": round(tc, 2), "cpu_model": info["cpu_model"], "blas": info["blas"],
+            "gpu_rel_err_on_sample": float(np.linalg.norm(sub - ref) / np.linalg.norm(ref))}
     gw.release()
     print(json.dumps(out), flush=True)
 

@@ -310,6 +310,11 @@ size_t gw_chi0_fixed_scratch_bytes(void);
  * built: M^B_vc = sum_G M^G_vc C_s^{GB} and
  *     chi_BB'(z) = s * sum_vc conj(M^B_vc) Delta_vc(z) M^B'_vc,
  * which equals C_s^H chi(z) C_s.
+ * The paper does not say in which metric chi(0) is diagonalised.  Both are
+ * offered: chi itself, or, given a weight w (w_G = sqrt(v_G), v the Coulomb
+ * diagonal of Eq. (3)), the symmetrised W chi W, W = diag(w), whose spectrum
+ * falls off with |q + G| as the Coulomb factor does; then
+ * M^B_vc = sum_G M^G_vc w_G C_s^{GB} and chi_BB'(z) = C_s^H W chi(z) W C_s.
  */
 typedef struct {
     double   tol;         /* residual |chi x - lambda x| / b of every kept pair, b a bound of
@@ -318,6 +323,8 @@ typedef struct {
     int32_t  guard;       /* block columns beyond n_eig; 0 = max(16, n_eig / 8) */
     int32_t  max_degree;  /* Chebyshev filter degree cap; 0 = 16 */
     uint64_t seed;        /* start block (a counter-based hash of seed and index) */
+    const double* weight; /* device [ng] or NULL: diagonalise diag(w) chi diag(w) instead of
+                             chi (w_G = sqrt(v_G): the symmetrised v^1/2 chi v^1/2) */
     void*    workspace;   /* device scratch owned by the caller (256-byte aligned) or NULL */
     size_t   workspace_bytes;
 } gw_diag_opts_t;
@@ -357,15 +364,17 @@ size_t gw_subspace_basis_workspace_bytes(int32_t ng, int32_t n_eig, const gw_dia
 /*
  * gw_chi0_subspace -- Transf and CHI-Freq: chi_BB'(z) of Eq. (6) for one
  * problem, M streamed in chunks as in gw_chi0, each chunk transformed to the
- * subspace (M^B = M C_s, FP64 MFMA GEMM) before the contraction over n_eig
+ * subspace (M^B = M W C_s, FP64 MFMA GEMM) before the contraction over n_eig
  * columns.  prob->chi is device OUT [nz][n_eig][n_eig]; basis is device
- * [ng][n_eig] (for instance from gw_subspace_basis).  The options, flags
- * (except GW_FLAG_GRAPH, GW_EUNSUPPORTED), precisions and workspace rules are
- * those of gw_chi0; the workspace size is
+ * [ng][n_eig] (for instance from gw_subspace_basis); weight is device [ng]
+ * (W = diag(weight), the weight the basis was found with) or NULL (W = I).
+ * The options, flags (except GW_FLAG_GRAPH, GW_EUNSUPPORTED), precisions and
+ * workspace rules are those of gw_chi0; the workspace size is
  * gw_chi0_subspace_workspace_bytes().
  */
-gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis, int32_t n_eig,
-                             const gw_opts_t* opts, void* stream);
+gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis,
+                             const double* weight, int32_t n_eig, const gw_opts_t* opts,
+                             void* stream);
 size_t gw_chi0_subspace_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
                                         const gw_opts_t* opts);
 

@@ -229,43 +229,53 @@ def pseudobands(psi, e, keep, slices, n_xi, theta):
     return out, np.array(ens, dtype=np.float64)
 
 
-def static_subspace_basis(chi_static, n_eig):
+def static_subspace_basis(chi_static, n_eig, weight=None):
     """Diag of the static subspace method (Fast Full-Frequency GW section): the
     static polarizability is diagonalised and its ``n_eig`` most significant
     eigenvectors, read as those of largest |eigenvalue|, become the columns of
     C_s.  Returns ``(C_s [N_G, n_eig], eigenvalues [n_eig])`` in decreasing
     |eigenvalue| (for the negative semidefinite chi0(0): most negative first).
+    With ``weight`` w (w_G = sqrt(v_G), v the Coulomb diagonal of Eq. (3)) the
+    matrix diagonalised is the symmetrised W chi W, W = diag(w); the paper
+    does not name the metric, and both readings are offered.
     A library Hermitian eigensolver is the step.
 
     Parity: pinned by a matrix built from a known spectrum, by plane waves
-    (diagonal chi, unit-vector basis) and by the diagonal static chi in the
-    subspace."""
-    lam, vec = np.linalg.eigh(np.asarray(chi_static, np.complex128))
+    (diagonal chi, unit-vector basis), by the diagonal static chi in the
+    subspace, and for the weight by a diagonal chi (eigenvalues w_G^2 chi_GG)
+    and the trace of W chi W."""
+    chi_static = np.asarray(chi_static, np.complex128)
+    if weight is not None:
+        w = np.asarray(weight, np.float64)
+        chi_static = w[:, None] * chi_static * w[None, :]
+    lam, vec = np.linalg.eigh(chi_static)
     order = np.argsort(-np.abs(lam), kind="stable")[:int(n_eig)]
     return vec[:, order], lam[order]
 
 
 def chi0_subspace(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, basis, spin=2.0,
-                  pair_chunk=4096) -> np.ndarray:
+                  pair_chunk=4096, weight=None) -> np.ndarray:
     """Eq. (6): chi_BB'(z) = s * sum_vc conj(M^B_vc) Delta_vc(z) M^B'_vc, with
     the subspace matrix elements M^B_vc = sum_G M^G_vc C_s^{GB} (the transform
     the paper states after Eq. (6)), summed over chunks of pairs.  ``basis`` is
-    C_s, ``[N_G, n_eig]``.  Returns ``[N_z, n_eig, n_eig]``.
+    C_s, ``[N_G, n_eig]``.  With ``weight`` w the basis is that of W chi W, and
+    M^B_vc = sum_G M^G_vc w_G C_s^{GB}.  Returns ``[N_z, n_eig, n_eig]``.
 
-    Parity: pinned by the full basis (C_s chi_B C_s^H = chi of Eq. (4)), by
-    the paper's identity chi_BB' = C_s^H chi C_s on a partial basis, and by
-    plane waves."""
+    Parity: pinned by the full basis (C_s chi_B C_s^H = chi of Eq. (4), and
+    W chi W with a weight), by the paper's identity chi_BB' = C_s^H chi C_s on a
+    partial basis, and by plane waves."""
     nv, nc = psi_v.shape[0], psi_c.shape[0]
     z = np.asarray(z, np.complex128).reshape(-1)
     basis = np.asarray(basis, np.complex128)
     nb = basis.shape[1]
+    wcol = np.ones(basis.shape[0]) if weight is None else np.asarray(weight, np.float64)
     delta = energy_factor(e_v, e_c, z)
     chi = np.zeros((z.size, nb, nb), dtype=np.complex128)
     npairs = nv * nc
     step = max(1, int(pair_chunk))
     for k0 in range(0, npairs, step):
         k1 = min(npairs, k0 + step)
-        mb = mtxel(psi_v, psi_c, gvec, n, volume, pairs=range(k0, k1)) @ basis
+        mb = (mtxel(psi_v, psi_c, gvec, n, volume, pairs=range(k0, k1)) * wcol[None, :]) @ basis
         for w in range(z.size):
             chi[w] += spin * ((np.conj(mb).T * delta[w, k0:k1][None, :]) @ mb)
     return chi

@@ -85,8 +85,8 @@ class _C128(ctypes.Structure):
 class _DiagOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("guard", ctypes.c_int32), ("max_degree", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("seed", ctypes.c_uint64), ("weight", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class _DiagInfo(ctypes.Structure):
@@ -138,8 +138,8 @@ def lib() -> ctypes.CDLL:
         L.gw_subspace_basis_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32,
                                                         ctypes.POINTER(_DiagOpts)]
         L.gw_chi0_subspace.restype = ctypes.c_int32
-        L.gw_chi0_subspace.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_int32,
-                                       ctypes.POINTER(_Opts), ctypes.c_void_p]
+        L.gw_chi0_subspace.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.POINTER(_Opts), ctypes.c_void_p]
         L.gw_chi0_subspace_workspace_bytes.restype = ctypes.c_size_t
         L.gw_chi0_subspace_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32,
                                                        ctypes.POINTER(_Opts)]
@@ -422,30 +422,43 @@ def gw_chi0_backward(problem: Chi0Problem, grad_chi: torch.Tensor, *, pair_chunk
     return tuple(outs)
 
 
-def _diag_opts(tol=0.0, max_iter=0, guard=0, max_degree=0, seed=0, workspace=None):
+def _weight(weight, ng, device):
+    if weight is None:
+        return None
+    _dev(weight, "weight", torch.float64)
+    if tuple(weight.shape) != (ng,) or weight.device != device:
+        raise ValueError(f"weight must be a float64 vector of {ng} on {device}")
+    return weight.data_ptr()
+
+
+def _diag_opts(tol=0.0, max_iter=0, guard=0, max_degree=0, seed=0, workspace=None, weight=None):
     o = _DiagOpts()
     o.tol, o.max_iter, o.guard, o.max_degree = float(tol), int(max_iter), int(guard), int(max_degree)
     o.seed = int(seed)
+    o.weight = weight
     o.workspace, o.workspace_bytes = _workspace(workspace)
     return o
 
 
-def subspace_basis_workspace_bytes(ng: int, n_eig: int, guard: int = 0) -> int:
-    o = _diag_opts(guard=guard)
+def subspace_basis_workspace_bytes(ng: int, n_eig: int, guard: int = 0,
+                                   weighted: bool = False) -> int:
+    o = _diag_opts(guard=guard, weight=1 if weighted else None)  # only tested for NULL
     return int(lib().gw_subspace_basis_workspace_bytes(int(ng), int(n_eig), ctypes.byref(o)))
 
 
-def gw_subspace_basis(chi_static: torch.Tensor, n_eig: int, *, tol=0.0, max_iter=0, guard=0,
-                      max_degree=0, seed=0, workspace=None, stream=None):
+def gw_subspace_basis(chi_static: torch.Tensor, n_eig: int, *, weight=None, tol=0.0, max_iter=0,
+                      guard=0, max_degree=0, seed=0, workspace=None, stream=None):
     """Diag: (basis [ng, n_eig], eigenvalues [n_eig], info) of the Hermitian,
-    negative semidefinite static polarizability chi_static [ng, ng]."""
+    negative semidefinite static polarizability chi_static [ng, ng], or of
+    W chi W with W = diag(weight) (weight: float64 device vector [ng])."""
     _dev(chi_static, "chi_static", torch.complex128)
     ng = chi_static.shape[0]
     if tuple(chi_static.shape) != (ng, ng):
         raise ValueError("chi_static must be square")
     basis = torch.empty((ng, int(n_eig)), dtype=torch.complex128, device=chi_static.device)
     ev = torch.empty(int(n_eig), dtype=torch.float64, device=chi_static.device)
-    o = _diag_opts(tol, max_iter, guard, max_degree, seed, workspace)
+    o = _diag_opts(tol, max_iter, guard, max_degree, seed, workspace,
+                   _weight(weight, ng, chi_static.device))
     info = _DiagInfo()
     with torch.cuda.device(chi_static.device):
         _check(lib().gw_subspace_basis(chi_static.data_ptr(), ng, int(n_eig), basis.data_ptr(),
@@ -468,11 +481,13 @@ def chi0_subspace_workspace_bytes(problem, n_eig: int, *, precision="fp64", n_sl
     return int(n)
 
 
-def gw_chi0_subspace(problem, basis: torch.Tensor, *, precision="fp64", n_slices=0,
+def gw_chi0_subspace(problem, basis: torch.Tensor, *, weight=None, precision="fp64", n_slices=0,
                      pair_chunk=4096, flags=0, spin=2.0, out=None, workspace=None, stream=None):
     """Transf + CHI-Freq (Eq. (6)): chi_BB'(z) [nz, n_eig, n_eig] of one problem
-    in the subspace spanned by the columns of basis [ng, n_eig]."""
+    in the subspace spanned by the columns of basis [ng, n_eig]; with weight
+    [ng], C^H W chi W C."""
     _dev(basis, "basis", torch.complex128)
+    wp = _weight(weight, basis.shape[0], basis.device)
     n_eig = basis.shape[1]
     nz = _host_c128(problem.z).shape[0]
     if out is None:
@@ -486,7 +501,7 @@ def gw_chi0_subspace(problem, basis: torch.Tensor, *, precision="fp64", n_slices
     arr.chi = out.data_ptr()
     o = _opts(precision, n_slices, pair_chunk, flags, spin, workspace)
     with torch.cuda.device(basis.device):
-        _check(lib().gw_chi0_subspace(ctypes.byref(arr), basis.data_ptr(), int(n_eig),
+        _check(lib().gw_chi0_subspace(ctypes.byref(arr), basis.data_ptr(), wp, int(n_eig),
                                       ctypes.byref(o), _stream(basis.device, stream)))
     return out
 

@@ -49,7 +49,13 @@ __global__ __launch_bounds__(256) void ddelta_kernel(const double* __restrict__ 
 // p1 = ar br, p2 = ai bi, p3 = (ar + ai)(br + bi); Re = p1 - p2,
 // Im = p3 - p1 - p2); the third accumulator set leaves registers for two
 // workgroups per CU.
-template <int TM>
+// SYM (Delta real, as on the imaginary and real axes): g_M = s Delta (P1 + P2)
+// = s Delta M (W + W^H); w then holds W + W^H (formed by sym_kernel) and one
+// product is formed instead of two, with one operand tile per stage; and
+// sum_i conj(M_i) (P1 + P2)_i = conj(q) + q = 2 Re q, so half of it is stored
+// as q (its real part is all that the energy gradient reads when Delta, and
+// so dDelta/dE, is real).
+template <int TM, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void bwd_gm_kernel(const double2* __restrict__ m, int64_t kc,
                                                      int ng, const double2* __restrict__ w,
                                                      const double2* __restrict__ delta,
@@ -100,8 +106,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
                                 std::min(j0 + (e & 15), glast);
             rb1[u].x = s1->x;
             rb1[u].y = s1->y;
-            rb2[u].x = s2->x;
-            rb2[u].y = s2->y;
+            if (!SYM) {
+                rb2[u].x = s2->x;
+                rb2[u].y = s2->y;
+            }
         }
     };
     const double2 zero = make_double2(0.0, 0.0);
@@ -120,7 +128,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
             const bool ok1 = j0 + (e >> 6) < ng && i0 + (e & 63) < ng;
             const bool ok2 = i0 + (e >> 4) < ng && j0 + (e & 15) < ng;
             s_b1[e >> 6][e & 63] = ok1 ? make_double2(rb1[u].x, rb1[u].y) : zero;
-            s_b2[e & 15][e >> 4] = ok2 ? make_double2(rb2[u].x, -rb2[u].y) : zero;
+            if (!SYM) s_b2[e & 15][e >> 4] = ok2 ? make_double2(rb2[u].x, -rb2[u].y) : zero;
         }
         __syncthreads();
         // issue priority 1 for the loads, 2 over the MFMAs, 0 for the stores
@@ -137,7 +145,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
                 b1[y] = s_b1[s * 4 + kq][wj * 32 + y * 16 + row];
-                b2[y] = s_b2[s * 4 + kq][wj * 32 + y * 16 + row];
+                if (!SYM) b2[y] = s_b2[s * 4 + kq][wj * 32 + y * 16 + row];
             }
             double as[BX], bs1[2], bs2[2];
 #pragma unroll
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
                 bs1[y] = b1[y].x + b1[y].y;
-                bs2[y] = b2[y].x + b2[y].y;
+                if (!SYM) bs2[y] = b2[y].x + b2[y].y;
             }
 #pragma unroll
             for (int x = 0; x < BX; ++x)
@@ -154,9 +162,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
                     p1r[x][y] = mfma_f64(a[x].x, b1[y].x, p1r[x][y]);
                     p1i[x][y] = mfma_f64(a[x].y, b1[y].y, p1i[x][y]);
                     p1s[x][y] = mfma_f64(as[x], bs1[y], p1s[x][y]);
-                    p2r[x][y] = mfma_f64(a[x].x, b2[y].x, p2r[x][y]);
-                    p2i[x][y] = mfma_f64(a[x].y, b2[y].y, p2i[x][y]);
-                    p2s[x][y] = mfma_f64(as[x], bs2[y], p2s[x][y]);
+                    if (!SYM) {
+                        p2r[x][y] = mfma_f64(a[x].x, b2[y].x, p2r[x][y]);
+                        p2i[x][y] = mfma_f64(a[x].y, b2[y].y, p2i[x][y]);
+                        p2s[x][y] = mfma_f64(as[x], bs2[y], p2s[x][y]);
+                    }
                 }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -177,12 +187,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
                 if (rok && c < ng) {
                     const double2 a = make_double2(p1r[x][y][t] - p1i[x][y][t],
                                                    p1s[x][y][t] - p1r[x][y][t] - p1i[x][y][t]);
-                    const double2 b = make_double2(p2r[x][y][t] - p2i[x][y][t],
-                                                   p2s[x][y][t] - p2r[x][y][t] - p2i[x][y][t]);
-                    double2 g = cmul_conj_a(d, a);
-                    const double2 h = cmul(d, b);
-                    g.x += h.x;
-                    g.y += h.y;
+                    double2 g, b;
+                    if (SYM) {  // a = M (W + W^H), Delta real
+                        g = make_double2(d.x * a.x, d.x * a.y);
+                        b = make_double2(0.5 * a.x, 0.5 * a.y);
+                    } else {
+                        b = make_double2(p2r[x][y][t] - p2i[x][y][t],
+                                         p2s[x][y][t] - p2r[x][y][t] - p2i[x][y][t]);
+                        g = cmul_conj_a(d, a);
+                        const double2 h = cmul(d, b);
+                        g.x += h.x;
+                        g.y += h.y;
+                    }
                     double2* dst = gm + r * ng + c;
                     if (mode) {
                         const double2 o = *dst;
@@ -203,6 +219,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
             }
             if (row == 0 && rok)
                 qpart[static_cast<int64_t>(blockIdx.x * 2 + wj) * kc + r] = make_double2(qre, qim);
+        }
+}
+
+// out = W + W^H for an [n][n] matrix, 32 x 32 tiles: the transposed tile
+// goes through LDS so that both reads are row-contiguous.
+__global__ __launch_bounds__(256) void sym_kernel(const double2* __restrict__ w, int n,
+                                                  double2* __restrict__ out) {
+    __shared__ double2 t[32][33];
+    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8)  // tile (j0.., i0..), transposed into t
+        if (j0 + r < n && i0 + tx < n) t[tx][r] = w[static_cast<int64_t>(j0 + r) * n + i0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8)
+        if (i0 + r < n && j0 + tx < n) {
+            const int64_t o = static_cast<int64_t>(i0 + r) * n + j0 + tx;
+            const double2 a = w[o], b = t[r][tx];
+            out[o] = make_double2(a.x + b.x, a.y - b.y);
         }
 }
 
@@ -481,6 +515,13 @@ struct Carve {
 
 constexpr int kYMax = 65535;  // gridDim.y limit
 
+// Delta of frequency w is real: on the imaginary axis (and at z = 0), where
+// delta_kernel sets its imaginary part to zero, and on the real axis.
+bool real_delta(const gw_problem_t& p, int w) {
+    const double2 z = reinterpret_cast<const double2*>(p.z)[w];
+    return z.x == 0.0 || z.y == 0.0;
+}
+
 // Chunking and scratch layout of one adjoint call.
 struct BwdLayout {
     int vb = 1, cwmax = 1;
@@ -488,6 +529,7 @@ struct BwdLayout {
     int nparts = 0;
     bool fuse = false;
     size_t o_m = 0, o_t2 = 0, o_d = 0, o_dd = 0, o_gm = 0, o_q = 0, o_de = 0, o_rho = 0, o_vp = 0;
+    size_t o_ws = 0;  // W + W^H of one frequency (frequencies with a real Delta)
     size_t total = 0;
 };
 
@@ -512,6 +554,9 @@ BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi
     L.o_d = cv.take(kmax * nz * sizeof(double2));
     L.o_dd = cv.take(kmax * nz * sizeof(double2));
     L.o_gm = cv.take(kmax * ng * sizeof(double2));
+    bool any_sym = false;
+    for (int w = 0; w < nz; ++w) any_sym = any_sym || real_delta(p, w);
+    L.o_ws = cv.take(any_sym ? static_cast<size_t>(ng) * ng * sizeof(double2) : 0);
     L.o_q = cv.take(kmax * nz * L.nparts * sizeof(double2));
     L.o_de = cv.take(kmax * sizeof(double));
     L.o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
@@ -565,6 +610,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     double* de = reinterpret_cast<double*>(base + o_de);
     double2* grho = reinterpret_cast<double2*>(base + o_rho);
     double2* vpart = grad_psi_v && fuse ? reinterpret_cast<double2*>(base + o_vp) : nullptr;
+    double2* wsym = reinterpret_cast<double2*>(base + L.o_ws);
     const double2* z = reinterpret_cast<const double2*>(p.z);
     const double2* psi_v = reinterpret_cast<const double2*>(p.psi_v);
     const double2* psi_c = reinterpret_cast<const double2*>(p.psi_c);
@@ -591,10 +637,18 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             }
             for (int w = 0; w < nz; ++w) {
                 ProfScope ps("bwd_gm", s);
-                hipLaunchKernelGGL(bwd_gm_kernel<32>,
+                // Delta real: one product against W + W^H
+                const bool sym = real_delta(p, w);
+                const double2* wop = grad_chi + static_cast<int64_t>(w) * ng * ng;
+                if (sym) {
+                    hipLaunchKernelGGL(sym_kernel, dim3(ceil_div(ng, 32), ceil_div(ng, 32)),
+                                       dim3(256), 0, s, wop, ng, wsym);
+                    wop = wsym;
+                }
+                auto gmk = sym ? bwd_gm_kernel<32, true> : bwd_gm_kernel<32, false>;
+                hipLaunchKernelGGL(gmk,
                                    dim3(ceil_div(ng, 64), static_cast<unsigned>(ceil_div64(kc, 32))),
-                                   dim3(256), 0, s, mbuf, kc, ng,
-                                   grad_chi + static_cast<int64_t>(w) * ng * ng, dbuf + w * kc, gm,
+                                   dim3(256), 0, s, mbuf, kc, ng, wop, dbuf + w * kc, gm,
                                    qpart + static_cast<int64_t>(w) * nparts * kc, w > 0 ? 1 : 0);
                 GW_HIP_TRY(hipGetLastError());
             }

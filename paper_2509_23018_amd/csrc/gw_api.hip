@@ -458,6 +458,7 @@ struct Chi0Layout {
     int ncols = 0;  // columns of the contracted operand (N_G, or n_eig)
     size_t off_m[2] = {0, 0}, off_d[2] = {0, 0};
     size_t off_mfull = 0;  // M on the G-sphere before the transform (subspace only)
+    size_t off_wbasis = 0; // W C_s, the weighted basis (subspace only)
     size_t off_t2 = 0, off_sp = 0, off_tune = 0, off_tail = 0;
     size_t total = 0;
 };
@@ -482,6 +483,7 @@ Chi0Layout chi0_layout(const gw_problem_t& pr, const Opts& o, const MtxelPlan& p
         L.off_d[1] = L.off_d[0];
     }
     L.off_mfull = cv.take(n_eig > 0 ? L.kmax * pr.ng * sizeof(double2) : 0);
+    L.off_wbasis = cv.take(n_eig > 0 ? static_cast<size_t>(pr.ng) * n_eig * sizeof(double2) : 0);
     L.off_t2 = cv.take(t2_elems(plan, L.kmax) * sizeof(double2));
     const bool split = o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16;
     L.off_sp = cv.take(split ? split_scratch_bytes(L.kmax, L.ncols, pr.nz, o.n_slices) : 0);
@@ -497,9 +499,10 @@ Chi0Layout chi0_layout(const gw_problem_t& pr, const Opts& o, const MtxelPlan& p
 // One problem: MTXEL (+ the subspace transform) + Delta + CHI0 per chunk, then
 // the Hermitian mirror.  base holds L.total bytes (L from chi0_layout with the
 // same arguments); with basis (device [N_G][n_eig], L.ncols = n_eig) chi is
-// [nz][n_eig][n_eig].
+// [nz][n_eig][n_eig], and with weight (device [N_G]) the basis is W C_s.
 void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
-              const Chi0Layout& L, const double2* basis = nullptr) {
+              const Chi0Layout& L, const double2* basis = nullptr,
+              const double* weight = nullptr) {
     const PlanRef plan_ref = get_plan(pr.grid.n, pr.gvec, pr.ng);
     const MtxelPlan& plan = *plan_ref;
     const int64_t ng = L.ncols;  // the contraction's width
@@ -511,6 +514,11 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
         return;
     }
     const bool two_streams = L.nbuf == 2;
+    if (basis && weight) {
+        double2* wb = reinterpret_cast<double2*>(base + L.off_wbasis);
+        launch_scale_rows(basis, wb, weight, pr.ng, L.ncols, s);
+        basis = wb;
+    }
     double2* mbuf[2] = {reinterpret_cast<double2*>(base + L.off_m[0]),
                         reinterpret_cast<double2*>(base + L.off_m[1])};
     double2* dbuf[2] = {reinterpret_cast<double2*>(base + L.off_d[0]),
@@ -1530,7 +1538,7 @@ gw_status_t gw_chi0_fixed(const gw_problem_t* prob, const gw_opts_t* opts, void*
 
 size_t gw_subspace_basis_workspace_bytes(int32_t ng, int32_t n_eig, const gw_diag_opts_t* opts) {
     if (ng < 1 || n_eig < 1 || n_eig > ng) return static_cast<size_t>(-1);
-    return subspace_basis_bytes(ng, n_eig, opts ? opts->guard : 0);
+    return subspace_basis_bytes(ng, n_eig, opts ? opts->guard : 0, opts && opts->weight);
 }
 
 gw_status_t gw_subspace_basis(const gw_c128* chi_static, int32_t ng, int32_t n_eig,
@@ -1552,13 +1560,14 @@ gw_status_t gw_subspace_basis(const gw_c128* chi_static, int32_t ng, int32_t n_e
             if (opts->max_degree > 0) prm.max_degree = opts->max_degree;
             prm.guard = opts->guard;
             prm.seed = opts->seed;
+            prm.weight = opts->weight;
             o.ws = static_cast<char*>(opts->workspace);
             o.ws_bytes = opts->workspace ? opts->workspace_bytes : 0;
             if (o.ws && (reinterpret_cast<uintptr_t>(o.ws) & 255))
                 fail(GW_EINVAL, "workspace must be 256-byte aligned");
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
-        char* base = call_scratch(subspace_basis_bytes(ng, n_eig, prm.guard), o, s);
+        char* base = call_scratch(subspace_basis_bytes(ng, n_eig, prm.guard, prm.weight), o, s);
         const DiagResult r = run_subspace_basis(reinterpret_cast<const double2*>(chi_static), ng,
                                                 n_eig, reinterpret_cast<double2*>(basis),
                                                 eigenvalues, prm, base, s);
@@ -1588,8 +1597,9 @@ size_t gw_chi0_subspace_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
     return st == GW_OK ? out : static_cast<size_t>(-1);
 }
 
-gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis, int32_t n_eig,
-                             const gw_opts_t* opts, void* stream) {
+gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis,
+                             const double* weight, int32_t n_eig, const gw_opts_t* opts,
+                             void* stream) {
     return guarded([&] {
         sweep_retired();
         if (!prob) fail(GW_EINVAL, "prob is NULL");
@@ -1604,7 +1614,7 @@ gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis, int
         const PlanRef plan = get_plan(prob->grid.n, prob->gvec, prob->ng);
         const Chi0Layout L = chi0_layout(*prob, o, *plan, 2, true, n_eig);
         char* base = call_scratch(L.total, o, s);
-        run_chi0(*prob, o, s, base, L, reinterpret_cast<const double2*>(basis));
+        run_chi0(*prob, o, s, base, L, reinterpret_cast<const double2*>(basis), weight);
     });
 }
 

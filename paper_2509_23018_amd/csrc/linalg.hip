@@ -170,6 +170,17 @@ __global__ __launch_bounds__(256) void zaxpby_kernel(int64_t n, double2 a, const
     }
 }
 
+__global__ __launch_bounds__(256) void scale_rows_kernel(const double2* in, double2* out,
+                                                         const double* __restrict__ w,
+                                                         int64_t n, int64_t cols) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double f = w[i / cols];
+        const double2 x = in[i];
+        out[i] = make_double2(f * x.x, f * x.y);
+    }
+}
+
 // ---------------------------------------------------------------- Jacobi
 //
 // Round-robin order on n' = n rounded up to even: in step r (r < n' - 1) the
@@ -399,6 +410,16 @@ void launch_zaxpby(int64_t n, double2 a, const double2* x, double2 b, const doub
     const int64_t blocks = std::min<int64_t>(ceil_div64(n, 256), 8192);
     hipLaunchKernelGGL(zaxpby_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, n, a,
                        x, b, y, z);
+    GW_HIP_TRY(hipGetLastError());
+}
+
+void launch_scale_rows(const double2* in, double2* out, const double* w, int64_t rows,
+                       int64_t cols, hipStream_t s) {
+    const int64_t n = rows * cols;
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>(ceil_div64(n, 256), 8192);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       in, out, w, n, cols);
     GW_HIP_TRY(hipGetLastError());
 }
 

@@ -37,6 +37,10 @@ void launch_zaxpby(int64_t n, double2 a, const double2* x, double2 b, const doub
 
 // out[b][:, j] = in[b][:, perm[b][j]] for `batch` [rows][n_in] blocks (perm
 // [batch][n_out]).
+// out[i][j] = w[i] in[i][j] for an [rows][cols] block (out may be in).
+void launch_scale_rows(const double2* in, double2* out, const double* w, int64_t rows,
+                       int64_t cols, hipStream_t s);
+
 void launch_gather_cols(const double2* in, double2* out, int rows, int n_in, int n_out,
                         const int* perm, int batch, hipStream_t s);
 

@@ -14,14 +14,19 @@
 //      below which lies what is not wanted) and grows fastest above it,
 //      scaled by its value at the upper bound b of the spectrum (three-term
 //      recurrence of the scaled polynomials); m is chosen so that the filter
-//      amplifies by at most 1e6, which keeps Y well enough conditioned for
-//      the Gram-matrix orthonormalisation below;
+//      amplifies the largest Ritz value (times 1.2, a margin for what the
+//      block has not yet found) by at most 2e6 over a_cut, which keeps Y well
+//      enough conditioned for the Gram-matrix orthonormalisation below;
 //   2. orthonormalise Y twice: G = Y^H Y = U S U^H (Jacobi), Y <- Y U S^-1/2;
 //   3. Rayleigh-Ritz: H = X^H A X = W T W^H (Jacobi), X <- X W, Ritz values
 //      in decreasing order;
 //   4. residuals r_j = |A x_j - t_j x_j| / b for the n_eig kept pairs.
 // It stops when every kept residual is below tol.  b is the largest absolute
 // row sum of chi (Gershgorin: an upper bound of the spectrum).
+//
+// With a weight w the matrix is W chi W, W = diag(w), applied as three steps
+// (scale the rows of the block, the GEMM with chi, scale the rows again), so
+// the weighted matrix is never formed.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -57,14 +62,15 @@ __global__ __launch_bounds__(256) void random_block_kernel(double2* __restrict__
     }
 }
 
-// Absolute row sums of a [n][n]: one workgroup per row.
+// Absolute row sums of W a W (w NULL: W = I) for a [n][n]: one workgroup per row.
 __global__ __launch_bounds__(256) void row_abs_sum_kernel(const double2* __restrict__ a, int n,
+                                                          const double* __restrict__ w,
                                                           double* __restrict__ out) {
     const int64_t i = blockIdx.x;
     double acc = 0.0;
     for (int j = threadIdx.x; j < n; j += 256) {
         const double2 x = a[i * n + j];
-        acc += hypot(x.x, x.y);
+        acc += hypot(x.x, x.y) * (w ? fabs(w[j]) : 1.0);
     }
     __shared__ double s[256];
     s[threadIdx.x] = acc;
@@ -73,7 +79,7 @@ __global__ __launch_bounds__(256) void row_abs_sum_kernel(const double2* __restr
         if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[i] = s[0];
+    if (threadIdx.x == 0) out[i] = s[0] * (w ? fabs(w[i]) : 1.0);
 }
 
 // d[j] = 1/sqrt(g_jj) for g_jj above thr, else 0 (a direction lost to rounding
@@ -146,19 +152,21 @@ struct Carve {
 struct DiagLayout {
     int nb = 0;
     size_t big[4] = {0, 0, 0, 0};      // [ng][nb] blocks
+    size_t wx = 0;                     // [ng][nb]: W x (weighted only)
     size_t g = 0, u = 0, w = 0, jw = 0;  // [nb][nb]: Gram / Ritz matrix, vectors, sorted vectors
     size_t vec = 0;                    // [ng] doubles (row sums), [nb] doubles (residuals)
     size_t theta = 0, perm = 0;
     size_t total = 0;
 };
 
-DiagLayout diag_layout(int ng, int n_eig, int guard) {
+DiagLayout diag_layout(int ng, int n_eig, int guard, bool weighted) {
     DiagLayout L;
     L.nb = std::min(ng, n_eig + guard);
     const size_t blk = static_cast<size_t>(ng) * L.nb * sizeof(double2);
     const size_t sm = static_cast<size_t>(L.nb) * L.nb * sizeof(double2);
     Carve cv;
     for (auto& b : L.big) b = cv.take(blk);
+    L.wx = cv.take(weighted ? blk : 0);
     L.g = cv.take(sm);
     L.u = cv.take(sm);
     L.w = cv.take(sm);
@@ -180,15 +188,16 @@ __global__ void negate_kernel(const double* __restrict__ in, double* __restrict_
 
 }  // namespace
 
-size_t subspace_basis_bytes(int ng, int n_eig, int guard) {
-    return diag_layout(ng, n_eig, guard > 0 ? guard : default_guard(n_eig)).total;
+size_t subspace_basis_bytes(int ng, int n_eig, int guard, bool weighted) {
+    return diag_layout(ng, n_eig, guard > 0 ? guard : default_guard(n_eig), weighted).total;
 }
 
 DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* basis,
                               double* eigenvalues, const DiagParams& prm, char* base,
                               hipStream_t s) {
     const int guard = prm.guard > 0 ? prm.guard : default_guard(n_eig);
-    const DiagLayout L = diag_layout(ng, n_eig, guard);
+    const double* wgt = prm.weight;
+    const DiagLayout L = diag_layout(ng, n_eig, guard, wgt != nullptr);
     const int nb = L.nb;
     double2* pool[4];
     for (int i = 0; i < 4; ++i) pool[i] = reinterpret_cast<double2*>(base + L.big[i]);
@@ -219,9 +228,16 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
         gg.beta = zero;
         launch_zgemm(oa, ob, gg, s);
     };
-    // y = scale * A x = -scale * chi x for an [ng][nb] block
+    // y = scale * A x = -scale * W chi W x for an [ng][nb] block
+    double2* wx = reinterpret_cast<double2*>(base + L.wx);
     auto apply_a = [&](const double2* x, double2* y, double scale) {
-        gemm(kOpN, kOpN, ng, nb, ng, make_double2(-scale, 0.0), chi, ng, x, nb, y, nb);
+        if (!wgt) {
+            gemm(kOpN, kOpN, ng, nb, ng, make_double2(-scale, 0.0), chi, ng, x, nb, y, nb);
+            return;
+        }
+        launch_scale_rows(x, wx, wgt, ng, nb, s);
+        gemm(kOpN, kOpN, ng, nb, ng, make_double2(-scale, 0.0), chi, ng, wx, nb, y, nb);
+        launch_scale_rows(y, y, wgt, ng, nb, s);
     };
     std::vector<double2> dg(nb);
     auto read_diag = [&](const double2* m) {
@@ -256,7 +272,7 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
 
     DiagResult res;
     // spectrum bound of A (Gershgorin)
-    hipLaunchKernelGGL(row_abs_sum_kernel, dim3(ng), dim3(256), 0, s, chi, ng, vec);
+    hipLaunchKernelGGL(row_abs_sum_kernel, dim3(ng), dim3(256), 0, s, chi, ng, wgt, vec);
     GW_HIP_TRY(hipGetLastError());
     std::vector<double> h(std::max(ng, nb));
     GW_HIP_TRY(hipMemcpyAsync(h.data(), vec, ng * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -282,12 +298,13 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
     GW_HIP_TRY(hipGetLastError());
     orth(pool[1], pool[0], pool[2]);
     std::vector<int> perm(nb);
-    double acut = 0.0;
+    double acut = 0.0, top = 0.0;
     for (int it = 0;; ++it) {
         if (it > 0) {
             // Chebyshev filter on [0, acut] scaled at bup: p_m(A) X, then orthonormalised
             const double e = 0.5 * acut, c = 0.5 * acut;
-            const double ach = std::acosh(std::max((bup - c) / e, 1.0 + 1e-12));
+            const double bdeg = std::min(bup, std::max(1.2 * top, 1.001 * acut));
+            const double ach = std::acosh(std::max((bdeg - c) / e, 1.0 + 1e-12));
             const int m =
                 std::max(1, std::min(prm.max_degree, static_cast<int>(std::log(2e6) / ach)));
             res.degree = m;
@@ -345,6 +362,7 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
         // below the smallest Ritz value of the block lies what is not wanted;
         // a zero floor (chi of lower rank than the block) still filters
         acut = std::max(dg[perm[nb - 1]].x, 1e-6 * bup);
+        top = dg[perm[0]].x;
         if (rmax <= prm.tol || it + 1 >= prm.max_iter || nb == ng) break;
     }
     // the first n_eig Ritz vectors; eigenvalues of chi are minus those of A

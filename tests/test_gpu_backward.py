@@ -22,11 +22,20 @@ def _herm(rng, nz, ng):
     # 12 valence x 3 conduction bands in one chunk: more valence bands than
     # the fused band reduction holds, so the two separate reductions run
     ((0.2j,), 1000, 12, 3),
+    # a real frequency (Delta real: the single-product path) beside a complex one
+    ((0.25, 0.3 + 0.02j, 0.6j), 23, 4, 11),
 ])
-def test_backward_matches_oracle_adjoint(zs, chunk, nv, nc):
+@pytest.mark.parametrize("herm", [True, False])
+def test_backward_matches_oracle_adjoint(zs, chunk, nv, nc, herm):
+    """The adjoint against the oracle's chain rule, for Hermitian cotangents
+    and general ones (the single product against W + W^H on frequencies with a
+    real Delta holds for any W)."""
     p = gen.make_problem((12, 10, 14), nv, nc, r2=9, z=zs, seed=21, pair_chunk=chunk)
     rng = np.random.default_rng(5)
     w = _herm(rng, len(p.z), p.ng)
+    if not herm:
+        w = np.ascontiguousarray(w + 0.3j * rng.standard_normal(w.shape) +
+                                 0.2 * rng.standard_normal(w.shape))
     dp = to_dev(p)
     got = gw.gw_chi0_backward(dp, torch.from_numpy(w).to(device()), pair_chunk=chunk)
     ref = oracle.chi0_backward(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, w,

@@ -167,12 +167,56 @@ def test_subspace_pipeline_on_device():
     assert np.abs(chib[0] - np.diag(ev.cpu().numpy())).max() < 1e-11 * np.abs(chib[0]).max()
 
 
+def test_subspace_weighted_against_oracle():
+    """The symmetrised form W chi W (w = sqrt of the Coulomb diagonal at a
+    shifted q): Diag of the oracle's chi0(0) against the oracle's weighted
+    eigenpairs (eigenvalues, diagonal static chi in the device basis), then
+    Transf + CHI-Freq with the oracle's weighted basis element by element, and
+    the whole weighted pipeline on the device against the oracle's projected
+    W chi W."""
+    p, chi = _chi_static_problem(seed=44, nv=3, nc=17)
+    wt = np.sqrt(oracle.coulomb(p.gvec, q=(0.1, -0.05, 0.2), cell_l=gen.CELL_L))
+    wd = torch.from_numpy(wt).to(device())
+    n_eig = 24
+    cs, want_ev = oracle.static_subspace_basis(chi[0], n_eig, weight=wt)
+    a = torch.from_numpy(np.ascontiguousarray(chi[0])).to(device())
+    basis, ev, info = gw.gw_subspace_basis(a, n_eig, weight=wd, tol=1e-12)
+    b, ev = basis.cpu().numpy(), ev.cpu().numpy()
+    scale = np.abs(want_ev).max()
+    assert np.abs(ev - want_ev).max() < 1e-11 * scale, (ev, want_ev, info)
+    wchiw = wt[None, :, None] * chi * wt[None, None, :]
+    assert np.abs(b.conj().T @ wchiw[0] @ b - np.diag(ev)).max() < 1e-10 * scale
+    dp = to_dev(p)
+    want = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                                spin=p.spin, pair_chunk=p.pair_chunk, weight=wt)
+    got = gw.gw_chi0_subspace(dp, torch.from_numpy(np.ascontiguousarray(cs)).to(device()),
+                              weight=wd, pair_chunk=p.pair_chunk).cpu().numpy()
+    assert rel_fro(got, want) < FP64_TOL, rel_fro(got, want)
+    # whole pipeline at n_eig = rank (20 pairs), where the projector is unique
+    p, chi = _chi_static_problem(seed=45)
+    wt = np.sqrt(oracle.coulomb(p.gvec, q=(0.1, -0.05, 0.2), cell_l=gen.CELL_L))
+    wd = torch.from_numpy(wt).to(device())
+    dp = to_dev(p)
+    chi_d = gw.gw_chi0(dp, pair_chunk=p.pair_chunk)
+    basis, ev, _ = gw.gw_subspace_basis(chi_d[0].contiguous(), 20, weight=wd, tol=1e-12)
+    b = basis.cpu().numpy()
+    chib = gw.gw_chi0_subspace(dp, basis, weight=wd, pair_chunk=p.pair_chunk).cpu().numpy()
+    cs, _ = oracle.static_subspace_basis(chi[0], 20, weight=wt)
+    proj = cs @ cs.conj().T
+    wchiw = wt[None, :, None] * chi * wt[None, None, :]
+    for w in range(len(p.z)):
+        ref = proj @ wchiw[w] @ proj
+        assert rel_fro(b @ chib[w] @ b.conj().T, ref) < 1e-10, w
+
+
 def test_subspace_argument_errors():
     a = torch.zeros((8, 8), dtype=torch.complex128, device=device())
     with pytest.raises(gw.GWError):
         gw.gw_subspace_basis(a, 9)
     with pytest.raises(gw.GWError):
         gw.gw_subspace_basis(a, 0)
+    with pytest.raises(ValueError):
+        gw.gw_subspace_basis(a, 3, weight=torch.ones(7, dtype=torch.float64, device=device()))
     basis, ev, info = gw.gw_subspace_basis(a, 3)      # chi = 0: unit vectors, zero eigenvalues
     assert torch.all(ev == 0)
     b = basis.cpu().numpy()

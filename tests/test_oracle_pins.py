@@ -607,6 +607,63 @@ def test_subspace_plane_waves():
         assert np.abs(chib[w] - np.diag(want[w, top])).max() < 1e-12 * np.abs(want).max()
 
 
+def test_subspace_weighted_plane_waves():
+    """The symmetrised form W chi W with plane waves: the kept G are those of
+    largest w_G^2 |chi_GG(0)| (a different set from the unweighted one here),
+    the eigenvalues are w_G^2 chi_GG(0) and chi_B(z) is diag(w_G^2 chi_GG(z)):
+    one factor w per matrix element, so a weight applied twice, or to only one
+    side, fails."""
+    n = (8, 8, 8)
+    kv = [(0, 0, 0), (1, 0, 0)]
+    kc = [(1, 0, 0), (2, 0, 0), (0, 1, 0), (0, 0, 2), (-1, 0, 0)]
+    pv, pc = _plane_waves(kv, n), _plane_waves(kc, n)
+    e_v = np.array([-0.2, -0.35])
+    e_c = np.array([0.1, 0.3, 0.45, 0.8, 1.05])
+    z = np.array([0.0, 0.6j, 0.25 + 0.005j])
+    gl = gen.gsphere(6)
+    want = np.zeros((3, gl.shape[0]), dtype=np.complex128)
+    for w, zz in enumerate(z):
+        for v, c in itertools.product(range(2), range(5)):
+            hit = np.where(np.all(gl == np.array(kv[v]) - np.array(kc[c]), axis=1))[0]
+            de = e_v[v] - e_c[c]
+            if hit.size:
+                want[w, hit[0]] += 2.0 * (1 / (de + zz) + 1 / (de - zz))
+    wt = np.sqrt(oracle.coulomb(gl, q=(0.1, 0.2, -0.3), cell_l=L))
+    n_eig = 3
+    cs, ev = oracle.static_subspace_basis(np.diag(want[0]), n_eig, weight=wt)
+    scaled = wt ** 2 * want[0].real
+    top = np.argsort(-np.abs(scaled), kind="stable")[:n_eig]
+    plain = np.argsort(-np.abs(want[0].real), kind="stable")[:n_eig]
+    assert set(top) != set(plain)
+    assert len(set(np.abs(scaled[top]).round(12))) == n_eig
+    assert np.allclose(ev, scaled[top], rtol=1e-14, atol=0)
+    assert np.allclose(np.abs(cs[top, range(n_eig)]), 1.0, atol=1e-14)
+    chib = oracle.chi0_subspace(pv, pc, e_v, e_c, gl, z, n, VOL, cs, spin=2.0, pair_chunk=4,
+                                weight=wt)
+    for w in range(3):
+        d = wt[top] ** 2 * want[w, top]
+        assert np.abs(chib[w] - np.diag(d)).max() < 1e-12 * np.abs(d).max()
+
+
+def test_subspace_weighted_full_basis():
+    """With a weight and n_eig = N_G, C_s chi_B C_s^H = W chi W at every
+    frequency (chi from Eq. (4) directly), the eigenvalues sum to the trace of
+    W chi(0) W, and with unit weights the weighted basis is the plain one."""
+    p = _subspace_problem(seed=34)
+    chi = _chi(p)
+    wt = np.sqrt(oracle.coulomb(p.gvec, q=(0.05, -0.1, 0.15), cell_l=L))
+    cs, ev = oracle.static_subspace_basis(chi[0], p.ng, weight=wt)
+    wchiw = wt[None, :, None] * chi * wt[None, None, :]
+    assert abs(ev.sum() - np.trace(wchiw[0]).real) < 1e-12 * np.abs(ev).sum()
+    chib = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                                spin=p.spin, pair_chunk=p.pair_chunk, weight=wt)
+    back = np.einsum("gb,wbc,hc->wgh", cs, chib, cs.conj())
+    assert np.abs(back - wchiw).max() < 1e-12 * np.abs(wchiw).max()
+    c1, e1 = oracle.static_subspace_basis(chi[0], 6, weight=np.ones(p.ng))
+    c0, e0 = oracle.static_subspace_basis(chi[0], 6)
+    assert np.array_equal(e1, e0) and np.array_equal(c1, c0)
+
+
 # ---------------------------------------------------------------- inverse dielectric matrix (Eq. (3))
 
 def test_coulomb_closed_form():
