@@ -683,7 +683,7 @@ def bench_batched(args):
 
 
 ADJOINT_KERNELS = ("mtxel_zy", "mtxel_x", "delta", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x",
-                   "bwd_yz", "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v")
+                   "bwd_yz", "bwd_yz_reduce", "bwd_reduce_c", "bwd_reduce_v")
 
 
 def bench_adjoint(args):

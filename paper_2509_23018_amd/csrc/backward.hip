@@ -9,9 +9,13 @@
 //   dL/dE_v = s sum_w sum_c Re[dDelta/dE_v q],  dL/dE_c = -(same) over v
 //   g_rho = dV sum_G g_M(G) e^{-i G.r}           pruned inverse transform
 //   dL/dpsi_c += psi_v g_rho,  dL/dpsi_v += psi_c conj(g_rho)  (ordered sums)
+// For chunks of at most 8 valence bands (the default chunk shapes) the last
+// two transform stages and both band sums run in one kernel and g_rho stays
+// in registers.
 // Every reduction runs in a fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <cstdint>
+#include <vector>
 
 #include "backward.hpp"
 #include "chi0.hpp"
@@ -380,6 +384,206 @@ __global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__
     }
 }
 
+constexpr int kFuseV = 8;   // valence bands of a chunk the fused band reductions take
+constexpr int kFuseC = 16;  // conduction bands per block of the fused band reductions
+constexpr int kPassV = 2;   // valence bands per pass of the fused inverse transform
+
+// Stages z and y of the inverse transform fused with both band reductions, so
+// that g_rho never leaves registers.  Workgroup (plane j1, block cb of kFuseC
+// conduction bands) takes every valence band of the chunk; wave w takes the
+// 16 x 16 output blocks (j2 block rb, j3 block nb) w, w + 4, ... of the plane,
+// and for each block and pair (vl, cl) forms T (stage z) and the g_rho block
+// (stage y) on the MFMAs as bwd_yz_kernel does, each lane then holding 4
+// values of the block (rows j2 = 16 rb + 4 t + lane/16, column
+// j3 = 16 nb + lane%16).  With those values in hand:
+//   grad_psi_c[c0 + cl](r) += sum_vl psi_v[v0 + vl](r) g_rho(r)  (this
+//       workgroup alone writes these points of these conduction bands);
+//   vpart[cb][vl](r) = sum_{cl in cb} psi_c[c0 + cl](r) conj(g_rho(r)), added
+//       over the blocks by vpart_reduce_kernel.
+// The valence bands go in passes of kPassV (their vpart sums stay in
+// registers), and T is formed again for each j2 block it feeds (a third more
+// MFMA work on a plane of two j2 blocks), against 2 x 16 bytes per point and
+// pair of HBM traffic when g_rho is stored and read back.
+// On the smallest box (one 16-wide block on the y and z axes) everything that
+// does not depend on the pair (the box map, both twiddle operands) is read
+// once per block into registers, and the stage-z operand of the next pair is
+// loaded while the current pair's MFMAs run; larger boxes read them per
+// k-step, and take the valence bands two at a time, to stay within the
+// registers.
+template <int NB2, int NB3>
+__global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
+    const double2* __restrict__ u, int n1, int n2, int n3, int n23, int nj2, int nj3,
+    const double2* __restrict__ w2inv, const double2* __restrict__ w3inv,
+    const int* __restrict__ boxmap, int64_t nr, double dv, const double2* __restrict__ psi_v,
+    const double2* __restrict__ psi_c, int v0, int c0, int cw, int vcount,
+    double2* __restrict__ gpc, double2* __restrict__ vpart) {
+    constexpr int KS3 = NB3 * 4, KS2 = NB2 * 4, BW3 = NB3 * 16;
+    constexpr bool HOIST = NB2 * NB3 == 1;
+    constexpr int PV = kPassV;  // valence bands per pass
+    constexpr int KH = HOIST ? KS3 : 1, NH = HOIST ? NB2 : 1;  // hoisted array extents
+    const int j1 = blockIdx.x, cb = blockIdx.y;
+    const int cl0 = cb * kFuseC, ncl = min(cw, cl0 + kFuseC) - cl0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
+    const int64_t plane = static_cast<int64_t>(j1) * n2 * n3;
+    for (int blk = wave; blk < nj2 * nj3; blk += 4) {
+        const int rb = blk / nj3, nb = blk - rb * nj3;
+        const int j3 = nb * 16 + row;
+        int64_t pos[4];
+        bool ok[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j2 = rb * 16 + 4 * t + kq;
+            ok[t] = j2 < n2 && j3 < n3;
+            pos[t] = ok[t] ? plane + static_cast<int64_t>(j2) * n3 + j3 : 0;
+        }
+        int bm[KH][NH];
+        double2 w3[KH], w2[NH][4];
+        if constexpr (HOIST) {
+#pragma unroll
+            for (int s = 0; s < KS3; ++s) {
+                w3[s] = w3inv[(s * nj3 + nb) * 64 + lane];
+#pragma unroll
+                for (int b2 = 0; b2 < NB2; ++b2)
+                    bm[s][b2] = boxmap[(b2 * 16 + row) * BW3 + 4 * s + kq];
+            }
+#pragma unroll
+            for (int b2 = 0; b2 < NB2; ++b2)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) w2[b2][t] = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
+        }
+        // stage-z operand of pair (vl, cl) on this plane (HOIST only)
+        auto load_a = [&](int vl, int cl, double2 (&a)[KH][NH]) {
+            const double2* urow =
+                u + ((static_cast<int64_t>(vl) * cw + cl0 + cl) * n1 + j1) * n23;
+#pragma unroll
+            for (int s = 0; s < KH; ++s)
+#pragma unroll
+                for (int b2 = 0; b2 < NH; ++b2) {
+                    const int d = bm[s][b2];
+                    const double2* src = urow + (d >= 0 ? d : 0);
+                    a[s][b2].x = src->x;
+                    a[s][b2].y = src->y;
+                }
+        };
+        for (int vp = 0; vp < vcount; vp += PV) {
+            const int nvp = min(PV, vcount - vp);
+            const int nq = ncl * nvp;  // pairs of this pass: q = cl * nvp + i
+            double2 av[PV][4];
+#pragma unroll
+            for (int i = 0; i < PV; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) av[i][t] = make_double2(0.0, 0.0);
+            // psi_c and the old grad_psi_c of conduction band cl at this lane's
+            // points, loaded with its first pair (the MFMAs of that pair, and of
+            // the band's other pairs, run before they are used)
+            double2 pc[4], ac[4], go[4];
+            double2 acur[KH][NH], anext[KH][NH];
+            if constexpr (HOIST) load_a(vp, 0, acur);
+            for (int q = 0; q < nq; ++q) {
+                const int cl = q / nvp, i = q - cl * nvp;
+                if (i == 0) {
+                    const int64_t row_c = static_cast<int64_t>(c0 + cl0 + cl) * nr;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        pc[t] = psi_c[row_c + pos[t]];
+                        go[t] = gpc ? gpc[row_c + pos[t]] : make_double2(0.0, 0.0);
+                        ac[t] = make_double2(0.0, 0.0);
+                    }
+                }
+                if constexpr (HOIST) {
+                    if (q + 1 < nq) {
+                        const int cn = (q + 1) / nvp;
+                        load_a(vp + (q + 1 - cn * nvp), cn, anext);
+                    }
+                }
+                const double2* pvr = psi_v + static_cast<int64_t>(v0 + vp + i) * nr;
+                double2 pv[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pv[t] = pvr[pos[t]];
+                // stage z: T[k2][j3] for this j3 block (three real products
+                // per complex one, as in bwd_yz_kernel)
+                dbl4 t1[NB2], t2[NB2], t3[NB2];
+#pragma unroll
+                for (int b2 = 0; b2 < NB2; ++b2) t1[b2] = t2[b2] = t3[b2] = zero4();
+                const double2* urow =
+                    u + ((static_cast<int64_t>(vp + i) * cw + cl0 + cl) * n1 + j1) * n23;
+                constexpr int UNR = HOIST ? KS3 : 2;  // bounded unrolling on large boxes
+#pragma unroll UNR
+                for (int s = 0; s < KS3; ++s) {
+                    double2 b;
+                    if constexpr (HOIST)
+                        b = w3[s];
+                    else
+                        b = w3inv[(s * nj3 + nb) * 64 + lane];
+                    const double bs = b.x + b.y;
+#pragma unroll
+                    for (int b2 = 0; b2 < NB2; ++b2) {
+                        double2 a;
+                        if constexpr (HOIST) {
+                            a = bm[s][b2] >= 0 ? acur[s][b2] : make_double2(0.0, 0.0);
+                        } else {
+                            const int d = boxmap[(b2 * 16 + row) * BW3 + 4 * s + kq];
+                            a = d >= 0 ? urow[d] : make_double2(0.0, 0.0);
+                        }
+                        t1[b2] = mfma_f64(a.x, b.x, t1[b2]);
+                        t2[b2] = mfma_f64(a.y, b.y, t2[b2]);
+                        t3[b2] = mfma_f64(a.x + a.y, bs, t3[b2]);
+                    }
+                }
+                // stage y: the g_rho block
+                dbl4 g1 = zero4(), g2 = zero4(), g3 = zero4();
+#pragma unroll
+                for (int b2 = 0; b2 < NB2; ++b2)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        double2 a;
+                        if constexpr (HOIST)
+                            a = w2[b2][t];
+                        else
+                            a = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
+                        const double p1 = t1[b2][t], p2 = t2[b2][t], p3 = t3[b2][t];
+                        g1 = mfma_f64(a.x, p1 - p2, g1);
+                        g2 = mfma_f64(a.y, p3 - p1 - p2, g2);
+                        g3 = mfma_f64(a.x + a.y, p3 - 2.0 * p2, g3);
+                    }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double gr = dv * (g1[t] - g2[t]), gi = dv * (g3[t] - g1[t] - g2[t]);
+                    ac[t].x += pv[t].x * gr - pv[t].y * gi;  // psi_v g
+                    ac[t].y += pv[t].x * gi + pv[t].y * gr;
+#pragma unroll
+                    for (int ii = 0; ii < PV; ++ii)
+                        if (ii == i) {
+                            av[ii][t].x += pc[t].x * gr + pc[t].y * gi;  // psi_c conj(g)
+                            av[ii][t].y += pc[t].y * gr - pc[t].x * gi;
+                        }
+                }
+                if (i == nvp - 1 && gpc)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (ok[t])
+                            gpc[static_cast<int64_t>(c0 + cl0 + cl) * nr + pos[t]] =
+                                make_double2(go[t].x + ac[t].x, go[t].y + ac[t].y);
+                if constexpr (HOIST) {
+#pragma unroll
+                    for (int s = 0; s < KS3; ++s)
+#pragma unroll
+                        for (int b2 = 0; b2 < NB2; ++b2) acur[s][b2] = anext[s][b2];
+                }
+            }
+            if (vpart)
+#pragma unroll
+                for (int i = 0; i < PV; ++i) {
+                    if (i >= nvp) break;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (ok[t])
+                            vpart[(static_cast<int64_t>(cb) * vcount + vp + i) * nr + pos[t]] = av[i][t];
+                }
+        }
+    }
+}
+
 // grad_psi_c[c0 + cl] += sum_vl psi_v[v0 + vl] * g_rho[vl*cw + cl]
 __global__ __launch_bounds__(256) void reduce_c_kernel(const double2* __restrict__ grho,
                                                        const double2* __restrict__ psi_v,
@@ -421,56 +625,6 @@ __global__ __launch_bounds__(256) void reduce_v_kernel(const double2* __restrict
     *dst = make_double2(o.x + re, o.y + im);
 }
 
-constexpr int kFuseV = 8;   // valence bands of a chunk the fused band reduction holds in registers
-constexpr int kFuseC = 16;  // conduction bands per thread of the fused band reduction
-
-// Both band reductions in one pass over g_rho, for chunks of at most kFuseV
-// valence bands: thread (r, conduction block cb) adds sum_vl psi_v g_rho to
-// grad_psi_c of the block's kFuseC conduction bands, and writes the block's
-// share of sum_cl psi_c conj(g_rho) for every valence band to vpart[cb][vl][r]
-// (added up by vpart_reduce_kernel).  gpc or vpart may be null.
-template <int VB>
-__global__ __launch_bounds__(256) void reduce_cv_kernel(const double2* __restrict__ grho,
-                                                        const double2* __restrict__ psi_v,
-                                                        const double2* __restrict__ psi_c,
-                                                        int64_t nr, int v0, int c0, int cw,
-                                                        double2* __restrict__ gpc,
-                                                        double2* __restrict__ vpart) {
-    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= nr) return;
-    const int cb = blockIdx.y, cl0 = cb * kFuseC, cl1 = min(cw, cl0 + kFuseC);
-    double2 pv[VB], av[VB];
-#pragma unroll
-    for (int vl = 0; vl < VB; ++vl) {
-        pv[vl] = psi_v[static_cast<int64_t>(v0 + vl) * nr + r];
-        av[vl] = make_double2(0.0, 0.0);
-    }
-    for (int cl = cl0; cl < cl1; ++cl) {
-        const double2 pc = psi_c[static_cast<int64_t>(c0 + cl) * nr + r];
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int vl = 0; vl < VB; ++vl) {
-            // g_rho is read once (non-temporal: it should not displace psi)
-            const int64_t gi = (static_cast<int64_t>(vl) * cw + cl) * nr + r;
-            const double* gq = reinterpret_cast<const double*>(grho + gi);
-            const double2 g =
-                make_double2(__builtin_nontemporal_load(gq), __builtin_nontemporal_load(gq + 1));
-            re += pv[vl].x * g.x - pv[vl].y * g.y;
-            im += pv[vl].x * g.y + pv[vl].y * g.x;
-            av[vl].x += pc.x * g.x + pc.y * g.y;  // pc * conj(g)
-            av[vl].y += pc.y * g.x - pc.x * g.y;
-        }
-        if (gpc) {
-            double2* dst = gpc + static_cast<int64_t>(c0 + cl) * nr + r;
-            const double2 o = *dst;
-            *dst = make_double2(o.x + re, o.y + im);
-        }
-    }
-    if (vpart)
-#pragma unroll
-        for (int vl = 0; vl < VB; ++vl)
-            vpart[(static_cast<int64_t>(cb) * VB + vl) * nr + r] = av[vl];
-}
 
 // grad_psi_v[v0 + vl][r] += sum_cb vpart[cb][vl][r], in block order.
 __global__ __launch_bounds__(256) void vpart_reduce_kernel(const double2* __restrict__ vpart,
@@ -528,7 +682,11 @@ struct BwdLayout {
     int64_t kmax = 0;
     int nparts = 0;
     bool fuse = false;
-    size_t o_m = 0, o_t2 = 0, o_d = 0, o_dd = 0, o_gm = 0, o_q = 0, o_de = 0, o_rho = 0, o_vp = 0;
+    // o_m, o_d, o_dd: two buffers each (MTXEL and Delta of chunk k + 1 on the
+    // companion stream while chunk k is worked on); o_t2m: MTXEL's own
+    // intermediate; o_t2: the x-stage output of the inverse transform
+    size_t o_m[2] = {0, 0}, o_d[2] = {0, 0}, o_dd[2] = {0, 0};
+    size_t o_t2m = 0, o_t2 = 0, o_gm = 0, o_q = 0, o_de = 0, o_rho = 0, o_vp = 0;
     size_t o_ws = 0;  // W + W^H of one frequency (frequencies with a real Delta)
     size_t total = 0;
 };
@@ -538,30 +696,41 @@ BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi
     BwdLayout L;
     const int64_t nr = plan.nr;
     const int ng = p.ng, nz = p.nz;
-    // chunk rectangle, capped so that the per-pair grids g_rho stay within 2 GiB
-    const int64_t per_pair = nr * static_cast<int64_t>(sizeof(double2));
-    const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
-    const int chunk = static_cast<int>(std::min<int64_t>(pair_chunk, cap));
-    // 4 valence bands per MTXEL tile: conduction width capped at chunk / 4
-    L.cwmax = std::max(1, std::min(p.nc, chunk / std::max(1, std::min(p.nv, 4))));
-    L.vb = std::max(1, std::min(p.nv, chunk / L.cwmax));
+    // chunk rectangle: 4 valence bands per MTXEL tile, conduction width capped
+    // at chunk / 4
+    auto shape = [&](int chunk) {
+        L.cwmax = std::max(1, std::min(p.nc, chunk / std::max(1, std::min(p.nv, 4))));
+        L.vb = std::max(1, std::min(p.nv, chunk / L.cwmax));
+    };
+    shape(pair_chunk);
+    // at most kFuseV valence bands: the inverse transform and the band
+    // reductions run fused and g_rho is never stored; otherwise the chunk is
+    // capped so that the per-pair grids g_rho stay within 2 GiB
+    L.fuse = L.vb <= kFuseV;
+    if (!L.fuse) {
+        const int64_t per_pair = nr * static_cast<int64_t>(sizeof(double2));
+        const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 31) / per_pair);
+        shape(static_cast<int>(std::min<int64_t>(pair_chunk, cap)));
+        L.fuse = L.vb <= kFuseV;
+    }
     L.kmax = static_cast<int64_t>(L.vb) * L.cwmax;
     L.nparts = 2 * ceil_div(ng, 64);
     const int64_t kmax = L.kmax;
     Carve cv;
-    L.o_m = cv.take(kmax * ng * sizeof(double2));
+    for (int b = 0; b < 2; ++b) {
+        L.o_m[b] = cv.take(kmax * ng * sizeof(double2));
+        L.o_d[b] = cv.take(kmax * nz * sizeof(double2));
+        L.o_dd[b] = cv.take(kmax * nz * sizeof(double2));
+    }
+    L.o_t2m = cv.take(t2_elems(plan, kmax) * sizeof(double2));
     L.o_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
-    L.o_d = cv.take(kmax * nz * sizeof(double2));
-    L.o_dd = cv.take(kmax * nz * sizeof(double2));
     L.o_gm = cv.take(kmax * ng * sizeof(double2));
     bool any_sym = false;
     for (int w = 0; w < nz; ++w) any_sym = any_sym || real_delta(p, w);
     L.o_ws = cv.take(any_sym ? static_cast<size_t>(ng) * ng * sizeof(double2) : 0);
     L.o_q = cv.take(kmax * nz * L.nparts * sizeof(double2));
     L.o_de = cv.take(kmax * sizeof(double));
-    L.o_rho = cv.take(want_psi ? kmax * nr * sizeof(double2) : 0);
-    // fused band reduction: chunks of at most kFuseV valence bands
-    L.fuse = L.vb <= kFuseV;
+    L.o_rho = cv.take(want_psi && !L.fuse ? kmax * nr * sizeof(double2) : 0);
     const int ncb_max = ceil_div(L.cwmax, kFuseC);
     L.o_vp = cv.take(want_psi && L.fuse && want_psi_v
                          ? static_cast<size_t>(ncb_max) * L.vb * nr * sizeof(double2)
@@ -583,7 +752,7 @@ size_t chi0_backward_bytes(const MtxelPlan& plan, const gw_problem_t& p, bool wa
 void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const double2* grad_chi,
                        double2* grad_psi_v, double2* grad_psi_c, double* grad_e_v,
                        double* grad_e_c, double spin, int pair_chunk, hipStream_t s,
-                       char* base) {
+                       char* base, hipStream_t aux, hipEvent_t* ev) {
     const int64_t nr = plan.nr;
     const int ng = p.ng, nz = p.nz;
     const int n1 = plan.n[0], n2 = plan.n[1], n3 = plan.n[2];
@@ -599,12 +768,16 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     const BwdLayout L = bwd_layout(plan, p, want_psi, grad_psi_v != nullptr, pair_chunk);
     const int vb = L.vb, cwmax = L.cwmax, nparts = L.nparts;
     const bool fuse = L.fuse;
-    const size_t o_m = L.o_m, o_t2 = L.o_t2, o_d = L.o_d, o_dd = L.o_dd, o_gm = L.o_gm,
-                 o_q = L.o_q, o_de = L.o_de, o_rho = L.o_rho, o_vp = L.o_vp;
-    double2* mbuf = reinterpret_cast<double2*>(base + o_m);
+    const size_t o_t2 = L.o_t2, o_gm = L.o_gm, o_q = L.o_q, o_de = L.o_de, o_rho = L.o_rho,
+                 o_vp = L.o_vp;
+    double2 *mbufs[2], *dbufs[2], *ddbufs[2];
+    for (int b = 0; b < 2; ++b) {
+        mbufs[b] = reinterpret_cast<double2*>(base + L.o_m[b]);
+        dbufs[b] = reinterpret_cast<double2*>(base + L.o_d[b]);
+        ddbufs[b] = reinterpret_cast<double2*>(base + L.o_dd[b]);
+    }
+    double2* t2m = reinterpret_cast<double2*>(base + L.o_t2m);
     double2* t2 = reinterpret_cast<double2*>(base + o_t2);
-    double2* dbuf = reinterpret_cast<double2*>(base + o_d);
-    double2* ddbuf = reinterpret_cast<double2*>(base + o_dd);
     double2* gm = reinterpret_cast<double2*>(base + o_gm);
     double2* qpart = reinterpret_cast<double2*>(base + o_q);
     double* de = reinterpret_cast<double*>(base + o_de);
@@ -616,25 +789,53 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     const double2* psi_c = reinterpret_cast<const double2*>(p.psi_c);
     const double dv = p.grid.volume / static_cast<double>(nr);
 
-    for (int v0 = 0; v0 < p.nv; v0 += vb) {
-        for (int c0 = 0; c0 < p.nc; c0 += cwmax) {
-            const int vcount = std::min(vb, p.nv - v0);
-            const int cw = std::min(cwmax, p.nc - c0);
-            const int64_t kc = static_cast<int64_t>(vcount) * cw;
-            PairMap pm{0, cw, v0, c0};
-            launch_mtxel(plan, psi_v, psi_c, Rect{v0, vcount, c0, cw}, p.grid.volume, t2, mbuf, s);
-            launch_delta(p.e_v, p.e_c, pm, kc, z, nz, spin, dbuf, s);
-            for (int w0 = 0; w0 < nz; w0 += kMaxZ) {
-                ZArgs za{};
-                za.nz = std::min(kMaxZ, nz - w0);
-                for (int w = 0; w < za.nz; ++w) {
-                    za.re[w] = z[w0 + w].x;
-                    za.im[w] = z[w0 + w].y;
-                }
-                hipLaunchKernelGGL(ddelta_kernel, dim3(static_cast<unsigned>(ceil_div64(kc, 256))),
-                                   dim3(256), 0, s, p.e_v, p.e_c, pm, kc, za, w0, ddbuf);
-                GW_HIP_TRY(hipGetLastError());
+    // chunks of vb valence x cwmax conduction bands; MTXEL, Delta and dDelta
+    // of chunk k + 1 run on the companion stream (buffer (k + 1) & 1) while
+    // chunk k is worked on here.  Events: ev[0] start on s; ev[1 + b] buffer
+    // b filled; ev[3 + b] buffer b read for the last time.
+    struct BChunk {
+        int v0, c0, vcount, cw;
+    };
+    std::vector<BChunk> chunks;
+    for (int v0 = 0; v0 < p.nv; v0 += vb)
+        for (int c0 = 0; c0 < p.nc; c0 += cwmax)
+            chunks.push_back({v0, c0, std::min(vb, p.nv - v0), std::min(cwmax, p.nc - c0)});
+    auto produce = [&](size_t k) {
+        const int b = static_cast<int>(k & 1);
+        const BChunk& c = chunks[k];
+        const int64_t kc = static_cast<int64_t>(c.vcount) * c.cw;
+        if (k >= 2) GW_HIP_TRY(hipStreamWaitEvent(aux, ev[3 + b], 0));
+        PairMap pm{0, c.cw, c.v0, c.c0};
+        launch_mtxel(plan, psi_v, psi_c, Rect{c.v0, c.vcount, c.c0, c.cw}, p.grid.volume, t2m,
+                     mbufs[b], aux);
+        launch_delta(p.e_v, p.e_c, pm, kc, z, nz, spin, dbufs[b], aux);
+        for (int w0 = 0; w0 < nz; w0 += kMaxZ) {
+            ZArgs za{};
+            za.nz = std::min(kMaxZ, nz - w0);
+            for (int w = 0; w < za.nz; ++w) {
+                za.re[w] = z[w0 + w].x;
+                za.im[w] = z[w0 + w].y;
             }
+            hipLaunchKernelGGL(ddelta_kernel, dim3(static_cast<unsigned>(ceil_div64(kc, 256))),
+                               dim3(256), 0, aux, p.e_v, p.e_c, pm, kc, za, w0, ddbufs[b]);
+            GW_HIP_TRY(hipGetLastError());
+        }
+        GW_HIP_TRY(hipEventRecord(ev[1 + b], aux));
+    };
+    GW_HIP_TRY(hipEventRecord(ev[0], s));
+    GW_HIP_TRY(hipStreamWaitEvent(aux, ev[0], 0));
+    produce(0);
+    for (size_t ck = 0; ck < chunks.size(); ++ck) {
+        {
+            const int b = static_cast<int>(ck & 1);
+            if (ck + 1 < chunks.size()) produce(ck + 1);
+            GW_HIP_TRY(hipStreamWaitEvent(s, ev[1 + b], 0));
+            const int v0 = chunks[ck].v0, c0 = chunks[ck].c0;
+            const int vcount = chunks[ck].vcount, cw = chunks[ck].cw;
+            const int64_t kc = static_cast<int64_t>(vcount) * cw;
+            double2* mbuf = mbufs[b];
+            double2* dbuf = dbufs[b];
+            double2* ddbuf = ddbufs[b];
             for (int w = 0; w < nz; ++w) {
                 ProfScope ps("bwd_gm", s);
                 // Delta real: one product against W + W^H
@@ -664,6 +865,8 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                                    dim3(256), 0, s, de, vcount, cw, v0, c0, grad_e_v, grad_e_c);
                 GW_HIP_TRY(hipGetLastError());
             }
+            // M, Delta and dDelta of buffer b are not read after this point
+            GW_HIP_TRY(hipEventRecord(ev[3 + b], s));
             if (!want_psi) continue;
             {
                 ProfScope ps("bwd_x", s);
@@ -672,33 +875,26 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                                    plan.w1inv, plan.gmap, t2);
                 GW_HIP_TRY(hipGetLastError());
             }
-            {
-                ProfScope ps("bwd_yz", s);
-                const int nj2 = plan.n2p / 16, nj3 = plan.n3p / 16;
-                auto yz = plan.nb2 == 1   ? bwd_yz_kernel<1>
-                          : plan.nb2 == 2 ? bwd_yz_kernel<2>
-                          : plan.nb2 == 3 ? bwd_yz_kernel<3>
-                                          : bwd_yz_kernel<4>;
-                hipLaunchKernelGGL(yz, dim3(static_cast<unsigned>(kc)), dim3(256), 0, s, t2, n1, n2,
-                                   n3, plan.n23, plan.nb3, nj2, nj3, plan.w2inv, plan.w3inv,
-                                   plan.boxmap, nr, dv, grho);
-                GW_HIP_TRY(hipGetLastError());
-            }
+            const int nj2 = plan.n2p / 16, nj3 = plan.n3p / 16;
             if (fuse) {
                 const int ncb = ceil_div(cw, kFuseC);
                 {
-                    ProfScope ps("bwd_reduce_cv", s);
-                    const dim3 grid(static_cast<unsigned>(ceil_div64(nr, 256)),
-                                    static_cast<unsigned>(ncb));
-                    switch (vcount) {
-#define GW_CV(VB)                                                                              \
-    case VB:                                                                                   \
-        hipLaunchKernelGGL(reduce_cv_kernel<VB>, grid, dim3(256), 0, s, grho, psi_v, psi_c, nr, \
-                           v0, c0, cw, grad_psi_c, vpart);                                     \
-        break;
-                        GW_CV(1) GW_CV(2) GW_CV(3) GW_CV(4) GW_CV(5) GW_CV(6) GW_CV(7) GW_CV(8)
-#undef GW_CV
-                    }
+                    ProfScope ps("bwd_yz_reduce", s);
+                    using YzrFn = decltype(&bwd_yz_reduce_kernel<1, 1>);
+                    static const YzrFn table[4][4] = {
+                        {bwd_yz_reduce_kernel<1, 1>, bwd_yz_reduce_kernel<1, 2>,
+                         bwd_yz_reduce_kernel<1, 3>, bwd_yz_reduce_kernel<1, 4>},
+                        {bwd_yz_reduce_kernel<2, 1>, bwd_yz_reduce_kernel<2, 2>,
+                         bwd_yz_reduce_kernel<2, 3>, bwd_yz_reduce_kernel<2, 4>},
+                        {bwd_yz_reduce_kernel<3, 1>, bwd_yz_reduce_kernel<3, 2>,
+                         bwd_yz_reduce_kernel<3, 3>, bwd_yz_reduce_kernel<3, 4>},
+                        {bwd_yz_reduce_kernel<4, 1>, bwd_yz_reduce_kernel<4, 2>,
+                         bwd_yz_reduce_kernel<4, 3>, bwd_yz_reduce_kernel<4, 4>}};
+                    hipLaunchKernelGGL(table[plan.nb2 - 1][plan.nb3 - 1],
+                                       dim3(static_cast<unsigned>(n1), static_cast<unsigned>(ncb)),
+                                       dim3(256), 0, s, t2, n1, n2, n3, plan.n23, nj2, nj3,
+                                       plan.w2inv, plan.w3inv, plan.boxmap, nr, dv, psi_v, psi_c,
+                                       v0, c0, cw, vcount, grad_psi_c, vpart);
                     GW_HIP_TRY(hipGetLastError());
                 }
                 if (vpart) {
@@ -709,6 +905,17 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                     GW_HIP_TRY(hipGetLastError());
                 }
                 continue;
+            }
+            {
+                ProfScope ps("bwd_yz", s);
+                auto yz = plan.nb2 == 1   ? bwd_yz_kernel<1>
+                          : plan.nb2 == 2 ? bwd_yz_kernel<2>
+                          : plan.nb2 == 3 ? bwd_yz_kernel<3>
+                                          : bwd_yz_kernel<4>;
+                hipLaunchKernelGGL(yz, dim3(static_cast<unsigned>(kc)), dim3(256), 0, s, t2, n1, n2,
+                                   n3, plan.n23, plan.nb3, nj2, nj3, plan.w2inv, plan.w3inv,
+                                   plan.boxmap, nr, dv, grho);
+                GW_HIP_TRY(hipGetLastError());
             }
             if (grad_psi_c)
                 for (int cl0 = 0; cl0 < cw; cl0 += kYMax) {

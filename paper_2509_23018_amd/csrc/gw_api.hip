@@ -1434,10 +1434,11 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
                                                 grad_e_v != nullptr || grad_e_c != nullptr,
                                                 o.pair_chunk);
         char* base = call_scratch(need, o, s);
+        AuxCtx& ax = aux_ctx(s);
         run_chi0_backward(*plan, p, reinterpret_cast<const double2*>(grad_chi),
                           reinterpret_cast<double2*>(grad_psi_v),
                           reinterpret_cast<double2*>(grad_psi_c), grad_e_v, grad_e_c, o.spin,
-                          o.pair_chunk, s, base);
+                          o.pair_chunk, s, base, ax.aux, ax.ev);
         mark_plan_used(*plan, s);
     });
 }
