@@ -334,6 +334,7 @@ typedef struct {
     int32_t degree;       /* filter degree of the last one */
     double  residual;     /* largest relative residual of the kept pairs */
     double  bound;        /* the bound b */
+    int32_t sweeps;       /* Jacobi sweeps of the Rayleigh-Ritz steps, in all */
 } gw_diag_info_t;
 
 /*
@@ -343,7 +344,8 @@ typedef struct {
  * are its most negative eigenvalues; the matrix must be Hermitian and negative
  * semidefinite (positive eigenvalues are treated as insignificant).
  * Chebyshev-filtered subspace iteration with Rayleigh-Ritz steps on FP64
- * MFMA GEMMs, Ritz problems by Jacobi rotations, all on the device.
+ * MFMA GEMMs, orthonormalisation by Cholesky-QR, Ritz problems by Jacobi
+ * rotations, all on the device.
  *
  * chi_static  device [ng][ng], read only.
  * basis       device OUT [ng][n_eig] row-major: column j is the j-th

@@ -91,7 +91,8 @@ class _DiagOpts(ctypes.Structure):
 
 class _DiagInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("degree", ctypes.c_int32),
-                ("residual", ctypes.c_double), ("bound", ctypes.c_double)]
+                ("residual", ctypes.c_double), ("bound", ctypes.c_double),
+                ("sweeps", ctypes.c_int32)]
 
 
 _LIB = None
@@ -465,7 +466,7 @@ def gw_subspace_basis(chi_static: torch.Tensor, n_eig: int, *, weight=None, tol=
                                        ev.data_ptr(), ctypes.byref(o), ctypes.byref(info),
                                        _stream(chi_static.device, stream)))
     return basis, ev, {"iterations": info.iterations, "degree": info.degree,
-                       "residual": info.residual, "bound": info.bound}
+                       "residual": info.residual, "bound": info.bound, "sweeps": info.sweeps}
 
 
 def chi0_subspace_workspace_bytes(problem, n_eig: int, *, precision="fp64", n_slices=0,

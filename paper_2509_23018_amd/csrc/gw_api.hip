@@ -1202,6 +1202,17 @@ bool batched_call(int nprob, const Opts& o) {
     return nprob > 1 && (o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16);
 }
 
+// M/Delta buffers of a per-problem call: 2 (MTXEL of the next chunk on the
+// companion stream) unless GW_CHI0_BUFFERS=1 (MTXEL and the contraction in
+// turn on the caller's stream).
+int chi0_buffers() {
+    static const int n = [] {
+        const char* e = std::getenv("GW_CHI0_BUFFERS");
+        return e && std::atoi(e) == 1 ? 1 : 2;
+    }();
+    return n;
+}
+
 // Scratch of a gw_chi0 call; in_workspace: as the call needs it in a caller
 // workspace (a captured graph then keeps its work buffer there).
 size_t chi0_call_bytes(const gw_problem_t* probs, int nprob, const Opts& o, bool in_workspace) {
@@ -1209,7 +1220,7 @@ size_t chi0_call_bytes(const gw_problem_t* probs, int nprob, const Opts& o, bool
     size_t need = 0;
     for (int q = 0; q < nprob; ++q) {
         const PlanRef plan = get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
-        need = std::max(need, chi0_layout(probs[q], o, *plan, 2, true).total);
+        need = std::max(need, chi0_layout(probs[q], o, *plan, chi0_buffers(), true).total);
     }
     return need;
 }
@@ -1222,7 +1233,7 @@ void chi0_call(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t 
     }
     for (int q = 0; q < nprob; ++q) {
         const PlanRef plan = get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
-        run_chi0(probs[q], o, s, base, chi0_layout(probs[q], o, *plan, 2, true));
+        run_chi0(probs[q], o, s, base, chi0_layout(probs[q], o, *plan, chi0_buffers(), true));
     }
 }
 
@@ -1577,6 +1588,7 @@ gw_status_t gw_subspace_basis(const gw_c128* chi_static, int32_t ng, int32_t n_e
             info->degree = r.degree;
             info->residual = r.residual;
             info->bound = r.bound;
+            info->sweeps = r.sweeps;
         }
     });
 }

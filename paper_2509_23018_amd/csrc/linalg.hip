@@ -181,6 +181,108 @@ __global__ __launch_bounds__(256) void scale_rows_kernel(const double2* in, doub
     }
 }
 
+// ---------------------------------------------------------------- Cholesky
+
+constexpr int kCB = 64;  // Cholesky block
+
+// out[0] = the largest real diagonal entry of g (one workgroup)
+__global__ __launch_bounds__(256) void diag_max_kernel(const double2* __restrict__ g, int n,
+                                                       double* __restrict__ out) {
+    __shared__ double s[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, g[static_cast<int64_t>(i) * n + i].x);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// Diagonal block K = [k0, k0 + kb) of g: the upper Cholesky factor R_KK of
+// g[K][K] (g[K][K] = R_KK^H R_KK) written back over it (lower part zero), and
+// X = R_KK^-1 into x ([kCB][kCB], upper; rows and columns of lost directions
+// zero).  A pivot at or below 1e-26 * gmax[0] is a lost direction.
+__global__ __launch_bounds__(256) void chol_block_kernel(double2* __restrict__ g, int n, int k0,
+                                                         int kb, const double* __restrict__ gmax,
+                                                         double2* __restrict__ x) {
+    __shared__ double2 r[kCB][kCB + 1];
+    __shared__ double2 xi[kCB][kCB + 1];
+    const int tid = threadIdx.x;
+    const double thr = 1e-26 * gmax[0];
+    for (int e = tid; e < kb * kb; e += 256) {
+        const int i = e / kb, j = e % kb;
+        r[i][j] = g[static_cast<int64_t>(k0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+        const double piv = r[k][k].x;
+        const bool lost = !(piv > thr);
+        const double rk = lost ? 0.0 : sqrt(piv);
+        __syncthreads();  // every thread has read the pivot
+        for (int j = k + tid; j < kb; j += 256) {
+            if (lost)
+                r[k][j] = make_double2(0.0, 0.0);
+            else if (j == k)
+                r[k][k] = make_double2(rk, 0.0);
+            else
+                r[k][j] = make_double2(r[k][j].x / rk, r[k][j].y / rk);
+        }
+        __syncthreads();
+        // trailing upper part: r[i][j] -= conj(r[k][i]) r[k][j], k < i <= j
+        const int m = kb - k - 1;
+        for (int e = tid; e < m * m; e += 256) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            if (j < i) continue;
+            const double2 a = r[k][i], b = r[k][j];
+            r[i][j].x -= a.x * b.x + a.y * b.y;  // conj(a) b
+            r[i][j].y -= a.x * b.y - a.y * b.x;
+        }
+        __syncthreads();
+    }
+    // X = R^-1, column j by thread j: back substitution upwards
+    if (tid < kb) {
+        const int j = tid;
+        for (int i = 0; i < kb; ++i) xi[i][j] = make_double2(0.0, 0.0);
+        const double rjj = r[j][j].x;
+        xi[j][j] = make_double2(rjj > 0.0 ? 1.0 / rjj : 0.0, 0.0);
+        for (int i = j - 1; i >= 0; --i) {
+            const double rii = r[i][i].x;
+            if (!(rii > 0.0)) continue;  // lost direction: row i of X stays zero
+            double sr = 0.0, si = 0.0;
+            for (int k = i + 1; k <= j; ++k) {
+                const double2 a = r[i][k], b = xi[k][j];
+                sr += a.x * b.x - a.y * b.y;
+                si += a.x * b.y + a.y * b.x;
+            }
+            xi[i][j] = make_double2(-sr / rii, -si / rii);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kb * kb; e += 256) {
+        const int i = e / kb, j = e % kb;
+        g[static_cast<int64_t>(k0 + i) * n + k0 + j] = j >= i ? r[i][j] : make_double2(0.0, 0.0);
+        x[i * kCB + j] = xi[i][j];
+    }
+}
+
+// dst[i][j] = src[i][j] for an [rows][cols] block (leading dimensions lds, ldd)
+__global__ __launch_bounds__(256) void copy_block_kernel(const double2* __restrict__ src,
+                                                         int64_t lds, double2* __restrict__ dst,
+                                                         int64_t ldd, int rows, int cols) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(rows) * cols) return;
+    const int64_t i = t / cols, j = t % cols;
+    dst[i * ldd + j] = src[i * lds + j];
+}
+
+__global__ __launch_bounds__(256) void zero_fill_kernel(double2* __restrict__ p, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = make_double2(0.0, 0.0);
+}
+
 // ---------------------------------------------------------------- Jacobi
 //
 // Round-robin order on n' = n rounded up to even: in step r (r < n' - 1) the
@@ -421,6 +523,97 @@ void launch_scale_rows(const double2* in, double2* out, const double* w, int64_t
     hipLaunchKernelGGL(scale_rows_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                        in, out, w, n, cols);
     GW_HIP_TRY(hipGetLastError());
+}
+
+size_t chol_work_bytes(int n) {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    // x (kCB x kCB), panel t (kCB x n), column block u (n x kCB), gmax
+    return al(sizeof(double2) * kCB * kCB) + 2 * al(sizeof(double2) * kCB * static_cast<size_t>(n)) + 256;
+}
+
+void chol_inverse(double2* g, double2* rinv, int n, void* work, hipStream_t s) {
+    if (n <= 0) return;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char* w = static_cast<char*>(work);
+    double2* x = reinterpret_cast<double2*>(w);
+    double2* t = reinterpret_cast<double2*>(w + al(sizeof(double2) * kCB * kCB));
+    double2* u = reinterpret_cast<double2*>(w + al(sizeof(double2) * kCB * kCB) +
+                                            al(sizeof(double2) * kCB * static_cast<size_t>(n)));
+    double* gmax = reinterpret_cast<double*>(w + al(sizeof(double2) * kCB * kCB) +
+                                             2 * al(sizeof(double2) * kCB * static_cast<size_t>(n)));
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    hipLaunchKernelGGL(zero_fill_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div64(nn, 256), 4096))),
+                       dim3(256), 0, s, rinv, nn);
+    hipLaunchKernelGGL(diag_max_kernel, dim3(1), dim3(256), 0, s, g, n, gmax);
+    GW_HIP_TRY(hipGetLastError());
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
+    for (int k0 = 0; k0 < n; k0 += kCB) {
+        const int kb = std::min(kCB, n - k0), rest = n - k0 - kb;
+        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(256), 0, s, g, n, k0, kb, gmax, x);
+        GW_HIP_TRY(hipGetLastError());
+        if (rest > 0) {
+            // panel of R: T = X^H g[K][K+], then g[K][K+] = T
+            ZGemm p;
+            p.m = kb;
+            p.n = rest;
+            p.k = kb;
+            p.a = x;
+            p.lda = kCB;
+            p.b = g + static_cast<int64_t>(k0) * n + k0 + kb;
+            p.ldb = n;
+            p.c = t;
+            p.ldc = n;
+            launch_zgemm(kOpC, kOpN, p, s);
+            hipLaunchKernelGGL(copy_block_kernel, dim3(static_cast<unsigned>(ceil_div64(static_cast<int64_t>(kb) * rest, 256))),
+                               dim3(256), 0, s, t, static_cast<int64_t>(n),
+                               g + static_cast<int64_t>(k0) * n + k0 + kb, static_cast<int64_t>(n), kb, rest);
+            GW_HIP_TRY(hipGetLastError());
+            // trailing update g[K+][K+] -= T^H T
+            ZGemm q;
+            q.m = rest;
+            q.n = rest;
+            q.k = kb;
+            q.a = t;
+            q.lda = n;
+            q.b = t;
+            q.ldb = n;
+            q.c = g + static_cast<int64_t>(k0 + kb) * n + k0 + kb;
+            q.ldc = n;
+            q.alpha = mone;
+            q.beta = one;
+            launch_zgemm(kOpC, kOpN, q, s);
+        }
+        // R^-1 column block K: diagonal block X, above it -R^-1[<K][<K] R[<K][K] X
+        hipLaunchKernelGGL(copy_block_kernel, dim3(static_cast<unsigned>(ceil_div64(static_cast<int64_t>(kb) * kb, 256))),
+                           dim3(256), 0, s, x, static_cast<int64_t>(kCB),
+                           rinv + static_cast<int64_t>(k0) * n + k0, static_cast<int64_t>(n), kb, kb);
+        GW_HIP_TRY(hipGetLastError());
+        if (k0 > 0) {
+            ZGemm a;  // U = R^-1[<K][<K] R[<K][K]
+            a.m = k0;
+            a.n = kb;
+            a.k = k0;
+            a.a = rinv;
+            a.lda = n;
+            a.b = g + k0;
+            a.ldb = n;
+            a.c = u;
+            a.ldc = kCB;
+            launch_zgemm(kOpN, kOpN, a, s);
+            ZGemm b;  // R^-1[<K][K] = -U X
+            b.m = k0;
+            b.n = kb;
+            b.k = kb;
+            b.a = u;
+            b.lda = kCB;
+            b.b = x;
+            b.ldb = kCB;
+            b.c = rinv + k0;
+            b.ldc = n;
+            b.alpha = mone;
+            launch_zgemm(kOpN, kOpN, b, s);
+        }
+    }
 }
 
 size_t jacobi_work_bytes(int n, int batch) {

@@ -35,12 +35,12 @@ void launch_zgemm(ZOp opa, ZOp opb, const ZGemm& g, hipStream_t s);
 void launch_zaxpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y,
                    double2* z, hipStream_t s);
 
-// out[b][:, j] = in[b][:, perm[b][j]] for `batch` [rows][n_in] blocks (perm
-// [batch][n_out]).
 // out[i][j] = w[i] in[i][j] for an [rows][cols] block (out may be in).
 void launch_scale_rows(const double2* in, double2* out, const double* w, int64_t rows,
                        int64_t cols, hipStream_t s);
 
+// out[b][:, j] = in[b][:, perm[b][j]] for `batch` [rows][n_in] blocks (perm
+// [batch][n_out]).
 void launch_gather_cols(const double2* in, double2* out, int rows, int n_in, int n_out,
                         const int* perm, int batch, hipStream_t s);
 
@@ -53,6 +53,17 @@ void launch_gather_cols(const double2* in, double2* out, int rows, int n_in, int
 // max_sweeps; returns the sweeps made (reads one scalar per sweep back: the
 // call waits for the stream).
 size_t jacobi_work_bytes(int n, int batch);
+
+// Inverse of the upper Cholesky factor of an n x n Hermitian positive
+// semidefinite G (row-major): G = R^H R, rinv = R^-1 (upper triangular,
+// n x n), blocked by 64 (the diagonal blocks factored and inverted in LDS, the
+// panels and trailing updates as GEMMs).  A pivot at or below 1e-26 of G's
+// largest diagonal entry marks its direction as lost: that row of R and that
+// row and column of rinv are zero, so Y rinv has a zero column there.  G is
+// overwritten (R in its upper triangle).  work: chol_work_bytes(n).  Only
+// enqueues.
+size_t chol_work_bytes(int n);
+void chol_inverse(double2* g, double2* rinv, int n, void* work, hipStream_t s);
 int jacobi_eigh(double2* a, double2* v, int n, int batch, double tol, int max_sweeps, void* work,
                 hipStream_t s);
 

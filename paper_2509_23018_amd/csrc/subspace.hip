@@ -17,8 +17,10 @@
 //      amplifies the largest Ritz value (times 1.2, a margin for what the
 //      block has not yet found) by at most 2e6 over a_cut, which keeps Y well
 //      enough conditioned for the Gram-matrix orthonormalisation below;
-//   2. orthonormalise Y twice: G = Y^H Y = U S U^H (Jacobi), Y <- Y U S^-1/2;
-//   3. Rayleigh-Ritz: H = X^H A X = W T W^H (Jacobi), X <- X W, Ritz values
+//   2. orthonormalise Y twice (Cholesky-QR): G = Y^H Y = R^H R, Y <- Y R^-1
+//      (chol_inverse: blocked, directions lost to rounding dropped);
+//   3. Rayleigh-Ritz: H = X^H A X = W T W^H (Jacobi, to 1e-3 of the previous
+//      iteration's largest residual, at least 1e-15), X <- X W, Ritz values
 //      in decreasing order;
 //   4. residuals r_j = |A x_j - t_j x_j| / b for the n_eig kept pairs.
 // It stops when every kept residual is below tol.  b is the largest absolute
@@ -82,19 +84,6 @@ __global__ __launch_bounds__(256) void row_abs_sum_kernel(const double2* __restr
     if (threadIdx.x == 0) out[i] = s[0] * (w ? fabs(w[i]) : 1.0);
 }
 
-// d[j] = 1/sqrt(g_jj) for g_jj above thr, else 0 (a direction lost to rounding
-// is dropped rather than blown up); v[:, j] *= d[j].
-__global__ __launch_bounds__(256) void inv_sqrt_scale_kernel(const double2* __restrict__ g,
-                                                             double2* __restrict__ v, int n,
-                                                             double thr) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= static_cast<int64_t>(n) * n) return;
-    const int j = static_cast<int>(t % n);
-    const double gjj = g[static_cast<int64_t>(j) * n + j].x;
-    const double d = gjj > thr ? 1.0 / sqrt(gjj) : 0.0;
-    v[t] = make_double2(v[t].x * d, v[t].y * d);
-}
-
 // out[:, j] = in[:, perm[j]] for an [rows][n] block.
 __global__ __launch_bounds__(256) void gather_cols_kernel(const double2* __restrict__ in,
                                                           double2* __restrict__ out, int rows,
@@ -154,6 +143,7 @@ struct DiagLayout {
     size_t big[4] = {0, 0, 0, 0};      // [ng][nb] blocks
     size_t wx = 0;                     // [ng][nb]: W x (weighted only)
     size_t g = 0, u = 0, w = 0, jw = 0;  // [nb][nb]: Gram / Ritz matrix, vectors, sorted vectors
+    size_t cw = 0;                       // Cholesky work
     size_t vec = 0;                    // [ng] doubles (row sums), [nb] doubles (residuals)
     size_t theta = 0, perm = 0;
     size_t total = 0;
@@ -171,6 +161,7 @@ DiagLayout diag_layout(int ng, int n_eig, int guard, bool weighted) {
     L.u = cv.take(sm);
     L.w = cv.take(sm);
     L.jw = cv.take(jacobi_work_bytes(L.nb, 1));
+    L.cw = cv.take(chol_work_bytes(L.nb));
     L.vec = cv.take(static_cast<size_t>(std::max(ng, L.nb)) * sizeof(double));
     L.theta = cv.take(static_cast<size_t>(L.nb) * sizeof(double));
     L.perm = cv.take(static_cast<size_t>(L.nb) * sizeof(int));
@@ -205,6 +196,7 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
     double2* u = reinterpret_cast<double2*>(base + L.u);
     double2* w = reinterpret_cast<double2*>(base + L.w);
     void* jw = base + L.jw;
+    void* cwk = base + L.cw;
     double* vec = reinterpret_cast<double*>(base + L.vec);
     double* theta = reinterpret_cast<double*>(base + L.theta);
     int* perm_d = reinterpret_cast<int*>(base + L.perm);
@@ -245,20 +237,13 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
                                     sizeof(double2), nb, hipMemcpyDeviceToHost, s));
         GW_HIP_TRY(hipStreamSynchronize(s));
     };
-    // orthonormalise y into z, two passes through the Gram matrix (tmp: scratch)
+    // orthonormalise y into z: two passes of Cholesky-QR (tmp: scratch)
     auto orth = [&](const double2* y, double2* z, double2* tmp) {
         const double2* src = y;
         for (int pass = 0; pass < 2; ++pass) {
             double2* dst = pass == 0 ? tmp : z;
             gemm(kOpC, kOpN, nb, nb, ng, one, src, nb, src, nb, g, nb);
-            (void)jacobi_eigh(g, u, nb, 1, 1e-15, 60, jw, s);
-            read_diag(g);
-            double gmax = 0.0;
-            for (const auto& x : dg) gmax = std::max(gmax, x.x);
-            // a direction whose Gram eigenvalue is lost in rounding is dropped
-            hipLaunchKernelGGL(inv_sqrt_scale_kernel, dim3(static_cast<unsigned>(ceil_div64(nn, 256))),
-                               dim3(256), 0, s, g, u, nb, 1e-26 * gmax);
-            GW_HIP_TRY(hipGetLastError());
+            chol_inverse(g, u, nb, cwk, s);
             gemm(kOpN, kOpN, ng, nb, nb, one, src, nb, u, nb, dst, nb);
             src = dst;
         }
@@ -337,7 +322,8 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
         const int ti = spare(0), yi = spare(1), ai = spare(2);
         apply_a(pool[xi], pool[ti], 1.0);
         gemm(kOpC, kOpN, nb, nb, ng, one, pool[xi], nb, pool[ti], nb, g, nb);
-        (void)jacobi_eigh(g, u, nb, 1, 1e-15, 60, jw, s);
+        const double rr_tol = it == 0 ? 1e-6 : std::max(1e-15, std::min(1e-6, 1e-3 * res.residual));
+        res.sweeps += jacobi_eigh(g, u, nb, 1, rr_tol, 60, jw, s);
         read_diag(g);
         std::iota(perm.begin(), perm.end(), 0);
         std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return dg[a].x > dg[b].x; });

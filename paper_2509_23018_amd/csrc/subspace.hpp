@@ -22,6 +22,7 @@ struct DiagResult {
     int degree = 0;         // filter degree of the last iteration
     double residual = 0.0;  // largest relative residual of the kept pairs
     double bound = 0.0;     // Gershgorin bound of |chi|
+    int sweeps = 0;         // Jacobi sweeps of the Rayleigh-Ritz steps, in all
 };
 
 // Device scratch of run_subspace_basis (guard 0 = the default; weighted: with a
