@@ -348,7 +348,8 @@ def bench_chi0_72cube(args):
     full = {"fp64": {"s_per_build": round(t64, 3), "tflops": round(flops_build / t64 / 1e12, 3),
                      "pairs_per_s": round(nv * nc / t64, 1), "kernel_ms_per_step": ks64}}
     _log(t_start, f"whole FP64 build {t64:.2f} s")
-    modes = [("fp32", 0)] + [("split_bf16", S) for S in args.split_slices]
+    modes = ([("fp32", 0)] + [("split_bf16", S) for S in args.split_slices] +
+             [("split_fp16x9", 4)])
     for prec, ns in modes:
         dt, got, ks = build(prec, ns)
         err = float(torch.linalg.vector_norm(got - ref_rows) / torch.linalg.vector_norm(ref_rows))
@@ -392,6 +393,9 @@ def bench_chi0_72cube(args):
     ok = [v for k, v in full.items() if k.startswith("split_bf16") and
           cpu["errors"][k]["rel_err_32rows"] <= 1e-10 and v["rel_err_vs_device_fp64_32rows"] <= 1e-10]
     out["split_bf16_at_1e-10"] = min(ok, key=lambda x: x["n_slices"]) if ok else None
+    ok = [v for k, v in full.items() if k.startswith("split_fp16x9") and
+          cpu["errors"][k]["rel_err_32rows"] <= 1e-10 and v["rel_err_vs_device_fp64_32rows"] <= 1e-10]
+    out["split_fp16x9_at_1e-10"] = min(ok, key=lambda x: x["n_slices"]) if ok else None
     _log(t_start, "done")
     gw.release()
     print(json.dumps(out), flush=True)

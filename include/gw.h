@@ -100,7 +100,9 @@ enum {
     GW_FP64       = 0,      /* FP64 MFMA */
     GW_FP32       = 1,      /* operands rounded to FP32, FP32 products */
     GW_SPLIT_BF16 = 2,      /* fixed-point slices in BF16, FP32 accumulation */
-    GW_SPLIT_FP16 = 3       /* fixed-point slices in FP16, FP32 accumulation */
+    GW_SPLIT_FP16 = 3,      /* fixed-point slices in FP16, FP32 accumulation */
+    GW_SPLIT_FP16X9 = 4     /* fixed-point 9-bit slices in FP16 (2 to 4 slices), FP32
+                               accumulation exact over blocks of 32 pairs */
 };
 
 /* gw_opts_t.flags */

@@ -24,6 +24,7 @@ import torch  # noqa: F401  (loads the HIP runtime that libgw binds to)
 
 __all__ = [
     "GWError", "lib", "library_path", "GW_FP64", "GW_FP32", "GW_SPLIT_BF16", "GW_SPLIT_FP16",
+    "GW_SPLIT_FP16X9",
     "GW_FLAG_NO_HERMITIAN", "GW_FLAG_ACCUMULATE", "GW_FLAG_GRAPH", "GW_FLAG_AUTOTUNE",
     "GW_FLAG_FP64_TILE128", "GW_FLAG_ACC_HERMITIAN",
     "Chi0Problem", "gw_mtxel", "gw_chi0", "gw_chi0_fixed", "workspace_bytes", "new_workspace",
@@ -35,7 +36,7 @@ __all__ = [
     "profile_read",
 ]
 
-GW_FP64, GW_FP32, GW_SPLIT_BF16, GW_SPLIT_FP16 = 0, 1, 2, 3
+GW_FP64, GW_FP32, GW_SPLIT_BF16, GW_SPLIT_FP16, GW_SPLIT_FP16X9 = 0, 1, 2, 3, 4
 GW_FLAG_NO_HERMITIAN = 1 << 0
 GW_FLAG_ACCUMULATE = 1 << 1
 GW_FLAG_GRAPH = 1 << 2
@@ -43,7 +44,7 @@ GW_FLAG_AUTOTUNE = 1 << 3
 GW_FLAG_FP64_TILE128 = 1 << 4
 GW_FLAG_ACC_HERMITIAN = 1 << 5
 PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "split_bf16": GW_SPLIT_BF16,
-              "split_fp16": GW_SPLIT_FP16}
+              "split_fp16": GW_SPLIT_FP16, "split_fp16x9": GW_SPLIT_FP16X9}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libgw.so")

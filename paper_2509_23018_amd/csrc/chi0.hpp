@@ -60,24 +60,24 @@ void launch_chi0_f64_batched(const QDesc* qd, const int4* items, int nitems, int
                              hipStream_t s, int variant, int grid);
 
 // Reduced-precision contractions (same semantics as launch_chi0_f64).
-// prec 2 = split BF16, 3 = split FP16 with S slices; scratch holds
-// split_scratch_bytes(kc, ng, nz, S) bytes.
+// prec 2 = split BF16, 3 = split FP16, 4 = split FP16 with 9-bit slices, with
+// S slices; scratch holds split_scratch_bytes(kc, ng, nz, S) bytes.
 size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S);
 void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        const double2* delta, int nz, const WList& wl, double2* chi,
                        bool accumulate, void* scratch, hipStream_t s,
-                       double2* tail_ws = nullptr);  // split BF16 only (launch_chi0_sbf16)
+                       double2* tail_ws = nullptr);  // precisions 2 and 4 (launch_chi0_sbf16)
 void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta, const WList& wl,
                      double2* chi, bool accumulate, hipStream_t s);
 constexpr int kSplitTile = 64;  // tile edge of the FP16-split and FP32 kernels
-// Split BF16 on the 32x32 MFMA (grouped shifts, 128 x 64 workgroup tiles; the
-// Hermitian rule and mirror use 128-wide square blocks); same scratch layout
-// size as launch_chi0_split.
+// Split BF16 (f16: split FP16 with 9-bit slices) on the 32x32 MFMA (grouped
+// shifts, 128 x 64 workgroup tiles; the Hermitian rule and mirror use
+// 128-wide square blocks); same scratch layout size as launch_chi0_split.
 // With tail_ws (device, sbf16_tail_bytes() bytes) a last partial round of
-// tiles is cut along the 128-pair blocks and reduced by a second launch.
+// tiles is cut along the exponent blocks and reduced by a second launch.
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
-                       hipStream_t s, double2* tail_ws = nullptr);
+                       hipStream_t s, double2* tail_ws = nullptr, bool f16 = false);
 size_t sbf16_tail_bytes();  // for the current device
 // Operands of one problem's chunk for the split-BF16 contraction (device
 // pointers into scratch; frequency w's B slices and sigma follow at fixed
@@ -91,14 +91,14 @@ struct SbDesc {
     int ng, ngp, nkb, mode;
 };
 // Bytes of that layout for a chunk of kc pairs (split_scratch_bytes covers it).
-size_t sbf16_scratch_bytes(int64_t kc, int ng, int nz, int S);
+size_t sbf16_scratch_bytes(int64_t kc, int ng, int nz, int S, bool f16 = false);
 // Descriptor of the slices of a chunk of kc pairs laid out in scratch (chi and
 // mode unset); the layout launch_sbf16_prep writes.
-SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch);
+SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch, bool f16 = false);
 // Slices of one chunk for the frequencies of wl (scratch as for
 // launch_chi0_split); returns the descriptor with chi and mode unset.
 SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const double2* delta,
-                         int nz, const WList& wl, void* scratch, hipStream_t s);
+                         int nz, const WList& wl, void* scratch, hipStream_t s, bool f16 = false);
 // Persistent split-BF16 contraction over items (problem, frequency, 128-row
 // block, 64-column block); counter must be 0 on entry.
 void launch_chi0_sbf16_batched(int S, const SbDesc* qd, const int4* items, int nitems,
@@ -106,7 +106,7 @@ void launch_chi0_sbf16_batched(int S, const SbDesc* qd, const int4* items, int n
 constexpr int kSbTileI = 128, kSbTileJ = 64;  // split-BF16 workgroup tile
 
 // Tile edge whose on-or-above-diagonal blocks a reduced-precision mode computes.
-inline int split_tile(int prec) { return prec == 2 ? 128 : kSplitTile; }
+inline int split_tile(int prec) { return prec == 2 || prec == 4 ? 128 : kSplitTile; }
 
 // Fill the tiles strictly below the diagonal (tile x tile blocks) from the
 // conjugate transpose.

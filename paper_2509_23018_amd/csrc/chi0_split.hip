@@ -445,7 +445,8 @@ size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S) {
     const int64_t nkb = (kmax + kBlk - 1) / kBlk;
     const size_t per = static_cast<size_t>(nkb) * S * 2 * ng * kBlk * 2 + 256;
     const size_t sig = static_cast<size_t>(nkb) * ng * sizeof(double) + 256;
-    return std::max((per + sig) * static_cast<size_t>(1 + nz), sbf16_scratch_bytes(kmax, ng, nz, S));
+    return std::max({(per + sig) * static_cast<size_t>(1 + nz), sbf16_scratch_bytes(kmax, ng, nz, S),
+                     sbf16_scratch_bytes(kmax, ng, nz, S, true)});
 }
 
 void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
@@ -453,8 +454,9 @@ void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        bool accumulate, void* scratch, hipStream_t s, double2* tail_ws) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
-    if (prec == 2) {
-        launch_chi0_sbf16(S, m, kc, ng, delta, nz, wl, chi, accumulate, scratch, s, tail_ws);
+    if (prec == 2 || prec == 4) {
+        launch_chi0_sbf16(S, m, kc, ng, delta, nz, wl, chi, accumulate, scratch, s, tail_ws,
+                          prec == 4);
         return;
     }
     const int nkb = static_cast<int>((kc + kBlk - 1) / kBlk);

@@ -40,36 +40,87 @@ namespace gw {
 
 namespace {
 
-constexpr int kBlkB = 128;                   // pairs per exponent block
 constexpr int kStep = 8;                     // pairs per MFMA k-step (K = 16)
-constexpr int kStepsPerBlk = kBlkB / kStep;  // 16
 constexpr int kTI = 128, kTJ = 64;           // workgroup tile: rows G, columns G'
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Slice formats.
+// SlBf16: 8-bit slices, x 2^(8-e) = q_0 + q_1 2^-8 + ... (|q_0| <= 256,
+//   |q_s| <= 128), slice s stored as the BF16 value q_s 2^-8s; over blocks of
+//   KB = 128 pairs the t = 0 and t = 1 sums stay exact in FP32 (above).
+// SlF16x9: 9-bit slices, x 2^(9-e) = q_0 + q_1 2^-9 + ... (|q_0| <= 512,
+//   |q_s| <= 256), slice s stored as the FP16 value q_s 2^(6-9s): at most 11
+//   significant bits, and for s <= 3 within FP16's range (the fourth slice as
+//   an exact subnormal, a multiple of 2^-21), so at most four slices.  A
+//   product q_0 q_0' 2^12 reaches 2^30: over KB = 32 pairs (64 real products
+//   per component) the t = 0 sum is a multiple of 2^12 below 2^36 and the
+//   t = 1 sum (128 products) a multiple of 2^3 below 2^27, both exact in FP32;
+//   t >= 2 is below 2^-18 of the result.  sigma = 2^(e - 9 - 6).
+// The last slice of four is 2^-35 of the block maximum for FP16 against 2^-32
+// for BF16; with the same ten products (t <= 3) the error drops about 20x.
+struct SlBf16 {
+    static constexpr int KB = 128, BITS = 8, SHIFT = 0, SMAX = 6;
+    static __device__ __forceinline__ uint32_t enc(double q, int sl) {
+        // q 2^(-8 sl) has at most 8 significant bits: the top half of its FP32
+        // bits is its exact BF16 encoding
+        return __float_as_uint(ldexpf(static_cast<float>(q), -8 * sl)) >> 16;
+    }
+    static __device__ __forceinline__ f32x16 mfma(u32x4 a, u32x4 b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+};
+struct SlF16x9 {
+    static constexpr int KB = 32, BITS = 9, SHIFT = 6, SMAX = 4;
+    static __device__ __forceinline__ uint32_t enc(double q, int sl) {
+        const _Float16 h = static_cast<_Float16>(ldexpf(static_cast<float>(q), SHIFT - 9 * sl));
+        return __builtin_bit_cast(uint16_t, h);
+    }
+    static __device__ __forceinline__ f32x16 mfma(u32x4 a, u32x4 b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+};
+template <class F>
+constexpr int ksteps() {  // k-steps per exponent block
+    return F::KB / kStep;
+}
+
 // ---------------------------------------------------------------- slicing
 
-// One workgroup per (block of 128 pairs, 16 columns of G); thread (k-step
-// ks, column c) keeps the 8 pairs of its k-step in registers.  Output layout,
-// in 32-bit words (Re in the low half, Im in the high half, both BF16):
+// One workgroup per (block of KB pairs, prep_cols<F>() columns of G); thread
+// (k-step ks, column c) keeps the 8 pairs of its k-step in registers: a wave
+// holds 4 k-steps of 16 columns, and the KB / 32 waves of a block share one
+// set of columns.  Output layout, in 32-bit words (Re in the low half, Im in
+// the high half):
 //   slices[kb][ks][s][g][p]   p = pair within the k-step (0..7),
 // i.e. per (block, k-step, slice) a [ng][8]-word array: a 128-row panel of a
 // tile is one contiguous 4 KB run, and a thread writes its 8 pairs as one
-// 32-byte run.  sigma[kb][g] = 2^(e-8), rows padded to ngp (a multiple of
-// 128, which the grid covers) with 1.0 so that a tile's sigma panel is whole.
-constexpr int kPrepCols = 16;
+// 32-byte run.  sigma[kb][g] = 2^(e - BITS - SHIFT), rows padded to ngp (a
+// multiple of 128, which the grid covers) with 1.0 so that a tile's sigma
+// panel is whole.
+template <class F>
+constexpr int prep_cols() {
+    return 16 * (4 / (ksteps<F>() / 4));
+}
 
+template <class F>
 __global__ __launch_bounds__(256) void sbf16_prep_kernel(
     const double2* __restrict__ m, const double2* __restrict__ delta, int64_t kc, int ng, int ngp,
     int S, int nkb, WList wl, uint32_t* __restrict__ slices_a, double* __restrict__ sigma_a,
     uint32_t* __restrict__ slices_b, double* __restrict__ sigma_b) {
-    __shared__ double s_part[4][kPrepCols];  // per-wave column maxima
+    constexpr int WPB = ksteps<F>() / 4;  // waves per block of pairs
+    static_assert(WPB >= 1 && 4 % WPB == 0, "prep mapping");
+    __shared__ double s_part[4][16];      // per-wave column maxima
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int c = lane & (kPrepCols - 1), ks = wave * 4 + (lane >> 4);
-    const int g = blockIdx.x * kPrepCols + c, kb = blockIdx.y;
-    const int64_t k0 = static_cast<int64_t>(kb) * kBlkB + ks * kStep;
+    const int c = lane & 15, ks = (wave % WPB) * 4 + (lane >> 4);
+    const int cg = wave / WPB;  // column group of this wave
+    const int g = blockIdx.x * prep_cols<F>() + cg * 16 + c, kb = blockIdx.y;
+    const int64_t k0 = static_cast<int64_t>(kb) * F::KB + ks * kStep;
     const int kn = static_cast<int>(std::max<int64_t>(0, std::min<int64_t>(kStep, kc - k0)));
     const bool gv = g < ng;
     // lanes of one k-step read 16 consecutive G: 256-byte runs of a row of M
@@ -77,7 +128,7 @@ __global__ __launch_bounds__(256) void sbf16_prep_kernel(
 #pragma unroll
     for (int p = 0; p < kStep; ++p)
         x[p] = (gv && p < kn) ? m[(k0 + p) * ng + g] : make_double2(0.0, 0.0);
-    const size_t per_op = static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep;  // words
+    const size_t per_op = static_cast<size_t>(nkb) * ksteps<F>() * S * ng * kStep;  // words
     const int nop = 1 + wl.nh + wl.nf;
     for (int op = 0; op < nop; ++op) {
         double2 y[kStep];
@@ -93,16 +144,18 @@ __global__ __launch_bounds__(256) void sbf16_prep_kernel(
         double mx = 0.0;
 #pragma unroll
         for (int p = 0; p < kStep; ++p) mx = fmax(mx, fmax(fabs(y[p].x), fabs(y[p].y)));
-        // over the 4 k-steps of this wave (lanes c, c+16, c+32, c+48), then the 4 waves
+        // over the 4 k-steps of this wave (lanes c, c+16, c+32, c+48), then the
+        // WPB waves of the block
         mx = fmax(mx, __shfl_xor(mx, 16));
         mx = fmax(mx, __shfl_xor(mx, 32));
-        if (lane < kPrepCols) s_part[wave][c] = mx;
+        if (lane < 16) s_part[wave][c] = mx;
         __syncthreads();
-        mx = fmax(fmax(s_part[0][c], s_part[1][c]), fmax(s_part[2][c], s_part[3][c]));
+#pragma unroll
+        for (int w2 = 0; w2 < WPB; ++w2) mx = fmax(mx, s_part[cg * WPB + w2][c]);
         int e = 0;
         if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1): |x| < 2^e
-        if (tid < kPrepCols && g < ngp) {
-            const double sg = gv ? ldexp(1.0, e - 8) : 1.0;
+        if (wave % WPB == 0 && lane < 16 && g < ngp) {
+            const double sg = gv ? ldexp(1.0, e - F::BITS - F::SHIFT) : 1.0;
             if (op == 0)
                 sigma_a[static_cast<size_t>(kb) * ngp + g] = sg;
             else
@@ -112,24 +165,19 @@ __global__ __launch_bounds__(256) void sbf16_prep_kernel(
             double rr[kStep], ri[kStep];
 #pragma unroll
             for (int p = 0; p < kStep; ++p) {
-                rr[p] = ldexp(y[p].x, 8 - e);
-                ri[p] = ldexp(y[p].y, 8 - e);
+                rr[p] = ldexp(y[p].x, F::BITS - e);
+                ri[p] = ldexp(y[p].y, F::BITS - e);
             }
             uint32_t* out = op == 0 ? slices_a : slices_b + static_cast<size_t>(wl.w[op - 1]) * per_op;
-            uint32_t* o = out + ((static_cast<size_t>(kb) * kStepsPerBlk + ks) * S * ng + g) * kStep;
+            uint32_t* o = out + ((static_cast<size_t>(kb) * ksteps<F>() + ks) * S * ng + g) * kStep;
             for (int sl = 0; sl < S; ++sl) {
                 uint32_t word[kStep];
 #pragma unroll
                 for (int p = 0; p < kStep; ++p) {
                     const double qr = rint(rr[p]), qi = rint(ri[p]);
-                    // q 2^(-8 sl) has at most 8 significant bits: the top half of its FP32 bits
-                    // is its exact BF16 encoding
-                    const uint32_t br = __float_as_uint(ldexpf(static_cast<float>(qr), -8 * sl)) >> 16;
-                    const uint32_t bi =
-                        __float_as_uint(ldexpf(static_cast<float>(qi), -8 * sl)) & 0xffff0000u;
-                    word[p] = bi | br;
-                    rr[p] = (rr[p] - qr) * 256.0;
-                    ri[p] = (ri[p] - qi) * 256.0;
+                    word[p] = (F::enc(qi, sl) << 16) | F::enc(qr, sl);
+                    rr[p] = ldexp(rr[p] - qr, F::BITS);
+                    ri[p] = ldexp(ri[p] - qi, F::BITS);
                 }
                 u32x4* dst = reinterpret_cast<u32x4*>(o + static_cast<size_t>(sl) * ng * kStep);
                 dst[0] = u32x4{word[0], word[1], word[2], word[3]};
@@ -168,10 +216,6 @@ __device__ __forceinline__ void rect_item_tile(int t, const WList& wl, int nb,
     bj = 2 * (code & 0xffff) + half;
 }
 
-__device__ __forceinline__ f32x16 mfma32(u32x4 a, u32x4 b, f32x16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-}
 
 // (Re, Im) -> (Im, -Re) in every 32-bit word of a fragment.
 __device__ __forceinline__ u32x4 swap_neg(u32x4 v) {
@@ -237,7 +281,7 @@ struct SbGeom {
 // sb and sigb are that frequency's B slices and sigma.  The caller has made
 // sure every wave of the workgroup calls this with the same arguments and
 // that no earlier reader of lds is still running.
-template <int S, int NWI, int NWJ, int BI, int BJ, bool PART = false>
+template <class F, int S, int NWI, int NWJ, int BI, int BJ, bool PART = false>
 __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                                            const double* __restrict__ siga,
                                            const u32x4* __restrict__ sb,
@@ -251,6 +295,7 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
     constexpr int CA = Geo::CA, CB = Geo::CB, CSA = Geo::CSA, CSB = Geo::CSB, NCH = Geo::NCH;
     constexpr int NLD = Geo::NLD, NCHP = Geo::NCHP, kStages = Geo::kStages;
     constexpr int KSUB = Geo::KSUB, NSLOT = Geo::NSLOT;
+    constexpr int kStepsPerBlk = ksteps<F>();
     static_assert(kStepsPerBlk % KSUB == 0, "stages within a block");
     const int i0 = bi * kTI, j0 = bj * kTJ;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -379,8 +424,8 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                     const bool fresh = decltype(first)::value && b == 0 && a == g;
 #pragma unroll
                     for (int x = 0; x < BI; ++x) {
-                        accR[g][x][y] = mfma32(fa.v[a][x], fb, fresh ? zero16 : accR[g][x][y]);
-                        accI[g][x][y] = mfma32(fa.v[a][x], fbi, fresh ? zero16 : accI[g][x][y]);
+                        accR[g][x][y] = F::mfma(fa.v[a][x], fb, fresh ? zero16 : accR[g][x][y]);
+                        accI[g][x][y] = F::mfma(fa.v[a][x], fbi, fresh ? zero16 : accI[g][x][y]);
                     }
                 }
             }
@@ -522,7 +567,7 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
 // cut into `parts` ranges of 128-pair blocks: workgroup n_main + j*parts + p
 // writes item n_main + j's partial sum over range p to ws[j*parts + p]
 // (kTI x kTJ), and sbf16_tail_reduce_kernel adds the parts into chi.
-template <int S, int NWI, int NWJ, int BI, int BJ>
+template <class F, int S, int NWI, int NWJ, int BI, int BJ>
 __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     const u32x4* __restrict__ sa, const double* __restrict__ siga, const u32x4* __restrict__ sb_all,
     const double* __restrict__ sigb_all, int ng, int ngp, int nkb, WList wl,
@@ -530,13 +575,13 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     int parts, double2* __restrict__ ws) {
     extern __shared__ u32x4 lds[];
     const int b = blockIdx.x;
-    const size_t blk = static_cast<size_t>(kStepsPerBlk) * S * ng * 2;  // chunks per block
+    const size_t blk = static_cast<size_t>(ksteps<F>()) * S * ng * 2;  // chunks per block
     const size_t plane = static_cast<size_t>(nkb) * blk;
     int w, bi, bj;
     if (b < n_main) {
         rect_item_tile(xcd_item(b, n_main), wl, nb, order, w, bi, bj);
         if (bj * kTJ >= ng) return;  // right half of the last block column lies past N_G
-        sbf16_tile<S, NWI, NWJ, BI, BJ>(sa, siga, sb_all + w * plane,
+        sbf16_tile<F, S, NWI, NWJ, BI, BJ>(sa, siga, sb_all + w * plane,
                                         sigb_all + static_cast<size_t>(w) * nkb * ngp, ng, ngp,
                                         nkb, chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj,
                                         lds);
@@ -546,7 +591,7 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     rect_item_tile(n_main + j, wl, nb, order, w, bi, bj);
     if (bj * kTJ >= ng) return;  // nothing of it is ever read
     const int kb0 = p * nkb / parts, kb1 = (p + 1) * nkb / parts;
-    sbf16_tile<S, NWI, NWJ, BI, BJ, true>(
+    sbf16_tile<F, S, NWI, NWJ, BI, BJ, true>(
         sa + kb0 * blk, siga + static_cast<size_t>(kb0) * ngp, sb_all + w * plane + kb0 * blk,
         sigb_all + (static_cast<size_t>(w) * nkb + kb0) * ngp, ng, ngp, kb1 - kb0,
         ws + static_cast<int64_t>(u) * kTI * kTJ, 0, bi, bj, lds);
@@ -595,8 +640,8 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
         const int4 t = items[it];
         const SbDesc d = qd[t.x];
         if (t.w * kTJ >= d.ng) continue;
-        const size_t plane = static_cast<size_t>(d.nkb) * kStepsPerBlk * S * d.ng * 2;
-        sbf16_tile<S, NWI, NWJ, BI, BJ>(
+        const size_t plane = static_cast<size_t>(d.nkb) * ksteps<SlBf16>() * S * d.ng * 2;
+        sbf16_tile<SlBf16, S, NWI, NWJ, BI, BJ>(
             reinterpret_cast<const u32x4*>(d.sa), d.siga,
             reinterpret_cast<const u32x4*>(d.sb) + t.y * plane,
             d.sigb + static_cast<size_t>(t.y) * d.nkb * d.ngp, d.ng, d.ngp, d.nkb,
@@ -604,13 +649,13 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
     }
 }
 
-template <int S, int NWI, int NWJ, int BI, int BJ>
+template <class F, int S, int NWI, int NWJ, int BI, int BJ>
 void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
                     const double* sigb, int ng, int ngp, int nkb, const WList& wl, double2* chi,
                     bool accumulate, int nb, int n_main, int parts, double2* ws, int grid,
                     hipStream_t s) {
     const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
-    auto fn = chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>;
+    auto fn = chi0_sbf16_kernel<F, S, NWI, NWJ, BI, BJ>;
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
@@ -624,7 +669,7 @@ void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
 template <int S, int NWI, int NWJ, int BI, int BJ>
 int sbf16_per_cu_t() {
     const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
-    const void* fn = reinterpret_cast<const void*>(chi0_sbf16_kernel<S, NWI, NWJ, BI, BJ>);
+    const void* fn = reinterpret_cast<const void*>(chi0_sbf16_kernel<SlBf16, S, NWI, NWJ, BI, BJ>);
     GW_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
     int n = 0;
@@ -657,21 +702,23 @@ int sbf16_slots(int S) {
 }  // namespace
 
 // Bytes of the layout sbf16_desc describes: A slices, A sigma, nz B slices,
-// nz B sigma, each rounded up to 256 B.
-size_t sbf16_scratch_bytes(int64_t kc, int ng, int nz, int S) {
-    const int64_t nkb = (kc + kBlkB - 1) / kBlkB;
+// nz B sigma, each rounded up to 256 B (f16: the FP16 9-bit format).
+size_t sbf16_scratch_bytes(int64_t kc, int ng, int nz, int S, bool f16) {
+    const int kbp = f16 ? SlF16x9::KB : SlBf16::KB;
+    const int64_t nkb = (kc + kbp - 1) / kbp;
     const int ngp = ceil_div(ng, kTI) * kTI;
-    const size_t per_b = (static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep * 4 + 255) &
+    const size_t per_b = (static_cast<size_t>(nkb) * (kbp / kStep) * S * ng * kStep * 4 + 255) &
                          ~static_cast<size_t>(255);
     const size_t sig_b =
         (static_cast<size_t>(nkb) * ngp * sizeof(double) + 255) & ~static_cast<size_t>(255);
     return (per_b + sig_b) * static_cast<size_t>(1 + nz);
 }
 
-SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch) {
-    const int nkb = static_cast<int>((kc + kBlkB - 1) / kBlkB);
+SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch, bool f16) {
+    const int kbp = f16 ? SlF16x9::KB : SlBf16::KB;
+    const int nkb = static_cast<int>((kc + kbp - 1) / kbp);
     const int ngp = ceil_div(ng, kTI) * kTI;
-    const size_t per_b = (static_cast<size_t>(nkb) * kStepsPerBlk * S * ng * kStep * 4 + 255) &
+    const size_t per_b = (static_cast<size_t>(nkb) * (kbp / kStep) * S * ng * kStep * 4 + 255) &
                          ~static_cast<size_t>(255);
     const size_t sig_b =
         (static_cast<size_t>(nkb) * ngp * sizeof(double) + 255) & ~static_cast<size_t>(255);
@@ -688,13 +735,20 @@ SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch) {
 }
 
 SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const double2* delta,
-                         int nz, const WList& wl, void* scratch, hipStream_t s) {
-    const SbDesc d = sbf16_desc(S, kc, ng, nz, scratch);
+                         int nz, const WList& wl, void* scratch, hipStream_t s, bool f16) {
+    const SbDesc d = sbf16_desc(S, kc, ng, nz, scratch, f16);
     ProfScope ps("split_prep", s);
-    hipLaunchKernelGGL(sbf16_prep_kernel, dim3(d.ngp / kPrepCols, d.nkb), dim3(256), 0, s, m, delta,
-                       kc, ng, d.ngp, S, d.nkb, wl, const_cast<uint32_t*>(d.sa),
-                       const_cast<double*>(d.siga), const_cast<uint32_t*>(d.sb),
-                       const_cast<double*>(d.sigb));
+    auto run = [&](auto fmt) {
+        using F = decltype(fmt);
+        hipLaunchKernelGGL(sbf16_prep_kernel<F>, dim3(d.ngp / prep_cols<F>(), d.nkb), dim3(256), 0,
+                           s, m, delta, kc, ng, d.ngp, S, d.nkb, wl, const_cast<uint32_t*>(d.sa),
+                           const_cast<double*>(d.siga), const_cast<uint32_t*>(d.sb),
+                           const_cast<double*>(d.sigb));
+    };
+    if (f16)
+        run(SlF16x9{});
+    else
+        run(SlBf16{});
     GW_HIP_TRY(hipGetLastError());
     return d;
 }
@@ -707,10 +761,11 @@ size_t sbf16_tail_bytes() {
 
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
-                       hipStream_t s, double2* tail_ws) {
+                       hipStream_t s, double2* tail_ws, bool f16) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
-    if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
-    const SbDesc d = launch_sbf16_prep(S, m, kc, ng, delta, nz, wl, scratch, s);
+    if (S < 2 || S > (f16 ? SlF16x9::SMAX : SlBf16::SMAX))
+        throw Error{-4, f16 ? "split FP16 supports 2..4 slices" : "split BF16 supports 2..6 slices"};
+    const SbDesc d = launch_sbf16_prep(S, m, kc, ng, delta, nz, wl, scratch, s, f16);
     const int nb = ceil_div(ng, kTI);
     const int64_t nitems = 2 * (static_cast<int64_t>(wl.nh) * (nb * (nb + 1) / 2) +
                                 static_cast<int64_t>(wl.nf) * nb * nb);
@@ -731,18 +786,34 @@ void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double
     const int grid = n_main + n_tail * parts;
     {
         ProfScope ps("chi0_split", s);
-        switch (S) {
-#define GW_SB_LAUNCH(SS)                                                                      \
-    case SS:                                                                                  \
-        launch_sbf16_t<SS, 4, 2, 1, 1>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, \
-                                       accumulate, nb, n_main, parts, tail_ws, grid, s);      \
+        if (f16) {
+            switch (S) {
+#define GW_SF_LAUNCH(SS)                                                                          \
+    case SS:                                                                                      \
+        launch_sbf16_t<SlF16x9, SS, 4, 2, 1, 1>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, \
+                                                chi, accumulate, nb, n_main, parts, tail_ws, grid, \
+                                                s);                                                \
         break;
-            GW_SB_LAUNCH(2)
-            GW_SB_LAUNCH(3)
-            GW_SB_LAUNCH(4)
-            GW_SB_LAUNCH(5)
-            GW_SB_LAUNCH(6)
+                GW_SF_LAUNCH(2)
+                GW_SF_LAUNCH(3)
+                GW_SF_LAUNCH(4)
+#undef GW_SF_LAUNCH
+            }
+        } else {
+            switch (S) {
+#define GW_SB_LAUNCH(SS)                                                                         \
+    case SS:                                                                                     \
+        launch_sbf16_t<SlBf16, SS, 4, 2, 1, 1>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, \
+                                               chi, accumulate, nb, n_main, parts, tail_ws, grid, \
+                                               s);                                                \
+        break;
+                GW_SB_LAUNCH(2)
+                GW_SB_LAUNCH(3)
+                GW_SB_LAUNCH(4)
+                GW_SB_LAUNCH(5)
+                GW_SB_LAUNCH(6)
 #undef GW_SB_LAUNCH
+            }
         }
         GW_HIP_TRY(hipGetLastError());
     }

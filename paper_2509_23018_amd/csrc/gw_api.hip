@@ -203,6 +203,11 @@ struct Opts {
     size_t ws_bytes = 0;
 };
 
+// Split precisions: fixed-point slices, FP32 accumulation.
+bool is_split(int p) { return p == GW_SPLIT_BF16 || p == GW_SPLIT_FP16 || p == GW_SPLIT_FP16X9; }
+// Split precisions contracted by the 32x32 grouped kernel (128 x 64 tiles).
+bool sliced_32x32(int p) { return p == GW_SPLIT_BF16 || p == GW_SPLIT_FP16X9; }
+
 Opts read_opts(const gw_opts_t* o) {
     Opts r;
     if (!o) return r;
@@ -217,10 +222,9 @@ Opts read_opts(const gw_opts_t* o) {
         fail(GW_EINVAL, "workspace must be 256-byte aligned");
     if (r.pair_chunk < 1) fail(GW_EINVAL, "pair_chunk must be >= 1 (or 0 for the default)");
     if (!std::isfinite(r.spin)) fail(GW_EINVAL, "spin must be finite");
-    if (r.precision < GW_FP64 || r.precision > GW_SPLIT_FP16)
+    if (r.precision < GW_FP64 || r.precision > GW_SPLIT_FP16X9)
         fail(GW_EINVAL, "unknown precision " + std::to_string(r.precision));
-    if ((r.precision == GW_SPLIT_BF16 || r.precision == GW_SPLIT_FP16) &&
-        (r.n_slices < 2 || r.n_slices > 8))
+    if (is_split(r.precision) && (r.n_slices < 2 || r.n_slices > 8))
         fail(GW_EINVAL, "n_slices must be in [2, 8] for split precision");
     if (r.flags & ~(GW_FLAG_NO_HERMITIAN | GW_FLAG_ACCUMULATE | GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE |
                     GW_FLAG_FP64_TILE128 | GW_FLAG_ACC_HERMITIAN))
@@ -228,6 +232,14 @@ Opts read_opts(const gw_opts_t* o) {
     if ((r.flags & GW_FLAG_ACC_HERMITIAN) && !(r.flags & GW_FLAG_ACCUMULATE))
         fail(GW_EINVAL, "GW_FLAG_ACC_HERMITIAN needs GW_FLAG_ACCUMULATE");
     return r;
+}
+
+// Slice counts this build implements (read_opts has checked [2, 8]).
+void check_slices(const Opts& o) {
+    if (o.precision == GW_SPLIT_FP16X9 && o.n_slices > 4)
+        fail(GW_EUNSUPPORTED, "9-bit FP16 slices: at most 4 (a fifth leaves FP16's range)");
+    if (is_split(o.precision) && o.n_slices > 6)
+        fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
 }
 
 void check_problem(const gw_problem_t& p, int idx) {
@@ -485,12 +497,12 @@ Chi0Layout chi0_layout(const gw_problem_t& pr, const Opts& o, const MtxelPlan& p
     L.off_mfull = cv.take(n_eig > 0 ? L.kmax * pr.ng * sizeof(double2) : 0);
     L.off_wbasis = cv.take(n_eig > 0 ? static_cast<size_t>(pr.ng) * n_eig * sizeof(double2) : 0);
     L.off_t2 = cv.take(t2_elems(plan, L.kmax) * sizeof(double2));
-    const bool split = o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16;
+    const bool split = is_split(o.precision);
     L.off_sp = cv.take(split ? split_scratch_bytes(L.kmax, L.ncols, pr.nz, o.n_slices) : 0);
     L.off_tune = cv.take(tune_candidate(o) ? nw * nw * sizeof(double2) : 0);
     L.off_tail = cv.take(!tail                          ? 0
                          : o.precision == GW_FP64        ? chi0_f64_tail_bytes()
-                         : o.precision == GW_SPLIT_BF16 ? sbf16_tail_bytes()
+                         : sliced_32x32(o.precision)     ? sbf16_tail_bytes()
                                                         : 0);
     L.total = cv.off;
     return L;
@@ -524,7 +536,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
     double2* dbuf[2] = {reinterpret_cast<double2*>(base + L.off_d[0]),
                         reinterpret_cast<double2*>(base + L.off_d[1])};
     double2* t2 = reinterpret_cast<double2*>(base + L.off_t2);
-    double2* tail_ws = L.tail && (o.precision == GW_FP64 || o.precision == GW_SPLIT_BF16)
+    double2* tail_ws = L.tail && (o.precision == GW_FP64 || sliced_32x32(o.precision))
                            ? reinterpret_cast<double2*>(base + L.off_tail)
                            : nullptr;
     const std::vector<Chunk> chunks = make_chunks(pr, L.cs);
@@ -1192,8 +1204,7 @@ Opts check_chi0_args(const gw_problem_t* probs, int nprob, const gw_opts_t* opts
     if (nprob > 0 && !probs) fail(GW_EINVAL, "probs is NULL");
     const Opts o = read_opts(opts);
     for (int q = 0; q < nprob; ++q) check_problem(probs[q], q);
-    if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
-        fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+    check_slices(o);
     for (int q = 0; q < nprob; ++q) (void)get_plan(probs[q].grid.n, probs[q].gvec, probs[q].ng);
     return o;
 }
@@ -1487,7 +1498,7 @@ char* fixed_scratch() {
 // Throws in no-allocation mode when the tile-order table a contraction of
 // `ncols` columns would use does not exist yet.
 void require_tile_orders(const Opts& o, int ncols, int variant) {
-    if (o.precision == GW_SPLIT_BF16)
+    if (sliced_32x32(o.precision))
         (void)tile_order(ceil_div(ncols, kSbTileI), 4);
     else if (o.precision == GW_FP64)
         (void)tile_order(ceil_div(ncols, chi0_variant_tile(variant)));
@@ -1510,8 +1521,7 @@ gw_status_t gw_chi0_fixed(const gw_problem_t* prob, const gw_opts_t* opts, void*
         if (o.ws) fail(GW_EINVAL, "gw_chi0_fixed uses its fixed scratch: workspace must be NULL");
         if (o.flags & (GW_FLAG_GRAPH | GW_FLAG_AUTOTUNE))
             fail(GW_EINVAL, "GW_FLAG_GRAPH and GW_FLAG_AUTOTUNE allocate: not with gw_chi0_fixed");
-        if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
-            fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+        check_slices(o);
         hipStream_t s = static_cast<hipStream_t>(stream);
         char* base = fixed_scratch();  // once per device; no allocation
         NoAllocScope no_alloc;
@@ -1621,8 +1631,7 @@ gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis,
         if (n_eig < 1 || n_eig > prob->ng) fail(GW_EINVAL, "n_eig must lie in [1, ng]");
         if (!basis) fail(GW_EINVAL, "basis is NULL");
         if (o.flags & GW_FLAG_GRAPH) fail(GW_EUNSUPPORTED, "GW_FLAG_GRAPH is for batched gw_chi0");
-        if ((o.precision == GW_SPLIT_BF16 || o.precision == GW_SPLIT_FP16) && o.n_slices > 6)
-            fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+        check_slices(o);
         hipStream_t s = static_cast<hipStream_t>(stream);
         const PlanRef plan = get_plan(prob->grid.n, prob->gvec, prob->ng);
         const Chi0Layout L = chi0_layout(*prob, o, *plan, 2, true, n_eig);

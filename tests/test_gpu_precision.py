@@ -61,16 +61,19 @@ def _chunk_ranges(nv, nc, chunk):
     return out
 
 
-def split_bound(m, d, S, nv, nc, chunk, first_rounded=3, kb=KB, m_cols=None):
+def split_bound(m, d, S, nv, nc, chunk, first_rounded=3, kb=KB, m_cols=None, bits=8):
     """Elementwise bound on |chi_split - chi| for one frequency (d = s*Delta).
     Products with sa + sb >= first_rounded share FP32 accumulators that round
-    (BF16: t >= 2 in one group; FP16: one group per t, t >= 3 rounding).
+    (BF16 and 9-bit FP16: t >= 2 in one group; FP16: one group per t, t >= 3
+    rounding).  bits: slice width (8, or 9 for the 9-bit FP16 slices: the
+    residual after S slices is 2^(e - 9 S - 1) per component, slice s >= 1
+    at most 2^(e - 1 - 9 s)).
     m holds M at the rows' G; m_cols, if given, M at the columns' G (the
     bound of entry (i, j) depends only on columns i of m and j of m_cols)."""
     m_cols = m if m_cols is None else m_cols
     shape = (m.shape[1], m_cols.shape[1])
     bound = np.zeros(shape)
-    amp = lambda e, s: np.where(s == 0, 2.0 ** e, 2.0 ** (e - 1 - 8 * s))
+    amp = lambda e, s: np.where(s == 0, 2.0 ** e, 2.0 ** (e - 1 - bits * s))
     for idx in _chunk_ranges(nv, nc, chunk):
         a = m[idx]
         b = d[idx, None] * m_cols[idx]
@@ -79,8 +82,8 @@ def split_bound(m, d, S, nv, nc, chunk, first_rounded=3, kb=KB, m_cols=None):
             sl = slice(blk * kb, (blk + 1) * kb)
             aa, bb = np.abs(a[sl]), np.abs(b[sl])                         # [kb, ng]
             n = aa.shape[0]
-            eps_a = np.sqrt(2) * 2.0 ** (ea[blk] - 8 * S - 1)
-            eps_b = np.sqrt(2) * 2.0 ** (eb[blk] - 8 * S - 1)
+            eps_a = np.sqrt(2) * 2.0 ** (ea[blk] - bits * S - 1)
+            eps_b = np.sqrt(2) * 2.0 ** (eb[blk] - bits * S - 1)
             trunc = np.outer(aa.sum(0), eps_b) + np.outer(eps_a, bb.sum(0) + n * eps_b)
             dropped = np.zeros(shape)
             small = np.zeros(shape)
@@ -129,6 +132,32 @@ def test_split_error_within_bound_and_monotone(prec):
         # BF16 rounds the t >= 2 group in FP32 (about 2^-40 per product):
         # a floor near 2e-11 that extra slices do not lower
         assert errs[4] <= 1.05 * errs[3] and errs[4] <= 5e-11, errs
+
+
+def test_split_fp16x9_within_bound_and_monotone():
+    """FP16 slices of 9 bits over blocks of 32 pairs: every element within its
+    bound for 2 to 4 slices, the error falling with the slice count, 1e-10
+    reached at 4 slices (10 products, as BF16 at 4 slices, which stops near
+    1e-9), more than 4 slices refused."""
+    p = _problem((0.0, 0.4j, 0.35 + 0.005j))
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin, pair_chunk=p.pair_chunk)
+    m, d = _operands(p)
+    errs = []
+    for S in (2, 3, 4):
+        got = run_chi0(p, precision="split_fp16x9", n_slices=S)
+        errs.append(rel_fro(got, ref))
+        for w in range(len(p.z)):
+            bnd = split_bound(m, d[w], S, p.nv, p.nc, p.pair_chunk, first_rounded=2, kb=32, bits=9)
+            bnd = np.maximum(bnd, bnd.T)
+            excess = np.abs(got[w] - ref[w]) - bnd - 1e-15 * np.abs(ref[w]).max()
+            assert excess.max() <= 0, (S, w, excess.max())
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] <= 1e-10, errs
+    bf4 = rel_fro(run_chi0(p, precision="split_bf16", n_slices=4), ref)
+    assert errs[2] < 0.2 * bf4, (errs, bf4)
+    with pytest.raises(gw.GWError):
+        run_chi0(p, precision="split_fp16x9", n_slices=5)
 
 
 def test_fp32_path():
@@ -193,6 +222,8 @@ def test_split_edge_shapes():
                       spin=p.spin, pair_chunk=200)
     got = run_chi0(p, precision="split_fp16", n_slices=6)
     assert rel_fro(got, ref) < 1e-12
+    got = run_chi0(p, precision="split_fp16x9", n_slices=4)
+    assert rel_fro(got, ref) < 1e-10
 
 
 @pytest.mark.parametrize("S", [3, 4, 5])

@@ -7,9 +7,9 @@ Workload 2 has 256 x 3,840 bands on a 72^3 grid, 6,031 G (|g|^2 <= 126) and
 sphere, the frequencies and the chunk rectangle (4 valence x 1,024 conduction
 bands) and take 4 x 1,024 recipe bands: the 32 G rows drawn with
 default_rng(1002) against 32 sampled columns, from the oracle's direct sums
-(Eq. (4) on those entries).  FP64 must agree to 1e-12; FP32 and split BF16
-(3 and 5 slices) must stay inside the elementwise a-posteriori bound of their
-arithmetic on every sampled entry.
+(Eq. (4) on those entries).  FP64 must agree to 1e-12; FP32, split BF16 (3
+and 5 slices) and split FP16 with 9-bit slices (4 slices) must stay inside the
+elementwise a-posteriori bound of their arithmetic on every sampled entry.
 """
 import numpy as np
 import pytest
@@ -83,11 +83,13 @@ def _bound_both_ways(bound_fn):
 
 
 @pytest.mark.parametrize("chunk", [4096, 2048], ids=["rect4x1024", "chunk2048"])
-@pytest.mark.parametrize("prec,ns", [("fp32", 0), ("split_bf16", 3), ("split_bf16", 5)])
+@pytest.mark.parametrize("prec,ns", [("fp32", 0), ("split_bf16", 3), ("split_bf16", 5),
+                                     ("split_fp16x9", 4)])
 def test_workload2_reduced_precision_within_bound(prec, ns, chunk):
-    """FP32 and split BF16 (the 3 slices of the precision study, and 5) on the
-    workload-2 shape: every sampled entry inside the a-posteriori bound of its
-    arithmetic, and the relative error of the right order."""
+    """FP32, split BF16 (the 3 slices of the precision study, and 5) and 9-bit
+    FP16 slices (4) on the workload-2 shape: every sampled entry inside the
+    a-posteriori bound of its arithmetic, and the relative error of the right
+    order."""
     w = _workload2_sample()
     p, ref = w["p"], w["ref"]
     got = _run_sampled(w, chunk, precision=prec, n_slices=ns)
@@ -98,10 +100,11 @@ def test_workload2_reduced_precision_within_bound(prec, ns, chunk):
             bnd = _bound_both_ways(lambda t: fp32_bound(w["m_c"], d, m_cols=w["m_r"]) if t
                                    else fp32_bound(w["m_r"], d, m_cols=w["m_c"]))
         else:
+            f16 = prec == "split_fp16x9"
             bnd = _bound_both_ways(
                 lambda t: split_bound(w["m_c"] if t else w["m_r"], d, ns, p.nv, p.nc, chunk,
-                                      first_rounded=2, kb=128,
-                                      m_cols=w["m_r"] if t else w["m_c"]))
+                                      first_rounded=2, kb=32 if f16 else 128,
+                                      m_cols=w["m_r"] if t else w["m_c"], bits=9 if f16 else 8))
         excess = np.abs(got[iw] - ref[iw]) - bnd - 1e-15 * np.abs(ref[iw]).max()
         assert excess.max() <= 0, (prec, ns, iw, excess.max())
     if prec == "fp32":
@@ -113,7 +116,7 @@ def test_workload2_reduced_precision_within_bound(prec, ns, chunk):
 
 
 @pytest.mark.parametrize("prec,ns,tol", [("fp64", 0, FP64_TOL), ("fp32", 0, 1e-5),
-                                         ("split_bf16", 5, 1e-10)])
+                                         ("split_bf16", 5, 1e-10), ("split_fp16x9", 4, 1e-10)])
 def test_nv_block_accumulation(prec, ns, tol):
     """chi built as the benchmark builds it: one call per block of valence
     bands, the first overwriting and the rest accumulating with the Hermitian

@@ -73,7 +73,7 @@ def test_coarser_operands_break_bound():
     assert np.any(np.abs(got - ref) > fp32_bound(m, d[0]))
 
 
-def _split_model(m, d, S, nv, nc, chunk, grouped=True, kb=128):
+def _split_model(m, d, S, nv, nc, chunk, grouped=True, kb=128, bits=8):
     """chi by the split-BF16 model: per chunk (rectangle of bands, as the
     library streams them) and block of kb pairs, each operand column gets the
     exponent e with max(|Re|, |Im|) < 2^e, and x 2^(8-e) is cut into S
@@ -88,12 +88,12 @@ def _split_model(m, d, S, nv, nc, chunk, grouped=True, kb=128):
     def slices(x):
         mx = np.maximum(np.abs(x.real), np.abs(x.imag)).max(axis=0)
         e = np.where(mx > 0, np.frexp(mx)[1], 0).astype(np.float64)
-        y = x * 2.0 ** (8 - e)
+        y = x * 2.0 ** (bits - e)
         out = []
         for s in range(S):
             q = np.round(y.real) + 1j * np.round(y.imag)
-            out.append(q * 2.0 ** (-8 * s))
-            y = (y - q) * 256.0
+            out.append(q * 2.0 ** (-bits * s))
+            y = (y - q) * 2.0 ** bits
         return e, out
 
     ng = m.shape[1]
@@ -116,7 +116,7 @@ def _split_model(m, d, S, nv, nc, chunk, grouped=True, kb=128):
                         acc_i[g] += np.outer(ar[p], bi[p])
                         acc_i[g] -= np.outer(ai[p], br[p])
             tot = sum(r.astype(np.float64) + 1j * i.astype(np.float64) for r, i in zip(acc_r, acc_i))
-            chi += 2.0 ** (ea[:, None] + eb[None, :] - 16) * tot
+            chi += 2.0 ** (ea[:, None] + eb[None, :] - 2 * bits) * tot
     return chi
 
 
@@ -150,3 +150,23 @@ def test_split_one_accumulator_breaks_bound():
     got = _split_model(m, d[0], 5, p.nv, p.nc, p.pair_chunk, grouped=False)
     bnd = split_bound(m, d[0], 5, p.nv, p.nc, p.pair_chunk, first_rounded=2, kb=128)
     assert np.any(np.abs(got - ref) > bnd + 1e-15 * np.abs(ref).max())
+
+
+def test_split_fp16x9_model_inside_bound():
+    """The 9-bit FP16 slicing (blocks of 32 pairs, t = 0 and t = 1 exact, t >= 2
+    in one FP32 group) stays inside its bound for 2 to 4 slices, and 4 slices
+    reach below 1e-10 where 8-bit slices at 4 do not."""
+    from test_gpu_precision import split_bound
+    p = _split_problem()
+    m, d = _operands(p)
+    ref = oracle.chi0(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                      spin=p.spin)[0]
+    errs = {}
+    for S in (2, 3, 4):
+        got = _split_model(m, d[0], S, p.nv, p.nc, p.pair_chunk, kb=32, bits=9)
+        bnd = split_bound(m, d[0], S, p.nv, p.nc, p.pair_chunk, first_rounded=2, kb=32, bits=9)
+        assert np.all(np.abs(got - ref) <= bnd + 1e-15 * np.abs(ref).max()), S
+        errs[S] = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    bf4 = _split_model(m, d[0], 4, p.nv, p.nc, p.pair_chunk)
+    e_bf4 = np.linalg.norm(bf4 - ref) / np.linalg.norm(ref)
+    assert errs[2] > errs[3] > errs[4] and errs[4] < 1e-10 < e_bf4, (errs, e_bf4)
