@@ -615,13 +615,21 @@ def bench_batched(args):
     """64 q-points (4x4x4 shifted grid) on a 40^3 grid, 48 valence bands and
     300-900 conduction bands each, G-spheres of 400-4,000 vectors, 16
     imaginary frequencies: one graph-captured gw_chi0 call over all problems,
-    FP64 and split BF16.  Band sets are drawn on the GPU (timing only; parity
-    of this workload is tested on four q-points at full size)."""
+    FP64 (with the tile autotuner, its choices kept in a cache file) and split
+    BF16.  Band sets are drawn on the GPU; every precision is checked against
+    the FP64 oracle's direct sums on 16 x 16 sampled entries of the q-points
+    with the fewest and the most G."""
+    import tempfile
+
     import numpy as np
     import torch
 
     import paper_2509_23018_amd as gw
     from workloads import gen
+
+    tune_fd, tune_path = tempfile.mkstemp(prefix="gw_autotune_", suffix=".txt")
+    os.close(tune_fd)
+    os.environ["GW_AUTOTUNE_CACHE"] = tune_path   # read by the library at its first tuning
 
     dev = torch.device("cuda", 0)
     qs, ngs, ncs = gen.batched_shapes()
@@ -654,9 +662,16 @@ def bench_batched(args):
            "runs": []}
     ref = None
     keep = [int(np.argmin(ngs)), int(np.argmax(ngs)), int(np.argmax(ncs))]
+    osample = keep[:2]                       # q-points checked against the oracle
+    srng = np.random.default_rng(1004)
+    sidx = {q: (np.sort(srng.choice(int(ngs[q]), 16, replace=False)),
+                np.sort(srng.choice(int(ngs[q]), 16, replace=False))) for q in osample}
+    dev_entries = {}
     for prec, ns in [("fp64", 0)] + [("split_bf16", k) for k in args.split_slices]:
+        flags = gw.GW_FLAG_GRAPH | (gw.GW_FLAG_AUTOTUNE if prec == "fp64" else 0)
+
         def call():
-            gw.gw_chi0(probs, precision=prec, n_slices=ns, flags=gw.GW_FLAG_GRAPH)
+            gw.gw_chi0(probs, precision=prec, n_slices=ns, flags=flags)
         t_cap = time.perf_counter()
         call()  # builds plans, captures the graph, runs once
         torch.cuda.synchronize()
@@ -668,7 +683,12 @@ def bench_batched(args):
         gw.profile_reset()
         run = {"precision": prec, "n_slices": ns or None, "s_per_call": round(dt, 4),
                "first_call_s": round(t_cap, 3), "tflops": round(flops / dt / 1e12, 3),
-               "pairs_per_s": round(pairs / dt, 1)}
+               "pairs_per_s": round(pairs / dt, 1), "autotune": prec == "fp64"}
+        key = f"{prec}{ns or ''}"
+        dev_entries[key] = {}
+        for q in osample:
+            r_i, c_i = (torch.from_numpy(x).to(dev) for x in sidx[q])
+            dev_entries[key][q] = probs[q].chi[:, r_i][:, :, c_i].cpu().numpy()
         if prec == "fp64":
             ref = [probs[q].chi.clone() for q in keep]
         else:
@@ -682,6 +702,26 @@ def bench_batched(args):
               f"{free / 2**30:.1f} of {total / 2**30:.1f} GiB, torch reserved "
               f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     out["err_sample_q"] = keep
+    # the oracle's direct sums on the sampled entries (input preparation:
+    # the device bands of those q-points copied to the host)
+    import oracle
+    t_or = time.perf_counter()
+    oerr = {k: {} for k in dev_entries}
+    for q in osample:
+        pr = probs[q]
+        r_i, c_i = sidx[q]
+        want = oracle.chi0_entries(pr.psi_v.cpu().numpy(), pr.psi_c.cpu().numpy(),
+                                   pr.e_v.cpu().numpy(), pr.e_c.cpu().numpy(),
+                                   pr.gvec[r_i], pr.gvec[c_i], z, n, volume)
+        for k, got in dev_entries.items():
+            oerr[k][int(q)] = float(np.linalg.norm(got[q] - want) / np.linalg.norm(want))
+    out["oracle_entries"] = {
+        "sample": "16 x 16 entries (rows and columns drawn with numpy default_rng(1004)), all 16 "
+                  f"frequencies, q-points {osample} (fewest and most G); oracle direct sums",
+        "seconds": round(time.perf_counter() - t_or, 1), "rel_err": oerr}
+    with open(tune_path) as fh:
+        out["autotune_cache"] = [ln.strip() for ln in fh if ln.strip()]
+    os.unlink(tune_path)
     gw.release()
     print(json.dumps(out), flush=True)
 

@@ -1792,20 +1792,19 @@ gw_status_t gw_heev(const gw_c128* a, int32_t n, int32_t batch, double* w, gw_c1
         double2* vtmp = reinterpret_cast<double2*>(v);
         (void)jacobi_eigh(ac, vtmp, n, batch, tol > 0.0 ? tol : 1e-15, 100, jw, s);
         // eigenvalues in increasing order, eigenvectors to match
-        std::vector<double2> dg(static_cast<size_t>(n) * batch);
-        for (int b = 0; b < batch; ++b)
-            GW_HIP_TRY(hipMemcpy2DAsync(dg.data() + static_cast<size_t>(b) * n, sizeof(double2),
-                                        ac + b * nn, (n + 1) * sizeof(double2), sizeof(double2), n,
-                                        hipMemcpyDeviceToHost, s));
+        // (the diagonals gathered into w on the device, then one plain copy)
+        std::vector<double> dg(static_cast<size_t>(n) * batch);
+        launch_diag_re(ac, n, batch, w, s);
+        GW_HIP_TRY(hipMemcpyAsync(dg.data(), w, dg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         GW_HIP_TRY(hipStreamSynchronize(s));
         std::vector<int> perm(static_cast<size_t>(n) * batch);
         std::vector<double> wv(static_cast<size_t>(n) * batch);
         for (int b = 0; b < batch; ++b) {
             int* pb = perm.data() + static_cast<size_t>(b) * n;
-            const double2* db = dg.data() + static_cast<size_t>(b) * n;
+            const double* db = dg.data() + static_cast<size_t>(b) * n;
             for (int i = 0; i < n; ++i) pb[i] = i;
-            std::stable_sort(pb, pb + n, [&](int x, int y) { return db[x].x < db[y].x; });
-            for (int i = 0; i < n; ++i) wv[static_cast<size_t>(b) * n + i] = db[pb[i]].x;
+            std::stable_sort(pb, pb + n, [&](int x, int y) { return db[x] < db[y]; });
+            for (int i = 0; i < n; ++i) wv[static_cast<size_t>(b) * n + i] = db[pb[i]];
         }
         GW_HIP_TRY(hipMemcpyAsync(perm_d, perm.data(), perm.size() * sizeof(int),
                                   hipMemcpyHostToDevice, s));

@@ -181,6 +181,13 @@ __global__ __launch_bounds__(256) void scale_rows_kernel(const double2* in, doub
     }
 }
 
+__global__ __launch_bounds__(256) void diag_re_kernel(const double2* __restrict__ a, int n,
+                                                      double* __restrict__ out) {
+    const int64_t b = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) out[b * n + j] = a[b * n * n + static_cast<int64_t>(j) * n + j].x;
+}
+
 // ---------------------------------------------------------------- Cholesky
 
 constexpr int kCB = 64;  // Cholesky block
@@ -512,6 +519,12 @@ void launch_zaxpby(int64_t n, double2 a, const double2* x, double2 b, const doub
     const int64_t blocks = std::min<int64_t>(ceil_div64(n, 256), 8192);
     hipLaunchKernelGGL(zaxpby_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, n, a,
                        x, b, y, z);
+    GW_HIP_TRY(hipGetLastError());
+}
+
+void launch_diag_re(const double2* a, int n, int batch, double* out, hipStream_t s) {
+    if (n <= 0 || batch <= 0) return;
+    hipLaunchKernelGGL(diag_re_kernel, dim3(ceil_div(n, 256), batch), dim3(256), 0, s, a, n, out);
     GW_HIP_TRY(hipGetLastError());
 }
 

@@ -39,6 +39,9 @@ void launch_zaxpby(int64_t n, double2 a, const double2* x, double2 b, const doub
 void launch_scale_rows(const double2* in, double2* out, const double* w, int64_t rows,
                        int64_t cols, hipStream_t s);
 
+// out[b][j] = Re a[b][j][j] for `batch` n x n matrices (batch stride n*n).
+void launch_diag_re(const double2* a, int n, int batch, double* out, hipStream_t s);
+
 // out[b][:, j] = in[b][:, perm[b][j]] for `batch` [rows][n_in] blocks (perm
 // [batch][n_out]).
 void launch_gather_cols(const double2* in, double2* out, int rows, int n_in, int n_out,

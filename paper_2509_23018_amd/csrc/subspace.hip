@@ -231,10 +231,11 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
         gemm(kOpN, kOpN, ng, nb, ng, make_double2(-scale, 0.0), chi, ng, wx, nb, y, nb);
         launch_scale_rows(y, y, wgt, ng, nb, s);
     };
-    std::vector<double2> dg(nb);
+    // the real diagonal of an [nb][nb] matrix, gathered on the device and read back
+    std::vector<double> dg(nb);
     auto read_diag = [&](const double2* m) {
-        GW_HIP_TRY(hipMemcpy2DAsync(dg.data(), sizeof(double2), m, (nb + 1) * sizeof(double2),
-                                    sizeof(double2), nb, hipMemcpyDeviceToHost, s));
+        launch_diag_re(m, nb, 1, vec, s);
+        GW_HIP_TRY(hipMemcpyAsync(dg.data(), vec, nb * sizeof(double), hipMemcpyDeviceToHost, s));
         GW_HIP_TRY(hipStreamSynchronize(s));
     };
     // orthonormalise y into z: two passes of Cholesky-QR (tmp: scratch)
@@ -326,7 +327,7 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
         res.sweeps += jacobi_eigh(g, u, nb, 1, rr_tol, 60, jw, s);
         read_diag(g);
         std::iota(perm.begin(), perm.end(), 0);
-        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return dg[a].x > dg[b].x; });
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return dg[a] > dg[b]; });
         GW_HIP_TRY(hipMemcpyAsync(perm_d, perm.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(gather_cols_kernel, dim3(static_cast<unsigned>(ceil_div64(nn, 256))),
                            dim3(256), 0, s, u, w, nb, nb, nb, perm_d);
@@ -347,8 +348,8 @@ DiagResult run_subspace_basis(const double2* chi, int ng, int n_eig, double2* ba
         xi = yi;
         // below the smallest Ritz value of the block lies what is not wanted;
         // a zero floor (chi of lower rank than the block) still filters
-        acut = std::max(dg[perm[nb - 1]].x, 1e-6 * bup);
-        top = dg[perm[0]].x;
+        acut = std::max(dg[perm[nb - 1]], 1e-6 * bup);
+        top = dg[perm[0]];
         if (rmax <= prm.tol || it + 1 >= prm.max_iter || nb == ng) break;
     }
     // the first n_eig Ritz vectors; eigenvalues of chi are minus those of A
