@@ -1012,7 +1012,14 @@ def bench_subspace(args):
                                                   pair_chunk=w.pair_chunk))
     _log(t_start, f"static chi0(0): {t_static:.2f} s")
     chi_s = stat[0].contiguous()
-    del stat
+    # the same chi0(0) keeping M of every pair resident in HBM
+    # (pairs x N_G complex, 95 GB here), so CHI-Freq skips MTXEL
+    (stat_k, m_keep), t_static_keep = _sync_time(
+        lambda: gw.gw_chi0_keep_m(prob(np.zeros(1, np.complex128)), pair_chunk=w.pair_chunk))
+    keep_equal = bool(torch.equal(stat_k, stat))
+    _log(t_start, f"static chi0(0) keeping M ({m_keep.numel() * 16 / 1e9:.1f} GB): "
+                  f"{t_static_keep:.2f} s, equal to the plain call: {keep_equal}")
+    del stat, stat_k
     runs = []
     for frac in (0.1, 0.2):
         n_eig = int(round(frac * ng))
@@ -1020,6 +1027,10 @@ def bench_subspace(args):
             lambda: gw.gw_subspace_basis(chi_s, n_eig, weight=wt, tol=1e-8, seed=7))
         chib, t_sub = _sync_time(lambda: gw.gw_chi0_subspace(prob(w.z), basis, weight=wt,
                                                                pair_chunk=w.pair_chunk))
+        chib_m, t_sub_m = _sync_time(lambda: gw.gw_chi0_from_m(prob(w.z), m_keep, basis,
+                                                               weight=wt, pair_chunk=w.pair_chunk))
+        from_m_equal = bool(torch.equal(chib_m, chib))
+        del chib_m
         # W chi(z) W ~ C_s chi_B(z) C_s^H on the 32 rows
         crow = basis[rows].contiguous()
         t1 = gw.gw_zgemm("N", "N", crow[None].expand(nz, -1, -1).contiguous(), chib)
@@ -1041,11 +1052,18 @@ def bench_subspace(args):
             "transf_plus_chi_freq_tflops": round((sub_flops + transf_flops) / t_sub / 1e12, 3),
             "subspace_path_s": round(t_static + t_diag + t_sub, 3),
             "speedup_vs_full_plane_waves": round(t_full / (t_static + t_diag + t_sub), 3),
+            "chi_freq_from_kept_m_s": round(t_sub_m, 3),
+            "chi_freq_from_kept_m_tflops": round(sub_flops / t_sub_m / 1e12, 3),
+            "kept_m_equal_to_recomputed": from_m_equal,
+            "subspace_path_kept_m_s": round(t_static_keep + t_diag + t_sub_m, 3),
+            "speedup_kept_m_vs_full_plane_waves":
+                round(t_full / (t_static_keep + t_diag + t_sub_m), 3),
             "rel_err_32rows_per_freq": err,
             "eigenvalue_range": [float(evals[0]), float(evals[-1])],
         })
         _log(t_start, f"n_eig {n_eig}: Diag {t_diag:.2f} s ({info['iterations']} iterations, "
-                      f"residual {info['residual']:.1e}), CHI-Freq {t_sub:.2f} s, "
+                      f"residual {info['residual']:.1e}), CHI-Freq {t_sub:.2f} s "
+                      f"({t_sub_m:.2f} s from kept M, equal: {from_m_equal}), "
                       f"errors {min(err):.2e}..{max(err):.2e}")
         del basis, chib, crow, t1, approx, proj, wb
         torch.cuda.empty_cache()
@@ -1057,7 +1075,12 @@ def bench_subspace(args):
            "full_plane_waves_s": round(t_full, 3),
            "full_tflops": round(8.0 * ng * ng * pairs * nz / t_full / 1e12, 3),
            "static_chi0_s": round(t_static, 3),
+           "static_chi0_keep_m_s": round(t_static_keep, 3),
+           "kept_m_gb": round(m_keep.numel() * 16 / 1e9, 2),
+           "kept_m_static_equal": keep_equal,
            "runs": runs}
+    del m_keep
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         # the oracle's Diag step (a library Hermitian eigensolver) on the same
         # chi0(0), eigenvalues only, against the device's kept eigenvalues

@@ -383,6 +383,45 @@ size_t gw_chi0_subspace_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
                                         const gw_opts_t* opts);
 
 /*
+ * Matrix elements kept in device memory.  The static subspace method builds
+ * chi(0) in plane waves, diagonalises it, then builds chi_BB'(z) from the
+ * same matrix elements; with HBM to hold M of every pair (16 N_G bytes per
+ * pair: 95 GB for 983,040 pairs and 6,031 G) the second pass can read M
+ * instead of running MTXEL again.
+ *
+ * gw_chi0_keep_m -- gw_chi0 of one problem (Eq. (4)) that also leaves M of
+ * every pair in m_keep: device OUT [nv*nc][ng], in the order the call streams
+ * its pair chunks: rectangles of vb valence x cw conduction bands, with
+ * cw = min(nc, chunk / min(nv, 4)) and vb = min(nv, chunk / cw) for
+ * chunk = opts->pair_chunk (0: 4096), valence blocks outer, conduction blocks
+ * inner, each rectangle [vcount][cw] row-major.  Options, precisions, flags
+ * (GW_FLAG_GRAPH is GW_EUNSUPPORTED) and workspace as gw_chi0 with nprob = 1
+ * (size: gw_workspace_bytes(prob, 1, opts, 0)).  m_keep is owned by the
+ * caller; NULL with nv*nc > 0 is GW_EINVAL.
+ */
+gw_status_t gw_chi0_keep_m(const gw_problem_t* prob, gw_c128* m_keep, const gw_opts_t* opts,
+                           void* stream);
+
+/*
+ * gw_chi0_from_m -- chi of one problem from M kept by gw_chi0_keep_m with the
+ * same problem shape and pair_chunk (no MTXEL; prob->psi_v and psi_c are not
+ * read, the energies and frequencies are): with basis NULL Eq. (4) into
+ * prob->chi [nz][ng][ng]; with basis (device [ng][n_eig]) and weight (device
+ * [ng] or NULL) Transf and CHI-Freq of Eq. (6) as gw_chi0_subspace into
+ * prob->chi [nz][n_eig][n_eig].  Workspace size:
+ * gw_chi0_from_m_workspace_bytes(prob, basis ? n_eig : 0, opts).  The
+ * results are bit-identical to gw_chi0 / gw_chi0_subspace with the same
+ * options.  GW_EINVAL: m_keep NULL with nv*nc > 0, n_eig outside [1, ng] with
+ * a basis, n_eig != 0 without one; GW_FLAG_GRAPH is GW_EUNSUPPORTED.  An
+ * m_keep from another shape or pair_chunk is not detected.
+ */
+gw_status_t gw_chi0_from_m(const gw_problem_t* prob, const gw_c128* m_keep, const gw_c128* basis,
+                           const double* weight, int32_t n_eig, const gw_opts_t* opts,
+                           void* stream);
+size_t gw_chi0_from_m_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
+                                      const gw_opts_t* opts);
+
+/*
  * gw_epsinv -- the inverse dielectric matrix of Eq. (3),
  *     eps^-1(z) = [I - v chi(z)]^-1,
  * for nz frequencies, with v the diagonal Coulomb matrix.  Block Gauss-Jordan

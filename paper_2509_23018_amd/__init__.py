@@ -31,7 +31,8 @@ __all__ = [
     "pseudobands_workspace_bytes",
     "gw_chi0_backward", "gw_pseudobands", "gw_subspace_basis", "gw_chi0_subspace",
     "subspace_basis_workspace_bytes", "chi0_subspace_workspace_bytes", "gw_zgemm", "gw_heev",
-    "gw_epsinv", "gw_gpp_sigma", "Chi0", "chi0", "release", "profile_enable",
+    "gw_epsinv", "gw_gpp_sigma", "gw_chi0_keep_m", "gw_chi0_from_m", "Chi0", "chi0", "release",
+    "profile_enable",
     "profile_reset",
     "profile_read",
 ]
@@ -145,6 +146,16 @@ def lib() -> ctypes.CDLL:
         L.gw_chi0_subspace_workspace_bytes.restype = ctypes.c_size_t
         L.gw_chi0_subspace_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32,
                                                        ctypes.POINTER(_Opts)]
+        L.gw_chi0_keep_m.restype = ctypes.c_int32
+        L.gw_chi0_keep_m.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p,
+                                     ctypes.POINTER(_Opts), ctypes.c_void_p]
+        L.gw_chi0_from_m.restype = ctypes.c_int32
+        L.gw_chi0_from_m.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Opts),
+                                     ctypes.c_void_p]
+        L.gw_chi0_from_m_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_chi0_from_m_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32,
+                                                     ctypes.POINTER(_Opts)]
         L.gw_zgemm.restype = ctypes.c_int32
         L.gw_zgemm.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, _C128, ctypes.c_void_p, ctypes.c_int64,
@@ -489,6 +500,9 @@ def gw_chi0_subspace(problem, basis: torch.Tensor, *, weight=None, precision="fp
     in the subspace spanned by the columns of basis [ng, n_eig]; with weight
     [ng], C^H W chi W C."""
     _dev(basis, "basis", torch.complex128)
+    ng = int(np.asarray(problem.gvec).shape[0])
+    if basis.dim() != 2 or basis.shape[0] != ng or basis.shape[1] < 1:
+        raise ValueError(f"basis must be [{ng}, n_eig] with n_eig >= 1")
     wp = _weight(weight, basis.shape[0], basis.device)
     n_eig = basis.shape[1]
     nz = _host_c128(problem.z).shape[0]
@@ -505,6 +519,64 @@ def gw_chi0_subspace(problem, basis: torch.Tensor, *, weight=None, precision="fp
     with torch.cuda.device(basis.device):
         _check(lib().gw_chi0_subspace(ctypes.byref(arr), basis.data_ptr(), wp, int(n_eig),
                                       ctypes.byref(o), _stream(basis.device, stream)))
+    return out
+
+
+def gw_chi0_keep_m(problem: Chi0Problem, m_keep: Optional[torch.Tensor] = None, *,
+                   precision="fp64", n_slices=0, pair_chunk=4096, flags=0, spin=2.0,
+                   workspace=None, stream=None):
+    """gw_chi0 of one problem that also keeps M of every pair (device
+    [nv*nc, ng], in the order the call streams its chunks); returns
+    (chi, m_keep)."""
+    npairs = problem.psi_v.shape[0] * problem.psi_c.shape[0]
+    ng = int(np.asarray(problem.gvec).shape[0])
+    if m_keep is None:
+        m_keep = torch.empty((npairs, ng), dtype=torch.complex128, device=problem.psi_v.device)
+    _dev(m_keep, "m_keep", torch.complex128)
+    if tuple(m_keep.shape) != (npairs, ng):
+        raise ValueError(f"m_keep must have shape {(npairs, ng)}")
+    arr = _Problem()
+    keep: list = []
+    problem._fill(arr, keep)
+    o = _opts(precision, n_slices, pair_chunk, flags, spin, workspace)
+    with torch.cuda.device(problem.psi_v.device):
+        _check(lib().gw_chi0_keep_m(ctypes.byref(arr), m_keep.data_ptr(), ctypes.byref(o),
+                                    _stream(problem.psi_v.device, stream)))
+    return problem.chi, m_keep
+
+
+def gw_chi0_from_m(problem: Chi0Problem, m_keep: torch.Tensor, basis: Optional[torch.Tensor] = None,
+                   *, weight=None, precision="fp64", n_slices=0, pair_chunk=4096, flags=0,
+                   spin=2.0, out=None, workspace=None, stream=None) -> torch.Tensor:
+    """chi from M kept by gw_chi0_keep_m (same problem shape and pair_chunk):
+    Eq. (4) [nz, ng, ng], or with basis [ng, n_eig] (and weight) Eq. (6)
+    [nz, n_eig, n_eig]."""
+    _dev(m_keep, "m_keep", torch.complex128)
+    ng = int(np.asarray(problem.gvec).shape[0])
+    nz = _host_c128(problem.z).shape[0]
+    n_eig = 0
+    wp = None
+    if basis is not None:
+        _dev(basis, "basis", torch.complex128)
+        n_eig = basis.shape[1]
+        if basis.dim() != 2 or basis.shape[0] != ng or n_eig < 1:
+            raise ValueError(f"basis must be [{ng}, n_eig] with n_eig >= 1")
+        wp = _weight(weight, basis.shape[0], basis.device)
+    ncol = n_eig or ng
+    if out is None:
+        out = torch.empty((nz, ncol, ncol), dtype=torch.complex128, device=m_keep.device)
+    _dev(out, "out", torch.complex128)
+    if tuple(out.shape) != (nz, ncol, ncol):
+        raise ValueError(f"out must have shape {(nz, ncol, ncol)}")
+    arr = _Problem()
+    keep: list = []
+    problem._fill(arr, keep, alloc_chi=False)
+    arr.chi = out.data_ptr()
+    o = _opts(precision, n_slices, pair_chunk, flags, spin, workspace)
+    with torch.cuda.device(m_keep.device):
+        _check(lib().gw_chi0_from_m(ctypes.byref(arr), m_keep.data_ptr(),
+                                    basis.data_ptr() if basis is not None else None, wp,
+                                    int(n_eig), ctypes.byref(o), _stream(m_keep.device, stream)))
     return out
 
 

@@ -512,9 +512,18 @@ Chi0Layout chi0_layout(const gw_problem_t& pr, const Opts& o, const MtxelPlan& p
 // the Hermitian mirror.  base holds L.total bytes (L from chi0_layout with the
 // same arguments); with basis (device [N_G][n_eig], L.ncols = n_eig) chi is
 // [nz][n_eig][n_eig], and with weight (device [N_G]) the basis is W C_s.
+// M kept in device memory across calls: out (written by MTXEL, chunk by
+// chunk) or in (read instead of running MTXEL), both [npairs][N_G] in the
+// order the call streams its chunks (the rectangles of chunk_shape for the
+// same problem and pair_chunk, each [vcount][cw] row-major).
+struct MKeep {
+    double2* out = nullptr;
+    const double2* in = nullptr;
+};
+
 void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
               const Chi0Layout& L, const double2* basis = nullptr,
-              const double* weight = nullptr) {
+              const double* weight = nullptr, MKeep mk = {}) {
     const PlanRef plan_ref = get_plan(pr.grid.n, pr.gvec, pr.ng);
     const MtxelPlan& plan = *plan_ref;
     const int64_t ng = L.ncols;  // the contraction's width
@@ -540,6 +549,15 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
                            ? reinterpret_cast<double2*>(base + L.off_tail)
                            : nullptr;
     const std::vector<Chunk> chunks = make_chunks(pr, L.cs);
+    std::vector<int64_t> moff(chunks.size(), 0);  // first row of chunk k in kept M
+    for (size_t k = 1; k < chunks.size(); ++k) moff[k] = moff[k - 1] + chunks[k - 1].kc;
+    // the contraction's operand of chunk k: buffer k & 1, or kept M itself
+    auto cmat = [&](size_t k) -> const double2* {
+        if (basis) return mbuf[k & 1];
+        if (mk.in) return mk.in + moff[k] * pr.ng;
+        if (mk.out) return mk.out + moff[k] * pr.ng;
+        return mbuf[k & 1];
+    };
     int variant = 0;
     bool tune = false;
     if (o.precision == GW_FP64 && (o.flags & GW_FLAG_FP64_TILE128)) {
@@ -561,10 +579,18 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
         const hipStream_t ps = two_streams ? ax->aux : s;
         if (two_streams && k >= 2) GW_HIP_TRY(hipStreamWaitEvent(ax->aux, ax->ev[3 + b], 0));
         const Chunk& c = chunks[k];
-        double2* mout = basis ? reinterpret_cast<double2*>(base + L.off_mfull) : mbuf[b];
-        launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
-                     reinterpret_cast<const double2*>(pr.psi_c),
-                     Rect{c.pm.v0, c.vcount, c.pm.c0, c.pm.cw}, pr.grid.volume, t2, mout, ps);
+        const double2* mout;
+        if (mk.in) {
+            mout = mk.in + moff[k] * pr.ng;
+        } else {
+            double2* dst = mk.out    ? mk.out + moff[k] * pr.ng
+                           : basis   ? reinterpret_cast<double2*>(base + L.off_mfull)
+                                     : mbuf[b];
+            launch_mtxel(plan, reinterpret_cast<const double2*>(pr.psi_v),
+                         reinterpret_cast<const double2*>(pr.psi_c),
+                         Rect{c.pm.v0, c.vcount, c.pm.c0, c.pm.cw}, pr.grid.volume, t2, dst, ps);
+            mout = dst;
+        }
         if (basis) {  // Transf: M^B = M C_s
             ZGemm g;
             g.m = static_cast<int>(c.kc);
@@ -594,7 +620,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
         one.nf = 1;
         double2* trial_chi = reinterpret_cast<double2*>(base + L.off_tune);
         variant = tune_variant(L.ncols, chunks[0].kc, s, [&](int v) {
-            launch_chi0_f64(mbuf[0], chunks[0].kc, L.ncols, dbuf[0], one, trial_chi, false, s, v,
+            launch_chi0_f64(cmat(0), chunks[0].kc, L.ncols, dbuf[0], one, trial_chi, false, s, v,
                             tail_ws);
         });
     }
@@ -607,13 +633,14 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
         }
         for (const WList& wl : wlists) {
             const bool acc = accumulate || k > 0;
+            const double2* mk_k = cmat(k);
             if (o.precision == GW_FP64)
-                launch_chi0_f64(mbuf[b], chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s, variant,
+                launch_chi0_f64(mk_k, chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s, variant,
                                 tail_ws);
             else if (o.precision == GW_FP32)
-                launch_chi0_f32(mbuf[b], chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s);
+                launch_chi0_f32(mk_k, chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s);
             else
-                launch_chi0_split(o.precision, o.n_slices, mbuf[b], chunks[k].kc, L.ncols, dbuf[b],
+                launch_chi0_split(o.precision, o.n_slices, mk_k, chunks[k].kc, L.ncols, dbuf[b],
                                   pr.nz, wl, chi, acc, base + L.off_sp, s, tail_ws);
         }
         if (two_streams) GW_HIP_TRY(hipEventRecord(ax->ev[3 + b], s));
@@ -1637,6 +1664,70 @@ gw_status_t gw_chi0_subspace(const gw_problem_t* prob, const gw_c128* basis,
         const Chi0Layout L = chi0_layout(*prob, o, *plan, 2, true, n_eig);
         char* base = call_scratch(L.total, o, s);
         run_chi0(*prob, o, s, base, L, reinterpret_cast<const double2*>(basis), weight);
+    });
+}
+
+// ---------------------------------------------------------------- kept matrix elements
+
+gw_status_t gw_chi0_keep_m(const gw_problem_t* prob, gw_c128* m_keep, const gw_opts_t* opts,
+                           void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        const Opts o = read_opts(opts);
+        check_problem(*prob, 0);
+        check_slices(o);
+        if (static_cast<int64_t>(prob->nv) * prob->nc > 0 && !m_keep)
+            fail(GW_EINVAL, "m_keep is NULL");
+        if (o.flags & GW_FLAG_GRAPH) fail(GW_EUNSUPPORTED, "GW_FLAG_GRAPH is for batched gw_chi0");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const PlanRef plan = get_plan(prob->grid.n, prob->gvec, prob->ng);
+        const Chi0Layout L = chi0_layout(*prob, o, *plan, chi0_buffers(), true);
+        char* base = call_scratch(L.total, o, s);
+        MKeep mk;
+        mk.out = reinterpret_cast<double2*>(m_keep);
+        run_chi0(*prob, o, s, base, L, nullptr, nullptr, mk);
+    });
+}
+
+size_t gw_chi0_from_m_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
+                                      const gw_opts_t* opts) {
+    size_t out = 0;
+    const gw_status_t st = guarded([&] {
+        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        const Opts o = read_opts(opts);
+        gw_problem_t p = *prob;
+        static gw_c128 dummy{0.0, 0.0};
+        if (!p.chi) p.chi = &dummy;
+        check_problem(p, 0);
+        const PlanRef plan = get_plan(p.grid.n, p.gvec, p.ng);
+        out = chi0_layout(p, o, *plan, 2, true, n_eig > 0 ? n_eig : 0).total;
+    });
+    return st == GW_OK ? out : static_cast<size_t>(-1);
+}
+
+gw_status_t gw_chi0_from_m(const gw_problem_t* prob, const gw_c128* m_keep, const gw_c128* basis,
+                           const double* weight, int32_t n_eig, const gw_opts_t* opts,
+                           void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        if (!prob) fail(GW_EINVAL, "prob is NULL");
+        const Opts o = read_opts(opts);
+        check_problem(*prob, 0);
+        check_slices(o);
+        if (static_cast<int64_t>(prob->nv) * prob->nc > 0 && !m_keep)
+            fail(GW_EINVAL, "m_keep is NULL");
+        if (basis && (n_eig < 1 || n_eig > prob->ng)) fail(GW_EINVAL, "n_eig must lie in [1, ng]");
+        if (!basis && n_eig != 0) fail(GW_EINVAL, "n_eig must be 0 when basis is NULL");
+        if (o.flags & GW_FLAG_GRAPH) fail(GW_EUNSUPPORTED, "GW_FLAG_GRAPH is for batched gw_chi0");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const PlanRef plan = get_plan(prob->grid.n, prob->gvec, prob->ng);
+        const Chi0Layout L = chi0_layout(*prob, o, *plan, 2, true, basis ? n_eig : 0);
+        char* base = call_scratch(L.total, o, s);
+        MKeep mk;
+        mk.in = reinterpret_cast<const double2*>(m_keep);
+        run_chi0(*prob, o, s, base, L, reinterpret_cast<const double2*>(basis),
+                 basis ? weight : nullptr, mk);
     });
 }
 

@@ -209,6 +209,61 @@ def test_subspace_weighted_against_oracle():
         assert rel_fro(b @ chib[w] @ b.conj().T, ref) < 1e-10, w
 
 
+def _chunk_order(nv, nc, chunk):
+    """Pair indices p = v*nc + c in the order gw_chi0 streams its chunks
+    (rectangles of vb valence x cw conduction bands, valence blocks outer)."""
+    cw = max(1, min(nc, chunk // max(1, min(nv, 4))))
+    vb = max(1, min(nv, chunk // cw))
+    order = []
+    for v0 in range(0, nv, vb):
+        for c0 in range(0, nc, cw):
+            for v in range(v0, min(nv, v0 + vb)):
+                order.extend(v * nc + c for c in range(c0, min(nc, c0 + cw)))
+    return np.array(order)
+
+
+@pytest.mark.parametrize("chunk", [7, 4096])
+def test_keep_m_and_chi_from_kept_m(chunk):
+    """gw_chi0_keep_m: chi as gw_chi0 gives it (the same kernels on the same
+    data: bit for bit) and M of every pair in chunk order against the oracle's
+    MTXEL; gw_chi0_from_m: chi at other frequencies and chi_BB' of Eq. (6)
+    (weighted basis) from the kept M, without MTXEL, against the oracle and
+    bit for bit against gw_chi0 / gw_chi0_subspace."""
+    p, chi = _chi_static_problem(seed=46, nv=3, nc=17)
+    dp = to_dev(p)
+    want = gw.gw_chi0(dp, pair_chunk=chunk).clone()
+    dp2 = to_dev(p)
+    got, mk = gw.gw_chi0_keep_m(dp2, pair_chunk=chunk)
+    assert torch.equal(got, want)
+    m_or = oracle.mtxel(p.psi_v, p.psi_c, p.gvec, p.n, p.volume)
+    order = _chunk_order(p.nv, p.nc, chunk)
+    assert rel_fro(mk.cpu().numpy(), m_or[order]) < FP64_TOL
+    # chi at the same problem's frequencies, from the kept M
+    dp3 = to_dev(p)
+    from_m = gw.gw_chi0_from_m(dp3, mk, pair_chunk=chunk)
+    assert torch.equal(from_m, want)
+    assert rel_fro(from_m.cpu().numpy(), chi) < FP64_TOL
+    # Eq. (6) from the kept M with the oracle's weighted basis
+    wt = np.sqrt(oracle.coulomb(p.gvec, q=(0.1, -0.05, 0.2), cell_l=gen.CELL_L))
+    wd = torch.from_numpy(wt).to(device())
+    cs, _ = oracle.static_subspace_basis(chi[0], 12, weight=wt)
+    csd = torch.from_numpy(np.ascontiguousarray(cs)).to(device())
+    sub_m = gw.gw_chi0_from_m(dp3, mk, csd, weight=wd, pair_chunk=chunk)
+    sub = gw.gw_chi0_subspace(dp3, csd, weight=wd, pair_chunk=chunk)
+    assert torch.equal(sub_m, sub)
+    ref = oracle.chi0_subspace(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume, cs,
+                               spin=p.spin, pair_chunk=chunk, weight=wt)
+    assert rel_fro(sub_m.cpu().numpy(), ref) < FP64_TOL
+    with pytest.raises(ValueError):
+        gw.gw_chi0_from_m(dp3, mk, csd[:, :0], pair_chunk=chunk)
+    with pytest.raises(ValueError):
+        gw.gw_chi0_from_m(dp3, mk, csd[1:], pair_chunk=chunk)
+    wide = torch.zeros((p.gvec.shape[0], p.gvec.shape[0] + 1), dtype=torch.complex128,
+                       device=device())
+    with pytest.raises(gw.GWError):
+        gw.gw_chi0_from_m(dp3, mk, wide, pair_chunk=chunk)
+
+
 def test_subspace_argument_errors():
     a = torch.zeros((8, 8), dtype=torch.complex128, device=device())
     with pytest.raises(gw.GWError):
