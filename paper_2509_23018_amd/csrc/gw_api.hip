@@ -1330,31 +1330,36 @@ gw_status_t gw_mtxel(const gw_grid_t* grid, const gw_c128* psi_v, int32_t nv,
         if (!m_out) fail(GW_EINVAL, "m_out is NULL");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const PlanRef plan = get_plan(grid->n, gvec, ng);
-        // the linear pair range as rectangles of at most kBatch pairs
+        // the linear pair range as rectangles of at most kBatch pairs: partial
+        // rows alone, whole rows in blocks of up to 4 valence bands (the MTXEL
+        // tile height) cut into column ranges, written with row stride nc
         constexpr int64_t kBatch = 4096;
-        std::vector<std::pair<Rect, int64_t>> rects;  // (rectangle, first output row)
+        struct Piece {
+            Rect r;
+            int64_t row0;  // output row of the rectangle's first pair
+        };
+        std::vector<Piece> rects;
         int64_t p0 = pair_begin;
         const int64_t pend = pair_begin + pair_count;
         while (p0 < pend) {
             const int v = static_cast<int>(p0 / nc), c = static_cast<int>(p0 % nc);
-            Rect r;
             if (c != 0 || pend - p0 < nc) {  // part of one row
                 const int64_t cnt = std::min<int64_t>({nc - c, pend - p0, kBatch});
-                r = Rect{v, 1, c, static_cast<int32_t>(cnt)};
-            } else if (nc > kBatch) {        // a long row, in pieces
-                r = Rect{v, 1, 0, static_cast<int32_t>(kBatch)};
-            } else {                          // whole rows
-                const int64_t rows = std::min<int64_t>((pend - p0) / nc, kBatch / nc);
-                r = Rect{v, static_cast<int32_t>(rows), 0, nc};
+                rects.push_back({Rect{v, 1, c, static_cast<int32_t>(cnt)}, p0 - pair_begin});
+                p0 += cnt;
+                continue;
             }
-            rects.push_back({r, p0 - pair_begin});
-            p0 += static_cast<int64_t>(r.nv) * r.nc;
+            const int vb = static_cast<int>(std::min<int64_t>((pend - p0) / nc, 4));
+            const int cw = static_cast<int>(std::min<int64_t>(nc, kBatch / vb));
+            for (int c0 = 0; c0 < nc; c0 += cw)
+                rects.push_back({Rect{v, vb, c0, std::min(cw, nc - c0)}, p0 - pair_begin + c0});
+            p0 += static_cast<int64_t>(vb) * nc;
         }
         double2* t2 = static_cast<double2*>(scratch(t2_elems(*plan, kBatch) * sizeof(double2), s));
         for (const auto& rr : rects)
             launch_mtxel(*plan, reinterpret_cast<const double2*>(psi_v),
-                         reinterpret_cast<const double2*>(psi_c), rr.first, grid->volume, t2,
-                         reinterpret_cast<double2*>(m_out) + rr.second * ng, s);
+                         reinterpret_cast<const double2*>(psi_c), rr.r, grid->volume, t2,
+                         reinterpret_cast<double2*>(m_out) + rr.row0 * ng, s, nc);
         mark_plan_used(*plan, s);
     });
 }

@@ -60,41 +60,58 @@ constexpr int kZyThreads = 64 * kZyWaves;
 constexpr int kSlab = 16;              // j3 values per LDS slab (4 MFMA k-steps)
 constexpr int kRowStride = kSlab + 1;  // padded LDS row: column reads hit distinct banks
 
+// The value this lane's partner in its 16-lane row (lane ^ 8) holds: a DPP
+// row rotation by 8, two 32-bit moves.
+__device__ __forceinline__ double row_swap8(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), 0x128, 0xf,
+                                               0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x128, 0xf, 0xf, false);
+    return __longlong_as_double(static_cast<long long>(
+        (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+        static_cast<unsigned>(lo)));
+}
+
 // One workgroup = a tile of 4 valence x (2*PPW) conduction bands (4*2*PPW
 // pairs); wave w owns valence band w/2 and PPW conduction bands.  For every
 // (j1 plane, 16-row block of j2, 16-wide slab of j3) the tile's band rows are
 // staged once in LDS and shared by all the pairs that use them; the next
 // slab's global loads are in flight while the current one is contracted.
-// K3: both stages take each complex product a b as three real MFMA
-// products (Karatsuba: a.x b.x, a.y b.y, (a.x + a.y)(b.x + b.y);
-// Re = p1 - p2, Im = p3 - p1 - p2), the third accumulator sets paid for by
-// one pair fewer per wave.
-template <int NB2, int NB3, int PPW, bool K3>
+// Both stages run on real twiddles, two real MFMA products per 16 x 16 block
+// (the real and the imaginary part of the complex operand):
+//  * stage z: B = the cos | sin columns of 8 k3 classes (NB3 blocks); before
+//    stage y each lane swaps with its partner column (c ^ 8) to form T1 at
+//    k3 = +a (columns c < 8) and k3 = -a (columns c >= 8);
+//  * stage y: A = the cos | sin rows of 8 k2 classes (NB2 blocks).  Output
+//    row 4 t + kq sits in element t, so a class's cos row (t = 0, 1) and sin
+//    row (t = 2, 3) share a lane and T2 at k2 = +-a is formed in place.
+// k-steps of j3 or j2 beyond the grid (the padding to 16) are skipped.
+template <int NB2, int NB3, int PPW>
 __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const double2* __restrict__ psi_v, const double2* __restrict__ psi_c, int64_t nr, Rect rc,
     int n1, int planes_per_group, int n2, int n3, int n2p, int n3p,
-    const double2* __restrict__ w3tab,
-    const double2* __restrict__ w2tab, const int* __restrict__ boxmap, int n23,
-    double2* __restrict__ t2) {
+    const double* __restrict__ w3tab, const double* __restrict__ w2tab,
+    const int* __restrict__ boxmap, int n23, double2* __restrict__ t2) {
     constexpr int TV = 4, TC = 2 * PPW, NBANDS = TV + TC;
     constexpr int NFILL = NBANDS * 256 / kZyThreads;  // staged elements per thread
     extern __shared__ double2 lds[];
     const int nslab = n3p / kSlab;
     const int q = n3p >> 2;
     const int nrb1 = n2p >> 4;
-    const int w3n = q * NB3 * 64;
+    const int w3n = q * NB3 * 64;          // doubles (multiples of 64: whole double2 slots)
     const int w2n = nrb1 * 4 * NB2 * 64;
     constexpr int boxn = NB2 * 16 * NB3 * 16;
-    double2* s_w3 = lds;
-    double2* s_w2 = lds + w3n;
-    int* s_box = reinterpret_cast<int*>(lds + w3n + w2n);
-    double2* s_slab = lds + w3n + w2n + boxn / 4;  // [NBANDS][16][kRowStride]
+    double* s_w3 = reinterpret_cast<double*>(lds);
+    double* s_w2 = reinterpret_cast<double*>(lds + w3n / 2);
+    int* s_box = reinterpret_cast<int*>(lds + w3n / 2 + w2n / 2);
+    double2* s_slab = lds + w3n / 2 + w2n / 2 + boxn / 4;  // [NBANDS][16][kRowStride]
     for (int i = threadIdx.x; i < w3n; i += kZyThreads) s_w3[i] = w3tab[i];
     for (int i = threadIdx.x; i < w2n; i += kZyThreads) s_w2[i] = w2tab[i];
     for (int i = threadIdx.x; i < boxn; i += kZyThreads) s_box[i] = boxmap[i];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
+    const bool cos_col = row < 8;  // this lane's stage-z column: cosine (else sine) of its class
     const int tv0 = blockIdx.y * TV, tc0 = blockIdx.x * TC;
 
     // staging slots of this thread: band fb[u], row fr[u], column fc[u]
@@ -135,16 +152,17 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
     for (int p = 0; p < PPW; ++p) pok[p] = tv0 + vl < rc.nv && tc0 + cl0 + p < rc.nc;
 
-    // accumulators: Re, Im (a?s unused), or with K3 the three products
-    dbl4 a1r[PPW][NB3], a1i[PPW][NB3], a1s[PPW][NB3];
-    dbl4 a2r[PPW][NB2][NB3], a2i[PPW][NB2][NB3], a2s[PPW][NB2][NB3];
+    // accumulators (Re, Im): stage z per class block of k3, stage y per class
+    // blocks of k2 and k3
+    dbl4 a1r[PPW][NB3], a1i[PPW][NB3];
+    dbl4 a2r[PPW][NB2][NB3], a2i[PPW][NB2][NB3];
 #pragma unroll
     for (int p = 0; p < PPW; ++p)
 #pragma unroll
         for (int b3 = 0; b3 < NB3; ++b3) {
-            a1r[p][b3] = a1i[p][b3] = a1s[p][b3] = zero4();
+            a1r[p][b3] = a1i[p][b3] = zero4();
 #pragma unroll
-            for (int b2 = 0; b2 < NB2; ++b2) a2r[p][b2][b3] = a2i[p][b2][b3] = a2s[p][b2][b3] = zero4();
+            for (int b2 = 0; b2 < NB2; ++b2) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
         }
 
     // this workgroup's planes: j1 in [j1b, j1e)
@@ -176,66 +194,62 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int ks = sl * 4 + kk;
+            if (4 * ks >= n3) break;  // padding k-steps (uniform)
             const double2 xv = s_slab[(vl * 16 + row) * kRowStride + 4 * kk + kq];
-            double2 w3[NB3];
-            double w3s[NB3];
+            double w3[NB3];
 #pragma unroll
-            for (int b3 = 0; b3 < NB3; ++b3) {
-                w3[b3] = s_w3[(ks * NB3 + b3) * 64 + lane];
-                w3s[b3] = w3[b3].x + w3[b3].y;
-            }
+            for (int b3 = 0; b3 < NB3; ++b3) w3[b3] = s_w3[(ks * NB3 + b3) * 64 + lane];
 #pragma unroll
             for (int p = 0; p < PPW; ++p) {
                 const double2 xc = s_slab[((TV + cl0 + p) * 16 + row) * kRowStride + 4 * kk + kq];
                 const double2 rho = cmul_conj_a(xv, xc);
-                if constexpr (K3) {
-                    const double rs = rho.x + rho.y;
 #pragma unroll
-                    for (int b3 = 0; b3 < NB3; ++b3) {
-                        a1r[p][b3] = mfma_f64(rho.x, w3[b3].x, a1r[p][b3]);
-                        a1i[p][b3] = mfma_f64(rho.y, w3[b3].y, a1i[p][b3]);
-                        a1s[p][b3] = mfma_f64(rs, w3s[b3], a1s[p][b3]);
-                    }
-                } else {
-#pragma unroll
-                    for (int b3 = 0; b3 < NB3; ++b3)
-                        cmfma(a1r[p][b3], a1i[p][b3], rho.x, rho.y, w3[b3].x, w3[b3].y);
+                for (int b3 = 0; b3 < NB3; ++b3) {
+                    a1r[p][b3] = mfma_f64(rho.x, w3[b3], a1r[p][b3]);
+                    a1i[p][b3] = mfma_f64(rho.y, w3[b3], a1i[p][b3]);
                 }
             }
         }
         if (sl == nslab - 1) {
-            // y stage: a1[p][b3] element t of lane l is T1[j2 = rb1*16 + 4*t + kq][k3 = b3*16 + row],
-            // the B operand of k-step t (k index kq)
+            // y stage, k-step t (k index kq): a1[p][b3] element t of lane l is the
+            // cos (row < 8) or sin sum of k3 class 8*b3 + (row & 7) at
+            // j2 = rb1*16 + 4*t + kq; with the partner lane's sum, T1 at
+            // k3 = +a (cos lanes) is C + i S and at -a (sin lanes) C - i S, the
+            // B operand column b3*16 + row
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
+                if (rb1 * 16 + 4 * t >= n2) break;  // padding k-steps (uniform)
+                double tre[PPW][NB3], tim[PPW][NB3];
+#pragma unroll
+                for (int p = 0; p < PPW; ++p)
+#pragma unroll
+                    for (int b3 = 0; b3 < NB3; ++b3) {
+                        const double r = a1r[p][b3][t], i = a1i[p][b3][t];
+                        const double rp = row_swap8(r), ip = row_swap8(i);
+                        tre[p][b3] = cos_col ? r - ip : rp + i;
+                        tim[p][b3] = cos_col ? i + rp : ip - r;
+                    }
 #pragma unroll
                 for (int b2 = 0; b2 < NB2; ++b2) {
-                    const double2 w = s_w2[((rb1 * 4 + t) * NB2 + b2) * 64 + lane];
-                    const double ws = w.x + w.y;
+                    const double w = s_w2[((rb1 * 4 + t) * NB2 + b2) * 64 + lane];
 #pragma unroll
                     for (int p = 0; p < PPW; ++p)
 #pragma unroll
                         for (int b3 = 0; b3 < NB3; ++b3) {
-                            if constexpr (K3) {
-                                // T1 = (p1 - p2, p3 - p1 - p2); Re T1 + Im T1 = p3 - 2 p2
-                                const double p1 = a1r[p][b3][t], p2 = a1i[p][b3][t],
-                                             p3 = a1s[p][b3][t];
-                                const double tr = p1 - p2, ti = p3 - p1 - p2, ts = p3 - 2.0 * p2;
-                                a2r[p][b2][b3] = mfma_f64(w.x, tr, a2r[p][b2][b3]);
-                                a2i[p][b2][b3] = mfma_f64(w.y, ti, a2i[p][b2][b3]);
-                                a2s[p][b2][b3] = mfma_f64(ws, ts, a2s[p][b2][b3]);
-                            } else {
-                                cmfma(a2r[p][b2][b3], a2i[p][b2][b3], w.x, w.y, a1r[p][b3][t],
-                                      a1i[p][b3][t]);
-                            }
+                            a2r[p][b2][b3] = mfma_f64(w, tre[p][b3], a2r[p][b2][b3]);
+                            a2i[p][b2][b3] = mfma_f64(w, tim[p][b3], a2i[p][b2][b3]);
                         }
                 }
             }
 #pragma unroll
             for (int p = 0; p < PPW; ++p)
 #pragma unroll
-                for (int b3 = 0; b3 < NB3; ++b3) a1r[p][b3] = a1i[p][b3] = a1s[p][b3] = zero4();
+                for (int b3 = 0; b3 < NB3; ++b3) a1r[p][b3] = a1i[p][b3] = zero4();
             if (rb1 == nrb1 - 1) {
+                // a2[p][b2][b3] elements t = 0, 1 of lane l: the cos sums of k2
+                // class 8*b2 + 4*t + kq, elements t + 2 the sin sums, at stage-y
+                // column b3*16 + row.  T2 at k2 = +a is C + i S, at -a C - i S;
+                // s_box[(class slot * 2 + sign) * NB3*16 + column] is its disc index.
 #pragma unroll
                 for (int p = 0; p < PPW; ++p) {
                     if (pok[p]) {
@@ -246,21 +260,21 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 #pragma unroll
                             for (int b3 = 0; b3 < NB3; ++b3)
 #pragma unroll
-                                for (int t = 0; t < 4; ++t) {
-                                    const int d = s_box[(b2 * 16 + 4 * t + kq) * (NB3 * 16) +
-                                                        b3 * 16 + row];
-                                    if (d >= 0) {
-                                        const double p1 = a2r[p][b2][b3][t], p2 = a2i[p][b2][b3][t];
-                                        o[d] = K3 ? make_double2(p1 - p2, a2s[p][b2][b3][t] - p1 - p2)
-                                                  : make_double2(p1, p2);
-                                    }
+                                for (int t = 0; t < 2; ++t) {
+                                    const double cr = a2r[p][b2][b3][t], ci = a2i[p][b2][b3][t];
+                                    const double sr = a2r[p][b2][b3][t + 2],
+                                                 si = a2i[p][b2][b3][t + 2];
+                                    const int e = ((b2 * 8 + 4 * t + kq) * 2) * (NB3 * 16) +
+                                                  b3 * 16 + row;
+                                    const int dp = s_box[e], dm = s_box[e + NB3 * 16];
+                                    if (dp >= 0) o[dp] = make_double2(cr - si, ci + sr);
+                                    if (dm >= 0) o[dm] = make_double2(cr + si, ci - sr);
                                 }
                     }
 #pragma unroll
                     for (int b2 = 0; b2 < NB2; ++b2)
 #pragma unroll
-                        for (int b3 = 0; b3 < NB3; ++b3)
-                            a2r[p][b2][b3] = a2i[p][b2][b3] = a2s[p][b2][b3] = zero4();
+                        for (int b3 = 0; b3 < NB3; ++b3) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
                 }
             }
         }
@@ -276,14 +290,21 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 
 // ---------------------------------------------------------------- kernel 2
 
-// M_box[k1][d] = sum_j1 W1[k1][j1] T2[j1][d] on MFMA: A = x twiddles (LDS,
-// lane order), B = T2 rows (coalesced), output scattered to the G list.
+// M_box[k1][d] = sum_j1 W1[k1][j1] T2[j1][d] on MFMA: A = the real cos | sin
+// rows of 8 k1 classes per block (LDS, lane order), B = the real and the
+// imaginary part of T2 rows (coalesced): two real products per block.  Output
+// row 4 t + kq is element t, so a class's cos sum (t = 0, 1) and sin sum
+// (t = 2, 3) share a lane: M at k1 = +a is C + i S and at -a C - i S,
+// scattered to the G list.
+// Pair k of the launch (k0 + blockIdx.x in the rectangle's row-major order,
+// cw pairs per valence row) is written to output row (k / cw) * ldm + k % cw.
 template <int NB1>
 __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
     const double2* __restrict__ t2, int n1, int n1p, int n23, int n23p,
-    const double2* __restrict__ w1tab, const int* __restrict__ gmap, int ng, double dv,
-    int64_t npairs, double2* __restrict__ m_out) {
-    extern __shared__ double2 s_w1[];
+    const double* __restrict__ w1tab, const int* __restrict__ gmap, int ng, double dv,
+    int64_t npairs, int64_t k0, int cw, int64_t ldm, double2* __restrict__ m_out) {
+    extern __shared__ double2 lds_x[];
+    double* s_w1 = reinterpret_cast<double*>(lds_x);
     const int q1 = n1p >> 2;
     for (int i = threadIdx.x; i < NB1 * q1 * 64; i += kThreads) s_w1[i] = w1tab[i];
     __syncthreads();
@@ -291,7 +312,8 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
     if (k >= npairs) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
     const double2* src = t2 + k * static_cast<int64_t>(n1) * n23;
-    double2* dst = m_out + k * static_cast<int64_t>(ng);
+    const int64_t kg = k0 + k;
+    double2* dst = m_out + ((kg / cw) * ldm + kg % cw) * static_cast<int64_t>(ng);
     const int ndb = n23p >> 4;
     for (int db = wave; db < ndb; db += kWaves) {
         dbl4 ar[NB1], ai[NB1];
@@ -313,8 +335,9 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
                 if (ks < q1) {
 #pragma unroll
                     for (int b = 0; b < NB1; ++b) {
-                        const double2 w = s_w1[(b * q1 + ks) * 64 + lane];
-                        cmfma(ar[b], ai[b], w.x, w.y, xb[u].x, xb[u].y);
+                        const double w = s_w1[(ks * NB1 + b) * 64 + lane];
+                        ar[b] = mfma_f64(w, xb[u].x, ar[b]);
+                        ai[b] = mfma_f64(w, xb[u].y, ai[b]);
                     }
                 }
             }
@@ -322,29 +345,31 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
 #pragma unroll
         for (int b = 0; b < NB1; ++b)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int g = gmap[(b * 16 + 4 * t + kq) * n23p + d];
-                if (g >= 0) dst[g] = make_double2(dv * ar[b][t], dv * ai[b][t]);
+            for (int t = 0; t < 2; ++t) {
+                const double cr = ar[b][t], ci = ai[b][t], sr = ar[b][t + 2], si = ai[b][t + 2];
+                const int e = ((b * 8 + 4 * t + kq) * 2) * n23p + d;
+                const int gp = gmap[e], gm = gmap[e + n23p];
+                if (gp >= 0) dst[gp] = make_double2(dv * (cr - si), dv * (ci + sr));
+                if (gm >= 0) dst[gm] = make_double2(dv * (cr + si), dv * (ci - sr));
             }
     }
 }
 
 using ZyKernel = void (*)(const double2*, const double2*, int64_t, Rect, int, int, int, int, int,
-                          int, const double2*, const double2*, const int*, int, double2*);
+                          int, const double*, const double*, const int*, int, double2*);
 
-// Pairs per wave by the widest box axis (in 16-wide blocks), within the
-// registers of two waves per SIMD; the single-block case uses K3.
+// Pairs per wave by the wider class-block count, within the registers of two
+// waves per SIMD.
+constexpr int zy_ppw(int nb2, int nb3) {
+    return (nb2 > nb3 ? nb2 : nb3) == 1 ? 4 : ((nb2 > nb3 ? nb2 : nb3) == 2 ? 2 : 1);
+}
+
 template <int NB2, int NB3>
 ZyKernel zy_ptr() {
-    constexpr int nb = NB2 > NB3 ? NB2 : NB3;
-    constexpr int ppw = nb == 1 ? 3 : (nb == 2 ? 2 : 1);
-    return &mtxel_zy_kernel<NB2, NB3, ppw, nb == 1>;
+    return &mtxel_zy_kernel<NB2, NB3, zy_ppw(NB2, NB3)>;
 }
 
-int zy_pairs_per_wave(int nb2, int nb3) {
-    const int nb = std::max(nb2, nb3);
-    return nb == 1 ? 3 : (nb == 2 ? 2 : 1);
-}
+int zy_pairs_per_wave(int nb2, int nb3) { return zy_ppw(nb2, nb3); }
 
 ZyKernel select_zy(int nb2, int nb3) {
     static const ZyKernel table[4][4] = {
@@ -356,8 +381,8 @@ ZyKernel select_zy(int nb2, int nb3) {
     return table[nb2 - 1][nb3 - 1];
 }
 
-using XKernel = void (*)(const double2*, int, int, int, int, const double2*, const int*, int,
-                         double, int64_t, double2*);
+using XKernel = void (*)(const double2*, int, int, int, int, const double*, const int*, int,
+                         double, int64_t, int64_t, int, int64_t, double2*);
 
 XKernel select_x(int nb1) {
     static const XKernel table[4] = {&mtxel_x_kernel<1>, &mtxel_x_kernel<2>, &mtxel_x_kernel<3>,
@@ -405,21 +430,38 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
     p->nb3 = ceil_div(p->m3, 16);
     if (p->nb1 > 4 || p->nb2 > 4 || p->nb3 > 4)
         throw Error{-4, "G list spans more than 64 distinct values along an axis (unsupported)"};
+    // frequency classes a = min(k, N - k) along y and z: the forward stages
+    // work on these
+    auto classes = [](const std::vector<int>& l, int nn) {
+        std::set<int> sh;
+        for (int k : l) sh.insert(std::min(k, nn - k));
+        return std::vector<int>(sh.begin(), sh.end());
+    };
+    const std::vector<int> lh1 = classes(l1, n[0]), lh2 = classes(l2, n[1]),
+                           lh3 = classes(l3, n[2]);
+    p->mh1 = static_cast<int>(lh1.size());
+    p->mh2 = static_cast<int>(lh2.size());
+    p->mh3 = static_cast<int>(lh3.size());
+    p->nbh1 = ceil_div(p->mh1, 8);
+    p->nbh2 = ceil_div(p->mh2, 8);
+    p->nbh3 = ceil_div(p->mh3, 8);
+    if (p->nbh1 > 4 || p->nbh2 > 4 || p->nbh3 > 4)
+        throw Error{-4, "G list spans more than 32 classes min(k, N - k) along an axis (unsupported)"};
     p->n2p = ceil_div(n[1], 16) * 16;
     p->n3p = ceil_div(n[2], 16) * 16;
     const int q = p->n3p / 4, nrb1 = p->n2p / 16;
-    const int bw2 = p->nb2 * 16, bw3 = p->nb3 * 16;
+    const int bw2 = p->nb2 * 16, bw3 = p->nb3 * 16, bwh3 = p->nbh3 * 16;
     {
-        const int ppw = zy_pairs_per_wave(p->nb2, p->nb3);
+        const int ppw = zy_pairs_per_wave(p->nbh2, p->nbh3);
         const size_t nbands = 4 + 2 * static_cast<size_t>(ppw);
-        p->lds_yz = (static_cast<size_t>(q) * p->nb3 * 64 + static_cast<size_t>(nrb1) * 4 * p->nb2 * 64 +
-                     static_cast<size_t>(bw2) * bw3 / 4 + nbands * 16 * kRowStride) *
+        p->lds_yz = (static_cast<size_t>(q) * p->nbh3 * 32 + static_cast<size_t>(nrb1) * 4 * p->nbh2 * 32 +
+                     static_cast<size_t>(p->nbh2) * 16 * bwh3 / 4 + nbands * 16 * kRowStride) *
                     sizeof(double2);
     }
     if (p->lds_yz > kMaxLds)
         throw Error{-4, "grid too large for the LDS-resident twiddle operands (unsupported)"};
     p->n1p = ceil_div(n[0], 4) * 4;
-    p->lds_x = static_cast<size_t>(p->nb1) * (p->n1p / 4) * 64 * sizeof(double2);
+    p->lds_x = static_cast<size_t>(p->nbh1) * (p->n1p / 4) * 64 * sizeof(double);
     if (p->lds_x > kMaxLds) throw Error{-4, "N1 too large (unsupported)"};
 
     std::map<int, int> i2, i3;
@@ -433,6 +475,30 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
     for (int i = 0; i < ng; ++i) disc.insert({i2[k2[i]], i3[k3[i]]});
     for (const auto& d : disc) box[d.first * bw3 + d.second] = nd++;
     p->n23 = nd;
+    // forward stage-y outputs: (k2 class slot h2, sign) x column, the column of
+    // block b and slot c giving k3 = +a3 (c < 8) or N3 - a3 (c >= 8) with
+    // a3 = lh3[8 b + (c & 7)]; an output whose (k2, k3) is not in the disc, or
+    // that repeats +a (a = 0 or N/2), is -1
+    auto freq = [](const std::vector<int>& lh, int h, bool minus, int nn) {
+        if (h >= static_cast<int>(lh.size())) return -1;
+        const int a = lh[h];
+        if (minus && (a == 0 || 2 * a == nn)) return -1;
+        return minus ? nn - a : a;
+    };
+    std::vector<int> boxf(static_cast<size_t>(p->nbh2) * 16 * bwh3, -1);
+    for (int h2 = 0; h2 < p->nbh2 * 8; ++h2)
+        for (int sg = 0; sg < 2; ++sg) {
+            const int k2v = freq(lh2, h2, sg == 1, n[1]);
+            const auto it2 = i2.find(k2v);
+            if (k2v < 0 || it2 == i2.end()) continue;
+            for (int col = 0; col < bwh3; ++col) {
+                const int k3v = freq(lh3, (col >> 4) * 8 + (col & 7), (col & 15) >= 8, n[2]);
+                const auto it3 = i3.find(k3v);
+                if (k3v < 0 || it3 == i3.end()) continue;
+                boxf[(static_cast<size_t>(h2) * 2 + sg) * bwh3 + col] =
+                    box[it2->second * bw3 + it3->second];
+            }
+        }
     p->n23p = ceil_div(nd, 16) * 16;
     std::map<int, int> i1;
     for (int i = 0; i < p->m1; ++i) i1[l1[i]] = i;
@@ -441,40 +507,42 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
         g_disc[i] = box[i2[k2[i]] * bw3 + i3[k3[i]]];
         gmap[static_cast<size_t>(i1[k1[i]]) * p->n23p + g_disc[i]] = i;
     }
-    const int q1 = p->n1p / 4;
-    std::vector<double2> w1(static_cast<size_t>(p->nb1) * q1 * 64);
-    for (int b = 0; b < p->nb1; ++b)
-        for (int ks = 0; ks < q1; ++ks)
-            for (int l = 0; l < 64; ++l) {
-                const int kk = b * 16 + (l & 15);
-                const int j1 = 4 * ks + (l >> 4);
-                w1[(static_cast<size_t>(b) * q1 + ks) * 64 + l] =
-                    (j1 < n[0] && kk < p->m1) ? host_root(static_cast<int64_t>(l1[kk]) * j1, n[0])
-                                             : make_double2(0.0, 0.0);
-            }
-
-    std::vector<double2> w3(static_cast<size_t>(q) * p->nb3 * 64);
-    for (int ks = 0; ks < q; ++ks)
-        for (int b3 = 0; b3 < p->nb3; ++b3)
-            for (int l = 0; l < 64; ++l) {
-                const int j3 = 4 * ks + (l >> 4);
-                const int kk = b3 * 16 + (l & 15);
-                w3[(static_cast<size_t>(ks) * p->nb3 + b3) * 64 + l] =
-                    (j3 < n[2] && kk < p->m3) ? host_root(static_cast<int64_t>(l3[kk]) * j3, n[2])
-                                             : make_double2(0.0, 0.0);
-            }
-    std::vector<double2> w2(static_cast<size_t>(nrb1) * 4 * p->nb2 * 64);
-    for (int rb1 = 0; rb1 < nrb1; ++rb1)
-        for (int t = 0; t < 4; ++t)
-            for (int b2 = 0; b2 < p->nb2; ++b2)
+    // real twiddle operands of the forward stages: lane l of k-step s, block b
+    // holds, for j = 4 s + l/16 and class a = lh[8 b + (l & 7)], cos(2 pi a j/N)
+    // (l & 15 < 8) or the sine (exactly 0 for a = 0 and a = N/2); zero past
+    // the grid or the classes.  Stage z takes it as B (class = column), stage
+    // y as A (class = row): the same lane layout.
+    auto real_tab = [](const std::vector<int>& lh, int nbh, int nks, int nn) {
+        std::vector<double> w(static_cast<size_t>(nks) * nbh * 64, 0.0);
+        for (int s = 0; s < nks; ++s)
+            for (int b = 0; b < nbh; ++b)
                 for (int l = 0; l < 64; ++l) {
-                    const int kk = b2 * 16 + (l & 15);
-                    const int j2 = rb1 * 16 + 4 * t + (l >> 4);
-                    w2[((static_cast<size_t>(rb1) * 4 + t) * p->nb2 + b2) * 64 + l] =
-                        (j2 < n[1] && kk < p->m2)
-                            ? host_root(static_cast<int64_t>(l2[kk]) * j2, n[1])
-                            : make_double2(0.0, 0.0);
+                    const int j = 4 * s + (l >> 4);
+                    const int h = b * 8 + (l & 7);
+                    if (j >= nn || h >= static_cast<int>(lh.size())) continue;
+                    const int a = lh[h];
+                    const double2 r = host_root(static_cast<int64_t>(a) * j, nn);
+                    const bool sine = (l & 15) >= 8;
+                    w[(static_cast<size_t>(s) * nbh + b) * 64 + l] =
+                        sine ? ((a == 0 || 2 * a == nn) ? 0.0 : r.y) : r.x;
                 }
+        return w;
+    };
+    const std::vector<double> w3 = real_tab(lh3, p->nbh3, q, n[2]);
+    const std::vector<double> w2 = real_tab(lh2, p->nbh2, nrb1 * 4, n[1]);
+    const std::vector<double> w1 = real_tab(lh1, p->nbh1, p->n1p / 4, n[0]);
+    // forward stage-x outputs: (k1 class slot, sign: 0 for k1 = a, 1 for k1 = N1 - a,
+    // a != 0, N1/2) x disc index -> G index
+    std::vector<int> gmapf(static_cast<size_t>(p->nbh1) * 16 * p->n23p, -1);
+    {
+        std::map<int, int> ih1;
+        for (int h = 0; h < p->mh1; ++h) ih1[lh1[h]] = h;
+        for (int i = 0; i < ng; ++i) {
+            const int a = std::min(k1[i], n[0] - k1[i]);
+            const int sg = k1[i] == a ? 0 : 1;
+            gmapf[(static_cast<size_t>(ih1[a]) * 2 + sg) * p->n23p + g_disc[i]] = i;
+        }
+    }
     // adjoint tables, in the lane layouts of the transposed stages:
     //   x: U[j1][d]   = sum_k1 conj(e^{2 pi i k1 j1/N1}) B[k1][d]   (A = W1inv[j1][k1])
     //   z: T[k2][j3]  = sum_k3 Ubox[k2][k3] conj(e^{2 pi i k3 j3/N3}) (B = W3inv[k3][j3])
@@ -514,10 +582,12 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
                                              : make_double2(0.0, 0.0);
             }
 
-    p->w1tab = upload(w1);
+    p->w1re = upload(w1);
+    p->gmapf = upload(gmapf);
     p->gmap = upload(gmap);
-    p->w3tab = upload(w3);
-    p->w2tab = upload(w2);
+    p->w3re = upload(w3);
+    p->w2re = upload(w2);
+    p->boxf = upload(boxf);
     p->boxmap = upload(box);
     p->w1inv = upload(w1i);
     p->w2inv = upload(w2i);
@@ -528,16 +598,19 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
 }  // namespace
 
 void MtxelPlan::release() {
-    (void)hipFree(w1tab);
+    (void)hipFree(w1re);
+    (void)hipFree(gmapf);
     (void)hipFree(gmap);
-    (void)hipFree(w3tab);
-    (void)hipFree(w2tab);
+    (void)hipFree(w3re);
+    (void)hipFree(boxf);
+    (void)hipFree(w2re);
     (void)hipFree(boxmap);
     (void)hipFree(w1inv);
     (void)hipFree(w2inv);
     (void)hipFree(w3inv);
-    w1tab = w3tab = w2tab = w1inv = w2inv = w3inv = nullptr;
-    gmap = boxmap = nullptr;
+    w1inv = w2inv = w3inv = nullptr;
+    w1re = w2re = w3re = nullptr;
+    gmapf = gmap = boxf = boxmap = nullptr;
     if (last_use) (void)hipEventDestroy(last_use);
     last_use = nullptr;
 }
@@ -596,11 +669,12 @@ size_t t2_elems(const MtxelPlan& p, int64_t npairs) {
 }
 
 void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c, Rect rc,
-                  double volume, double2* t2, double2* m_out, hipStream_t s) {
+                  double volume, double2* t2, double2* m_out, hipStream_t s, int64_t ldm) {
+    if (ldm == 0) ldm = rc.nc;
     const int64_t npairs = static_cast<int64_t>(rc.nv) * rc.nc;
     if (npairs <= 0) return;
-    ZyKernel kz = select_zy(p.nb2, p.nb3);
-    const int ppw = zy_pairs_per_wave(p.nb2, p.nb3);
+    ZyKernel kz = select_zy(p.nbh2, p.nbh3);
+    const int ppw = zy_pairs_per_wave(p.nbh2, p.nbh3);
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kz),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(p.lds_yz)));
@@ -613,10 +687,10 @@ void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c
         const dim3 grid(gx, gy, ceil_div(p.n[0], pp));
         ProfScope ps("mtxel_zy", s);
         hipLaunchKernelGGL(kz, grid, dim3(kZyThreads), p.lds_yz, s, psi_v, psi_c, p.nr, rc, p.n[0],
-                           pp, p.n[1], p.n[2], p.n2p, p.n3p, p.w3tab, p.w2tab, p.boxmap, p.n23, t2);
+                           pp, p.n[1], p.n[2], p.n2p, p.n3p, p.w3re, p.w2re, p.boxf, p.n23, t2);
         GW_HIP_TRY(hipGetLastError());
     }
-    XKernel kx = select_x(p.nb1);
+    XKernel kx = select_x(p.nbh1);
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kx),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(p.lds_x)));
@@ -626,7 +700,7 @@ void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c
         ProfScope ps("mtxel_x", s);
         hipLaunchKernelGGL(kx, dim3(static_cast<unsigned>(kb)), dim3(kThreads), p.lds_x, s,
                            t2 + k0 * static_cast<int64_t>(p.n[0]) * p.n23, p.n[0], p.n1p, p.n23,
-                           p.n23p, p.w1tab, p.gmap, p.ng, dv, kb, m_out + k0 * p.ng);
+                           p.n23p, p.w1re, p.gmapf, p.ng, dv, kb, k0, rc.nc, ldm, m_out);
         GW_HIP_TRY(hipGetLastError());
     }
 }

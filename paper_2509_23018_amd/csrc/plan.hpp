@@ -32,12 +32,22 @@ struct Rect {
 //   stage y : T2[j1][k2][k3]  = sum_j2 e^{+2 pi i k2 j2/N2} T1[j1][j2][k3]
 //             (kept only on the "disc", the distinct (k2,k3) of the G list)
 //   stage x : M(G)            = dV * sum_j1 e^{+2 pi i k1 j1/N1} T2[j1][disc(G)]
+// The forward stages z and y run on real twiddles: with a = min(k, N - k) the
+// class of a frequency k, C_a = sum_j cos(2 pi a j/N) x_j and S_a = sum_j
+// sin(2 pi a j/N) x_j give the transform at k = a as C_a + i S_a and at
+// k = N - a as C_a - i S_a, so a pair of conjugate frequencies costs two
+// products with real coefficients instead of two complex ones.  Classes are
+// packed 8 to a 16-wide block: slot c < 8 holds the cosine of class 8b + c,
+// slot c + 8 its sine (stage z: columns of the B operand, stages y and x: rows
+// of the A operand).
 struct MtxelPlan {
     int n[3] = {0, 0, 0};
     int64_t nr = 0;
     int ng = 0;
     int m1 = 0, m2 = 0, m3 = 0;    // distinct k1, k2, k3 values
     int nb1 = 0, nb2 = 0, nb3 = 0; // 16-wide blocks covering them
+    int mh1 = 0, mh2 = 0, mh3 = 0;    // distinct k1, k2, k3 classes min(k, N - k)
+    int nbh1 = 0, nbh2 = 0, nbh3 = 0; // 8-class blocks covering them (forward stages x, y, z)
     int n1p = 0;          // N1 rounded up to 4
     int n23p = 0;         // disc size rounded up to 16
     int n2p = 0, n3p = 0; // N2 rounded up to 16, N3 rounded up to 16
@@ -48,11 +58,13 @@ struct MtxelPlan {
     std::vector<int32_t> gvec;  // host copy (cache key)
 
     // device tables (owned)
-    double2* w1tab = nullptr;   // [nb1][n1p/4][64]      stage-x MFMA A operand, lane layout
-    int* gmap = nullptr;        // [nb1*16][n23p] -> G index or -1
-    double2* w3tab = nullptr;   // [n3p/4][nb3][64]      stage-z MFMA B operand, lane layout
-    double2* w2tab = nullptr;   // [n2p/16][4][nb2][64]  stage-y MFMA A operand, lane layout
-    int* boxmap = nullptr;      // [nb2*16][nb3*16] -> disc index or -1
+    double* w1re = nullptr;     // [nbh1][n1p/4][64]     stage-x MFMA A operand (cos | sin), lane layout
+    int* gmapf = nullptr;       // [nbh1*8][2][n23p] (k1 class, sign, disc index) -> G index or -1
+    int* gmap = nullptr;        // [nb1*16][n23p] (k1 index, disc index) -> G index or -1
+    double* w3re = nullptr;     // [n3p/4][nbh3][64]     stage-z MFMA B operand (cos | sin), lane layout
+    double* w2re = nullptr;     // [n2p/4][nbh2][64]     stage-y MFMA A operand (cos | sin), lane layout
+    int* boxf = nullptr;        // [nbh2*8][2][nbh3*16] (k2 class, sign, stage-y column) -> disc or -1
+    int* boxmap = nullptr;      // [nb2*16][nb3*16] (k2, k3) index -> disc index or -1
     // used by the adjoint (the transposed stages, conjugate twiddles)
     int n1p16 = 0;              // N1 rounded up to 16
     double2* w1inv = nullptr;   // [n1p16/16][nb1*4][64]  adjoint stage-x MFMA A operand
@@ -78,10 +90,11 @@ PlanRef get_plan(const int n[3], const int32_t* gvec, int ng);
 void mark_plan_used(MtxelPlan& p, hipStream_t s);
 void release_plans();
 
-// MTXEL launches: m_out[k][i] = M_{pair k}(G_i) for the pairs of rc, in row
-// order k = (v - v0)*nc + (c - c0).  t2 is scratch of t2_elems(plan, pairs).
+// MTXEL launches: m_out[k][i] = M_{pair k}(G_i) for the pairs of rc, at output
+// row k = (v - v0)*ldm + (c - c0) (ldm = 0: rc.nc, the rectangle's own
+// row-major order).  t2 is scratch of t2_elems(plan, pairs).
 size_t t2_elems(const MtxelPlan& p, int64_t npairs);
 void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c, Rect rc,
-                  double volume, double2* t2, double2* m_out, hipStream_t s);
+                  double volume, double2* t2, double2* m_out, hipStream_t s, int64_t ldm = 0);
 
 }  // namespace gw

@@ -52,6 +52,21 @@ def test_mtxel_full_grid_and_pair_range():
     assert rel_fro(m, ref) < FP64_TOL
 
 
+def test_mtxel_pair_range_rectangles():
+    """A pair range that starts and ends inside a row and spans whole rows of
+    more than 1,024 conduction bands: it is cut into a partial row, blocks of 4
+    valence bands split into column ranges, a single row and a partial row,
+    written at their places in the linear pair order."""
+    n = (8, 6, 5)
+    nv, nc = 7, 1100
+    p = gen.make_problem(n, nv, nc, r2=3, seed=11, orthonormalize=False)
+    b, cnt = 1000, 6 * nc + 50
+    m = gw.gw_mtxel(_dev(p.psi_v), _dev(p.psi_c), p.gvec, n, p.volume, pair_begin=b,
+                    pair_count=cnt).cpu().numpy()
+    ref = oracle.mtxel(p.psi_v, p.psi_c, p.gvec, n, p.volume, pairs=range(b, b + cnt))
+    assert rel_fro(m, ref) < FP64_TOL
+
+
 def test_mtxel_plane_waves_exact():
     n = (16, 12, 10)
     kv = [(0, 0, 0), (3, -2, 4), (-8, 5, -5)]
