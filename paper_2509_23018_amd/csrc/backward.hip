@@ -284,90 +284,145 @@ __global__ __launch_bounds__(256) void de_reduce_kernel(const double* __restrict
 // taken as the forward stages transposed, on FP64 MFMA 16x16x4 with twiddle
 // operands read in lane order from the plan (A lane l: [row l%16][k l/16];
 // B lane l: [k l/16][col l%16]; D element t of lane l: [4t + l/16][l%16]).
+// Each axis sums over frequency classes a = min(k, N - k): the two
+// frequencies of a class enter as
+//   X(+a) e^{-i th} + X(-a) e^{+i th} = P cos th + Q sin th,
+//   P = X(+a) + X(-a),  Q = -i (X(+a) - X(-a)),  th = 2 pi a j/N,
+// so every stage multiplies by real cos | sin twiddles (two real MFMA
+// products per block).  A block's 16 slots are the cos (slots 0-7) and sin
+// (8-15) slots of 8 classes; a lane's k index kq meets slot 4 s + kq at
+// k-step s, so the P of the classes kq and 4 + kq (k-steps 0, 1) and their
+// Q (k-steps 2, 3) come from the same two pairs of values.
 
-// Stage x, one workgroup per pair: U[k][j1][d] = sum_k1 conj(e^{2 pi i k1 j1/N1})
-// B[k1][d], with B[k1][d] = g_M[k][G] for the G at (k1, disc d), else 0.  The
-// 4 waves take (16 j1) x (16 d) output blocks in turn.
+// -i x
+__device__ __forceinline__ double2 mul_mi(double2 x) { return make_double2(x.y, -x.x); }
+
+// The A or B operand of the 4 k-steps of a class block from the values of
+// the lane's two classes: x[0], x[1] at +a, x[2], x[3] at -a.
+__device__ __forceinline__ void pq_block(const double2 (&x)[4], double2 (&o)[4]) {
+    o[0] = make_double2(x[0].x + x[2].x, x[0].y + x[2].y);
+    o[1] = make_double2(x[1].x + x[3].x, x[1].y + x[3].y);
+    o[2] = mul_mi(make_double2(x[0].x - x[2].x, x[0].y - x[2].y));
+    o[3] = mul_mi(make_double2(x[1].x - x[3].x, x[1].y - x[3].y));
+}
+
+// Stage x, one workgroup per pair: U[k][j1][d] = sum over k1 of
+// e^{-2 pi i k1 j1/N1} g_M[k][G(k1, d)] (0 where (k1, d) is no G).  The 4 waves
+// take (16 j1) x (16 d) output blocks in turn; B[slot][d] is formed from the
+// G values at +-a1 (gmapf: (class, sign, d) -> G).
 __global__ __launch_bounds__(256) void bwd_x_kernel(const double2* __restrict__ gm, int ng, int n1,
-                                                    int n1b, int ks1, int n23, int n23p,
-                                                    const double2* __restrict__ w1inv,
-                                                    const int* __restrict__ gmap,
+                                                    int n1b, int nbh1, int n23, int n23p,
+                                                    const double* __restrict__ w1ir,
+                                                    const int* __restrict__ gmapf,
                                                     double2* __restrict__ u) {
     const int64_t k = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
     const double2* src = gm + k * ng;
     double2* dst = u + k * n1 * n23;
     const int ndb = n23p >> 4;
+    const int ks1 = nbh1 * 4;
     for (int tile = wave; tile < n1b * ndb; tile += 4) {
         const int rb = tile / ndb, db = tile - rb * ndb;
+        const int d = db * 16 + row;
         dbl4 ar = zero4(), ai = zero4();
-        for (int s = 0; s < ks1; ++s) {
-            const double2 a = w1inv[(rb * ks1 + s) * 64 + lane];
-            const int g = gmap[(4 * s + kq) * n23p + db * 16 + row];
-            const double2 b = g >= 0 ? src[g] : make_double2(0.0, 0.0);
-            cmfma(ar, ai, a.x, a.y, b.x, b.y);
+        for (int b = 0; b < nbh1; ++b) {
+            double2 x[4], bo[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // i = 0, 1: classes 8b + kq, 8b + 4 + kq at +a; i = 2, 3 at -a
+                const int g = gmapf[((8 * b + 4 * (i & 1) + kq) * 2 + (i >> 1)) * n23p + d];
+                x[i] = g >= 0 ? src[g] : make_double2(0.0, 0.0);
+            }
+            pq_block(x, bo);
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl) {
+                const double a = w1ir[(rb * ks1 + 4 * b + sl) * 64 + lane];
+                ar = mfma_f64(a, bo[sl].x, ar);
+                ai = mfma_f64(a, bo[sl].y, ai);
+            }
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int j1 = rb * 16 + 4 * t + kq, d = db * 16 + row;
+            const int j1 = rb * 16 + 4 * t + kq;
             if (j1 < n1 && d < n23) dst[j1 * n23 + d] = make_double2(ar[t], ai[t]);
         }
     }
 }
 
+// Stage z of one plane, j3 block nb and k2 block b2: T[k2 row][j3] =
+// sum over k3 of U(k2, k3) e^{-2 pi i k3 j3/N3}, the A operand formed from U at
+// (k2 of the lane's row, +-a3) (boxi), the B operand the real inverse z
+// twiddles.  Rows of T: slot r < 8 is k2 = +a2 of class 8 b2 + r, r >= 8 is
+// -a2 of class 8 b2 + r - 8, so a T element t (t = 0, 1) and t + 2 are the
+// two frequencies of one k2 class.
+template <int NB3>
+__device__ __forceinline__ void inv_stage_z(const double2* __restrict__ urow,
+                                            const int* __restrict__ boxi, const double* __restrict__ w3ir,
+                                            int b2, int nb, int nj3, int lane, int row, int kq,
+                                            dbl4& tr, dbl4& ti) {
+#pragma unroll
+    for (int b3 = 0; b3 < NB3; ++b3) {
+        double2 x[4], ao[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int d = boxi[(b2 * 16 + row) * (NB3 * 16) + b3 * 16 + 4 * i + kq];
+            x[i] = d >= 0 ? urow[d] : make_double2(0.0, 0.0);
+        }
+        pq_block(x, ao);
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+            const double b = w3ir[((4 * b3 + sl) * nj3 + nb) * 64 + lane];
+            tr = mfma_f64(ao[sl].x, b, tr);
+            ti = mfma_f64(ao[sl].y, b, ti);
+        }
+    }
+}
+
+// Stage y of one (j2 block rb, j3 block): g_rho[j2][j3] += sum over k2 of
+// e^{-2 pi i k2 j2/N2} T[k2][j3]: the B operand of k-step t is P (t = 0, 1) or
+// Q (t = 2, 3) of the k2 classes 8 b2 + 4 (t & 1) + kq, formed in the lane from
+// T elements t & 1 and (t & 1) + 2.
+__device__ __forceinline__ void inv_stage_y(const dbl4& tr, const dbl4& ti, const double* __restrict__ w2ir,
+                                            int rb, int ks2, int b2, int lane, dbl4& gr, dbl4& gi) {
+    double2 x[4], bo[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = make_double2(tr[t], ti[t]);
+    pq_block(x, bo);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double a = w2ir[(rb * ks2 + b2 * 4 + t) * 64 + lane];
+        gr = mfma_f64(a, bo[t].x, gr);
+        gi = mfma_f64(a, bo[t].y, gi);
+    }
+}
+
 // Stages z and y, one workgroup per pair, wave w taking the planes j1 = w,
-// w + 4, ...  Per plane and 16-wide block of j3:
-//   T[k2][j3]     = sum_k3 Ubox[k2][k3] conj(e^{2 pi i k3 j3/N3})
-//                   (Ubox = this plane's U placed on the (k2, k3) box)
-//   g_rho[j2][j3] = dV sum_k2 conj(e^{2 pi i k2 j2/N2}) T[k2][j3]
-// The accumulators of T (rows k2 = 4t + l/16) are the B operands of the
-// second product as they stand.
-template <int NB2>
+// w + 4, ...: per plane and 16-wide block of j3, T for every k2 block (stage
+// z), then each 16-row block of j2 (stage y).
+template <int NB2, int NB3>
 __global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__ u, int n1, int n2,
-                                                     int n3, int n23, int nb3, int nj2, int nj3,
-                                                     const double2* __restrict__ w2inv,
-                                                     const double2* __restrict__ w3inv,
-                                                     const int* __restrict__ boxmap, int64_t nr,
+                                                     int n3, int n23, int nj2, int nj3,
+                                                     const double* __restrict__ w2ir,
+                                                     const double* __restrict__ w3ir,
+                                                     const int* __restrict__ boxi, int64_t nr,
                                                      double dv, double2* __restrict__ grho) {
     const int64_t k = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
-    const int bw3 = nb3 * 16, ks3 = nb3 * 4;
     constexpr int KS2 = NB2 * 4;
     for (int j1 = wave; j1 < n1; j1 += 4) {
         const double2* urow = u + (k * n1 + j1) * n23;
         double2* out = grho + k * nr + static_cast<int64_t>(j1) * n2 * n3;
         for (int nb = 0; nb < nj3; ++nb) {
-            // both products take each complex a b as three real MFMA products
-            // (Karatsuba: p1 = a.x b.x, p2 = a.y b.y, p3 = (a.x + a.y)(b.x + b.y);
-            // Re = p1 - p2, Im = p3 - p1 - p2)
-            dbl4 t1[NB2], t2[NB2], t3[NB2];
+            dbl4 tr[NB2], ti[NB2];
 #pragma unroll
-            for (int b2 = 0; b2 < NB2; ++b2) t1[b2] = t2[b2] = t3[b2] = zero4();
-            for (int s = 0; s < ks3; ++s) {
-                const double2 b = w3inv[(s * nj3 + nb) * 64 + lane];
-                const double bs = b.x + b.y;
-#pragma unroll
-                for (int b2 = 0; b2 < NB2; ++b2) {
-                    const int d = boxmap[(b2 * 16 + row) * bw3 + 4 * s + kq];
-                    const double2 a = d >= 0 ? urow[d] : make_double2(0.0, 0.0);
-                    t1[b2] = mfma_f64(a.x, b.x, t1[b2]);
-                    t2[b2] = mfma_f64(a.y, b.y, t2[b2]);
-                    t3[b2] = mfma_f64(a.x + a.y, bs, t3[b2]);
-                }
+            for (int b2 = 0; b2 < NB2; ++b2) {
+                tr[b2] = ti[b2] = zero4();
+                inv_stage_z<NB3>(urow, boxi, w3ir, b2, nb, nj3, lane, row, kq, tr[b2], ti[b2]);
             }
             for (int rb = 0; rb < nj2; ++rb) {
-                dbl4 g1 = zero4(), g2 = zero4(), g3 = zero4();
+                dbl4 gr = zero4(), gi = zero4();
 #pragma unroll
-                for (int b2 = 0; b2 < NB2; ++b2)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const double2 a = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
-                        // T = (p1 - p2, p3 - p1 - p2), Re T + Im T = p3 - 2 p2
-                        const double p1 = t1[b2][t], p2 = t2[b2][t], p3 = t3[b2][t];
-                        g1 = mfma_f64(a.x, p1 - p2, g1);
-                        g2 = mfma_f64(a.y, p3 - p1 - p2, g2);
-                        g3 = mfma_f64(a.x + a.y, p3 - 2.0 * p2, g3);
-                    }
+                for (int b2 = 0; b2 < NB2; ++b2) inv_stage_y(tr[b2], ti[b2], w2ir, rb, KS2, b2, lane, gr, gi);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int j2 = rb * 16 + 4 * t + kq, j3 = nb * 16 + row;
@@ -375,8 +430,8 @@ __global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__
                         // g_rho is read back by a later kernel, from HBM: the
                         // stores are non-temporal
                         double* q = reinterpret_cast<double*>(out + j2 * n3 + j3);
-                        __builtin_nontemporal_store(dv * (g1[t] - g2[t]), q);
-                        __builtin_nontemporal_store(dv * (g3[t] - g1[t] - g2[t]), q + 1);
+                        __builtin_nontemporal_store(dv * gr[t], q);
+                        __builtin_nontemporal_store(dv * gi[t], q + 1);
                     }
                 }
             }
@@ -404,23 +459,21 @@ constexpr int kPassV = 2;   // valence bands per pass of the fused inverse trans
 // registers), and T is formed again for each j2 block it feeds (a third more
 // MFMA work on a plane of two j2 blocks), against 2 x 16 bytes per point and
 // pair of HBM traffic when g_rho is stored and read back.
-// On the smallest box (one 16-wide block on the y and z axes) everything that
+// On the smallest box (one class block on the y and z axes) everything that
 // does not depend on the pair (the box map, both twiddle operands) is read
-// once per block into registers, and the stage-z operand of the next pair is
+// once per block into registers, and the stage-z values of the next pair are
 // loaded while the current pair's MFMAs run; larger boxes read them per
-// k-step, and take the valence bands two at a time, to stay within the
-// registers.
+// k-step.
 template <int NB2, int NB3>
 __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
     const double2* __restrict__ u, int n1, int n2, int n3, int n23, int nj2, int nj3,
-    const double2* __restrict__ w2inv, const double2* __restrict__ w3inv,
-    const int* __restrict__ boxmap, int64_t nr, double dv, const double2* __restrict__ psi_v,
+    const double* __restrict__ w2ir, const double* __restrict__ w3ir,
+    const int* __restrict__ boxi, int64_t nr, double dv, const double2* __restrict__ psi_v,
     const double2* __restrict__ psi_c, int v0, int c0, int cw, int vcount,
     double2* __restrict__ gpc, double2* __restrict__ vpart) {
-    constexpr int KS3 = NB3 * 4, KS2 = NB2 * 4, BW3 = NB3 * 16;
+    constexpr int KS2 = NB2 * 4;
     constexpr bool HOIST = NB2 * NB3 == 1;
     constexpr int PV = kPassV;  // valence bands per pass
-    constexpr int KH = HOIST ? KS3 : 1, NH = HOIST ? NB2 : 1;  // hoisted array extents
     const int j1 = blockIdx.x, cb = blockIdx.y;
     const int cl0 = cb * kFuseC, ncl = min(cw, cl0 + kFuseC) - cl0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
@@ -436,34 +489,27 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
             ok[t] = j2 < n2 && j3 < n3;
             pos[t] = ok[t] ? plane + static_cast<int64_t>(j2) * n3 + j3 : 0;
         }
-        int bm[KH][NH];
-        double2 w3[KH], w2[NH][4];
+        // HOIST: the box entries and both twiddle operands of the one class block
+        int bm[4];
+        double w3[4], w2[4];
         if constexpr (HOIST) {
 #pragma unroll
-            for (int s = 0; s < KS3; ++s) {
-                w3[s] = w3inv[(s * nj3 + nb) * 64 + lane];
-#pragma unroll
-                for (int b2 = 0; b2 < NB2; ++b2)
-                    bm[s][b2] = boxmap[(b2 * 16 + row) * BW3 + 4 * s + kq];
+            for (int i = 0; i < 4; ++i) {
+                bm[i] = boxi[row * 16 + 4 * i + kq];
+                w3[i] = w3ir[(i * nj3 + nb) * 64 + lane];
+                w2[i] = w2ir[(rb * KS2 + i) * 64 + lane];
             }
-#pragma unroll
-            for (int b2 = 0; b2 < NB2; ++b2)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) w2[b2][t] = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
         }
-        // stage-z operand of pair (vl, cl) on this plane (HOIST only)
-        auto load_a = [&](int vl, int cl, double2 (&a)[KH][NH]) {
+        // stage-z values of pair (vl, cl) on this plane (HOIST only)
+        auto load_x = [&](int vl, int cl, double2 (&x)[4]) {
             const double2* urow =
                 u + ((static_cast<int64_t>(vl) * cw + cl0 + cl) * n1 + j1) * n23;
 #pragma unroll
-            for (int s = 0; s < KH; ++s)
-#pragma unroll
-                for (int b2 = 0; b2 < NH; ++b2) {
-                    const int d = bm[s][b2];
-                    const double2* src = urow + (d >= 0 ? d : 0);
-                    a[s][b2].x = src->x;
-                    a[s][b2].y = src->y;
-                }
+            for (int i = 0; i < 4; ++i) {
+                const double2* src = urow + (bm[i] >= 0 ? bm[i] : 0);
+                x[i].x = src->x;
+                x[i].y = src->y;
+            }
         };
         for (int vp = 0; vp < vcount; vp += PV) {
             const int nvp = min(PV, vcount - vp);
@@ -477,8 +523,8 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
             // points, loaded with its first pair (the MFMAs of that pair, and of
             // the band's other pairs, run before they are used)
             double2 pc[4], ac[4], go[4];
-            double2 acur[KH][NH], anext[KH][NH];
-            if constexpr (HOIST) load_a(vp, 0, acur);
+            double2 xcur[4], xnext[4];
+            if constexpr (HOIST) load_x(vp, 0, xcur);
             for (int q = 0; q < nq; ++q) {
                 const int cl = q / nvp, i = q - cl * nvp;
                 if (i == 0) {
@@ -493,69 +539,56 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
                 if constexpr (HOIST) {
                     if (q + 1 < nq) {
                         const int cn = (q + 1) / nvp;
-                        load_a(vp + (q + 1 - cn * nvp), cn, anext);
+                        load_x(vp + (q + 1 - cn * nvp), cn, xnext);
                     }
                 }
                 const double2* pvr = psi_v + static_cast<int64_t>(v0 + vp + i) * nr;
                 double2 pv[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) pv[t] = pvr[pos[t]];
-                // stage z: T[k2][j3] for this j3 block (three real products
-                // per complex one, as in bwd_yz_kernel)
-                dbl4 t1[NB2], t2[NB2], t3[NB2];
+                dbl4 gr = zero4(), gi = zero4();
+                if constexpr (HOIST) {
+                    // stage z on the one class block, then stage y
+                    double2 x[4], ao[4];
 #pragma unroll
-                for (int b2 = 0; b2 < NB2; ++b2) t1[b2] = t2[b2] = t3[b2] = zero4();
-                const double2* urow =
-                    u + ((static_cast<int64_t>(vp + i) * cw + cl0 + cl) * n1 + j1) * n23;
-                constexpr int UNR = HOIST ? KS3 : 2;  // bounded unrolling on large boxes
-#pragma unroll UNR
-                for (int s = 0; s < KS3; ++s) {
-                    double2 b;
-                    if constexpr (HOIST)
-                        b = w3[s];
-                    else
-                        b = w3inv[(s * nj3 + nb) * 64 + lane];
-                    const double bs = b.x + b.y;
+                    for (int ii = 0; ii < 4; ++ii)
+                        x[ii] = bm[ii] >= 0 ? xcur[ii] : make_double2(0.0, 0.0);
+                    pq_block(x, ao);
+                    dbl4 tr = zero4(), ti = zero4();
 #pragma unroll
-                    for (int b2 = 0; b2 < NB2; ++b2) {
-                        double2 a;
-                        if constexpr (HOIST) {
-                            a = bm[s][b2] >= 0 ? acur[s][b2] : make_double2(0.0, 0.0);
-                        } else {
-                            const int d = boxmap[(b2 * 16 + row) * BW3 + 4 * s + kq];
-                            a = d >= 0 ? urow[d] : make_double2(0.0, 0.0);
-                        }
-                        t1[b2] = mfma_f64(a.x, b.x, t1[b2]);
-                        t2[b2] = mfma_f64(a.y, b.y, t2[b2]);
-                        t3[b2] = mfma_f64(a.x + a.y, bs, t3[b2]);
+                    for (int sl = 0; sl < 4; ++sl) {
+                        tr = mfma_f64(ao[sl].x, w3[sl], tr);
+                        ti = mfma_f64(ao[sl].y, w3[sl], ti);
                     }
-                }
-                // stage y: the g_rho block
-                dbl4 g1 = zero4(), g2 = zero4(), g3 = zero4();
+                    double2 y[4], bo[4];
 #pragma unroll
-                for (int b2 = 0; b2 < NB2; ++b2)
+                    for (int t = 0; t < 4; ++t) y[t] = make_double2(tr[t], ti[t]);
+                    pq_block(y, bo);
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        double2 a;
-                        if constexpr (HOIST)
-                            a = w2[b2][t];
-                        else
-                            a = w2inv[(rb * KS2 + b2 * 4 + t) * 64 + lane];
-                        const double p1 = t1[b2][t], p2 = t2[b2][t], p3 = t3[b2][t];
-                        g1 = mfma_f64(a.x, p1 - p2, g1);
-                        g2 = mfma_f64(a.y, p3 - p1 - p2, g2);
-                        g3 = mfma_f64(a.x + a.y, p3 - 2.0 * p2, g3);
+                        gr = mfma_f64(w2[t], bo[t].x, gr);
+                        gi = mfma_f64(w2[t], bo[t].y, gi);
                     }
+                } else {
+                    const double2* urow =
+                        u + ((static_cast<int64_t>(vp + i) * cw + cl0 + cl) * n1 + j1) * n23;
+#pragma unroll 1
+                    for (int b2 = 0; b2 < NB2; ++b2) {
+                        dbl4 tr = zero4(), ti = zero4();
+                        inv_stage_z<NB3>(urow, boxi, w3ir, b2, nb, nj3, lane, row, kq, tr, ti);
+                        inv_stage_y(tr, ti, w2ir, rb, KS2, b2, lane, gr, gi);
+                    }
+                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const double gr = dv * (g1[t] - g2[t]), gi = dv * (g3[t] - g1[t] - g2[t]);
-                    ac[t].x += pv[t].x * gr - pv[t].y * gi;  // psi_v g
-                    ac[t].y += pv[t].x * gi + pv[t].y * gr;
+                    const double g_r = dv * gr[t], g_i = dv * gi[t];
+                    ac[t].x += pv[t].x * g_r - pv[t].y * g_i;  // psi_v g
+                    ac[t].y += pv[t].x * g_i + pv[t].y * g_r;
 #pragma unroll
                     for (int ii = 0; ii < PV; ++ii)
                         if (ii == i) {
-                            av[ii][t].x += pc[t].x * gr + pc[t].y * gi;  // psi_c conj(g)
-                            av[ii][t].y += pc[t].y * gr - pc[t].x * gi;
+                            av[ii][t].x += pc[t].x * g_r + pc[t].y * g_i;  // psi_c conj(g)
+                            av[ii][t].y += pc[t].y * g_r - pc[t].x * g_i;
                         }
                 }
                 if (i == nvp - 1 && gpc)
@@ -566,9 +599,7 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
                                 make_double2(go[t].x + ac[t].x, go[t].y + ac[t].y);
                 if constexpr (HOIST) {
 #pragma unroll
-                    for (int s = 0; s < KS3; ++s)
-#pragma unroll
-                        for (int b2 = 0; b2 < NB2; ++b2) acur[s][b2] = anext[s][b2];
+                    for (int ii = 0; ii < 4; ++ii) xcur[ii] = xnext[ii];
                 }
             }
             if (vpart)
@@ -871,8 +902,8 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             {
                 ProfScope ps("bwd_x", s);
                 hipLaunchKernelGGL(bwd_x_kernel, dim3(static_cast<unsigned>(kc)), dim3(256), 0, s,
-                                   gm, ng, n1, plan.n1p16 / 16, plan.nb1 * 4, plan.n23, plan.n23p,
-                                   plan.w1inv, plan.gmap, t2);
+                                   gm, ng, n1, plan.n1p16 / 16, plan.nbh1, plan.n23, plan.n23p,
+                                   plan.w1ir, plan.gmapf, t2);
                 GW_HIP_TRY(hipGetLastError());
             }
             const int nj2 = plan.n2p / 16, nj3 = plan.n3p / 16;
@@ -890,10 +921,10 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                          bwd_yz_reduce_kernel<3, 3>, bwd_yz_reduce_kernel<3, 4>},
                         {bwd_yz_reduce_kernel<4, 1>, bwd_yz_reduce_kernel<4, 2>,
                          bwd_yz_reduce_kernel<4, 3>, bwd_yz_reduce_kernel<4, 4>}};
-                    hipLaunchKernelGGL(table[plan.nb2 - 1][plan.nb3 - 1],
+                    hipLaunchKernelGGL(table[plan.nbh2 - 1][plan.nbh3 - 1],
                                        dim3(static_cast<unsigned>(n1), static_cast<unsigned>(ncb)),
                                        dim3(256), 0, s, t2, n1, n2, n3, plan.n23, nj2, nj3,
-                                       plan.w2inv, plan.w3inv, plan.boxmap, nr, dv, psi_v, psi_c,
+                                       plan.w2ir, plan.w3ir, plan.boxi, nr, dv, psi_v, psi_c,
                                        v0, c0, cw, vcount, grad_psi_c, vpart);
                     GW_HIP_TRY(hipGetLastError());
                 }
@@ -908,13 +939,15 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             }
             {
                 ProfScope ps("bwd_yz", s);
-                auto yz = plan.nb2 == 1   ? bwd_yz_kernel<1>
-                          : plan.nb2 == 2 ? bwd_yz_kernel<2>
-                          : plan.nb2 == 3 ? bwd_yz_kernel<3>
-                                          : bwd_yz_kernel<4>;
-                hipLaunchKernelGGL(yz, dim3(static_cast<unsigned>(kc)), dim3(256), 0, s, t2, n1, n2,
-                                   n3, plan.n23, plan.nb3, nj2, nj3, plan.w2inv, plan.w3inv,
-                                   plan.boxmap, nr, dv, grho);
+                using YzFn = decltype(&bwd_yz_kernel<1, 1>);
+                static const YzFn ytable[4][4] = {
+                    {bwd_yz_kernel<1, 1>, bwd_yz_kernel<1, 2>, bwd_yz_kernel<1, 3>, bwd_yz_kernel<1, 4>},
+                    {bwd_yz_kernel<2, 1>, bwd_yz_kernel<2, 2>, bwd_yz_kernel<2, 3>, bwd_yz_kernel<2, 4>},
+                    {bwd_yz_kernel<3, 1>, bwd_yz_kernel<3, 2>, bwd_yz_kernel<3, 3>, bwd_yz_kernel<3, 4>},
+                    {bwd_yz_kernel<4, 1>, bwd_yz_kernel<4, 2>, bwd_yz_kernel<4, 3>, bwd_yz_kernel<4, 4>}};
+                hipLaunchKernelGGL(ytable[plan.nbh2 - 1][plan.nbh3 - 1], dim3(static_cast<unsigned>(kc)),
+                                   dim3(256), 0, s, t2, n1, n2, n3, plan.n23, nj2, nj3, plan.w2ir,
+                                   plan.w3ir, plan.boxi, nr, dv, grho);
                 GW_HIP_TRY(hipGetLastError());
             }
             if (grad_psi_c)

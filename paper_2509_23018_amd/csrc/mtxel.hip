@@ -90,8 +90,8 @@ template <int NB2, int NB3, int PPW>
 __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const double2* __restrict__ psi_v, const double2* __restrict__ psi_c, int64_t nr, Rect rc,
     int n1, int planes_per_group, int n2, int n3, int n2p, int n3p,
-    const double* __restrict__ w3tab, const double* __restrict__ w2tab,
-    const int* __restrict__ boxmap, int n23, double2* __restrict__ t2) {
+    const double* __restrict__ w3re, const double* __restrict__ w2re,
+    const int* __restrict__ boxf, int n23, double2* __restrict__ t2) {
     constexpr int TV = 4, TC = 2 * PPW, NBANDS = TV + TC;
     constexpr int NFILL = NBANDS * 256 / kZyThreads;  // staged elements per thread
     extern __shared__ double2 lds[];
@@ -105,9 +105,9 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     double* s_w2 = reinterpret_cast<double*>(lds + w3n / 2);
     int* s_box = reinterpret_cast<int*>(lds + w3n / 2 + w2n / 2);
     double2* s_slab = lds + w3n / 2 + w2n / 2 + boxn / 4;  // [NBANDS][16][kRowStride]
-    for (int i = threadIdx.x; i < w3n; i += kZyThreads) s_w3[i] = w3tab[i];
-    for (int i = threadIdx.x; i < w2n; i += kZyThreads) s_w2[i] = w2tab[i];
-    for (int i = threadIdx.x; i < boxn; i += kZyThreads) s_box[i] = boxmap[i];
+    for (int i = threadIdx.x; i < w3n; i += kZyThreads) s_w3[i] = w3re[i];
+    for (int i = threadIdx.x; i < w2n; i += kZyThreads) s_w2[i] = w2re[i];
+    for (int i = threadIdx.x; i < boxn; i += kZyThreads) s_box[i] = boxf[i];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kq = lane >> 4;
@@ -301,12 +301,12 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
 template <int NB1>
 __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
     const double2* __restrict__ t2, int n1, int n1p, int n23, int n23p,
-    const double* __restrict__ w1tab, const int* __restrict__ gmap, int ng, double dv,
+    const double* __restrict__ w1re, const int* __restrict__ gmapf, int ng, double dv,
     int64_t npairs, int64_t k0, int cw, int64_t ldm, double2* __restrict__ m_out) {
     extern __shared__ double2 lds_x[];
     double* s_w1 = reinterpret_cast<double*>(lds_x);
     const int q1 = n1p >> 2;
-    for (int i = threadIdx.x; i < NB1 * q1 * 64; i += kThreads) s_w1[i] = w1tab[i];
+    for (int i = threadIdx.x; i < NB1 * q1 * 64; i += kThreads) s_w1[i] = w1re[i];
     __syncthreads();
     const int64_t k = blockIdx.x;
     if (k >= npairs) return;
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
             for (int t = 0; t < 2; ++t) {
                 const double cr = ar[b][t], ci = ai[b][t], sr = ar[b][t + 2], si = ai[b][t + 2];
                 const int e = ((b * 8 + 4 * t + kq) * 2) * n23p + d;
-                const int gp = gmap[e], gm = gmap[e + n23p];
+                const int gp = gmapf[e], gm = gmapf[e + n23p];
                 if (gp >= 0) dst[gp] = make_double2(dv * (cr - si), dv * (ci + sr));
                 if (gm >= 0) dst[gm] = make_double2(dv * (cr + si), dv * (ci - sr));
             }
@@ -500,13 +500,7 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
             }
         }
     p->n23p = ceil_div(nd, 16) * 16;
-    std::map<int, int> i1;
-    for (int i = 0; i < p->m1; ++i) i1[l1[i]] = i;
-    std::vector<int> gmap(static_cast<size_t>(p->nb1) * 16 * p->n23p, -1);
-    for (int i = 0; i < ng; ++i) {
-        g_disc[i] = box[i2[k2[i]] * bw3 + i3[k3[i]]];
-        gmap[static_cast<size_t>(i1[k1[i]]) * p->n23p + g_disc[i]] = i;
-    }
+    for (int i = 0; i < ng; ++i) g_disc[i] = box[i2[k2[i]] * bw3 + i3[k3[i]]];
     // real twiddle operands of the forward stages: lane l of k-step s, block b
     // holds, for j = 4 s + l/16 and class a = lh[8 b + (l & 7)], cos(2 pi a j/N)
     // (l & 15 < 8) or the sine (exactly 0 for a = 0 and a = N/2); zero past
@@ -543,55 +537,67 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
             gmapf[(static_cast<size_t>(ih1[a]) * 2 + sg) * p->n23p + g_disc[i]] = i;
         }
     }
-    // adjoint tables, in the lane layouts of the transposed stages:
-    //   x: U[j1][d]   = sum_k1 conj(e^{2 pi i k1 j1/N1}) B[k1][d]   (A = W1inv[j1][k1])
-    //   z: T[k2][j3]  = sum_k3 Ubox[k2][k3] conj(e^{2 pi i k3 j3/N3}) (B = W3inv[k3][j3])
-    //   y: R[j2][j3]  = sum_k2 conj(e^{2 pi i k2 j2/N2}) T[k2][j3]   (A = W2inv[j2][k2])
+    // adjoint (inverse) stages, e^{-2 pi i k j/N} summed over classes as
+    // P cos + Q sin: the real cos | sin operands in the transposed lane layouts.
+    // Slot of lane l at k-step s: 4 (s % 4) + l/16 of class block s/4 (slot < 8:
+    // cosine of class 8 (s/4) + slot, else the sine of class 8 (s/4) + slot - 8).
+    //   x: A = [j1][slot], [n1p16/16][nbh1*4][64], j1 = 16 rb + l%16
+    //   y: A = [j2][slot], [n2p/16][nbh2*4][64],   j2 = 16 rb + l%16
+    //   z: B = [slot][j3], [nbh3*4][n3p/16][64],   j3 = 16 nb + l%16
     p->n1p16 = ceil_div(n[0], 16) * 16;
-    auto conj_root = [](int64_t num, int64_t den) {
-        const double2 w = host_root(num, den);
-        return make_double2(w.x, -w.y);
+    auto inv_val = [](const std::vector<int>& lh, int s, int l, int j, int nn) {
+        const int slot = 4 * (s & 3) + (l >> 4);
+        const int h = (s >> 2) * 8 + (slot & 7);
+        if (j >= nn || h >= static_cast<int>(lh.size())) return 0.0;
+        const int a = lh[h];
+        const double2 r = host_root(static_cast<int64_t>(a) * j, nn);
+        if (slot < 8) return r.x;
+        return (a == 0 || 2 * a == nn) ? 0.0 : r.y;
     };
-    const int ks1 = p->nb1 * 4, ks2 = p->nb2 * 4, ks3 = p->nb3 * 4;
-    std::vector<double2> w1i(static_cast<size_t>(p->n1p16 / 16) * ks1 * 64);
-    for (int rb = 0; rb < p->n1p16 / 16; ++rb)
-        for (int s = 0; s < ks1; ++s)
-            for (int l = 0; l < 64; ++l) {
-                const int j1 = rb * 16 + (l & 15), kk = 4 * s + (l >> 4);
-                w1i[(static_cast<size_t>(rb) * ks1 + s) * 64 + l] =
-                    (j1 < n[0] && kk < p->m1) ? conj_root(static_cast<int64_t>(l1[kk]) * j1, n[0])
-                                             : make_double2(0.0, 0.0);
-            }
-    std::vector<double2> w2i(static_cast<size_t>(nrb1) * ks2 * 64);
-    for (int rb = 0; rb < nrb1; ++rb)
-        for (int s = 0; s < ks2; ++s)
-            for (int l = 0; l < 64; ++l) {
-                const int j2 = rb * 16 + (l & 15), kk = 4 * s + (l >> 4);
-                w2i[(static_cast<size_t>(rb) * ks2 + s) * 64 + l] =
-                    (j2 < n[1] && kk < p->m2) ? conj_root(static_cast<int64_t>(l2[kk]) * j2, n[1])
-                                             : make_double2(0.0, 0.0);
-            }
+    auto inv_rows = [&](const std::vector<int>& lh, int nbh, int nrb, int nn) {
+        std::vector<double> w(static_cast<size_t>(nrb) * nbh * 4 * 64);
+        for (int rb = 0; rb < nrb; ++rb)
+            for (int sk = 0; sk < nbh * 4; ++sk)
+                for (int l = 0; l < 64; ++l)
+                    w[(static_cast<size_t>(rb) * nbh * 4 + sk) * 64 + l] =
+                        inv_val(lh, sk, l, rb * 16 + (l & 15), nn);
+        return w;
+    };
+    const std::vector<double> w1i = inv_rows(lh1, p->nbh1, p->n1p16 / 16, n[0]);
+    const std::vector<double> w2i = inv_rows(lh2, p->nbh2, nrb1, n[1]);
     const int nj3 = p->n3p / 16;
-    std::vector<double2> w3i(static_cast<size_t>(ks3) * nj3 * 64);
-    for (int s = 0; s < ks3; ++s)
+    std::vector<double> w3i(static_cast<size_t>(p->nbh3) * 4 * nj3 * 64);
+    for (int sk = 0; sk < p->nbh3 * 4; ++sk)
         for (int nb = 0; nb < nj3; ++nb)
-            for (int l = 0; l < 64; ++l) {
-                const int kk = 4 * s + (l >> 4), j3 = nb * 16 + (l & 15);
-                w3i[(static_cast<size_t>(s) * nj3 + nb) * 64 + l] =
-                    (j3 < n[2] && kk < p->m3) ? conj_root(static_cast<int64_t>(l3[kk]) * j3, n[2])
-                                             : make_double2(0.0, 0.0);
-            }
+            for (int l = 0; l < 64; ++l)
+                w3i[(static_cast<size_t>(sk) * nj3 + nb) * 64 + l] =
+                    inv_val(lh3, sk, l, nb * 16 + (l & 15), n[2]);
+    // inverse stage-z gather: row r of k2 block b2 is k2 = +a2 (r < 8) or -a2
+    // (r >= 8) of class 8 b2 + r % 8; column 4 i + kq of k3 block b3 is the value
+    // i of that lane: k3 = +a3 (i < 2) or -a3 (i >= 2) of class 8 b3 + 4 (i % 2) + kq
+    std::vector<int> boxi(static_cast<size_t>(p->nbh2) * 16 * bwh3, -1);
+    for (int r2 = 0; r2 < p->nbh2 * 16; ++r2) {
+        const int k2v = freq(lh2, (r2 >> 4) * 8 + (r2 & 7), (r2 & 15) >= 8, n[1]);
+        const auto it2 = i2.find(k2v);
+        if (k2v < 0 || it2 == i2.end()) continue;
+        for (int c3 = 0; c3 < bwh3; ++c3) {
+            const int i = (c3 & 15) >> 2, kqc = c3 & 3;
+            const int k3v = freq(lh3, (c3 >> 4) * 8 + 4 * (i & 1) + kqc, i >= 2, n[2]);
+            const auto it3 = i3.find(k3v);
+            if (k3v < 0 || it3 == i3.end()) continue;
+            boxi[static_cast<size_t>(r2) * bwh3 + c3] = box[it2->second * bw3 + it3->second];
+        }
+    }
 
     p->w1re = upload(w1);
     p->gmapf = upload(gmapf);
-    p->gmap = upload(gmap);
     p->w3re = upload(w3);
     p->w2re = upload(w2);
     p->boxf = upload(boxf);
-    p->boxmap = upload(box);
-    p->w1inv = upload(w1i);
-    p->w2inv = upload(w2i);
-    p->w3inv = upload(w3i);
+    p->w1ir = upload(w1i);
+    p->w2ir = upload(w2i);
+    p->w3ir = upload(w3i);
+    p->boxi = upload(boxi);
     return p;
 }
 
@@ -600,17 +606,15 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
 void MtxelPlan::release() {
     (void)hipFree(w1re);
     (void)hipFree(gmapf);
-    (void)hipFree(gmap);
     (void)hipFree(w3re);
     (void)hipFree(boxf);
     (void)hipFree(w2re);
-    (void)hipFree(boxmap);
-    (void)hipFree(w1inv);
-    (void)hipFree(w2inv);
-    (void)hipFree(w3inv);
-    w1inv = w2inv = w3inv = nullptr;
-    w1re = w2re = w3re = nullptr;
-    gmapf = gmap = boxf = boxmap = nullptr;
+    (void)hipFree(w1ir);
+    (void)hipFree(w2ir);
+    (void)hipFree(w3ir);
+    (void)hipFree(boxi);
+    w1re = w2re = w3re = w1ir = w2ir = w3ir = nullptr;
+    gmapf = boxf = boxi = nullptr;
     if (last_use) (void)hipEventDestroy(last_use);
     last_use = nullptr;
 }

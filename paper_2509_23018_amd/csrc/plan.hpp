@@ -58,18 +58,17 @@ struct MtxelPlan {
     std::vector<int32_t> gvec;  // host copy (cache key)
 
     // device tables (owned)
-    double* w1re = nullptr;     // [nbh1][n1p/4][64]     stage-x MFMA A operand (cos | sin), lane layout
+    double* w1re = nullptr;     // [n1p/4][nbh1][64]     stage-x MFMA A operand (cos | sin), lane layout
     int* gmapf = nullptr;       // [nbh1*8][2][n23p] (k1 class, sign, disc index) -> G index or -1
-    int* gmap = nullptr;        // [nb1*16][n23p] (k1 index, disc index) -> G index or -1
     double* w3re = nullptr;     // [n3p/4][nbh3][64]     stage-z MFMA B operand (cos | sin), lane layout
     double* w2re = nullptr;     // [n2p/4][nbh2][64]     stage-y MFMA A operand (cos | sin), lane layout
     int* boxf = nullptr;        // [nbh2*8][2][nbh3*16] (k2 class, sign, stage-y column) -> disc or -1
-    int* boxmap = nullptr;      // [nb2*16][nb3*16] (k2, k3) index -> disc index or -1
-    // used by the adjoint (the transposed stages, conjugate twiddles)
+    // used by the adjoint (the transposed stages, e^{-2 pi i k j/N} as P cos + Q sin)
     int n1p16 = 0;              // N1 rounded up to 16
-    double2* w1inv = nullptr;   // [n1p16/16][nb1*4][64]  adjoint stage-x MFMA A operand
-    double2* w2inv = nullptr;   // [n2p/16][nb2*4][64]    adjoint stage-y MFMA A operand
-    double2* w3inv = nullptr;   // [nb3*4][n3p/16][64]    adjoint stage-z MFMA B operand
+    double* w1ir = nullptr;     // [n1p16/16][nbh1*4][64] adjoint stage-x MFMA A operand (cos | sin)
+    double* w2ir = nullptr;     // [n2p/16][nbh2*4][64]   adjoint stage-y MFMA A operand (cos | sin)
+    double* w3ir = nullptr;     // [nbh3*4][n3p/16][64]   adjoint stage-z MFMA B operand (cos | sin)
+    int* boxi = nullptr;        // [nbh2*16][nbh3*16] adjoint stage-z gather -> disc index or -1
 
     int device = 0;
     hipEvent_t last_use = nullptr;  // recorded after the last enqueued work that read the tables

@@ -141,14 +141,15 @@ def _ellipsoid(semi):
 
 
 @pytest.mark.parametrize("n,semi", [
-    ((8, 44, 14), (2.5, 20.5, 5.5)),    # 41 k2 values: three 16-wide blocks on y
-    ((12, 10, 64), (4.5, 3.5, 30.5)),   # 61 k3 values: four blocks on z, N3 = 64
-    ((40, 12, 12), (19.5, 4.5, 4.5)),   # 39 k1 values, N1 = 40: three row blocks on x
+    ((8, 44, 14), (2.5, 20.5, 5.5)),    # 41 k2 values, 21 classes: three class blocks on y
+    ((12, 10, 64), (4.5, 3.5, 30.5)),   # 61 k3 values, 31 classes: four blocks on z, N3 = 64
+    ((40, 12, 12), (19.5, 4.5, 4.5)),   # 39 k1 values, 20 classes, N1 = 40: three blocks on x
 ])
 def test_backward_wide_g_lists(n, semi):
-    """G lists spanning several 16-wide blocks along one axis (the adjoint's
-    transposed stages then run several k-blocks and output blocks), against
-    the oracle adjoint; the forward chi0 of the same problem too."""
+    """G lists spanning several blocks of 8 frequency classes min(k, N - k)
+    along one axis (the stages then run several class blocks and output
+    blocks), against the oracle adjoint; the forward chi0 of the same problem
+    too."""
     gvec = _ellipsoid(semi)
     p = gen.make_problem(n, 2, 5, gvec=gvec, z=(0.2j, 0.5 + 0.01j), seed=31, pair_chunk=7)
     rng = np.random.default_rng(6)

@@ -27,8 +27,8 @@ def _dev(a):
 @pytest.mark.parametrize("n,nv,nc,r2", [
     ((16, 16, 16), 4, 28, 10),      # workload 0 shape
     ((12, 10, 9), 3, 5, 8),         # non-cubic, odd axis
-    ((24, 24, 24), 2, 7, 40),       # |g| <= 6: 13 values per axis, one 16-wide block
-    ((36, 20, 44), 2, 3, 90),       # m3 = 19 -> two 16-wide blocks, N2 not a multiple of 16
+    ((24, 24, 24), 2, 7, 40),       # |g| <= 6: 13 values (7 classes) per axis, one block
+    ((36, 20, 44), 2, 3, 90),       # 19 k3 values, 10 classes: two blocks, N2 not a multiple of 16
     ((8, 8, 8), 1, 3, 20),          # sphere clipped by the grid: keeps g = -4, drops g = +4
 ])
 def test_mtxel_matches_oracle(n, nv, nc, r2):
@@ -120,7 +120,7 @@ def _box_g(r1, r2, r3):
 @pytest.mark.parametrize("n,g", [
     ((6, 10, 16), _box_g((-2, 2), (-4, 3), (-8, 7))),     # N3 = 16: the whole k3 window
     ((5, 9, 32), _box_g((-2, 2), (-4, 4), (-7, 7))),      # N3 = 32
-    ((7, 12, 48), _box_g((-3, 3), (-6, 5), (-8, 5))),     # N3 = 48, window not centred
+    ((7, 12, 48), _box_g((-3, 3), (-6, 5), (-8, 5))),     # N3 = 48, window not centred: unpaired k3
     ((4, 24, 64), _box_g((-1, 1), (-10, 10), (-6, 6))),   # N3 = 64, 21 k2 values: two y blocks
 ])
 def test_mtxel_box_g_lists(n, g):
