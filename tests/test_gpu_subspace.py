@@ -264,6 +264,20 @@ def test_keep_m_and_chi_from_kept_m(chunk):
         gw.gw_chi0_from_m(dp3, mk, wide, pair_chunk=chunk)
 
 
+@pytest.mark.parametrize("prec,ns", [("fp32", 0), ("split_bf16", 3), ("split_fp16x9", 4)])
+def test_chi_from_kept_m_reduced_precision(prec, ns):
+    """The kept-M path runs the same contraction kernels in every precision:
+    chi from gw_chi0_from_m equals gw_chi0 in that precision bit for bit, on
+    several chunks with a ragged last one."""
+    p, _ = _chi_static_problem(seed=47, nv=3, nc=17)
+    chunk = 11
+    want = gw.gw_chi0(to_dev(p), precision=prec, n_slices=ns, pair_chunk=chunk).clone()
+    dp = to_dev(p)
+    _, mk = gw.gw_chi0_keep_m(dp, pair_chunk=chunk)
+    got = gw.gw_chi0_from_m(dp, mk, precision=prec, n_slices=ns, pair_chunk=chunk)
+    assert torch.equal(got, want)
+
+
 def test_subspace_argument_errors():
     a = torch.zeros((8, 8), dtype=torch.complex128, device=device())
     with pytest.raises(gw.GWError):
