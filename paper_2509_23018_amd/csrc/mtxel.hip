@@ -54,11 +54,12 @@ T* upload(const std::vector<T>& h) {
 
 // ---------------------------------------------------------------- kernel 1
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kLoadBatch = 8;  // x-stage k-steps whose loads are issued together
 constexpr int kZyWaves = 8;
 constexpr int kZyThreads = 64 * kZyWaves;
-constexpr int kSlab = 16;              // j3 values per LDS slab (4 MFMA k-steps)
-constexpr int kRowStride = kSlab + 1;  // padded LDS row: column reads hit distinct banks
+constexpr int kSlab = 16;  // j3 values per LDS slab (4 MFMA k-steps)
 
 // The value this lane's partner in its 16-lane row (lane ^ 8) holds: a DPP
 // row rotation by 8, two 32-bit moves.
@@ -72,11 +73,42 @@ __device__ __forceinline__ double row_swap8(double v) {
         static_cast<unsigned>(lo)));
 }
 
+// The slab ring is written by global_load_lds and read with ds_read, and the
+// kernel orders the two itself (vmcnt waits and a barrier per slab).  Both go
+// through these helpers' restrict pointers: the alias scopes that inlining
+// attaches let the compiler see that a read is not waiting on the loads in
+// flight, which it would otherwise drain before every read (with them, the
+// ring - 1 slabs in flight keep flying).
+template <int NFILL>
+__device__ __forceinline__ void ring_fill(double2* __restrict__ ring, int off,
+                                          const double2* const (&src)[NFILL]) {
+#pragma unroll
+    for (int u = 0; u < NFILL; ++u)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const u32x4*>(src[u]),
+                                         reinterpret_cast<u32x4*>(ring + off + u * kZyThreads), 16,
+                                         0, 0);
+}
+__device__ __forceinline__ double2 ring_read(const double2* __restrict__ ring, int off) {
+    return ring[off];
+}
+
+// vmcnt(n) alone (expcnt and lgkmcnt left at their no-wait maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 // One workgroup = a tile of 4 valence x (2*PPW) conduction bands (4*2*PPW
-// pairs); wave w owns valence band w/2 and PPW conduction bands.  For every
-// (j1 plane, 16-row block of j2, 16-wide slab of j3) the tile's band rows are
-// staged once in LDS and shared by all the pairs that use them; the next
-// slab's global loads are in flight while the current one is contracted.
+// pairs); wave w owns valence band w/2 and PPW conduction bands.  The planes
+// of the workgroup are walked as (j1 plane, 16-row block of j2, 16-wide slab
+// of j3); each slab of the tile's band rows is written straight from global
+// memory into a ring of `ring` LDS slots (no registers), ring - 1 slabs ahead
+// of the one contracted, and shared by all the pairs that use it.  Slab entry
+// (band b, row r, position q) holds column q ^ r, so the 16 rows of one
+// column sit in 16 distinct bank groups.  Entries past the grid or the tile
+// load a clamped in-range value: its products meet zero twiddles, skipped
+// k-steps or pairs that are not written.
 // Both stages run on real twiddles, two real MFMA products per 16 x 16 block
 // (the real and the imaginary part of the complex operand):
 //  * stage z: B = the cos | sin columns of 8 k3 classes (NB3 blocks); before
@@ -91,9 +123,11 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const double2* __restrict__ psi_v, const double2* __restrict__ psi_c, int64_t nr, Rect rc,
     int n1, int planes_per_group, int n2, int n3, int n2p, int n3p,
     const double* __restrict__ w3re, const double* __restrict__ w2re,
-    const int* __restrict__ boxf, int n23, double2* __restrict__ t2) {
+    const int* __restrict__ boxf, int n23, double2* __restrict__ t2, int ring) {
     constexpr int TV = 4, TC = 2 * PPW, NBANDS = TV + TC;
-    constexpr int NFILL = NBANDS * 256 / kZyThreads;  // staged elements per thread
+    constexpr int NSLAB = NBANDS * 256;             // 16-byte entries per slab
+    constexpr int NFILL = NSLAB / kZyThreads;       // loads per thread per slab
+    static_assert(NSLAB % kZyThreads == 0, "slab fill");
     extern __shared__ double2 lds[];
     const int nslab = n3p / kSlab;
     const int q = n3p >> 2;
@@ -104,7 +138,7 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     double* s_w3 = reinterpret_cast<double*>(lds);
     double* s_w2 = reinterpret_cast<double*>(lds + w3n / 2);
     int* s_box = reinterpret_cast<int*>(lds + w3n / 2 + w2n / 2);
-    double2* s_slab = lds + w3n / 2 + w2n / 2 + boxn / 4;  // [NBANDS][16][kRowStride]
+    double2* s_ring = lds + w3n / 2 + w2n / 2 + boxn / 4;  // [ring][NBANDS][16][16]
     for (int i = threadIdx.x; i < w3n; i += kZyThreads) s_w3[i] = w3re[i];
     for (int i = threadIdx.x; i < w2n; i += kZyThreads) s_w2[i] = w2re[i];
     for (int i = threadIdx.x; i < boxn; i += kZyThreads) s_box[i] = boxf[i];
@@ -114,38 +148,32 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const bool cos_col = row < 8;  // this lane's stage-z column: cosine (else sine) of its class
     const int tv0 = blockIdx.y * TV, tc0 = blockIdx.x * TC;
 
-    // staging slots of this thread: band fb[u], row fr[u], column fc[u]
+    // staging entries of this thread: e = u * 512 + tid -> band e / 256, row
+    // fr[u], column fc[u] (position e % 16 = fc ^ fr); band rows clamped
     const double2* fptr[NFILL];
-    int fr[NFILL], fc[NFILL], fb[NFILL];
-    bool fok[NFILL];
+    int fr[NFILL], fc[NFILL];
 #pragma unroll
     for (int u = 0; u < NFILL; ++u) {
         const int e = tid + kZyThreads * u;
-        fb[u] = e >> 8;
+        const int fb = e >> 8;
         fr[u] = (e >> 4) & 15;
-        fc[u] = e & 15;
-        if (fb[u] < TV) {
-            fok[u] = tv0 + fb[u] < rc.nv;
-            fptr[u] = psi_v + (fok[u] ? static_cast<int64_t>(rc.v0 + tv0 + fb[u]) * nr : 0);
-        } else {
-            fok[u] = tc0 + fb[u] - TV < rc.nc;
-            fptr[u] = psi_c + (fok[u] ? static_cast<int64_t>(rc.c0 + tc0 + fb[u] - TV) * nr : 0);
-        }
+        fc[u] = (e & 15) ^ fr[u];
+        if (fb < TV)
+            fptr[u] = psi_v + static_cast<int64_t>(rc.v0 + min(tv0 + fb, rc.nv - 1)) * nr;
+        else
+            fptr[u] = psi_c + static_cast<int64_t>(rc.c0 + min(tc0 + fb - TV, rc.nc - 1)) * nr;
     }
-    double2 fv[NFILL];
-    auto gload = [&](int j1, int rb1, int sl) {
+    auto issue = [&](int j1, int rb1, int sl, int slot) {
+        const double2* src[NFILL];
 #pragma unroll
         for (int u = 0; u < NFILL; ++u) {
-            const int j2 = rb1 * 16 + fr[u], j3 = sl * kSlab + fc[u];
-            fv[u] = (fok[u] && j2 < n2 && j3 < n3)
-                        ? fptr[u][(static_cast<int64_t>(j1) * n2 + j2) * n3 + j3]
-                        : make_double2(0.0, 0.0);
+            const int j2 = min(rb1 * 16 + fr[u], n2 - 1), j3 = min(sl * kSlab + fc[u], n3 - 1);
+            src[u] = fptr[u] + (static_cast<int64_t>(j1) * n2 + j2) * n3 + j3;
         }
+        ring_fill<NFILL>(s_ring, slot * NSLAB + wave * 64, src);
     };
-    auto sstore = [&]() {
-#pragma unroll
-        for (int u = 0; u < NFILL; ++u) s_slab[(fb[u] * 16 + fr[u]) * kRowStride + fc[u]] = fv[u];
-    };
+    // slab entry of (band, row, column)
+    auto sent = [&](int band, int r, int c) { return band * 256 + r * 16 + (c ^ r); };
 
     const int vl = wave >> 1, cl0 = (wave & 1) * PPW;
     bool pok[PPW];
@@ -168,70 +196,136 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     // this workgroup's planes: j1 in [j1b, j1e)
     const int j1b = blockIdx.z * planes_per_group;
     const int j1e = min(n1, j1b + planes_per_group);
-    int j1 = j1b, rb1 = 0, sl = 0;      // position being contracted
-    int nj1 = j1b, nrb = 0, nsl = 0;    // position being loaded
-    gload(j1b, 0, 0);
     const int total = (j1e - j1b) * nrb1 * nslab;
-    for (int it = 0; it < total; ++it) {
-        __syncthreads();  // previous slab fully read (and tables visible)
-        sstore();
-        __syncthreads();
-        // advance the load position (clamped at the end: a harmless re-load)
-        if (++nsl == nslab) {
-            nsl = 0;
-            if (++nrb == nrb1) {
-                nrb = 0;
-                if (++nj1 == j1e) {
-                    nj1 = j1e - 1;
-                    nrb = nrb1 - 1;
-                    nsl = nslab - 1;
+    int j1 = j1b, rb1 = 0, sl = 0;      // position being contracted
+    int nj1 = j1b, nrb = 0, nsl = 0;    // next position to load (clamped at the last slab)
+    auto advance = [&](int& a, int& b, int& c) {
+        if (++c == nslab) {
+            c = 0;
+            if (++b == nrb1) {
+                b = 0;
+                if (++a == j1e) {
+                    a = j1e - 1;
+                    b = nrb1 - 1;
+                    c = nslab - 1;
                 }
             }
         }
-        gload(nj1, nrb, nsl);
-        __builtin_amdgcn_sched_barrier(0);
-        // z stage on this slab: A = rho rows (j2 = rb1*16+row, j3 = 16*sl + 4*kk + kq)
+    };
+    __syncthreads();  // tables visible
+    for (int i = 0; i < ring - 1; ++i) {
+        issue(nj1, nrb, nsl, i);
+        advance(nj1, nrb, nsl);
+    }
+    // T2 of plane pj1: a2[p][b2][b3] elements t = 0, 1 of lane l are the cos
+    // sums of k2 class 8*b2 + 4*t + kq, elements t + 2 the sin sums, at
+    // stage-y column b3*16 + row.  T2 at k2 = +a is C + i S, at -a C - i S;
+    // s_box[(class slot * 2 + sign) * NB3*16 + column] is its disc index.
+    auto store_plane = [&](int pj1) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const int ks = sl * 4 + kk;
-            if (4 * ks >= n3) break;  // padding k-steps (uniform)
-            const double2 xv = s_slab[(vl * 16 + row) * kRowStride + 4 * kk + kq];
-            double w3[NB3];
+        for (int p = 0; p < PPW; ++p) {
+            if (pok[p]) {
+                const int64_t k = static_cast<int64_t>(tv0 + vl) * rc.nc + tc0 + cl0 + p;
+                double2* o = t2 + (k * n1 + pj1) * n23;
 #pragma unroll
-            for (int b3 = 0; b3 < NB3; ++b3) w3[b3] = s_w3[(ks * NB3 + b3) * 64 + lane];
+                for (int b2 = 0; b2 < NB2; ++b2)
 #pragma unroll
-            for (int p = 0; p < PPW; ++p) {
-                const double2 xc = s_slab[((TV + cl0 + p) * 16 + row) * kRowStride + 4 * kk + kq];
-                const double2 rho = cmul_conj_a(xv, xc);
+                    for (int b3 = 0; b3 < NB3; ++b3)
 #pragma unroll
-                for (int b3 = 0; b3 < NB3; ++b3) {
-                    a1r[p][b3] = mfma_f64(rho.x, w3[b3], a1r[p][b3]);
-                    a1i[p][b3] = mfma_f64(rho.y, w3[b3], a1i[p][b3]);
+                        for (int t = 0; t < 2; ++t) {
+                            const double cr = a2r[p][b2][b3][t], ci = a2i[p][b2][b3][t];
+                            const double sr = a2r[p][b2][b3][t + 2], si = a2i[p][b2][b3][t + 2];
+                            const int e = ((b2 * 8 + 4 * t + kq) * 2) * (NB3 * 16) + b3 * 16 + row;
+                            const int dp = s_box[e], dm = s_box[e + NB3 * 16];
+                            if (dp >= 0) o[dp] = make_double2(cr - si, ci + sr);
+                            if (dm >= 0) o[dm] = make_double2(cr + si, ci - sr);
+                        }
+            }
+#pragma unroll
+            for (int b2 = 0; b2 < NB2; ++b2)
+#pragma unroll
+                for (int b3 = 0; b3 < NB3; ++b3) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
+        }
+    };
+    constexpr bool kPack = PPW % 2 == 0;
+    const bool half_last = (n2 & 15) != 0 && (n2 & 15) <= 8;  // last j2 block at most 8 rows
+    int pending = -1;  // plane whose T2 is complete and not yet stored
+    int cur = 0, fill = ring - 1;  // ring slots: contracted, refilled next
+    for (int it = 0; it < total; ++it) {
+        // this slab has landed in every wave, and every wave is done with the
+        // slot the next load refills.  At most the ring - 2 later slabs' loads
+        // of this wave are outstanding: loads complete in order among
+        // themselves, so while any load of this slab is in flight so are all
+        // NFILL of each later slab, whatever the t2 stores in between do
+        if (ring == 3)
+            wait_vmcnt<NFILL>();
+        else
+            wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");  // keep the LDS reads below the barrier
+        if (pending >= 0) {  // a slab before the next y stage: a2 is free again in time
+            store_plane(pending);
+            pending = -1;
+        }
+        issue(nj1, nrb, nsl, fill);
+        advance(nj1, nrb, nsl);
+        const int slab = cur * NSLAB;
+        // The last 16-row block of j2 may hold at most 8 rows of the grid: then,
+        // with an even number of pairs per wave, pairs 2q and 2q + 1 share one
+        // row set of the MFMAs (rows r < 8: pair 2q at j2 = rb1*16 + r; rows
+        // r >= 8: pair 2q + 1 at j2 = rb1*16 + r - 8) in accumulator set q.
+        const bool packed = kPack && rb1 == nrb1 - 1 && half_last;
+        // z stage on this slab: A = rho rows (j2 = rb1*16+row, j3 = 16*sl + 4*kk + kq;
+        // packed: pair 2p + row/8 at j2 = rb1*16 + row%8 into set p)
+        {
+            const int zrow = packed ? (row & 7) : row;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int ks = sl * 4 + kk;
+                if (4 * ks >= n3) break;  // padding k-steps (uniform)
+                const double2 xv = ring_read(s_ring, slab + sent(vl, zrow, 4 * kk + kq));
+                double w3[NB3];
+#pragma unroll
+                for (int b3 = 0; b3 < NB3; ++b3) w3[b3] = s_w3[(ks * 64 + lane) * NB3 + b3];
+#pragma unroll
+                for (int p = 0; p < PPW; ++p) {
+                    if (packed && 2 * p >= PPW) break;  // uniform
+                    const int band = packed ? TV + cl0 + 2 * p + (row >> 3) : TV + cl0 + p;
+                    const double2 xc = ring_read(s_ring, slab + sent(band, zrow, 4 * kk + kq));
+                    const double2 rho = cmul_conj_a(xv, xc);
+#pragma unroll
+                    for (int b3 = 0; b3 < NB3; ++b3) {
+                        a1r[p][b3] = mfma_f64(rho.x, w3[b3], a1r[p][b3]);
+                        a1i[p][b3] = mfma_f64(rho.y, w3[b3], a1i[p][b3]);
+                    }
                 }
             }
         }
         if (sl == nslab - 1) {
-            // y stage, k-step t (k index kq): a1[p][b3] element t of lane l is the
-            // cos (row < 8) or sin sum of k3 class 8*b3 + (row & 7) at
-            // j2 = rb1*16 + 4*t + kq; with the partner lane's sum, T1 at
-            // k3 = +a (cos lanes) is C + i S and at -a (sin lanes) C - i S, the
-            // B operand column b3*16 + row
+            // y stage, k-step t of the block's rows (k index kq): a1[p][b3]
+            // element t of lane l is the cos (row < 8) or sin sum of k3 class
+            // 8*b3 + (row & 7) at j2 = rb1*16 + 4*t + kq (packed: pair p's sums
+            // are set p/2, elements 2 (p % 2) + t, t < 2); with the partner
+            // lane's sum, T1 at k3 = +a (cos lanes) is C + i S and at -a (sin
+            // lanes) C - i S, the B operand column b3*16 + row
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                if (rb1 * 16 + 4 * t >= n2) break;  // padding k-steps (uniform)
+                if ((packed && t >= 2) || rb1 * 16 + 4 * t >= n2) break;  // uniform
                 double tre[PPW][NB3], tim[PPW][NB3];
 #pragma unroll
                 for (int p = 0; p < PPW; ++p)
 #pragma unroll
                     for (int b3 = 0; b3 < NB3; ++b3) {
-                        const double r = a1r[p][b3][t], i = a1i[p][b3][t];
+                        const int ps = kPack ? p / 2 : p, es = 2 * (p & 1) + (t & 1);
+                        const double r = packed ? a1r[ps][b3][es] : a1r[p][b3][t];
+                        const double i = packed ? a1i[ps][b3][es] : a1i[p][b3][t];
                         const double rp = row_swap8(r), ip = row_swap8(i);
                         tre[p][b3] = cos_col ? r - ip : rp + i;
                         tim[p][b3] = cos_col ? i + rp : ip - r;
                     }
 #pragma unroll
                 for (int b2 = 0; b2 < NB2; ++b2) {
-                    const double w = s_w2[((rb1 * 4 + t) * NB2 + b2) * 64 + lane];
+                    const double w = s_w2[((rb1 * 4 + t) * 64 + lane) * NB2 + b2];
 #pragma unroll
                     for (int p = 0; p < PPW; ++p)
 #pragma unroll
@@ -245,38 +339,7 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
             for (int p = 0; p < PPW; ++p)
 #pragma unroll
                 for (int b3 = 0; b3 < NB3; ++b3) a1r[p][b3] = a1i[p][b3] = zero4();
-            if (rb1 == nrb1 - 1) {
-                // a2[p][b2][b3] elements t = 0, 1 of lane l: the cos sums of k2
-                // class 8*b2 + 4*t + kq, elements t + 2 the sin sums, at stage-y
-                // column b3*16 + row.  T2 at k2 = +a is C + i S, at -a C - i S;
-                // s_box[(class slot * 2 + sign) * NB3*16 + column] is its disc index.
-#pragma unroll
-                for (int p = 0; p < PPW; ++p) {
-                    if (pok[p]) {
-                        const int64_t k = static_cast<int64_t>(tv0 + vl) * rc.nc + tc0 + cl0 + p;
-                        double2* o = t2 + (k * n1 + j1) * n23;
-#pragma unroll
-                        for (int b2 = 0; b2 < NB2; ++b2)
-#pragma unroll
-                            for (int b3 = 0; b3 < NB3; ++b3)
-#pragma unroll
-                                for (int t = 0; t < 2; ++t) {
-                                    const double cr = a2r[p][b2][b3][t], ci = a2i[p][b2][b3][t];
-                                    const double sr = a2r[p][b2][b3][t + 2],
-                                                 si = a2i[p][b2][b3][t + 2];
-                                    const int e = ((b2 * 8 + 4 * t + kq) * 2) * (NB3 * 16) +
-                                                  b3 * 16 + row;
-                                    const int dp = s_box[e], dm = s_box[e + NB3 * 16];
-                                    if (dp >= 0) o[dp] = make_double2(cr - si, ci + sr);
-                                    if (dm >= 0) o[dm] = make_double2(cr + si, ci - sr);
-                                }
-                    }
-#pragma unroll
-                    for (int b2 = 0; b2 < NB2; ++b2)
-#pragma unroll
-                        for (int b3 = 0; b3 < NB3; ++b3) a2r[p][b2][b3] = a2i[p][b2][b3] = zero4();
-                }
-            }
+            if (rb1 == nrb1 - 1) pending = j1;  // stored after the next barrier
         }
         if (++sl == nslab) {
             sl = 0;
@@ -285,7 +348,11 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
                 ++j1;
             }
         }
+        cur = cur + 1 == ring ? 0 : cur + 1;
+        fill = fill + 1 == ring ? 0 : fill + 1;
     }
+    if (pending >= 0) store_plane(pending);
+    wait_vmcnt<0>();  // no load into this workgroup's LDS may outlive it
 }
 
 // ---------------------------------------------------------------- kernel 2
@@ -335,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
                 if (ks < q1) {
 #pragma unroll
                     for (int b = 0; b < NB1; ++b) {
-                        const double w = s_w1[(ks * NB1 + b) * 64 + lane];
+                        const double w = s_w1[(ks * 64 + lane) * NB1 + b];
                         ar[b] = mfma_f64(w, xb[u].x, ar[b]);
                         ai[b] = mfma_f64(w, xb[u].y, ai[b]);
                     }
@@ -356,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
 }
 
 using ZyKernel = void (*)(const double2*, const double2*, int64_t, Rect, int, int, int, int, int,
-                          int, const double*, const double*, const int*, int, double2*);
+                          int, const double*, const double*, const int*, int, double2*, int);
 
 // Pairs per wave by the wider class-block count, within the registers of two
 // waves per SIMD.
@@ -452,11 +519,15 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
     const int q = p->n3p / 4, nrb1 = p->n2p / 16;
     const int bw2 = p->nb2 * 16, bw3 = p->nb3 * 16, bwh3 = p->nbh3 * 16;
     {
+        // tables, then a ring of 3 slabs (2 where 3 do not fit)
         const int ppw = zy_pairs_per_wave(p->nbh2, p->nbh3);
         const size_t nbands = 4 + 2 * static_cast<size_t>(ppw);
-        p->lds_yz = (static_cast<size_t>(q) * p->nbh3 * 32 + static_cast<size_t>(nrb1) * 4 * p->nbh2 * 32 +
-                     static_cast<size_t>(p->nbh2) * 16 * bwh3 / 4 + nbands * 16 * kRowStride) *
-                    sizeof(double2);
+        const size_t tables = (static_cast<size_t>(q) * p->nbh3 * 32 +
+                               static_cast<size_t>(nrb1) * 4 * p->nbh2 * 32 +
+                               static_cast<size_t>(p->nbh2) * 16 * bwh3 / 4) * sizeof(double2);
+        const size_t slab = nbands * 256 * sizeof(double2);
+        p->ring = tables + 3 * slab <= kMaxLds ? 3 : 2;
+        p->lds_yz = tables + p->ring * slab;
     }
     if (p->lds_yz > kMaxLds)
         throw Error{-4, "grid too large for the LDS-resident twiddle operands (unsupported)"};
@@ -501,8 +572,9 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
         }
     p->n23p = ceil_div(nd, 16) * 16;
     for (int i = 0; i < ng; ++i) g_disc[i] = box[i2[k2[i]] * bw3 + i3[k3[i]]];
-    // real twiddle operands of the forward stages: lane l of k-step s, block b
-    // holds, for j = 4 s + l/16 and class a = lh[8 b + (l & 7)], cos(2 pi a j/N)
+    // real twiddle operands of the forward stages, [k-step s][lane l][block b]
+    // (a lane reads the blocks of a k-step as one run): for j = 4 s + l/16 and
+    // class a = lh[8 b + (l & 7)], cos(2 pi a j/N)
     // (l & 15 < 8) or the sine (exactly 0 for a = 0 and a = N/2); zero past
     // the grid or the classes.  Stage z takes it as B (class = column), stage
     // y as A (class = row): the same lane layout.
@@ -517,7 +589,7 @@ std::unique_ptr<MtxelPlan> build_plan(const int n[3], const int32_t* gvec, int n
                     const int a = lh[h];
                     const double2 r = host_root(static_cast<int64_t>(a) * j, nn);
                     const bool sine = (l & 15) >= 8;
-                    w[(static_cast<size_t>(s) * nbh + b) * 64 + l] =
+                    w[(static_cast<size_t>(s) * 64 + l) * nbh + b] =
                         sine ? ((a == 0 || 2 * a == nn) ? 0.0 : r.y) : r.x;
                 }
         return w;
@@ -691,7 +763,7 @@ void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c
         const dim3 grid(gx, gy, ceil_div(p.n[0], pp));
         ProfScope ps("mtxel_zy", s);
         hipLaunchKernelGGL(kz, grid, dim3(kZyThreads), p.lds_yz, s, psi_v, psi_c, p.nr, rc, p.n[0],
-                           pp, p.n[1], p.n[2], p.n2p, p.n3p, p.w3re, p.w2re, p.boxf, p.n23, t2);
+                           pp, p.n[1], p.n[2], p.n2p, p.n3p, p.w3re, p.w2re, p.boxf, p.n23, t2, p.ring);
         GW_HIP_TRY(hipGetLastError());
     }
     XKernel kx = select_x(p.nbh1);

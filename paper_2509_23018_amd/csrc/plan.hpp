@@ -53,15 +53,16 @@ struct MtxelPlan {
     int n2p = 0, n3p = 0; // N2 rounded up to 16, N3 rounded up to 16
     int n23 = 0;          // disc size
     size_t lds_yz = 0;    // dynamic LDS of the fused product + z + y kernel
+    int ring = 3;         // slab slots of that kernel's LDS ring (2 where 3 do not fit)
     size_t lds_x = 0;     // dynamic LDS of the x-stage kernel
 
     std::vector<int32_t> gvec;  // host copy (cache key)
 
     // device tables (owned)
-    double* w1re = nullptr;     // [n1p/4][nbh1][64]     stage-x MFMA A operand (cos | sin), lane layout
+    double* w1re = nullptr;     // [n1p/4][64][nbh1]     stage-x MFMA A operand (cos | sin), lane layout
     int* gmapf = nullptr;       // [nbh1*8][2][n23p] (k1 class, sign, disc index) -> G index or -1
-    double* w3re = nullptr;     // [n3p/4][nbh3][64]     stage-z MFMA B operand (cos | sin), lane layout
-    double* w2re = nullptr;     // [n2p/4][nbh2][64]     stage-y MFMA A operand (cos | sin), lane layout
+    double* w3re = nullptr;     // [n3p/4][64][nbh3]     stage-z MFMA B operand (cos | sin), lane layout
+    double* w2re = nullptr;     // [n2p/4][64][nbh2]     stage-y MFMA A operand (cos | sin), lane layout
     int* boxf = nullptr;        // [nbh2*8][2][nbh3*16] (k2 class, sign, stage-y column) -> disc or -1
     // used by the adjoint (the transposed stages, e^{-2 pi i k j/N} as P cos + Q sin)
     int n1p16 = 0;              // N1 rounded up to 16
