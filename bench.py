@@ -812,6 +812,22 @@ def bench_adjoint(args):
     gw.profile_enable(False)
     kernels = {k: gw.profile_read(k) for k in ADJOINT_KERNELS}
     gw.profile_reset()
+    # the same adjoint reading M kept by the forward (gw_chi0_keep_m, then
+    # gw_chi0_backward_from_m): no MTXEL in the adjoint
+    m_keep = torch.empty((npairs, ng), dtype=torch.complex128, device=dp.psi_v.device)
+
+    def fwd_keep():
+        gw.gw_chi0_keep_m(dp, m_keep, precision="fp64", pair_chunk=chunk)
+
+    def bwd_kept():
+        return gw.gw_chi0_backward(dp, w, pair_chunk=chunk, m_keep=m_keep)
+
+    fwd_keep()
+    kept_equal = all(torch.equal(a, b) for a, b in
+                     zip(bwd_kept(), gw.gw_chi0_backward(dp, w, pair_chunk=chunk)))
+    torch.cuda.synchronize()
+    t_fwd_keep = _timed(fwd_keep, steps)
+    t_bwd_kept = _timed(bwd_kept, steps)
     # The adjoint's GEMMs: g_M = s (conj(Delta) M W + Delta M W^H), two products
     # of 8 flops per (pair, G, G'); where Delta is real (this static workload,
     # and every imaginary or real frequency) one product M (W + W^H).
@@ -836,6 +852,10 @@ def bench_adjoint(args):
         "s_per_forward": round(t_fwd, 5),
         "s_per_adjoint": round(t_bwd, 5),
         "adjoint_over_forward": round(t_bwd / t_fwd, 3),
+        "kept_m": {"bytes": npairs * ng * 16, "s_per_forward_keeping_m": round(t_fwd_keep, 5),
+                   "s_per_adjoint_from_kept_m": round(t_bwd_kept, 5),
+                   "adjoint_over_forward": round(t_bwd_kept / t_fwd, 3),
+                   "gradients_equal_to_recomputing_adjoint": kept_equal},
         "adjoint_gemm_tflops_per_s": round(gemm_flops / t_bwd / 1e12, 3),
         "pairs_per_s": round(npairs / t_bwd, 1),
         "kernel_ms_per_call": {k: round(v[1] / steps, 3) for k, v in kernels.items()},

@@ -422,6 +422,24 @@ size_t gw_chi0_from_m_workspace_bytes(const gw_problem_t* prob, int32_t n_eig,
                                       const gw_opts_t* opts);
 
 /*
+ * gw_chi0_backward_from_m -- gw_chi0_backward reading M kept by
+ * gw_chi0_keep_m (same problem shape and pair_chunk) instead of recomputing
+ * it: the adjoint's chunks are the forward's rectangles, in the same order,
+ * so chunk k is read at its rows of m_keep.  Same gradients, arguments and
+ * outputs as gw_chi0_backward (psi_v and psi_c are still read, by the band
+ * sums); bit-identical to it.  GW_EINVAL: m_keep NULL with nv*nc > 0, or a
+ * pair_chunk whose adjoint chunks would differ from the forward's (chunks of
+ * more than 8 valence bands whose per-pair g_rho would exceed 2 GiB).  Scratch:
+ * gw_chi0_backward_from_m_workspace_bytes(prob, opts) (no M buffers, no MTXEL
+ * intermediate), in opts->workspace or the library's own.
+ */
+gw_status_t gw_chi0_backward_from_m(const gw_problem_t* prob, const gw_c128* m_keep,
+                                    const gw_c128* grad_chi, gw_c128* grad_psi_v,
+                                    gw_c128* grad_psi_c, double* grad_e_v, double* grad_e_c,
+                                    const gw_opts_t* opts, void* stream);
+size_t gw_chi0_backward_from_m_workspace_bytes(const gw_problem_t* prob, const gw_opts_t* opts);
+
+/*
  * gw_epsinv -- the inverse dielectric matrix of Eq. (3),
  *     eps^-1(z) = [I - v chi(z)]^-1,
  * for nz frequencies, with v the diagonal Coulomb matrix.  Block Gauss-Jordan

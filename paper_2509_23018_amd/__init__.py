@@ -153,6 +153,14 @@ def lib() -> ctypes.CDLL:
         L.gw_chi0_from_m.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Opts),
                                      ctypes.c_void_p]
+        L.gw_chi0_backward_from_m.restype = ctypes.c_int32
+        L.gw_chi0_backward_from_m.argtypes = [ctypes.POINTER(_Problem), ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(_Opts), ctypes.c_void_p]
+        L.gw_chi0_backward_from_m_workspace_bytes.restype = ctypes.c_size_t
+        L.gw_chi0_backward_from_m_workspace_bytes.argtypes = [ctypes.POINTER(_Problem),
+                                                              ctypes.POINTER(_Opts)]
         L.gw_chi0_from_m_workspace_bytes.restype = ctypes.c_size_t
         L.gw_chi0_from_m_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int32,
                                                      ctypes.POINTER(_Opts)]
@@ -411,9 +419,17 @@ def gw_chi0_fixed(problem: Chi0Problem, *, precision="fp64", n_slices=0, pair_ch
 
 
 def gw_chi0_backward(problem: Chi0Problem, grad_chi: torch.Tensor, *, pair_chunk=4096,
-                     spin=2.0, need=(True, True, True, True), stream=None, workspace=None):
-    """Returns (grad_psi_v, grad_psi_c, grad_e_v, grad_e_c); entries not in `need` are None."""
+                     spin=2.0, need=(True, True, True, True), stream=None, workspace=None,
+                     m_keep: Optional[torch.Tensor] = None):
+    """Returns (grad_psi_v, grad_psi_c, grad_e_v, grad_e_c); entries not in `need` are None.
+    With m_keep (M from gw_chi0_keep_m with the same problem and pair_chunk) the
+    adjoint reads M instead of recomputing it (gw_chi0_backward_from_m)."""
     pr = problem
+    if m_keep is not None:
+        _dev(m_keep, "m_keep", torch.complex128)
+        npairs = pr.psi_v.shape[0] * pr.psi_c.shape[0]
+        if tuple(m_keep.shape) != (npairs, int(np.asarray(pr.gvec).shape[0])):
+            raise ValueError("m_keep must be [nv*nc, ng] as gw_chi0_keep_m returns it")
     _dev(grad_chi, "grad_chi", torch.complex128)
     p = _Problem()
     keep: list = []
@@ -430,8 +446,15 @@ def gw_chi0_backward(problem: Chi0Problem, grad_chi: torch.Tensor, *, pair_chunk
     ptr = [o.data_ptr() if o is not None else None for o in outs]
     o = _opts("fp64", 0, pair_chunk, 0, spin, workspace)
     with torch.cuda.device(pr.psi_v.device):
-        _check(lib().gw_chi0_backward(ctypes.byref(p), grad_chi.data_ptr(), ptr[0], ptr[1], ptr[2],
-                                      ptr[3], ctypes.byref(o), _stream(pr.psi_v.device, stream)))
+        if m_keep is None:
+            _check(lib().gw_chi0_backward(ctypes.byref(p), grad_chi.data_ptr(), ptr[0], ptr[1],
+                                          ptr[2], ptr[3], ctypes.byref(o),
+                                          _stream(pr.psi_v.device, stream)))
+        else:
+            _check(lib().gw_chi0_backward_from_m(ctypes.byref(p), m_keep.data_ptr(),
+                                                 grad_chi.data_ptr(), ptr[0], ptr[1], ptr[2],
+                                                 ptr[3], ctypes.byref(o),
+                                                 _stream(pr.psi_v.device, stream)))
     return tuple(outs)
 
 
@@ -686,16 +709,23 @@ class Chi0(torch.autograd.Function):
     """chi0(psi_v, psi_c, e_v, e_c) with a hand-written adjoint (gw_chi0_backward).
 
     Gradients follow PyTorch's complex convention.  The G list, frequencies,
-    grid and options are non-differentiable constants."""
+    grid and options are non-differentiable constants.  With keep_m the
+    forward keeps M of every pair (nv*nc*ng complex values of device memory)
+    and the adjoint reads it instead of recomputing it."""
 
     @staticmethod
     def forward(ctx, psi_v, psi_c, e_v, e_c, gvec, z, n, volume, pair_chunk=4096, spin=2.0,
-                precision="fp64", n_slices=0):
+                precision="fp64", n_slices=0, keep_m=False):
         pr = Chi0Problem(n=n, volume=volume, psi_v=psi_v.contiguous(), psi_c=psi_c.contiguous(),
                          e_v=e_v.contiguous(), e_c=e_c.contiguous(), gvec=_host_i32(gvec),
                          z=_host_c128(z))
-        chi = gw_chi0(pr, precision=precision, n_slices=n_slices, pair_chunk=pair_chunk,
-                      spin=spin)
+        ctx.m_keep = None
+        if keep_m:
+            chi, ctx.m_keep = gw_chi0_keep_m(pr, precision=precision, n_slices=n_slices,
+                                             pair_chunk=pair_chunk, spin=spin)
+        else:
+            chi = gw_chi0(pr, precision=precision, n_slices=n_slices, pair_chunk=pair_chunk,
+                          spin=spin)
         ctx.save_for_backward(pr.psi_v, pr.psi_c, pr.e_v, pr.e_c)
         ctx.meta = (pr.gvec, pr.z, tuple(n), volume, pair_chunk, spin)
         return chi
@@ -708,14 +738,15 @@ class Chi0(torch.autograd.Function):
                          gvec=gvec, z=z)
         need = tuple(bool(x) for x in ctx.needs_input_grad[:4])
         g = gw_chi0_backward(pr, grad_chi.contiguous(), pair_chunk=pair_chunk, spin=spin,
-                             need=need)
-        return (*g, None, None, None, None, None, None, None, None)
+                             need=need, m_keep=ctx.m_keep)
+        ctx.m_keep = None
+        return (*g, None, None, None, None, None, None, None, None, None)
 
 
 def chi0(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, *, pair_chunk=4096, spin=2.0,
-         precision="fp64", n_slices=0):
+         precision="fp64", n_slices=0, keep_m=False):
     return Chi0.apply(psi_v, psi_c, e_v, e_c, gvec, z, n, volume, pair_chunk, spin, precision,
-                      n_slices)
+                      n_slices, keep_m)
 
 
 def release():

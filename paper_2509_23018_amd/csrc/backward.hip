@@ -515,10 +515,18 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
             const int nvp = min(PV, vcount - vp);
             const int nq = ncl * nvp;  // pairs of this pass: q = cl * nvp + i
             double2 av[PV][4];
+            // psi_v of the pass's valence bands at this lane's points, read once
+            // for all the conduction bands of the block
+            double2 pvs[PV][4];
 #pragma unroll
-            for (int i = 0; i < PV; ++i)
+            for (int i = 0; i < PV; ++i) {
+                const double2* pvr = psi_v + static_cast<int64_t>(v0 + vp + min(i, nvp - 1)) * nr;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) av[i][t] = make_double2(0.0, 0.0);
+                for (int t = 0; t < 4; ++t) {
+                    av[i][t] = make_double2(0.0, 0.0);
+                    pvs[i][t] = pvr[pos[t]];
+                }
+            }
             // psi_c and the old grad_psi_c of conduction band cl at this lane's
             // points, loaded with its first pair (the MFMAs of that pair, and of
             // the band's other pairs, run before they are used)
@@ -542,10 +550,14 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
                         load_x(vp + (q + 1 - cn * nvp), cn, xnext);
                     }
                 }
-                const double2* pvr = psi_v + static_cast<int64_t>(v0 + vp + i) * nr;
                 double2 pv[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) pv[t] = pvr[pos[t]];
+                for (int t = 0; t < 4; ++t) {
+                    pv[t] = pvs[0][t];
+#pragma unroll
+                    for (int ii = 1; ii < PV; ++ii)
+                        if (ii == i) pv[t] = pvs[ii][t];
+                }
                 dbl4 gr = zero4(), gi = zero4();
                 if constexpr (HOIST) {
                     // stage z on the one class block, then stage y
@@ -723,7 +735,7 @@ struct BwdLayout {
 };
 
 BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi, bool want_psi_v,
-                     int pair_chunk) {
+                     int pair_chunk, bool kept) {
     BwdLayout L;
     const int64_t nr = plan.nr;
     const int ng = p.ng, nz = p.nz;
@@ -744,16 +756,27 @@ BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi
         shape(static_cast<int>(std::min<int64_t>(pair_chunk, cap)));
         L.fuse = L.vb <= kFuseV;
     }
+    if (kept) {
+        // kept M holds gw_chi0's chunks of the same pair_chunk, in the same order
+        const int cwf = std::max(1, std::min(p.nc, pair_chunk / std::max(1, std::min(p.nv, 4))));
+        const int vbf = std::max(1, std::min(p.nv, pair_chunk / cwf));
+        if (L.vb != vbf || L.cwmax != cwf)
+            throw Error{GW_EINVAL,
+                        "kept M: the adjoint's chunks (" + std::to_string(L.vb) + " x " +
+                            std::to_string(L.cwmax) + ") are not the forward's (" +
+                            std::to_string(vbf) + " x " + std::to_string(cwf) +
+                            "); use a pair_chunk whose chunks span at most 8 valence bands"};
+    }
     L.kmax = static_cast<int64_t>(L.vb) * L.cwmax;
     L.nparts = 2 * ceil_div(ng, 64);
     const int64_t kmax = L.kmax;
     Carve cv;
     for (int b = 0; b < 2; ++b) {
-        L.o_m[b] = cv.take(kmax * ng * sizeof(double2));
+        L.o_m[b] = cv.take(kept ? 0 : kmax * ng * sizeof(double2));
         L.o_d[b] = cv.take(kmax * nz * sizeof(double2));
         L.o_dd[b] = cv.take(kmax * nz * sizeof(double2));
     }
-    L.o_t2m = cv.take(t2_elems(plan, kmax) * sizeof(double2));
+    L.o_t2m = cv.take(kept ? 0 : t2_elems(plan, kmax) * sizeof(double2));
     L.o_t2 = cv.take(t2_elems(plan, kmax) * sizeof(double2));
     L.o_gm = cv.take(kmax * ng * sizeof(double2));
     bool any_sym = false;
@@ -773,31 +796,33 @@ BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi
 }  // namespace
 
 size_t chi0_backward_bytes(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi_v,
-                           bool want_psi_c, bool want_e, int pair_chunk) {
+                           bool want_psi_c, bool want_e, int pair_chunk, bool kept) {
     const int64_t npairs = static_cast<int64_t>(p.nv) * p.nc;
     const bool want_psi = want_psi_v || want_psi_c;
     if (npairs == 0 || (!want_psi && !want_e)) return 0;
-    return bwd_layout(plan, p, want_psi, want_psi_v, pair_chunk).total;
+    return bwd_layout(plan, p, want_psi, want_psi_v, pair_chunk, kept).total;
 }
 
 void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const double2* grad_chi,
                        double2* grad_psi_v, double2* grad_psi_c, double* grad_e_v,
                        double* grad_e_c, double spin, int pair_chunk, hipStream_t s,
-                       char* base, hipStream_t aux, hipEvent_t* ev) {
+                       char* base, hipStream_t aux, hipEvent_t* ev, const double2* m_keep) {
     const int64_t nr = plan.nr;
     const int ng = p.ng, nz = p.nz;
     const int n1 = plan.n[0], n2 = plan.n[1], n3 = plan.n[2];
+    const int64_t npairs = static_cast<int64_t>(p.nv) * p.nc;
+    const bool want_psi = grad_psi_v || grad_psi_c;
+    const bool want_e = grad_e_v || grad_e_c;
+    const bool work = npairs > 0 && (want_psi || want_e);
+    const BwdLayout L = work ? bwd_layout(plan, p, want_psi, grad_psi_v != nullptr, pair_chunk,
+                                          m_keep != nullptr)
+                             : BwdLayout{};
+    const int vb = L.vb, cwmax = L.cwmax, nparts = L.nparts;
     launch_fill_zero(grad_psi_v, grad_psi_v ? static_cast<int64_t>(p.nv) * nr : 0, s);
     launch_fill_zero(grad_psi_c, grad_psi_c ? static_cast<int64_t>(p.nc) * nr : 0, s);
     fill_zero_f64(grad_e_v, p.nv, s);
     fill_zero_f64(grad_e_c, p.nc, s);
-    const int64_t npairs = static_cast<int64_t>(p.nv) * p.nc;
-    const bool want_psi = grad_psi_v || grad_psi_c;
-    const bool want_e = grad_e_v || grad_e_c;
-    if (npairs == 0 || (!want_psi && !want_e)) return;
-
-    const BwdLayout L = bwd_layout(plan, p, want_psi, grad_psi_v != nullptr, pair_chunk);
-    const int vb = L.vb, cwmax = L.cwmax, nparts = L.nparts;
+    if (!work) return;
     const bool fuse = L.fuse;
     const size_t o_t2 = L.o_t2, o_gm = L.o_gm, o_q = L.o_q, o_de = L.o_de, o_rho = L.o_rho,
                  o_vp = L.o_vp;
@@ -831,14 +856,18 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
     for (int v0 = 0; v0 < p.nv; v0 += vb)
         for (int c0 = 0; c0 < p.nc; c0 += cwmax)
             chunks.push_back({v0, c0, std::min(vb, p.nv - v0), std::min(cwmax, p.nc - c0)});
+    std::vector<int64_t> moff(chunks.size(), 0);  // first row of chunk k in kept M
+    for (size_t k = 1; k < chunks.size(); ++k)
+        moff[k] = moff[k - 1] + static_cast<int64_t>(chunks[k - 1].vcount) * chunks[k - 1].cw;
     auto produce = [&](size_t k) {
         const int b = static_cast<int>(k & 1);
         const BChunk& c = chunks[k];
         const int64_t kc = static_cast<int64_t>(c.vcount) * c.cw;
         if (k >= 2) GW_HIP_TRY(hipStreamWaitEvent(aux, ev[3 + b], 0));
         PairMap pm{0, c.cw, c.v0, c.c0};
-        launch_mtxel(plan, psi_v, psi_c, Rect{c.v0, c.vcount, c.c0, c.cw}, p.grid.volume, t2m,
-                     mbufs[b], aux);
+        if (!m_keep)
+            launch_mtxel(plan, psi_v, psi_c, Rect{c.v0, c.vcount, c.c0, c.cw}, p.grid.volume, t2m,
+                         mbufs[b], aux);
         launch_delta(p.e_v, p.e_c, pm, kc, z, nz, spin, dbufs[b], aux);
         for (int w0 = 0; w0 < nz; w0 += kMaxZ) {
             ZArgs za{};
@@ -864,7 +893,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
             const int v0 = chunks[ck].v0, c0 = chunks[ck].c0;
             const int vcount = chunks[ck].vcount, cw = chunks[ck].cw;
             const int64_t kc = static_cast<int64_t>(vcount) * cw;
-            double2* mbuf = mbufs[b];
+            const double2* mbuf = m_keep ? m_keep + moff[ck] * ng : mbufs[b];
             double2* dbuf = dbufs[b];
             double2* ddbuf = ddbufs[b];
             for (int w = 0; w < nz; ++w) {

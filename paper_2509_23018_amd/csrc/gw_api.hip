@@ -1497,6 +1497,46 @@ gw_status_t gw_chi0_backward(const gw_problem_t* prob, const gw_c128* grad_chi,
     });
 }
 
+gw_status_t gw_chi0_backward_from_m(const gw_problem_t* prob, const gw_c128* m_keep,
+                                    const gw_c128* grad_chi, gw_c128* grad_psi_v,
+                                    gw_c128* grad_psi_c, double* grad_e_v, double* grad_e_c,
+                                    const gw_opts_t* opts, void* stream) {
+    return guarded([&] {
+        sweep_retired();
+        const Opts o = read_opts(opts);
+        const gw_problem_t p = backward_problem(prob, grad_chi);
+        if (!grad_chi) fail(GW_EINVAL, "grad_chi is NULL");
+        if (static_cast<int64_t>(p.nv) * p.nc > 0 && !m_keep) fail(GW_EINVAL, "m_keep is NULL");
+        if (o.precision != GW_FP64) fail(GW_EUNSUPPORTED, "the adjoint is FP64 only");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const PlanRef plan = get_plan(p.grid.n, p.gvec, p.ng);
+        const size_t need = chi0_backward_bytes(*plan, p, grad_psi_v != nullptr,
+                                                grad_psi_c != nullptr,
+                                                grad_e_v != nullptr || grad_e_c != nullptr,
+                                                o.pair_chunk, true);
+        char* base = call_scratch(need, o, s);
+        AuxCtx& ax = aux_ctx(s);
+        run_chi0_backward(*plan, p, reinterpret_cast<const double2*>(grad_chi),
+                          reinterpret_cast<double2*>(grad_psi_v),
+                          reinterpret_cast<double2*>(grad_psi_c), grad_e_v, grad_e_c, o.spin,
+                          o.pair_chunk, s, base, ax.aux, ax.ev,
+                          reinterpret_cast<const double2*>(m_keep));
+        mark_plan_used(*plan, s);
+    });
+}
+
+size_t gw_chi0_backward_from_m_workspace_bytes(const gw_problem_t* prob, const gw_opts_t* opts) {
+    size_t out = 0;
+    const gw_status_t st = guarded([&] {
+        const Opts o = read_opts(opts);
+        static const gw_c128 dummy{0.0, 0.0};
+        const gw_problem_t p = backward_problem(prob, &dummy);
+        const PlanRef plan = get_plan(p.grid.n, p.gvec, p.ng);
+        out = chi0_backward_bytes(*plan, p, true, true, true, o.pair_chunk, true);
+    });
+    return st == GW_OK ? out : static_cast<size_t>(-1);
+}
+
 // ---------------------------------------------------------------- fixed scratch
 
 }  // extern "C"

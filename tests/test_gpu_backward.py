@@ -44,6 +44,65 @@ def test_backward_matches_oracle_adjoint(zs, chunk, nv, nc, herm):
         assert rel_fro(g.cpu().numpy(), r) < FP64_TOL
 
 
+@pytest.mark.parametrize("zs,chunk,nv,nc", [
+    ((0.0,), 17, 4, 11),
+    ((0.2j,), 1000, 12, 3),                 # one chunk of 12 valence bands: the unfused path
+    ((0.25, 0.3 + 0.02j, 0.6j), 23, 4, 11),
+])
+def test_backward_from_kept_m(zs, chunk, nv, nc):
+    """gw_chi0_backward_from_m with M kept by gw_chi0_keep_m: the same kernels
+    on the same chunks, so the gradients equal gw_chi0_backward's bit for bit
+    (and through the autograd function with keep_m); the oracle adjoint too."""
+    p = gen.make_problem((12, 10, 14), nv, nc, r2=9, z=zs, seed=22, pair_chunk=chunk)
+    w = torch.from_numpy(_herm(np.random.default_rng(6), len(p.z), p.ng)).to(device())
+    dp = to_dev(p)
+    want = gw.gw_chi0_backward(dp, w, pair_chunk=chunk)
+    _, mk = gw.gw_chi0_keep_m(to_dev(p), pair_chunk=chunk)
+    got = gw.gw_chi0_backward(dp, w, pair_chunk=chunk, m_keep=mk)
+    for g, r in zip(got, want):
+        assert torch.equal(g, r)
+    ref = oracle.chi0_backward(p.psi_v, p.psi_c, p.e_v, p.e_c, p.gvec, p.z, p.n, p.volume,
+                               w.cpu().numpy(), spin=p.spin, pair_chunk=chunk)
+    for g, r in zip(got, ref):
+        assert rel_fro(g.cpu().numpy(), r) < FP64_TOL
+    # through torch.autograd: L = Re sum(conj(W) chi)
+    leaves = [t.clone().requires_grad_(True) for t in (dp.psi_v, dp.psi_c, dp.e_v, dp.e_c)]
+    grads = []
+    for keep in (False, True):
+        for t in leaves:
+            t.grad = None
+        chi = gw.chi0(*leaves, p.gvec, p.z, p.n, p.volume, pair_chunk=chunk, keep_m=keep)
+        torch.real(torch.sum(torch.conj(w) * chi)).backward()
+        grads.append([t.grad.clone() for t in leaves])
+    for a, b in zip(*grads):
+        assert torch.equal(a, b)
+
+
+def test_backward_from_kept_m_errors():
+    p = gen.make_problem((8, 8, 8), 2, 5, r2=3, z=(0.3j,), seed=1, pair_chunk=7)
+    dp = to_dev(p)
+    w = torch.zeros((1, p.ng, p.ng), dtype=torch.complex128, device=device())
+    with pytest.raises(ValueError):   # not the shape gw_chi0_keep_m returns
+        gw.gw_chi0_backward(dp, w, pair_chunk=7,
+                            m_keep=torch.zeros((9, p.ng), dtype=torch.complex128, device=device()))
+    # a grid on which the adjoint caps 64-valence-band chunks (g_rho of 4,096
+    # pairs past 2 GiB) while the forward keeps them: GW_EINVAL before any work
+    n = (40, 40, 40)
+    g = gen.gsphere(3)
+    nv, nc = 64, 100
+    psi_v = torch.zeros((nv, 64000), dtype=torch.complex128, device=device())
+    psi_c = torch.zeros((nc, 64000), dtype=torch.complex128, device=device())
+    big = gw.Chi0Problem(n=n, volume=gen.CELL_L ** 3, psi_v=psi_v, psi_c=psi_c,
+                         e_v=torch.zeros(nv, dtype=torch.float64, device=device()),
+                         e_c=torch.ones(nc, dtype=torch.float64, device=device()), gvec=g,
+                         z=np.zeros(1, np.complex128))
+    with pytest.raises(gw.GWError, match="kept M"):
+        gw.gw_chi0_backward(big, torch.zeros((1, len(g), len(g)), dtype=torch.complex128,
+                                             device=device()), pair_chunk=4096,
+                            m_keep=torch.zeros((nv * nc, len(g)), dtype=torch.complex128,
+                                               device=device()))
+
+
 def test_autograd_function_and_finite_differences():
     """L = Re tr(A chi0) through torch.autograd, against central differences."""
     p = gen.make_problem((10, 10, 10), 3, 6, r2=6, z=(0.0,), seed=8, pair_chunk=5)
