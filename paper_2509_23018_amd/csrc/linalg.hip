@@ -320,21 +320,31 @@ struct Rot {
     double2 s;  // S
 };
 
-__device__ __forceinline__ Rot rotation(const double2* __restrict__ a, int n, int p, int q) {
+__device__ __forceinline__ Rot rotation_of(double hpp, double hqq, double2 b) {
     Rot r{1.0, make_double2(0.0, 0.0)};
-    if (q >= n) return r;
-    const double2 b = a[static_cast<int64_t>(p) * n + q];
     const double ab = hypot(b.x, b.y);
     if (ab == 0.0) return r;
-    const double hpp = a[static_cast<int64_t>(p) * n + p].x;
-    const double hqq = a[static_cast<int64_t>(q) * n + q].x;
     const double tau = (hqq - hpp) / (2.0 * ab);
     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    const double c = 1.0 / sqrt(1.0 + t * t);
+    // c = 1 / sqrt(1 + t^2), then one Newton step on c^2 (1 + t^2) = 1 with the
+    // products kept exact by fma: for small t the rounded c alone leaves
+    // c^2 + |S|^2 - 1 at about +eps/2 on average, a bias that thousands of
+    // rotations per entry turn into a (1 + O(1e-13)) scaling of the spectrum
+    const double c0 = 1.0 / sqrt(1.0 + t * t);
+    const double pp = c0 * c0, pe = fma(c0, c0, -pp);
+    const double qq = t * t, qe = fma(t, t, -qq);
+    const double res = (pp - 1.0) + pe + fma(pp, qq, pp * qe + pe * qq);
+    const double c = c0 - 0.5 * c0 * res;
     const double sc = t * c / ab;  // S = t c b / |b|
     r.c = c;
     r.s = make_double2(sc * b.x, sc * b.y);
     return r;
+}
+
+__device__ __forceinline__ Rot rotation(const double2* __restrict__ a, int n, int p, int q) {
+    if (q >= n) return Rot{1.0, make_double2(0.0, 0.0)};
+    return rotation_of(a[static_cast<int64_t>(p) * n + p].x, a[static_cast<int64_t>(q) * n + q].x,
+                       a[static_cast<int64_t>(p) * n + q]);
 }
 
 // blocks [0, na): 2 x 2 blocks (k1, k2) of A; blocks [na, ...): (row, pair) of V
@@ -411,6 +421,239 @@ __global__ __launch_bounds__(256) void jacobi_step_kernel(const double2* __restr
     const double2 u = cmul(sc, xq), w = cmul(ro.s, xp);
     v_out[static_cast<int64_t>(i) * n + p] = make_double2(ro.c * xp.x - u.x, ro.c * xp.y - u.y);
     v_out[static_cast<int64_t>(i) * n + q] = make_double2(w.x + ro.c * xq.x, w.y + ro.c * xq.y);
+}
+
+// ---------------------------------------------------------------- block Jacobi
+//
+// For n >= kBJMin the same rotations are grouped by blocks of kBJ = 16
+// indices.  The blocks (n rounded up to whole blocks, then to an even count;
+// a block past n is a phantom) meet in the round-robin order above, and in
+// one block step each pair of blocks (I, J) owns the 32 x 32 Hermitian
+// sub-matrix S = A[I u J, I u J]:
+//   1. one workgroup per pair runs one cyclic sweep of the element rotations
+//      on S in LDS (31 steps of 16 disjoint rotations) and accumulates them
+//      into the unitary Q = J_1 J_2 ... J_31;
+//   2. one launch applies every pair's Q at once: the tile of A on rows
+//      I_k u J_k and columns I_l u J_l becomes Q_k^H A[., .] Q_l, and the
+//      columns I_l u J_l of V become V[:, .] Q_l.
+// A tile depends only on its own entries and two Q's, so step 2 is in place;
+// the tiles with k <= l are computed and the others written as their
+// conjugate transposes, which keeps A exactly Hermitian.  A block sweep
+// (blocks - 1 steps) meets every pair of indices at least once, as an element
+// sweep does, but reads and writes A and V once per block step instead of
+// once per element step.  Entries past n are zero in S, so their rotations
+// are the identity and never couple them with the others; they are neither
+// read nor written.
+
+constexpr int kBJ = 16, kBP = 2 * kBJ, kBJMin = 64;
+
+struct Quad {  // a 2 x 2 block of complex entries
+    double2 a00, a01, a10, a11;
+};
+
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {  // c + a b
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 cfma_conj_a(double2 a, double2 b, double2 c) {  // c + conj(a) b
+    return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+
+__device__ __forceinline__ int bj_row(int t, int bp, int bq) {  // local index -> global index
+    return t < kBJ ? bp * kBJ + t : bq * kBJ + (t - kBJ);
+}
+
+// one pair's sweep; q_out[pair] = Q (32 x 32, row-major)
+__global__ __launch_bounds__(256) void bj_inner_kernel(const double2* __restrict__ a, int n,
+                                                       int nbp, int r,
+                                                       double2* __restrict__ q_out,
+                                                       int64_t a_stride, int64_t q_stride) {
+    const int64_t bz = blockIdx.z;
+    a += bz * a_stride;
+    q_out += bz * q_stride + static_cast<int64_t>(blockIdx.x) * kBP * kBP;
+    const int bp = rr_index(blockIdx.x, r, nbp), bq = rr_index(nbp - 1 - blockIdx.x, r, nbp);
+    __shared__ double2 sm[kBP][kBP + 1];
+    __shared__ double2 qm[kBP][kBP + 1];
+    __shared__ double rc[kBP / 2];
+    __shared__ double2 rs[kBP / 2];
+    const int t = threadIdx.x;
+    for (int e = t; e < kBP * kBP; e += 256) {
+        const int i = e / kBP, j = e % kBP;
+        const int gi = bj_row(i, bp, bq), gj = bj_row(j, bp, bq);
+        sm[i][j] = gi < n && gj < n ? a[static_cast<int64_t>(gi) * n + gj] : make_double2(0.0, 0.0);
+        qm[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    const int k1 = t / (kBP / 2), k2 = t % (kBP / 2);
+    for (int r2 = 0; r2 < kBP - 1; ++r2) {
+        if (t < kBP / 2) {
+            int p, q;
+            rr_pair(t, r2, kBP, p, q);
+            const Rot ro = rotation_of(sm[p][p].x, sm[q][q].x, sm[p][q]);
+            rc[t] = ro.c;
+            rs[t] = ro.s;
+        }
+        __syncthreads();
+        int p1, q1, p2, q2;
+        rr_pair(k1, r2, kBP, p1, q1);
+        rr_pair(k2, r2, kBP, p2, q2);
+        const double c1 = rc[k1], c2 = rc[k2];
+        const double2 s1 = rs[k1], s2 = rs[k2];
+        const double2 s1c = make_double2(s1.x, -s1.y), s2c = make_double2(s2.x, -s2.y);
+        // right: [x_p, x_q] <- [c x_p - conj(S) x_q, S x_p + c x_q]
+        auto right = [&](double2 xp, double2 xq, double2& op, double2& oq) {
+            const double2 u = cmul(s2c, xq), w = cmul(s2, xp);
+            op = make_double2(c2 * xp.x - u.x, c2 * xp.y - u.y);
+            oq = make_double2(w.x + c2 * xq.x, w.y + c2 * xq.y);
+        };
+        // left: rows p' = c row_p - S row_q, q' = conj(S) row_p + c row_q
+        auto left = [&](double2 xp, double2 xq, double2& op, double2& oq) {
+            const double2 u = cmul(s1, xq), w = cmul(s1c, xp);
+            op = make_double2(c1 * xp.x - u.x, c1 * xp.y - u.y);
+            oq = make_double2(w.x + c1 * xq.x, w.y + c1 * xq.y);
+        };
+        double2 bpp, bpq, bqp, bqq, cpp, cpq, cqp, cqq;
+        right(sm[p1][p2], sm[p1][q2], bpp, bpq);
+        right(sm[q1][p2], sm[q1][q2], bqp, bqq);
+        left(bpp, bqp, cpp, cqp);
+        left(bpq, bqq, cpq, cqq);
+        if (k1 == k2) {  // the rotated pair: exact zeros off the diagonal, real diagonal
+            cpq = cqp = make_double2(0.0, 0.0);
+            cpp.y = 0.0;
+            cqq.y = 0.0;
+        }
+        sm[p1][p2] = cpp;
+        sm[p1][q2] = cpq;
+        sm[q1][p2] = cqp;
+        sm[q1][q2] = cqq;
+        // Q <- Q J on rows k1 and k1 + 16, columns (p2, q2)
+        for (int h = 0; h < 2; ++h) {
+            const int i = k1 + h * (kBP / 2);
+            double2 op, oq;
+            right(qm[i][p2], qm[i][q2], op, oq);
+            qm[i][p2] = op;
+            qm[i][q2] = oq;
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < kBP * kBP; e += 256) q_out[e] = qm[e / kBP][e % kBP];
+}
+
+// Workgroups [0, na): tiles (k, l), k <= l, of A, numbered row by row of the
+// upper triangle of pairs; [na, na + ceil(n / 32) * npair): tiles (row chunk,
+// pair l) of V.  Each thread owns a 2 x 2 block of the 32 x 32 tile.
+__global__ __launch_bounds__(256) void bj_update_kernel(double2* __restrict__ a,
+                                                        double2* __restrict__ v, int n, int nbp,
+                                                        int r, const double2* __restrict__ qs,
+                                                        int64_t a_stride, int64_t q_stride,
+                                                        int na) {
+    const int64_t bz = blockIdx.z;
+    a += bz * a_stride;
+    v += bz * a_stride;
+    qs += bz * q_stride;
+    const int npair = nbp / 2;
+    __shared__ double2 xm[kBP][kBP + 1];
+    __shared__ double2 ym[kBP][kBP + 1];
+    __shared__ double2 qk[kBP][kBP + 1];
+    __shared__ double2 ql[kBP][kBP + 1];
+    const int t = threadIdx.x;
+    const int i0 = 2 * (t / (kBP / 2)), j0 = 2 * (t % (kBP / 2));
+    const double2 zero = make_double2(0.0, 0.0);
+    // (x q_l)[i0.., j0..]
+    auto mul_right = [&]() {
+        const double2 z = make_double2(0.0, 0.0);
+        Quad acc{z, z, z, z};
+#pragma unroll 4
+        for (int c = 0; c < kBP; ++c) {
+            const double2 x0 = xm[i0][c], x1 = xm[i0 + 1][c];
+            const double2 b0 = ql[c][j0], b1 = ql[c][j0 + 1];
+            acc.a00 = cfma(x0, b0, acc.a00);
+            acc.a01 = cfma(x0, b1, acc.a01);
+            acc.a10 = cfma(x1, b0, acc.a10);
+            acc.a11 = cfma(x1, b1, acc.a11);
+        }
+        return acc;
+    };
+    int blk = blockIdx.x;
+    if (blk < na) {
+        int k = 0;
+        while (blk >= npair - k) {
+            blk -= npair - k;
+            ++k;
+        }
+        const int l = k + blk;
+        const int bpk = rr_index(k, r, nbp), bqk = rr_index(nbp - 1 - k, r, nbp);
+        const int bpl = rr_index(l, r, nbp), bql = rr_index(nbp - 1 - l, r, nbp);
+        for (int e = t; e < kBP * kBP; e += 256) {
+            const int i = e / kBP, j = e % kBP;
+            const int gi = bj_row(i, bpk, bqk), gj = bj_row(j, bpl, bql);
+            xm[i][j] = gi < n && gj < n ? a[static_cast<int64_t>(gi) * n + gj] : make_double2(0.0, 0.0);
+            qk[i][j] = qs[static_cast<int64_t>(k) * kBP * kBP + e];
+            ql[i][j] = qs[static_cast<int64_t>(l) * kBP * kBP + e];
+        }
+        __syncthreads();
+        const Quad y = mul_right();
+        ym[i0][j0] = y.a00;
+        ym[i0][j0 + 1] = y.a01;
+        ym[i0 + 1][j0] = y.a10;
+        ym[i0 + 1][j0 + 1] = y.a11;
+        __syncthreads();
+        // T = q_k^H y
+        Quad tt{zero, zero, zero, zero};
+#pragma unroll 4
+        for (int c = 0; c < kBP; ++c) {
+            const double2 h0 = qk[c][i0], h1 = qk[c][i0 + 1];
+            const double2 y0 = ym[c][j0], y1 = ym[c][j0 + 1];
+            tt.a00 = cfma_conj_a(h0, y0, tt.a00);
+            tt.a01 = cfma_conj_a(h0, y1, tt.a01);
+            tt.a10 = cfma_conj_a(h1, y0, tt.a10);
+            tt.a11 = cfma_conj_a(h1, y1, tt.a11);
+        }
+        // xm is free (every thread has read it in mul_right before the barrier)
+        xm[i0][j0] = tt.a00;
+        xm[i0][j0 + 1] = tt.a01;
+        xm[i0 + 1][j0] = tt.a10;
+        xm[i0 + 1][j0 + 1] = tt.a11;
+        __syncthreads();
+        for (int e = t; e < kBP * kBP; e += 256) {
+            const int i = e / kBP, j = e % kBP;
+            if (k == l) {  // Hermitian part of the diagonal tile
+                const int gi = bj_row(i, bpk, bqk), gj = bj_row(j, bpk, bqk);
+                if (gi < n && gj < n) {
+                    const double2 x = xm[i][j], y = xm[j][i];
+                    a[static_cast<int64_t>(gi) * n + gj] =
+                        make_double2(0.5 * (x.x + y.x), i == j ? 0.0 : 0.5 * (x.y - y.y));
+                }
+            } else {
+                const int gi = bj_row(i, bpk, bqk), gj = bj_row(j, bpl, bql);
+                if (gi < n && gj < n) a[static_cast<int64_t>(gi) * n + gj] = xm[i][j];
+                // row i of the mirrored tile: rows I_l u J_l, columns I_k u J_k
+                const int hi = bj_row(i, bpl, bql), hj = bj_row(j, bpk, bqk);
+                if (hi < n && hj < n) {
+                    const double2 x = xm[j][i];
+                    a[static_cast<int64_t>(hi) * n + hj] = make_double2(x.x, -x.y);
+                }
+            }
+        }
+        return;
+    }
+    blk -= na;
+    const int chunk = blk / npair, l = blk % npair;
+    const int bpl = rr_index(l, r, nbp), bql = rr_index(nbp - 1 - l, r, nbp);
+    const int row0 = chunk * kBP;
+    for (int e = t; e < kBP * kBP; e += 256) {
+        const int i = e / kBP, j = e % kBP;
+        const int gj = bj_row(j, bpl, bql);
+        xm[i][j] = row0 + i < n && gj < n ? v[static_cast<int64_t>(row0 + i) * n + gj] : make_double2(0.0, 0.0);
+        ql[i][j] = qs[static_cast<int64_t>(l) * kBP * kBP + e];
+    }
+    __syncthreads();
+    const Quad y = mul_right();
+    const double2 out[4] = {y.a00, y.a01, y.a10, y.a11};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int gi = row0 + i0 + e / 2, gj = bj_row(j0 + e % 2, bpl, bql);
+        if (gi < n && gj < n) v[static_cast<int64_t>(gi) * n + gj] = out[e];
+    }
 }
 
 __global__ __launch_bounds__(256) void eye_kernel(double2* __restrict__ v, int n, int64_t stride) {
@@ -630,33 +873,50 @@ void chol_inverse(double2* g, double2* rinv, int n, void* work, hipStream_t s) {
 }
 
 size_t jacobi_work_bytes(int n, int batch) {
+    // reduction partials and the two results per entry
+    const size_t red = static_cast<size_t>(batch) * kRedBlocks * 2 * 8 +
+                       static_cast<size_t>(batch) * 2 * 8 + 512;
+    if (n >= kBJMin) {  // one Q per pair of blocks
+        const int nblk = ceil_div(n, kBJ), nbp = nblk + (nblk & 1);
+        const size_t qb = static_cast<size_t>(nbp / 2) * kBP * kBP * sizeof(double2) * batch;
+        return ((qb + 255) & ~size_t(255)) + red;
+    }
+    // second A and V buffers
     const size_t nn = static_cast<size_t>(n) * n * batch * sizeof(double2);
-    // second A and V buffers, reduction partials and the two results per entry
-    return 2 * ((nn + 255) & ~size_t(255)) + static_cast<size_t>(batch) * kRedBlocks * 2 * 8 +
-           static_cast<size_t>(batch) * 2 * 8 + 512;
+    return 2 * ((nn + 255) & ~size_t(255)) + red;
 }
 
 int jacobi_eigh(double2* a, double2* v, int n, int batch, double tol, int max_sweeps, void* work,
                 hipStream_t s) {
     if (n <= 0 || batch <= 0) return 0;
     const int64_t nn = static_cast<int64_t>(n) * n;
-    const size_t nnb = (static_cast<size_t>(nn) * batch * sizeof(double2) + 255) & ~size_t(255);
+    const bool blocked = n >= kBJMin;
+    const int nblk = ceil_div(n, kBJ), nbp = nblk + (nblk & 1), npair = nbp / 2;
+    const int64_t q_stride = static_cast<int64_t>(npair) * kBP * kBP;
+    const size_t first =
+        blocked ? ((static_cast<size_t>(q_stride) * batch * sizeof(double2) + 255) & ~size_t(255))
+                : 2 * ((static_cast<size_t>(nn) * batch * sizeof(double2) + 255) & ~size_t(255));
     char* w = static_cast<char*>(work);
-    double2* a2 = reinterpret_cast<double2*>(w);
-    double2* v2 = reinterpret_cast<double2*>(w + nnb);
-    double* part = reinterpret_cast<double*>(w + 2 * nnb);
+    double* part = reinterpret_cast<double*>(w + first);
     double* res = part + static_cast<size_t>(batch) * kRedBlocks * 2;
     const unsigned eb = static_cast<unsigned>(std::min<int64_t>(ceil_div64(nn, 256), 4096));
     hipLaunchKernelGGL(eye_kernel, dim3(eb, 1, batch), dim3(256), 0, s, v, n, nn);
     GW_HIP_TRY(hipGetLastError());
     if (n == 1) return 0;
+    // element sweeps: A and V ping-pong between the caller's buffers and the work area
     const int np = n + (n & 1), half = np / 2;
-    const int64_t na = static_cast<int64_t>(half) * half;
-    const int64_t total = na + static_cast<int64_t>(n) * half;
-    const dim3 grid(static_cast<unsigned>(ceil_div64(total, 256)), 1, batch);
+    const int64_t na_el = static_cast<int64_t>(half) * half;
+    const dim3 grid_el(static_cast<unsigned>(ceil_div64(na_el + static_cast<int64_t>(n) * half, 256)),
+                       1, batch);
+    const size_t nnb = (static_cast<size_t>(nn) * batch * sizeof(double2) + 255) & ~size_t(255);
+    double2 *ac = a, *an = reinterpret_cast<double2*>(w), *vc = v,
+            *vn = reinterpret_cast<double2*>(w + nnb);
+    // block sweeps: in place, Q's in the work area
+    double2* qs = reinterpret_cast<double2*>(w);
+    const int na_bl = npair * (npair + 1) / 2;
+    const int nv_bl = ceil_div(n, kBP) * npair;
     std::vector<double> h(2 * static_cast<size_t>(batch));
     std::vector<double> prev(batch, -1.0);
-    double2 *ac = a, *an = a2, *vc = v, *vn = v2;
     int sweeps = 0;
     for (; sweeps < max_sweeps; ++sweeps) {
         hipLaunchKernelGGL(offnorm_partial_kernel, dim3(kRedBlocks, 1, batch), dim3(256), 0, s, ac,
@@ -679,11 +939,20 @@ int jacobi_eigh(double2* a, double2* v, int n, int batch, double tol, int max_sw
         }
         if (done) break;
         ProfScope ps("jacobi_sweep", s);
-        for (int r = 0; r < np - 1; ++r) {
-            hipLaunchKernelGGL(jacobi_step_kernel, grid, dim3(256), 0, s, ac, an, vc, vn, n, np, r,
-                               na, nn);
-            std::swap(ac, an);
-            std::swap(vc, vn);
+        if (blocked) {
+            for (int r = 0; r < nbp - 1; ++r) {
+                hipLaunchKernelGGL(bj_inner_kernel, dim3(npair, 1, batch), dim3(256), 0, s, ac, n,
+                                   nbp, r, qs, nn, q_stride);
+                hipLaunchKernelGGL(bj_update_kernel, dim3(na_bl + nv_bl, 1, batch), dim3(256), 0,
+                                   s, ac, vc, n, nbp, r, qs, nn, q_stride, na_bl);
+            }
+        } else {
+            for (int r = 0; r < np - 1; ++r) {
+                hipLaunchKernelGGL(jacobi_step_kernel, grid_el, dim3(256), 0, s, ac, an, vc, vn, n,
+                                   np, r, na_el, nn);
+                std::swap(ac, an);
+                std::swap(vc, vn);
+            }
         }
         GW_HIP_TRY(hipGetLastError());
     }

@@ -49,8 +49,10 @@ void launch_gather_cols(const double2* in, double2* out, int rows, int n_in, int
 
 // Eigen-decomposition of `batch` Hermitian n x n matrices (row-major, leading
 // dimension n, batch stride n*n) by cyclic two-sided Jacobi rotations in
-// parallel (round-robin) order: on return the diagonal of a holds the
-// eigenvalues, v (n x n, columns = eigenvectors) satisfies A0 v = v diag(a).
+// parallel (round-robin) order, for n >= 64 grouped into blocks of 16 whose
+// pairs are rotated in LDS and applied as 32 x 32 unitaries: on return the
+// diagonal of a holds the eigenvalues, v (n x n, columns = eigenvectors)
+// satisfies A0 v = v diag(a).
 // `work` holds jacobi_work_bytes(n, batch) bytes.  Sweeps until the
 // off-diagonal Frobenius norm is below tol times the Frobenius norm, or
 // max_sweeps; returns the sweeps made (reads one scalar per sweep back: the

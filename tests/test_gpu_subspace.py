@@ -52,7 +52,9 @@ def test_zgemm_shapes(m, n, k):
     assert rel_fro(got, a @ b) < 1e-14 if k else np.all(got == 0)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 64, 129])
+# n < 64: element sweeps; n >= 64: blocks of 16 (129: a ragged last block and
+# a phantom block; 300: 19 blocks, ragged, odd count)
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 64, 129, 300])
 def test_heev_matches_numpy(n):
     rng = np.random.default_rng(n)
     x = _crand(rng, 2, n, n)
@@ -60,23 +62,25 @@ def test_heev_matches_numpy(n):
     a[1] *= 1e-3                              # a second, differently scaled matrix
     w, v = gw.gw_heev(torch.from_numpy(a).to(device()))
     w, v = w.cpu().numpy(), v.cpu().numpy()
+    tol = 1e-13
     for i in range(2):
         scale = np.abs(np.linalg.eigvalsh(a[i])).max()
-        assert np.abs(w[i] - np.linalg.eigvalsh(a[i])).max() < 1e-13 * scale
-        assert np.abs(v[i].conj().T @ v[i] - np.eye(n)).max() < 1e-13
-        assert np.abs(a[i] @ v[i] - v[i] * w[i][None, :]).max() < 1e-13 * scale
+        assert np.abs(w[i] - np.linalg.eigvalsh(a[i])).max() < tol * scale
+        assert np.abs(v[i].conj().T @ v[i] - np.eye(n)).max() < tol
+        assert np.abs(a[i] @ v[i] - v[i] * w[i][None, :]).max() < tol * scale
 
 
-def test_heev_degenerate_spectrum():
+@pytest.mark.parametrize("n", [40, 200])
+def test_heev_degenerate_spectrum(n):
     rng = np.random.default_rng(3)
-    n = 40
     u, _ = np.linalg.qr(_crand(rng, n, n))
-    lam = np.repeat([-2.0, 0.5, 3.0, 3.0 + 1e-9], 10)
+    lam = np.repeat([-2.0, 0.5, 3.0, 3.0 + 1e-9], n // 4)
     a = (u * lam) @ u.conj().T
     w, v = gw.gw_heev(torch.from_numpy(a).to(device()))
     w, v = w.cpu().numpy(), v.cpu().numpy()
-    assert np.abs(w - np.sort(lam)).max() < 1e-13 * 3
-    assert np.abs(a @ v - v * w[None, :]).max() < 1e-13 * 3
+    tol = 1e-13
+    assert np.abs(w - np.sort(lam)).max() < tol * 3
+    assert np.abs(a @ v - v * w[None, :]).max() < tol * 3
 
 
 def _known_spectrum(ng, lam, seed):
