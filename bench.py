@@ -520,6 +520,34 @@ def bench_chi0_48cube(args):
           ", ".join(f"{k} {v[1] / args.steps:.2f}" for k, v in kernels.items()),
           file=sys.stderr, flush=True)
 
+    # MTXEL alone, after the timed region: the step's 64 x 960 pairs as 16
+    # rows of 4 valence bands (the pipeline's chunk rectangle) through
+    # gw_mtxel with nothing else on the GPU
+    mt_out = torch.empty((4 * p.nc, p.ng), dtype=torch.complex128, device=dev)
+
+    def mtxel_step():
+        for v0 in range(0, p.nv, 4):
+            gw.gw_mtxel(dp.psi_v[v0:v0 + 4], dp.psi_c, p.gvec, p.n, p.volume, out=mt_out)
+
+    mtxel_step()
+    torch.cuda.synchronize()
+    mt_reps = 3
+    gw.profile_reset()
+    gw.profile_enable(True)
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev_a.record()
+    for _ in range(mt_reps):
+        mtxel_step()
+    ev_b.record()
+    torch.cuda.synchronize()
+    gw.profile_enable(False)
+    mt_alone = ev_a.elapsed_time(ev_b) / mt_reps
+    mt_kern = {k: round(gw.profile_read(k)[1] / mt_reps, 3) for k in ("mtxel_zy", "mtxel_x")}
+    gw.profile_reset()
+    del mt_out
+    print(f"[bench] MTXEL alone: {mt_alone:.2f} ms per step ({mt_kern})", file=sys.stderr,
+          flush=True)
+
     ng, npairs, nz = p.ng, p.npairs, len(p.z)
     flops_step = 8.0 * ng * ng * npairs * nz
     value = flops_step * args.steps / elapsed / 1e12
@@ -569,6 +597,13 @@ def bench_chi0_48cube(args):
         },
         "pairs_per_s": round(pairs_s, 1),
         "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in kernels.items()},
+        "mtxel": {
+            "alone_ms_per_step": round(mt_alone, 3),
+            "alone_kernel_ms_per_step": mt_kern,
+            "alone_ms_per_chunk": round(mt_alone / -(-p.nv // 4), 4),
+            "pairs_per_chunk": 4 * p.nc,
+            "share_of_step": round(mt_alone / (elapsed / args.steps * 1e3), 4),
+        },
         "roofline": {
             "kernel": "chi0_f64_kernel",
             "bound": "mfma",

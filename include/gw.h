@@ -215,7 +215,10 @@ gw_status_t gw_chi0(const gw_problem_t* probs, int32_t nprob,
  *   g_rho(r) = dV * sum_G g_M(G) exp(-i G.r)
  *   dL/dpsi_c = sum_v psi_v * g_rho,  dL/dpsi_v = sum_c psi_c * conj(g_rho)
  *
- * M chunks are recomputed, not stored.  Outputs (device, overwritten):
+ * M chunks are recomputed, not stored.  Where Delta is real (zero and
+ * imaginary frequencies) the product runs against W + W^H, formed once per
+ * call for every frequency when those planes fit GW_SYM_KEEP_BYTES of scratch
+ * (default 1 GiB), else once per chunk.  Outputs (device, overwritten):
  * grad_psi_v [nv][N_r], grad_psi_c [nc][N_r], grad_e_v [nv], grad_e_c [nc];
  * any of them may be NULL to skip it.  prob->chi is not read.
  */

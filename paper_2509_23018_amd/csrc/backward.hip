@@ -15,6 +15,7 @@
 // Every reduction runs in a fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <vector>
 
 #include "backward.hpp"
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(256) void de_kernel(const double2* __restrict__ qpa
     double acc = 0.0;
     for (int w = 0; w < nz; ++w) {
         double qr = 0.0, qi = 0.0;
+#pragma unroll 8
         for (int p = 0; p < nparts; ++p) {
             const double2 q = qpart[(static_cast<int64_t>(w) * nparts + p) * kc + k];
             qr += q.x;
@@ -263,16 +265,31 @@ __global__ __launch_bounds__(256) void de_kernel(const double2* __restrict__ qpa
     de[k] = spin * acc;
 }
 
+// Energy gradients of one chunk from de[vl][cl]: workgroup v < vcount adds
+// row v (sum over the chunk's conduction bands, a tree in LDS) into
+// g_ev[v0 + v]; workgroups from vcount on take 256 conduction bands each and
+// subtract their columns (sums over at most the chunk's valence bands).
 __global__ __launch_bounds__(256) void de_reduce_kernel(const double* __restrict__ de, int vcount,
                                                         int cw, int v0, int c0,
                                                         double* __restrict__ g_ev,
                                                         double* __restrict__ g_ec) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g_ev && i < vcount) {
+    const int t = threadIdx.x;
+    if (static_cast<int>(blockIdx.x) < vcount) {
+        if (!g_ev) return;
+        const int v = blockIdx.x;
         double acc = 0.0;
-        for (int c = 0; c < cw; ++c) acc += de[static_cast<int64_t>(i) * cw + c];
-        g_ev[v0 + i] += acc;
+        for (int c = t; c < cw; c += 256) acc += de[static_cast<int64_t>(v) * cw + c];
+        __shared__ double red[256];
+        red[t] = acc;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) g_ev[v0 + v] += red[0];
+        return;
     }
+    const int i = (blockIdx.x - vcount) * 256 + t;
     if (g_ec && i < cw) {
         double acc = 0.0;
         for (int v = 0; v < vcount; ++v) acc += de[static_cast<int64_t>(v) * cw + i];
@@ -720,6 +737,12 @@ bool real_delta(const gw_problem_t& p, int w) {
 }
 
 // Chunking and scratch layout of one adjoint call.
+// Budget for keeping W + W^H of every frequency (GW_SYM_KEEP_BYTES overrides)
+size_t sym_keep_bytes() {
+    const char* e = std::getenv("GW_SYM_KEEP_BYTES");
+    return e ? static_cast<size_t>(std::strtoull(e, nullptr, 10)) : size_t(1) << 30;
+}
+
 struct BwdLayout {
     int vb = 1, cwmax = 1;
     int64_t kmax = 0;
@@ -730,7 +753,11 @@ struct BwdLayout {
     // intermediate; o_t2: the x-stage output of the inverse transform
     size_t o_m[2] = {0, 0}, o_d[2] = {0, 0}, o_dd[2] = {0, 0};
     size_t o_t2m = 0, o_t2 = 0, o_gm = 0, o_q = 0, o_de = 0, o_rho = 0, o_vp = 0;
-    size_t o_ws = 0;  // W + W^H of one frequency (frequencies with a real Delta)
+    // W + W^H (frequencies with a real Delta): of every frequency, formed once
+    // per call, when those planes fit in sym_keep_bytes() (sym_all); else of
+    // one, formed again per chunk
+    size_t o_ws = 0;
+    bool sym_all = false;
     size_t total = 0;
 };
 
@@ -781,7 +808,9 @@ BwdLayout bwd_layout(const MtxelPlan& plan, const gw_problem_t& p, bool want_psi
     L.o_gm = cv.take(kmax * ng * sizeof(double2));
     bool any_sym = false;
     for (int w = 0; w < nz; ++w) any_sym = any_sym || real_delta(p, w);
-    L.o_ws = cv.take(any_sym ? static_cast<size_t>(ng) * ng * sizeof(double2) : 0);
+    const size_t plane = static_cast<size_t>(ng) * ng * sizeof(double2);
+    L.sym_all = any_sym && static_cast<size_t>(nz) * plane <= sym_keep_bytes();
+    L.o_ws = cv.take(any_sym ? (L.sym_all ? static_cast<size_t>(nz) : 1) * plane : 0);
     L.o_q = cv.take(kmax * nz * L.nparts * sizeof(double2));
     L.o_de = cv.take(kmax * sizeof(double));
     L.o_rho = cv.take(want_psi && !L.fuse ? kmax * nr * sizeof(double2) : 0);
@@ -882,6 +911,15 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
         }
         GW_HIP_TRY(hipEventRecord(ev[1 + b], aux));
     };
+    if (L.sym_all) {
+        ProfScope ps("bwd_gm", s);
+        for (int w = 0; w < nz; ++w)
+            if (real_delta(p, w))
+                hipLaunchKernelGGL(sym_kernel, dim3(ceil_div(ng, 32), ceil_div(ng, 32)), dim3(256),
+                                   0, s, grad_chi + static_cast<int64_t>(w) * ng * ng, ng,
+                                   wsym + static_cast<int64_t>(w) * ng * ng);
+        GW_HIP_TRY(hipGetLastError());
+    }
     GW_HIP_TRY(hipEventRecord(ev[0], s));
     GW_HIP_TRY(hipStreamWaitEvent(aux, ev[0], 0));
     produce(0);
@@ -901,7 +939,9 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                 // Delta real: one product against W + W^H
                 const bool sym = real_delta(p, w);
                 const double2* wop = grad_chi + static_cast<int64_t>(w) * ng * ng;
-                if (sym) {
+                if (sym && L.sym_all) {
+                    wop = wsym + static_cast<int64_t>(w) * ng * ng;
+                } else if (sym) {
                     hipLaunchKernelGGL(sym_kernel, dim3(ceil_div(ng, 32), ceil_div(ng, 32)),
                                        dim3(256), 0, s, wop, ng, wsym);
                     wop = wsym;
@@ -921,7 +961,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
                     GW_HIP_TRY(hipGetLastError());
                 }
                 ProfScope ps("bwd_de_reduce", s);
-                hipLaunchKernelGGL(de_reduce_kernel, dim3(ceil_div(std::max(vcount, cw), 256)),
+                hipLaunchKernelGGL(de_reduce_kernel, dim3(vcount + ceil_div(cw, 256)),
                                    dim3(256), 0, s, de, vcount, cw, v0, c0, grad_e_v, grad_e_c);
                 GW_HIP_TRY(hipGetLastError());
             }

@@ -44,6 +44,25 @@ def test_backward_matches_oracle_adjoint(zs, chunk, nv, nc, herm):
         assert rel_fro(g.cpu().numpy(), r) < FP64_TOL
 
 
+def test_backward_sym_planes_per_call_or_per_chunk():
+    """W + W^H formed once per call for every real-Delta frequency (the
+    default when the planes fit) or once per chunk (a 1-byte budget): the
+    same products on the same operands, so the same bits."""
+    import os
+    p = gen.make_problem((12, 10, 14), 4, 11, r2=9, z=(0.25, 0.3 + 0.02j, 0.6j), seed=23,
+                         pair_chunk=23)
+    w = torch.from_numpy(_herm(np.random.default_rng(7), len(p.z), p.ng)).to(device())
+    dp = to_dev(p)
+    want = gw.gw_chi0_backward(dp, w, pair_chunk=23)
+    os.environ["GW_SYM_KEEP_BYTES"] = "1"
+    try:
+        got = gw.gw_chi0_backward(dp, w, pair_chunk=23)
+    finally:
+        os.environ.pop("GW_SYM_KEEP_BYTES", None)
+    for g, r in zip(got, want):
+        assert torch.equal(g, r)
+
+
 @pytest.mark.parametrize("zs,chunk,nv,nc", [
     ((0.0,), 17, 4, 11),
     ((0.2j,), 1000, 12, 3),                 # one chunk of 12 valence bands: the unfused path
