@@ -224,10 +224,10 @@ def bench_chi0_72cube(args):
                             gvec=w.gvec, z=w.z, chi=chi) for b in range(nblk)]
     acc = gw.GW_FLAG_ACCUMULATE | gw.GW_FLAG_ACC_HERMITIAN
 
-    def step(k, prec="fp64", ns=0):
+    def step(k, prec="fp64", ns=0, extra=0):
         b = k % nblk
         gw.gw_chi0(probs[b], precision=prec, n_slices=ns, pair_chunk=w.pair_chunk,
-                   flags=0 if b == 0 else acc)
+                   flags=(0 if b == 0 else acc) | extra)
 
     for k in range(args.warmup):
         step(k)
@@ -355,15 +355,22 @@ def bench_chi0_72cube(args):
     rows = np.sort(np.random.default_rng(1002).choice(ng, 32, replace=False))
     rows_d = torch.from_numpy(rows).to(dev)
 
+    # whole builds with the autotuner (FP64 tile, split LDS ring), its choices
+    # logged to a file; the warm-up step of each build does the tuning
+    import tempfile
+    tune_fd, tune_path = tempfile.mkstemp(prefix="gw_autotune_", suffix=".txt")
+    os.close(tune_fd)
+    os.environ["GW_AUTOTUNE_CACHE"] = tune_path
+
     def build(prec, ns):
         """One whole chi0 (all 16 NV blocks); returns seconds and the 32 rows."""
-        step(0, prec, ns)                      # warm-up (plans, slice buffers)
+        step(0, prec, ns, gw.GW_FLAG_AUTOTUNE)  # warm-up (plans, slice buffers, tuning)
         torch.cuda.synchronize()
         gw.profile_reset()
         gw.profile_enable(True)
         t = time.perf_counter()
         for k in range(nblk):
-            step(k, prec, ns)
+            step(k, prec, ns, gw.GW_FLAG_AUTOTUNE)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         gw.profile_enable(False)
@@ -395,6 +402,10 @@ def bench_chi0_72cube(args):
                       f"{err:.2e}")
     out["whole_build"] = full
     del ref_rows
+    with open(tune_path) as fh:
+        out["whole_build_autotune"] = [ln.strip() for ln in fh if ln.strip()]
+    os.environ.pop("GW_AUTOTUNE_CACHE", None)
+    os.remove(tune_path)
 
     # every precision on a 4 x 256-band sample of the same bands against the
     # FP64 oracle (which is also the CPU baseline)
@@ -681,8 +692,8 @@ def bench_batched(args):
     """64 q-points (4x4x4 shifted grid) on a 40^3 grid, 48 valence bands and
     300-900 conduction bands each, G-spheres of 400-4,000 vectors, 16
     imaginary frequencies: one graph-captured gw_chi0 call over all problems,
-    FP64 (with the tile autotuner, its choices kept in a cache file) and split
-    BF16.  Band sets are drawn on the GPU; every precision is checked against
+    FP64 and split BF16, with the autotuner (FP64 tile shape, split LDS ring;
+    its choices kept in a cache file).  Band sets are drawn on the GPU; every precision is checked against
     the FP64 oracle's direct sums on 16 x 16 sampled entries of the q-points
     with the fewest and the most G."""
     import tempfile
@@ -734,7 +745,7 @@ def bench_batched(args):
                 np.sort(srng.choice(int(ngs[q]), 16, replace=False))) for q in osample}
     dev_entries = {}
     for prec, ns in [("fp64", 0)] + [("split_bf16", k) for k in args.split_slices]:
-        flags = gw.GW_FLAG_GRAPH | (gw.GW_FLAG_AUTOTUNE if prec == "fp64" else 0)
+        flags = gw.GW_FLAG_GRAPH | gw.GW_FLAG_AUTOTUNE
 
         def call():
             gw.gw_chi0(probs, precision=prec, n_slices=ns, flags=flags)
@@ -749,7 +760,7 @@ def bench_batched(args):
         gw.profile_reset()
         run = {"precision": prec, "n_slices": ns or None, "s_per_call": round(dt, 4),
                "first_call_s": round(t_cap, 3), "tflops": round(flops / dt / 1e12, 3),
-               "pairs_per_s": round(pairs / dt, 1), "autotune": prec == "fp64"}
+               "pairs_per_s": round(pairs / dt, 1), "autotune": True}
         key = f"{prec}{ns or ''}"
         dev_entries[key] = {}
         for q in osample:

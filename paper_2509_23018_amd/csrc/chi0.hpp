@@ -66,7 +66,8 @@ size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S);
 void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        const double2* delta, int nz, const WList& wl, double2* chi,
                        bool accumulate, void* scratch, hipStream_t s,
-                       double2* tail_ws = nullptr);  // precisions 2 and 4 (launch_chi0_sbf16)
+                       double2* tail_ws = nullptr,  // precisions 2 and 4 (launch_chi0_sbf16)
+                       int variant = 0);            // their LDS ring, 0..kNumSplitVariants-1
 void launch_chi0_f32(const double2* m, int64_t kc, int ng, const double2* delta, const WList& wl,
                      double2* chi, bool accumulate, hipStream_t s);
 constexpr int kSplitTile = 64;  // tile edge of the FP16-split and FP32 kernels
@@ -75,9 +76,16 @@ constexpr int kSplitTile = 64;  // tile edge of the FP16-split and FP32 kernels
 // 128-wide square blocks); same scratch layout size as launch_chi0_split.
 // With tail_ws (device, sbf16_tail_bytes() bytes) a last partial round of
 // tiles is cut along the exponent blocks and reduced by a second launch.
+// variant: the LDS ring (0: the preferred stage height and depth for S; 1:
+// the other stage height), the same arithmetic in the same order.
+constexpr int kNumSplitVariants = 2;
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
-                       hipStream_t s, double2* tail_ws = nullptr, bool f16 = false);
+                       hipStream_t s, double2* tail_ws = nullptr, bool f16 = false,
+                       int variant = 0);
+// Workgroups of the split-BF16 contraction with S slices and ring variant rv
+// resident on the current device.
+int sbf16_slots(int S, int rv = 0);
 size_t sbf16_tail_bytes();  // for the current device
 // Operands of one problem's chunk for the split-BF16 contraction (device
 // pointers into scratch; frequency w's B slices and sigma follow at fixed
@@ -100,9 +108,10 @@ SbDesc sbf16_desc(int S, int64_t kc, int ng, int nz, void* scratch, bool f16 = f
 SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const double2* delta,
                          int nz, const WList& wl, void* scratch, hipStream_t s, bool f16 = false);
 // Persistent split-BF16 contraction over items (problem, frequency, 128-row
-// block, 64-column block); counter must be 0 on entry.
+// block, 64-column block); counter must be 0 on entry.  variant: the LDS ring,
+// as for launch_chi0_sbf16.
 void launch_chi0_sbf16_batched(int S, const SbDesc* qd, const int4* items, int nitems,
-                               int* counter, int grid, hipStream_t s);
+                               int* counter, int grid, hipStream_t s, int variant = 0);
 constexpr int kSbTileI = 128, kSbTileJ = 64;  // split-BF16 workgroup tile
 
 // Tile edge whose on-or-above-diagonal blocks a reduced-precision mode computes.

@@ -451,12 +451,13 @@ size_t split_scratch_bytes(int64_t kmax, int ng, int nz, int S) {
 
 void launch_chi0_split(int prec, int S, const double2* m, int64_t kc, int ng,
                        const double2* delta, int nz, const WList& wl, double2* chi,
-                       bool accumulate, void* scratch, hipStream_t s, double2* tail_ws) {
+                       bool accumulate, void* scratch, hipStream_t s, double2* tail_ws,
+                       int variant) {
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
     if (prec == 2 || prec == 4) {
         launch_chi0_sbf16(S, m, kc, ng, delta, nz, wl, chi, accumulate, scratch, s, tail_ws,
-                          prec == 4);
+                          prec == 4, variant);
         return;
     }
     const int nkb = static_cast<int>((kc + kBlk - 1) / kBlk);

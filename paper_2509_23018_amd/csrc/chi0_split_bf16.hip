@@ -29,6 +29,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "chi0.hpp"
@@ -254,8 +255,10 @@ __device__ __forceinline__ void wait_vm_lgkm0() {
 // the same number of 16-byte loads per step (spare lanes fetch a valid
 // address into padding), so "this step has landed" is vmcnt(loads per step)
 // after the next step's loads are in flight.
-// Stage geometry of the contraction for S slices and NW waves.
-template <int S, int NW>
+// Stage geometry of the contraction for S slices and NW waves; RV picks the
+// ring (0: the preferred one below; 1: the other stage height, for the
+// autotuner).
+template <int S, int NW, int RV = 0>
 struct SbGeom {
     static constexpr int NT = NW * 64;
     static constexpr int CA = kTI * 2 * S, CB = kTJ * 2 * S;  // slice chunks (16 B) per k-step
@@ -270,7 +273,10 @@ struct SbGeom {
     // chunk; at five slices, with the same slot size, it is not.
     static constexpr size_t kSlot = static_cast<size_t>(NCHP) * 16;
     static constexpr size_t kMax = 159 * 1024;
-    static constexpr int KSUB = S == 4 ? 1 : 6 * kSlot <= kMax || 4 * kSlot <= kMax ? 2 : 1;
+    static constexpr int KSUB0 = S == 4 ? 1 : 6 * kSlot <= kMax || 4 * kSlot <= kMax ? 2 : 1;
+    // variant 1: one k-step per stage where variant 0 takes two, two where it
+    // takes one and four slots fit (else the same ring as variant 0)
+    static constexpr int KSUB = RV == 0 ? KSUB0 : KSUB0 == 2 ? 1 : 4 * kSlot <= kMax ? 2 : 1;
     static constexpr int kStages = KSUB == 2 ? (6 * kSlot <= kMax ? 3 : 2) : (4 * kSlot <= kMax ? 4 : 3);
     static constexpr int NSLOT = KSUB * kStages;
     static constexpr size_t lds_bytes = NSLOT * kSlot;
@@ -281,7 +287,7 @@ struct SbGeom {
 // sb and sigb are that frequency's B slices and sigma.  The caller has made
 // sure every wave of the workgroup calls this with the same arguments and
 // that no earlier reader of lds is still running.
-template <class F, int S, int NWI, int NWJ, int BI, int BJ, bool PART = false>
+template <class F, int S, int NWI, int NWJ, int BI, int BJ, bool PART = false, int RV = 0>
 __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                                            const double* __restrict__ siga,
                                            const u32x4* __restrict__ sb,
@@ -289,7 +295,7 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
                                            int nkb, double2* __restrict__ cw, int mode, int bi,
                                            int bj, u32x4* __restrict__ lds) {
     static_assert(NWI * BI * 32 == kTI && NWJ * BJ * 32 == kTJ, "tile shape");
-    using Geo = SbGeom<S, NWI * NWJ>;
+    using Geo = SbGeom<S, NWI * NWJ, RV>;
     constexpr int NW = NWI * NWJ;
     constexpr int G = S < 3 ? S : 3;
     constexpr int CA = Geo::CA, CB = Geo::CB, CSA = Geo::CSA, CSB = Geo::CSB, NCH = Geo::NCH;
@@ -567,7 +573,7 @@ __device__ __forceinline__ void sbf16_tile(const u32x4* __restrict__ sa,
 // cut into `parts` ranges of 128-pair blocks: workgroup n_main + j*parts + p
 // writes item n_main + j's partial sum over range p to ws[j*parts + p]
 // (kTI x kTJ), and sbf16_tail_reduce_kernel adds the parts into chi.
-template <class F, int S, int NWI, int NWJ, int BI, int BJ>
+template <class F, int S, int NWI, int NWJ, int BI, int BJ, int RV>
 __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     const u32x4* __restrict__ sa, const double* __restrict__ siga, const u32x4* __restrict__ sb_all,
     const double* __restrict__ sigb_all, int ng, int ngp, int nkb, WList wl,
@@ -581,7 +587,7 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     if (b < n_main) {
         rect_item_tile(xcd_item(b, n_main), wl, nb, order, w, bi, bj);
         if (bj * kTJ >= ng) return;  // right half of the last block column lies past N_G
-        sbf16_tile<F, S, NWI, NWJ, BI, BJ>(sa, siga, sb_all + w * plane,
+        sbf16_tile<F, S, NWI, NWJ, BI, BJ, false, RV>(sa, siga, sb_all + w * plane,
                                         sigb_all + static_cast<size_t>(w) * nkb * ngp, ng, ngp,
                                         nkb, chi + static_cast<int64_t>(w) * ng * ng, mode, bi, bj,
                                         lds);
@@ -591,7 +597,7 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_kernel(
     rect_item_tile(n_main + j, wl, nb, order, w, bi, bj);
     if (bj * kTJ >= ng) return;  // nothing of it is ever read
     const int kb0 = p * nkb / parts, kb1 = (p + 1) * nkb / parts;
-    sbf16_tile<F, S, NWI, NWJ, BI, BJ, true>(
+    sbf16_tile<F, S, NWI, NWJ, BI, BJ, true, RV>(
         sa + kb0 * blk, siga + static_cast<size_t>(kb0) * ngp, sb_all + w * plane + kb0 * blk,
         sigb_all + (static_cast<size_t>(w) * nkb + kb0) * ngp, ng, ngp, kb1 - kb0,
         ws + static_cast<int64_t>(u) * kTI * kTJ, 0, bi, bj, lds);
@@ -625,7 +631,7 @@ __global__ __launch_bounds__(256) void sbf16_tail_reduce_kernel(
 
 // Persistent: workgroups pull items (problem, frequency, 128-row block,
 // 64-column block) from *counter until none is left.
-template <int S, int NWI, int NWJ, int BI, int BJ>
+template <int S, int NWI, int NWJ, int BI, int BJ, int RV>
 __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
     const SbDesc* __restrict__ qd, const int4* __restrict__ items, int nitems,
     int* __restrict__ counter) {
@@ -641,7 +647,7 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
         const SbDesc d = qd[t.x];
         if (t.w * kTJ >= d.ng) continue;
         const size_t plane = static_cast<size_t>(d.nkb) * ksteps<SlBf16>() * S * d.ng * 2;
-        sbf16_tile<SlBf16, S, NWI, NWJ, BI, BJ>(
+        sbf16_tile<SlBf16, S, NWI, NWJ, BI, BJ, false, RV>(
             reinterpret_cast<const u32x4*>(d.sa), d.siga,
             reinterpret_cast<const u32x4*>(d.sb) + t.y * plane,
             d.sigb + static_cast<size_t>(t.y) * d.nkb * d.ngp, d.ng, d.ngp, d.nkb,
@@ -649,13 +655,13 @@ __global__ __launch_bounds__(NWI* NWJ * 64) void chi0_sbf16_batched_kernel(
     }
 }
 
-template <class F, int S, int NWI, int NWJ, int BI, int BJ>
+template <class F, int S, int NWI, int NWJ, int BI, int BJ, int RV>
 void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
                     const double* sigb, int ng, int ngp, int nkb, const WList& wl, double2* chi,
                     bool accumulate, int nb, int n_main, int parts, double2* ws, int grid,
                     hipStream_t s) {
-    const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
-    auto fn = chi0_sbf16_kernel<F, S, NWI, NWJ, BI, BJ>;
+    const size_t lds = SbGeom<S, NWI * NWJ, RV>::lds_bytes;
+    auto fn = chi0_sbf16_kernel<F, S, NWI, NWJ, BI, BJ, RV>;
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
@@ -666,10 +672,11 @@ void launch_sbf16_t(const uint32_t* sa, const double* siga, const uint32_t* sb,
 }
 
 // Workgroups of the S-slice contraction resident on one CU.
-template <int S, int NWI, int NWJ, int BI, int BJ>
+template <int S, int NWI, int NWJ, int BI, int BJ, int RV>
 int sbf16_per_cu_t() {
-    const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
-    const void* fn = reinterpret_cast<const void*>(chi0_sbf16_kernel<SlBf16, S, NWI, NWJ, BI, BJ>);
+    const size_t lds = SbGeom<S, NWI * NWJ, RV>::lds_bytes;
+    const void* fn =
+        reinterpret_cast<const void*>(chi0_sbf16_kernel<SlBf16, S, NWI, NWJ, BI, BJ, RV>);
     GW_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
     int n = 0;
@@ -677,29 +684,38 @@ int sbf16_per_cu_t() {
     return std::max(1, n);
 }
 
-// Workgroups of the S-slice contraction resident on the current device.
-int sbf16_slots(int S) {
+}  // namespace
+
+// Workgroups of the S-slice contraction (ring variant rv) resident on the
+// current device.
+int sbf16_slots(int S, int rv) {
     static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;  // (device, S) -> slots
+    static std::map<std::tuple<int, int, int>, int> cache;  // (device, S, rv) -> slots
     int dev = 0;
     GW_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(mu);
-    int& n = cache[{dev, S}];
+    int& n = cache[{dev, S, rv}];
     if (n > 0) return n;
     int per_cu = 1, cus = 0;
-    switch (S) {
-        case 2: per_cu = sbf16_per_cu_t<2, 4, 2, 1, 1>(); break;
-        case 3: per_cu = sbf16_per_cu_t<3, 4, 2, 1, 1>(); break;
-        case 4: per_cu = sbf16_per_cu_t<4, 4, 2, 1, 1>(); break;
-        case 5: per_cu = sbf16_per_cu_t<5, 4, 2, 1, 1>(); break;
-        default: per_cu = sbf16_per_cu_t<6, 4, 2, 1, 1>(); break;
-    }
+    auto pick = [&](auto rvc) {
+        constexpr int R = decltype(rvc)::value;
+        switch (S) {
+            case 2: per_cu = sbf16_per_cu_t<2, 4, 2, 1, 1, R>(); break;
+            case 3: per_cu = sbf16_per_cu_t<3, 4, 2, 1, 1, R>(); break;
+            case 4: per_cu = sbf16_per_cu_t<4, 4, 2, 1, 1, R>(); break;
+            case 5: per_cu = sbf16_per_cu_t<5, 4, 2, 1, 1, R>(); break;
+            default: per_cu = sbf16_per_cu_t<6, 4, 2, 1, 1, R>(); break;
+        }
+    };
+    if (rv == 1)
+        pick(std::integral_constant<int, 1>{});
+    else
+        pick(std::integral_constant<int, 0>{});
     GW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     n = per_cu * std::max(1, cus);
     return n;
 }
 
-}  // namespace
 
 // Bytes of the layout sbf16_desc describes: A slices, A sigma, nz B slices,
 // nz B sigma, each rounded up to 256 B (f16: the FP16 9-bit format).
@@ -755,13 +771,15 @@ SbDesc launch_sbf16_prep(int S, const double2* m, int64_t kc, int ng, const doub
 
 size_t sbf16_tail_bytes() {
     int slots = 0;
-    for (int S = 2; S <= 6; ++S) slots = std::max(slots, sbf16_slots(S));
+    for (int S = 2; S <= 6; ++S)
+        for (int rv = 0; rv < kNumSplitVariants; ++rv) slots = std::max(slots, sbf16_slots(S, rv));
     return static_cast<size_t>(slots) * kTI * kTJ * sizeof(double2);
 }
 
 void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double2* delta, int nz,
                        const WList& wl, double2* chi, bool accumulate, void* scratch,
-                       hipStream_t s, double2* tail_ws, bool f16) {
+                       hipStream_t s, double2* tail_ws, bool f16, int variant) {
+    if (variant < 0 || variant >= kNumSplitVariants) variant = 0;
     if (kc <= 0 || wl.nh + wl.nf == 0) return;
     if (S < 2 || S > (f16 ? SlF16x9::SMAX : SlBf16::SMAX))
         throw Error{-4, f16 ? "split FP16 supports 2..4 slices" : "split BF16 supports 2..6 slices"};
@@ -774,7 +792,7 @@ void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double
     // along the 128-pair blocks (as in launch_chi0_f64).
     int n_main = static_cast<int>(nitems), parts = 1, n_tail = 0;
     if (tail_ws) {
-        const int slots = sbf16_slots(S);
+        const int slots = sbf16_slots(S, variant);
         const int rem = static_cast<int>(nitems % slots);
         const int pc = std::min(rem > 0 ? slots / rem : 0, d.nkb);
         if (rem > 0 && 2 * rem <= slots && pc >= 2) {
@@ -786,35 +804,35 @@ void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double
     const int grid = n_main + n_tail * parts;
     {
         ProfScope ps("chi0_split", s);
-        if (f16) {
+        auto run = [&](auto fmt, auto sc, auto rvc) {
+            using F = decltype(fmt);
+            launch_sbf16_t<F, decltype(sc)::value, 4, 2, 1, 1, decltype(rvc)::value>(
+                d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, chi, accumulate, nb, n_main,
+                parts, tail_ws, grid, s);
+        };
+        auto by_s = [&](auto fmt, auto rvc) {
             switch (S) {
-#define GW_SF_LAUNCH(SS)                                                                          \
-    case SS:                                                                                      \
-        launch_sbf16_t<SlF16x9, SS, 4, 2, 1, 1>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, \
-                                                chi, accumulate, nb, n_main, parts, tail_ws, grid, \
-                                                s);                                                \
-        break;
-                GW_SF_LAUNCH(2)
-                GW_SF_LAUNCH(3)
-                GW_SF_LAUNCH(4)
-#undef GW_SF_LAUNCH
+                case 2: run(fmt, std::integral_constant<int, 2>{}, rvc); break;
+                case 3: run(fmt, std::integral_constant<int, 3>{}, rvc); break;
+                case 4: run(fmt, std::integral_constant<int, 4>{}, rvc); break;
+                case 5:
+                    if constexpr (decltype(fmt)::SMAX >= 5) run(fmt, std::integral_constant<int, 5>{}, rvc);
+                    break;
+                default:
+                    if constexpr (decltype(fmt)::SMAX >= 6) run(fmt, std::integral_constant<int, 6>{}, rvc);
+                    break;
             }
-        } else {
-            switch (S) {
-#define GW_SB_LAUNCH(SS)                                                                         \
-    case SS:                                                                                     \
-        launch_sbf16_t<SlBf16, SS, 4, 2, 1, 1>(d.sa, d.siga, d.sb, d.sigb, ng, d.ngp, d.nkb, wl, \
-                                               chi, accumulate, nb, n_main, parts, tail_ws, grid, \
-                                               s);                                                \
-        break;
-                GW_SB_LAUNCH(2)
-                GW_SB_LAUNCH(3)
-                GW_SB_LAUNCH(4)
-                GW_SB_LAUNCH(5)
-                GW_SB_LAUNCH(6)
-#undef GW_SB_LAUNCH
-            }
-        }
+        };
+        auto by_rv = [&](auto fmt) {
+            if (variant == 1)
+                by_s(fmt, std::integral_constant<int, 1>{});
+            else
+                by_s(fmt, std::integral_constant<int, 0>{});
+        };
+        if (f16)
+            by_rv(SlF16x9{});
+        else
+            by_rv(SlBf16{});
         GW_HIP_TRY(hipGetLastError());
     }
     if (n_tail > 0) {
@@ -827,12 +845,12 @@ void launch_chi0_sbf16(int S, const double2* m, int64_t kc, int ng, const double
 }
 
 namespace {
-template <int S>
+template <int S, int RV>
 void launch_sbf16_batched_s(const SbDesc* qd, const int4* items, int nitems, int* counter, int grid,
                             hipStream_t s) {
     constexpr int NWI = 4, NWJ = 2;
-    const size_t lds = SbGeom<S, NWI * NWJ>::lds_bytes;
-    auto fn = chi0_sbf16_batched_kernel<S, NWI, NWJ, 1, 1>;
+    const size_t lds = SbGeom<S, NWI * NWJ, RV>::lds_bytes;
+    auto fn = chi0_sbf16_batched_kernel<S, NWI, NWJ, 1, 1, RV>;
     GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    static_cast<int>(lds)));
@@ -842,18 +860,25 @@ void launch_sbf16_batched_s(const SbDesc* qd, const int4* items, int nitems, int
 }  // namespace
 
 void launch_chi0_sbf16_batched(int S, const SbDesc* qd, const int4* items, int nitems,
-                               int* counter, int grid, hipStream_t s) {
+                               int* counter, int grid, hipStream_t s, int variant) {
     if (nitems <= 0) return;
     if (S < 2 || S > 6) throw Error{-4, "split precision supports 2..6 slices"};
     grid = std::max(1, std::min(grid, nitems));
     ProfScope ps("chi0_split_batched", s);
-    switch (S) {
-        case 2: launch_sbf16_batched_s<2>(qd, items, nitems, counter, grid, s); break;
-        case 3: launch_sbf16_batched_s<3>(qd, items, nitems, counter, grid, s); break;
-        case 4: launch_sbf16_batched_s<4>(qd, items, nitems, counter, grid, s); break;
-        case 5: launch_sbf16_batched_s<5>(qd, items, nitems, counter, grid, s); break;
-        default: launch_sbf16_batched_s<6>(qd, items, nitems, counter, grid, s); break;
-    }
+    auto by_s = [&](auto rvc) {
+        constexpr int R = decltype(rvc)::value;
+        switch (S) {
+            case 2: launch_sbf16_batched_s<2, R>(qd, items, nitems, counter, grid, s); break;
+            case 3: launch_sbf16_batched_s<3, R>(qd, items, nitems, counter, grid, s); break;
+            case 4: launch_sbf16_batched_s<4, R>(qd, items, nitems, counter, grid, s); break;
+            case 5: launch_sbf16_batched_s<5, R>(qd, items, nitems, counter, grid, s); break;
+            default: launch_sbf16_batched_s<6, R>(qd, items, nitems, counter, grid, s); break;
+        }
+    };
+    if (variant == 1)
+        by_s(std::integral_constant<int, 1>{});
+    else
+        by_s(std::integral_constant<int, 0>{});
     GW_HIP_TRY(hipGetLastError());
 }
 

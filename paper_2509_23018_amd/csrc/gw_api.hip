@@ -4,12 +4,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cctype>
 #include <cstring>
 #include <functional>
 #include <list>
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_set>
 #include <utility>
 #include <vector>
@@ -342,12 +344,14 @@ bool autotune_enabled(const Opts& o) {
     return env || (o.flags & GW_FLAG_AUTOTUNE);
 }
 
-// Best FP64 tile variant per (N_G, chunk pairs), chosen by timing every
-// candidate on real data once; kept for the process and, when GW_AUTOTUNE_CACHE
-// names a file, in that file ("ng kc variant ms..." per line).
+// Best variant per (kernel, N_G, chunk pairs), chosen by timing every
+// candidate on real data once: the FP64 tile shape (kernel "f64") or the LDS
+// ring of a split contraction ("sbf16-S<n>", "f16x9-S<n>").  Kept for the
+// process and, when GW_AUTOTUNE_CACHE names a file, in that file ("kernel ng
+// kc variant ms..." per line; a line without the kernel name is an FP64 one).
 struct TuneCache {
     std::mutex mu;
-    std::map<std::pair<int, int64_t>, int> best;
+    std::map<std::tuple<std::string, int, int64_t>, int> best;
     bool loaded = false;
 };
 
@@ -358,40 +362,62 @@ TuneCache& tune_cache() {
 
 const char* tune_file() { return std::getenv("GW_AUTOTUNE_CACHE"); }
 
-int lookup_variant(int ng, int64_t kc) {
-    const int forced = chi0_forced_variant();
-    if (forced >= 0) return forced < kNumChi0Variants ? forced : 0;
+// Tuning key and number of candidates of a contraction precision.
+std::string tune_kind(const Opts& o) {
+    if (o.precision == GW_FP64) return "f64";
+    return std::string(o.precision == 4 ? "f16x9" : "sbf16") + "-S" + std::to_string(o.n_slices);
+}
+int tune_count(const std::string& kind) { return kind == "f64" ? kNumChi0Variants : kNumSplitVariants; }
+
+// Forced split ring (GW_SPLIT_VARIANT), or -1.
+int split_forced_variant() {
+    const char* e = std::getenv("GW_SPLIT_VARIANT");
+    if (!e) return -1;
+    const int v = std::atoi(e);
+    return v >= 0 && v < kNumSplitVariants ? v : 0;
+}
+
+int lookup_variant(const std::string& kind, int ng, int64_t kc) {
+    const int forced = kind == "f64" ? chi0_forced_variant() : split_forced_variant();
+    if (forced >= 0) return forced < tune_count(kind) ? forced : 0;
     TuneCache& tc = tune_cache();
     std::lock_guard<std::mutex> lk(tc.mu);
     if (!tc.loaded) {
         tc.loaded = true;
         if (const char* f = tune_file()) {
             if (FILE* fp = std::fopen(f, "r")) {
-                int a, v;
-                long long b;
-                char line[256];
-                while (std::fgets(line, sizeof line, fp))
-                    if (std::sscanf(line, "%d %lld %d", &a, &b, &v) == 3 && v >= 0 &&
-                        v < kNumChi0Variants)
-                        tc.best[{a, b}] = v;
+                char line[512], name[64];
+                while (std::fgets(line, sizeof line, fp)) {
+                    int a, v;
+                    long long b;
+                    if (std::sscanf(line, "%63s %d %lld %d", name, &a, &b, &v) == 4 &&
+                        !std::isdigit(static_cast<unsigned char>(name[0]))) {
+                        if (v >= 0 && v < tune_count(name)) tc.best[{name, a, b}] = v;
+                    } else if (std::sscanf(line, "%d %lld %d", &a, &b, &v) == 3 && v >= 0 &&
+                               v < kNumChi0Variants) {
+                        tc.best[{"f64", a, b}] = v;
+                    }
+                }
                 std::fclose(fp);
             }
         }
     }
-    auto it = tc.best.find({ng, kc});
+    auto it = tc.best.find({kind, ng, kc});
     return it == tc.best.end() ? -1 : it->second;
 }
 
 // trial(v) enqueues variant v's contraction of the same data on s.
-int tune_variant(int ng, int64_t kc, hipStream_t s, const std::function<void(int)>& trial) {
-    const int known = lookup_variant(ng, kc);
+int tune_variant(const std::string& kind, int ng, int64_t kc, hipStream_t s,
+                 const std::function<void(int)>& trial) {
+    const int known = lookup_variant(kind, ng, kc);
     if (known >= 0) return known;
+    const int nv = tune_count(kind);
     hipEvent_t e0, e1;
     GW_HIP_TRY(hipEventCreate(&e0));
     GW_HIP_TRY(hipEventCreate(&e1));
-    float ms[kNumChi0Variants];
+    std::vector<float> ms(nv, 0.0f);
     int best = 0;
-    for (int v = 0; v < kNumChi0Variants; ++v) {
+    for (int v = 0; v < nv; ++v) {
         trial(v);  // warm-up (kernel load, caches)
         GW_HIP_TRY(hipEventRecord(e0, s));
         trial(v);
@@ -404,11 +430,11 @@ int tune_variant(int ng, int64_t kc, hipStream_t s, const std::function<void(int
     (void)hipEventDestroy(e1);
     TuneCache& tc = tune_cache();
     std::lock_guard<std::mutex> lk(tc.mu);
-    tc.best[{ng, kc}] = best;
+    tc.best[{kind, ng, kc}] = best;
     if (const char* f = tune_file()) {
         if (FILE* fp = std::fopen(f, "a")) {
-            std::fprintf(fp, "%d %lld %d", ng, static_cast<long long>(kc), best);
-            for (int v = 0; v < kNumChi0Variants; ++v) std::fprintf(fp, " %.4f", ms[v]);
+            std::fprintf(fp, "%s %d %lld %d", kind.c_str(), ng, static_cast<long long>(kc), best);
+            for (int v = 0; v < nv; ++v) std::fprintf(fp, " %.4f", ms[v]);
             std::fprintf(fp, "\n");
             std::fclose(fp);
         }
@@ -450,9 +476,12 @@ char* call_scratch(size_t need, const Opts& o, hipStream_t s) {
     return static_cast<char*>(scratch(need, s));
 }
 
-// The autotuner may time tile shapes inside this call (FP64, default tile).
+// The autotuner may time variants inside this call: FP64 tile shapes (default
+// tile) or the LDS ring of the split-BF16 / 9-bit FP16 contractions.
 bool tune_candidate(const Opts& o) {
-    return o.precision == GW_FP64 && !(o.flags & GW_FLAG_FP64_TILE128) && autotune_enabled(o);
+    const bool f64 = o.precision == GW_FP64 && !(o.flags & GW_FLAG_FP64_TILE128);
+    const bool split = o.precision == 2 || o.precision == 4;
+    return (f64 || split) && autotune_enabled(o);
 }
 
 // Scratch layout of one problem's pipeline.  nbuf M/Delta buffers (2: MTXEL
@@ -560,10 +589,11 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
     };
     int variant = 0;
     bool tune = false;
+    const bool split_ring = o.precision == 2 || o.precision == 4;
     if (o.precision == GW_FP64 && (o.flags & GW_FLAG_FP64_TILE128)) {
         variant = 1;
-    } else if (o.precision == GW_FP64) {
-        variant = lookup_variant(L.ncols, chunks[0].kc);
+    } else if (o.precision == GW_FP64 || split_ring) {
+        variant = lookup_variant(tune_kind(o), L.ncols, chunks[0].kc);
         tune = variant < 0 && autotune_enabled(o);
         if (variant < 0) variant = 0;
     }
@@ -619,9 +649,14 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
         one.w[0] = 0;
         one.nf = 1;
         double2* trial_chi = reinterpret_cast<double2*>(base + L.off_tune);
-        variant = tune_variant(L.ncols, chunks[0].kc, s, [&](int v) {
-            launch_chi0_f64(cmat(0), chunks[0].kc, L.ncols, dbuf[0], one, trial_chi, false, s, v,
-                            tail_ws);
+        variant = tune_variant(tune_kind(o), L.ncols, chunks[0].kc, s, [&](int v) {
+            if (split_ring)
+                launch_chi0_split(o.precision, o.n_slices, cmat(0), chunks[0].kc, L.ncols,
+                                  dbuf[0], pr.nz, one, trial_chi, false, base + L.off_sp, s,
+                                  tail_ws, v);
+            else
+                launch_chi0_f64(cmat(0), chunks[0].kc, L.ncols, dbuf[0], one, trial_chi, false,
+                                s, v, tail_ws);
         });
     }
     for (size_t k = 0; k < chunks.size(); ++k) {
@@ -641,7 +676,7 @@ void run_chi0(const gw_problem_t& pr, const Opts& o, hipStream_t s, char* base,
                 launch_chi0_f32(mk_k, chunks[k].kc, L.ncols, dbuf[b], wl, chi, acc, s);
             else
                 launch_chi0_split(o.precision, o.n_slices, mk_k, chunks[k].kc, L.ncols, dbuf[b],
-                                  pr.nz, wl, chi, acc, base + L.off_sp, s, tail_ws);
+                                  pr.nz, wl, chi, acc, base + L.off_sp, s, tail_ws, variant);
         }
         if (two_streams) GW_HIP_TRY(hipEventRecord(ax->ev[3 + b], s));
     }
@@ -693,7 +728,7 @@ int resident_cus() {
 }
 
 int persistent_grid(const BatchPlan& bp) {
-    if (bp.split) return resident_cus();  // one workgroup per CU (LDS ring)
+    if (bp.split) return sbf16_slots(bp.S, bp.variant);  // the LDS ring sets the residency
     return resident_cus() * chi0_f64_batched_blocks_per_cu(bp.variant);
 }
 
@@ -869,7 +904,7 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
             }
             launch_chi0_sbf16_batched(
                 bp.S, reinterpret_cast<const SbDesc*>(tab + bp.off_desc) + static_cast<size_t>(r) * nprob,
-                items, bp.nitems[r], counter, bp.grid, s);
+                items, bp.nitems[r], counter, bp.grid, s, bp.variant);
         } else {
             launch_chi0_f64_batched(
                 reinterpret_cast<const QDesc*>(tab + bp.off_desc) + static_cast<size_t>(r) * nprob,
@@ -891,7 +926,7 @@ void enqueue_batch(const BatchPlan& bp, const gw_problem_t* probs, const Opts& o
 // (M, Delta, t2) and one trial frequency plane.
 struct TuneLayout {
     int qmax = -1;
-    size_t om = 0, od = 0, ot = 0, oc = 0, total = 0;
+    size_t om = 0, od = 0, ot = 0, oc = 0, osp = 0, total = 0;
 };
 
 TuneLayout batch_tune_layout(const gw_problem_t* probs, int nprob, const Opts& o) {
@@ -911,16 +946,21 @@ TuneLayout batch_tune_layout(const gw_problem_t* probs, int nprob, const Opts& o
     t.od = cv.take(ch[0].kc * pr.nz * sizeof(double2));
     t.ot = cv.take(t2_elems(*plan, ch[0].kc) * sizeof(double2));
     t.oc = cv.take(static_cast<size_t>(pr.ng) * pr.ng * sizeof(double2));
+    if (o.precision == GW_SPLIT_BF16)
+        t.osp = cv.take(split_scratch_bytes(ch[0].kc, pr.ng, pr.nz, o.n_slices));
     t.total = cv.off;
     return t;
 }
 
-// Tile variant of a batch: forced, cached, or tuned on its largest problem's
-// first chunk (one frequency, into the call's scratch so no output is touched).
+// Tile variant (FP64) or LDS ring (split BF16) of a batch: forced, cached, or
+// tuned on its largest problem's first chunk (one frequency, into the call's
+// scratch so no output is touched; the split ring with the one-launch kernel
+// of the same tiles).
 int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream_t s,
                   char* base) {
-    if (o.precision != GW_FP64) return 0;
-    if (o.flags & GW_FLAG_FP64_TILE128) return 1;
+    const bool split = o.precision == GW_SPLIT_BF16;
+    if (o.precision != GW_FP64 && !split) return 0;
+    if (!split && (o.flags & GW_FLAG_FP64_TILE128)) return 1;
     int qmax = -1;
     for (int q = 0; q < nprob; ++q)
         if (static_cast<int64_t>(probs[q].nv) * probs[q].nc > 0 &&
@@ -930,7 +970,8 @@ int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream
     const gw_problem_t& pr = probs[qmax];
     const ChunkShape cs = chunk_shape(pr.nv, pr.nc, o.pair_chunk);
     const std::vector<Chunk> ch = make_chunks(pr, cs);
-    int v = lookup_variant(pr.ng, ch[0].kc);
+    const std::string kind = tune_kind(o);
+    int v = lookup_variant(kind, pr.ng, ch[0].kc);
     if (v >= 0) return v;
     if (!autotune_enabled(o)) return 0;
     const TuneLayout t = batch_tune_layout(probs, nprob, o);
@@ -944,10 +985,16 @@ int batch_variant(const gw_problem_t* probs, int nprob, const Opts& o, hipStream
     WList wl{};
     wl.w[0] = 0;
     wl.nf = 1;
-    v = tune_variant(pr.ng, ch[0].kc, s, [&](int vv) {
-        launch_chi0_f64(reinterpret_cast<const double2*>(base + t.om), ch[0].kc, pr.ng,
-                        reinterpret_cast<const double2*>(base + t.od), wl,
-                        reinterpret_cast<double2*>(base + t.oc), false, s, vv);
+    v = tune_variant(kind, pr.ng, ch[0].kc, s, [&](int vv) {
+        if (split)
+            launch_chi0_split(o.precision, o.n_slices, reinterpret_cast<const double2*>(base + t.om),
+                              ch[0].kc, pr.ng, reinterpret_cast<const double2*>(base + t.od), pr.nz,
+                              wl, reinterpret_cast<double2*>(base + t.oc), false, base + t.osp, s,
+                              nullptr, vv);
+        else
+            launch_chi0_f64(reinterpret_cast<const double2*>(base + t.om), ch[0].kc, pr.ng,
+                            reinterpret_cast<const double2*>(base + t.od), wl,
+                            reinterpret_cast<double2*>(base + t.oc), false, s, vv);
     });
     mark_plan_used(*plan, s);
     return v;
@@ -1081,6 +1128,13 @@ size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Tile variants the batch may run with (the layout of its tables depends on it).
 std::vector<int> possible_variants(const Opts& o) {
+    if (o.precision == GW_SPLIT_BF16) {
+        const int forced = split_forced_variant();
+        if (forced >= 0) return {forced};
+        std::vector<int> v;
+        for (int i = 0; i < kNumSplitVariants; ++i) v.push_back(i);
+        return v;
+    }
     if (o.precision != GW_FP64) return {0};
     if (o.flags & GW_FLAG_FP64_TILE128) return {1};
     const int forced = chi0_forced_variant();
@@ -1620,7 +1674,9 @@ gw_status_t gw_chi0_fixed(const gw_problem_t* prob, const gw_opts_t* opts, void*
             int variant = 0;
             if (o.precision == GW_FP64) {
                 const std::vector<Chunk> ch = make_chunks(*prob, L.cs);
-                variant = (o.flags & GW_FLAG_FP64_TILE128) ? 1 : std::max(0, lookup_variant(prob->ng, ch[0].kc));
+                variant = (o.flags & GW_FLAG_FP64_TILE128)
+                              ? 1
+                              : std::max(0, lookup_variant("f64", prob->ng, ch[0].kc));
             }
             require_tile_orders(o, prob->ng, variant);
         }
