@@ -111,8 +111,13 @@ enum {
 #define GW_FLAG_GRAPH         (1u << 2)  /* capture the whole call into a HIP graph on first
                                             use and replay it when called again with the same
                                             problems (same pointers, sizes, G lists, z, opts) */
-#define GW_FLAG_AUTOTUNE      (1u << 3)  /* time the CHI0 tile shapes on this data once per
-                                            shape and keep the fastest (also GW_AUTOTUNE=1) */
+#define GW_FLAG_AUTOTUNE      (1u << 3)  /* time the CHI0 variants on this data once per
+                                            (kernel, N_G, chunk) and keep the fastest (also
+                                            GW_AUTOTUNE=1): the FP64 tile shape, or the LDS
+                                            ring of the split-BF16 / 9-bit FP16 contraction
+                                            (same bits either way).  GW_AUTOTUNE_CACHE names
+                                            a file that keeps the choices; GW_CHI0_VARIANT and
+                                            GW_SPLIT_VARIANT force one */
 #define GW_FLAG_FP64_TILE128  (1u << 4)  /* FP64: contract on 128x128 tiles (8 waves, four
                                             real MFMA products per complex one) instead of the
                                             default 64x64 tiles; takes precedence over the
