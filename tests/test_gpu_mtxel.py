@@ -122,12 +122,17 @@ def _box_g(r1, r2, r3):
     ((5, 9, 32), _box_g((-2, 2), (-4, 4), (-7, 7))),      # N3 = 32
     ((7, 12, 48), _box_g((-3, 3), (-6, 5), (-8, 5))),     # N3 = 48, window not centred: unpaired k3
     ((4, 24, 64), _box_g((-1, 1), (-10, 10), (-6, 6))),   # N3 = 64, 21 k2 values: two y blocks
+    # more than 24 classes on both the y and z axes: four class blocks each
+    # (and 26 x 19), the stage-y accumulators beyond the registers of a wave
+    ((3, 52, 52), _box_g((-1, 1), (-25, 25), (-25, 25))),
+    ((3, 52, 40), _box_g((-1, 1), (-25, 25), (-18, 18))),
 ])
 def test_mtxel_box_g_lists(n, g):
-    """Box-shaped G lists with holes on grids with N3 a multiple of 16 (up to
-    64), the k3 values filling the window [-8, 7] or part of it off centre,
-    and 21 k2 values (two y-stage blocks): against the oracle, with ragged
-    pair tiles (3 valence x 37 conduction bands)."""
+    """Box-shaped G lists with holes on grids with N3 from 16 to 64, the k3
+    values filling the window [-8, 7] or part of it off centre, 21 k2 values
+    (two y-stage blocks), and 26 classes on y with 26 or 19 on z (the largest
+    stage-y blocks): against the oracle, with ragged pair tiles (3 valence x
+    37 conduction bands)."""
     keep = np.ones(len(g), bool)
     keep[::7] = False                    # holes in the disc
     g = np.ascontiguousarray(g[keep])
