@@ -118,12 +118,18 @@ __device__ __forceinline__ void wait_vmcnt() {
 //    row 4 t + kq sits in element t, so a class's cos row (t = 0, 1) and sin
 //    row (t = 2, 3) share a lane and T2 at k2 = +-a is formed in place.
 // k-steps of j3 or j2 beyond the grid (the padding to 16) are skipped.
-template <int NB2, int NB3, int PPW>
+// A launch takes the k2 class blocks [b2_0, b2_0 + NB2) of the plan's NB2T:
+// where all NB2T blocks of stage-y accumulators would not fit the registers
+// of a wave, two launches split them (each runs stage z again on the same
+// slabs and writes its own classes of T2).
+template <int NB2, int NB3, int PPW, int NB2T>
 __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const double2* __restrict__ psi_v, const double2* __restrict__ psi_c, int64_t nr, Rect rc,
     int n1, int planes_per_group, int n2, int n3, int n2p, int n3p,
     const double* __restrict__ w3re, const double* __restrict__ w2re,
-    const int* __restrict__ boxf, int n23, double2* __restrict__ t2, int ring) {
+    const int* __restrict__ boxf, int n23, double2* __restrict__ t2, int ring, int b2_first) {
+    static_assert(NB2 <= NB2T, "class blocks of one launch");
+    const int b2_0 = NB2 == NB2T ? 0 : b2_first;  // a constant where one launch takes all
     constexpr int TV = 4, TC = 2 * PPW, NBANDS = TV + TC;
     constexpr int NSLAB = NBANDS * 256;             // 16-byte entries per slab
     constexpr int NFILL = NSLAB / kZyThreads;       // loads per thread per slab
@@ -133,8 +139,8 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
     const int q = n3p >> 2;
     const int nrb1 = n2p >> 4;
     const int w3n = q * NB3 * 64;          // doubles (multiples of 64: whole double2 slots)
-    const int w2n = nrb1 * 4 * NB2 * 64;
-    constexpr int boxn = NB2 * 16 * NB3 * 16;
+    const int w2n = nrb1 * 4 * NB2T * 64;
+    constexpr int boxn = NB2T * 16 * NB3 * 16;
     double* s_w3 = reinterpret_cast<double*>(lds);
     double* s_w2 = reinterpret_cast<double*>(lds + w3n / 2);
     int* s_box = reinterpret_cast<int*>(lds + w3n / 2 + w2n / 2);
@@ -235,7 +241,8 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
                         for (int t = 0; t < 2; ++t) {
                             const double cr = a2r[p][b2][b3][t], ci = a2i[p][b2][b3][t];
                             const double sr = a2r[p][b2][b3][t + 2], si = a2i[p][b2][b3][t + 2];
-                            const int e = ((b2 * 8 + 4 * t + kq) * 2) * (NB3 * 16) + b3 * 16 + row;
+                            const int e =
+                                (((b2_0 + b2) * 8 + 4 * t + kq) * 2) * (NB3 * 16) + b3 * 16 + row;
                             const int dp = s_box[e], dm = s_box[e + NB3 * 16];
                             if (dp >= 0) o[dp] = make_double2(cr - si, ci + sr);
                             if (dm >= 0) o[dm] = make_double2(cr + si, ci - sr);
@@ -325,7 +332,7 @@ __global__ __launch_bounds__(kZyThreads) void mtxel_zy_kernel(
                     }
 #pragma unroll
                 for (int b2 = 0; b2 < NB2; ++b2) {
-                    const double w = s_w2[((rb1 * 4 + t) * 64 + lane) * NB2 + b2];
+                    const double w = s_w2[((rb1 * 4 + t) * 64 + lane) * NB2T + b2_0 + b2];
 #pragma unroll
                     for (int p = 0; p < PPW; ++p)
 #pragma unroll
@@ -423,7 +430,7 @@ __global__ __launch_bounds__(kThreads) void mtxel_x_kernel(
 }
 
 using ZyKernel = void (*)(const double2*, const double2*, int64_t, Rect, int, int, int, int, int,
-                          int, const double*, const double*, const int*, int, double2*, int);
+                          int, const double*, const double*, const int*, int, double2*, int, int);
 
 // Pairs per wave by the wider class-block count, within the registers of two
 // waves per SIMD.
@@ -431,19 +438,39 @@ constexpr int zy_ppw(int nb2, int nb3) {
     return (nb2 > nb3 ? nb2 : nb3) == 1 ? 4 : ((nb2 > nb3 ? nb2 : nb3) == 2 ? 2 : 1);
 }
 
+// The launches of stage z and y for a box of NB2 x NB3 class blocks: one, or
+// where the stage-y accumulators of all NB2 blocks would spill (more than
+// three blocks on one axis and three on the other), two over halves of the k2
+// blocks.
+struct ZyLaunches {
+    ZyKernel k[2];
+    int b2_0[2];
+    int count;
+};
+
 template <int NB2, int NB3>
-ZyKernel zy_ptr() {
-    return &mtxel_zy_kernel<NB2, NB3, zy_ppw(NB2, NB3)>;
+ZyLaunches zy_launches() {
+    if constexpr (NB2 * NB3 > 9) {
+        constexpr int H = (NB2 + 1) / 2;
+        return {{&mtxel_zy_kernel<H, NB3, zy_ppw(H, NB3), NB2>,
+                 &mtxel_zy_kernel<NB2 - H, NB3, zy_ppw(NB2 - H, NB3), NB2>},
+                {0, H}, 2};
+    } else {
+        return {{&mtxel_zy_kernel<NB2, NB3, zy_ppw(NB2, NB3), NB2>, nullptr}, {0, 0}, 1};
+    }
 }
 
-int zy_pairs_per_wave(int nb2, int nb3) { return zy_ppw(nb2, nb3); }
+// Pairs per wave of the launches of a box (the same for both halves).
+int zy_pairs_per_wave(int nb2, int nb3) {
+    return nb2 * nb3 > 9 ? zy_ppw((nb2 + 1) / 2, nb3) : zy_ppw(nb2, nb3);
+}
 
-ZyKernel select_zy(int nb2, int nb3) {
-    static const ZyKernel table[4][4] = {
-        {zy_ptr<1, 1>(), zy_ptr<1, 2>(), zy_ptr<1, 3>(), zy_ptr<1, 4>()},
-        {zy_ptr<2, 1>(), zy_ptr<2, 2>(), zy_ptr<2, 3>(), zy_ptr<2, 4>()},
-        {zy_ptr<3, 1>(), zy_ptr<3, 2>(), zy_ptr<3, 3>(), zy_ptr<3, 4>()},
-        {zy_ptr<4, 1>(), zy_ptr<4, 2>(), zy_ptr<4, 3>(), zy_ptr<4, 4>()},
+const ZyLaunches& select_zy(int nb2, int nb3) {
+    static const ZyLaunches table[4][4] = {
+        {zy_launches<1, 1>(), zy_launches<1, 2>(), zy_launches<1, 3>(), zy_launches<1, 4>()},
+        {zy_launches<2, 1>(), zy_launches<2, 2>(), zy_launches<2, 3>(), zy_launches<2, 4>()},
+        {zy_launches<3, 1>(), zy_launches<3, 2>(), zy_launches<3, 3>(), zy_launches<3, 4>()},
+        {zy_launches<4, 1>(), zy_launches<4, 2>(), zy_launches<4, 3>(), zy_launches<4, 4>()},
     };
     return table[nb2 - 1][nb3 - 1];
 }
@@ -749,11 +776,12 @@ void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c
     if (ldm == 0) ldm = rc.nc;
     const int64_t npairs = static_cast<int64_t>(rc.nv) * rc.nc;
     if (npairs <= 0) return;
-    ZyKernel kz = select_zy(p.nbh2, p.nbh3);
+    const ZyLaunches& zl = select_zy(p.nbh2, p.nbh3);
     const int ppw = zy_pairs_per_wave(p.nbh2, p.nbh3);
-    GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kz),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   static_cast<int>(p.lds_yz)));
+    for (int h = 0; h < zl.count; ++h)
+        GW_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(zl.k[h]),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(p.lds_yz)));
     {
         // pair tiles x groups of j1 planes: enough workgroups to fill the chip
         const int gx = ceil_div(rc.nc, 2 * ppw), gy = ceil_div(rc.nv, 4);
@@ -762,8 +790,10 @@ void launch_mtxel(const MtxelPlan& p, const double2* psi_v, const double2* psi_c
         const int pp = ceil_div(p.n[0], want);
         const dim3 grid(gx, gy, ceil_div(p.n[0], pp));
         ProfScope ps("mtxel_zy", s);
-        hipLaunchKernelGGL(kz, grid, dim3(kZyThreads), p.lds_yz, s, psi_v, psi_c, p.nr, rc, p.n[0],
-                           pp, p.n[1], p.n[2], p.n2p, p.n3p, p.w3re, p.w2re, p.boxf, p.n23, t2, p.ring);
+        for (int h = 0; h < zl.count; ++h)
+            hipLaunchKernelGGL(zl.k[h], grid, dim3(kZyThreads), p.lds_yz, s, psi_v, psi_c, p.nr, rc,
+                               p.n[0], pp, p.n[1], p.n[2], p.n2p, p.n3p, p.w3re, p.w2re, p.boxf,
+                               p.n23, t2, p.ring, zl.b2_0[h]);
         GW_HIP_TRY(hipGetLastError());
     }
     XKernel kx = select_x(p.nbh1);
