@@ -803,7 +803,7 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-ADJOINT_KERNELS = ("mtxel_zy", "mtxel_x", "delta", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x",
+ADJOINT_KERNELS = ("mtxel_zy", "mtxel_x", "delta", "bwd_sym", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x",
                    "bwd_yz", "bwd_yz_reduce", "bwd_reduce_c", "bwd_reduce_v")
 
 

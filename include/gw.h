@@ -537,7 +537,7 @@ int32_t gw_abi_version(void);
  * kernel launches and files the pair under the kernel's name ("mtxel_zy",
  * "mtxel_x", "delta", "chi0_f64", "chi0_tail", "chi0_f64_batched",
  * "split_prep", "chi0_split", "chi0_split_tail", "chi0_split_batched",
- * "chi0_f32", "mirror", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x", "bwd_yz",
+ * "chi0_f32", "mirror", "bwd_sym", "bwd_gm", "bwd_de", "bwd_de_reduce", "bwd_x", "bwd_yz",
  * "bwd_reduce_cv", "bwd_reduce_c", "bwd_reduce_v", "pseudo_prep", "pseudo_keep",
  * "pseudo_mix").
  * gw_profile_read waits for the recorded events of `kernel` and returns the

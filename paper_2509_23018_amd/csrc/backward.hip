@@ -912,7 +912,7 @@ void run_chi0_backward(const MtxelPlan& plan, const gw_problem_t& p, const doubl
         GW_HIP_TRY(hipEventRecord(ev[1 + b], aux));
     };
     if (L.sym_all) {
-        ProfScope ps("bwd_gm", s);
+        ProfScope ps("bwd_sym", s);
         for (int w = 0; w < nz; ++w)
             if (real_delta(p, w))
                 hipLaunchKernelGGL(sym_kernel, dim3(ceil_div(ng, 32), ceil_div(ng, 32)), dim3(256),
