@@ -458,7 +458,11 @@ __global__ __launch_bounds__(256) void bwd_yz_kernel(const double2* __restrict__
 
 constexpr int kFuseV = 8;   // valence bands of a chunk the fused band reductions take
 constexpr int kFuseC = 16;  // conduction bands per block of the fused band reductions
-constexpr int kPassV = 2;   // valence bands per pass of the fused inverse transform
+// Valence bands per pass of the fused inverse transform: each pass reads
+// psi_c and reads and writes grad_psi_c of the block's conduction bands once,
+// so wider passes move fewer bytes; their vpart sums stay in registers, and
+// four still leave two waves per SIMD up to two class blocks on the z axis.
+constexpr int pass_v(int nb3) { return nb3 <= 2 ? 4 : 2; }
 
 // Stages z and y of the inverse transform fused with both band reductions, so
 // that g_rho never leaves registers.  Workgroup (plane j1, block cb of kFuseC
@@ -472,8 +476,8 @@ constexpr int kPassV = 2;   // valence bands per pass of the fused inverse trans
 //       workgroup alone writes these points of these conduction bands);
 //   vpart[cb][vl](r) = sum_{cl in cb} psi_c[c0 + cl](r) conj(g_rho(r)), added
 //       over the blocks by vpart_reduce_kernel.
-// The valence bands go in passes of kPassV (their vpart sums stay in
-// registers), and T is formed again for each j2 block it feeds (a third more
+// The valence bands go in passes of pass_v(NB3) (their vpart sums stay in
+// registers, psi_v of a pair's band is loaded one pair ahead), and T is formed again for each j2 block it feeds (a third more
 // MFMA work on a plane of two j2 blocks), against 2 x 16 bytes per point and
 // pair of HBM traffic when g_rho is stored and read back.
 // On the smallest box (one class block on the y and z axes) everything that
@@ -490,7 +494,7 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
     double2* __restrict__ gpc, double2* __restrict__ vpart) {
     constexpr int KS2 = NB2 * 4;
     constexpr bool HOIST = NB2 * NB3 == 1;
-    constexpr int PV = kPassV;  // valence bands per pass
+    constexpr int PV = pass_v(NB3);  // valence bands per pass
     const int j1 = blockIdx.x, cb = blockIdx.y;
     const int cl0 = cb * kFuseC, ncl = min(cw, cl0 + kFuseC) - cl0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 15, kq = lane >> 4;
@@ -532,18 +536,21 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
             const int nvp = min(PV, vcount - vp);
             const int nq = ncl * nvp;  // pairs of this pass: q = cl * nvp + i
             double2 av[PV][4];
-            // psi_v of the pass's valence bands at this lane's points, read once
-            // for all the conduction bands of the block
-            double2 pvs[PV][4];
 #pragma unroll
-            for (int i = 0; i < PV; ++i) {
-                const double2* pvr = psi_v + static_cast<int64_t>(v0 + vp + min(i, nvp - 1)) * nr;
+            for (int i = 0; i < PV; ++i)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    av[i][t] = make_double2(0.0, 0.0);
-                    pvs[i][t] = pvr[pos[t]];
-                }
-            }
+                for (int t = 0; t < 4; ++t) av[i][t] = make_double2(0.0, 0.0);
+            // psi_v of a pair's valence band at this lane's points, loaded one
+            // pair ahead (the chunk's valence bands stay in the L2): registers
+            // for the vpart sums of a wider pass instead of a copy per band
+            auto load_pv = [&](int qq, double2 (&dst)[4]) {
+                const int c = qq / nvp;
+                const double2* pvr = psi_v + static_cast<int64_t>(v0 + vp + (qq - c * nvp)) * nr;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) dst[t] = pvr[pos[t]];
+            };
+            double2 pvc[4], pvn[4];
+            load_pv(0, pvc);
             // psi_c and the old grad_psi_c of conduction band cl at this lane's
             // points, loaded with its first pair (the MFMAs of that pair, and of
             // the band's other pairs, run before they are used)
@@ -567,14 +574,10 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
                         load_x(vp + (q + 1 - cn * nvp), cn, xnext);
                     }
                 }
+                if (q + 1 < nq) load_pv(q + 1, pvn);
                 double2 pv[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    pv[t] = pvs[0][t];
-#pragma unroll
-                    for (int ii = 1; ii < PV; ++ii)
-                        if (ii == i) pv[t] = pvs[ii][t];
-                }
+                for (int t = 0; t < 4; ++t) pv[t] = pvc[t];
                 dbl4 gr = zero4(), gi = zero4();
                 if constexpr (HOIST) {
                     // stage z on the one class block, then stage y
@@ -630,6 +633,8 @@ __global__ __launch_bounds__(256) void bwd_yz_reduce_kernel(
 #pragma unroll
                     for (int ii = 0; ii < 4; ++ii) xcur[ii] = xnext[ii];
                 }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pvc[t] = pvn[t];
             }
             if (vpart)
 #pragma unroll
