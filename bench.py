@@ -16,7 +16,7 @@ convention) and pairs/s, the roofline of the dominant kernel (chi0_f64, FP64
 MFMA, executed flops) from HIP events recorded on the stream it runs on,
 MTXEL's share and rate, one whole build in FP64, FP32 and split BF16 with
 errors against the device FP64 build (32 rows), every precision on a
-4 x 256-band sample against the FP64 oracle, and the oracle's time on that
+4 x 512-band sample against the FP64 oracle, and the oracle's time on that
 sample (the CPU baseline).
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-legs]
@@ -123,7 +123,7 @@ def main():
 
 
 W2_BLOCK_NV = 16        # valence bands per step of the 72^3 workload (one NV block)
-W2_SAMPLE = (4, 256)    # valence x conduction bands of its oracle sample
+W2_SAMPLE = (4, 512)    # valence x conduction bands of its oracle sample
 PROFILE_TRAFFIC_72 = os.path.join(ROOT, "profiles", "chi0_f64_kernel_72cube_983040pairs_pmc.md")
 
 
@@ -188,7 +188,7 @@ def bench_chi0_72cube(args):
     block of every cycle overwrites it): 16 steps build the whole chi0.  Also
     times one whole build in FP64, FP32 and split BF16 (3, 4, 5 slices) with
     their 32-row errors against the device FP64 build, and every precision on
-    a 4 x 256-band sample against the FP64 oracle, which is the CPU baseline."""
+    a 4 x 512-band sample against the FP64 oracle, which is the CPU baseline."""
     import numpy as np
     import torch
 
@@ -407,7 +407,7 @@ def bench_chi0_72cube(args):
     os.environ.pop("GW_AUTOTUNE_CACHE", None)
     os.remove(tune_path)
 
-    # every precision on a 4 x 256-band sample of the same bands against the
+    # every precision on a 4 x 512-band sample of the same bands against the
     # FP64 oracle (which is also the CPU baseline)
     sv, sc = W2_SAMPLE
     sp = gw.Chi0Problem(n=n, volume=w.volume, psi_v=w.psi[:sv], psi_c=psi_c[:sc],
