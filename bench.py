@@ -639,8 +639,9 @@ def bench_chi0_48cube(args):
     ref = gw.gw_chi0(dp, precision="fp64", pair_chunk=chunk).clone()
     splits = []
     for ns in args.split_slices:
-        def sstep():
-            gw.gw_chi0(dp, precision="split_bf16", n_slices=ns, pair_chunk=chunk)
+        def sstep():  # with the autotuner (the LDS ring); the untimed first call tunes
+            gw.gw_chi0(dp, precision="split_bf16", n_slices=ns, pair_chunk=chunk,
+                       flags=gw.GW_FLAG_AUTOTUNE)
         sstep()
         torch.cuda.synchronize()
         gw.profile_reset()
