@@ -89,7 +89,7 @@ enum {
     GW_EINVAL       = -1,   /* bad argument (message says which) */
     GW_ENOMEM       = -2,   /* device allocation of library scratch failed */
     GW_EHIP         = -3,   /* a HIP runtime call failed */
-    GW_EUNSUPPORTED = -4,   /* valid request this build does not implement */
+    GW_EUNSUPPORTED = -4,   /* valid request this library does not implement */
     GW_EINTERNAL    = -5
 };
 

@@ -236,12 +236,12 @@ Opts read_opts(const gw_opts_t* o) {
     return r;
 }
 
-// Slice counts this build implements (read_opts has checked [2, 8]).
+// Slice counts this library implements (read_opts has checked [2, 8]).
 void check_slices(const Opts& o) {
     if (o.precision == GW_SPLIT_FP16X9 && o.n_slices > 4)
         fail(GW_EUNSUPPORTED, "9-bit FP16 slices: at most 4 (a fifth leaves FP16's range)");
     if (is_split(o.precision) && o.n_slices > 6)
-        fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this build");
+        fail(GW_EUNSUPPORTED, "split precision supports up to 6 slices in this library");
 }
 
 void check_problem(const gw_problem_t& p, int idx) {
